@@ -1,0 +1,23 @@
+"""CPU oracle for the augmented HOC biharmonic solver (FP64, plain and slow).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this package:
+only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import, call or run anything under ``oracle/``.  It shares no code with the
+HIP implementation; the only module both sides use is the seeded input
+generator ``workloads`` (analytic fields, no discretisation arithmetic).
+
+Two tiers:
+
+* ``direct``  -- the plain definition: the coupled HOC linear system of
+  Section 2.2 (block system ``eq-coupled``, with the readings listed in
+  ``readings.py``) assembled entry by entry in FP64 and solved by a sparse LU.
+  Also the explicit Schur complement S_h and right-hand side b of Section 2.3.
+* ``fast``    -- Algorithm 1 step by step (ConstructSchurRHS, SchurMatVec,
+  matrix-free GMRES, recovery of V then U) with library DST-I transforms
+  (scipy.fft) as the fast Poisson solver.  Used at sizes the direct tier
+  cannot reach, and pinned against the direct tier.
+
+``dst`` holds the naive O(N^2) discrete sine transform, ``stencils`` the
+compact operators, ``grid`` node numbering and the layout of Q.
+"""
+from . import grid, stencils, dst, direct, fast  # noqa: F401

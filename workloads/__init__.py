@@ -1,0 +1,356 @@
+"""Seeded, synthetic problem generators shared by the oracle and the GPU path.
+
+This module holds the *inputs* only: analytic coefficient fields alpha, the
+manufactured solutions u, and the data that the model problem of Section 2
+(eq. (1) with the clamped conditions (eq-bc)) derives from them:
+
+    f      = -div(alpha grad-free Laplacian): f = -Delta(alpha Delta u) + beta Delta u, beta = 0
+    g_D    = u on the boundary
+    g_N    = outward normal derivative of u on the relative interior of each face
+    lapgD  = on face-interior nodes, the tangential part of Delta u (what the
+             Dirichlet data fixes, Sec. 2.2 boundary Laplacian decomposition);
+             on edges and corners, the full Delta u (Remark 1)
+
+Nothing here discretises anything: no stencil, transform or solver lives in
+this module, so it carries none of the method's arithmetic.  Arrays are nodal,
+in memory order (z, y, x) with x fastest, and can be produced either as numpy
+arrays (host) or as torch tensors on a device (for the large grids), using the
+same symbolic derivation.
+"""
+from __future__ import annotations
+
+import functools
+import math
+from dataclasses import dataclass, field
+from typing import Any, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Problem", "manufactured", "config1", "config2", "config3", "config4_specs",
+    "config4_instance", "cavity", "plate", "poly_exact", "node_coords",
+]
+
+
+@dataclass
+class Problem:
+    """One clamped problem on a box: grid, coefficient and data (nodal arrays).
+
+    n: intervals per axis, axis order (x, y[, z]).  lo/hi: box corners.
+    Arrays are numpy (host) or torch tensors; None means identically zero.
+    u_exact / v_exact are the analytic solution and v = alpha*Delta u sampled
+    at the nodes when known (None otherwise).
+    """
+    n: tuple
+    lo: tuple
+    hi: tuple
+    alpha: Any
+    f: Any
+    gD: Any = None
+    gN: Any = None
+    lapgD: Any = None
+    u_exact: Any = None
+    v_exact: Any = None
+    name: str = ""
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def h(self) -> tuple:
+        return tuple((b - a) / m for a, b, m in zip(self.lo, self.hi, self.n))
+
+
+def node_coords(n: Sequence[int], lo: Sequence[float], hi: Sequence[float]):
+    """1-D node coordinates x_i = x_L + i h_x, i = 0..N_x, per axis (Sec. 2, grid)."""
+    return [lo[a] + (hi[a] - lo[a]) * np.arange(n[a] + 1) / n[a] for a in range(len(n))]
+
+
+# --------------------------------------------------------------------------------------
+# symbolic derivation (sympy), cached per expression
+# --------------------------------------------------------------------------------------
+
+def _symbols(dim):
+    import sympy as sp
+    return sp.symbols("x y z")[:dim]
+
+
+@functools.lru_cache(maxsize=None)
+def _derive(alpha_src: str, u_src: str, dim: int, params: tuple = ()):
+    """Derive f = -Delta(alpha Delta u), Delta u, grad u for string expressions."""
+    import sympy as sp
+    X = _symbols(dim)
+    ns = {s.name: s for s in X}
+    ns.update({p: sp.Symbol(p) for p in params})
+    ns.update({"pi": sp.pi, "sin": sp.sin, "cos": sp.cos, "exp": sp.exp})
+    alpha = sp.sympify(alpha_src, locals=ns)
+    u = sp.sympify(u_src, locals=ns)
+    lap = lambda w: sum(sp.diff(w, s, 2) for s in X)
+    lu = lap(u)
+    v = alpha * lu
+    f = -lap(v)
+    exprs = {
+        "alpha": alpha, "u": u, "lapu": lu, "v": v, "f": f,
+        **{f"du{a}": sp.diff(u, X[a]) for a in range(dim)},
+        **{f"d2u{a}": sp.diff(u, X[a], 2) for a in range(dim)},
+    }
+    return X, tuple(sp.Symbol(p) for p in params), exprs
+
+
+def _lambdify(expr, X, P, xp_name):
+    import sympy as sp
+    if xp_name == "torch":
+        import torch
+        mod = {"sin": torch.sin, "cos": torch.cos, "exp": torch.exp, "pi": math.pi,
+               "sqrt": torch.sqrt}
+    else:
+        mod = {"sin": np.sin, "cos": np.cos, "exp": np.exp, "pi": math.pi, "sqrt": np.sqrt}
+    return sp.lambdify(list(X) + list(P), expr, modules=[mod, "math"], cse=True)
+
+
+@functools.lru_cache(maxsize=None)
+def _fn(alpha_src, u_src, dim, params, key, xp_name):
+    X, P, exprs = _derive(alpha_src, u_src, dim, params)
+    return _lambdify(exprs[key], X, P, xp_name)
+
+
+class _Eval:
+    """Evaluate derived expressions on (sub)grids with numpy or torch."""
+
+    def __init__(self, alpha_src, u_src, dim, params=(), pvals=(), xp="numpy",
+                 device=None, dtype=None):
+        self.a, self.u, self.dim = alpha_src, u_src, dim
+        self.params, self.pvals = tuple(params), tuple(pvals)
+        self.xp, self.device = xp, device
+        self.dtype = dtype
+
+    def coords(self, c1d, axis):
+        """Reshape a 1-D coordinate array to broadcast along `axis` (memory order z,y,x)."""
+        shape = [1] * self.dim
+        shape[self.dim - 1 - axis] = len(c1d)
+        if self.xp == "torch":
+            import torch
+            return torch.as_tensor(np.asarray(c1d), dtype=torch.float64,
+                                   device=self.device).reshape(shape)
+        return np.asarray(c1d, dtype=np.float64).reshape(shape)
+
+    def __call__(self, key, cs):
+        fn = _fn(self.a, self.u, self.dim, self.params, key, self.xp)
+        out = fn(*cs, *self.pvals)
+        if self.xp == "torch":
+            import torch
+            shape = tuple(torch.broadcast_shapes(*[tuple(c.shape) for c in cs]))
+        else:
+            shape = np.broadcast_shapes(*[c.shape for c in cs])
+        return self._full(out, shape)
+
+    def _full(self, val, shape):
+        if self.xp == "torch":
+            import torch
+            if not torch.is_tensor(val):
+                val = torch.tensor(float(val), dtype=torch.float64, device=self.device)
+            return val.to(torch.float64).expand(shape).contiguous()
+        val = np.asarray(val, dtype=np.float64)
+        return np.ascontiguousarray(np.broadcast_to(val, shape))
+
+
+def _zeros(ev, shape):
+    if ev.xp == "torch":
+        import torch
+        return torch.zeros(shape, dtype=torch.float64, device=ev.device)
+    return np.zeros(shape)
+
+
+def _boundary_data(ev: _Eval, n, c1d):
+    """Nodal g_D, g_N, lapgD built from boundary evaluations only (O(N^{d-1}) work).
+
+    Returns None for fields that vanish identically on the boundary."""
+    dim = len(n)
+    shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+    gD = _zeros(ev, shape)
+    gN = _zeros(ev, shape)
+    lap = _zeros(ev, shape)
+    mod = ev.xp == "torch"
+
+    def sl(axis, idx):
+        s = [slice(None)] * dim
+        s[dim - 1 - axis] = slice(idx, idx + 1)
+        return tuple(s)
+
+    for a in range(dim):
+        for side, idx in ((0, 0), (1, n[a])):
+            cs = [ev.coords(c1d[b], b) if b != a else ev.coords(c1d[a][idx:idx + 1], a)
+                  for b in range(dim)]
+            u_b = ev("u", cs)
+            gD[sl(a, idx)] = u_b
+            # outward normal derivative: -d/dx_a on the low side, +d/dx_a on the high side
+            du = ev(f"du{a}", cs)
+            gN_b = -du if side == 0 else du
+            lapu = ev("lapu", cs)
+            tang = lapu - ev(f"d2u{a}", cs)
+            # face-interior nodes only for g_N / tangential Laplacian
+            inner = [slice(None)] * dim
+            for b in range(dim):
+                if b != a:
+                    inner[dim - 1 - b] = slice(1, n[b])
+            inner = tuple(inner)
+            tgt = sl(a, idx)
+            gsub = gN[tgt]
+            gsub[inner] = gN_b[inner]
+            gN[tgt] = gsub
+            lsub = lap[tgt]
+            # edges/corners get full Delta u (Remark 1); face interior the tangential part
+            lsub[...] = lapu
+            lsub[inner] = tang[inner]
+            lap[tgt] = lsub
+    # Fields whose boundary values are pure rounding noise (e.g. sin(pi*1.0) ~ 1e-16
+    # instead of 0) are reported as identically zero.
+    out = []
+    for arr in (gD, gN, lap):
+        mx = float(arr.abs().max()) if mod else float(np.abs(arr).max())
+        out.append(None if mx < 1e-12 else arr)
+    return out
+
+
+def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None, *,
+                 params=(), pvals=(), xp="numpy", device=None, with_exact=True,
+                 chunk=None, name=""):
+    """Sample a manufactured clamped problem.
+
+    alpha_src/u_src: expressions in x, y[, z] (and `params`).  f follows the
+    paper's sign convention of eq. (1) with beta = 0.  xp = "numpy" gives host
+    arrays; xp = "torch" builds the nodal fields on `device` (in z-chunks of
+    `chunk` planes for large 3-D grids).
+    """
+    dim = len(n)
+    lo = tuple(lo) if lo is not None else (0.0,) * dim
+    hi = tuple(hi) if hi is not None else (1.0,) * dim
+    ev = _Eval(alpha_src, u_src, dim, params, pvals, xp, device)
+    c1d = node_coords(n, lo, hi)
+    shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+    keys = ["alpha", "f"] + (["u", "v"] if with_exact else [])
+    out = {}
+    if dim == 3 and chunk is not None:
+        for k in keys:
+            out[k] = _zeros(ev, shape)
+        for z0 in range(0, n[2] + 1, chunk):
+            z1 = min(n[2] + 1, z0 + chunk)
+            cs = [ev.coords(c1d[0], 0), ev.coords(c1d[1], 1), ev.coords(c1d[2][z0:z1], 2)]
+            for k in keys:
+                out[k][z0:z1] = ev(k, cs)
+    else:
+        cs = [ev.coords(c1d[a], a) for a in range(dim)]
+        for k in keys:
+            out[k] = ev(k, cs)
+    gD, gN, lap = _boundary_data(ev, n, c1d)
+    return Problem(tuple(n), lo, hi, out["alpha"], out["f"], gD, gN, lap,
+                   out.get("u"), out.get("v"), name=name,
+                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals))})
+
+
+# --------------------------------------------------------------------------------------
+# the benchmark configurations (all fully clamped, beta = 0)
+# --------------------------------------------------------------------------------------
+
+def config1(n=32, **kw):
+    """2-D, alpha = 1, u = sin^2(pi x) sin^2(pi y) on the unit square (Delta^2 u = f form)."""
+    return manufactured("1", "sin(pi*x)**2*sin(pi*y)**2", (n, n), name=f"c1_n{n}", **kw)
+
+
+def config2(n=256, **kw):
+    """2-D variable coefficient alpha = 1 + 0.5 sin(2 pi x) cos(2 pi y), u = sin^2 sin^2 e^{x+y}."""
+    return manufactured("1 + 0.5*sin(2*pi*x)*cos(2*pi*y)",
+                        "sin(pi*x)**2*sin(pi*y)**2*exp(x + y)", (n, n), name=f"c2_n{n}", **kw)
+
+
+C3_ALPHA = "1 + 0.5*sin(2*pi*x)*sin(2*pi*y)*sin(2*pi*z)"
+C3_U = "sin(pi*x)**2*sin(pi*y)**2*sin(pi*z)**2"
+
+
+def config3(n=128, **kw):
+    """3-D unit cube, alpha = 1 + 0.5 sin sin sin (2 pi), u = sin^2 sin^2 sin^2 (pi)."""
+    return manufactured(C3_ALPHA, C3_U, (n, n, n), name=f"c3_n{n}", **kw)
+
+
+C4_SIZES = (64, 96, 128, 192, 256, 384, 512)
+C4_ALPHA = "1 + c*sin(2*pi*p*x)*cos(2*pi*q*y)"
+C4_U = "sin(pi*x)**2*sin(pi*y)**2*cos(k*(x + y))"
+
+
+def config4_specs(count=512, seed=0):
+    """Seeded draws for the batched 2-D workload.
+
+    Per instance, in this order: n uniform over C4_SIZES, c ~ U(0, 0.8),
+    p, q integers in [1, 4], k ~ U(10, 80)."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(rng.choice(C4_SIZES))
+        c = float(rng.uniform(0.0, 0.8))
+        p = int(rng.integers(1, 5))
+        q = int(rng.integers(1, 5))
+        k = float(rng.uniform(10.0, 80.0))
+        specs.append({"n": n, "c": c, "p": p, "q": q, "k": k})
+    return specs
+
+
+def config4_instance(spec, **kw):
+    return manufactured(C4_ALPHA, C4_U, (spec["n"], spec["n"]), params=("c", "p", "q", "k"),
+                        pvals=(spec["c"], spec["p"], spec["q"], spec["k"]),
+                        name=f"c4_n{spec['n']}", **kw)
+
+
+def cavity(n=64):
+    """Lid-driven cavity stream function: Delta^2 psi = 0, psi = 0, psi_n = 1 on y = 1."""
+    dim = 2
+    shape = (n + 1, n + 1)
+    gN = np.zeros(shape)
+    gN[n, 1:n] = 1.0  # y = 1 face interior; outward normal is +y, [-u_y, u_x] = [-1, 0]
+    return Problem((n, n), (0.0, 0.0), (1.0, 1.0), np.ones(shape), np.zeros(shape),
+                   None, gN, None, name=f"cavity_n{n}")
+
+
+def plate(n=64):
+    """Clamped unit plate under a unit central load (load reading: trapezoid weights on even n).
+
+    The paper's load 1/(4h^2) on |x-1/2| <= h, |y-1/2| <= h covers 9 nodes on an
+    even grid; we weight them by the tensor trapezoid rule (1, 1/2, 1/4) so that
+    the load integrates to one.  On odd n the literal 4-node reading is used.
+    Sign: the paper's form -Delta(alpha Delta u) = f with Delta^2 u = load gives
+    f = -load.
+    """
+    h = 1.0 / n
+    x = np.arange(n + 1) * h
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    load = np.zeros((n + 1, n + 1))
+    mask = (np.abs(X - 0.5) <= h + 1e-12) & (np.abs(Y - 0.5) <= h + 1e-12)
+    if n % 2 == 0:
+        w1 = np.where(np.abs(x - 0.5) < 1e-12, 1.0, 0.5)
+        W = np.outer(w1, w1)
+        load[mask] = W[mask] / (4 * h * h)
+    else:
+        load[mask] = 1.0 / (4 * h * h)
+    return Problem((n, n), (0.0, 0.0), (1.0, 1.0), np.ones((n + 1, n + 1)), -load,
+                   name=f"plate_n{n}")
+
+
+def poly_exact(n, dim=2, **kw):
+    """Polynomial-exactness problem: u of total degree 4, alpha of degree 3, all data nonzero.
+
+    For such data v = alpha Delta u has degree <= 5, so the compact scheme
+    reproduces u at every node to rounding (the operators are exact for
+    polynomials of degree <= 5 and the one-sided normal formula for degree <= 4).
+    """
+    if dim == 2:
+        u = "1 + x - 2*y + x*y + 0.5*x**2*y**2 - 0.3*x**3*y + 0.2*x**4 + 0.1*y**4 - 0.7*x**2 + 0.4*y**3"
+        a = "2 + 0.3*x + 0.2*y + 0.1*x*y + 0.05*x**3"
+        lo, hi = (-0.3, 0.1), (0.9, 1.4)
+    else:
+        u = ("1 + x - 2*y + 0.5*z + x*y*z + 0.5*x**2*y**2 - 0.3*x**3*z + 0.2*x**4"
+             " + 0.1*y**4 - 0.7*z**2*x + 0.4*y**3 + 0.25*z**4 - 0.2*y*z**3")
+        a = "2 + 0.3*x + 0.2*y - 0.1*z + 0.1*x*y*z + 0.05*z**3"
+        lo, hi = (-0.3, 0.1, 0.2), (0.9, 1.4, 1.1)
+    return manufactured(a, u, n if isinstance(n, (tuple, list)) else (n,) * dim, lo, hi,
+                        name=f"poly{dim}d", **kw)
