@@ -1,0 +1,157 @@
+/*
+ * ahoc.h -- C ABI of the MI355X (gfx950) augmented high-order-compact solver
+ * for clamped, variable-coefficient biharmonic problems.
+ *
+ * Problem (Section 2, eq. (1) with the clamped conditions eq-bc, beta = 0):
+ *     -Delta( alpha Delta u ) = f    in the box  [lo_0,hi_0] x ... (dim = 2 or 3)
+ *     u = g_D,  du/dn = g_N          on every face (fully clamped)
+ * discretised by the fourth-order compact scheme of Sec. 2.2 (19-point L_h and
+ * 7-point M in 3-D, 9-point L_h and 5-point M in 2-D) on a uniform grid with
+ * n[a] intervals per axis.  The unknown boundary values Q of v = alpha Delta u
+ * on the face interiors are found from the Schur-complement system S_h Q = b
+ * (Sec. 2.3, eq-schur) with a matrix-free GMRES whose matrix-vector product is
+ * Lemma 1 / Algorithm 1 (SchurMatVec): two DST-I fast Poisson solves, the
+ * variable-coefficient weighting M(V/alpha), and the one-sided boundary
+ * residual gather.
+ *
+ * Conventions
+ *   - Every array argument is a DEVICE pointer (HIP device memory) unless
+ *     stated otherwise.  Nodal arrays hold (n_z+1)(n_y+1)(n_x+1) doubles
+ *     (2-D: (n_y+1)(n_x+1)), x fastest.
+ *   - Q (length ahoc_nq) is ordered by faces x-, x+, y-, y+[, z-, z+]; inside a
+ *     face the two tangential axes are row-major, lower axis fastest.
+ *   - The caller owns every buffer it passes.  ahoc_setup copies what it needs
+ *     into handle-owned device memory, so problem arrays may be freed after
+ *     setup returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  ahoc_setup,
+ *     ahoc_solve and ahoc_solve_batched return after the work has completed;
+ *     ahoc_schur_apply, ahoc_poisson and ahoc_dst1 are asynchronous on the stream.
+ *   - Errors are reported by return code only; ahoc_last_error() gives text.
+ *   - A handle is not thread-safe; distinct handles are independent.
+ */
+#ifndef AHOC_H
+#define AHOC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AHOC_OK = 0,
+  AHOC_E_INVALID = -1,     /* bad argument: dim, sizes, NULL arrays, alpha <= 0 */
+  AHOC_E_NOMEM = -2,       /* device allocation failed                           */
+  AHOC_E_NOCONV = -3,      /* tolerance not reached; outputs hold the last iterate */
+  AHOC_E_HIP = -4,         /* a HIP runtime call failed                          */
+  AHOC_E_UNSUPPORTED = -5  /* grid size without a transform plan (n must be 2^a or 3*2^a, 8..8192) */
+} ahoc_status;
+
+typedef enum {
+  AHOC_FP64 = 0,  /* every step in FP64                                          */
+  AHOC_MIXED = 1  /* FP32 transforms/stencils inside FP64 iterative refinement;
+                     residual, Krylov vectors, Arnoldi, Givens, updates in FP64   */
+} ahoc_precision;
+
+/* One clamped problem.  alpha and f are required; gD, gN, lapgD may be NULL (= 0).
+ *   alpha  nodal coefficient, must satisfy alpha > 0 everywhere (checked)
+ *   f      nodal right-hand side in the sign of eq. (1): f = -Delta(alpha Delta u)
+ *   gD     nodal; boundary entries are the Dirichlet data u = g_D
+ *   gN     nodal; on face-interior nodes the OUTWARD normal derivative of u
+ *   lapgD  nodal; on face-interior nodes the tangential part of Delta u fixed by
+ *          g_D (Sec. 2.2 boundary Laplacian decomposition); on edges and corners
+ *          the full Delta u (Remark 1) */
+typedef struct {
+  int dim;       /* 2 or 3 */
+  int n[3];      /* intervals per axis, n[a] >= 8 (unused axis ignored) */
+  double lo[3];
+  double hi[3];
+  const double* alpha;
+  const double* f;
+  const double* gD;
+  const double* gN;
+  const double* lapgD;
+} ahoc_problem;
+
+typedef struct {
+  int precision;      /* ahoc_precision                                              */
+  int restart;        /* GMRES restart length m (default 30)                         */
+  int max_iters;      /* cap on GMRES iterations per Schur solve (default 2000)      */
+  double tol;         /* FP64: relative Schur residual ||b - S Q|| / ||b|| (1e-12)   */
+  double inner_tol;   /* MIXED: relative Schur residual of each correction (1e-6)    */
+  double sweep_tol;   /* MIXED: stop when the estimated remaining relative change of
+                         U (max norm) is below this (default 1e-11)                  */
+  int max_sweeps;     /* MIXED: refinement sweeps cap (default 8)                    */
+  int tile_fp64;      /* DST work-group tile in pencil pairs, 0 = default            */
+  int tile_fp32;
+} ahoc_options;
+
+typedef struct {
+  int converged;
+  int gmres_iters;       /* total over sweeps                           */
+  int sweeps;            /* refinement sweeps (1 for FP64)              */
+  int matvecs;           /* Schur matrix-vector products                */
+  double schur_relres;   /* last GMRES relative residual estimate       */
+  double last_update;    /* last sweep's max |dU| / max |U|             */
+  double t_solve_ms;     /* wall time of ahoc_solve                     */
+} ahoc_stats;
+
+typedef struct ahoc_handle ahoc_handle;
+
+/* Fill `opt` with the defaults listed above. */
+void ahoc_default_options(ahoc_options* opt);
+
+/* Validate the problem, derive 1/alpha, M f, the boundary data lifts and the
+ * transform tables, allocate the workspace (hipMalloc).  Returns
+ * AHOC_E_INVALID for dim not in {2,3}, n[a] < 8, NULL alpha/f or min alpha <= 0,
+ * AHOC_E_UNSUPPORTED if a transform length has no plan.  *out is set only on
+ * success; release it with ahoc_destroy. */
+ahoc_status ahoc_setup(const ahoc_problem* prob, const ahoc_options* opt, void* stream,
+                       ahoc_handle** out);
+
+/* Number of augmented unknowns N_q of the handle's grid. */
+size_t ahoc_nq(const ahoc_handle* h);
+
+/* y = S_h q (Lemma 1 in homogeneous form: R(q) - R(0)), q and y of length N_q,
+ * FP64 in and out; the transforms and stencils run in the handle's precision. */
+ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* stream);
+
+/* Right-hand side b = -R(0) of the Schur system (Algorithm 1, ConstructSchurRHS), FP64, length N_q. */
+ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream);
+
+/* Solve.  u (nodal, required) receives U; v (nodal or NULL) receives V = alpha Delta u
+ * (interior V, Q on face interiors, alpha*lapgD on edges/corners); q (length N_q or
+ * NULL) receives Q.  stats may be NULL.  Returns AHOC_E_NOCONV (outputs still
+ * written) when the tolerance is not met. */
+ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* stats,
+                       void* stream);
+
+/* Solve `count` independent problems (sizes and coefficients may differ) with
+ * shared options.  u is a HOST array of `count` device pointers; stats a host
+ * array of `count` entries (or NULL).  Returns the first non-OK status. */
+ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_options* opt,
+                               double* const* u, ahoc_stats* stats, void* stream);
+
+/* Dirichlet solve with the compact operator on the handle's interior grid:
+ * w = L_int^{-1} g (homogeneous boundary), g and w interior arrays of FP64
+ * ((n_z-1)(n_y-1)(n_x-1), x fastest), in the handle's precision internally. */
+ahoc_status ahoc_poisson(ahoc_handle* h, const double* g, double* w, void* stream);
+
+/* Stand-alone batched DST-I along one axis of an interior-shaped array:
+ * out[..., k, ...] = sum_{m=1}^{N-1} in[..., m, ...] sin(pi k m / N), N = nint[axis]+1.
+ * precision: AHOC_FP64 (double arrays) or AHOC_MIXED (float arrays).
+ * nint: interior sizes (x, y[, z]); in may equal out. */
+ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const void* in, void* out,
+                      void* stream);
+
+void ahoc_destroy(ahoc_handle* h);
+
+const char* ahoc_status_string(ahoc_status s);
+/* Text of the last error recorded by this library (thread-local). */
+const char* ahoc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AHOC_H */

@@ -1,0 +1,262 @@
+"""Python binding of libahoc (the MI355X augmented HOC biharmonic solver).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+behind the C ABI declared in include/ahoc.h.  PyTorch provides device memory
+and the current stream.  Importing this package on a machine without the
+built library raises ImportError -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libahoc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, E_INVALID, E_NOMEM, E_NOCONV, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+FP64, MIXED = 0, 1
+
+c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("dim", c_int), ("n", c_int * 3), ("lo", c_double * 3), ("hi", c_double * 3),
+                ("alpha", c_void_p), ("f", c_void_p), ("gD", c_void_p), ("gN", c_void_p),
+                ("lapgD", c_void_p)]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("tol", c_double),
+                ("inner_tol", c_double), ("sweep_tol", c_double), ("max_sweeps", c_int),
+                ("tile_fp64", c_int), ("tile_fp32", c_int)]
+
+
+class _Stats(ctypes.Structure):
+    _fields_ = [("converged", c_int), ("gmres_iters", c_int), ("sweeps", c_int), ("matvecs", c_int),
+                ("schur_relres", c_double), ("last_update", c_double), ("t_solve_ms", c_double)]
+
+
+_H = c_void_p
+_lib.ahoc_default_options.argtypes = [ctypes.POINTER(_Options)]
+_lib.ahoc_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), c_void_p, ctypes.POINTER(_H)]
+_lib.ahoc_setup.restype = c_int
+_lib.ahoc_nq.argtypes = [_H]
+_lib.ahoc_nq.restype = c_size_t
+_lib.ahoc_schur_apply.argtypes = [_H, c_void_p, c_void_p, c_void_p]
+_lib.ahoc_schur_apply.restype = c_int
+_lib.ahoc_schur_rhs.argtypes = [_H, c_void_p, c_void_p]
+_lib.ahoc_schur_rhs.restype = c_int
+_lib.ahoc_solve.argtypes = [_H, c_void_p, c_void_p, c_void_p, ctypes.POINTER(_Stats), c_void_p]
+_lib.ahoc_solve.restype = c_int
+_lib.ahoc_solve_batched.argtypes = [c_int, ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
+                                    ctypes.POINTER(c_void_p), ctypes.POINTER(_Stats), c_void_p]
+_lib.ahoc_solve_batched.restype = c_int
+_lib.ahoc_poisson.argtypes = [_H, c_void_p, c_void_p, c_void_p]
+_lib.ahoc_poisson.restype = c_int
+_lib.ahoc_dst1.argtypes = [c_int, c_int, ctypes.POINTER(c_int), c_int, c_void_p, c_void_p, c_void_p]
+_lib.ahoc_dst1.restype = c_int
+_lib.ahoc_destroy.argtypes = [_H]
+_lib.ahoc_status_string.argtypes = [c_int]
+_lib.ahoc_status_string.restype = ctypes.c_char_p
+_lib.ahoc_last_error.restype = ctypes.c_char_p
+
+EXPORTED = ["ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_schur_rhs",
+            "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
+            "ahoc_status_string", "ahoc_last_error"]
+
+
+class AhocError(RuntimeError):
+    def __init__(self, code, where=""):
+        msg = _lib.ahoc_status_string(code).decode()
+        last = (_lib.ahoc_last_error() or b"").decode()
+        super().__init__(f"{where}: {msg} ({code}) {last}")
+        self.code = code
+
+
+def _check(code, where):
+    if code != OK:
+        raise AhocError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(x, device):
+    """A contiguous float64 tensor on `device` (numpy or torch input); None stays None."""
+    if x is None:
+        return None
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+    return x.to(device=device, dtype=torch.float64).contiguous()
+
+
+def _ptr(t):
+    return None if t is None else c_void_p(t.data_ptr())
+
+
+def default_options(precision=FP64, **kw) -> _Options:
+    o = _Options()
+    _lib.ahoc_default_options(ctypes.byref(o))
+    o.precision = precision
+    for k, v in kw.items():
+        if v is not None:
+            setattr(o, k, v)
+    return o
+
+
+@dataclass
+class Stats:
+    converged: bool
+    gmres_iters: int
+    sweeps: int
+    matvecs: int
+    schur_relres: float
+    last_update: float
+    t_solve_ms: float
+
+
+def _stats(s: _Stats) -> Stats:
+    return Stats(bool(s.converged), s.gmres_iters, s.sweeps, s.matvecs, s.schur_relres,
+                 s.last_update, s.t_solve_ms)
+
+
+def _problem_struct(n, lo, hi, tens):
+    dim = len(n)
+    p = _Problem()
+    p.dim = dim
+    for a in range(3):
+        p.n[a] = int(n[a]) if a < dim else 0
+        p.lo[a] = float(lo[a]) if a < dim else 0.0
+        p.hi[a] = float(hi[a]) if a < dim else 0.0
+    p.alpha, p.f, p.gD, p.gN, p.lapgD = [(t.data_ptr() if t is not None else None) for t in tens]
+    return p
+
+
+class Solver:
+    """One problem set up on the GPU (wraps an ahoc_handle).
+
+    `problem` carries n, lo, hi and nodal alpha, f, gD, gN, lapgD (numpy or torch,
+    memory order z, y, x), e.g. a workloads.Problem.
+    """
+
+    def __init__(self, problem, precision=FP64, device="cuda:0", **opts):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.n = tuple(problem.n)
+        self.dim = len(self.n)
+        tens = [_dev(getattr(problem, k), self.device) for k in ("alpha", "f", "gD", "gN", "lapgD")]
+        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens)
+        self.options = default_options(precision, **opts)
+        h = _H()
+        with torch.cuda.device(self.device):
+            _check(_lib.ahoc_setup(ctypes.byref(self._p), ctypes.byref(self.options), _stream(),
+                                   ctypes.byref(h)), "ahoc_setup")
+        self._h = h
+        self.nq = int(_lib.ahoc_nq(h))
+        self.nodal_shape = tuple(m + 1 for m in reversed(self.n))
+        self.interior_shape = tuple(m - 1 for m in reversed(self.n))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.ahoc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _vec(self, x, size):
+        t = _dev(x, self.device)
+        assert t.numel() == size
+        return t
+
+    def schur_apply(self, q):
+        torch = _torch()
+        q = self._vec(q, self.nq)
+        y = torch.empty(self.nq, dtype=torch.float64, device=self.device)
+        _check(_lib.ahoc_schur_apply(self._h, _ptr(q), _ptr(y), _stream()), "ahoc_schur_apply")
+        return y
+
+    def schur_rhs(self):
+        torch = _torch()
+        b = torch.empty(self.nq, dtype=torch.float64, device=self.device)
+        _check(_lib.ahoc_schur_rhs(self._h, _ptr(b), _stream()), "ahoc_schur_rhs")
+        return b
+
+    def poisson(self, g):
+        torch = _torch()
+        g = _dev(g, self.device).reshape(-1)
+        w = torch.empty_like(g)
+        _check(_lib.ahoc_poisson(self._h, _ptr(g), _ptr(w), _stream()), "ahoc_poisson")
+        return w.reshape(self.interior_shape)
+
+    def solve(self, want_v=False, want_q=False, out=None):
+        torch = _torch()
+        u = out if out is not None else torch.empty(self.nodal_shape, dtype=torch.float64,
+                                                    device=self.device)
+        v = torch.empty(self.nodal_shape, dtype=torch.float64, device=self.device) if want_v else None
+        q = torch.empty(self.nq, dtype=torch.float64, device=self.device) if want_q else None
+        s = _Stats()
+        rc = _lib.ahoc_solve(self._h, _ptr(u), _ptr(v), _ptr(q), ctypes.byref(s), _stream())
+        if rc not in (OK, E_NOCONV):
+            _check(rc, "ahoc_solve")
+        return u, v, q, _stats(s)
+
+
+def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
+    """Solve independent problems with shared options; returns (list of u, list of Stats, status)."""
+    torch = _torch()
+    dev = torch.device(device)
+    keep, structs, outs = [], [], []
+    for pb in problems:
+        tens = [_dev(getattr(pb, k), dev) for k in ("alpha", "f", "gD", "gN", "lapgD")]
+        keep.append(tens)
+        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens))
+        outs.append(torch.empty(tuple(m + 1 for m in reversed(pb.n)), dtype=torch.float64, device=dev))
+    cnt = len(problems)
+    parr = (_Problem * cnt)(*structs)
+    uarr = (c_void_p * cnt)(*[o.data_ptr() for o in outs])
+    sarr = (_Stats * cnt)()
+    o = default_options(precision, **opts)
+    rc = _lib.ahoc_solve_batched(cnt, parr, ctypes.byref(o), uarr, sarr, _stream())
+    if rc not in (OK, E_NOCONV):
+        _check(rc, "ahoc_solve_batched")
+    return outs, [_stats(s) for s in sarr], rc
+
+
+def dst1(x, axis, precision=FP64):
+    """Batched DST-I along `axis` (axis order x, y[, z]) of an interior-shaped tensor (memory order)."""
+    torch = _torch()
+    dim = x.dim()
+    nint = (c_int * 3)(*([x.shape[dim - 1 - a] for a in range(dim)] + [1] * (3 - dim)))
+    dt = torch.float64 if precision == FP64 else torch.float32
+    xin = x.to(dtype=dt).contiguous()
+    out = torch.empty_like(xin)
+    _check(_lib.ahoc_dst1(precision, dim, nint, axis, _ptr(xin), _ptr(out), _stream()), "ahoc_dst1")
+    return out

@@ -1,0 +1,780 @@
+// Host orchestration and C ABI of the augmented HOC solver (gfx950).
+//
+// Algorithm 1 of the paper, organised for one GPU:
+//   ConstructSchurRHS   b = -R(0): v-solve with Q = 0, u-solve, boundary gather
+//   SchurMatVec         homogeneous form R(Q) - R(0) (Lemma 1): lift Q, DST Poisson
+//                       solve for V, M(V/alpha), DST Poisson solve for U, gather
+//   GMRES(m)            device-resident FP64 Krylov basis, CGS2 Arnoldi, Givens
+//   recovery            V from Q^m, then U from V
+// Every step runs in HIP kernels; the host only sequences launches and reads
+// one scalar per GMRES iteration.  In mixed precision the whole scheme above
+// runs in FP32 as the inner solver of an FP64 iterative refinement on the
+// coupled system (FP64 residual, FP64 Krylov vectors, FP64 updates).
+#include "../../include/ahoc.h"
+#include "common.h"
+#include "kernels.h"
+
+#include <chrono>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace ahoc {
+
+static thread_local std::string g_err;
+void set_last_error(const char* what, const char* where) {
+  g_err = std::string(where ? where : "") + ": " + (what ? what : "");
+}
+
+namespace {
+
+template <typename T> struct Prec {
+  DstTables<T> tb[3];
+  int tile[3] = {0, 0, 0};
+  T* s[3] = {nullptr, nullptr, nullptr};
+  T* ia = nullptr;    // nodal 1/alpha
+  T* af = nullptr;    // alpha on face nodes (N_q)
+  T* bufA = nullptr;  // interior work (V)
+  T* bufB = nullptr;  // interior work (U)
+  T* qT = nullptr;    // N_q, Q in this precision
+  T* zq = nullptr;    // N_q zeros
+  DstScale<T> scV, scU, scP;
+  bool ready = false;
+};
+
+}  // namespace
+}  // namespace ahoc
+
+using namespace ahoc;
+
+struct ahoc_handle {
+  Geom g;
+  Weights w;
+  ahoc_options opt;
+  // FP64 problem data
+  double* ia64 = nullptr;
+  double* af64 = nullptr;
+  double* src_v = nullptr;
+  double* src_u = nullptr;  // null when g_D = 0
+  double* src_q = nullptr;
+  double* gD = nullptr;     // nodal copy, null when g_D = 0
+  double* vedge = nullptr;  // nodal alpha*lapgD, null when lapgD = 0
+  Prec<double> p64;
+  Prec<float> p32;
+  // refinement state (mixed)
+  double *U64 = nullptr, *V64 = nullptr, *Q64 = nullptr;
+  float *ru = nullptr, *rv = nullptr, *rq = nullptr;
+  // Krylov
+  int m = 30;
+  int nb_dot = 256;
+  double *Vb = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr;
+  double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *part = nullptr, *y = nullptr;
+  double *resid = nullptr, *beta = nullptr, *bvec = nullptr, *dq = nullptr, *rvec = nullptr, *R = nullptr;
+  double* red = nullptr;     // reduction partials
+  double* pinned = nullptr;  // host-pinned scalars
+  std::vector<void*> allocs;
+};
+
+namespace ahoc {
+namespace {
+
+int dalloc(ahoc_handle* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e), "hipMalloc");
+    (void)hipGetLastError();
+    return ST_NOMEM;
+  }
+  h->allocs.push_back(*p);
+  return ST_OK;
+}
+
+#define TRY(...)                \
+  do {                          \
+    int rc__ = (__VA_ARGS__);   \
+    if (rc__) return rc__;      \
+  } while (0)
+
+template <typename T> int alloc_t(ahoc_handle* h, T** p, long long n) {
+  return dalloc(h, reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
+}
+
+void make_geom(const ahoc_problem* pb, Geom& g) {
+  std::memset(&g, 0, sizeof(g));
+  g.dim = pb->dim;
+  for (int a = 0; a < 3; ++a) {
+    if (a < g.dim) {
+      g.n[a] = pb->n[a];
+      g.ni[a] = pb->n[a] - 1;
+      g.nn[a] = pb->n[a] + 1;
+      g.h[a] = (pb->hi[a] - pb->lo[a]) / pb->n[a];
+    } else {
+      g.n[a] = 2;
+      g.ni[a] = 1;
+      g.nn[a] = 1;
+      g.h[a] = 1.0;
+    }
+  }
+  g.nint = (long long)g.ni[0] * g.ni[1] * g.ni[2];
+  g.nnodal = (long long)g.nn[0] * g.nn[1] * g.nn[2];
+  int off = 0;
+  for (int a = 0; a < g.dim; ++a) {
+    long long fs = 1;
+    for (int b = 0; b < g.dim; ++b)
+      if (b != a) fs *= g.ni[b];
+    g.face_off[2 * a] = off;
+    off += (int)fs;
+    g.face_off[2 * a + 1] = off;
+    off += (int)fs;
+  }
+  for (int f = 2 * g.dim; f < 7; ++f) g.face_off[f] = off;
+  g.nq = off;
+}
+
+void make_weights(const Geom& g, Weights& w) {
+  const double ix2 = 1.0 / (g.h[0] * g.h[0]), iy2 = 1.0 / (g.h[1] * g.h[1]);
+  if (g.dim == 2) {
+    // nine-point compact Laplacian
+    w.c0 = -20.0 * (ix2 + iy2) / 12.0;
+    w.cf[0] = (10.0 * ix2 - 2.0 * iy2) / 12.0;
+    w.cf[1] = (10.0 * iy2 - 2.0 * ix2) / 12.0;
+    w.cf[2] = 0.0;
+    w.ce[0] = (ix2 + iy2) / 12.0;
+    w.ce[1] = w.ce[2] = 0.0;
+    w.m0 = 8.0 / 12.0;
+  } else {
+    // 19-point compact Laplacian, planes L_{k-1}, L_k, L_{k+1} with prefactor 1/12
+    const double iz2 = 1.0 / (g.h[2] * g.h[2]);
+    w.c0 = -16.0 * (ix2 + iy2 + iz2) / 12.0;
+    w.cf[0] = (8.0 * ix2 - 2.0 * iy2 - 2.0 * iz2) / 12.0;
+    w.cf[1] = (8.0 * iy2 - 2.0 * ix2 - 2.0 * iz2) / 12.0;
+    w.cf[2] = (8.0 * iz2 - 2.0 * ix2 - 2.0 * iy2) / 12.0;
+    w.ce[0] = (ix2 + iy2) / 12.0;
+    w.ce[1] = (ix2 + iz2) / 12.0;
+    w.ce[2] = (iy2 + iz2) / 12.0;
+    w.m0 = 6.0 / 12.0;
+  }
+  w.m1 = 1.0 / 12.0;
+  w.os[0] = -85.0 / 18.0;
+  w.os[1] = 6.0;
+  w.os[2] = -1.5;
+  w.os[3] = 2.0 / 9.0;
+  w.os_gn = 11.0 / 3.0;
+}
+
+template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hipStream_t st) {
+  const Geom& g = h->g;
+  for (int a = 0; a < g.dim; ++a) {
+    TRY(dst_tables_init<T>(P.tb[a], g.n[a]));
+    P.tile[a] = tile_opt > 0 ? tile_opt : dst_default_tile(g.n[a], (int)sizeof(T));
+    if (P.tile[a] <= 0) return ST_UNSUPPORTED;
+    // eigenvalues of the 1-D second difference on sine mode k: -(4/h^2) sin^2(k pi / (2N))
+    std::vector<T> s(g.ni[a]);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int k = 1; k <= g.ni[a]; ++k) {
+      const long double sv = sinl(pi * k / (2.0L * g.n[a]));
+      s[k - 1] = (T)(-4.0L * sv * sv / ((long double)g.h[a] * g.h[a]));
+    }
+    TRY(alloc_t(h, &P.s[a], g.ni[a]));
+    AHOC_HIP_TRY(hipMemcpy(P.s[a], s.data(), sizeof(T) * g.ni[a], hipMemcpyHostToDevice));
+  }
+  TRY(alloc_t(h, &P.bufA, g.nint));
+  TRY(alloc_t(h, &P.bufB, g.nint));
+  TRY(alloc_t(h, &P.qT, g.nq));
+  TRY(alloc_t(h, &P.zq, g.nq));
+  AHOC_HIP_TRY(hipMemsetAsync(P.zq, 0, sizeof(T) * g.nq, st));
+  double norm = 1.0;
+  for (int a = 0; a < g.dim; ++a) norm *= 2.0 / g.n[a];
+  const int t = g.dim - 1;
+  DstScale<T> sc;
+  sc.s_this = P.s[t];
+  sc.s_a = P.s[0];
+  sc.na = g.ni[0];
+  if (g.dim == 3) {
+    sc.s_b = P.s[1];
+    sc.c_ta = (T)((g.h[2] * g.h[2] + g.h[0] * g.h[0]) / 12.0);
+    sc.c_tb = (T)((g.h[2] * g.h[2] + g.h[1] * g.h[1]) / 12.0);
+    sc.c_ab = (T)((g.h[0] * g.h[0] + g.h[1] * g.h[1]) / 12.0);
+  } else {
+    sc.s_b = nullptr;
+    sc.c_ta = (T)((g.h[1] * g.h[1] + g.h[0] * g.h[0]) / 12.0);
+    sc.c_tb = 0;
+    sc.c_ab = 0;
+  }
+  P.scV = sc;
+  P.scV.scale = (T)(-norm);  // V = -L^{-1}(...)
+  P.scU = sc;
+  P.scU.scale = (T)norm;     // U = +L^{-1}(...)
+  P.scP = P.scU;
+  P.ready = true;
+  return ST_OK;
+}
+
+template <typename T> void prec_free(Prec<T>& P) {
+  for (int a = 0; a < 3; ++a) dst_tables_free(P.tb[a]);
+  P.ready = false;
+}
+
+// In-place Dirichlet solve on an interior array: buf <- scale * S (S buf / lambda).
+template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st) {
+  const Geom& g = h->g;
+  if (g.dim == 2) {
+    TRY(dst_pass<T>(P.tb[0], buf, buf, g.ni[1], 1, nullptr, P.tile[0], st));
+    TRY(dst_pass<T>(P.tb[1], buf, buf, 1, g.ni[0], &sc, P.tile[1], st));
+    TRY(dst_pass<T>(P.tb[0], buf, buf, g.ni[1], 1, nullptr, P.tile[0], st));
+  } else {
+    const long long rows = (long long)g.ni[1] * g.ni[2];
+    TRY(dst_pass<T>(P.tb[0], buf, buf, rows, 1, nullptr, P.tile[0], st));
+    TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.ni[0], nullptr, P.tile[1], st));
+    TRY(dst_pass<T>(P.tb[2], buf, buf, 1, (long long)g.ni[0] * g.ni[1], &sc, P.tile[2], st));
+    TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.ni[0], nullptr, P.tile[1], st));
+    TRY(dst_pass<T>(P.tb[0], buf, buf, rows, 1, nullptr, P.tile[0], st));
+  }
+  return ST_OK;
+}
+
+// V = -L^{-1}(src + L_bnd[Q])  into P.bufA
+template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  TRY(lift<T>(h->g, h->w, Q, src, P.bufA, st));
+  return poisson<T>(h, P, P.bufA, P.scV, st);
+}
+
+// U = L^{-1}(M(V/alpha) + src)  with V = P.bufA, into P.bufB
+template <typename T> int usolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  TRY(rhs_u<T>(h->g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
+  return poisson<T>(h, P, P.bufB, P.scU, st);
+}
+
+template <typename T> const T* q_in(ahoc_handle* h, Prec<T>& P, const double* q, hipStream_t st, int* rc) {
+  if constexpr (sizeof(T) == 8) {
+    (void)h; (void)P; (void)st;
+    *rc = ST_OK;
+    return reinterpret_cast<const T*>(q);
+  } else {
+    *rc = convert<double, float>(h->g.nq, q, P.qT, st);
+    return P.qT;
+  }
+}
+
+// y = S_h q  (homogeneous Lemma-1 form)
+template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, double* y, hipStream_t st) {
+  int rc = 0;
+  const T* qT = q_in<T>(h, P, q, st, &rc);
+  TRY(rc);
+  TRY(vsolve<T>(h, P, qT, nullptr, st));
+  TRY(usolve<T>(h, P, qT, nullptr, st));
+  return gather<T>(h->g, h->w, P.bufB, qT, P.af, nullptr, y, st);
+}
+
+// b = -R(0) for sources (src_v, src_u, src_q) in precision T
+template <typename T>
+int schur_rhs(ahoc_handle* h, Prec<T>& P, const T* sv, const T* su, const T* sq, double* b, hipStream_t st) {
+  TRY(vsolve<T>(h, P, P.zq, sv, st));
+  TRY(usolve<T>(h, P, P.zq, su, st));
+  TRY(gather<T>(h->g, h->w, P.bufB, P.zq, P.af, sq, h->R, st));
+  return axpby(h->g.nq, -1.0, h->R, 0.0, b, st);
+}
+
+double read_scalar(ahoc_handle* h, const double* dptr, hipStream_t st, int* rc) {
+  hipError_t e = hipMemcpyAsync(h->pinned, dptr, sizeof(double), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e), "read_scalar");
+    *rc = ST_HIP;
+    return 0.0;
+  }
+  *rc = ST_OK;
+  return h->pinned[0];
+}
+
+int dot_dev(ahoc_handle* h, const double* a, const double* b, long long n, double* out, hipStream_t st) {
+  TRY(mdot_partial(a, n, 1, b, n, h->part, h->nb_dot, st));
+  return mdot_reduce(h->part, h->nb_dot, 1, out, 0, st);
+}
+
+double absmax(ahoc_handle* h, const void* x, bool dbl, long long n, hipStream_t st, int* rc) {
+  const int nb = 1024;
+  *rc = dbl ? absmax_partial<double>(n, (const double*)x, h->red, nb, st)
+            : absmax_partial<float>(n, (const float*)x, h->red, nb, st);
+  if (*rc) return 0.0;
+  std::vector<double> hb(nb);
+  hipError_t e = hipMemcpyAsync(hb.data(), h->red, sizeof(double) * nb, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e), "absmax");
+    *rc = ST_HIP;
+    return 0.0;
+  }
+  double m = 0;
+  for (double v : hb) m = v > m ? v : m;
+  return m;
+}
+
+struct GmresResult {
+  int iters = 0;
+  double relres = 0;
+  bool converged = false;
+};
+
+// Restarted GMRES(m) on S_h x = b, x = 0 on entry.  All vectors FP64 on the device.
+template <typename T>
+int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
+          GmresResult& res, int* matvecs, hipStream_t st) {
+  const long long nq = h->g.nq;
+  const int m = h->m;
+  const int ldh = m + 1;
+  int rc = 0;
+  TRY(fill(nq, 0.0, x, st));
+  TRY(dot_dev(h, b, b, nq, h->nrm, st));
+  const double bnorm = std::sqrt(read_scalar(h, h->nrm, st, &rc));
+  TRY(rc);
+  res = GmresResult();
+  if (!(bnorm > 0)) {
+    res.converged = bnorm == 0;
+    return ST_OK;
+  }
+  bool first = true;
+  while (true) {
+    const double* r = b;
+    if (!first) {
+      TRY(matvec<T>(h, P, x, h->rvec, st));
+      ++*matvecs;
+      TRY(axpby(nq, 1.0, b, -1.0, h->rvec, st));  // r = b - S x
+      r = h->rvec;
+    }
+    first = false;
+    TRY(dot_dev(h, r, r, nq, h->nrm, st));
+    TRY(start_cycle(h->Vb, r, nq, h->nrm, h->gv, m, h->beta, st));
+    const double beta = read_scalar(h, h->beta, st, &rc);
+    TRY(rc);
+    res.relres = beta / bnorm;
+    if (beta <= tol * bnorm) {
+      res.converged = true;
+      return ST_OK;
+    }
+    if (res.iters >= max_iters) return ST_OK;
+    int jj = 0;
+    bool done = false;
+    for (int j = 0; j < m; ++j) {
+      double* vj = h->Vb + (long long)j * nq;
+      double* w = h->Vb + (long long)(j + 1) * nq;
+      TRY(matvec<T>(h, P, vj, w, st));
+      ++*matvecs;
+      TRY(mdot_partial(h->Vb, nq, j + 1, w, nq, h->part, h->nb_dot, st));
+      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, h->h1, 0, st));
+      TRY(maxpy(w, h->Vb, nq, j + 1, h->h1, -1.0, nq, st));
+      TRY(mdot_partial(h->Vb, nq, j + 1, w, nq, h->part, h->nb_dot, st));
+      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, h->h2, 0, st));
+      TRY(maxpy(w, h->Vb, nq, j + 1, h->h2, -1.0, nq, st));
+      TRY(dot_dev(h, w, w, nq, h->nrm, st));
+      TRY(givens_step(h->H, ldh, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
+      TRY(scale_by_inv(w, nq, h->resid, st));
+      ++res.iters;
+      jj = j + 1;
+      const double est = read_scalar(h, h->resid, st, &rc) / bnorm;
+      TRY(rc);
+      res.relres = est;
+      if (est <= tol) {
+        done = true;
+        res.converged = true;
+        break;
+      }
+      if (res.iters >= max_iters) break;
+    }
+    TRY(back_solve(h->H, ldh, h->gv, jj, h->y, st));
+    TRY(maxpy(x, h->Vb, nq, jj, h->y, 1.0, nq, st));
+    if (done || res.iters >= max_iters) return ST_OK;
+  }
+}
+
+int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
+  Geom& g = h->g;
+  make_geom(pb, g);
+  make_weights(g, h->w);
+  h->m = h->opt.restart;
+  // FP64 data
+  TRY(alloc_t(h, &h->ia64, g.nnodal));
+  TRY(alloc_t(h, &h->af64, g.nq));
+  TRY(alloc_t(h, &h->src_v, g.nint));
+  TRY(alloc_t(h, &h->src_q, g.nq));
+  if (pb->gD) {
+    TRY(alloc_t(h, &h->src_u, g.nint));
+    TRY(alloc_t(h, &h->gD, g.nnodal));
+    AHOC_HIP_TRY(hipMemcpyAsync(h->gD, pb->gD, sizeof(double) * g.nnodal, hipMemcpyDeviceToDevice, st));
+  }
+  TRY(alloc_t(h, &h->red, 1024));
+  TRY(alloc_t(h, &h->R, g.nq));
+  const bool mixed = h->opt.precision == AHOC_MIXED;
+  float* ia32 = nullptr;
+  float* af32 = nullptr;
+  if (mixed) {
+    TRY(alloc_t(h, &ia32, g.nnodal));
+    TRY(alloc_t(h, &af32, g.nq));
+  }
+  TRY(setup_inv_alpha(g.nnodal, pb->alpha, h->ia64, ia32, h->red, 1024, st));
+  {
+    std::vector<double> hb(1024);
+    AHOC_HIP_TRY(hipMemcpyAsync(hb.data(), h->red, sizeof(double) * 1024, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
+    double mn = 1e300;
+    for (double v : hb) mn = v < mn ? v : mn;
+    if (!(mn > 0.0)) {
+      set_last_error("alpha must be positive everywhere", "ahoc_setup");
+      return ST_INVALID;
+    }
+  }
+  TRY(setup_face_alpha(g, pb->alpha, h->af64, af32, st));
+  TRY(setup_sources(g, h->w, pb->f, pb->alpha, pb->gD, pb->gN, pb->lapgD, h->src_v, h->src_u,
+                    h->src_q, st));
+  if (pb->lapgD) {
+    // V = alpha * Delta u on edges and corners (Remark 1); read there only
+    TRY(alloc_t(h, &h->vedge, g.nnodal));
+    TRY(mul(g.nnodal, pb->alpha, pb->lapgD, h->vedge, st));
+  }
+  // FP64 machinery (plain solve, or the refinement's reference operators)
+  h->p64.ia = h->ia64;
+  h->p64.af = h->af64;
+  if (!mixed) TRY(prec_init<double>(h, h->p64, h->opt.tile_fp64, st));
+  if (mixed) {
+    h->p32.ia = ia32;
+    h->p32.af = af32;
+    TRY(prec_init<float>(h, h->p32, h->opt.tile_fp32, st));
+    TRY(alloc_t(h, &h->U64, g.nint));
+    TRY(alloc_t(h, &h->V64, g.nint));
+    TRY(alloc_t(h, &h->Q64, g.nq));
+    TRY(alloc_t(h, &h->ru, g.nint));
+    TRY(alloc_t(h, &h->rv, g.nint));
+    TRY(alloc_t(h, &h->rq, g.nq));
+  }
+  // Krylov workspace
+  const int m = h->m;
+  TRY(alloc_t(h, &h->Vb, (long long)(m + 1) * g.nq));
+  TRY(alloc_t(h, &h->H, (long long)(m + 1) * m));
+  TRY(alloc_t(h, &h->cs, m));
+  TRY(alloc_t(h, &h->sn, m));
+  TRY(alloc_t(h, &h->gv, m + 1));
+  TRY(alloc_t(h, &h->h1, m + 1));
+  TRY(alloc_t(h, &h->h2, m + 1));
+  TRY(alloc_t(h, &h->nrm, 2));
+  TRY(alloc_t(h, &h->resid, 2));
+  TRY(alloc_t(h, &h->beta, 2));
+  TRY(alloc_t(h, &h->y, m + 2));
+  TRY(alloc_t(h, &h->part, (long long)(m + 1) * h->nb_dot));
+  TRY(alloc_t(h, &h->bvec, g.nq));
+  TRY(alloc_t(h, &h->dq, g.nq));
+  TRY(alloc_t(h, &h->rvec, g.nq));
+  AHOC_HIP_TRY(hipMemsetAsync(h->H, 0, sizeof(double) * (m + 1) * m, st));
+  AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned), 64, hipHostMallocDefault));
+  AHOC_HIP_TRY(hipStreamSynchronize(st));
+  return ST_OK;
+}
+
+}  // namespace
+}  // namespace ahoc
+
+// ======================================================================================
+// C ABI
+// ======================================================================================
+
+extern "C" {
+
+void ahoc_default_options(ahoc_options* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->precision = AHOC_FP64;
+  o->restart = 30;
+  o->max_iters = 2000;
+  o->tol = 1e-12;
+  o->inner_tol = 1e-6;
+  o->sweep_tol = 1e-11;
+  o->max_sweeps = 8;
+  o->tile_fp64 = 0;
+  o->tile_fp32 = 0;
+}
+
+const char* ahoc_status_string(ahoc_status s) {
+  switch (s) {
+    case AHOC_OK: return "ok";
+    case AHOC_E_INVALID: return "invalid argument";
+    case AHOC_E_NOMEM: return "out of device memory";
+    case AHOC_E_NOCONV: return "not converged";
+    case AHOC_E_HIP: return "HIP runtime error";
+    case AHOC_E_UNSUPPORTED: return "unsupported size";
+  }
+  return "unknown status";
+}
+
+const char* ahoc_last_error(void) { return ahoc::g_err.c_str(); }
+
+void ahoc_destroy(ahoc_handle* h) {
+  if (!h) return;
+  (void)hipDeviceSynchronize();
+  ahoc::prec_free(h->p64);
+  ahoc::prec_free(h->p32);
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->pinned) (void)hipHostFree(h->pinned);
+  delete h;
+}
+
+size_t ahoc_nq(const ahoc_handle* h) { return h ? (size_t)h->g.nq : 0; }
+
+ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, void* stream, ahoc_handle** out) {
+  if (!pb || !out) return AHOC_E_INVALID;
+  *out = nullptr;
+  if (pb->dim != 2 && pb->dim != 3) {
+    ahoc::set_last_error("dim must be 2 or 3", "ahoc_setup");
+    return AHOC_E_INVALID;
+  }
+  if (!pb->alpha || !pb->f) {
+    ahoc::set_last_error("alpha and f are required", "ahoc_setup");
+    return AHOC_E_INVALID;
+  }
+  for (int a = 0; a < pb->dim; ++a) {
+    if (pb->n[a] < 8 || !(pb->hi[a] > pb->lo[a])) {
+      ahoc::set_last_error("need n[a] >= 8 and hi > lo", "ahoc_setup");
+      return AHOC_E_INVALID;
+    }
+    if (!ahoc::dst_supported(pb->n[a])) {
+      ahoc::set_last_error("no transform plan for this n (use 2^a or 3*2^a)", "ahoc_setup");
+      return AHOC_E_UNSUPPORTED;
+    }
+  }
+  ahoc_handle* h = new ahoc_handle();
+  if (opt) h->opt = *opt;
+  else ahoc_default_options(&h->opt);
+  if (h->opt.restart < 1 || h->opt.restart > 200) h->opt.restart = 30;
+  if (h->opt.precision != AHOC_FP64 && h->opt.precision != AHOC_MIXED) {
+    delete h;
+    return AHOC_E_INVALID;
+  }
+  const int rc = ahoc::setup_impl(pb, (hipStream_t)stream, h);
+  if (rc) {
+    ahoc_destroy(h);
+    return (ahoc_status)rc;
+  }
+  *out = h;
+  return AHOC_OK;
+}
+
+ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* stream) {
+  if (!h || !q || !y) return AHOC_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = h->opt.precision == AHOC_MIXED ? ahoc::matvec<float>(h, h->p32, q, y, st)
+                                          : ahoc::matvec<double>(h, h->p64, q, y, st);
+  return (ahoc_status)rc;
+}
+
+ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream) {
+  if (!h || !b) return AHOC_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (h->opt.precision == AHOC_MIXED) {
+    using namespace ahoc;
+    rc = convert<double, float>(h->g.nint, h->src_v, h->rv, st);
+    if (!rc && h->src_u) rc = convert<double, float>(h->g.nint, h->src_u, h->ru, st);
+    if (!rc) rc = convert<double, float>(h->g.nq, h->src_q, h->rq, st);
+    if (!rc) rc = schur_rhs<float>(h, h->p32, h->rv, h->src_u ? h->ru : nullptr, h->rq, b, st);
+  } else {
+    rc = ahoc::schur_rhs<double>(h, h->p64, h->src_v, h->src_u, h->src_q, b, st);
+  }
+  return (ahoc_status)rc;
+}
+
+ahoc_status ahoc_poisson(ahoc_handle* h, const double* gin, double* wout, void* stream) {
+  if (!h || !gin || !wout) return AHOC_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  using namespace ahoc;
+  int rc;
+  if (h->opt.precision == AHOC_MIXED) {
+    rc = convert<double, float>(h->g.nint, gin, h->p32.bufA, st);
+    if (!rc) rc = poisson<float>(h, h->p32, h->p32.bufA, h->p32.scP, st);
+    if (!rc) rc = convert<float, double>(h->g.nint, h->p32.bufA, wout, st);
+  } else {
+    rc = convert<double, double>(h->g.nint, gin, h->p64.bufA, st);
+    if (!rc) rc = poisson<double>(h, h->p64, h->p64.bufA, h->p64.scP, st);
+    if (!rc) rc = convert<double, double>(h->g.nint, h->p64.bufA, wout, st);
+  }
+  return (ahoc_status)rc;
+}
+
+}  // extern "C"
+
+namespace ahoc {
+namespace {
+
+int solve_fp64(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+  Prec<double>& P = h->p64;
+  GmresResult gr;
+  int mv = 0;
+  TRY(schur_rhs<double>(h, P, h->src_v, h->src_u, h->src_q, h->bvec, st));
+  TRY(gmres<double>(h, P, h->bvec, h->dq, h->opt.tol, h->opt.max_iters, gr, &mv, st));
+  TRY(vsolve<double>(h, P, h->dq, h->src_v, st));
+  TRY(usolve<double>(h, P, h->dq, h->src_u, st));
+  TRY(out_u<double>(h->g, P.bufB, h->gD, u, st));
+  if (v) TRY(out_v<double>(h->g, P.bufA, h->dq, h->vedge, v, st));
+  if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->dq, sizeof(double) * h->g.nq, hipMemcpyDeviceToDevice, st));
+  AHOC_HIP_TRY(hipStreamSynchronize(st));
+  s->converged = gr.converged;
+  s->gmres_iters = gr.iters;
+  s->sweeps = 1;
+  s->matvecs = mv;
+  s->schur_relres = gr.relres;
+  s->last_update = 0;
+  return gr.converged ? ST_OK : ST_NOCONV;
+}
+
+int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+  Prec<float>& P = h->p32;
+  const Geom& g = h->g;
+  int rc = 0;
+  TRY(fill(g.nint, 0.0, h->U64, st));
+  TRY(fill(g.nint, 0.0, h->V64, st));
+  TRY(fill(g.nq, 0.0, h->Q64, st));
+  int iters = 0, mv = 0, sweeps = 0;
+  double prev = 0, upd = 0, relres = 0;
+  bool conv = false;
+  for (int sw = 0; sw < h->opt.max_sweeps; ++sw) {
+    // residual of the coupled system at the current FP64 state (the data itself at sweep 0)
+    const float* su = h->ru;
+    if (sw == 0) {
+      TRY(convert<double, float>(g.nint, h->src_v, h->rv, st));
+      if (h->src_u) TRY(convert<double, float>(g.nint, h->src_u, h->ru, st));
+      else su = nullptr;
+      TRY(convert<double, float>(g.nq, h->src_q, h->rq, st));
+    } else {
+      TRY(resid64<float>(g, h->w, h->U64, h->V64, h->Q64, h->ia64, h->af64, h->src_u, h->src_v,
+                         h->src_q, h->ru, h->rv, h->rq, st));
+    }
+    // correction: Schur solve in FP32 operators with FP64 Krylov, then recovery
+    GmresResult gr;
+    TRY(schur_rhs<float>(h, P, h->rv, su, h->rq, h->bvec, st));
+    TRY(gmres<float>(h, P, h->bvec, h->dq, h->opt.inner_tol, h->opt.max_iters, gr, &mv, st));
+    iters += gr.iters;
+    relres = gr.relres;
+    TRY(convert<double, float>(g.nq, h->dq, P.qT, st));
+    TRY(vsolve<float>(h, P, P.qT, h->rv, st));
+    TRY(usolve<float>(h, P, P.qT, su, st));
+    TRY(accumulate<float>(g.nint, P.bufB, h->U64, st));
+    TRY(accumulate<float>(g.nint, P.bufA, h->V64, st));
+    TRY(accumulate<double>(g.nq, h->dq, h->Q64, st));
+    ++sweeps;
+    const double du = absmax(h, P.bufB, false, g.nint, st, &rc);
+    TRY(rc);
+    const double un = absmax(h, h->U64, true, g.nint, st, &rc);
+    TRY(rc);
+    upd = un > 0 ? du / un : 0.0;
+    // remaining change estimated from the observed contraction of the updates
+    if (upd <= h->opt.sweep_tol * 1e-3) {
+      conv = true;
+      break;
+    }
+    if (sw > 0 && prev > 0) {
+      const double rho = upd / prev;
+      if (rho < 1.0 && upd * rho / (1.0 - rho) <= h->opt.sweep_tol) {
+        conv = true;
+        break;
+      }
+    }
+    prev = upd;
+  }
+  TRY(out_u<double>(g, h->U64, h->gD, u, st));
+  if (v) TRY(out_v<double>(g, h->V64, h->Q64, h->vedge, v, st));
+  if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->Q64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
+  AHOC_HIP_TRY(hipStreamSynchronize(st));
+  s->converged = conv;
+  s->gmres_iters = iters;
+  s->sweeps = sweeps;
+  s->matvecs = mv;
+  s->schur_relres = relres;
+  s->last_update = upd;
+  return conv ? ST_OK : ST_NOCONV;
+}
+
+}  // namespace
+}  // namespace ahoc
+
+extern "C" {
+
+ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* stats, void* stream) {
+  if (!h || !u) return AHOC_E_INVALID;
+  ahoc_stats local;
+  std::memset(&local, 0, sizeof(local));
+  hipStream_t st = (hipStream_t)stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, u, v, q, &local, st)
+                                          : ahoc::solve_fp64(h, u, v, q, &local, st);
+  const auto t1 = std::chrono::steady_clock::now();
+  local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  if (stats) *stats = local;
+  return (ahoc_status)rc;
+}
+
+ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_options* opt,
+                               double* const* u, ahoc_stats* stats, void* stream) {
+  if (count < 0 || (count > 0 && (!probs || !u))) return AHOC_E_INVALID;
+  ahoc_status first = AHOC_OK;
+  for (int i = 0; i < count; ++i) {
+    ahoc_handle* h = nullptr;
+    ahoc_status rc = ahoc_setup(&probs[i], opt, stream, &h);
+    if (rc == AHOC_OK) {
+      rc = ahoc_solve(h, u[i], nullptr, nullptr, stats ? &stats[i] : nullptr, stream);
+      ahoc_destroy(h);
+    }
+    if (rc != AHOC_OK && first == AHOC_OK) first = rc;
+  }
+  return first;
+}
+
+ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const void* in, void* out,
+                      void* stream) {
+  using namespace ahoc;
+  if (!nint || !in || !out || (dim != 2 && dim != 3) || axis < 0 || axis >= dim) return AHOC_E_INVALID;
+  long long ni[3] = {1, 1, 1};
+  for (int a = 0; a < dim; ++a) {
+    if (nint[a] < 1) return AHOC_E_INVALID;
+    ni[a] = nint[a];
+  }
+  const int N = (int)ni[axis] + 1;
+  if (!dst_supported(N)) return AHOC_E_UNSUPPORTED;
+  long long inner = 1, outer = 1;
+  for (int a = 0; a < axis; ++a) inner *= ni[a];
+  for (int a = axis + 1; a < 3; ++a) outer *= ni[a];
+  if (axis == 0) {
+    outer = ni[1] * ni[2];
+    inner = 1;
+  }
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, void*> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  hipStream_t st = (hipStream_t)stream;
+  int rc;
+  if (precision == AHOC_MIXED) {
+    auto key = std::make_pair(N, 4);
+    DstTables<float>* tb = (DstTables<float>*)cache[key];
+    if (!tb) {
+      tb = new DstTables<float>();
+      if ((rc = dst_tables_init<float>(*tb, N))) { delete tb; return (ahoc_status)rc; }
+      cache[key] = tb;
+    }
+    rc = dst_pass<float>(*tb, (const float*)in, (float*)out, outer, inner, nullptr, 0, st);
+  } else if (precision == AHOC_FP64) {
+    auto key = std::make_pair(N, 8);
+    DstTables<double>* tb = (DstTables<double>*)cache[key];
+    if (!tb) {
+      tb = new DstTables<double>();
+      if ((rc = dst_tables_init<double>(*tb, N))) { delete tb; return (ahoc_status)rc; }
+      cache[key] = tb;
+    }
+    rc = dst_pass<double>(*tb, (const double*)in, (double*)out, outer, inner, nullptr, 0, st);
+  } else {
+    return AHOC_E_INVALID;
+  }
+  return (ahoc_status)rc;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Shared device/host definitions of the HIP implementation (gfx950).
+//
+// Layout conventions (all arrays):
+//   nodal arrays      (N_z+1)(N_y+1)(N_x+1) doubles, x fastest (2-D: (N_y+1)(N_x+1))
+//   interior arrays   (N_z-1)(N_y-1)(N_x-1) in the working precision, x fastest
+//   augmented vector  Q: faces x-, x+, y-, y+[, z-, z+]; inside a face the two
+//                     tangential axes row-major, lower axis fastest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ahoc {
+
+template <typename T> struct Cx;
+template <> struct Cx<float> { using type = float2; };
+template <> struct Cx<double> { using type = double2; };
+template <typename T> using cx = typename Cx<T>::type;
+
+// Grid geometry of one instance.
+struct Geom {
+  int dim;
+  int n[3];          // intervals N_a (unused axes: 2)
+  int ni[3];         // interior counts N_a - 1 (unused axes: 1)
+  int nn[3];         // nodal counts N_a + 1 (unused axes: 1)
+  double h[3];       // spacings
+  long long nint;    // prod ni
+  long long nnodal;  // prod nn
+  int nq;            // augmented unknowns
+  int face_off[7];   // start of each face in Q, face f = 2*axis + side
+};
+
+// Weights of the compact operators, by offset class.
+//   3-D L_h: centre, face neighbours (+-x, +-y, +-z), edge neighbours (xy, xz, yz)
+//   2-D L_h: centre, (+-x), (+-y), corners (xy)
+//   M:       centre m0 and the 2*dim face neighbours m1
+struct Weights {
+  double c0;
+  double cf[3];
+  double ce[3];  // ce[0] = xy, ce[1] = xz, ce[2] = yz
+  double m0, m1;
+  double os[4];  // one-sided normal weights a_0..a_3
+  double os_gn;  // Neumann weight 11/3
+};
+
+// Status codes of the C ABI (mirrors include/ahoc.h).
+enum : int { ST_OK = 0, ST_INVALID = -1, ST_NOMEM = -2, ST_NOCONV = -3, ST_HIP = -4,
+             ST_UNSUPPORTED = -5 };
+
+#define AHOC_HIP_TRY(...)                                      \
+  do {                                                         \
+    hipError_t e__ = (__VA_ARGS__);                            \
+    if (e__ != hipSuccess) {                                   \
+      ahoc::set_last_error(hipGetErrorString(e__), #__VA_ARGS__); \
+      return ahoc::ST_HIP;                                     \
+    }                                                          \
+  } while (0)
+
+void set_last_error(const char* what, const char* where);
+
+// ------------------------------------------------------------------------------------
+// DST-I passes (dst.hip)
+// ------------------------------------------------------------------------------------
+
+// Precomputed tables for one transform length N (pencil length N-1).
+template <typename T> struct DstTables {
+  int N = 0;
+  int ppt = 0;        // points per thread (compile-time variant selector)
+  int nrad = 0;
+  int rad[12] = {0};  // radix sequence, product N
+  cx<T>* tw = nullptr;   // exp(-2 pi i k / N), k = 0..N-1
+  T* sn = nullptr;       // sin(pi m / N), m = 0..N/2
+};
+
+// Eigen-scaling parameters for the fused middle pass along the slowest axis.
+template <typename T> struct DstScale {
+  const T* s_this = nullptr;  // s_t(k), k = 1..n_t   (length n_t)
+  const T* s_a = nullptr;     // fastest other axis, length n_a
+  const T* s_b = nullptr;     // second other axis (3-D), length n_b, or null
+  int na = 1;                 // column decode: col = ia + na * ib
+  T c_ta = 0, c_tb = 0, c_ab = 0;
+  T scale = 0;                // sign * prod_a 2/N_a
+};
+
+// One pass of the batched DST-I along an axis of an interior array viewed as
+// [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils (rows).
+template <typename T>
+int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
+             const DstScale<T>* fused, int tile_seqs, hipStream_t st);
+
+template <typename T> int dst_tables_init(DstTables<T>& tb, int N);
+template <typename T> void dst_tables_free(DstTables<T>& tb);
+bool dst_supported(int N);
+int dst_ppt(int N);
+int dst_default_tile(int N, int elem_bytes);
+
+}  // namespace ahoc

@@ -1,0 +1,531 @@
+// Grid-stencil kernels of the augmented scheme (gfx950).
+//
+//   lift      G = src + L_h^bnd[Q]      right-hand side of the v-equation
+//                                       (-L_h V = M f, V = Q on face interiors)
+//   rhs_u     G = src + M(V / alpha)    right-hand side of the u-equation, with
+//                                       V = Q on the face-interior nodes M reaches
+//   gather    R = alpha_b h^-2 (6 U1 - 3/2 U2 + 2/9 U3) - Q - src_q
+//                                       boundary residual of Lemma 1 (one-sided
+//                                       normal formula of Sec. 2.2, known data in src_q)
+//   resid64   FP64 residual of the coupled system (iterative refinement)
+//   setup     1/alpha, alpha on faces, M f and the data lifts
+//
+// All are memory-bound streaming kernels: one thread per node, neighbours come
+// through L1/L2.  Interior arrays use the working precision T; data, the
+// refinement state and the Krylov vectors are FP64.
+#include "common.h"
+#include "kernels.h"
+
+namespace ahoc {
+
+namespace {
+
+constexpr int TPB = 256;
+
+inline unsigned nblocks(long long n) {
+  long long b = (n + TPB - 1) / TPB;
+  if (b > 1048576) b = 1048576;
+  return (unsigned)(b < 1 ? 1 : b);
+}
+
+__device__ __forceinline__ long long nod(const Geom& g, int i, int j, int k) {
+  return ((long long)k * g.nn[1] + j) * g.nn[0] + i;
+}
+__device__ __forceinline__ long long inr(const Geom& g, int i, int j, int k) {
+  return ((long long)(k - 1) * g.ni[1] + (j - 1)) * g.ni[0] + (i - 1);
+}
+
+// number of coordinates of node (i,j,k) on the boundary
+template <int DIM> __device__ __forceinline__ int nbnd(const Geom& g, int i, int j, int k) {
+  int c = (i == 0 || i == g.n[0]) + (j == 0 || j == g.n[1]);
+  if (DIM == 3) c += (k == 0 || k == g.n[2]);
+  return c;
+}
+
+// Q index of a face-interior node.
+template <int DIM> __device__ __forceinline__ int qidx(const Geom& g, int i, int j, int k) {
+  if (i == 0 || i == g.n[0]) {
+    const int f = (i == 0) ? 0 : 1;
+    return g.face_off[f] + (DIM == 3 ? (k - 1) * g.ni[1] : 0) + (j - 1);
+  }
+  if (j == 0 || j == g.n[1]) {
+    const int f = (j == 0) ? 2 : 3;
+    return g.face_off[f] + (DIM == 3 ? (k - 1) * g.ni[0] : 0) + (i - 1);
+  }
+  const int f = (k == 0) ? 4 : 5;
+  return g.face_off[f] + (j - 1) * g.ni[0] + (i - 1);
+}
+
+// decode a linear interior index into (i, j, k), 1-based
+template <int DIM> __device__ __forceinline__ void dec_int(const Geom& g, long long e, int& i, int& j, int& k) {
+  i = (int)(e % g.ni[0]) + 1;
+  long long r = e / g.ni[0];
+  if (DIM == 3) {
+    j = (int)(r % g.ni[1]) + 1;
+    k = (int)(r / g.ni[1]) + 1;
+  } else {
+    j = (int)r + 1;
+    k = 0;
+  }
+}
+
+// decode Q index -> boundary node, face axis and inward step
+template <int DIM>
+__device__ __forceinline__ void dec_q(const Geom& g, int q, int& i, int& j, int& k, int& axis, int& step) {
+  int f = 0;
+  while (f + 1 < 2 * DIM && q >= g.face_off[f + 1]) ++f;
+  const int t = q - g.face_off[f];
+  axis = f >> 1;
+  const int side = f & 1;
+  step = side ? -1 : 1;
+  const int fix = side ? g.n[axis] : 0;
+  if (DIM == 2) {
+    k = 0;
+    if (axis == 0) { i = fix; j = t + 1; }
+    else { j = fix; i = t + 1; }
+  } else {
+    if (axis == 0) { i = fix; j = t % g.ni[1] + 1; k = t / g.ni[1] + 1; }
+    else if (axis == 1) { j = fix; i = t % g.ni[0] + 1; k = t / g.ni[0] + 1; }
+    else { k = fix; i = t % g.ni[0] + 1; j = t / g.ni[0] + 1; }
+  }
+}
+
+// weight of L_h at offset (dx, dy, dz); 0 for offsets outside the compact stencil
+template <int DIM> __device__ __forceinline__ double lw(const Weights& w, int dx, int dy, int dz) {
+  const int nz = (dx != 0) + (dy != 0) + (dz != 0);
+  if (nz == 0) return w.c0;
+  if (nz == 1) return dx ? w.cf[0] : (dy ? w.cf[1] : w.cf[2]);
+  if (nz == 2) {
+    if (DIM == 2) return w.ce[0];
+    return dz == 0 ? w.ce[0] : (dy == 0 ? w.ce[1] : w.ce[2]);
+  }
+  return 0.0;
+}
+
+// ---------------------------------------------------------------------------------
+template <typename T, int DIM>
+__global__ void k_lift(Geom g, Weights w, const T* __restrict__ Q, const T* __restrict__ src,
+                       T* __restrict__ G) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    dec_int<DIM>(g, e, i, j, k);
+    T acc = src ? src[e] : T(0);
+    const bool nearb = i == 1 || i == g.ni[0] || j == 1 || j == g.ni[1] ||
+                       (DIM == 3 && (k == 1 || k == g.ni[2]));
+    if (nearb) {
+      const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+      for (int dz = zlo; dz <= zhi; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const double wt = lw<DIM>(w, dx, dy, dz);
+            if (wt == 0.0 || (dx == 0 && dy == 0 && dz == 0)) continue;
+            const int qi = i + dx, qj = j + dy, qk = k + dz;
+            if (nbnd<DIM>(g, qi, qj, qk) == 1) acc += (T)wt * Q[qidx<DIM>(g, qi, qj, qk)];
+          }
+    }
+    G[e] = acc;
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_rhs_u(Geom g, Weights w, const T* __restrict__ V, const T* __restrict__ Q,
+                        const T* __restrict__ ia, const T* __restrict__ src, T* __restrict__ G) {
+  const T m0 = (T)w.m0, m1 = (T)w.m1;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    dec_int<DIM>(g, e, i, j, k);
+    T acc = src ? src[e] : T(0);
+    acc += m0 * V[e] * ia[nod(g, i, j, k)];
+    T nb = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int s = -1; s <= 1; s += 2) {
+        const int qi = i + (a == 0 ? s : 0), qj = j + (a == 1 ? s : 0), qk = k + (a == 2 ? s : 0);
+        const bool bnd = (a == 0 && (qi == 0 || qi == g.n[0])) || (a == 1 && (qj == 0 || qj == g.n[1])) ||
+                         (a == 2 && (qk == 0 || qk == g.n[2]));
+        const T vq = bnd ? Q[qidx<DIM>(g, qi, qj, qk)] : V[inr(g, qi, qj, DIM == 3 ? qk : 1)];
+        nb += vq * ia[nod(g, qi, qj, qk)];
+      }
+    G[e] = acc + m1 * nb;
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __restrict__ Q,
+                         const T* __restrict__ af, const T* __restrict__ srcq, double* __restrict__ R) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    T u[3];
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      const int ui = i + (ax == 0 ? st * m : 0), uj = j + (ax == 1 ? st * m : 0),
+                uk = k + (ax == 2 ? st * m : 0);
+      u[m - 1] = U[inr(g, ui, uj, DIM == 3 ? uk : 1)];
+    }
+    const T ih2 = (T)(1.0 / (g.h[ax] * g.h[ax]));
+    T r = af[q] * ih2 * ((T)w.os[1] * u[0] + (T)w.os[2] * u[1] + (T)w.os[3] * u[2]) - Q[q];
+    if (srcq) r -= srcq[q];
+    R[q] = (double)r;
+  }
+}
+
+// FP64 residual of the coupled system at the interior nodes:
+//   r_v = src_v + L_h[V]            (V = interior V, Q on face interiors, 0 on edges)
+//   r_u = src_u + M(V/alpha) - L_h[U]   (U = interior U, 0 on the boundary)
+template <typename T, int DIM>
+__global__ void k_resid_vol(Geom g, Weights w, const double* __restrict__ U, const double* __restrict__ V,
+                            const double* __restrict__ Q, const double* __restrict__ ia,
+                            const double* __restrict__ src_u, const double* __restrict__ src_v,
+                            T* __restrict__ ru, T* __restrict__ rv) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    dec_int<DIM>(g, e, i, j, k);
+    double lv = 0, lu = 0, mv = 0;
+    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wt = lw<DIM>(w, dx, dy, dz);
+          if (wt == 0.0) continue;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          const int nb = nbnd<DIM>(g, qi, qj, qk);
+          double vq = 0, uq = 0;
+          if (nb == 0) {
+            const long long qe = inr(g, qi, qj, DIM == 3 ? qk : 1);
+            vq = V[qe];
+            uq = U[qe];
+          } else if (nb == 1) {
+            vq = Q[qidx<DIM>(g, qi, qj, qk)];
+          }
+          lv += wt * vq;
+          lu += wt * uq;
+          const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
+          if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * vq * ia[nod(g, qi, qj, qk)];
+        }
+    rv[e] = (T)(src_v[e] + lv);
+    ru[e] = (T)((src_u ? src_u[e] : 0.0) + mv - lu);
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_resid_q(Geom g, Weights w, const double* __restrict__ U, const double* __restrict__ Q,
+                          const double* __restrict__ af, const double* __restrict__ src_q,
+                          T* __restrict__ rq) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    double u[3];
+#pragma unroll
+    for (int m = 1; m <= 3; ++m) {
+      const int ui = i + (ax == 0 ? st * m : 0), uj = j + (ax == 1 ? st * m : 0),
+                uk = k + (ax == 2 ? st * m : 0);
+      u[m - 1] = U[inr(g, ui, uj, DIM == 3 ? uk : 1)];
+    }
+    const double ih2 = 1.0 / (g.h[ax] * g.h[ax]);
+    const double G = af[q] * ih2 * (w.os[1] * u[0] + w.os[2] * u[1] + w.os[3] * u[2]);
+    rq[q] = (T)((src_q ? src_q[q] : 0.0) + Q[q] - G);
+  }
+}
+
+// ---------------------------------------------------------------------------------
+// setup (FP64 inputs)
+
+__global__ void k_inv_alpha(long long n, const double* __restrict__ alpha, double* __restrict__ ia64,
+                            float* __restrict__ ia32, double* __restrict__ bmin) {
+  __shared__ double red[TPB];
+  double mn = 1e300;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double a = alpha[e];
+    mn = fmin(mn, a);
+    const double r = 1.0 / a;
+    ia64[e] = r;
+    if (ia32) ia32[e] = (float)r;
+  }
+  red[threadIdx.x] = mn;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bmin[blockIdx.x] = red[0];
+}
+
+template <int DIM>
+__global__ void k_face_alpha(Geom g, const double* __restrict__ alpha, double* __restrict__ af64,
+                             float* __restrict__ af32) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    const double a = alpha[nod(g, i, j, k)];
+    af64[q] = a;
+    if (af32) af32[q] = (float)a;
+  }
+}
+
+// src_v = M f + (L_h contributions of the known edge/corner values V = alpha * lapgD)
+// src_u = -(L_h contributions of U = g_D on the boundary)
+template <int DIM>
+__global__ void k_src_vol(Geom g, Weights w, const double* __restrict__ f, const double* __restrict__ alpha,
+                          const double* __restrict__ gD, const double* __restrict__ lapgD,
+                          double* __restrict__ src_v, double* __restrict__ src_u) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    dec_int<DIM>(g, e, i, j, k);
+    double mf = w.m0 * f[nod(g, i, j, k)];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int s = -1; s <= 1; s += 2)
+        mf += w.m1 * f[nod(g, i + (a == 0 ? s : 0), j + (a == 1 ? s : 0), k + (a == 2 ? s : 0))];
+    double ev = 0, eu = 0;
+    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wt = lw<DIM>(w, dx, dy, dz);
+          if (wt == 0.0) continue;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          const int nb = nbnd<DIM>(g, qi, qj, qk);
+          if (nb == 0) continue;
+          const long long qn = nod(g, qi, qj, qk);
+          if (nb >= 2 && lapgD) ev += wt * alpha[qn] * lapgD[qn];
+          if (gD) eu += wt * gD[qn];
+        }
+    src_v[e] = mf + ev;
+    if (src_u) src_u[e] = -eu;
+  }
+}
+
+// src_q = -alpha_b [ a_0 g_D / h^2 + (11/3) g_N / h + lapgD ]   (known part of the q-row)
+template <int DIM>
+__global__ void k_src_q(Geom g, Weights w, const double* __restrict__ alpha, const double* __restrict__ gD,
+                        const double* __restrict__ gN, const double* __restrict__ lapgD,
+                        double* __restrict__ src_q) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    const long long b = nod(g, i, j, k);
+    const double h = g.h[ax];
+    double t = 0;
+    if (gD) t += w.os[0] * gD[b] / (h * h);
+    if (gN) t += w.os_gn * gN[b] / h;
+    if (lapgD) t += lapgD[b];
+    src_q[q] = -alpha[b] * t;
+  }
+}
+
+// nodal outputs
+template <typename T, int DIM>
+__global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restrict__ gD, double* __restrict__ u) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nnodal;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % g.nn[0]);
+    const long long r = e / g.nn[0];
+    const int j = (int)(r % g.nn[1]);
+    const int k = (int)(r / g.nn[1]);
+    const int nb = nbnd<DIM>(g, i, j, k);
+    u[e] = nb == 0 ? (double)Ui[inr(g, i, j, DIM == 3 ? k : 1)] : (gD ? gD[e] : 0.0);
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_out_v(Geom g, const T* __restrict__ Vi, const double* __restrict__ Q,
+                        const double* __restrict__ vedge, double* __restrict__ v) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nnodal;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % g.nn[0]);
+    const long long r = e / g.nn[0];
+    const int j = (int)(r % g.nn[1]);
+    const int k = (int)(r / g.nn[1]);
+    const int nb = nbnd<DIM>(g, i, j, k);
+    double val;
+    if (nb == 0) val = (double)Vi[inr(g, i, j, DIM == 3 ? k : 1)];
+    else if (nb == 1) val = Q[qidx<DIM>(g, i, j, k)];
+    else val = vedge ? vedge[e] : 0.0;
+    v[e] = val;
+  }
+}
+
+template <typename Ti, typename To>
+__global__ void k_cvt(long long n, const Ti* __restrict__ in, To* __restrict__ out) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    out[e] = (To)in[e];
+}
+
+template <typename Tx>
+__global__ void k_acc(long long n, const Tx* __restrict__ x, double* __restrict__ y) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    y[e] += (double)x[e];
+}
+
+template <typename Tx>
+__global__ void k_absmax(long long n, const Tx* __restrict__ x, double* __restrict__ bmax) {
+  __shared__ double red[TPB];
+  double m = 0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    m = fmax(m, fabs((double)x[e]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+}
+
+__global__ void k_mul(long long n, const double* __restrict__ a, const double* __restrict__ b,
+                      double* __restrict__ out) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    out[e] = a[e] * b[e];
+}
+
+__global__ void k_fill(long long n, double v, double* __restrict__ x) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    x[e] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------
+// launchers
+
+#define LAUNCH_DIM(KER, grid, ...)                                                     \
+  do {                                                                                 \
+    if (g.dim == 3) hipLaunchKernelGGL((KER<3>), grid, dim3(TPB), 0, st, __VA_ARGS__); \
+    else hipLaunchKernelGGL((KER<2>), grid, dim3(TPB), 0, st, __VA_ARGS__);           \
+    AHOC_HIP_TRY(hipGetLastError());                                                   \
+  } while (0)
+
+#define LAUNCH_TDIM(KER, T, grid, ...)                                                     \
+  do {                                                                                     \
+    if (g.dim == 3) hipLaunchKernelGGL((KER<T, 3>), grid, dim3(TPB), 0, st, __VA_ARGS__);  \
+    else hipLaunchKernelGGL((KER<T, 2>), grid, dim3(TPB), 0, st, __VA_ARGS__);            \
+    AHOC_HIP_TRY(hipGetLastError());                                                       \
+  } while (0)
+
+template <typename T>
+int lift(const Geom& g, const Weights& w, const T* Q, const T* src, T* G, hipStream_t st) {
+  LAUNCH_TDIM(k_lift, T, dim3(nblocks(g.nint)), g, w, Q, src, G);
+  return ST_OK;
+}
+
+template <typename T>
+int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
+          hipStream_t st) {
+  LAUNCH_TDIM(k_rhs_u, T, dim3(nblocks(g.nint)), g, w, V, Q, ia, src, G);
+  return ST_OK;
+}
+
+template <typename T>
+int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af, const T* srcq,
+           double* R, hipStream_t st) {
+  LAUNCH_TDIM(k_gather, T, dim3(nblocks(g.nq)), g, w, U, Q, af, srcq, R);
+  return ST_OK;
+}
+
+template <typename T>
+int resid64(const Geom& g, const Weights& w, const double* U, const double* V, const double* Q,
+            const double* ia, const double* af, const double* src_u, const double* src_v,
+            const double* src_q, T* ru, T* rv, T* rq, hipStream_t st) {
+  LAUNCH_TDIM(k_resid_vol, T, dim3(nblocks(g.nint)), g, w, U, V, Q, ia, src_u, src_v, ru, rv);
+  LAUNCH_TDIM(k_resid_q, T, dim3(nblocks(g.nq)), g, w, U, Q, af, src_q, rq);
+  return ST_OK;
+}
+
+int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32, double* bmin,
+                    int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_inv_alpha, dim3(nb), dim3(TPB), 0, st, n, alpha, ia64, ia32, bmin);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st) {
+  LAUNCH_DIM(k_face_alpha, dim3(nblocks(g.nq)), g, alpha, af64, af32);
+  return ST_OK;
+}
+
+int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
+                  const double* gD, const double* gN, const double* lapgD, double* src_v,
+                  double* src_u, double* src_q, hipStream_t st) {
+  LAUNCH_DIM(k_src_vol, dim3(nblocks(g.nint)), g, w, f, alpha, gD, lapgD, src_v, src_u);
+  LAUNCH_DIM(k_src_q, dim3(nblocks(g.nq)), g, w, alpha, gD, gN, lapgD, src_q);
+  return ST_OK;
+}
+
+template <typename T>
+int out_u(const Geom& g, const T* Ui, const double* gD, double* u, hipStream_t st) {
+  LAUNCH_TDIM(k_out_u, T, dim3(nblocks(g.nnodal)), g, Ui, gD, u);
+  return ST_OK;
+}
+
+template <typename T>
+int out_v(const Geom& g, const T* Vi, const double* Q, const double* vedge, double* v, hipStream_t st) {
+  LAUNCH_TDIM(k_out_v, T, dim3(nblocks(g.nnodal)), g, Vi, Q, vedge, v);
+  return ST_OK;
+}
+
+int mul(long long n, const double* a, const double* b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_mul, dim3(nblocks(n)), dim3(TPB), 0, st, n, a, b, out);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+template <typename Ti, typename To>
+int convert(long long n, const Ti* in, To* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_cvt<Ti, To>), dim3(nblocks(n)), dim3(TPB), 0, st, n, in, out);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+template <typename Tx> int accumulate(long long n, const Tx* x, double* y, hipStream_t st) {
+  hipLaunchKernelGGL((k_acc<Tx>), dim3(nblocks(n)), dim3(TPB), 0, st, n, x, y);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+template <typename Tx>
+int absmax_partial(long long n, const Tx* x, double* bmax, int nb, hipStream_t st) {
+  hipLaunchKernelGGL((k_absmax<Tx>), dim3(nb), dim3(TPB), 0, st, n, x, bmax);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int fill(long long n, double v, double* x, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill, dim3(nblocks(n)), dim3(TPB), 0, st, n, v, x);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+#define INST_T(T)                                                                                  \
+  template int lift<T>(const Geom&, const Weights&, const T*, const T*, T*, hipStream_t);         \
+  template int rhs_u<T>(const Geom&, const Weights&, const T*, const T*, const T*, const T*, T*,   \
+                        hipStream_t);                                                              \
+  template int gather<T>(const Geom&, const Weights&, const T*, const T*, const T*, const T*,       \
+                         double*, hipStream_t);                                                    \
+  template int resid64<T>(const Geom&, const Weights&, const double*, const double*, const double*, \
+                          const double*, const double*, const double*, const double*,              \
+                          const double*, T*, T*, T*, hipStream_t);                                 \
+  template int out_u<T>(const Geom&, const T*, const double*, double*, hipStream_t);               \
+  template int out_v<T>(const Geom&, const T*, const double*, const double*, double*, hipStream_t); \
+  template int accumulate<T>(long long, const T*, double*, hipStream_t);                           \
+  template int absmax_partial<T>(long long, const T*, double*, int, hipStream_t);
+
+INST_T(float)
+INST_T(double)
+template int convert<double, float>(long long, const double*, float*, hipStream_t);
+template int convert<float, double>(long long, const float*, double*, hipStream_t);
+template int convert<double, double>(long long, const double*, double*, hipStream_t);
+
+}  // namespace ahoc

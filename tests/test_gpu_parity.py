@@ -1,0 +1,227 @@
+"""GPU parity of the HIP path against the CPU oracle (through the C ABI).
+
+Element-by-element comparisons on seeded inputs, at sizes the oracle finishes
+in seconds that span several work-group tiles and ragged tails:
+
+* DST-I passes (every axis, both precisions, radix-2/3 lengths) vs the naive sum;
+* the DST Poisson solve vs the oracle's library-transform solve;
+* ahoc_schur_apply / ahoc_schur_rhs vs the explicitly eliminated S_h and b;
+* ahoc_solve (FP64) vs the direct sparse solve of the coupled system;
+* mixed precision vs the FP64 path (<= 1e-10 relative, max norm on U);
+* polynomial exactness and fourth-order convergence at larger N.
+
+Tolerances: FP64 transforms 1e-12 relative to the largest output (the naive
+sum itself is accurate to ~1e-15; the paired transform's odd outputs carry an
+O(sqrt(N)) prefix-sum growth); FP32 transforms 2e-5 (N <= 4096: unit roundoff
+6e-8 times the O(sqrt(N) log N) growth); FP64 solves 1e-12 relative on U and
+1e-10 on Q (V and Q carry the h^-2-amplified rounding of the v-equation).
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, dst as odst, fast
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ah():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2609_16478_amd as mod
+    return mod
+
+
+def _rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+# ------------------------------------------------------------------------------------------
+# DST-I passes
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N", [8, 12, 16, 24, 32, 48, 96, 128, 192, 256, 384, 512, 1024])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_dst_axis_x_y_z(ah, N, prec):
+    rng = np.random.default_rng(N)
+    shape = (5, 7, N - 1)   # z, y, x: x-pass with ragged row tiles
+    x = rng.standard_normal(shape)
+    p = ah.FP64 if prec == "fp64" else ah.MIXED
+    tol = 1e-12 if prec == "fp64" else 2e-5
+    xt = torch.from_numpy(x).cuda()
+    out = ah.dst1(xt, 0, p).double().cpu().numpy()
+    ref = odst.dst1(x.astype(np.float32).astype(np.float64) if prec == "fp32" else x, axis=2)
+    assert _rel(out, ref) < tol
+    # the same length on the strided axes (y, then z), with ragged column tiles
+    for axis, shp in ((1, (3, N - 1, 37)), (2, (N - 1, 5, 13))):
+        x = rng.standard_normal(shp)
+        xin = x.astype(np.float32).astype(np.float64) if prec == "fp32" else x
+        out = ah.dst1(torch.from_numpy(x).cuda(), axis, p).double().cpu().numpy()
+        ref = odst.dst1(xin, axis=2 - axis)
+        assert _rel(out, ref) < tol, (axis, _rel(out, ref))
+
+
+@pytest.mark.parametrize("N", [2048, 4096])
+def test_dst_long_2d(ah, N):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((6, N - 1))
+    out = ah.dst1(torch.from_numpy(x).cuda(), 0, ah.FP64).cpu().numpy()
+    assert _rel(out, odst.dst1(x, axis=1)) < 1e-12
+    x = rng.standard_normal((N - 1, 9))
+    out = ah.dst1(torch.from_numpy(x).cuda(), 1, ah.FP64).cpu().numpy()
+    assert _rel(out, odst.dst1(x, axis=0)) < 1e-12
+
+
+def test_dst_involution_on_gpu(ah):
+    N = 64
+    x = torch.randn(3, N - 1, dtype=torch.float64, device="cuda")
+    y = ah.dst1(ah.dst1(x, 0), 0)
+    assert torch.allclose(y, x * (N / 2), rtol=0, atol=1e-12 * N)
+
+
+# ------------------------------------------------------------------------------------------
+# Poisson solve
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [(16, 16), (32, 24), (8, 8, 8), (16, 12, 24)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_poisson_matches_oracle(ah, n, prec):
+    p = W.Problem(n, (0.0,) * len(n), (1.0, 1.3, 0.8)[:len(n)],
+                  np.ones(tuple(m + 1 for m in reversed(n))), np.zeros(tuple(m + 1 for m in reversed(n))))
+    ft = fast.FastTier(p)
+    g = np.random.default_rng(3).standard_normal(ft.g.interior_shape)
+    ref = ft.poisson(g)
+    with ah.Solver(p, precision=ah.FP64 if prec == "fp64" else ah.MIXED) as s:
+        out = s.poisson(g).cpu().numpy()
+    assert _rel(out, ref) < (1e-12 if prec == "fp64" else 1e-5)
+
+
+# ------------------------------------------------------------------------------------------
+# Schur operator (Lemma 1) against explicit elimination
+# ------------------------------------------------------------------------------------------
+
+SCHUR_CASES = {
+    "c2_16": lambda: W.config2(16),
+    "c2_32x24": lambda: W.manufactured("1 + 0.5*sin(2*pi*x)*cos(2*pi*y)", "sin(pi*x)**2*sin(pi*y)**2",
+                                       (32, 24), (0.0, 0.0), (1.0, 0.75)),
+    "c3_8": lambda: W.config3(8),
+    "c3_8x12x16": lambda: W.manufactured(W.C3_ALPHA, W.C3_U, (8, 12, 16), (0, 0, 0), (1.0, 1.2, 1.5)),
+    "poly2d_16": lambda: W.poly_exact(16, 2),
+    "poly3d_8": lambda: W.poly_exact(8, 3),
+}
+
+
+@pytest.mark.parametrize("case", list(SCHUR_CASES))
+def test_schur_apply_matches_explicit(ah, case):
+    p = SCHUR_CASES[case]()
+    S, b, asm = direct.schur(p)
+    rng = np.random.default_rng(11)
+    Q = rng.standard_normal((3, S.shape[0]))
+    with ah.Solver(p) as s:
+        assert s.nq == S.shape[0]
+        for q in Q:
+            y = s.schur_apply(q).cpu().numpy()
+            assert _rel(y, S @ q) < 1e-12, case
+        bg = s.schur_rhs().cpu().numpy()
+        assert _rel(bg, b) < 1e-11, case
+
+
+def test_schur_apply_linearity(ah):
+    p = W.config2(32)
+    with ah.Solver(p) as s:
+        rng = np.random.default_rng(2)
+        a, b = rng.standard_normal((2, s.nq))
+        ya, yb = s.schur_apply(a), s.schur_apply(b)
+        yab = s.schur_apply(2.0 * a - 3.0 * b)
+        assert torch.allclose(yab, 2 * ya - 3 * yb, rtol=0, atol=1e-11 * yab.abs().max().item())
+
+
+@pytest.mark.parametrize("case", ["c2_16", "c3_8"])
+def test_schur_apply_fp32_close(ah, case):
+    p = SCHUR_CASES[case]()
+    S, b, asm = direct.schur(p)
+    q = np.random.default_rng(5).standard_normal(S.shape[0])
+    with ah.Solver(p, precision=ah.MIXED) as s:
+        y = s.schur_apply(q).cpu().numpy()
+    assert _rel(y, S @ q) < 2e-5
+
+
+# ------------------------------------------------------------------------------------------
+# whole solve
+# ------------------------------------------------------------------------------------------
+
+DIRECT_CASES = {
+    "c1_32": lambda: W.config1(32),
+    "c2_64": lambda: W.config2(64),
+    "cavity_32": lambda: W.cavity(32),
+    "plate_32": lambda: W.plate(32),
+    "poly2d_24x16": lambda: W.poly_exact((24, 16), 2),
+    "c3_12": lambda: W.config3(12),
+    "poly3d_8x12x16": lambda: W.poly_exact((8, 12, 16), 3),
+}
+
+
+@pytest.mark.parametrize("case", list(DIRECT_CASES))
+def test_solve_fp64_matches_direct(ah, case):
+    p = DIRECT_CASES[case]()
+    U, V, Q, asm = direct.solve(p)
+    with ah.Solver(p, tol=1e-14) as s:
+        u, v, q, st = s.solve(want_v=True, want_q=True)
+    assert st.converged
+    assert _rel(u.cpu().numpy(), U) < 1e-12, case
+    assert _rel(q.cpu().numpy(), Q) < 1e-10, case
+    assert _rel(v.cpu().numpy(), V) < 1e-10, case
+
+
+@pytest.mark.parametrize("case", ["c2_64", "c3_12", "poly2d_24x16", "cavity_32"])
+def test_solve_mixed_matches_fp64(ah, case):
+    p = DIRECT_CASES[case]()
+    with ah.Solver(p, tol=1e-14) as s:
+        u64, *_ = s.solve()
+    with ah.Solver(p, precision=ah.MIXED) as s:
+        um, _, _, st = s.solve()
+    assert st.sweeps >= 2
+    assert _rel(um.cpu().numpy(), u64.cpu().numpy()) <= 1e-10, (case, st)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 256), (2, 512), (3, 32), (3, 64)])
+def test_polynomial_exactness_large(ah, dim, n):
+    # the discrete solution equals the sampled polynomial at any N (rounding only)
+    p = W.poly_exact(n, dim)
+    with ah.Solver(p, tol=1e-13) as s:
+        u, _, _, st = s.solve()
+    err = np.abs(u.cpu().numpy() - p.u_exact).max() / np.abs(p.u_exact).max()
+    assert err < 1e-11, (err, st)
+
+
+def test_fourth_order_on_gpu(ah):
+    errs = []
+    for n in (64, 128, 256):
+        p = W.config2(n)
+        with ah.Solver(p, tol=1e-13) as s:
+            u, *_ = s.solve()
+        errs.append(np.abs(u.cpu().numpy() - p.u_exact).max())
+    assert all(14.0 < errs[i] / errs[i + 1] < 19.0 for i in range(2)), errs
+
+
+def test_fast_tier_parity_at_larger_n(ah):
+    # beyond the direct tier: the oracle's Algorithm-1 path at 2-D N = 256
+    p = W.config2(256)
+    Uf, Vf, Qf, info = fast.FastTier(p).solve(tol=1e-13)
+    with ah.Solver(p, tol=1e-13) as s:
+        u, *_ = s.solve()
+    assert _rel(u.cpu().numpy(), Uf) < 1e-11
+
+
+def test_batched_matches_single(ah):
+    probs = [W.config4_instance(sp) for sp in W.config4_specs(4, seed=0)]
+    outs, stats, rc = ah.solve_batched(probs, tol=1e-13)
+    assert rc == ah.OK
+    for pb, u in zip(probs, outs):
+        with ah.Solver(pb, tol=1e-13) as s:
+            u1, *_ = s.solve()
+        assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < 1e-12
