@@ -1,0 +1,187 @@
+"""Benchmark: time-to-solution and DOF/s of the clamped variable-coefficient 3-D biharmonic
+solve on one MI355X (mixed precision: FP32 transforms inside FP64 refinement), next to the
+plain FP64 GPU form, with the DST pass kernel's roofline and the CPU oracle as baseline.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--n 1024] [--no-fp64] [--no-cpu]
+
+A step is one whole solve (ConstructSchurRHS, GMRES with Schur matvecs, recovery, and for
+the mixed form the FP64 refinement sweeps) of the synthetic problem with inputs resident in
+HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "solve time + DOF/s at 1024^3 to 1e-10 rel err, mixed vs FP64; DST HBM GB/s"
+
+
+def _pmc_traffic(kernel_src_hash):
+    """Measured HBM bytes per DST pass launch from the committed rocprofv3 PMC summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "dst_pass_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("dst_source_sha1") != kernel_src_hash:
+        return None
+    try:
+        return {"fetch_bytes": float(kv["fetch_bytes_per_launch"]), "write_bytes": float(kv["write_bytes_per_launch"]),
+                "n": int(kv["n"])}
+    except (KeyError, ValueError):
+        return None
+
+
+def _src_hash():
+    p = os.path.join(ROOT, "paper_2609_16478_amd", "csrc", "dst.hip")
+    return hashlib.sha1(open(p, "rb").read()).hexdigest()
+
+
+def cpu_baseline(n=80):
+    """The oracle's Algorithm-1 tier (scipy DST-I, numpy stencils, FP64 GMRES) on the same
+    problem family at n^3, timed on this host."""
+    import numpy as np
+    import workloads as W
+    from oracle import fast
+    cores = len(os.sched_getaffinity(0))
+    p = W.config3(n)
+    t0 = time.perf_counter()
+    ft = fast.FastTier(p, workers=cores)
+    U, V, Q, info = ft.solve(tol=1e-11)
+    dt = time.perf_counter() - t0
+    err = float(np.abs(U - p.u_exact).max() / np.abs(p.u_exact).max())
+    return {"value": n ** 3 / dt, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+            "sample": f"one FP64 fast-tier solve (scipy DST-I + own GMRES(30), tol 1e-11) of the "
+                      f"same 3-D problem at n={n} ({info['iters']} GMRES iterations, {dt:.1f} s, "
+                      f"rel err vs exact {err:.2e}); DOF = n^3",
+            "time_s": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=80)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
+              "multi-GPU path; see DESIGN.md for how it would shard.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2609_16478_amd as ah
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    n = args.n
+    t0 = time.perf_counter()
+    prob = W.manufactured(W.C3_ALPHA, W.C3_U, (n, n, n), xp="torch", device=dev, chunk=32,
+                          with_exact=True)
+    u_exact = prob.u_exact
+    prob.v_exact = None
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    print(f"[bench] n={n} inputs generated on device in {t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    def run(prec, steps, warmup, **opts):
+        s = ah.Solver(prob, precision=prec, **opts)
+        out = torch.empty(s.nodal_shape, dtype=torch.float64, device=dev)
+        for i in range(warmup):
+            _, _, _, st = s.solve(out=out)
+            print(f"[bench] warmup prec={prec} {st}", file=sys.stderr, flush=True)
+        s.profile(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        stats = []
+        for i in range(steps):
+            _, _, _, st = s.solve(out=out)
+            stats.append(st)
+            print(f"[bench] step prec={prec} {st}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        kt = s.kernel_times()
+        s.close()
+        return out, dt, stats, kt
+
+    u_mx, dt_mx, st_mx, kt_mx = run(ah.MIXED, args.steps, args.warmup)
+    nrm_exact = u_exact.abs().max().item()
+    err_mx_exact = ((u_mx - u_exact).abs().max() / nrm_exact).item()
+    result_fp64 = None
+    err_mx_fp64 = None
+    if not args.no_fp64:
+        u_64, dt_64, st_64, kt_64 = run(ah.FP64, 1, 0, tol=1e-12)
+        err_mx_fp64 = ((u_mx - u_64).abs().max() / u_64.abs().max()).item()
+        err_64_exact = ((u_64 - u_exact).abs().max() / nrm_exact).item()
+        result_fp64 = {"ms_per_step": dt_64 * 1e3, "dof_per_s": n ** 3 / dt_64,
+                       "gmres_iters": st_64[-1].gmres_iters, "rel_err_vs_exact": err_64_exact,
+                       "speedup_mixed_over_fp64": dt_64 / dt_mx}
+        del u_64
+
+    # roofline of the dominant kernel: the DST-I pass (rows + strided launches share one kernel)
+    ms = kt_mx["dst_rows"][0] + kt_mx["dst_strided"][0]
+    cnt = kt_mx["dst_rows"][1] + kt_mx["dst_strided"][1]
+    bytes_launch = kt_mx["dst_rows"][2]
+    avg_s = ms / cnt / 1e3
+    achieved = bytes_launch / avg_s / 1e9
+    pmc = _pmc_traffic(_src_hash())
+    traffic = None
+    if pmc and pmc["n"] == n:
+        traffic = pmc["fetch_bytes"] + pmc["write_bytes"]
+    fused_ms, fused_cnt = kt_mx["dst_fused"][0], kt_mx["dst_fused"][1]
+    kernels = {k: {"avg_us": (v[0] / v[1] * 1e3 if v[1] else None), "launches": v[1],
+                   "GBps": (v[2] / (v[0] / v[1] / 1e3) / 1e9 if v[1] and v[0] > 0 else None)}
+               for k, v in kt_mx.items() if v[1]}
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(args.cpu_n)
+
+    st = st_mx[-1]
+    line = {
+        "metric": METRIC,
+        "value": n ** 3 / dt_mx,
+        "unit": "DOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt_mx * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"3-D clamped variable-coefficient biharmonic, n={n}^3, alpha=1+0.5 sin(2pi x)"
+                               f"sin(2pi y)sin(2pi z), u=sin^2(pi x)sin^2(pi y)sin^2(pi z); mixed precision "
+                               f"(FP32 DST bulk, FP64 refinement), GMRES(30)",
+                   "n": n, "dof": n ** 3, "interior_dof": (n - 1) ** 3,
+                   "gmres_iters": st.gmres_iters, "sweeps": st.sweeps,
+                   "rel_err_vs_fp64": err_mx_fp64, "rel_err_vs_exact": err_mx_exact,
+                   "fp64": result_fp64, "kernels": kernels},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_dst_pass<float,32,false> (DST-I pass, rows and strided)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6,
+                     "fused_pass_GBps": (bytes_launch / (fused_ms / fused_cnt / 1e3) / 1e9) if fused_cnt else None},
+        "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

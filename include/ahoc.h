@@ -78,7 +78,8 @@ typedef struct {
   int restart;        /* GMRES restart length m (default 30)                         */
   int max_iters;      /* cap on GMRES iterations per Schur solve (default 2000)      */
   double tol;         /* FP64: relative Schur residual ||b - S Q|| / ||b|| (1e-12)   */
-  double inner_tol;   /* MIXED: relative Schur residual of each correction (1e-6)    */
+  double inner_tol;   /* MIXED: relative Schur residual of each correction (1e-4); the
+                         inner solve also ends when FP32 rounding stalls its residual   */
   double sweep_tol;   /* MIXED: stop when the estimated remaining relative change of
                          U (max norm) is below this (default 1e-11)                  */
   int max_sweeps;     /* MIXED: refinement sweeps cap (default 8)                    */
@@ -143,6 +144,37 @@ ahoc_status ahoc_poisson(ahoc_handle* h, const double* g, double* w, void* strea
  * nint: interior sizes (x, y[, z]); in may equal out. */
 ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const void* in, void* out,
                       void* stream);
+
+/* Select the DST-I pass kernel family for subsequent launches (process-wide):
+ * 0 = automatic (length-specialised kernels for n in {32, 64, 96, 128, 192, 256, 384,
+ * 512, 768, 1024, 2048, 4096}, the generic radix-2/3/4/8 kernel otherwise),
+ * 1 = generic kernel for every length, 2 = specialised kernels only (other lengths
+ * return AHOC_E_UNSUPPORTED).  For tuning and for testing both families. */
+ahoc_status ahoc_set_dst_variant(int variant);
+
+/* Kernel classes for ahoc_kernel_times. */
+enum {
+  AHOC_K_DST_ROWS = 0,     /* DST-I pass along x (contiguous pencils)                   */
+  AHOC_K_DST_STRIDED = 1,  /* DST-I pass along y in 3-D (strided pencils)               */
+  AHOC_K_DST_FUSED = 2,    /* fused forward DST, eigen scaling, inverse DST (slowest axis) */
+  AHOC_K_LIFT = 3,         /* v-equation right-hand side from Q                          */
+  AHOC_K_RHS_U = 4,        /* u-equation right-hand side M(V/alpha)                      */
+  AHOC_K_GATHER = 5,       /* boundary residual gather                                   */
+  AHOC_K_KRYLOV = 6,       /* one Arnoldi step (CGS2 dots/axpys, norm, Givens, scale)     */
+  AHOC_K_RESID = 7,        /* FP64 coupled residual (mixed precision)                    */
+  AHOC_K_MATVEC = 8,       /* one whole Schur matrix-vector product                      */
+  AHOC_NKIND = 9
+};
+
+/* Enable (1) or disable (0) per-kernel-class timing of the handle's solves with
+ * HIP events recorded on the solve stream around each launch; resets the totals. */
+ahoc_status ahoc_profile(ahoc_handle* h, int enable);
+
+/* Accumulated time (ms) and launch count of one kernel class since ahoc_profile,
+ * and the algorithmic bytes one launch moves (what the operation must read and
+ * write at least once).  Synchronises the device.  Any output may be NULL. */
+ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long long* launches,
+                              double* bytes_per_launch);
 
 void ahoc_destroy(ahoc_handle* h);
 

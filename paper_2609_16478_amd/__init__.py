@@ -65,12 +65,22 @@ _lib.ahoc_poisson.argtypes = [_H, c_void_p, c_void_p, c_void_p]
 _lib.ahoc_poisson.restype = c_int
 _lib.ahoc_dst1.argtypes = [c_int, c_int, ctypes.POINTER(c_int), c_int, c_void_p, c_void_p, c_void_p]
 _lib.ahoc_dst1.restype = c_int
+_lib.ahoc_profile.argtypes = [_H, c_int]
+_lib.ahoc_profile.restype = c_int
+_lib.ahoc_kernel_times.argtypes = [_H, c_int, ctypes.POINTER(c_double), ctypes.POINTER(ctypes.c_longlong),
+                                   ctypes.POINTER(c_double)]
+_lib.ahoc_kernel_times.restype = c_int
+_lib.ahoc_set_dst_variant.argtypes = [c_int]
+_lib.ahoc_set_dst_variant.restype = c_int
 _lib.ahoc_destroy.argtypes = [_H]
 _lib.ahoc_status_string.argtypes = [c_int]
 _lib.ahoc_status_string.restype = ctypes.c_char_p
 _lib.ahoc_last_error.restype = ctypes.c_char_p
 
-EXPORTED = ["ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_schur_rhs",
+KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "resid",
+                "matvec"]
+
+EXPORTED = ["ahoc_set_dst_variant", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_schur_rhs",
             "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
             "ahoc_status_string", "ahoc_last_error"]
 
@@ -104,7 +114,7 @@ def _dev(x, device):
         return None
     torch = _torch()
     if isinstance(x, np.ndarray):
-        return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64)).to(device)
+        return torch.from_numpy(np.array(x, dtype=np.float64, order="C", copy=True)).to(device)
     return x.to(device=device, dtype=torch.float64).contiguous()
 
 
@@ -216,6 +226,20 @@ class Solver:
         _check(_lib.ahoc_poisson(self._h, _ptr(g), _ptr(w), _stream()), "ahoc_poisson")
         return w.reshape(self.interior_shape)
 
+    def profile(self, enable=True):
+        """Per-kernel-class HIP-event timing of subsequent solves (resets the totals)."""
+        _check(_lib.ahoc_profile(self._h, 1 if enable else 0), "ahoc_profile")
+
+    def kernel_times(self):
+        """{kind: (total_ms, launches, algorithmic bytes per launch)} since profile()."""
+        out = {}
+        for k, name in enumerate(KERNEL_KINDS):
+            ms, cnt, by = c_double(), ctypes.c_longlong(), c_double()
+            _check(_lib.ahoc_kernel_times(self._h, k, ctypes.byref(ms), ctypes.byref(cnt),
+                                          ctypes.byref(by)), "ahoc_kernel_times")
+            out[name] = (ms.value, cnt.value, by.value)
+        return out
+
     def solve(self, want_v=False, want_q=False, out=None):
         torch = _torch()
         u = out if out is not None else torch.empty(self.nodal_shape, dtype=torch.float64,
@@ -248,6 +272,11 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
     if rc not in (OK, E_NOCONV):
         _check(rc, "ahoc_solve_batched")
     return outs, [_stats(s) for s in sarr], rc
+
+
+def set_dst_variant(variant: int):
+    """0 = automatic, 1 = generic DST kernel everywhere, 2 = length-specialised kernels only."""
+    _check(_lib.ahoc_set_dst_variant(int(variant)), "ahoc_set_dst_variant")
 
 
 def dst1(x, axis, precision=FP64):

@@ -14,6 +14,7 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -77,6 +78,15 @@ struct ahoc_handle {
   double* red = nullptr;     // reduction partials
   double* pinned = nullptr;  // host-pinned scalars
   std::vector<void*> allocs;
+  // optional per-kernel-class timing with HIP events on the work stream
+  bool prof = false;
+  std::vector<hipEvent_t> evpool;
+  size_t evused = 0;
+  struct Pending { int kind; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double kms[AHOC_NKIND] = {0};
+  long long kcnt[AHOC_NKIND] = {0};
+  double kbytes[AHOC_NKIND] = {0};
 };
 
 namespace ahoc {
@@ -92,6 +102,41 @@ int dalloc(ahoc_handle* h, void** p, size_t bytes) {
   }
   h->allocs.push_back(*p);
   return ST_OK;
+}
+
+hipEvent_t tbegin(ahoc_handle* h, hipStream_t st) {
+  if (!h->prof) return nullptr;
+  if (h->evused + 2 > h->evpool.size()) {
+    for (int i = 0; i < 64; ++i) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      h->evpool.push_back(e);
+    }
+  }
+  hipEvent_t a = h->evpool[h->evused++];
+  (void)hipEventRecord(a, st);
+  return a;
+}
+
+void tend(ahoc_handle* h, int kind, hipEvent_t a, double bytes, hipStream_t st) {
+  if (!h->prof || !a) return;
+  hipEvent_t b = h->evpool[h->evused++];
+  (void)hipEventRecord(b, st);
+  h->pending.push_back({kind, a, b});
+  h->kbytes[kind] = bytes;
+}
+
+// Fold completed event pairs into the per-kind totals (the stream must be idle).
+void tresolve(ahoc_handle* h) {
+  for (auto& p : h->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      h->kms[p.kind] += ms;
+      h->kcnt[p.kind] += 1;
+    }
+  }
+  h->pending.clear();
+  h->evused = 0;
 }
 
 #define TRY(...)                \
@@ -171,8 +216,7 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
   const Geom& g = h->g;
   for (int a = 0; a < g.dim; ++a) {
     TRY(dst_tables_init<T>(P.tb[a], g.n[a]));
-    P.tile[a] = tile_opt > 0 ? tile_opt : dst_default_tile(g.n[a], (int)sizeof(T));
-    if (P.tile[a] <= 0) return ST_UNSUPPORTED;
+    P.tile[a] = tile_opt > 0 ? tile_opt : 0;  // 0: each kernel picks its default tile
     // eigenvalues of the 1-D second difference on sine mode k: -(4/h^2) sin^2(k pi / (2N))
     std::vector<T> s(g.ni[a]);
     const long double pi = 3.141592653589793238462643383279502884L;
@@ -223,30 +267,43 @@ template <typename T> void prec_free(Prec<T>& P) {
 // In-place Dirichlet solve on an interior array: buf <- scale * S (S buf / lambda).
 template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st) {
   const Geom& g = h->g;
+  const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);  // one read + one write of the array
+  auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner,
+                 const DstScale<T>* f, int tile) -> int {
+    hipEvent_t e = tbegin(h, st);
+    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, f, tile, st);
+    tend(h, kind, e, pass_bytes, st);
+    return rc;
+  };
   if (g.dim == 2) {
-    TRY(dst_pass<T>(P.tb[0], buf, buf, g.ni[1], 1, nullptr, P.tile[0], st));
-    TRY(dst_pass<T>(P.tb[1], buf, buf, 1, g.ni[0], &sc, P.tile[1], st));
-    TRY(dst_pass<T>(P.tb[0], buf, buf, g.ni[1], 1, nullptr, P.tile[0], st));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0]));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], 1, g.ni[0], &sc, P.tile[1]));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0]));
   } else {
     const long long rows = (long long)g.ni[1] * g.ni[2];
-    TRY(dst_pass<T>(P.tb[0], buf, buf, rows, 1, nullptr, P.tile[0], st));
-    TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.ni[0], nullptr, P.tile[1], st));
-    TRY(dst_pass<T>(P.tb[2], buf, buf, 1, (long long)g.ni[0] * g.ni[1], &sc, P.tile[2], st));
-    TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.ni[0], nullptr, P.tile[1], st));
-    TRY(dst_pass<T>(P.tb[0], buf, buf, rows, 1, nullptr, P.tile[0], st));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, nullptr, P.tile[0]));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.ni[0], nullptr, P.tile[1]));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.ni[0] * g.ni[1], &sc, P.tile[2]));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.ni[0], nullptr, P.tile[1]));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, nullptr, P.tile[0]));
   }
   return ST_OK;
 }
 
 // V = -L^{-1}(src + L_bnd[Q])  into P.bufA
 template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  hipEvent_t e = tbegin(h, st);
   TRY(lift<T>(h->g, h->w, Q, src, P.bufA, st));
+  tend(h, AHOC_K_LIFT, e, (double)h->g.nint * sizeof(T) * (src ? 2 : 1), st);
   return poisson<T>(h, P, P.bufA, P.scV, st);
 }
 
 // U = L^{-1}(M(V/alpha) + src)  with V = P.bufA, into P.bufB
 template <typename T> int usolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  hipEvent_t e = tbegin(h, st);
   TRY(rhs_u<T>(h->g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
+  // reads V and 1/alpha (nodal), writes G
+  tend(h, AHOC_K_RHS_U, e, (double)sizeof(T) * (2.0 * h->g.nint + h->g.nnodal) + (src ? h->g.nint * sizeof(T) : 0), st);
   return poisson<T>(h, P, P.bufB, P.scU, st);
 }
 
@@ -264,11 +321,18 @@ template <typename T> const T* q_in(ahoc_handle* h, Prec<T>& P, const double* q,
 // y = S_h q  (homogeneous Lemma-1 form)
 template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, double* y, hipStream_t st) {
   int rc = 0;
+  hipEvent_t e = tbegin(h, st);
   const T* qT = q_in<T>(h, P, q, st, &rc);
   TRY(rc);
   TRY(vsolve<T>(h, P, qT, nullptr, st));
   TRY(usolve<T>(h, P, qT, nullptr, st));
-  return gather<T>(h->g, h->w, P.bufB, qT, P.af, nullptr, y, st);
+  hipEvent_t eg = tbegin(h, st);
+  TRY(gather<T>(h->g, h->w, P.bufB, qT, P.af, nullptr, y, st));
+  tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (3 * sizeof(T) + 2 * sizeof(T) + sizeof(double)), st);
+  // algorithmic bytes of one matvec: lift write, 10 pass read+writes, rhs_u, gather
+  const double s = sizeof(T);
+  tend(h, AHOC_K_MATVEC, e, s * (21.0 * h->g.nint + 2.0 * h->g.nint + h->g.nnodal), st);
+  return ST_OK;
 }
 
 // b = -R(0) for sources (src_v, src_u, src_q) in precision T
@@ -322,9 +386,13 @@ struct GmresResult {
 };
 
 // Restarted GMRES(m) on S_h x = b, x = 0 on entry.  All vectors FP64 on the device.
+// With an FP32 operator the residual estimate levels off at the operator's rounding
+// level; the inner solve then stops once eight iterations gained less than a factor 2.
 template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
           GmresResult& res, int* matvecs, hipStream_t st) {
+  const bool inexact = sizeof(T) == 4;
+  std::vector<double> hist;
   const long long nq = h->g.nq;
   const int m = h->m;
   const int ldh = m + 1;
@@ -365,6 +433,7 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       double* w = h->Vb + (long long)(j + 1) * nq;
       TRY(matvec<T>(h, P, vj, w, st));
       ++*matvecs;
+      hipEvent_t ek = tbegin(h, st);
       TRY(mdot_partial(h->Vb, nq, j + 1, w, nq, h->part, h->nb_dot, st));
       TRY(mdot_reduce(h->part, h->nb_dot, j + 1, h->h1, 0, st));
       TRY(maxpy(w, h->Vb, nq, j + 1, h->h1, -1.0, nq, st));
@@ -374,6 +443,8 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       TRY(dot_dev(h, w, w, nq, h->nrm, st));
       TRY(givens_step(h->H, ldh, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
       TRY(scale_by_inv(w, nq, h->resid, st));
+      // CGS2: 2 x (j+1) dot sweeps and 2 x (j+1) axpy sweeps over the basis, plus norm and scale
+      tend(h, AHOC_K_KRYLOV, ek, 8.0 * nq * (4.0 * (j + 1) + 2.0 * 2 + 3.0), st);
       ++res.iters;
       jj = j + 1;
       const double est = read_scalar(h, h->resid, st, &rc) / bnorm;
@@ -382,6 +453,11 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       if (est <= tol) {
         done = true;
         res.converged = true;
+        break;
+      }
+      hist.push_back(est);
+      if (inexact && hist.size() > 8 && est < 1e-2 && est > 0.5 * hist[hist.size() - 9]) {
+        done = true;
         break;
       }
       if (res.iters >= max_iters) break;
@@ -490,7 +566,7 @@ void ahoc_default_options(ahoc_options* o) {
   o->restart = 30;
   o->max_iters = 2000;
   o->tol = 1e-12;
-  o->inner_tol = 1e-6;
+  o->inner_tol = 1e-4;
   o->sweep_tol = 1e-11;
   o->max_sweeps = 8;
   o->tile_fp64 = 0;
@@ -517,6 +593,7 @@ void ahoc_destroy(ahoc_handle* h) {
   ahoc::prec_free(h->p64);
   ahoc::prec_free(h->p32);
   for (void* p : h->allocs) (void)hipFree(p);
+  for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   delete h;
 }
@@ -647,8 +724,10 @@ int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, 
       else su = nullptr;
       TRY(convert<double, float>(g.nq, h->src_q, h->rq, st));
     } else {
+      hipEvent_t er = tbegin(h, st);
       TRY(resid64<float>(g, h->w, h->U64, h->V64, h->Q64, h->ia64, h->af64, h->src_u, h->src_v,
                          h->src_q, h->ru, h->rv, h->rq, st));
+      tend(h, AHOC_K_RESID, er, 8.0 * (3.0 * g.nint + g.nnodal) + 4.0 * 2.0 * g.nint, st);
     }
     // correction: Schur solve in FP32 operators with FP64 Krylov, then recovery
     GmresResult gr;
@@ -668,13 +747,16 @@ int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, 
     const double un = absmax(h, h->U64, true, g.nint, st, &rc);
     TRY(rc);
     upd = un > 0 ? du / un : 0.0;
-    // remaining change estimated from the observed contraction of the updates
+    // Remaining change of U after this sweep, estimated as upd * rho / (1 - rho) with the
+    // contraction rho no smaller than the inner solve's achieved relative residual (the
+    // first sweep's update is the whole solution, so its ratio says nothing about rho).
     if (upd <= h->opt.sweep_tol * 1e-3) {
       conv = true;
       break;
     }
-    if (sw > 0 && prev > 0) {
-      const double rho = upd / prev;
+    if (sw > 0) {
+      double rho = gr.relres;
+      if (sw > 1 && prev > 0) rho = std::max(rho, upd / prev);
       if (rho < 1.0 && upd * rho / (1.0 - rho) <= h->opt.sweep_tol) {
         conv = true;
         break;
@@ -711,7 +793,40 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   const auto t1 = std::chrono::steady_clock::now();
   local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (stats) *stats = local;
+  if (h->prof) {
+    (void)hipStreamSynchronize(st);
+    ahoc::tresolve(h);
+  }
   return (ahoc_status)rc;
+}
+
+ahoc_status ahoc_set_dst_variant(int variant) {
+  if (variant < 0 || variant > 2) return AHOC_E_INVALID;
+  ahoc::dst_set_variant(variant);
+  return AHOC_OK;
+}
+
+ahoc_status ahoc_profile(ahoc_handle* h, int enable) {
+  if (!h) return AHOC_E_INVALID;
+  (void)hipDeviceSynchronize();
+  ahoc::tresolve(h);
+  for (int k = 0; k < AHOC_NKIND; ++k) {
+    h->kms[k] = 0;
+    h->kcnt[k] = 0;
+  }
+  h->prof = enable != 0;
+  return AHOC_OK;
+}
+
+ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long long* launches,
+                              double* bytes_per_launch) {
+  if (!h || kind < 0 || kind >= AHOC_NKIND) return AHOC_E_INVALID;
+  (void)hipDeviceSynchronize();
+  ahoc::tresolve(h);
+  if (total_ms) *total_ms = h->kms[kind];
+  if (launches) *launches = h->kcnt[kind];
+  if (bytes_per_launch) *bytes_per_launch = h->kbytes[kind];
+  return AHOC_OK;
 }
 
 ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_options* opt,

@@ -90,6 +90,16 @@ template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
              const DstScale<T>* fused, int tile_seqs, hipStream_t st);
 
+// Length-specialised kernels (dst_fast.hip) for N in {32, 64, 96, ..., 4096}.
+bool dst_fast_supported(int N);
+int dst_fast_tile(int N, int elem_bytes);
+template <typename T>
+int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer,
+                  long long inner, const DstScale<T>* fused, int nseq, hipStream_t st);
+// 0 = automatic (specialised kernel where available), 1 = generic kernel only, 2 = specialised only
+void dst_set_variant(int v);
+int dst_get_variant();
+
 template <typename T> int dst_tables_init(DstTables<T>& tb, int N);
 template <typename T> void dst_tables_free(DstTables<T>& tb);
 bool dst_supported(int N);

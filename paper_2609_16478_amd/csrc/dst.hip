@@ -285,22 +285,49 @@ __global__ void __launch_bounds__(launch_cap<T>()) k_dst_pass(PassArgs<T> a) {
     ncols = left < P ? (int)left : P;
   }
 
-  // ---- load the tile: pencil p -> sequence p/2, component p%2, positions 1..L
+  // ---- load the tile: pencil p -> sequence p/2, component p%2, positions 1..L.
+  // Batches of U independent global loads per thread are issued before their
+  // LDS writes, so each wave keeps many HBM requests in flight.
+  constexpr int U = 16;
   if (rows) {
-    for (int p = 0; p < P; ++p) {
-      const T* src = a.in + (base + p) * (long long)L;
-      T* dstp = ldsr + 2 * ((p >> 1) * ld) + (p & 1);
-      const bool ok = p < ncols;
-      for (int m = threadIdx.x; m < L; m += blockDim.x) dstp[2 * (m + 1)] = ok ? src[m] : T(0);
+    const int per_row = (L + blockDim.x - 1) / blockDim.x;
+    const int iters = P * per_row;
+    for (int it0 = 0; it0 < iters; it0 += U) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int it = it0 + u;
+        const int p = it / per_row;
+        const int m = (it - p * per_row) * blockDim.x + threadIdx.x;
+        v[u] = (it < iters && p < ncols && m < L) ? a.in[(base + p) * (long long)L + m] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int it = it0 + u;
+        const int p = it / per_row;
+        const int m = (it - p * per_row) * blockDim.x + threadIdx.x;
+        if (it < iters && m < L) ldsr[2 * ((p >> 1) * ld + m + 1) + (p & 1)] = v[u];
+      }
     }
   } else {
     const int lp = __builtin_ctz(P);
     const int total = P * L;
-    for (int e = threadIdx.x; e < total; e += blockDim.x) {
-      const int c = e & (P - 1);
-      const int m = e >> lp;
-      const T v = (c < ncols) ? a.in[base + (long long)m * a.inner + c] : T(0);
-      ldsr[2 * ((c >> 1) * ld + m + 1) + (c & 1)] = v;
+    for (int e0 = 0; e0 < total; e0 += U * blockDim.x) {
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * blockDim.x + threadIdx.x;
+        const int c = e & (P - 1);
+        const int m = e >> lp;
+        v[u] = (e < total && c < ncols) ? a.in[base + (long long)m * a.inner + c] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = e0 + u * blockDim.x + threadIdx.x;
+        const int c = e & (P - 1);
+        const int m = e >> lp;
+        if (e < total) ldsr[2 * ((c >> 1) * ld + m + 1) + (c & 1)] = v[u];
+      }
     }
   }
   for (int q = threadIdx.x; q < nseq; q += blockDim.x) lds[q * ld] = mk<T>(0, 0);
@@ -333,14 +360,18 @@ __global__ void __launch_bounds__(launch_cap<T>()) k_dst_pass(PassArgs<T> a) {
 
   // ---- store
   if (rows) {
-    for (int p = 0; p < ncols; ++p) {
-      T* dst = a.out + (base + p) * (long long)L;
-      const T* srcp = ldsr + 2 * ((p >> 1) * ld) + (p & 1);
-      for (int m = threadIdx.x; m < L; m += blockDim.x) dst[m] = srcp[2 * (m + 1)];
+    const int per_row = (L + blockDim.x - 1) / blockDim.x;
+    const int iters = ncols * per_row;
+#pragma unroll 4
+    for (int it = 0; it < iters; ++it) {
+      const int p = it / per_row;
+      const int m = (it - p * per_row) * blockDim.x + threadIdx.x;
+      if (m < L) a.out[(base + p) * (long long)L + m] = ldsr[2 * ((p >> 1) * ld + m + 1) + (p & 1)];
     }
   } else {
     const int lp = __builtin_ctz(P);
     const int total = P * L;
+#pragma unroll 4
     for (int e = threadIdx.x; e < total; e += blockDim.x) {
       const int c = e & (P - 1);
       const int m = e >> lp;
@@ -451,10 +482,18 @@ template <typename T> void dst_tables_free(DstTables<T>& tb) {
   tb.N = 0;
 }
 
+static int g_variant = 0;
+void dst_set_variant(int v) { g_variant = v; }
+int dst_get_variant() { return g_variant; }
+
 template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
              const DstScale<T>* fused, int tile_seqs, hipStream_t st) {
   const int N = tb.N;
+  if (g_variant != 1 && dst_fast_supported(N)) {
+    const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, fused, tile_seqs, st);
+    if (rc != ST_UNSUPPORTED || g_variant == 2) return rc;
+  }
   const int ppt = tb.ppt;
   if (!ppt || !tb.tw) return ST_INVALID;
   const int tps = N / ppt;

@@ -44,9 +44,16 @@ def _rel(a, b):
 # DST-I passes
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("N", [8, 12, 16, 24, 32, 48, 96, 128, 192, 256, 384, 512, 1024])
+@pytest.fixture(params=[0, 1], ids=["auto", "generic"])
+def variant(request, ah):
+    ah.set_dst_variant(request.param)
+    yield request.param
+    ah.set_dst_variant(0)
+
+
+@pytest.mark.parametrize("N", [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_dst_axis_x_y_z(ah, N, prec):
+def test_dst_axis_x_y_z(ah, variant, N, prec):
     rng = np.random.default_rng(N)
     shape = (5, 7, N - 1)   # z, y, x: x-pass with ragged row tiles
     x = rng.standard_normal(shape)
@@ -66,7 +73,7 @@ def test_dst_axis_x_y_z(ah, N, prec):
 
 
 @pytest.mark.parametrize("N", [2048, 4096])
-def test_dst_long_2d(ah, N):
+def test_dst_long_2d(ah, variant, N):
     rng = np.random.default_rng(1)
     x = rng.standard_normal((6, N - 1))
     out = ah.dst1(torch.from_numpy(x).cuda(), 0, ah.FP64).cpu().numpy()
@@ -87,9 +94,9 @@ def test_dst_involution_on_gpu(ah):
 # Poisson solve
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("n", [(16, 16), (32, 24), (8, 8, 8), (16, 12, 24)])
+@pytest.mark.parametrize("n", [(16, 16), (32, 24), (8, 8, 8), (16, 12, 24), (64, 96), (32, 64, 96)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_poisson_matches_oracle(ah, n, prec):
+def test_poisson_matches_oracle(ah, variant, n, prec):
     p = W.Problem(n, (0.0,) * len(n), (1.0, 1.3, 0.8)[:len(n)],
                   np.ones(tuple(m + 1 for m in reversed(n))), np.zeros(tuple(m + 1 for m in reversed(n))))
     ft = fast.FastTier(p)
@@ -112,11 +119,14 @@ SCHUR_CASES = {
     "c3_8x12x16": lambda: W.manufactured(W.C3_ALPHA, W.C3_U, (8, 12, 16), (0, 0, 0), (1.0, 1.2, 1.5)),
     "poly2d_16": lambda: W.poly_exact(16, 2),
     "poly3d_8": lambda: W.poly_exact(8, 3),
+    "c2_32x64": lambda: W.manufactured("1 + 0.5*sin(2*pi*x)*cos(2*pi*y)", "sin(pi*x)**2*sin(pi*y)**2",
+                                       (32, 64), (0.0, 0.0), (1.0, 2.0)),
+    "c3_32x16x24": lambda: W.manufactured(W.C3_ALPHA, W.C3_U, (32, 16, 24), (0, 0, 0), (1.0, 0.5, 0.75)),
 }
 
 
 @pytest.mark.parametrize("case", list(SCHUR_CASES))
-def test_schur_apply_matches_explicit(ah, case):
+def test_schur_apply_matches_explicit(ah, variant, case):
     p = SCHUR_CASES[case]()
     S, b, asm = direct.schur(p)
     rng = np.random.default_rng(11)
