@@ -149,6 +149,14 @@ template <typename T> int alloc_t(ahoc_handle* h, T** p, long long n) {
   return dalloc(h, reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
 }
 
+// interior array (padded rows), zero-filled so the padding columns stay zero
+template <typename T> int alloc_int(ahoc_handle* h, T** p, hipStream_t st) {
+  int rc = alloc_t(h, p, h->g.nalloc);
+  if (rc) return rc;
+  AHOC_HIP_TRY(hipMemsetAsync(*p, 0, sizeof(T) * (size_t)h->g.nalloc, st));
+  return ST_OK;
+}
+
 void make_geom(const ahoc_problem* pb, Geom& g) {
   std::memset(&g, 0, sizeof(g));
   g.dim = pb->dim;
@@ -167,6 +175,9 @@ void make_geom(const ahoc_problem* pb, Geom& g) {
   }
   g.nint = (long long)g.ni[0] * g.ni[1] * g.ni[2];
   g.nnodal = (long long)g.nn[0] * g.nn[1] * g.nn[2];
+  // interior rows padded to 32 elements: 128 B aligned rows and column segments
+  g.px = ((g.ni[0] + 31) / 32) * 32;
+  g.nalloc = (long long)g.px * g.ni[1] * g.ni[2];
   int off = 0;
   for (int a = 0; a < g.dim; ++a) {
     long long fs = 1;
@@ -227,8 +238,8 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     TRY(alloc_t(h, &P.s[a], g.ni[a]));
     AHOC_HIP_TRY(hipMemcpy(P.s[a], s.data(), sizeof(T) * g.ni[a], hipMemcpyHostToDevice));
   }
-  TRY(alloc_t(h, &P.bufA, g.nint));
-  TRY(alloc_t(h, &P.bufB, g.nint));
+  TRY(alloc_int(h, &P.bufA, st));
+  TRY(alloc_int(h, &P.bufB, st));
   TRY(alloc_t(h, &P.qT, g.nq));
   TRY(alloc_t(h, &P.zq, g.nq));
   AHOC_HIP_TRY(hipMemsetAsync(P.zq, 0, sizeof(T) * g.nq, st));
@@ -238,7 +249,8 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
   DstScale<T> sc;
   sc.s_this = P.s[t];
   sc.s_a = P.s[0];
-  sc.na = g.ni[0];
+  sc.na = g.px;
+  sc.nva = g.ni[0];
   if (g.dim == 3) {
     sc.s_b = P.s[1];
     sc.c_ta = (T)((g.h[2] * g.h[2] + g.h[0] * g.h[0]) / 12.0);
@@ -271,20 +283,21 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
   auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner,
                  const DstScale<T>* f, int tile) -> int {
     hipEvent_t e = tbegin(h, st);
-    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, f, tile, st);
+    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, f, tile, st);
     tend(h, kind, e, pass_bytes, st);
     return rc;
   };
+  // strided passes also transform the (zero) padding columns of each row
   if (g.dim == 2) {
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0]));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[1], 1, g.ni[0], &sc, P.tile[1]));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], 1, g.px, &sc, P.tile[1]));
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0]));
   } else {
     const long long rows = (long long)g.ni[1] * g.ni[2];
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, nullptr, P.tile[0]));
-    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.ni[0], nullptr, P.tile[1]));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.ni[0] * g.ni[1], &sc, P.tile[2]));
-    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.ni[0], nullptr, P.tile[1]));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, nullptr, P.tile[1]));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.px * g.ni[1], &sc, P.tile[2]));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, nullptr, P.tile[1]));
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, nullptr, P.tile[0]));
   }
   return ST_OK;
@@ -476,10 +489,10 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
   // FP64 data
   TRY(alloc_t(h, &h->ia64, g.nnodal));
   TRY(alloc_t(h, &h->af64, g.nq));
-  TRY(alloc_t(h, &h->src_v, g.nint));
+  TRY(alloc_int(h, &h->src_v, st));
   TRY(alloc_t(h, &h->src_q, g.nq));
   if (pb->gD) {
-    TRY(alloc_t(h, &h->src_u, g.nint));
+    TRY(alloc_int(h, &h->src_u, st));
     TRY(alloc_t(h, &h->gD, g.nnodal));
     AHOC_HIP_TRY(hipMemcpyAsync(h->gD, pb->gD, sizeof(double) * g.nnodal, hipMemcpyDeviceToDevice, st));
   }
@@ -520,11 +533,11 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
     h->p32.ia = ia32;
     h->p32.af = af32;
     TRY(prec_init<float>(h, h->p32, h->opt.tile_fp32, st));
-    TRY(alloc_t(h, &h->U64, g.nint));
-    TRY(alloc_t(h, &h->V64, g.nint));
+    TRY(alloc_int(h, &h->U64, st));
+    TRY(alloc_int(h, &h->V64, st));
     TRY(alloc_t(h, &h->Q64, g.nq));
-    TRY(alloc_t(h, &h->ru, g.nint));
-    TRY(alloc_t(h, &h->rv, g.nint));
+    TRY(alloc_int(h, &h->ru, st));
+    TRY(alloc_int(h, &h->rv, st));
     TRY(alloc_t(h, &h->rq, g.nq));
   }
   // Krylov workspace
@@ -652,8 +665,8 @@ ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream) {
   int rc;
   if (h->opt.precision == AHOC_MIXED) {
     using namespace ahoc;
-    rc = convert<double, float>(h->g.nint, h->src_v, h->rv, st);
-    if (!rc && h->src_u) rc = convert<double, float>(h->g.nint, h->src_u, h->ru, st);
+    rc = convert<double, float>(h->g.nalloc, h->src_v, h->rv, st);
+    if (!rc && h->src_u) rc = convert<double, float>(h->g.nalloc, h->src_u, h->ru, st);
     if (!rc) rc = convert<double, float>(h->g.nq, h->src_q, h->rq, st);
     if (!rc) rc = schur_rhs<float>(h, h->p32, h->rv, h->src_u ? h->ru : nullptr, h->rq, b, st);
   } else {
@@ -667,14 +680,17 @@ ahoc_status ahoc_poisson(ahoc_handle* h, const double* gin, double* wout, void* 
   hipStream_t st = (hipStream_t)stream;
   using namespace ahoc;
   int rc;
+  // dense caller arrays (row length n_x - 1) <-> padded interior rows
+  const Geom& g = h->g;
+  const long long rows = (long long)g.ni[1] * g.ni[2];
   if (h->opt.precision == AHOC_MIXED) {
-    rc = convert<double, float>(h->g.nint, gin, h->p32.bufA, st);
+    rc = pitch_copy<double, float>(rows, g.ni[0], gin, g.ni[0], h->p32.bufA, g.px, st);
     if (!rc) rc = poisson<float>(h, h->p32, h->p32.bufA, h->p32.scP, st);
-    if (!rc) rc = convert<float, double>(h->g.nint, h->p32.bufA, wout, st);
+    if (!rc) rc = pitch_copy<float, double>(rows, g.ni[0], h->p32.bufA, g.px, wout, g.ni[0], st);
   } else {
-    rc = convert<double, double>(h->g.nint, gin, h->p64.bufA, st);
+    rc = pitch_copy<double, double>(rows, g.ni[0], gin, g.ni[0], h->p64.bufA, g.px, st);
     if (!rc) rc = poisson<double>(h, h->p64, h->p64.bufA, h->p64.scP, st);
-    if (!rc) rc = convert<double, double>(h->g.nint, h->p64.bufA, wout, st);
+    if (!rc) rc = pitch_copy<double, double>(rows, g.ni[0], h->p64.bufA, g.px, wout, g.ni[0], st);
   }
   return (ahoc_status)rc;
 }
@@ -709,8 +725,8 @@ int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, 
   Prec<float>& P = h->p32;
   const Geom& g = h->g;
   int rc = 0;
-  TRY(fill(g.nint, 0.0, h->U64, st));
-  TRY(fill(g.nint, 0.0, h->V64, st));
+  TRY(fill(g.nalloc, 0.0, h->U64, st));
+  TRY(fill(g.nalloc, 0.0, h->V64, st));
   TRY(fill(g.nq, 0.0, h->Q64, st));
   int iters = 0, mv = 0, sweeps = 0;
   double prev = 0, upd = 0, relres = 0;
@@ -719,8 +735,8 @@ int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, 
     // residual of the coupled system at the current FP64 state (the data itself at sweep 0)
     const float* su = h->ru;
     if (sw == 0) {
-      TRY(convert<double, float>(g.nint, h->src_v, h->rv, st));
-      if (h->src_u) TRY(convert<double, float>(g.nint, h->src_u, h->ru, st));
+      TRY(convert<double, float>(g.nalloc, h->src_v, h->rv, st));
+      if (h->src_u) TRY(convert<double, float>(g.nalloc, h->src_u, h->ru, st));
       else su = nullptr;
       TRY(convert<double, float>(g.nq, h->src_q, h->rq, st));
     } else {
@@ -738,13 +754,13 @@ int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, 
     TRY(convert<double, float>(g.nq, h->dq, P.qT, st));
     TRY(vsolve<float>(h, P, P.qT, h->rv, st));
     TRY(usolve<float>(h, P, P.qT, su, st));
-    TRY(accumulate<float>(g.nint, P.bufB, h->U64, st));
-    TRY(accumulate<float>(g.nint, P.bufA, h->V64, st));
+    TRY(accumulate<float>(g.nalloc, P.bufB, h->U64, st));
+    TRY(accumulate<float>(g.nalloc, P.bufA, h->V64, st));
     TRY(accumulate<double>(g.nq, h->dq, h->Q64, st));
     ++sweeps;
-    const double du = absmax(h, P.bufB, false, g.nint, st, &rc);
+    const double du = absmax(h, P.bufB, false, g.nalloc, st, &rc);
     TRY(rc);
-    const double un = absmax(h, h->U64, true, g.nint, st, &rc);
+    const double un = absmax(h, h->U64, true, g.nalloc, st, &rc);
     TRY(rc);
     upd = un > 0 ? du / un : 0.0;
     // Remaining change of U after this sweep, estimated as upd * rho / (1 - rho) with the
@@ -876,7 +892,7 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
       if ((rc = dst_tables_init<float>(*tb, N))) { delete tb; return (ahoc_status)rc; }
       cache[key] = tb;
     }
-    rc = dst_pass<float>(*tb, (const float*)in, (float*)out, outer, inner, nullptr, 0, st);
+    rc = dst_pass<float>(*tb, (const float*)in, (float*)out, outer, inner, ni[0], nullptr, 0, st);
   } else if (precision == AHOC_FP64) {
     auto key = std::make_pair(N, 8);
     DstTables<double>* tb = (DstTables<double>*)cache[key];
@@ -885,7 +901,7 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
       if ((rc = dst_tables_init<double>(*tb, N))) { delete tb; return (ahoc_status)rc; }
       cache[key] = tb;
     }
-    rc = dst_pass<double>(*tb, (const double*)in, (double*)out, outer, inner, nullptr, 0, st);
+    rc = dst_pass<double>(*tb, (const double*)in, (double*)out, outer, inner, ni[0], nullptr, 0, st);
   } else {
     return AHOC_E_INVALID;
   }

@@ -26,8 +26,10 @@ struct Geom {
   int ni[3];         // interior counts N_a - 1 (unused axes: 1)
   int nn[3];         // nodal counts N_a + 1 (unused axes: 1)
   double h[3];       // spacings
-  long long nint;    // prod ni
+  long long nint;    // prod ni (interior nodes)
   long long nnodal;  // prod nn
+  int px;            // row pitch of interior arrays (ni[0] rounded up to 32 elements)
+  long long nalloc;  // px * ni[1] * ni[2]: elements of an interior array incl. row padding
   int nq;            // augmented unknowns
   int face_off[7];   // start of each face in Q, face f = 2*axis + side
 };
@@ -79,23 +81,25 @@ template <typename T> struct DstScale {
   const T* s_this = nullptr;  // s_t(k), k = 1..n_t   (length n_t)
   const T* s_a = nullptr;     // fastest other axis, length n_a
   const T* s_b = nullptr;     // second other axis (3-D), length n_b, or null
-  int na = 1;                 // column decode: col = ia + na * ib
+  int na = 1;                 // column decode: col = ia + na * ib (na = row pitch)
+  int nva = 1;                // valid ia < nva (columns ia >= nva are row padding)
   T c_ta = 0, c_tb = 0, c_ab = 0;
   T scale = 0;                // sign * prod_a 2/N_a
 };
 
 // One pass of the batched DST-I along an axis of an interior array viewed as
-// [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils (rows).
+// [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils: `outer` rows
+// of L elements starting `pitch` elements apart.
 template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
-             const DstScale<T>* fused, int tile_seqs, hipStream_t st);
+             long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st);
 
 // Length-specialised kernels (dst_fast.hip) for N in {32, 64, 96, ..., 4096}.
 bool dst_fast_supported(int N);
 int dst_fast_tile(int N, int elem_bytes);
 template <typename T>
 int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer,
-                  long long inner, const DstScale<T>* fused, int nseq, hipStream_t st);
+                  long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st);
 // 0 = automatic (specialised kernel where available), 1 = generic kernel only, 2 = specialised only
 void dst_set_variant(int v);
 int dst_get_variant();

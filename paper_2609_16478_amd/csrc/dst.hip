@@ -248,6 +248,7 @@ template <typename T> struct PassArgs {
   const T* sn;
   long long outer;   // rows (inner == 1) or slabs
   long long inner;   // contiguous extent; 1 = contiguous pencils
+  long long pitch;   // row stride of contiguous pencils
   long long ntile_inner;
   DstScale<T> fs;
 };
@@ -299,7 +300,7 @@ __global__ void __launch_bounds__(launch_cap<T>()) k_dst_pass(PassArgs<T> a) {
         const int it = it0 + u;
         const int p = it / per_row;
         const int m = (it - p * per_row) * blockDim.x + threadIdx.x;
-        v[u] = (it < iters && p < ncols && m < L) ? a.in[(base + p) * (long long)L + m] : T(0);
+        v[u] = (it < iters && p < ncols && m < L) ? a.in[(base + p) * a.pitch + m] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -338,13 +339,13 @@ __global__ void __launch_bounds__(launch_cap<T>()) k_dst_pass(PassArgs<T> a) {
     // columns of this pair, decoded into the other axes' mode indices
     const long long ca = c0 + 2 * s, cb = ca + 1;
     auto coef = [&](long long col, T& Ao, T& Bo) {
-      if (col >= a.inner) {
+      const long long ib = col / a.fs.na;
+      const long long ia = col - ib * a.fs.na;
+      if (col >= a.inner || ia >= a.fs.nva) {
         Ao = 1;
         Bo = 0;
         return;
       }
-      const long long ib = col / a.fs.na;
-      const long long ia = col - ib * a.fs.na;
       const T sa = a.fs.s_a[ia];
       const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
       Ao = sa + sb + a.fs.c_ab * sa * sb;
@@ -366,7 +367,7 @@ __global__ void __launch_bounds__(launch_cap<T>()) k_dst_pass(PassArgs<T> a) {
     for (int it = 0; it < iters; ++it) {
       const int p = it / per_row;
       const int m = (it - p * per_row) * blockDim.x + threadIdx.x;
-      if (m < L) a.out[(base + p) * (long long)L + m] = ldsr[2 * ((p >> 1) * ld + m + 1) + (p & 1)];
+      if (m < L) a.out[(base + p) * a.pitch + m] = ldsr[2 * ((p >> 1) * ld + m + 1) + (p & 1)];
     }
   } else {
     const int lp = __builtin_ctz(P);
@@ -488,10 +489,11 @@ int dst_get_variant() { return g_variant; }
 
 template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
-             const DstScale<T>* fused, int tile_seqs, hipStream_t st) {
+             long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st) {
   const int N = tb.N;
+  if (inner == 1 && pitch < N - 1) return ST_INVALID;
   if (g_variant != 1 && dst_fast_supported(N)) {
-    const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, fused, tile_seqs, st);
+    const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, pitch, fused, tile_seqs, st);
     if (rc != ST_UNSUPPORTED || g_variant == 2) return rc;
   }
   const int ppt = tb.ppt;
@@ -514,6 +516,7 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
   a.sn = tb.sn;
   a.outer = outer;
   a.inner = inner;
+  a.pitch = pitch;
   const long long P = 2LL * nseq;
   long long blocks;
   if (inner == 1) {
@@ -542,8 +545,8 @@ template int dst_tables_init<double>(DstTables<double>&, int);
 template void dst_tables_free<float>(DstTables<float>&);
 template void dst_tables_free<double>(DstTables<double>&);
 template int dst_pass<float>(const DstTables<float>&, const float*, float*, long long, long long,
-                             const DstScale<float>*, int, hipStream_t);
+                             long long, const DstScale<float>*, int, hipStream_t);
 template int dst_pass<double>(const DstTables<double>&, const double*, double*, long long,
-                              long long, const DstScale<double>*, int, hipStream_t);
+                              long long, long long, const DstScale<double>*, int, hipStream_t);
 
 }  // namespace ahoc

@@ -396,7 +396,8 @@ template <typename T> struct Args {
   T* out;
   const cx<T>* tw;
   const T* sn;
-  long long outer, inner, ntile_inner;
+  long long outer, inner, pitch, ntile_inner;
+  int lg_nseq;
   DstScale<T> fs;
 };
 
@@ -412,29 +413,36 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   constexpr int HN = N / 2;
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   const int nseq = blockDim.x / TPS;
+  const int lgq = a.lg_nseq;
   const int s = threadIdx.x / TPS;
   const int ts = threadIdx.x - s * TPS;
   cx<T>* seq = lds + s * LDQ;
   cx<T>* tot = lds + nseq * LDQ + s * (TPS / 64 > 0 ? TPS / 64 : 1);
   const int P = 2 * nseq;
 
+  // The tile's first element (uniform 64-bit base); per-lane offsets below are 32-bit.
   const bool rows = (a.inner == 1);
   long long base = 0, c0 = 0;
   int ncols = P;
+  int es, ps;  // element stride along a pencil, stride between pencils
   if (rows) {
     const long long row0 = (long long)blockIdx.x * P;
-    base = row0 * L;  // element offset of the tile's first row
+    base = row0 * a.pitch;
     const long long left = a.outer - row0;
     ncols = left < P ? (int)left : P;
+    es = 1;
+    ps = (int)a.pitch;
   } else {
     const long long o = blockIdx.x / a.ntile_inner;
     c0 = (blockIdx.x - o * a.ntile_inner) * (long long)P;
     base = o * (long long)L * a.inner + c0;
     const long long left = a.inner - c0;
     ncols = left < P ? (int)left : P;
+    es = (int)a.inner;
+    ps = 1;
   }
-  const long long es = rows ? 1 : a.inner;           // element stride along the pencil
-  const long long ps = rows ? (long long)L : 1;      // pencil stride
+  const T* __restrict__ src = a.in + base;
+  T* __restrict__ dst = a.out + base;
 
   // ---- load + pre-weighting: item = (pair q, position m in 1..N/2)
   {
@@ -450,17 +458,18 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
           q = it / HN;
           m = 1 + (it - q * HN);
         } else {
-          q = it % nseq;
-          m = 1 + it / nseq;
+          q = it & (nseq - 1);
+          m = 1 + (it >> lgq);
         }
         const bool ok = it < items;
-        const int pa = 2 * q, pb = 2 * q + 1;
-        const long long ra = base + pa * ps, rb = base + pb * ps;
-        const bool oka = ok && pa < ncols, okb = ok && pb < ncols;
-        xa[u] = oka ? a.in[ra + (long long)(m - 1) * es] : T(0);
-        xb[u] = okb ? a.in[rb + (long long)(m - 1) * es] : T(0);
-        ya[u] = (oka && m < HN) ? a.in[ra + (long long)(N - m - 1) * es] : T(0);
-        yb[u] = (okb && m < HN) ? a.in[rb + (long long)(N - m - 1) * es] : T(0);
+        const int pa = 2 * q;
+        const bool oka = ok && pa < ncols, okb = ok && pa + 1 < ncols;
+        const int o1 = pa * ps + (m - 1) * es;       // pencil a, position m
+        const int o2 = pa * ps + (N - m - 1) * es;   // pencil a, position N - m
+        xa[u] = oka ? src[o1] : T(0);
+        xb[u] = okb ? src[o1 + ps] : T(0);
+        ya[u] = (oka && m < HN) ? src[o2] : T(0);
+        yb[u] = (okb && m < HN) ? src[o2 + ps] : T(0);
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -471,8 +480,8 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
             q = it / HN;
             m = 1 + (it - q * HN);
           } else {
-            q = it % nseq;
-            m = 1 + it / nseq;
+            q = it & (nseq - 1);
+            m = 1 + (it >> lgq);
           }
           const T w = a.sn[m];
           cx<T>* sq = lds + q * LDQ;
@@ -511,13 +520,13 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   if constexpr (FUSED) {
     const long long ca = c0 + 2 * s, cb = ca + 1;
     auto coef = [&](long long col, T& Ao, T& Bo) {
-      if (col >= a.inner) {
+      const long long ib = col / a.fs.na;
+      const long long ia = col - ib * a.fs.na;
+      if (col >= a.inner || ia >= a.fs.nva) {
         Ao = 1;
         Bo = 0;
         return;
       }
-      const long long ib = col / a.fs.na;
-      const long long ia = col - ib * a.fs.na;
       const T sa = a.fs.s_a[ia];
       const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
       Ao = sa + sb + a.fs.c_ab * sa * sb;
@@ -541,13 +550,14 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
         q = it / L;
         m = 1 + (it - q * L);
       } else {
-        q = it % nseq;
-        m = 1 + it / nseq;
+        q = it & (nseq - 1);
+        m = 1 + (it >> lgq);
       }
       const cx<T> v = lds[q * LDQ + pad(m)];
-      const int pa = 2 * q, pb = 2 * q + 1;
-      if (pa < ncols) a.out[base + pa * ps + (long long)(m - 1) * es] = v.x;
-      if (pb < ncols) a.out[base + pb * ps + (long long)(m - 1) * es] = v.y;
+      const int pa = 2 * q;
+      const int o = pa * ps + (m - 1) * es;
+      if (pa < ncols) dst[o] = v.x;
+      if (pa + 1 < ncols) dst[o + ps] = v.y;
     }
   }
 }
@@ -629,8 +639,11 @@ int dst_fast_tile(int N, int elem_bytes) {
 
 template <typename T>
 int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer,
-                  long long inner, const DstScale<T>* fused, int nseq, hipStream_t st) {
+                  long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st) {
   if (fused && inner == 1) return ST_INVALID;
+  // per-lane offsets are 32-bit: one slab (rows: one tile) must stay below 2^31 elements
+  if ((double)(N - 1) * (double)inner >= 2147483647.0 || (inner == 1 && 256.0 * pitch >= 2147483647.0))
+    return ST_UNSUPPORTED;
   fast::Args<T> a;
   a.in = in;
   a.out = out;
@@ -638,8 +651,10 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   a.sn = sn;
   a.outer = outer;
   a.inner = inner;
+  a.pitch = pitch;
   if (nseq <= 0) nseq = dst_fast_tile(N, (int)sizeof(T));
   if (nseq <= 0 || (nseq & (nseq - 1))) return ST_UNSUPPORTED;
+  a.lg_nseq = __builtin_ctz(nseq);
   a.ntile_inner = inner == 1 ? 1 : (inner + 2LL * nseq - 1) / (2LL * nseq);
   if (fused) a.fs = *fused;
   const bool f = fused != nullptr;
@@ -661,8 +676,8 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
 }
 
 template int dst_fast_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long,
-                                  long long, const DstScale<float>*, int, hipStream_t);
+                                  long long, long long, const DstScale<float>*, int, hipStream_t);
 template int dst_fast_pass<double>(int, const cx<double>*, const double*, const double*, double*,
-                                   long long, long long, const DstScale<double>*, int, hipStream_t);
+                                   long long, long long, long long, const DstScale<double>*, int, hipStream_t);
 
 }  // namespace ahoc

@@ -29,6 +29,8 @@ int out_u(const Geom& g, const T* Ui, const double* gD, double* u, hipStream_t s
 template <typename T>
 int out_v(const Geom& g, const T* Vi, const double* Q, const double* vedge, double* v, hipStream_t st);
 int mul(long long n, const double* a, const double* b, double* out, hipStream_t st);
+template <typename Ti, typename To>
+int pitch_copy(long long rows, int cols, const Ti* in, long long ip, To* out, long long op, hipStream_t st);
 template <typename Ti, typename To> int convert(long long n, const Ti* in, To* out, hipStream_t st);
 template <typename Tx> int accumulate(long long n, const Tx* x, double* y, hipStream_t st);
 template <typename Tx>

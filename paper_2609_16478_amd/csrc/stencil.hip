@@ -32,7 +32,7 @@ __device__ __forceinline__ long long nod(const Geom& g, int i, int j, int k) {
   return ((long long)k * g.nn[1] + j) * g.nn[0] + i;
 }
 __device__ __forceinline__ long long inr(const Geom& g, int i, int j, int k) {
-  return ((long long)(k - 1) * g.ni[1] + (j - 1)) * g.ni[0] + (i - 1);
+  return ((long long)(k - 1) * g.ni[1] + (j - 1)) * g.px + (i - 1);
 }
 
 // number of coordinates of node (i,j,k) on the boundary
@@ -56,10 +56,10 @@ template <int DIM> __device__ __forceinline__ int qidx(const Geom& g, int i, int
   return g.face_off[f] + (j - 1) * g.ni[0] + (i - 1);
 }
 
-// decode a linear interior index into (i, j, k), 1-based
-template <int DIM> __device__ __forceinline__ void dec_int(const Geom& g, long long e, int& i, int& j, int& k) {
-  i = (int)(e % g.ni[0]) + 1;
-  long long r = e / g.ni[0];
+// decode a linear interior-array index into (i, j, k), 1-based; false on row padding
+template <int DIM> __device__ __forceinline__ bool dec_int(const Geom& g, long long e, int& i, int& j, int& k) {
+  i = (int)(e % g.px) + 1;
+  long long r = e / g.px;
   if (DIM == 3) {
     j = (int)(r % g.ni[1]) + 1;
     k = (int)(r / g.ni[1]) + 1;
@@ -67,6 +67,7 @@ template <int DIM> __device__ __forceinline__ void dec_int(const Geom& g, long l
     j = (int)r + 1;
     k = 0;
   }
+  return i <= g.ni[0];
 }
 
 // decode Q index -> boundary node, face axis and inward step
@@ -106,10 +107,13 @@ template <int DIM> __device__ __forceinline__ double lw(const Weights& w, int dx
 template <typename T, int DIM>
 __global__ void k_lift(Geom g, Weights w, const T* __restrict__ Q, const T* __restrict__ src,
                        T* __restrict__ G) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
        e += (long long)gridDim.x * blockDim.x) {
     int i, j, k;
-    dec_int<DIM>(g, e, i, j, k);
+    if (!dec_int<DIM>(g, e, i, j, k)) {
+      G[e] = T(0);
+      continue;
+    }
     T acc = src ? src[e] : T(0);
     const bool nearb = i == 1 || i == g.ni[0] || j == 1 || j == g.ni[1] ||
                        (DIM == 3 && (k == 1 || k == g.ni[2]));
@@ -132,10 +136,13 @@ template <typename T, int DIM>
 __global__ void k_rhs_u(Geom g, Weights w, const T* __restrict__ V, const T* __restrict__ Q,
                         const T* __restrict__ ia, const T* __restrict__ src, T* __restrict__ G) {
   const T m0 = (T)w.m0, m1 = (T)w.m1;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
        e += (long long)gridDim.x * blockDim.x) {
     int i, j, k;
-    dec_int<DIM>(g, e, i, j, k);
+    if (!dec_int<DIM>(g, e, i, j, k)) {
+      G[e] = T(0);
+      continue;
+    }
     T acc = src ? src[e] : T(0);
     acc += m0 * V[e] * ia[nod(g, i, j, k)];
     T nb = 0;
@@ -181,10 +188,14 @@ __global__ void k_resid_vol(Geom g, Weights w, const double* __restrict__ U, con
                             const double* __restrict__ Q, const double* __restrict__ ia,
                             const double* __restrict__ src_u, const double* __restrict__ src_v,
                             T* __restrict__ ru, T* __restrict__ rv) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
        e += (long long)gridDim.x * blockDim.x) {
     int i, j, k;
-    dec_int<DIM>(g, e, i, j, k);
+    if (!dec_int<DIM>(g, e, i, j, k)) {
+      rv[e] = T(0);
+      ru[e] = T(0);
+      continue;
+    }
     double lv = 0, lu = 0, mv = 0;
     const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
     for (int dz = zlo; dz <= zhi; ++dz)
@@ -274,10 +285,14 @@ template <int DIM>
 __global__ void k_src_vol(Geom g, Weights w, const double* __restrict__ f, const double* __restrict__ alpha,
                           const double* __restrict__ gD, const double* __restrict__ lapgD,
                           double* __restrict__ src_v, double* __restrict__ src_u) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nint;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
        e += (long long)gridDim.x * blockDim.x) {
     int i, j, k;
-    dec_int<DIM>(g, e, i, j, k);
+    if (!dec_int<DIM>(g, e, i, j, k)) {
+      src_v[e] = 0.0;
+      if (src_u) src_u[e] = 0.0;
+      continue;
+    }
     double mf = w.m0 * f[nod(g, i, j, k)];
 #pragma unroll
     for (int a = 0; a < DIM; ++a)
@@ -383,6 +398,19 @@ __global__ void k_absmax(long long n, const Tx* __restrict__ x, double* __restri
   if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
 }
 
+// rows x cols block copy between arrays with different row pitches (with conversion)
+template <typename Ti, typename To>
+__global__ void k_pitch_copy(long long rows, int cols, const Ti* __restrict__ in, long long ip,
+                             To* __restrict__ out, long long op) {
+  const long long n = rows * cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / cols;
+    const int c = (int)(e - r * cols);
+    out[r * op + c] = (To)in[r * ip + c];
+  }
+}
+
 __global__ void k_mul(long long n, const double* __restrict__ a, const double* __restrict__ b,
                       double* __restrict__ out) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
@@ -417,14 +445,14 @@ __global__ void k_fill(long long n, double v, double* __restrict__ x) {
 
 template <typename T>
 int lift(const Geom& g, const Weights& w, const T* Q, const T* src, T* G, hipStream_t st) {
-  LAUNCH_TDIM(k_lift, T, dim3(nblocks(g.nint)), g, w, Q, src, G);
+  LAUNCH_TDIM(k_lift, T, dim3(nblocks(g.nalloc)), g, w, Q, src, G);
   return ST_OK;
 }
 
 template <typename T>
 int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
           hipStream_t st) {
-  LAUNCH_TDIM(k_rhs_u, T, dim3(nblocks(g.nint)), g, w, V, Q, ia, src, G);
+  LAUNCH_TDIM(k_rhs_u, T, dim3(nblocks(g.nalloc)), g, w, V, Q, ia, src, G);
   return ST_OK;
 }
 
@@ -439,7 +467,7 @@ template <typename T>
 int resid64(const Geom& g, const Weights& w, const double* U, const double* V, const double* Q,
             const double* ia, const double* af, const double* src_u, const double* src_v,
             const double* src_q, T* ru, T* rv, T* rq, hipStream_t st) {
-  LAUNCH_TDIM(k_resid_vol, T, dim3(nblocks(g.nint)), g, w, U, V, Q, ia, src_u, src_v, ru, rv);
+  LAUNCH_TDIM(k_resid_vol, T, dim3(nblocks(g.nalloc)), g, w, U, V, Q, ia, src_u, src_v, ru, rv);
   LAUNCH_TDIM(k_resid_q, T, dim3(nblocks(g.nq)), g, w, U, Q, af, src_q, rq);
   return ST_OK;
 }
@@ -459,7 +487,7 @@ int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
                   const double* gD, const double* gN, const double* lapgD, double* src_v,
                   double* src_u, double* src_q, hipStream_t st) {
-  LAUNCH_DIM(k_src_vol, dim3(nblocks(g.nint)), g, w, f, alpha, gD, lapgD, src_v, src_u);
+  LAUNCH_DIM(k_src_vol, dim3(nblocks(g.nalloc)), g, w, f, alpha, gD, lapgD, src_v, src_u);
   LAUNCH_DIM(k_src_q, dim3(nblocks(g.nq)), g, w, alpha, gD, gN, lapgD, src_q);
   return ST_OK;
 }
@@ -473,6 +501,13 @@ int out_u(const Geom& g, const T* Ui, const double* gD, double* u, hipStream_t s
 template <typename T>
 int out_v(const Geom& g, const T* Vi, const double* Q, const double* vedge, double* v, hipStream_t st) {
   LAUNCH_TDIM(k_out_v, T, dim3(nblocks(g.nnodal)), g, Vi, Q, vedge, v);
+  return ST_OK;
+}
+
+template <typename Ti, typename To>
+int pitch_copy(long long rows, int cols, const Ti* in, long long ip, To* out, long long op, hipStream_t st) {
+  hipLaunchKernelGGL((k_pitch_copy<Ti, To>), dim3(nblocks(rows * cols)), dim3(TPB), 0, st, rows, cols, in, ip, out, op);
+  AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 
@@ -524,6 +559,9 @@ int fill(long long n, double v, double* x, hipStream_t st) {
 
 INST_T(float)
 INST_T(double)
+template int pitch_copy<double, float>(long long, int, const double*, long long, float*, long long, hipStream_t);
+template int pitch_copy<float, double>(long long, int, const float*, long long, double*, long long, hipStream_t);
+template int pitch_copy<double, double>(long long, int, const double*, long long, double*, long long, hipStream_t);
 template int convert<double, float>(long long, const double*, float*, hipStream_t);
 template int convert<float, double>(long long, const float*, double*, hipStream_t);
 template int convert<double, double>(long long, const double*, double*, hipStream_t);
