@@ -45,7 +45,7 @@ def _pmc_traffic(kernel_src_hash):
 
 
 def _src_hash():
-    p = os.path.join(ROOT, "paper_2609_16478_amd", "csrc", "dst.hip")
+    p = os.path.join(ROOT, "paper_2609_16478_amd", "csrc", "dst_fast.hip")
     return hashlib.sha1(open(p, "rb").read()).hexdigest()
 
 
@@ -78,6 +78,11 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=80)
+    ap.add_argument("--profile-matvec", type=int, default=0,
+                    help="profiling target: set up the mixed-precision handle and run this many "
+                         "Schur matvecs, then exit (no JSON line)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="profiling target: three plain 2 GiB device copies (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
@@ -89,6 +94,14 @@ def main():
     import workloads as W
 
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        x = torch.ones(2 ** 28, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(f"[bench] copy calibration: 3 copies of {x.numel() * 8} bytes", file=sys.stderr)
+        return
     n = args.n
     t0 = time.perf_counter()
     prob = W.manufactured(W.C3_ALPHA, W.C3_U, (n, n, n), xp="torch", device=dev, chunk=32,
@@ -98,6 +111,17 @@ def main():
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     print(f"[bench] n={n} inputs generated on device in {t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    if args.profile_matvec:
+        s = ah.Solver(prob, precision=ah.MIXED)
+        q = torch.randn(s.nq, dtype=torch.float64, device=dev)
+        for _ in range(args.profile_matvec):
+            q = s.schur_apply(q)
+            q = q / q.norm()
+        torch.cuda.synchronize()
+        s.close()
+        print(f"[bench] {args.profile_matvec} Schur matvecs done (n={n})", file=sys.stderr)
+        return
 
     def run(prec, steps, warmup, **opts):
         s = ah.Solver(prob, precision=prec, **opts)
@@ -175,7 +199,7 @@ def main():
                    "fp64": result_fp64, "kernels": kernels},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_dst_pass<float,32,false> (DST-I pass, rows and strided)",
+                     "kernel": f"k_dst_fast<float,{n},false> (DST-I pass along x and y)",
                      "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6,
                      "fused_pass_GBps": (bytes_launch / (fused_ms / fused_cnt / 1e3) / 1e9) if fused_cnt else None},
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
