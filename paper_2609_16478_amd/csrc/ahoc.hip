@@ -43,6 +43,10 @@ template <typename T> struct Prec {
   T* bufB = nullptr;  // interior work (U)
   T* qT = nullptr;    // N_q, Q in this precision
   T* zq = nullptr;    // N_q zeros
+  T* wf[3] = {nullptr, nullptr, nullptr};  // per axis: one-sided face weights w_lo(k), w_hi(k)
+  T* Fx = nullptr;    // face sums: x faces [2][n_y' n_z'], y faces [2][n_z' px], z faces [2][n_y' px]
+  T* Fy = nullptr;
+  T* Fz = nullptr;
   DstScale<T> scV, scU, scP;
   bool ready = false;
 };
@@ -237,6 +241,25 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     }
     TRY(alloc_t(h, &P.s[a], g.ni[a]));
     AHOC_HIP_TRY(hipMemcpy(P.s[a], s.data(), sizeof(T) * g.ni[a], hipMemcpyHostToDevice));
+    // 6 U_1 - 3/2 U_2 + 2/9 U_3 of a sine mode k, for the low face (nodes 1,2,3) and the
+    // high face (nodes N-1, N-2, N-3, where sin(pi k (N-m)/N) = (-1)^(k+1) sin(pi k m/N))
+    std::vector<T> wv(2 * g.ni[a]);
+    for (int k = 1; k <= g.ni[a]; ++k) {
+      long double acc = 0;
+      for (int m = 1; m <= 3; ++m) acc += (long double)h->w.os[m] * sinl(pi * k * m / (long double)g.n[a]);
+      wv[k - 1] = (T)acc;
+      wv[g.ni[a] + k - 1] = (T)((k % 2 == 1) ? acc : -acc);
+    }
+    TRY(alloc_t(h, &P.wf[a], 2 * g.ni[a]));
+    AHOC_HIP_TRY(hipMemcpy(P.wf[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice));
+  }
+  if (g.dim == 3) {
+    TRY(alloc_t(h, &P.Fx, 2LL * g.ni[1] * g.ni[2]));
+    TRY(alloc_t(h, &P.Fy, 2LL * g.px * g.ni[2]));
+    TRY(alloc_t(h, &P.Fz, 2LL * g.px * g.ni[1]));
+  } else {
+    TRY(alloc_t(h, &P.Fx, 2LL * g.ni[1]));
+    TRY(alloc_t(h, &P.Fy, 2LL * g.px));
   }
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
@@ -320,6 +343,72 @@ template <typename T> int usolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T
   return poisson<T>(h, P, P.bufB, P.scU, st);
 }
 
+// Whether every axis has a length-specialised DST kernel (needed for the face sums).
+bool faces_available(const Geom& g) {
+  if (dst_get_variant() == 1) return false;
+  for (int a = 0; a < g.dim; ++a)
+    if (!dst_fast_supported(g.n[a])) return false;
+  return true;
+}
+
+// U-solve for the boundary residual only.  The one-sided combination
+// 6 U_1 - 3/2 U_2 + 2/9 U_3 on each face is formed from the spectrum along that face's
+// normal (a weighted sum over modes) instead of from physical U next to the face: the
+// rounding error of a transform is then not amplified by the h^-2 of the gather, and the
+// last inverse x pass is not needed.  Face sums land in P.Fx, P.Fy, P.Fz (physical).
+template <typename T> int usolve_faces(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  const Geom& g = h->g;
+  hipEvent_t e = tbegin(h, st);
+  TRY(rhs_u<T>(g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
+  tend(h, AHOC_K_RHS_U, e, (double)sizeof(T) * (2.0 * g.nint + g.nnodal) + (src ? g.nint * sizeof(T) : 0), st);
+  T* buf = P.bufB;
+  const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);
+  auto run = [&](int kind, const DstTables<T>& tb, T* arr, long long outer, long long inner,
+                 const DstScale<T>* f, int tile, const DstFaces<T>* fc, double bytes) -> int {
+    hipEvent_t ev = tbegin(h, st);
+    const int rc = dst_pass<T>(tb, arr, arr, outer, inner, g.px, f, tile, st, fc);
+    if (bytes > 0) tend(h, kind, ev, bytes, st);
+    return rc;
+  };
+  if (g.dim == 3) {
+    const long long rows = (long long)g.ni[1] * g.ni[2];
+    DstFaces<T> fz;
+    fz.out = P.Fz;
+    fz.w = P.wf[2];
+    fz.plane = (long long)g.px * g.ni[1];
+    fz.mode = 1;
+    DstFaces<T> fy;
+    fy.out = P.Fy;
+    fy.w = P.wf[1];
+    fy.plane = (long long)g.px * g.ni[2];
+    fy.mode = 2;
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], buf, rows, 1, nullptr, P.tile[0], nullptr, pass_bytes));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], buf, g.ni[2], g.px, nullptr, P.tile[1], nullptr, pass_bytes));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[2], buf, 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fz, pass_bytes));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], buf, g.ni[2], g.px, nullptr, P.tile[1], &fy, pass_bytes));
+    hipEvent_t ef = tbegin(h, st);
+    TRY(face_rows<T>(rows, g.ni[0], g.px, buf, P.wf[0], P.Fx, rows, st));
+    // remaining inverse transforms of the small face arrays (spectral in x, and in y for Fz)
+    TRY(dst_pass<T>(P.tb[0], P.Fz, P.Fz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Fz, P.Fz, 2, g.px, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
+    tend(h, AHOC_K_GATHER, ef, (double)g.nint * sizeof(T), st);
+  } else {
+    DstFaces<T> fy;
+    fy.out = P.Fy;
+    fy.w = P.wf[1];
+    fy.plane = g.px;
+    fy.mode = 1;
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], buf, g.ni[1], 1, nullptr, P.tile[0], nullptr, pass_bytes));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], buf, 1, g.px, &P.scU, P.tile[1], &fy, pass_bytes));
+    hipEvent_t ef = tbegin(h, st);
+    TRY(face_rows<T>(g.ni[1], g.ni[0], g.px, buf, P.wf[0], P.Fx, g.ni[1], st));
+    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2, 1, g.px, nullptr, 0, st));
+    tend(h, AHOC_K_GATHER, ef, (double)g.nint * sizeof(T), st);
+  }
+  return ST_OK;
+}
+
 template <typename T> const T* q_in(ahoc_handle* h, Prec<T>& P, const double* q, hipStream_t st, int* rc) {
   if constexpr (sizeof(T) == 8) {
     (void)h; (void)P; (void)st;
@@ -338,11 +427,17 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
   const T* qT = q_in<T>(h, P, q, st, &rc);
   TRY(rc);
   TRY(vsolve<T>(h, P, qT, nullptr, st));
-  TRY(usolve<T>(h, P, qT, nullptr, st));
-  hipEvent_t eg = tbegin(h, st);
-  TRY(gather<T>(h->g, h->w, P.bufB, qT, P.af, nullptr, y, st));
-  tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (3 * sizeof(T) + 2 * sizeof(T) + sizeof(double)), st);
-  // algorithmic bytes of one matvec: lift write, 10 pass read+writes, rhs_u, gather
+  if (faces_available(h->g)) {
+    TRY(usolve_faces<T>(h, P, qT, nullptr, st));
+    TRY(gather_faces<T>(h->g, P.Fx, P.Fy, P.Fz, qT, P.af, nullptr, y, st));
+  } else {
+    TRY(usolve<T>(h, P, qT, nullptr, st));
+    hipEvent_t eg = tbegin(h, st);
+    TRY(gather<T>(h->g, h->w, P.bufB, qT, P.af, nullptr, y, st));
+    tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (3 * sizeof(T) + 2 * sizeof(T) + sizeof(double)), st);
+  }
+  // algorithmic bytes of one matvec: lift write, pass read+writes, rhs_u, gather (the face
+  // path replaces the last inverse pass by a read-only row reduction)
   const double s = sizeof(T);
   tend(h, AHOC_K_MATVEC, e, s * (21.0 * h->g.nint + 2.0 * h->g.nint + h->g.nnodal), st);
   return ST_OK;
@@ -352,8 +447,13 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
 template <typename T>
 int schur_rhs(ahoc_handle* h, Prec<T>& P, const T* sv, const T* su, const T* sq, double* b, hipStream_t st) {
   TRY(vsolve<T>(h, P, P.zq, sv, st));
-  TRY(usolve<T>(h, P, P.zq, su, st));
-  TRY(gather<T>(h->g, h->w, P.bufB, P.zq, P.af, sq, h->R, st));
+  if (faces_available(h->g)) {
+    TRY(usolve_faces<T>(h, P, P.zq, su, st));
+    TRY(gather_faces<T>(h->g, P.Fx, P.Fy, P.Fz, P.zq, P.af, sq, h->R, st));
+  } else {
+    TRY(usolve<T>(h, P, P.zq, su, st));
+    TRY(gather<T>(h->g, h->w, P.bufB, P.zq, P.af, sq, h->R, st));
+  }
   return axpby(h->g.nq, -1.0, h->R, 0.0, b, st);
 }
 

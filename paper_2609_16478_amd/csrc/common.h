@@ -87,19 +87,33 @@ template <typename T> struct DstScale {
   T scale = 0;                // sign * prod_a 2/N_a
 };
 
+// Optional face sums of a pass (one-sided normal combination along the pass axis):
+//   mode 1 (fused pass): out[col] = sum_k W(k) w_lo(k), out[plane + col] = sum_k W(k) w_hi(k)
+//          over the scaled spectrum W of each column, before the inverse transform;
+//   mode 2 (plain strided pass): the same sums over the pass *input*, written at
+//          out[o * inner + col] (+ plane for the high face), o = slab index.
+template <typename T> struct DstFaces {
+  T* out = nullptr;
+  const T* w = nullptr;  // w_lo[0..L), w_hi[0..L)
+  long long plane = 0;
+  int mode = 0;
+};
+
 // One pass of the batched DST-I along an axis of an interior array viewed as
 // [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils: `outer` rows
 // of L elements starting `pitch` elements apart.
 template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
-             long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st);
+             long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st,
+             const DstFaces<T>* faces = nullptr);
 
 // Length-specialised kernels (dst_fast.hip) for N in {32, 64, 96, ..., 4096}.
 bool dst_fast_supported(int N);
 int dst_fast_tile(int N, int elem_bytes);
 template <typename T>
 int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer,
-                  long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st);
+                  long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st,
+                  const DstFaces<T>* faces = nullptr);
 // 0 = automatic (specialised kernel where available), 1 = generic kernel only, 2 = specialised only
 void dst_set_variant(int v);
 int dst_get_variant();

@@ -489,13 +489,15 @@ int dst_get_variant() { return g_variant; }
 
 template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
-             long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st) {
+             long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st,
+             const DstFaces<T>* faces) {
   const int N = tb.N;
   if (inner == 1 && pitch < N - 1) return ST_INVALID;
   if (g_variant != 1 && dst_fast_supported(N)) {
-    const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, pitch, fused, tile_seqs, st);
+    const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, pitch, fused, tile_seqs, st, faces);
     if (rc != ST_UNSUPPORTED || g_variant == 2) return rc;
   }
+  if (faces && faces->mode) return ST_UNSUPPORTED;  // face sums only in the specialised kernels
   const int ppt = tb.ppt;
   if (!ppt || !tb.tw) return ST_INVALID;
   const int tps = N / ppt;
@@ -545,8 +547,9 @@ template int dst_tables_init<double>(DstTables<double>&, int);
 template void dst_tables_free<float>(DstTables<float>&);
 template void dst_tables_free<double>(DstTables<double>&);
 template int dst_pass<float>(const DstTables<float>&, const float*, float*, long long, long long,
-                             long long, const DstScale<float>*, int, hipStream_t);
+                             long long, const DstScale<float>*, int, hipStream_t, const DstFaces<float>*);
 template int dst_pass<double>(const DstTables<double>&, const double*, double*, long long,
-                              long long, long long, const DstScale<double>*, int, hipStream_t);
+                              long long, long long, const DstScale<double>*, int, hipStream_t,
+                              const DstFaces<double>*);
 
 }  // namespace ahoc

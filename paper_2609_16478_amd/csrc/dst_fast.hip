@@ -399,11 +399,43 @@ template <typename T> struct Args {
   long long outer, inner, pitch, ntile_inner;
   int lg_nseq;
   DstScale<T> fs;
+  DstFaces<T> fc;
 };
+
+// sum over the TPS lanes of one pencil pair (all lanes receive the total)
+template <typename T, int TPS>
+__device__ __forceinline__ void seg_sum4(T& a, T& b, T& c, T& d, cx<T>* tot, int ts) {
+  constexpr int W = TPS < 64 ? TPS : 64;
+#pragma unroll
+  for (int m = W / 2; m >= 1; m >>= 1) {
+    a += __shfl_xor(a, m, W);
+    b += __shfl_xor(b, m, W);
+    c += __shfl_xor(c, m, W);
+    d += __shfl_xor(d, m, W);
+  }
+  if constexpr (TPS > 64) {
+    const int wv = ts >> 6;
+    if ((ts & 63) == 0) {
+      tot[2 * wv].x = a;
+      tot[2 * wv].y = b;
+      tot[2 * wv + 1].x = c;
+      tot[2 * wv + 1].y = d;
+    }
+    __syncthreads();
+    a = b = c = d = 0;
+    for (int q = 0; q < TPS / 64; ++q) {
+      a += tot[2 * q].x;
+      b += tot[2 * q].y;
+      c += tot[2 * q + 1].x;
+      d += tot[2 * q + 1].y;
+    }
+    __syncthreads();
+  }
+}
 
 template <typename T> constexpr int cap() { return sizeof(T) == 8 ? 256 : 512; }
 
-template <typename T, int N, bool FUSED>
+template <typename T, int N, bool FUSED, int FACES>
 __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   constexpr int PPT = Plan<N>::PPT;
@@ -416,8 +448,10 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   const int lgq = a.lg_nseq;
   const int s = threadIdx.x / TPS;
   const int ts = threadIdx.x - s * TPS;
+  constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);  // per pair: scan / face partials
   cx<T>* seq = lds + s * LDQ;
-  cx<T>* tot = lds + nseq * LDQ + s * (TPS / 64 > 0 ? TPS / 64 : 1);
+  cx<T>* tot = lds + nseq * LDQ + s * NTOT;
+  cx<T>* fscr = lds + nseq * LDQ + nseq * NTOT;  // FACES == 2: two words per thread
   const int P = 2 * nseq;
 
   // The tile's first element (uniform 64-bit base); per-lane offsets below are 32-bit.
@@ -445,6 +479,7 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   T* __restrict__ dst = a.out + base;
 
   // ---- load + pre-weighting: item = (pair q, position m in 1..N/2)
+  T fla = 0, fha = 0, flb = 0, fhb = 0;  // FACES == 2: face sums of this thread's items
   {
     constexpr int U = 8;
     const int items = nseq * HN;
@@ -470,6 +505,27 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
         xb[u] = okb ? src[o1 + ps] : T(0);
         ya[u] = (oka && m < HN) ? src[o2] : T(0);
         yb[u] = (okb && m < HN) ? src[o2 + ps] : T(0);
+      }
+      if constexpr (FACES == 2) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int it = i0 + u * blockDim.x + threadIdx.x;
+          if (it < items) {
+            const int m = 1 + (it >> lgq);
+            const T wl1 = a.fc.w[m - 1], wh1 = a.fc.w[L + m - 1];
+            fla += xa[u] * wl1;
+            fha += xa[u] * wh1;
+            flb += xb[u] * wl1;
+            fhb += xb[u] * wh1;
+            if (m < HN) {
+              const T wl2 = a.fc.w[N - m - 1], wh2 = a.fc.w[L + N - m - 1];
+              fla += ya[u] * wl2;
+              fha += ya[u] * wh2;
+              flb += yb[u] * wl2;
+              fhb += yb[u] * wh2;
+            }
+          }
+        }
       }
 #pragma unroll
       for (int u = 0; u < U; ++u) {
@@ -510,8 +566,37 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
       zz.y = 0;
       lds[threadIdx.x * LDQ] = zz;
     }
+    if constexpr (FACES == 2) {
+      fscr[2 * threadIdx.x].x = fla;
+      fscr[2 * threadIdx.x].y = fha;
+      fscr[2 * threadIdx.x + 1].x = flb;
+      fscr[2 * threadIdx.x + 1].y = fhb;
+    }
   }
   __syncthreads();
+  if constexpr (FACES == 2) {
+    // threads q, q + nseq, q + 2 nseq, ... loaded pair q: fixed-order sum, one writer per pair
+    if (threadIdx.x < nseq) {
+      const int q = threadIdx.x;
+      T la = 0, ha = 0, lb = 0, hb = 0;
+      for (int t = q; t < (int)blockDim.x; t += nseq) {
+        la += fscr[2 * t].x;
+        ha += fscr[2 * t].y;
+        lb += fscr[2 * t + 1].x;
+        hb += fscr[2 * t + 1].y;
+      }
+      const long long o = blockIdx.x / a.ntile_inner;
+      const long long fi = o * a.inner + c0 + 2 * q;
+      if (2 * q < ncols) {
+        a.fc.out[fi] = la;
+        a.fc.out[a.fc.plane + fi] = ha;
+      }
+      if (2 * q + 1 < ncols) {
+        a.fc.out[fi + 1] = lb;
+        a.fc.out[a.fc.plane + fi + 1] = hb;
+      }
+    }
+  }
 
   cx<T> A, B;
   A.x = A.y = T(1);
@@ -535,6 +620,33 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
     coef(ca, A.x, B.x);
     coef(cb, A.y, B.y);
     post<T, N, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
+    if constexpr (FACES == 1) {
+      // face sums of the scaled spectrum along this axis, per column
+      T la = 0, ha = 0, lb = 0, hb = 0;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const int m = 1 + ts + i * TPS;
+        if (m < N) {
+          const cx<T> v = seq[pad(m)];
+          const T wl = a.fc.w[m - 1], wh = a.fc.w[L + m - 1];
+          la += v.x * wl;
+          ha += v.x * wh;
+          lb += v.y * wl;
+          hb += v.y * wh;
+        }
+      }
+      seg_sum4<T, TPS>(la, ha, lb, hb, tot, ts);
+      if (ts == 0) {
+        if (ca < a.inner) {
+          a.fc.out[ca] = la;
+          a.fc.out[a.fc.plane + ca] = ha;
+        }
+        if (cb < a.inner) {
+          a.fc.out[cb] = lb;
+          a.fc.out[a.fc.plane + cb] = hb;
+        }
+      }
+    }
     pre_lds<T, N>(seq, ts, a.sn);
     fft<T, N>(seq, ts, a.tw);
   }
@@ -562,12 +674,18 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   }
 }
 
-template <typename T, int N, bool F> void set_attr() {
+template <typename T, int N, bool F, int FC> void set_attr() {
   static std::once_flag once;
   std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_fast<T, N, F>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_fast<T, N, F, FC>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
+}
+
+template <typename T, int N, bool F, int FC>
+void launch_one(const Args<T>& a, unsigned blocks, int threads, size_t lds, hipStream_t st) {
+  set_attr<T, N, F, FC>();
+  hipLaunchKernelGGL((k_dst_fast<T, N, F, FC>), dim3(blocks), dim3(threads), lds, st, a);
 }
 
 template <typename T, int N>
@@ -575,19 +693,23 @@ int launch(const Args<T>& a, bool fused, int nseq, hipStream_t st) {
   constexpr int TPS = N / Plan<N>::PPT;
   const int threads = nseq * TPS;
   if (threads > cap<T>() || threads % 64 != 0) return ST_UNSUPPORTED;
-  const int ntot = nseq * (TPS / 64 > 0 ? TPS / 64 : 1);
-  const size_t lds = (size_t)(nseq * seq_stride<N>() + ntot) * sizeof(cx<T>);
+  const int ntot = nseq * 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  const int nscr = a.fc.mode == 2 ? 2 * threads : 0;
+  const size_t lds = (size_t)(nseq * seq_stride<N>() + ntot + nscr) * sizeof(cx<T>);
   if (lds > 160 * 1024) return ST_UNSUPPORTED;
   const long long P = 2LL * nseq;
   const long long blocks = a.inner == 1 ? (a.outer + P - 1) / P : a.outer * a.ntile_inner;
   if (blocks <= 0) return ST_OK;
   if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+  const unsigned nb = (unsigned)blocks;
   if (fused) {
-    set_attr<T, N, true>();
-    hipLaunchKernelGGL((k_dst_fast<T, N, true>), dim3((unsigned)blocks), dim3(threads), lds, st, a);
+    if (a.fc.mode == 1) launch_one<T, N, true, 1>(a, nb, threads, lds, st);
+    else if (a.fc.mode == 0) launch_one<T, N, true, 0>(a, nb, threads, lds, st);
+    else return ST_INVALID;
   } else {
-    set_attr<T, N, false>();
-    hipLaunchKernelGGL((k_dst_fast<T, N, false>), dim3((unsigned)blocks), dim3(threads), lds, st, a);
+    if (a.fc.mode == 2) launch_one<T, N, false, 2>(a, nb, threads, lds, st);
+    else if (a.fc.mode == 0) launch_one<T, N, false, 0>(a, nb, threads, lds, st);
+    else return ST_INVALID;
   }
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
@@ -639,8 +761,11 @@ int dst_fast_tile(int N, int elem_bytes) {
 
 template <typename T>
 int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer,
-                  long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st) {
+                  long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st,
+                  const DstFaces<T>* faces) {
   if (fused && inner == 1) return ST_INVALID;
+  if (faces && faces->mode == 2 && (fused || inner == 1)) return ST_INVALID;
+  if (faces && faces->mode == 1 && !fused) return ST_INVALID;
   // per-lane offsets are 32-bit: one slab (rows: one tile) must stay below 2^31 elements
   if ((double)(N - 1) * (double)inner >= 2147483647.0 || (inner == 1 && 256.0 * pitch >= 2147483647.0))
     return ST_UNSUPPORTED;
@@ -657,6 +782,7 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   a.lg_nseq = __builtin_ctz(nseq);
   a.ntile_inner = inner == 1 ? 1 : (inner + 2LL * nseq - 1) / (2LL * nseq);
   if (fused) a.fs = *fused;
+  if (faces) a.fc = *faces;
   const bool f = fused != nullptr;
   switch (N) {
     case 32: return fast::launch<T, 32>(a, f, nseq, st);
@@ -676,8 +802,10 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
 }
 
 template int dst_fast_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long,
-                                  long long, long long, const DstScale<float>*, int, hipStream_t);
+                                  long long, long long, const DstScale<float>*, int, hipStream_t,
+                                  const DstFaces<float>*);
 template int dst_fast_pass<double>(int, const cx<double>*, const double*, const double*, double*,
-                                   long long, long long, long long, const DstScale<double>*, int, hipStream_t);
+                                   long long, long long, long long, const DstScale<double>*, int, hipStream_t,
+                                   const DstFaces<double>*);
 
 }  // namespace ahoc

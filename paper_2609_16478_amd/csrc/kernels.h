@@ -14,6 +14,13 @@ int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, 
 template <typename T>
 int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af, const T* srcq,
            double* R, hipStream_t st);
+// x-face sums of rows that are spectral in x (see stencil.hip)
+template <typename T>
+int face_rows(long long rows, int nx, int px, const T* X, const T* w, T* F, long long plane, hipStream_t st);
+// boundary residual from face sums formed in spectral space
+template <typename T>
+int gather_faces(const Geom& g, const T* Fx, const T* Fy, const T* Fz, const T* Q, const T* af,
+                 const T* srcq, double* R, hipStream_t st);
 template <typename T>
 int resid64(const Geom& g, const Weights& w, const double* U, const double* V, const double* Q,
             const double* ia, const double* af, const double* src_u, const double* src_v,

@@ -180,6 +180,67 @@ __global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __
   }
 }
 
+// Face sums along x from an array that is spectral in x (rows of the interior layout):
+//   F[r] = sum_k X[r, k] w_lo(k),  F[plane + r] = sum_k X[r, k] w_hi(k)
+// one wavefront per row, fixed-order reduction.
+template <typename T>
+__global__ void k_face_rows(long long rows, int nx, int px, const T* __restrict__ X, const T* __restrict__ w,
+                            T* __restrict__ F, long long plane) {
+  const int lane = threadIdx.x & 63;
+  const long long wv = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long r = wv; r < rows; r += nw) {
+    const T* x = X + r * px;
+    T lo = 0, hi = 0;
+    for (int c = lane; c < nx; c += 64) {
+      const T v = x[c];
+      lo += v * w[c];
+      hi += v * w[nx + c];
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      lo += __shfl_xor(lo, m, 64);
+      hi += __shfl_xor(hi, m, 64);
+    }
+    if (lane == 0) {
+      F[r] = lo;
+      F[plane + r] = hi;
+    }
+  }
+}
+
+// Boundary residual from the face sums S = 6 U1 - 3/2 U2 + 2/9 U3 (formed in spectral space):
+//   R = alpha_b h^-2 S - Q - src_q
+//   3-D: x faces S = Fx[s][(k-1) n_y' + (j-1)], y faces Fy[s][(k-1) px + (i-1)],
+//        z faces Fz[s][(j-1) px + (i-1)];  2-D: Fx[s][j-1], Fy[s][i-1]
+template <typename T, int DIM>
+__global__ void k_gather_faces(Geom g, const T* __restrict__ Fx, const T* __restrict__ Fy,
+                               const T* __restrict__ Fz, const T* __restrict__ Q, const T* __restrict__ af,
+                               const T* __restrict__ srcq, double* __restrict__ R) {
+  const long long px_plane = DIM == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1];
+  const long long py_plane = DIM == 3 ? (long long)g.px * g.ni[2] : g.px;
+  const long long pz_plane = (long long)g.px * g.ni[1];
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    const int sd = st > 0 ? 0 : 1;  // low face (step +1) -> 0
+    T S;
+    if (ax == 0) {
+      const long long r = DIM == 3 ? (long long)(k - 1) * g.ni[1] + (j - 1) : (j - 1);
+      S = Fx[sd * px_plane + r];
+    } else if (ax == 1) {
+      const long long r = DIM == 3 ? (long long)(k - 1) * g.px + (i - 1) : (i - 1);
+      S = Fy[sd * py_plane + r];
+    } else {
+      S = Fz[sd * pz_plane + (long long)(j - 1) * g.px + (i - 1)];
+    }
+    const T ih2 = (T)(1.0 / (g.h[ax] * g.h[ax]));
+    T r = af[q] * ih2 * S - Q[q];
+    if (srcq) r -= srcq[q];
+    R[q] = (double)r;
+  }
+}
+
 // FP64 residual of the coupled system at the interior nodes:
 //   r_v = src_v + L_h[V]            (V = interior V, Q on face interiors, 0 on edges)
 //   r_u = src_u + M(V/alpha) - L_h[U]   (U = interior U, 0 on the boundary)
@@ -464,6 +525,22 @@ int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af,
 }
 
 template <typename T>
+int face_rows(long long rows, int nx, int px, const T* X, const T* w, T* F, long long plane, hipStream_t st) {
+  long long b = (rows + 3) / 4;  // four rows (wavefronts) per block of 256
+  if (b > 1048576) b = 1048576;
+  hipLaunchKernelGGL((k_face_rows<T>), dim3((unsigned)(b < 1 ? 1 : b)), dim3(TPB), 0, st, rows, nx, px, X, w, F, plane);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+template <typename T>
+int gather_faces(const Geom& g, const T* Fx, const T* Fy, const T* Fz, const T* Q, const T* af,
+                 const T* srcq, double* R, hipStream_t st) {
+  LAUNCH_TDIM(k_gather_faces, T, dim3(nblocks(g.nq)), g, Fx, Fy, Fz, Q, af, srcq, R);
+  return ST_OK;
+}
+
+template <typename T>
 int resid64(const Geom& g, const Weights& w, const double* U, const double* V, const double* Q,
             const double* ia, const double* af, const double* src_u, const double* src_v,
             const double* src_q, T* ru, T* rv, T* rq, hipStream_t st) {
@@ -544,6 +621,9 @@ int fill(long long n, double v, double* x, hipStream_t st) {
 }
 
 #define INST_T(T)                                                                                  \
+  template int face_rows<T>(long long, int, int, const T*, const T*, T*, long long, hipStream_t);  \
+  template int gather_faces<T>(const Geom&, const T*, const T*, const T*, const T*, const T*,       \
+                               const T*, double*, hipStream_t);                                    \
   template int lift<T>(const Geom&, const Weights&, const T*, const T*, T*, hipStream_t);         \
   template int rhs_u<T>(const Geom&, const Weights&, const T*, const T*, const T*, const T*, T*,   \
                         hipStream_t);                                                              \
