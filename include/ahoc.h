@@ -152,6 +152,15 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
  * return AHOC_E_UNSUPPORTED).  For tuning and for testing both families. */
 ahoc_status ahoc_set_dst_variant(int variant);
 
+/* Override the default work-group tile (pencil pairs per work-group, a power of two;
+ * 0 restores the default) of one DST-I pass kind of the length-specialised kernels,
+ * process-wide: pass 0 = rows (contiguous pencils), 1 = strided pencils, 2 = fused
+ * forward/scale/inverse pass; precision selects the FP64 or the FP32 (AHOC_MIXED)
+ * kernels.  A tile whose work-group exceeds the kernel's size or LDS limits makes the
+ * launch return AHOC_E_UNSUPPORTED; the fused pass clamps it to its default.  The
+ * per-handle ahoc_options.tile_* fields take precedence.  For tuning. */
+ahoc_status ahoc_set_dst_tile(int pass, int precision, int pairs);
+
 /* Kernel classes for ahoc_kernel_times. */
 enum {
   AHOC_K_DST_ROWS = 0,     /* DST-I pass along x (contiguous pencils)                   */

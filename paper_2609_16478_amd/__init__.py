@@ -72,6 +72,8 @@ _lib.ahoc_kernel_times.argtypes = [_H, c_int, ctypes.POINTER(c_double), ctypes.P
 _lib.ahoc_kernel_times.restype = c_int
 _lib.ahoc_set_dst_variant.argtypes = [c_int]
 _lib.ahoc_set_dst_variant.restype = c_int
+_lib.ahoc_set_dst_tile.argtypes = [c_int, c_int, c_int]
+_lib.ahoc_set_dst_tile.restype = c_int
 _lib.ahoc_destroy.argtypes = [_H]
 _lib.ahoc_status_string.argtypes = [c_int]
 _lib.ahoc_status_string.restype = ctypes.c_char_p
@@ -80,7 +82,7 @@ _lib.ahoc_last_error.restype = ctypes.c_char_p
 KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "resid",
                 "matvec"]
 
-EXPORTED = ["ahoc_set_dst_variant", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_schur_rhs",
+EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_schur_rhs",
             "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
             "ahoc_status_string", "ahoc_last_error"]
 
@@ -277,6 +279,12 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
 def set_dst_variant(variant: int):
     """0 = automatic, 1 = generic DST kernel everywhere, 2 = length-specialised kernels only."""
     _check(_lib.ahoc_set_dst_variant(int(variant)), "ahoc_set_dst_variant")
+
+
+def set_dst_tile(pass_kind: int, precision: int, pairs: int):
+    """Default work-group tile (pencil pairs) of one DST pass kind: 0 rows, 1 strided, 2 fused;
+    pairs = 0 restores the built-in choice."""
+    _check(_lib.ahoc_set_dst_tile(int(pass_kind), int(precision), int(pairs)), "ahoc_set_dst_tile")
 
 
 def dst1(x, axis, precision=FP64):

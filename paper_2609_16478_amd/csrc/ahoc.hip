@@ -922,6 +922,12 @@ ahoc_status ahoc_set_dst_variant(int variant) {
   return AHOC_OK;
 }
 
+ahoc_status ahoc_set_dst_tile(int pass, int precision, int pairs) {
+  if (precision != AHOC_FP64 && precision != AHOC_MIXED) return AHOC_E_INVALID;
+  const int rc = ahoc::dst_set_tile(pass, precision == AHOC_FP64 ? 8 : 4, pairs);
+  return rc == ahoc::ST_OK ? AHOC_OK : AHOC_E_INVALID;
+}
+
 ahoc_status ahoc_profile(ahoc_handle* h, int enable) {
   if (!h) return AHOC_E_INVALID;
   (void)hipDeviceSynchronize();

@@ -109,7 +109,9 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
 
 // Length-specialised kernels (dst_fast.hip) for N in {32, 64, 96, ..., 4096}.
 bool dst_fast_supported(int N);
-int dst_fast_tile(int N, int elem_bytes);
+enum { DST_PASS_ROWS = 0, DST_PASS_STRIDED = 1, DST_PASS_FUSED = 2 };
+int dst_fast_tile(int N, int elem_bytes, int kind);
+int dst_set_tile(int kind, int elem_bytes, int pairs);
 template <typename T>
 int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer,
                   long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st,

@@ -203,6 +203,13 @@ template <> struct Plan<768> { static constexpr int S = 3, R0 = 8, R1 = 8, R2 = 
 template <> struct Plan<1024> { static constexpr int S = 2, R0 = 32, R1 = 32, R2 = 1, PPT = 32; };
 template <> struct Plan<2048> { static constexpr int S = 3, R0 = 16, R1 = 8, R2 = 16, PPT = 16; };
 template <> struct Plan<4096> { static constexpr int S = 3, R0 = 16, R1 = 16, R2 = 16, PPT = 16; };
+// Row-pass plans: contiguous pencils need no wide tiles for coalescing, so the row pass
+// trades a third stage for 16 points per thread: one wavefront per pencil pair and small
+// work-groups, many of which share a compute unit and overlap their load and FFT phases.
+template <int N> struct RowPlan : Plan<N> {};
+template <> struct RowPlan<512> { static constexpr int S = 3, R0 = 16, R1 = 8, R2 = 4, PPT = 16; };
+template <> struct RowPlan<1024> { static constexpr int S = 3, R0 = 16, R1 = 16, R2 = 4, PPT = 16; };
+template <int N, bool ROWP> using PlanOf = std::conditional_t<ROWP, RowPlan<N>, Plan<N>>;
 
 __device__ __forceinline__ constexpr int pad(int m) { return m + (m >> 5); }
 template <int N> __host__ __device__ constexpr int seq_stride() {
@@ -246,8 +253,7 @@ __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restric
   __syncthreads();
 }
 
-template <typename T, int N> __device__ __forceinline__ void fft(cx<T>* seq, int ts, const cx<T>* __restrict__ tw) {
-  using P = Plan<N>;
+template <typename T, int N, class P> __device__ __forceinline__ void fft(cx<T>* seq, int ts, const cx<T>* __restrict__ tw) {
   stage<T, N, P::R0, 1, P::PPT>(seq, ts, tw);
   stage<T, N, P::R1, P::R0, P::PPT>(seq, ts, tw);
   if constexpr (P::S == 3) stage<T, N, P::R2, P::R0 * P::R1, P::PPT>(seq, ts, tw);
@@ -255,10 +261,10 @@ template <typename T, int N> __device__ __forceinline__ void fft(cx<T>* seq, int
 
 // Split the pair and form the DST-I outputs in place (positions 1..N-1, 0 -> 0).
 // With SCALE, output m of pencil a (b) is multiplied by scale / (A.x + B.x s[m-1]).
-template <typename T, int N, bool SCALE>
+template <typename T, int N, class P, bool SCALE>
 __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx<T> B,
                                      const T* __restrict__ s_this, T scale) {
-  constexpr int PPT = Plan<N>::PPT;
+  constexpr int PPT = P::PPT;
   constexpr int TPS = N / PPT;
   constexpr int H = PPT / 2;
   cx<T> ev[H], cc[H];
@@ -356,9 +362,9 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
 }
 
 // Pre-weighting of a sequence already in LDS (second transform of the fused pass).
-template <typename T, int N>
+template <typename T, int N, class P>
 __device__ __forceinline__ void pre_lds(cx<T>* seq, int ts, const T* __restrict__ sn) {
-  constexpr int PPT = Plan<N>::PPT;
+  constexpr int PPT = P::PPT;
   constexpr int TPS = N / PPT;
   cx<T> z[PPT / 2], zr[PPT / 2];
 #pragma unroll
@@ -433,12 +439,17 @@ __device__ __forceinline__ void seg_sum4(T& a, T& b, T& c, T& d, cx<T>* tot, int
   }
 }
 
-template <typename T> constexpr int cap() { return sizeof(T) == 8 ? 256 : 512; }
+// Work-group size cap: 16 points per thread leave room for 1024-thread (FP32) or 512-thread
+// (FP64) groups in the single-transform passes; the fused pass holds more live state.
+template <typename T, int N, bool FUSED, bool ROWP> constexpr int cap() {
+  return PlanOf<N, ROWP>::PPT <= 16 && !FUSED ? (sizeof(T) == 8 ? 512 : 1024) : (sizeof(T) == 8 ? 256 : 512);
+}
 
-template <typename T, int N, bool FUSED, int FACES>
-__global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
+template <typename T, int N, bool FUSED, int FACES, bool ROWP>
+__global__ void __launch_bounds__((cap<T, N, FUSED, ROWP>())) k_dst_fast(Args<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int PPT = Plan<N>::PPT;
+  using PL = PlanOf<N, ROWP>;
+  constexpr int PPT = PL::PPT;
   constexpr int TPS = N / PPT;
   constexpr int L = N - 1;
   constexpr int LDQ = seq_stride<N>();
@@ -601,7 +612,7 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   cx<T> A, B;
   A.x = A.y = T(1);
   B.x = B.y = T(0);
-  fft<T, N>(seq, ts, a.tw);
+  fft<T, N, PL>(seq, ts, a.tw);
   if constexpr (FUSED) {
     const long long ca = c0 + 2 * s, cb = ca + 1;
     auto coef = [&](long long col, T& Ao, T& Bo) {
@@ -619,7 +630,7 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
     };
     coef(ca, A.x, B.x);
     coef(cb, A.y, B.y);
-    post<T, N, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
+    post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
     if constexpr (FACES == 1) {
       // face sums of the scaled spectrum along this axis, per column
       T la = 0, ha = 0, lb = 0, hb = 0;
@@ -647,10 +658,10 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
         }
       }
     }
-    pre_lds<T, N>(seq, ts, a.sn);
-    fft<T, N>(seq, ts, a.tw);
+    pre_lds<T, N, PL>(seq, ts, a.sn);
+    fft<T, N, PL>(seq, ts, a.tw);
   }
-  post<T, N, false>(seq, tot, ts, A, B, nullptr, T(0));
+  post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
 
   // ---- store: item = (pair q, position m in 1..N-1)
   {
@@ -674,45 +685,48 @@ __global__ void __launch_bounds__(cap<T>()) k_dst_fast(Args<T> a) {
   }
 }
 
-template <typename T, int N, bool F, int FC> void set_attr() {
+template <typename T, int N, bool F, int FC, bool RP> void set_attr() {
   static std::once_flag once;
   std::call_once(once, [] {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_fast<T, N, F, FC>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_dst_fast<T, N, F, FC, RP>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   });
 }
 
-template <typename T, int N, bool F, int FC>
-void launch_one(const Args<T>& a, unsigned blocks, int threads, size_t lds, hipStream_t st) {
-  set_attr<T, N, F, FC>();
-  hipLaunchKernelGGL((k_dst_fast<T, N, F, FC>), dim3(blocks), dim3(threads), lds, st, a);
-}
-
-template <typename T, int N>
-int launch(const Args<T>& a, bool fused, int nseq, hipStream_t st) {
-  constexpr int TPS = N / Plan<N>::PPT;
+template <typename T, int N, bool F, int FC, bool RP>
+int launch_one(const Args<T>& a, int nseq, hipStream_t st) {
+  constexpr int TPS = N / PlanOf<N, RP>::PPT;
   const int threads = nseq * TPS;
-  if (threads > cap<T>() || threads % 64 != 0) return ST_UNSUPPORTED;
+  if (threads > cap<T, N, F, RP>() || threads % 64 != 0) return ST_UNSUPPORTED;
   const int ntot = nseq * 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
-  const int nscr = a.fc.mode == 2 ? 2 * threads : 0;
+  const int nscr = FC == 2 ? 2 * threads : 0;
   const size_t lds = (size_t)(nseq * seq_stride<N>() + ntot + nscr) * sizeof(cx<T>);
   if (lds > 160 * 1024) return ST_UNSUPPORTED;
   const long long P = 2LL * nseq;
   const long long blocks = a.inner == 1 ? (a.outer + P - 1) / P : a.outer * a.ntile_inner;
   if (blocks <= 0) return ST_OK;
   if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
-  const unsigned nb = (unsigned)blocks;
-  if (fused) {
-    if (a.fc.mode == 1) launch_one<T, N, true, 1>(a, nb, threads, lds, st);
-    else if (a.fc.mode == 0) launch_one<T, N, true, 0>(a, nb, threads, lds, st);
-    else return ST_INVALID;
-  } else {
-    if (a.fc.mode == 2) launch_one<T, N, false, 2>(a, nb, threads, lds, st);
-    else if (a.fc.mode == 0) launch_one<T, N, false, 0>(a, nb, threads, lds, st);
-    else return ST_INVALID;
-  }
+  set_attr<T, N, F, FC, RP>();
+  hipLaunchKernelGGL((k_dst_fast<T, N, F, FC, RP>), dim3((unsigned)blocks), dim3(threads), lds, st, a);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
+}
+
+template <int N> constexpr bool has_row_plan() { return N == 512 || N == 1024; }
+
+template <typename T, int N>
+int launch(const Args<T>& a, int kind, int nseq, hipStream_t st) {
+  if (kind == DST_PASS_FUSED) {
+    if (a.fc.mode == 1) return launch_one<T, N, true, 1, false>(a, nseq, st);
+    if (a.fc.mode == 0) return launch_one<T, N, true, 0, false>(a, nseq, st);
+    return ST_INVALID;
+  }
+  if (a.fc.mode == 2) return launch_one<T, N, false, 2, false>(a, nseq, st);
+  if (a.fc.mode != 0) return ST_INVALID;
+  if constexpr (has_row_plan<N>()) {
+    if (kind == DST_PASS_ROWS) return launch_one<T, N, false, 0, true>(a, nseq, st);
+  }
+  return launch_one<T, N, false, 0, false>(a, nseq, st);
 }
 
 }  // namespace fast
@@ -727,7 +741,9 @@ bool dst_fast_supported(int N) {
   }
 }
 
-int dst_fast_tps(int N) {
+// Threads per pencil pair of the plan a pass of this kind uses.
+static int fast_tps(int N, int kind) {
+  const bool rp = kind == DST_PASS_ROWS;
   switch (N) {
     case 32: return 32 / fast::Plan<32>::PPT;
     case 64: return 64 / fast::Plan<64>::PPT;
@@ -736,24 +752,42 @@ int dst_fast_tps(int N) {
     case 192: return 192 / fast::Plan<192>::PPT;
     case 256: return 256 / fast::Plan<256>::PPT;
     case 384: return 384 / fast::Plan<384>::PPT;
-    case 512: return 512 / fast::Plan<512>::PPT;
+    case 512: return 512 / (rp ? fast::RowPlan<512>::PPT : fast::Plan<512>::PPT);
     case 768: return 768 / fast::Plan<768>::PPT;
-    case 1024: return 1024 / fast::Plan<1024>::PPT;
+    case 1024: return 1024 / (rp ? fast::RowPlan<1024>::PPT : fast::Plan<1024>::PPT);
     case 2048: return 2048 / fast::Plan<2048>::PPT;
     case 4096: return 4096 / fast::Plan<4096>::PPT;
     default: return 0;
   }
 }
 
-// Pencil pairs per work-group: 16 (FP32) / 8 (FP64) for 128 B row segments in the
-// strided passes, at least one wavefront, within the launch cap and 160 KB of LDS.
-int dst_fast_tile(int N, int elem_bytes) {
-  const int tps = dst_fast_tps(N);
+static int g_tile_override[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+
+int dst_set_tile(int kind, int elem_bytes, int pairs) {
+  if (kind < 0 || kind > 2 || (elem_bytes != 4 && elem_bytes != 8) || pairs < 0 || (pairs & (pairs - 1)))
+    return ST_INVALID;
+  g_tile_override[kind][elem_bytes == 8] = pairs;
+  return ST_OK;
+}
+
+// Default pencil pairs per work-group.  Strided and fused passes: 16 (FP32) / 8 (FP64)
+// pairs, i.e. 128 B row segments, within the launch cap and 150 KB of LDS.  Row passes
+// read contiguous pencils, so they take the smallest work-group of at least `row_threads`
+// threads: several independent groups per compute unit overlap memory and arithmetic.
+int dst_fast_tile(int N, int elem_bytes, int kind) {
+  const int tps = fast_tps(N, kind);
   if (!tps) return 0;
-  const int cap = elem_bytes == 8 ? 256 : 512;
-  int nseq = elem_bytes == 8 ? 8 : 16;
-  while (nseq * tps < 64) nseq *= 2;
+  const int ppt = N / tps;
+  const bool fused = kind == DST_PASS_FUSED;
+  const int cap = ppt <= 16 && !fused ? (elem_bytes == 8 ? 512 : 1024) : (elem_bytes == 8 ? 256 : 512);
   const int stride = (N + (N >> 5) + 1) | 1;
+  int nseq = elem_bytes == 8 ? 8 : 16;
+  if (kind == DST_PASS_ROWS) {
+    const int row_threads = 64;
+    nseq = 1;
+    while (nseq * tps < row_threads) nseq *= 2;
+  }
+  while (nseq * tps < 64) nseq *= 2;
   while (nseq > 1 && (nseq * tps > cap || (size_t)nseq * stride * 2 * elem_bytes > 150 * 1024)) nseq /= 2;
   if (nseq * tps > cap || (nseq * tps) % 64) return 0;
   return nseq;
@@ -769,6 +803,7 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   // per-lane offsets are 32-bit: one slab (rows: one tile) must stay below 2^31 elements
   if ((double)(N - 1) * (double)inner >= 2147483647.0 || (inner == 1 && 256.0 * pitch >= 2147483647.0))
     return ST_UNSUPPORTED;
+  const int kind = fused ? DST_PASS_FUSED : (inner == 1 ? DST_PASS_ROWS : DST_PASS_STRIDED);
   fast::Args<T> a;
   a.in = in;
   a.out = out;
@@ -777,26 +812,28 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   a.outer = outer;
   a.inner = inner;
   a.pitch = pitch;
-  if (nseq <= 0) nseq = dst_fast_tile(N, (int)sizeof(T));
+  const int dflt = dst_fast_tile(N, (int)sizeof(T), kind);
+  const int ovr = g_tile_override[kind][sizeof(T) == 8];
+  if (nseq <= 0) nseq = ovr > 0 ? ovr : dflt;
+  if (fused && nseq > dflt) nseq = dflt;  // the fused pass has a lower size cap
   if (nseq <= 0 || (nseq & (nseq - 1))) return ST_UNSUPPORTED;
   a.lg_nseq = __builtin_ctz(nseq);
   a.ntile_inner = inner == 1 ? 1 : (inner + 2LL * nseq - 1) / (2LL * nseq);
   if (fused) a.fs = *fused;
   if (faces) a.fc = *faces;
-  const bool f = fused != nullptr;
   switch (N) {
-    case 32: return fast::launch<T, 32>(a, f, nseq, st);
-    case 64: return fast::launch<T, 64>(a, f, nseq, st);
-    case 96: return fast::launch<T, 96>(a, f, nseq, st);
-    case 128: return fast::launch<T, 128>(a, f, nseq, st);
-    case 192: return fast::launch<T, 192>(a, f, nseq, st);
-    case 256: return fast::launch<T, 256>(a, f, nseq, st);
-    case 384: return fast::launch<T, 384>(a, f, nseq, st);
-    case 512: return fast::launch<T, 512>(a, f, nseq, st);
-    case 768: return fast::launch<T, 768>(a, f, nseq, st);
-    case 1024: return fast::launch<T, 1024>(a, f, nseq, st);
-    case 2048: return fast::launch<T, 2048>(a, f, nseq, st);
-    case 4096: return fast::launch<T, 4096>(a, f, nseq, st);
+    case 32: return fast::launch<T, 32>(a, kind, nseq, st);
+    case 64: return fast::launch<T, 64>(a, kind, nseq, st);
+    case 96: return fast::launch<T, 96>(a, kind, nseq, st);
+    case 128: return fast::launch<T, 128>(a, kind, nseq, st);
+    case 192: return fast::launch<T, 192>(a, kind, nseq, st);
+    case 256: return fast::launch<T, 256>(a, kind, nseq, st);
+    case 384: return fast::launch<T, 384>(a, kind, nseq, st);
+    case 512: return fast::launch<T, 512>(a, kind, nseq, st);
+    case 768: return fast::launch<T, 768>(a, kind, nseq, st);
+    case 1024: return fast::launch<T, 1024>(a, kind, nseq, st);
+    case 2048: return fast::launch<T, 2048>(a, kind, nseq, st);
+    case 4096: return fast::launch<T, 4096>(a, kind, nseq, st);
     default: return ST_UNSUPPORTED;
   }
 }
