@@ -165,14 +165,21 @@ ahoc_status ahoc_set_dst_tile(int pass, int precision, int pairs);
 enum {
   AHOC_K_DST_ROWS = 0,     /* DST-I pass along x (contiguous pencils)                   */
   AHOC_K_DST_STRIDED = 1,  /* DST-I pass along y in 3-D (strided pencils)               */
-  AHOC_K_DST_FUSED = 2,    /* fused forward DST, eigen scaling, inverse DST (slowest axis) */
-  AHOC_K_LIFT = 3,         /* v-equation right-hand side from Q                          */
+  AHOC_K_DST_FUSED = 2,    /* fused forward DST and eigen scaling along the slowest axis, then
+                              the inverse DST (Poisson solves) or the face sums (U-solve)  */
+  AHOC_K_LIFT = 3,         /* v-equation right-hand side from Q (face layers and their
+                              2-D spectra in the spectral form)                           */
   AHOC_K_RHS_U = 4,        /* u-equation right-hand side M(V/alpha)                      */
-  AHOC_K_GATHER = 5,       /* boundary residual gather                                   */
+  AHOC_K_GATHER = 5,       /* boundary residual gather (with the face-sum reductions and
+                              2-D inverse transforms in the spectral form)                */
   AHOC_K_KRYLOV = 6,       /* one Arnoldi step (CGS2 dots/axpys, norm, Givens, scale)     */
   AHOC_K_RESID = 7,        /* FP64 coupled residual (mixed precision)                    */
   AHOC_K_MATVEC = 8,       /* one whole Schur matrix-vector product                      */
-  AHOC_NKIND = 9
+  AHOC_K_DST_GEN = 9,      /* V-solve: spectrum of the face-layer lift generated, scaled and
+                              inverted along the slowest axis (writes the volume only)     */
+  AHOC_K_FACE_REDUCE = 10, /* U-solve: face sums along the two fastest axes from the stored
+                              scaled spectrum (reads the volume only)                      */
+  AHOC_NKIND = 11
 };
 
 /* Enable (1) or disable (0) per-kernel-class timing of the handle's solves with

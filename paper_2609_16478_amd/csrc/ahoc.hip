@@ -44,9 +44,14 @@ template <typename T> struct Prec {
   T* qT = nullptr;    // N_q, Q in this precision
   T* zq = nullptr;    // N_q zeros
   T* wf[3] = {nullptr, nullptr, nullptr};  // per axis: one-sided face weights w_lo(k), w_hi(k)
-  T* Fx = nullptr;    // face sums: x faces [2][n_y' n_z'], y faces [2][n_z' px], z faces [2][n_y' px]
+  T* wl[3] = {nullptr, nullptr, nullptr};  // per axis: layer sines sin(pi k/N), (-1)^(k+1) sin(pi k/N)
+  // face arrays (lift layers / face sums): 3-D x faces [2][n_z'][n_y'], y faces [2][n_z'][px],
+  // z faces [2][n_y'][px]; 2-D x faces [2][n_y'], y faces [2][px]
+  T* Fx = nullptr;
   T* Fy = nullptr;
   T* Fz = nullptr;
+  // spectral entry/exit of the matvec (when every axis has a specialised kernel)
+  bool spectral = false;
   DstScale<T> scV, scU, scP;
   bool ready = false;
 };
@@ -227,6 +232,14 @@ void make_weights(const Geom& g, Weights& w) {
   w.os_gn = 11.0 / 3.0;
 }
 
+// Whether every axis has a length-specialised DST kernel (needed for the spectral lift and face sums).
+bool faces_available(const Geom& g) {
+  if (dst_get_variant() == 1) return false;
+  for (int a = 0; a < g.dim; ++a)
+    if (!dst_fast_supported(g.n[a])) return false;
+  return true;
+}
+
 template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hipStream_t st) {
   const Geom& g = h->g;
   for (int a = 0; a < g.dim; ++a) {
@@ -252,15 +265,28 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     }
     TRY(alloc_t(h, &P.wf[a], 2 * g.ni[a]));
     AHOC_HIP_TRY(hipMemcpy(P.wf[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice));
+    // sine of mode k at the interior layer next to the low face (node 1) and the high face
+    // (node N-1): the normal factor of a face layer's spectrum
+    for (int k = 1; k <= g.ni[a]; ++k) {
+      const long double sv = sinl(pi * k / (long double)g.n[a]);
+      wv[k - 1] = (T)sv;
+      wv[g.ni[a] + k - 1] = (T)((k % 2 == 1) ? sv : -sv);
+    }
+    TRY(alloc_t(h, &P.wl[a], 2 * g.ni[a]));
+    AHOC_HIP_TRY(hipMemcpy(P.wl[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice));
   }
   if (g.dim == 3) {
     TRY(alloc_t(h, &P.Fx, 2LL * g.ni[1] * g.ni[2]));
     TRY(alloc_t(h, &P.Fy, 2LL * g.px * g.ni[2]));
     TRY(alloc_t(h, &P.Fz, 2LL * g.px * g.ni[1]));
+    AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.px * g.ni[2], st));
+    AHOC_HIP_TRY(hipMemsetAsync(P.Fz, 0, sizeof(T) * 2 * g.px * g.ni[1], st));
   } else {
     TRY(alloc_t(h, &P.Fx, 2LL * g.ni[1]));
     TRY(alloc_t(h, &P.Fy, 2LL * g.px));
+    AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.px, st));
   }
+  P.spectral = faces_available(g);
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
   TRY(alloc_t(h, &P.qT, g.nq));
@@ -343,69 +369,120 @@ template <typename T> int usolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T
   return poisson<T>(h, P, P.bufB, P.scU, st);
 }
 
-// Whether every axis has a length-specialised DST kernel (needed for the face sums).
-bool faces_available(const Geom& g) {
-  if (dst_get_variant() == 1) return false;
-  for (int a = 0; a < g.dim; ++a)
-    if (!dst_fast_supported(g.n[a])) return false;
-  return true;
+// 2-D DST-I of every face array, in place (the unnormalised transform is its own inverse
+// up to the factor folded into the eigen scaling).
+template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) {
+  const Geom& g = h->g;
+  if (g.dim == 3) {
+    TRY(dst_pass<T>(P.tb[0], P.Fz, P.Fz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Fz, P.Fz, 2, g.px, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], P.Fx, P.Fx, 2, g.ni[1], g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], P.Fy, P.Fy, 2, g.px, g.px, nullptr, 0, st));
+  } else {
+    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2, 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2, 1, g.ni[1], nullptr, 0, st));
+  }
+  return ST_OK;
 }
 
-// U-solve for the boundary residual only.  The one-sided combination
-// 6 U_1 - 3/2 U_2 + 2/9 U_3 on each face is formed from the spectrum along that face's
-// normal (a weighted sum over modes) instead of from physical U next to the face: the
-// rounding error of a transform is then not amplified by the h^-2 of the gather, and the
-// last inverse x pass is not needed.  Face sums land in P.Fx, P.Fy, P.Fz (physical).
-template <typename T> int usolve_faces(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+// Homogeneous V-solve V = -L^{-1} L_h^bnd[Q] into P.bufA through the spectral lift: face
+// layers of the lift, their 2-D spectra, then the slowest-axis pass generates the 3-D
+// spectrum, scales it and inverts along its axis; the other axes are inverted as usual.
+template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st) {
+  const Geom& g = h->g;
+  hipEvent_t e = tbegin(h, st);
+  TRY(face_lift<T>(g, h->w, Q, P.Fx, P.Fy, P.Fz, st));
+  TRY(face_dst2<T>(h, P, st));
+  tend(h, AHOC_K_LIFT, e, (double)g.nq * 2.0 * sizeof(T), st);
+  const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);
+  T* buf = P.bufA;
+  DstGen<T> gen;
+  gen.wa = P.wl[0];
+  gen.nwa = g.ni[0];
+  gen.la = P.Fx;
+  hipEvent_t eg = tbegin(h, st);
+  if (g.dim == 3) {
+    gen.lp = P.Fz;
+    gen.pplane = (long long)g.px * g.ni[1];
+    gen.wp = P.wl[2];
+    gen.aplane = (long long)g.ni[1] * g.ni[2];
+    gen.apitch = g.ni[1];
+    gen.lb = P.Fy;
+    gen.bplane = (long long)g.px * g.ni[2];
+    gen.bpitch = g.px;
+    gen.wb = P.wl[1];
+    gen.nwb = g.ni[1];
+    TRY(dst_gen_pass<T>(P.tb[2], buf, (long long)g.px * g.ni[1], P.scV, gen, st));
+  } else {
+    gen.lp = P.Fy;
+    gen.pplane = g.px;
+    gen.wp = P.wl[1];
+    gen.aplane = g.ni[1];
+    gen.apitch = 1;
+    TRY(dst_gen_pass<T>(P.tb[1], buf, g.px, P.scV, gen, st));
+  }
+  tend(h, AHOC_K_DST_GEN, eg, (double)g.nint * sizeof(T), st);
+  auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner, int tile) -> int {
+    hipEvent_t ev = tbegin(h, st);
+    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, nullptr, tile, st);
+    tend(h, kind, ev, pass_bytes, st);
+    return rc;
+  };
+  if (g.dim == 3) {
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, P.tile[1]));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, P.tile[0]));
+  } else {
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, P.tile[0]));
+  }
+  return ST_OK;
+}
+
+// U-solve for the boundary residual only: U = L^{-1}(M(V/alpha) + src) is never formed.
+// The forward transforms run as usual; the slowest-axis pass scales the spectrum, forms
+// the face sums along its own axis and stores the scaled spectrum; one streaming
+// reduction forms the sums along the other two axes, and 2-D inverse transforms of the
+// face arrays give the combination 6 U_1 - 3/2 U_2 + 2/9 U_3 next to each face.
+template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
   TRY(rhs_u<T>(g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
   tend(h, AHOC_K_RHS_U, e, (double)sizeof(T) * (2.0 * g.nint + g.nnodal) + (src ? g.nint * sizeof(T) : 0), st);
   T* buf = P.bufB;
   const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);
-  auto run = [&](int kind, const DstTables<T>& tb, T* arr, long long outer, long long inner,
-                 const DstScale<T>* f, int tile, const DstFaces<T>* fc, double bytes) -> int {
+  auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner, const DstScale<T>* f,
+                 int tile, const DstFaces<T>* fc) -> int {
     hipEvent_t ev = tbegin(h, st);
-    const int rc = dst_pass<T>(tb, arr, arr, outer, inner, g.px, f, tile, st, fc);
-    if (bytes > 0) tend(h, kind, ev, bytes, st);
+    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, f, tile, st, fc);
+    tend(h, kind, ev, pass_bytes, st);
     return rc;
   };
+  DstFaces<T> fp;
+  fp.mode = 1;
   if (g.dim == 3) {
-    const long long rows = (long long)g.ni[1] * g.ni[2];
-    DstFaces<T> fz;
-    fz.out = P.Fz;
-    fz.w = P.wf[2];
-    fz.plane = (long long)g.px * g.ni[1];
-    fz.mode = 1;
-    DstFaces<T> fy;
-    fy.out = P.Fy;
-    fy.w = P.wf[1];
-    fy.plane = (long long)g.px * g.ni[2];
-    fy.mode = 2;
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], buf, rows, 1, nullptr, P.tile[0], nullptr, pass_bytes));
-    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], buf, g.ni[2], g.px, nullptr, P.tile[1], nullptr, pass_bytes));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[2], buf, 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fz, pass_bytes));
-    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], buf, g.ni[2], g.px, nullptr, P.tile[1], &fy, pass_bytes));
-    hipEvent_t ef = tbegin(h, st);
-    TRY(face_rows<T>(rows, g.ni[0], g.px, buf, P.wf[0], P.Fx, rows, st));
-    // remaining inverse transforms of the small face arrays (spectral in x, and in y for Fz)
-    TRY(dst_pass<T>(P.tb[0], P.Fz, P.Fz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], P.Fz, P.Fz, 2, g.px, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
-    tend(h, AHOC_K_GATHER, ef, (double)g.nint * sizeof(T), st);
+    fp.out = P.Fz;
+    fp.w = P.wf[2];
+    fp.plane = (long long)g.px * g.ni[1];
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, nullptr, P.tile[0], nullptr));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, nullptr, P.tile[1], nullptr));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fp));
+    hipEvent_t er = tbegin(h, st);
+    TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy, st));
+    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
   } else {
-    DstFaces<T> fy;
-    fy.out = P.Fy;
-    fy.w = P.wf[1];
-    fy.plane = g.px;
-    fy.mode = 1;
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], buf, g.ni[1], 1, nullptr, P.tile[0], nullptr, pass_bytes));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[1], buf, 1, g.px, &P.scU, P.tile[1], &fy, pass_bytes));
-    hipEvent_t ef = tbegin(h, st);
-    TRY(face_rows<T>(g.ni[1], g.ni[0], g.px, buf, P.wf[0], P.Fx, g.ni[1], st));
-    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2, 1, g.px, nullptr, 0, st));
-    tend(h, AHOC_K_GATHER, ef, (double)g.nint * sizeof(T), st);
+    fp.out = P.Fy;
+    fp.w = P.wf[1];
+    fp.plane = g.px;
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0], nullptr));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], 1, g.px, &P.scU, P.tile[1], &fp));
+    hipEvent_t er = tbegin(h, st);
+    TRY(face_reduce<T>(buf, 1, g.ni[1], g.ni[0], g.px, P.wf[0], nullptr, P.Fx, nullptr, st));
+    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
   }
+  hipEvent_t ef = tbegin(h, st);
+  TRY(face_dst2<T>(h, P, st));
+  tend(h, AHOC_K_GATHER, ef, (double)g.nq * 2.0 * sizeof(T), st);
   return ST_OK;
 }
 
@@ -426,20 +503,29 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
   hipEvent_t e = tbegin(h, st);
   const T* qT = q_in<T>(h, P, q, st, &rc);
   TRY(rc);
-  TRY(vsolve<T>(h, P, qT, nullptr, st));
-  if (faces_available(h->g)) {
-    TRY(usolve_faces<T>(h, P, qT, nullptr, st));
+  if (P.spectral) {
+    TRY(vsolve_spec<T>(h, P, qT, st));
+    TRY(usolve_spec<T>(h, P, qT, nullptr, st));
+    hipEvent_t eg = tbegin(h, st);
     TRY(gather_faces<T>(h->g, P.Fx, P.Fy, P.Fz, qT, P.af, nullptr, y, st));
+    tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (3 * sizeof(T) + sizeof(double)), st);
   } else {
+    TRY(vsolve<T>(h, P, qT, nullptr, st));
     TRY(usolve<T>(h, P, qT, nullptr, st));
     hipEvent_t eg = tbegin(h, st);
     TRY(gather<T>(h->g, h->w, P.bufB, qT, P.af, nullptr, y, st));
     tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (3 * sizeof(T) + 2 * sizeof(T) + sizeof(double)), st);
   }
-  // algorithmic bytes of one matvec: lift write, pass read+writes, rhs_u, gather (the face
-  // path replaces the last inverse pass by a read-only row reduction)
+  // algorithmic bytes of one matvec.  Spectral form: generated pass (write), 2 (3-D) or 1
+  // (2-D) inverse passes, rhs_u (read V, 1/alpha, write), 2 or 1 forward passes, the
+  // forward/scale pass and the face reduction (read).  Otherwise: lift, 10 or 6 passes,
+  // rhs_u, gather.
   const double s = sizeof(T);
-  tend(h, AHOC_K_MATVEC, e, s * (21.0 * h->g.nint + 2.0 * h->g.nint + h->g.nnodal), st);
+  const Geom& g = h->g;
+  const double np = g.dim == 3 ? 2.0 : 1.0;
+  const double vol = P.spectral ? (1.0 + 2.0 * np + 2.0 + 2.0 * np + 2.0 + 1.0) * g.nint + g.nnodal
+                                : (1.0 + 2.0 * (2.0 * np + 1.0) * 2.0 + 2.0) * g.nint + g.nnodal;
+  tend(h, AHOC_K_MATVEC, e, s * vol, st);
   return ST_OK;
 }
 
@@ -447,8 +533,8 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
 template <typename T>
 int schur_rhs(ahoc_handle* h, Prec<T>& P, const T* sv, const T* su, const T* sq, double* b, hipStream_t st) {
   TRY(vsolve<T>(h, P, P.zq, sv, st));
-  if (faces_available(h->g)) {
-    TRY(usolve_faces<T>(h, P, P.zq, su, st));
+  if (P.spectral) {
+    TRY(usolve_spec<T>(h, P, P.zq, su, st));
     TRY(gather_faces<T>(h->g, P.Fx, P.Fy, P.Fz, P.zq, P.af, sq, h->R, st));
   } else {
     TRY(usolve<T>(h, P, P.zq, su, st));

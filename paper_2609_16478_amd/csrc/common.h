@@ -87,17 +87,55 @@ template <typename T> struct DstScale {
   T scale = 0;                // sign * prod_a 2/N_a
 };
 
-// Optional face sums of a pass (one-sided normal combination along the pass axis):
-//   mode 1 (fused pass): out[col] = sum_k W(k) w_lo(k), out[plane + col] = sum_k W(k) w_hi(k)
-//          over the scaled spectrum W of each column, before the inverse transform;
-//   mode 2 (plain strided pass): the same sums over the pass *input*, written at
-//          out[o * inner + col] (+ plane for the high face), o = slab index.
+// Optional face sums of a fused pass (one-sided normal combination along the pass axis):
+//   mode 1: out[col] = sum_k W(k) w_lo(k), out[plane + col] = sum_k W(k) w_hi(k) over the
+//           scaled spectrum W of each column; the pass then stores W itself (forward
+//           transform and eigen scaling only, no inverse transform).
 template <typename T> struct DstFaces {
   T* out = nullptr;
   const T* w = nullptr;  // w_lo[0..L), w_hi[0..L)
   long long plane = 0;
   int mode = 0;
 };
+
+// Spectral lift of the V-solve (dst_spectral.hip): the slowest-axis pass builds the
+// spectrum of the face-layer right-hand side from 2-D face spectra.  Layouts, with
+// L = N-1 along the pass axis, side 0 = low face, 1 = high face:
+//   lp [side][col]                faces normal to the pass axis (plane pplane)
+//   la [side][m-1][ib]            faces normal to the fastest axis a (plane aplane, row
+//                                 pitch apitch; 2-D: ib = 0)
+//   lb [side][m-1][ia]            faces normal to the middle axis b, 3-D only (plane
+//                                 bplane, row pitch bpitch)
+//   wp, wa, wb                    sines of the layer next to each face along the pass axis,
+//                                 axis a and axis b: [side][k-1], halves of length L, nwa, nwb
+template <typename T> struct DstGen {
+  const T* lp = nullptr;
+  long long pplane = 0;
+  const T* wp = nullptr;
+  const T* la = nullptr;
+  long long aplane = 0;
+  int apitch = 0;
+  const T* wa = nullptr;
+  int nwa = 0;
+  const T* lb = nullptr;
+  long long bplane = 0;
+  int bpitch = 0;
+  const T* wb = nullptr;
+  int nwb = 0;
+};
+
+template <typename T>
+int dst_gen_pass(const DstTables<T>& tb, T* out, long long inner, const DstScale<T>& sc, const DstGen<T>& gen,
+                 hipStream_t st);
+
+// Face contractions of a scaled spectrum W stored as planes [o][ky][kx] (row pitch px,
+// nx valid columns, ny rows, `planes` planes):
+//   fx[side][o][ky] = sum_kx W[o][ky][kx] wx[side][kx]        (every plane)
+//   fy[side][o][kx] = sum_ky W[o][ky][kx] wy[side][ky]        (when fy != null)
+// fx planes are [planes][ny], fy planes [planes][px] (padding columns written as zero).
+template <typename T>
+int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* wx, const T* wy, T* fx, T* fy,
+                hipStream_t st);
 
 // One pass of the batched DST-I along an axis of an interior array viewed as
 // [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils: `outer` rows

@@ -14,9 +14,11 @@ int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, 
 template <typename T>
 int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af, const T* srcq,
            double* R, hipStream_t st);
-// x-face sums of rows that are spectral in x (see stencil.hip)
+// face layers of the homogeneous lift (input of the spectral lift); fixed-order sums of partials
 template <typename T>
-int face_rows(long long rows, int nx, int px, const T* X, const T* w, T* F, long long plane, hipStream_t st);
+int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, hipStream_t st);
+template <typename T>
+int partial_sum(long long n, int count, long long stride, const T* in, T* out, hipStream_t st);
 // boundary residual from face sums formed in spectral space
 template <typename T>
 int gather_faces(const Geom& g, const T* Fx, const T* Fy, const T* Fz, const T* Q, const T* af,

@@ -22,6 +22,14 @@ namespace {
 
 constexpr int TPB = 256;
 
+// launch sizes of the row-based traversals: one work-group per interior / nodal row
+inline unsigned interior_rows(const Geom& g) {
+  return (unsigned)(g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1]);
+}
+inline unsigned nodal_rows(const Geom& g) {
+  return (unsigned)(g.dim == 3 ? (long long)g.nn[1] * g.nn[2] : g.nn[1]);
+}
+
 inline unsigned nblocks(long long n) {
   long long b = (n + TPB - 1) / TPB;
   if (b > 1048576) b = 1048576;
@@ -54,20 +62,6 @@ template <int DIM> __device__ __forceinline__ int qidx(const Geom& g, int i, int
   }
   const int f = (k == 0) ? 4 : 5;
   return g.face_off[f] + (j - 1) * g.ni[0] + (i - 1);
-}
-
-// decode a linear interior-array index into (i, j, k), 1-based; false on row padding
-template <int DIM> __device__ __forceinline__ bool dec_int(const Geom& g, long long e, int& i, int& j, int& k) {
-  i = (int)(e % g.px) + 1;
-  long long r = e / g.px;
-  if (DIM == 3) {
-    j = (int)(r % g.ni[1]) + 1;
-    k = (int)(r / g.ni[1]) + 1;
-  } else {
-    j = (int)r + 1;
-    k = 0;
-  }
-  return i <= g.ni[0];
 }
 
 // decode Q index -> boundary node, face axis and inward step
@@ -107,10 +101,13 @@ template <int DIM> __device__ __forceinline__ double lw(const Weights& w, int dx
 template <typename T, int DIM>
 __global__ void k_lift(Geom g, Weights w, const T* __restrict__ Q, const T* __restrict__ src,
                        T* __restrict__ G) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
-       e += (long long)gridDim.x * blockDim.x) {
-    int i, j, k;
-    if (!dec_int<DIM>(g, e, i, j, k)) {
+  // rows (j, k) across work-groups, x across threads (32-bit row decode)
+  const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i0_ = threadIdx.x; i0_ < g.px; i0_ += blockDim.x) {
+    const long long e = (long long)r_ * g.px + i0_;
+    const int i = i0_ + 1, j = (DIM == 3 ? r_ % g.ni[1] : r_) + 1, k = DIM == 3 ? r_ / g.ni[1] + 1 : 0;
+    if (i > g.ni[0]) {
       G[e] = T(0);
       continue;
     }
@@ -132,31 +129,38 @@ __global__ void k_lift(Geom g, Weights w, const T* __restrict__ Q, const T* __re
   }
 }
 
+// One work-group per interior row (j, k), threads along x: the row decode is two 32-bit
+// integer operations per row instead of 64-bit divisions per node.
 template <typename T, int DIM>
 __global__ void k_rhs_u(Geom g, Weights w, const T* __restrict__ V, const T* __restrict__ Q,
                         const T* __restrict__ ia, const T* __restrict__ src, T* __restrict__ G) {
   const T m0 = (T)w.m0, m1 = (T)w.m1;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
-       e += (long long)gridDim.x * blockDim.x) {
-    int i, j, k;
-    if (!dec_int<DIM>(g, e, i, j, k)) {
-      G[e] = T(0);
-      continue;
-    }
-    T acc = src ? src[e] : T(0);
-    acc += m0 * V[e] * ia[nod(g, i, j, k)];
-    T nb = 0;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-#pragma unroll
-      for (int s = -1; s <= 1; s += 2) {
-        const int qi = i + (a == 0 ? s : 0), qj = j + (a == 1 ? s : 0), qk = k + (a == 2 ? s : 0);
-        const bool bnd = (a == 0 && (qi == 0 || qi == g.n[0])) || (a == 1 && (qj == 0 || qj == g.n[1])) ||
-                         (a == 2 && (qk == 0 || qk == g.n[2]));
-        const T vq = bnd ? Q[qidx<DIM>(g, qi, qj, qk)] : V[inr(g, qi, qj, DIM == 3 ? qk : 1)];
-        nb += vq * ia[nod(g, qi, qj, qk)];
+  const int nrow = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  for (int r = blockIdx.x; r < nrow; r += gridDim.x) {
+    const int j = (DIM == 3 ? r % g.ni[1] : r) + 1;
+    const int k = DIM == 3 ? r / g.ni[1] + 1 : 0;
+    for (int i0 = threadIdx.x; i0 < g.px; i0 += blockDim.x) {
+      const long long e = (long long)r * g.px + i0;
+      const int i = i0 + 1;
+      if (i > g.ni[0]) {
+        G[e] = T(0);
+        continue;
       }
-    G[e] = acc + m1 * nb;
+      T acc = src ? src[e] : T(0);
+      acc += m0 * V[e] * ia[nod(g, i, j, k)];
+      T nb = 0;
+#pragma unroll
+      for (int a = 0; a < DIM; ++a)
+#pragma unroll
+        for (int s = -1; s <= 1; s += 2) {
+          const int qi = i + (a == 0 ? s : 0), qj = j + (a == 1 ? s : 0), qk = k + (a == 2 ? s : 0);
+          const bool bnd = (a == 0 && (qi == 0 || qi == g.n[0])) || (a == 1 && (qj == 0 || qj == g.n[1])) ||
+                           (a == 2 && (qk == 0 || qk == g.n[2]));
+          const T vq = bnd ? Q[qidx<DIM>(g, qi, qj, qk)] : V[inr(g, qi, qj, DIM == 3 ? qk : 1)];
+          nb += vq * ia[nod(g, qi, qj, qk)];
+        }
+      G[e] = acc + m1 * nb;
+    }
   }
 }
 
@@ -180,32 +184,101 @@ __global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __
   }
 }
 
-// Face sums along x from an array that is spectral in x (rows of the interior layout):
-//   F[r] = sum_k X[r, k] w_lo(k),  F[plane + r] = sum_k X[r, k] w_hi(k)
-// one wavefront per row, fixed-order reduction.
+// Face layers of the homogeneous lift L_h^bnd[Q]: the value at the interior node next to
+// a face, taken from that face's own Q (its nodes inside the 19-point (3-D) or 9-point
+// (2-D) stencil of the node), in the layouts of the spectral lift
+//   3-D  Lx[s][(k-1) n_y' + (j-1)], Ly[s][(k-1) px + (i-1)], Lz[s][(j-1) px + (i-1)]
+//   2-D  Lx[s][j-1], Ly[s][i-1]   (s = 0 low face, 1 high face; row padding zeroed)
+// Each interior node's lift is the sum over the faces it touches.
+template <int DIM>
+__device__ __forceinline__ void face_node(const Geom& g, int f, long long t, int& i, int& j, int& k, int& valid) {
+  const int ax = f >> 1, sd = f & 1;
+  valid = 1;
+  if (DIM == 2) {
+    k = 0;
+    if (ax == 0) {
+      i = sd ? g.ni[0] : 1;
+      j = (int)t + 1;
+    } else {
+      j = sd ? g.ni[1] : 1;
+      i = (int)t + 1;
+      valid = i <= g.ni[0];
+    }
+    return;
+  }
+  if (ax == 0) {  // [k][j]
+    i = sd ? g.ni[0] : 1;
+    k = (int)(t / g.ni[1]) + 1;
+    j = (int)(t % g.ni[1]) + 1;
+  } else if (ax == 1) {  // [k][i], pitch px
+    j = sd ? g.ni[1] : 1;
+    k = (int)(t / g.px) + 1;
+    i = (int)(t % g.px) + 1;
+    valid = i <= g.ni[0];
+  } else {  // [j][i], pitch px
+    k = sd ? g.ni[2] : 1;
+    j = (int)(t / g.px) + 1;
+    i = (int)(t % g.px) + 1;
+    valid = i <= g.ni[0];
+  }
+}
+
+template <typename T, int DIM>
+__global__ void k_face_lift(Geom g, Weights w, const T* __restrict__ Q, T* __restrict__ Lx, T* __restrict__ Ly,
+                            T* __restrict__ Lz, long long px_plane, long long py_plane, long long pz_plane) {
+  const long long tot = 2 * (px_plane + py_plane + (DIM == 3 ? pz_plane : 0));
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    int f;
+    long long t;
+    T* out;
+    if (e < 2 * px_plane) {
+      f = (int)(e / px_plane);
+      t = e - f * px_plane;
+      out = Lx + e;
+    } else if (e < 2 * (px_plane + py_plane)) {
+      const long long r = e - 2 * px_plane;
+      f = 2 + (int)(r / py_plane);
+      t = r - (f - 2) * py_plane;
+      out = Ly + r;
+    } else {
+      const long long r = e - 2 * (px_plane + py_plane);
+      f = 4 + (int)(r / pz_plane);
+      t = r - (f - 4) * pz_plane;
+      out = Lz + r;
+    }
+    int i, j, k, valid;
+    face_node<DIM>(g, f, t, i, j, k, valid);
+    T acc = 0;
+    if (valid) {
+      const int ax = f >> 1;
+      const int dn = (f & 1) ? 1 : -1;  // offset of the face plane from the node
+      for (int d1 = -1; d1 <= 1; ++d1)
+        for (int d2 = (DIM == 3 ? -1 : 0); d2 <= (DIM == 3 ? 1 : 0); ++d2) {
+          // tangential offsets: 3-D (d1, d2) along the two other axes; 2-D d1 only
+          int dx = 0, dy = 0, dz = 0;
+          if (ax == 0) { dx = dn; dy = d1; dz = d2; }
+          else if (ax == 1) { dy = dn; dx = d1; dz = d2; }
+          else { dz = dn; dx = d1; dy = d2; }
+          const double wt = lw<DIM>(w, dx, dy, dz);
+          if (wt == 0.0) continue;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          if (nbnd<DIM>(g, qi, qj, qk) == 1) acc += (T)wt * Q[qidx<DIM>(g, qi, qj, qk)];
+        }
+    }
+    *out = acc;
+  }
+}
+
+// out[e] = sum_{b < count} in[b * stride + e], e < n, in a fixed order
 template <typename T>
-__global__ void k_face_rows(long long rows, int nx, int px, const T* __restrict__ X, const T* __restrict__ w,
-                            T* __restrict__ F, long long plane) {
-  const int lane = threadIdx.x & 63;
-  const long long wv = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
-  const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long r = wv; r < rows; r += nw) {
-    const T* x = X + r * px;
-    T lo = 0, hi = 0;
-    for (int c = lane; c < nx; c += 64) {
-      const T v = x[c];
-      lo += v * w[c];
-      hi += v * w[nx + c];
-    }
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-      lo += __shfl_xor(lo, m, 64);
-      hi += __shfl_xor(hi, m, 64);
-    }
-    if (lane == 0) {
-      F[r] = lo;
-      F[plane + r] = hi;
-    }
+__global__ void k_partial_sum(long long n, int count, long long stride, const T* __restrict__ in,
+                              T* __restrict__ out) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    T acc = 0;
+    for (int b = 0; b < count; ++b) acc += in[b * stride + e];
+    out[e] = acc;
   }
 }
 
@@ -249,10 +322,13 @@ __global__ void k_resid_vol(Geom g, Weights w, const double* __restrict__ U, con
                             const double* __restrict__ Q, const double* __restrict__ ia,
                             const double* __restrict__ src_u, const double* __restrict__ src_v,
                             T* __restrict__ ru, T* __restrict__ rv) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
-       e += (long long)gridDim.x * blockDim.x) {
-    int i, j, k;
-    if (!dec_int<DIM>(g, e, i, j, k)) {
+  // rows (j, k) across work-groups, x across threads (32-bit row decode)
+  const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i0_ = threadIdx.x; i0_ < g.px; i0_ += blockDim.x) {
+    const long long e = (long long)r_ * g.px + i0_;
+    const int i = i0_ + 1, j = (DIM == 3 ? r_ % g.ni[1] : r_) + 1, k = DIM == 3 ? r_ / g.ni[1] + 1 : 0;
+    if (i > g.ni[0]) {
       rv[e] = T(0);
       ru[e] = T(0);
       continue;
@@ -346,10 +422,13 @@ template <int DIM>
 __global__ void k_src_vol(Geom g, Weights w, const double* __restrict__ f, const double* __restrict__ alpha,
                           const double* __restrict__ gD, const double* __restrict__ lapgD,
                           double* __restrict__ src_v, double* __restrict__ src_u) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nalloc;
-       e += (long long)gridDim.x * blockDim.x) {
-    int i, j, k;
-    if (!dec_int<DIM>(g, e, i, j, k)) {
+  // rows (j, k) across work-groups, x across threads (32-bit row decode)
+  const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i0_ = threadIdx.x; i0_ < g.px; i0_ += blockDim.x) {
+    const long long e = (long long)r_ * g.px + i0_;
+    const int i = i0_ + 1, j = (DIM == 3 ? r_ % g.ni[1] : r_) + 1, k = DIM == 3 ? r_ / g.ni[1] + 1 : 0;
+    if (i > g.ni[0]) {
       src_v[e] = 0.0;
       if (src_u) src_u[e] = 0.0;
       continue;
@@ -400,12 +479,13 @@ __global__ void k_src_q(Geom g, Weights w, const double* __restrict__ alpha, con
 // nodal outputs
 template <typename T, int DIM>
 __global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restrict__ gD, double* __restrict__ u) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nnodal;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(e % g.nn[0]);
-    const long long r = e / g.nn[0];
-    const int j = (int)(r % g.nn[1]);
-    const int k = (int)(r / g.nn[1]);
+  // nodal rows (j, k) across work-groups, x across threads
+  const int nrow_ = g.nn[1] * (DIM == 3 ? g.nn[2] : 1);
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i = threadIdx.x; i < g.nn[0]; i += blockDim.x) {
+    const long long e = (long long)r_ * g.nn[0] + i;
+    const int j = r_ % g.nn[1];
+    const int k = r_ / g.nn[1];
     const int nb = nbnd<DIM>(g, i, j, k);
     u[e] = nb == 0 ? (double)Ui[inr(g, i, j, DIM == 3 ? k : 1)] : (gD ? gD[e] : 0.0);
   }
@@ -414,12 +494,13 @@ __global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restri
 template <typename T, int DIM>
 __global__ void k_out_v(Geom g, const T* __restrict__ Vi, const double* __restrict__ Q,
                         const double* __restrict__ vedge, double* __restrict__ v) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < g.nnodal;
-       e += (long long)gridDim.x * blockDim.x) {
-    const int i = (int)(e % g.nn[0]);
-    const long long r = e / g.nn[0];
-    const int j = (int)(r % g.nn[1]);
-    const int k = (int)(r / g.nn[1]);
+  // nodal rows (j, k) across work-groups, x across threads
+  const int nrow_ = g.nn[1] * (DIM == 3 ? g.nn[2] : 1);
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i = threadIdx.x; i < g.nn[0]; i += blockDim.x) {
+    const long long e = (long long)r_ * g.nn[0] + i;
+    const int j = r_ % g.nn[1];
+    const int k = r_ / g.nn[1];
     const int nb = nbnd<DIM>(g, i, j, k);
     double val;
     if (nb == 0) val = (double)Vi[inr(g, i, j, DIM == 3 ? k : 1)];
@@ -506,14 +587,15 @@ __global__ void k_fill(long long n, double v, double* __restrict__ x) {
 
 template <typename T>
 int lift(const Geom& g, const Weights& w, const T* Q, const T* src, T* G, hipStream_t st) {
-  LAUNCH_TDIM(k_lift, T, dim3(nblocks(g.nalloc)), g, w, Q, src, G);
+  LAUNCH_TDIM(k_lift, T, dim3(interior_rows(g)), g, w, Q, src, G);
   return ST_OK;
 }
 
 template <typename T>
 int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
           hipStream_t st) {
-  LAUNCH_TDIM(k_rhs_u, T, dim3(nblocks(g.nalloc)), g, w, V, Q, ia, src, G);
+  const int nrow = g.dim == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  LAUNCH_TDIM(k_rhs_u, T, dim3((unsigned)(nrow < 1 ? 1 : nrow)), g, w, V, Q, ia, src, G);
   return ST_OK;
 }
 
@@ -525,10 +607,18 @@ int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af,
 }
 
 template <typename T>
-int face_rows(long long rows, int nx, int px, const T* X, const T* w, T* F, long long plane, hipStream_t st) {
-  long long b = (rows + 3) / 4;  // four rows (wavefronts) per block of 256
-  if (b > 1048576) b = 1048576;
-  hipLaunchKernelGGL((k_face_rows<T>), dim3((unsigned)(b < 1 ? 1 : b)), dim3(TPB), 0, st, rows, nx, px, X, w, F, plane);
+int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, hipStream_t st) {
+  const long long pxp = g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1];
+  const long long pyp = g.dim == 3 ? (long long)g.px * g.ni[2] : g.px;
+  const long long pzp = g.dim == 3 ? (long long)g.px * g.ni[1] : 0;
+  const long long tot = 2 * (pxp + pyp + pzp);
+  LAUNCH_TDIM(k_face_lift, T, dim3(nblocks(tot)), g, w, Q, Lx, Ly, Lz, pxp, pyp, pzp);
+  return ST_OK;
+}
+
+template <typename T>
+int partial_sum(long long n, int count, long long stride, const T* in, T* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_partial_sum<T>), dim3(nblocks(n)), dim3(TPB), 0, st, n, count, stride, in, out);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
@@ -544,7 +634,7 @@ template <typename T>
 int resid64(const Geom& g, const Weights& w, const double* U, const double* V, const double* Q,
             const double* ia, const double* af, const double* src_u, const double* src_v,
             const double* src_q, T* ru, T* rv, T* rq, hipStream_t st) {
-  LAUNCH_TDIM(k_resid_vol, T, dim3(nblocks(g.nalloc)), g, w, U, V, Q, ia, src_u, src_v, ru, rv);
+  LAUNCH_TDIM(k_resid_vol, T, dim3(interior_rows(g)), g, w, U, V, Q, ia, src_u, src_v, ru, rv);
   LAUNCH_TDIM(k_resid_q, T, dim3(nblocks(g.nq)), g, w, U, Q, af, src_q, rq);
   return ST_OK;
 }
@@ -564,20 +654,20 @@ int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
                   const double* gD, const double* gN, const double* lapgD, double* src_v,
                   double* src_u, double* src_q, hipStream_t st) {
-  LAUNCH_DIM(k_src_vol, dim3(nblocks(g.nalloc)), g, w, f, alpha, gD, lapgD, src_v, src_u);
+  LAUNCH_DIM(k_src_vol, dim3(interior_rows(g)), g, w, f, alpha, gD, lapgD, src_v, src_u);
   LAUNCH_DIM(k_src_q, dim3(nblocks(g.nq)), g, w, alpha, gD, gN, lapgD, src_q);
   return ST_OK;
 }
 
 template <typename T>
 int out_u(const Geom& g, const T* Ui, const double* gD, double* u, hipStream_t st) {
-  LAUNCH_TDIM(k_out_u, T, dim3(nblocks(g.nnodal)), g, Ui, gD, u);
+  LAUNCH_TDIM(k_out_u, T, dim3(nodal_rows(g)), g, Ui, gD, u);
   return ST_OK;
 }
 
 template <typename T>
 int out_v(const Geom& g, const T* Vi, const double* Q, const double* vedge, double* v, hipStream_t st) {
-  LAUNCH_TDIM(k_out_v, T, dim3(nblocks(g.nnodal)), g, Vi, Q, vedge, v);
+  LAUNCH_TDIM(k_out_v, T, dim3(nodal_rows(g)), g, Vi, Q, vedge, v);
   return ST_OK;
 }
 
@@ -621,7 +711,8 @@ int fill(long long n, double v, double* x, hipStream_t st) {
 }
 
 #define INST_T(T)                                                                                  \
-  template int face_rows<T>(long long, int, int, const T*, const T*, T*, long long, hipStream_t);  \
+  template int face_lift<T>(const Geom&, const Weights&, const T*, T*, T*, T*, hipStream_t);       \
+  template int partial_sum<T>(long long, int, long long, const T*, T*, hipStream_t);               \
   template int gather_faces<T>(const Geom&, const T*, const T*, const T*, const T*, const T*,       \
                                const T*, double*, hipStream_t);                                    \
   template int lift<T>(const Geom&, const Weights&, const T*, const T*, T*, hipStream_t);         \
