@@ -85,6 +85,8 @@ typedef struct {
   int max_sweeps;     /* MIXED: refinement sweeps cap (default 8)                    */
   int tile_fp64;      /* DST work-group tile in pencil pairs, 0 = default            */
   int tile_fp32;
+  int precond;        /* 1 (default): right-precondition GMRES with the boundary symbol
+                         (Sec. 4 solver settings; see ahoc_precond_apply); 0: none     */
 } ahoc_options;
 
 typedef struct {
@@ -116,6 +118,14 @@ size_t ahoc_nq(const ahoc_handle* h);
 /* y = S_h q (Lemma 1 in homogeneous form: R(q) - R(0)), q and y of length N_q,
  * FP64 in and out; the transforms and stencils run in the handle's precision. */
 ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* stream);
+
+/* y = P^{-1} q for the boundary-symbol preconditioner of the handle (Sec. 4 names a
+ * boundary-symbol preconditioner for the Schur GMRES without defining it).  P is the
+ * Schur complement of the constant-coefficient (alpha = 1) problem restricted to each
+ * pair of opposite faces: diagonal in the faces' 2-D sine basis up to the 2x2 coupling of
+ * the two faces, inverted mode by mode.  q, y: length N_q, FP64; asynchronous on the
+ * stream; AHOC_E_INVALID if the handle was set up with precond = 0. */
+ahoc_status ahoc_precond_apply(ahoc_handle* h, const double* q, double* y, void* stream);
 
 /* Right-hand side b = -R(0) of the Schur system (Algorithm 1, ConstructSchurRHS), FP64, length N_q. */
 ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream);
@@ -179,7 +189,8 @@ enum {
                               inverted along the slowest axis (writes the volume only)     */
   AHOC_K_FACE_REDUCE = 10, /* U-solve: face sums along the two fastest axes from the stored
                               scaled spectrum (reads the volume only)                      */
-  AHOC_NKIND = 11
+  AHOC_K_PRECOND = 11,     /* one application of the boundary-symbol preconditioner       */
+  AHOC_NKIND = 12
 };
 
 /* Enable (1) or disable (0) per-kernel-class timing of the handle's solves with

@@ -38,7 +38,7 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("tol", c_double),
                 ("inner_tol", c_double), ("sweep_tol", c_double), ("max_sweeps", c_int),
-                ("tile_fp64", c_int), ("tile_fp32", c_int)]
+                ("tile_fp64", c_int), ("tile_fp32", c_int), ("precond", c_int)]
 
 
 class _Stats(ctypes.Structure):
@@ -54,6 +54,8 @@ _lib.ahoc_nq.argtypes = [_H]
 _lib.ahoc_nq.restype = c_size_t
 _lib.ahoc_schur_apply.argtypes = [_H, c_void_p, c_void_p, c_void_p]
 _lib.ahoc_schur_apply.restype = c_int
+_lib.ahoc_precond_apply.argtypes = [_H, c_void_p, c_void_p, c_void_p]
+_lib.ahoc_precond_apply.restype = c_int
 _lib.ahoc_schur_rhs.argtypes = [_H, c_void_p, c_void_p]
 _lib.ahoc_schur_rhs.restype = c_int
 _lib.ahoc_solve.argtypes = [_H, c_void_p, c_void_p, c_void_p, ctypes.POINTER(_Stats), c_void_p]
@@ -80,9 +82,9 @@ _lib.ahoc_status_string.restype = ctypes.c_char_p
 _lib.ahoc_last_error.restype = ctypes.c_char_p
 
 KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "resid",
-                "matvec", "dst_gen", "face_reduce"]
+                "matvec", "dst_gen", "face_reduce", "precond"]
 
-EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_schur_rhs",
+EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
             "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
             "ahoc_status_string", "ahoc_last_error"]
 
@@ -213,6 +215,14 @@ class Solver:
         q = self._vec(q, self.nq)
         y = torch.empty(self.nq, dtype=torch.float64, device=self.device)
         _check(_lib.ahoc_schur_apply(self._h, _ptr(q), _ptr(y), _stream()), "ahoc_schur_apply")
+        return y
+
+    def precond_apply(self, q):
+        """y = P^-1 q with the handle's boundary-symbol preconditioner."""
+        torch = _torch()
+        q = self._vec(q, self.nq)
+        y = torch.empty(self.nq, dtype=torch.float64, device=self.device)
+        _check(_lib.ahoc_precond_apply(self._h, _ptr(q), _ptr(y), _stream()), "ahoc_precond_apply")
         return y
 
     def schur_rhs(self):

@@ -52,6 +52,11 @@ template <typename T> struct Prec {
   T* Fz = nullptr;
   // spectral entry/exit of the matvec (when every axis has a specialised kernel)
   bool spectral = false;
+  // boundary-symbol preconditioner: inverse 2x2 blocks per face mode (Q layout) and a
+  // work copy of the vector it is applied to
+  T* pc = nullptr;
+  T* qc = nullptr;
+  T* qP = nullptr;
   DstScale<T> scV, scU, scP;
   bool ready = false;
 };
@@ -84,6 +89,7 @@ struct ahoc_handle {
   double *Vb = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr;
   double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *part = nullptr, *y = nullptr;
   double *resid = nullptr, *beta = nullptr, *bvec = nullptr, *dq = nullptr, *rvec = nullptr, *R = nullptr;
+  double* zvec = nullptr;    // preconditioned Krylov vector
   double* red = nullptr;     // reduction partials
   double* pinned = nullptr;  // host-pinned scalars
   std::vector<void*> allocs;
@@ -287,6 +293,42 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.px, st));
   }
   P.spectral = faces_available(g);
+  if (h->opt.precond) {
+    // per-axis FP64 tables of the symbol: s(k), cos(pi k/N), sin(pi k/N), w_lo(k)
+    std::vector<double*> tabs(12, nullptr);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int a = 0; a < g.dim; ++a) {
+      const int L = g.ni[a];
+      std::vector<double> tv(4 * (size_t)L);
+      for (int k = 1; k <= L; ++k) {
+        const long double sh = sinl(pi * k / (2.0L * g.n[a]));
+        tv[k - 1] = (double)(-4.0L * sh * sh / ((long double)g.h[a] * g.h[a]));
+        tv[L + k - 1] = (double)cosl(pi * k / (long double)g.n[a]);
+        tv[2 * L + k - 1] = (double)sinl(pi * k / (long double)g.n[a]);
+        long double acc = 0;
+        for (int m = 1; m <= 3; ++m) acc += (long double)h->w.os[m] * sinl(pi * k * m / (long double)g.n[a]);
+        tv[3 * L + k - 1] = (double)acc;
+      }
+      double* d = nullptr;
+      TRY(alloc_t(h, &d, 4LL * L));
+      AHOC_HIP_TRY(hipMemcpy(d, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice));
+      for (int r = 0; r < 4; ++r) tabs[4 * a + r] = d + (long long)r * L;
+    }
+    double *pc64 = nullptr, *qc64 = nullptr;
+    TRY(alloc_t(h, &pc64, g.nq));
+    TRY(alloc_t(h, &qc64, g.nq));
+    TRY(precond_symbol(g, h->w, tabs.data(), pc64, qc64, st));
+    if constexpr (sizeof(T) == 8) {
+      P.pc = pc64;
+      P.qc = qc64;
+    } else {
+      TRY(alloc_t(h, &P.pc, g.nq));
+      TRY(alloc_t(h, &P.qc, g.nq));
+      TRY(convert<double, T>(g.nq, pc64, P.pc, st));
+      TRY(convert<double, T>(g.nq, qc64, P.qc, st));
+    }
+    TRY(alloc_t(h, &P.qP, g.nq));
+  }
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
   TRY(alloc_t(h, &P.qT, g.nq));
@@ -486,6 +528,40 @@ template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, co
   return ST_OK;
 }
 
+// 2-D DST-I of every face block of a Q-layout vector, in place.  Faces x-, x+ hold
+// [k][j], y-, y+ [k][i], z-, z+ [j][i] (lower axis fastest, no padding).
+template <typename T> int face_dst_q(ahoc_handle* h, Prec<T>& P, T* x, hipStream_t st) {
+  const Geom& g = h->g;
+  T* fx = x + g.face_off[0];
+  T* fy = x + g.face_off[2];
+  if (g.dim == 3) {
+    T* fz = x + g.face_off[4];
+    TRY(dst_pass<T>(P.tb[1], fx, fx, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], fx, fx, 2, g.ni[1], g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], fy, fy, 2LL * g.ni[2], 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], fy, fy, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], fz, fz, 2LL * g.ni[1], 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], fz, fz, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+  } else {
+    TRY(dst_pass<T>(P.tb[1], fx, fx, 2, 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], fy, fy, 2, 1, g.ni[0], nullptr, 0, st));
+  }
+  return ST_OK;
+}
+
+// y = P^-1 v (FP64 in and out, the transforms in the handle's precision)
+template <typename T> int precond_apply(ahoc_handle* h, Prec<T>& P, const double* v, double* y, hipStream_t st) {
+  const Geom& g = h->g;
+  hipEvent_t e = tbegin(h, st);
+  TRY(convert<double, T>(g.nq, v, P.qP, st));
+  TRY(face_dst_q<T>(h, P, P.qP, st));
+  TRY(precond_modes<T>(g, P.pc, P.qc, P.qP, st));
+  TRY(face_dst_q<T>(h, P, P.qP, st));
+  TRY(convert<T, double>(g.nq, P.qP, y, st));
+  tend(h, AHOC_K_PRECOND, e, (double)g.nq * (16.0 + 4.0 * sizeof(T)), st);
+  return ST_OK;
+}
+
 template <typename T> const T* q_in(ahoc_handle* h, Prec<T>& P, const double* q, hipStream_t st, int* rc) {
   if constexpr (sizeof(T) == 8) {
     (void)h; (void)P; (void)st;
@@ -584,13 +660,16 @@ struct GmresResult {
   bool converged = false;
 };
 
-// Restarted GMRES(m) on S_h x = b, x = 0 on entry.  All vectors FP64 on the device.
+// Restarted GMRES(m) on S_h x = b, x = 0 on entry, right-preconditioned by the boundary
+// symbol when it is enabled (x = P^-1 y, GMRES on S P^-1 y = b; the residual it monitors
+// is the true one).  All vectors FP64 on the device.
 // With an FP32 operator the residual estimate levels off at the operator's rounding
 // level; the inner solve then stops once eight iterations gained less than a factor 2.
 template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
           GmresResult& res, int* matvecs, hipStream_t st) {
   const bool inexact = sizeof(T) == 4;
+  const bool pre = P.pc != nullptr;
   std::vector<double> hist;
   const long long nq = h->g.nq;
   const int m = h->m;
@@ -630,7 +709,12 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
     for (int j = 0; j < m; ++j) {
       double* vj = h->Vb + (long long)j * nq;
       double* w = h->Vb + (long long)(j + 1) * nq;
-      TRY(matvec<T>(h, P, vj, w, st));
+      if (pre) {
+        TRY(precond_apply<T>(h, P, vj, h->zvec, st));
+        TRY(matvec<T>(h, P, h->zvec, w, st));
+      } else {
+        TRY(matvec<T>(h, P, vj, w, st));
+      }
       ++*matvecs;
       hipEvent_t ek = tbegin(h, st);
       TRY(mdot_partial(h->Vb, nq, j + 1, w, nq, h->part, h->nb_dot, st));
@@ -662,7 +746,14 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       if (res.iters >= max_iters) break;
     }
     TRY(back_solve(h->H, ldh, h->gv, jj, h->y, st));
-    TRY(maxpy(x, h->Vb, nq, jj, h->y, 1.0, nq, st));
+    if (pre) {  // x += P^-1 (V y); the cycle's residual vector is free again
+      TRY(fill(nq, 0.0, h->rvec, st));
+      TRY(maxpy(h->rvec, h->Vb, nq, jj, h->y, 1.0, nq, st));
+      TRY(precond_apply<T>(h, P, h->rvec, h->zvec, st));
+      TRY(axpby(nq, 1.0, h->zvec, 1.0, x, st));
+    } else {
+      TRY(maxpy(x, h->Vb, nq, jj, h->y, 1.0, nq, st));
+    }
     if (done || res.iters >= max_iters) return ST_OK;
   }
 }
@@ -743,6 +834,7 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
   TRY(alloc_t(h, &h->bvec, g.nq));
   TRY(alloc_t(h, &h->dq, g.nq));
   TRY(alloc_t(h, &h->rvec, g.nq));
+  TRY(alloc_t(h, &h->zvec, g.nq));
   AHOC_HIP_TRY(hipMemsetAsync(h->H, 0, sizeof(double) * (m + 1) * m, st));
   AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned), 64, hipHostMallocDefault));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
@@ -770,6 +862,7 @@ void ahoc_default_options(ahoc_options* o) {
   o->max_sweeps = 8;
   o->tile_fp64 = 0;
   o->tile_fp32 = 0;
+  o->precond = 1;
 }
 
 const char* ahoc_status_string(ahoc_status s) {
@@ -842,6 +935,19 @@ ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* s
   hipStream_t st = (hipStream_t)stream;
   int rc = h->opt.precision == AHOC_MIXED ? ahoc::matvec<float>(h, h->p32, q, y, st)
                                           : ahoc::matvec<double>(h, h->p64, q, y, st);
+  return (ahoc_status)rc;
+}
+
+ahoc_status ahoc_precond_apply(ahoc_handle* h, const double* q, double* y, void* stream) {
+  if (!h || !q || !y) return AHOC_E_INVALID;
+  hipStream_t st = (hipStream_t)stream;
+  const bool mixed = h->opt.precision == AHOC_MIXED;
+  if (mixed ? !h->p32.pc : !h->p64.pc) {
+    ahoc::set_last_error("the handle was set up with precond = 0", "ahoc_precond_apply");
+    return AHOC_E_INVALID;
+  }
+  int rc = mixed ? ahoc::precond_apply<float>(h, h->p32, q, y, st)
+                 : ahoc::precond_apply<double>(h, h->p64, q, y, st);
   return (ahoc_status)rc;
 }
 

@@ -19,6 +19,13 @@ template <typename T>
 int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, hipStream_t st);
 template <typename T>
 int partial_sum(long long n, int count, long long stride, const T* in, T* out, hipStream_t st);
+// boundary-symbol preconditioner (precond.hip): inverse 2x2 block coefficients per face
+// mode from per-axis FP64 tables {s, cos, sin, w_lo} x 3 axes, and their application to
+// face spectra of a Q-layout vector
+int precond_symbol(const Geom& g, const Weights& w, const double* const* tabs, double* pc, double* qc,
+                   hipStream_t st);
+template <typename T>
+int precond_modes(const Geom& g, const T* pc, const T* qc, T* x, hipStream_t st);
 // boundary residual from face sums formed in spectral space
 template <typename T>
 int gather_faces(const Geom& g, const T* Fx, const T* Fy, const T* Fz, const T* Q, const T* af,

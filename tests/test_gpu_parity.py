@@ -235,3 +235,65 @@ def test_batched_matches_single(ah):
         with ah.Solver(pb, tol=1e-13) as s:
             u1, *_ = s.solve()
         assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < 1e-12
+
+
+# ------------------------------------------------------------------------------------------
+# boundary-symbol preconditioner
+# ------------------------------------------------------------------------------------------
+
+def _face_sizes(n):
+    ni = [m - 1 for m in n]
+    if len(n) == 2:
+        return [ni[1], ni[1], ni[0], ni[0]]
+    return [ni[1] * ni[2]] * 2 + [ni[0] * ni[2]] * 2 + [ni[0] * ni[1]] * 2
+
+
+@pytest.mark.parametrize("n,hi", [((32, 24), (1.0, 0.75)), ((16, 12, 8), (1.0, 0.9, 0.6)), ((8, 8, 8), (1.0, 1.0, 1.0))])
+def test_precond_inverts_face_pair_block(ah, n, hi):
+    """With alpha = 1 the problem is separable, so the block of S_h that maps data on the two
+    faces normal to one axis to the residual on the same faces is exactly the symbol's
+    2x2-per-mode operator: S (P^-1 v) = v on that pair, and P^-1 v stays on the pair."""
+    shape = tuple(m + 1 for m in reversed(n))
+    p = W.Problem(n, (0.0,) * len(n), hi, np.ones(shape), np.zeros(shape))
+    S, b, asm = direct.schur(p)
+    sizes = _face_sizes(n)
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    rng = np.random.default_rng(17)
+    with ah.Solver(p) as s:
+        assert s.nq == S.shape[0] == off[-1]
+        for a in range(len(n)):
+            lo, hi_ = off[2 * a], off[2 * a + 2]
+            v = np.zeros(s.nq)
+            v[lo:hi_] = rng.standard_normal(hi_ - lo)
+            y = s.precond_apply(v).cpu().numpy()
+            assert np.abs(np.delete(y, np.arange(lo, hi_))).max() == 0.0
+            r = S @ y
+            assert _rel(r[lo:hi_], v[lo:hi_]) < 1e-11, (n, a)
+
+
+@pytest.mark.parametrize("case", ["c2_64", "c3_12", "cavity_32"])
+def test_solve_unpreconditioned_matches_direct(ah, case):
+    p = DIRECT_CASES[case]()
+    U, V, Q, asm = direct.solve(p)
+    with ah.Solver(p, tol=1e-14, precond=0) as s:
+        u, _, _, st = s.solve()
+    assert st.converged
+    assert _rel(u.cpu().numpy(), U) < 1e-12, case
+
+
+def test_precond_cuts_iterations(ah):
+    p = W.config2(128)
+    its = {}
+    for pc in (0, 1):
+        with ah.Solver(p, tol=1e-12, precond=pc) as s:
+            u, _, _, st = s.solve()
+        assert st.converged
+        its[pc] = (st.gmres_iters, u.cpu().numpy())
+    assert its[1][0] < 0.75 * its[0][0], its
+    assert _rel(its[1][1], its[0][1]) < 1e-11
+
+
+def test_precond_rejected_when_disabled(ah):
+    with ah.Solver(W.config2(16), precond=0) as s:
+        with pytest.raises(ah.AhocError):
+            s.precond_apply(np.zeros(s.nq))
