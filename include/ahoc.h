@@ -77,16 +77,23 @@ typedef struct {
   int precision;      /* ahoc_precision                                              */
   int restart;        /* GMRES restart length m (default 30)                         */
   int max_iters;      /* cap on GMRES iterations per Schur solve (default 2000)      */
-  double tol;         /* FP64: relative Schur residual ||b - S Q|| / ||b|| (1e-12)   */
-  double inner_tol;   /* MIXED: relative Schur residual of each correction (1e-4); the
+  double tol;         /* relative Schur residual ||b - S Q|| / ||b|| (1e-12): the FP64
+                         solve's GMRES tolerance, the MIXED (refine = 1) sweep stop    */
+  double inner_tol;   /* MIXED: relative Schur residual of each correction (1e-5); the
                          inner solve also ends when FP32 rounding stalls its residual   */
-  double sweep_tol;   /* MIXED: stop when the estimated remaining relative change of
-                         U (max norm) is below this (default 1e-11)                  */
+  double sweep_tol;   /* MIXED, refine = 0: stop when the estimated remaining relative
+                         change of U (max norm) is below this (default 1e-11)         */
   int max_sweeps;     /* MIXED: refinement sweeps cap (default 8)                    */
   int tile_fp64;      /* DST work-group tile in pencil pairs, 0 = default            */
   int tile_fp32;
   int precond;        /* 1 (default): right-precondition GMRES with the boundary symbol
                          (Sec. 4 solver settings; see ahoc_precond_apply); 0: none     */
+  int refine;         /* MIXED refinement: 1 (default) on the Schur system -- FP64
+                         residual b - S_h Q (FP64 operator), FP32-operator corrections,
+                         stop when ||b - S_h Q|| <= tol ||b||, FP64 recovery of U, V;
+                         0 on the coupled system -- FP64 residual of all three equation
+                         groups, corrections solved and recovered in FP32, stop on
+                         sweep_tol                                                     */
 } ahoc_options;
 
 typedef struct {

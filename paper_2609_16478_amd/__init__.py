@@ -38,7 +38,8 @@ class _Problem(ctypes.Structure):
 class _Options(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("tol", c_double),
                 ("inner_tol", c_double), ("sweep_tol", c_double), ("max_sweeps", c_int),
-                ("tile_fp64", c_int), ("tile_fp32", c_int), ("precond", c_int)]
+                ("tile_fp64", c_int), ("tile_fp32", c_int), ("precond", c_int),
+                ("refine", c_int)]
 
 
 class _Stats(ctypes.Structure):

@@ -52,11 +52,7 @@ template <typename T> struct Prec {
   T* Fz = nullptr;
   // spectral entry/exit of the matvec (when every axis has a specialised kernel)
   bool spectral = false;
-  // boundary-symbol preconditioner: inverse 2x2 blocks per face mode (Q layout) and a
-  // work copy of the vector it is applied to
-  T* pc = nullptr;
-  T* qc = nullptr;
-  T* qP = nullptr;
+
   DstScale<T> scV, scU, scP;
   bool ready = false;
 };
@@ -90,6 +86,14 @@ struct ahoc_handle {
   double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *part = nullptr, *y = nullptr;
   double *resid = nullptr, *beta = nullptr, *bvec = nullptr, *dq = nullptr, *rvec = nullptr, *R = nullptr;
   double* zvec = nullptr;    // preconditioned Krylov vector
+  double* b64 = nullptr;     // mixed, Schur refinement: FP64 right-hand side
+  // boundary-symbol preconditioner, applied in FP64 for either precision (its low modes
+  // are damped ~N-fold, so FP32 rounding of the face transforms would be amplified):
+  // inverse 2x2 block coefficients per face mode (Q layout) and FP64 transform tables
+  double* pc = nullptr;
+  double* qc = nullptr;
+  ahoc::DstTables<double> ptb[3];
+  bool ptb_own = false;
   double* red = nullptr;     // reduction partials
   double* pinned = nullptr;  // host-pinned scalars
   std::vector<void*> allocs;
@@ -293,42 +297,6 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.px, st));
   }
   P.spectral = faces_available(g);
-  if (h->opt.precond) {
-    // per-axis FP64 tables of the symbol: s(k), cos(pi k/N), sin(pi k/N), w_lo(k)
-    std::vector<double*> tabs(12, nullptr);
-    const long double pi = 3.141592653589793238462643383279502884L;
-    for (int a = 0; a < g.dim; ++a) {
-      const int L = g.ni[a];
-      std::vector<double> tv(4 * (size_t)L);
-      for (int k = 1; k <= L; ++k) {
-        const long double sh = sinl(pi * k / (2.0L * g.n[a]));
-        tv[k - 1] = (double)(-4.0L * sh * sh / ((long double)g.h[a] * g.h[a]));
-        tv[L + k - 1] = (double)cosl(pi * k / (long double)g.n[a]);
-        tv[2 * L + k - 1] = (double)sinl(pi * k / (long double)g.n[a]);
-        long double acc = 0;
-        for (int m = 1; m <= 3; ++m) acc += (long double)h->w.os[m] * sinl(pi * k * m / (long double)g.n[a]);
-        tv[3 * L + k - 1] = (double)acc;
-      }
-      double* d = nullptr;
-      TRY(alloc_t(h, &d, 4LL * L));
-      AHOC_HIP_TRY(hipMemcpy(d, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice));
-      for (int r = 0; r < 4; ++r) tabs[4 * a + r] = d + (long long)r * L;
-    }
-    double *pc64 = nullptr, *qc64 = nullptr;
-    TRY(alloc_t(h, &pc64, g.nq));
-    TRY(alloc_t(h, &qc64, g.nq));
-    TRY(precond_symbol(g, h->w, tabs.data(), pc64, qc64, st));
-    if constexpr (sizeof(T) == 8) {
-      P.pc = pc64;
-      P.qc = qc64;
-    } else {
-      TRY(alloc_t(h, &P.pc, g.nq));
-      TRY(alloc_t(h, &P.qc, g.nq));
-      TRY(convert<double, T>(g.nq, pc64, P.pc, st));
-      TRY(convert<double, T>(g.nq, qc64, P.qc, st));
-    }
-    TRY(alloc_t(h, &P.qP, g.nq));
-  }
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
   TRY(alloc_t(h, &P.qT, g.nq));
@@ -528,37 +496,74 @@ template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, co
   return ST_OK;
 }
 
+// Boundary-symbol preconditioner: FP64 symbol tables, the inverse block coefficients
+// and FP64 DST tables for the face transforms (shared with the FP64 operator if any).
+int precond_init(ahoc_handle* h, hipStream_t st) {
+  const Geom& g = h->g;
+  std::vector<double*> tabs(12, nullptr);
+  const long double pi = 3.141592653589793238462643383279502884L;
+  for (int a = 0; a < g.dim; ++a) {
+    const int L = g.ni[a];
+    std::vector<double> tv(4 * (size_t)L);
+    for (int k = 1; k <= L; ++k) {
+      const long double sh = sinl(pi * k / (2.0L * g.n[a]));
+      tv[k - 1] = (double)(-4.0L * sh * sh / ((long double)g.h[a] * g.h[a]));
+      tv[L + k - 1] = (double)cosl(pi * k / (long double)g.n[a]);
+      tv[2 * L + k - 1] = (double)sinl(pi * k / (long double)g.n[a]);
+      long double acc = 0;
+      for (int m = 1; m <= 3; ++m) acc += (long double)h->w.os[m] * sinl(pi * k * m / (long double)g.n[a]);
+      tv[3 * L + k - 1] = (double)acc;
+    }
+    double* d = nullptr;
+    TRY(alloc_t(h, &d, 4LL * L));
+    AHOC_HIP_TRY(hipMemcpy(d, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice));
+    for (int r = 0; r < 4; ++r) tabs[4 * a + r] = d + (long long)r * L;
+  }
+  TRY(alloc_t(h, &h->pc, g.nq));
+  TRY(alloc_t(h, &h->qc, g.nq));
+  TRY(precond_symbol(g, h->w, tabs.data(), h->pc, h->qc, st));
+  if (h->p64.ready) {
+    for (int a = 0; a < g.dim; ++a) h->ptb[a] = h->p64.tb[a];
+    h->ptb_own = false;
+  } else {
+    h->ptb_own = true;
+    for (int a = 0; a < g.dim; ++a) TRY(dst_tables_init<double>(h->ptb[a], g.n[a]));
+  }
+  AHOC_HIP_TRY(hipStreamSynchronize(st));
+  return ST_OK;
+}
+
 // 2-D DST-I of every face block of a Q-layout vector, in place.  Faces x-, x+ hold
 // [k][j], y-, y+ [k][i], z-, z+ [j][i] (lower axis fastest, no padding).
-template <typename T> int face_dst_q(ahoc_handle* h, Prec<T>& P, T* x, hipStream_t st) {
+int face_dst_q(ahoc_handle* h, double* x, hipStream_t st) {
   const Geom& g = h->g;
-  T* fx = x + g.face_off[0];
-  T* fy = x + g.face_off[2];
+  const DstTables<double>* tb = h->ptb;
+  double* fx = x + g.face_off[0];
+  double* fy = x + g.face_off[2];
   if (g.dim == 3) {
-    T* fz = x + g.face_off[4];
-    TRY(dst_pass<T>(P.tb[1], fx, fx, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[2], fx, fx, 2, g.ni[1], g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[0], fy, fy, 2LL * g.ni[2], 1, g.ni[0], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[2], fy, fy, 2, g.ni[0], g.ni[0], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[0], fz, fz, 2LL * g.ni[1], 1, g.ni[0], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], fz, fz, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+    double* fz = x + g.face_off[4];
+    TRY(dst_pass<double>(tb[1], fx, fx, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[2], fx, fx, 2, g.ni[1], g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], fy, fy, 2LL * g.ni[2], 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[2], fy, fy, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], fz, fz, 2LL * g.ni[1], 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[1], fz, fz, 2, g.ni[0], g.ni[0], nullptr, 0, st));
   } else {
-    TRY(dst_pass<T>(P.tb[1], fx, fx, 2, 1, g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[0], fy, fy, 2, 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[1], fx, fx, 2, 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], fy, fy, 2, 1, g.ni[0], nullptr, 0, st));
   }
   return ST_OK;
 }
 
-// y = P^-1 v (FP64 in and out, the transforms in the handle's precision)
-template <typename T> int precond_apply(ahoc_handle* h, Prec<T>& P, const double* v, double* y, hipStream_t st) {
+// y = P^-1 v (FP64), y may not alias v
+int precond_apply(ahoc_handle* h, const double* v, double* y, hipStream_t st) {
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
-  TRY(convert<double, T>(g.nq, v, P.qP, st));
-  TRY(face_dst_q<T>(h, P, P.qP, st));
-  TRY(precond_modes<T>(g, P.pc, P.qc, P.qP, st));
-  TRY(face_dst_q<T>(h, P, P.qP, st));
-  TRY(convert<T, double>(g.nq, P.qP, y, st));
-  tend(h, AHOC_K_PRECOND, e, (double)g.nq * (16.0 + 4.0 * sizeof(T)), st);
+  AHOC_HIP_TRY(hipMemcpyAsync(y, v, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
+  TRY(face_dst_q(h, y, st));
+  TRY(precond_modes<double>(g, h->pc, h->qc, y, st));
+  TRY(face_dst_q(h, y, st));
+  tend(h, AHOC_K_PRECOND, e, (double)g.nq * 16.0, st);
   return ST_OK;
 }
 
@@ -669,7 +674,7 @@ template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
           GmresResult& res, int* matvecs, hipStream_t st) {
   const bool inexact = sizeof(T) == 4;
-  const bool pre = P.pc != nullptr;
+  const bool pre = h->pc != nullptr;
   std::vector<double> hist;
   const long long nq = h->g.nq;
   const int m = h->m;
@@ -710,7 +715,7 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       double* vj = h->Vb + (long long)j * nq;
       double* w = h->Vb + (long long)(j + 1) * nq;
       if (pre) {
-        TRY(precond_apply<T>(h, P, vj, h->zvec, st));
+        TRY(precond_apply(h, vj, h->zvec, st));
         TRY(matvec<T>(h, P, h->zvec, w, st));
       } else {
         TRY(matvec<T>(h, P, vj, w, st));
@@ -749,7 +754,7 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
     if (pre) {  // x += P^-1 (V y); the cycle's residual vector is free again
       TRY(fill(nq, 0.0, h->rvec, st));
       TRY(maxpy(h->rvec, h->Vb, nq, jj, h->y, 1.0, nq, st));
-      TRY(precond_apply<T>(h, P, h->rvec, h->zvec, st));
+      TRY(precond_apply(h, h->rvec, h->zvec, st));
       TRY(axpby(nq, 1.0, h->zvec, 1.0, x, st));
     } else {
       TRY(maxpy(x, h->Vb, nq, jj, h->y, 1.0, nq, st));
@@ -805,17 +810,22 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
   // FP64 machinery (plain solve, or the refinement's reference operators)
   h->p64.ia = h->ia64;
   h->p64.af = h->af64;
-  if (!mixed) TRY(prec_init<double>(h, h->p64, h->opt.tile_fp64, st));
+  const bool schur_ir = mixed && h->opt.refine == 1;
+  if (!mixed || schur_ir) TRY(prec_init<double>(h, h->p64, h->opt.tile_fp64, st));
   if (mixed) {
     h->p32.ia = ia32;
     h->p32.af = af32;
     TRY(prec_init<float>(h, h->p32, h->opt.tile_fp32, st));
-    TRY(alloc_int(h, &h->U64, st));
-    TRY(alloc_int(h, &h->V64, st));
     TRY(alloc_t(h, &h->Q64, g.nq));
-    TRY(alloc_int(h, &h->ru, st));
-    TRY(alloc_int(h, &h->rv, st));
-    TRY(alloc_t(h, &h->rq, g.nq));
+    if (schur_ir) {
+      TRY(alloc_t(h, &h->b64, g.nq));
+    } else {
+      TRY(alloc_int(h, &h->U64, st));
+      TRY(alloc_int(h, &h->V64, st));
+      TRY(alloc_int(h, &h->ru, st));
+      TRY(alloc_int(h, &h->rv, st));
+      TRY(alloc_t(h, &h->rq, g.nq));
+    }
   }
   // Krylov workspace
   const int m = h->m;
@@ -838,6 +848,7 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
   AHOC_HIP_TRY(hipMemsetAsync(h->H, 0, sizeof(double) * (m + 1) * m, st));
   AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned), 64, hipHostMallocDefault));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
+  if (h->opt.precond) TRY(precond_init(h, st));
   return ST_OK;
 }
 
@@ -857,12 +868,13 @@ void ahoc_default_options(ahoc_options* o) {
   o->restart = 30;
   o->max_iters = 2000;
   o->tol = 1e-12;
-  o->inner_tol = 1e-4;
+  o->inner_tol = 1e-5;
   o->sweep_tol = 1e-11;
   o->max_sweeps = 8;
   o->tile_fp64 = 0;
   o->tile_fp32 = 0;
   o->precond = 1;
+  o->refine = 1;
 }
 
 const char* ahoc_status_string(ahoc_status s) {
@@ -884,6 +896,8 @@ void ahoc_destroy(ahoc_handle* h) {
   (void)hipDeviceSynchronize();
   ahoc::prec_free(h->p64);
   ahoc::prec_free(h->p32);
+  if (h->ptb_own)
+    for (int a = 0; a < 3; ++a) ahoc::dst_tables_free(h->ptb[a]);
   for (void* p : h->allocs) (void)hipFree(p);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
@@ -941,14 +955,15 @@ ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* s
 ahoc_status ahoc_precond_apply(ahoc_handle* h, const double* q, double* y, void* stream) {
   if (!h || !q || !y) return AHOC_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
-  const bool mixed = h->opt.precision == AHOC_MIXED;
-  if (mixed ? !h->p32.pc : !h->p64.pc) {
+  if (!h->pc) {
     ahoc::set_last_error("the handle was set up with precond = 0", "ahoc_precond_apply");
     return AHOC_E_INVALID;
   }
-  int rc = mixed ? ahoc::precond_apply<float>(h, h->p32, q, y, st)
-                 : ahoc::precond_apply<double>(h, h->p64, q, y, st);
-  return (ahoc_status)rc;
+  if (q == y) {
+    ahoc::set_last_error("q and y must not alias", "ahoc_precond_apply");
+    return AHOC_E_INVALID;
+  }
+  return (ahoc_status)ahoc::precond_apply(h, q, y, st);
 }
 
 ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream) {
@@ -1013,7 +1028,66 @@ int solve_fp64(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, h
   return gr.converged ? ST_OK : ST_NOCONV;
 }
 
+// Mixed precision, refinement on the Schur system: b and the residual r = b - S_h Q are
+// FP64 (FP64 operator), each correction S_h dQ = r is solved by GMRES with the FP32
+// operator (FP64 Krylov basis, Arnoldi, Givens), Q is updated in FP64, and the final
+// recovery of V and U from Q runs in FP64.  Stops when ||r|| <= tol ||b||.
+int solve_mixed_schur(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+  Prec<float>& P = h->p32;
+  Prec<double>& D = h->p64;
+  const Geom& g = h->g;
+  int rc = 0;
+  TRY(schur_rhs<double>(h, D, h->src_v, h->src_u, h->src_q, h->b64, st));
+  TRY(dot_dev(h, h->b64, h->b64, g.nq, h->nrm, st));
+  const double bnorm = std::sqrt(read_scalar(h, h->nrm, st, &rc));
+  TRY(rc);
+  TRY(fill(g.nq, 0.0, h->Q64, st));
+  AHOC_HIP_TRY(hipMemcpyAsync(h->bvec, h->b64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
+  int iters = 0, mv = 0, sweeps = 0;
+  double relres = bnorm > 0 ? 1.0 : 0.0, upd = 0;
+  bool conv = !(bnorm > 0);
+  for (int sw = 0; sw < h->opt.max_sweeps && !conv; ++sw) {
+    GmresResult gr;
+    TRY(gmres<float>(h, P, h->bvec, h->dq, h->opt.inner_tol, h->opt.max_iters, gr, &mv, st));
+    iters += gr.iters;
+    TRY(axpby(g.nq, 1.0, h->dq, 1.0, h->Q64, st));
+    ++sweeps;
+    const double dn = absmax(h, h->dq, true, g.nq, st, &rc);
+    TRY(rc);
+    const double qn = absmax(h, h->Q64, true, g.nq, st, &rc);
+    TRY(rc);
+    upd = qn > 0 ? dn / qn : 0.0;
+    // FP64 residual of the Schur system at the updated Q
+    hipEvent_t er = tbegin(h, st);
+    TRY(matvec<double>(h, D, h->Q64, h->bvec, st));
+    ++mv;
+    TRY(axpby(g.nq, 1.0, h->b64, -1.0, h->bvec, st));
+    TRY(dot_dev(h, h->bvec, h->bvec, g.nq, h->nrm, st));
+    relres = std::sqrt(read_scalar(h, h->nrm, st, &rc)) / bnorm;
+    TRY(rc);
+    tend(h, AHOC_K_RESID, er, 8.0 * (double)g.nq * 4.0, st);
+    conv = relres <= h->opt.tol;
+  }
+  TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+  TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+  TRY(out_u<double>(g, D.bufB, h->gD, u, st));
+  if (v) TRY(out_v<double>(g, D.bufA, h->Q64, h->vedge, v, st));
+  if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->Q64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
+  AHOC_HIP_TRY(hipStreamSynchronize(st));
+  s->converged = conv;
+  s->gmres_iters = iters;
+  s->sweeps = sweeps;
+  s->matvecs = mv;
+  s->schur_relres = relres;
+  s->last_update = upd;
+  return conv ? ST_OK : ST_NOCONV;
+}
+
+// Mixed precision, refinement on the coupled system: the FP64 residual of the whole
+// augmented system (u-, v- and q-rows) drives each sweep; the correction (Schur solve
+// and recovery) runs with the FP32 operators and is accumulated into FP64 U, V, Q.
 int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+  if (h->opt.refine == 1) return solve_mixed_schur(h, u, v, q, s, st);
   Prec<float>& P = h->p32;
   const Geom& g = h->g;
   int rc = 0;

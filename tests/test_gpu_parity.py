@@ -187,14 +187,15 @@ def test_solve_fp64_matches_direct(ah, case):
     assert _rel(v.cpu().numpy(), V) < 1e-10, case
 
 
+@pytest.mark.parametrize("refine", [1, 0], ids=["schur_ir", "coupled_ir"])
 @pytest.mark.parametrize("case", ["c2_64", "c3_12", "poly2d_24x16", "cavity_32"])
-def test_solve_mixed_matches_fp64(ah, case):
+def test_solve_mixed_matches_fp64(ah, case, refine):
     p = DIRECT_CASES[case]()
     with ah.Solver(p, tol=1e-14) as s:
         u64, *_ = s.solve()
-    with ah.Solver(p, precision=ah.MIXED) as s:
+    with ah.Solver(p, precision=ah.MIXED, refine=refine) as s:
         um, _, _, st = s.solve()
-    assert st.sweeps >= 2
+    assert st.converged and st.sweeps >= 2
     assert _rel(um.cpu().numpy(), u64.cpu().numpy()) <= 1e-10, (case, st)
 
 
