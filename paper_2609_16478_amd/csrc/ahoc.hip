@@ -94,8 +94,12 @@ struct ahoc_handle {
   double* qc = nullptr;
   ahoc::DstTables<double> ptb[3];
   bool ptb_own = false;
+  int* act = nullptr;        // per instance: still iterating (device)
+  int* kk = nullptr;         // per instance: Krylov dimension of the cycle (device)
+  double* ubuf = nullptr;    // batch: nodal U of all instances before the copy-out
   double* red = nullptr;     // reduction partials
-  double* pinned = nullptr;  // host-pinned scalars
+  double* pinned = nullptr;  // host-pinned scalars (2 per instance, at least 8)
+  int* pinned_i = nullptr;   // host-pinned ints (one per instance)
   std::vector<void*> allocs;
   // optional per-kernel-class timing with HIP events on the work stream
   bool prof = false;
@@ -164,20 +168,26 @@ void tresolve(ahoc_handle* h) {
     if (rc__) return rc__;      \
   } while (0)
 
+// sizes of whole-batch arrays (nb instances of the per-instance sizes)
+inline long long TQ(const Geom& g) { return (long long)g.nb * g.nq; }
+inline long long TA(const Geom& g) { return (long long)g.nb * g.nalloc; }
+inline long long TN(const Geom& g) { return (long long)g.nb * g.nnodal; }
+
 template <typename T> int alloc_t(ahoc_handle* h, T** p, long long n) {
   return dalloc(h, reinterpret_cast<void**>(p), sizeof(T) * (size_t)n);
 }
 
 // interior array (padded rows), zero-filled so the padding columns stay zero
 template <typename T> int alloc_int(ahoc_handle* h, T** p, hipStream_t st) {
-  int rc = alloc_t(h, p, h->g.nalloc);
+  int rc = alloc_t(h, p, TA(h->g));
   if (rc) return rc;
-  AHOC_HIP_TRY(hipMemsetAsync(*p, 0, sizeof(T) * (size_t)h->g.nalloc, st));
+  AHOC_HIP_TRY(hipMemsetAsync(*p, 0, sizeof(T) * (size_t)TA(h->g), st));
   return ST_OK;
 }
 
 void make_geom(const ahoc_problem* pb, Geom& g) {
   std::memset(&g, 0, sizeof(g));
+  g.nb = 1;
   g.dim = pb->dim;
   for (int a = 0; a < 3; ++a) {
     if (a < g.dim) {
@@ -291,17 +301,17 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     TRY(alloc_t(h, &P.Fz, 2LL * g.px * g.ni[1]));
     AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.px * g.ni[2], st));
     AHOC_HIP_TRY(hipMemsetAsync(P.Fz, 0, sizeof(T) * 2 * g.px * g.ni[1], st));
-  } else {
-    TRY(alloc_t(h, &P.Fx, 2LL * g.ni[1]));
-    TRY(alloc_t(h, &P.Fy, 2LL * g.px));
-    AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.px, st));
+  } else {  // per instance [2][n_y'] and [2][px]
+    TRY(alloc_t(h, &P.Fx, 2LL * g.nb * g.ni[1]));
+    TRY(alloc_t(h, &P.Fy, 2LL * g.nb * g.px));
+    AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.nb * g.px, st));
   }
   P.spectral = faces_available(g);
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
-  TRY(alloc_t(h, &P.qT, g.nq));
-  TRY(alloc_t(h, &P.zq, g.nq));
-  AHOC_HIP_TRY(hipMemsetAsync(P.zq, 0, sizeof(T) * g.nq, st));
+  TRY(alloc_t(h, &P.qT, TQ(g)));
+  TRY(alloc_t(h, &P.zq, TQ(g)));
+  AHOC_HIP_TRY(hipMemsetAsync(P.zq, 0, sizeof(T) * TQ(g), st));
   double norm = 1.0;
   for (int a = 0; a < g.dim; ++a) norm *= 2.0 / g.n[a];
   const int t = g.dim - 1;
@@ -338,7 +348,7 @@ template <typename T> void prec_free(Prec<T>& P) {
 // In-place Dirichlet solve on an interior array: buf <- scale * S (S buf / lambda).
 template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st) {
   const Geom& g = h->g;
-  const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);  // one read + one write of the array
+  const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);  // one read + one write of the array
   auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner,
                  const DstScale<T>* f, int tile) -> int {
     hipEvent_t e = tbegin(h, st);
@@ -347,10 +357,10 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
     return rc;
   };
   // strided passes also transform the (zero) padding columns of each row
-  if (g.dim == 2) {
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0]));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[1], 1, g.px, &sc, P.tile[1]));
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0]));
+  if (g.dim == 2) {  // a batch: nb slabs of n_y' rows
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, nullptr, P.tile[0]));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], g.nb, g.px, &sc, P.tile[1]));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, nullptr, P.tile[0]));
   } else {
     const long long rows = (long long)g.ni[1] * g.ni[2];
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, nullptr, P.tile[0]));
@@ -366,7 +376,7 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
 template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
   hipEvent_t e = tbegin(h, st);
   TRY(lift<T>(h->g, h->w, Q, src, P.bufA, st));
-  tend(h, AHOC_K_LIFT, e, (double)h->g.nint * sizeof(T) * (src ? 2 : 1), st);
+  tend(h, AHOC_K_LIFT, e, (double)h->g.nint * h->g.nb * sizeof(T) * (src ? 2 : 1), st);
   return poisson<T>(h, P, P.bufA, P.scV, st);
 }
 
@@ -375,7 +385,7 @@ template <typename T> int usolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T
   hipEvent_t e = tbegin(h, st);
   TRY(rhs_u<T>(h->g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
   // reads V and 1/alpha (nodal), writes G
-  tend(h, AHOC_K_RHS_U, e, (double)sizeof(T) * (2.0 * h->g.nint + h->g.nnodal) + (src ? h->g.nint * sizeof(T) : 0), st);
+  tend(h, AHOC_K_RHS_U, e, h->g.nb * ((double)sizeof(T) * (2.0 * h->g.nint + h->g.nnodal) + (src ? h->g.nint * sizeof(T) : 0)), st);
   return poisson<T>(h, P, P.bufB, P.scU, st);
 }
 
@@ -391,8 +401,8 @@ template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) 
     TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
     TRY(dst_pass<T>(P.tb[2], P.Fy, P.Fy, 2, g.px, g.px, nullptr, 0, st));
   } else {
-    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2, 1, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2, 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.nb, 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2LL * g.nb, 1, g.ni[1], nullptr, 0, st));
   }
   return ST_OK;
 }
@@ -405,8 +415,8 @@ template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hi
   hipEvent_t e = tbegin(h, st);
   TRY(face_lift<T>(g, h->w, Q, P.Fx, P.Fy, P.Fz, st));
   TRY(face_dst2<T>(h, P, st));
-  tend(h, AHOC_K_LIFT, e, (double)g.nq * 2.0 * sizeof(T), st);
-  const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);
+  tend(h, AHOC_K_LIFT, e, (double)TQ(g) * 2.0 * sizeof(T), st);
+  const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);
   T* buf = P.bufA;
   DstGen<T> gen;
   gen.wa = P.wl[0];
@@ -424,16 +434,18 @@ template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hi
     gen.bpitch = g.px;
     gen.wb = P.wl[1];
     gen.nwb = g.ni[1];
-    TRY(dst_gen_pass<T>(P.tb[2], buf, (long long)g.px * g.ni[1], P.scV, gen, st));
+    TRY(dst_gen_pass<T>(P.tb[2], buf, 1, (long long)g.px * g.ni[1], P.scV, gen, st));
   } else {
     gen.lp = P.Fy;
     gen.pplane = g.px;
     gen.wp = P.wl[1];
     gen.aplane = g.ni[1];
     gen.apitch = 1;
-    TRY(dst_gen_pass<T>(P.tb[1], buf, g.px, P.scV, gen, st));
+    gen.pslab = 2LL * g.px;  // instance o of a batch
+    gen.aslab = 2LL * g.ni[1];
+    TRY(dst_gen_pass<T>(P.tb[1], buf, g.nb, g.px, P.scV, gen, st));
   }
-  tend(h, AHOC_K_DST_GEN, eg, (double)g.nint * sizeof(T), st);
+  tend(h, AHOC_K_DST_GEN, eg, (double)g.nint * g.nb * sizeof(T), st);
   auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner, int tile) -> int {
     hipEvent_t ev = tbegin(h, st);
     const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, nullptr, tile, st);
@@ -444,7 +456,7 @@ template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hi
     TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, P.tile[1]));
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, P.tile[0]));
   } else {
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, P.tile[0]));
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, P.tile[0]));
   }
   return ST_OK;
 }
@@ -458,9 +470,9 @@ template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, co
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
   TRY(rhs_u<T>(g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
-  tend(h, AHOC_K_RHS_U, e, (double)sizeof(T) * (2.0 * g.nint + g.nnodal) + (src ? g.nint * sizeof(T) : 0), st);
+  tend(h, AHOC_K_RHS_U, e, g.nb * ((double)sizeof(T) * (2.0 * g.nint + g.nnodal) + (src ? g.nint * sizeof(T) : 0)), st);
   T* buf = P.bufB;
-  const double pass_bytes = 2.0 * (double)g.nint * sizeof(T);
+  const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);
   auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner, const DstScale<T>* f,
                  int tile, const DstFaces<T>* fc) -> int {
     hipEvent_t ev = tbegin(h, st);
@@ -478,21 +490,24 @@ template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, co
     TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, nullptr, P.tile[1], nullptr));
     TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fp));
     hipEvent_t er = tbegin(h, st);
-    TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy, st));
+    TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
+                       (long long)g.ni[2] * g.ni[1], g.ni[1], st));
     tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
   } else {
     fp.out = P.Fy;
     fp.w = P.wf[1];
     fp.plane = g.px;
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], g.ni[1], 1, nullptr, P.tile[0], nullptr));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[1], 1, g.px, &P.scU, P.tile[1], &fp));
+    fp.slab = 2LL * g.px;  // instance o of a batch
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, nullptr, P.tile[0], nullptr));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], g.nb, g.px, &P.scU, P.tile[1], &fp));
     hipEvent_t er = tbegin(h, st);
-    TRY(face_reduce<T>(buf, 1, g.ni[1], g.ni[0], g.px, P.wf[0], nullptr, P.Fx, nullptr, st));
-    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
+    TRY(face_reduce<T>(buf, g.nb, g.ni[1], g.ni[0], g.px, P.wf[0], nullptr, P.Fx, nullptr, g.ni[1],
+                       2LL * g.ni[1], st));
+    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * g.nb * sizeof(T), st);
   }
   hipEvent_t ef = tbegin(h, st);
   TRY(face_dst2<T>(h, P, st));
-  tend(h, AHOC_K_GATHER, ef, (double)g.nq * 2.0 * sizeof(T), st);
+  tend(h, AHOC_K_GATHER, ef, (double)TQ(g) * 2.0 * sizeof(T), st);
   return ST_OK;
 }
 
@@ -548,9 +563,11 @@ int face_dst_q(ahoc_handle* h, double* x, hipStream_t st) {
     TRY(dst_pass<double>(tb[2], fy, fy, 2, g.ni[0], g.ni[0], nullptr, 0, st));
     TRY(dst_pass<double>(tb[0], fz, fz, 2LL * g.ni[1], 1, g.ni[0], nullptr, 0, st));
     TRY(dst_pass<double>(tb[1], fz, fz, 2, g.ni[0], g.ni[0], nullptr, 0, st));
-  } else {
-    TRY(dst_pass<double>(tb[1], fx, fx, 2, 1, g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<double>(tb[0], fy, fy, 2, 1, g.ni[0], nullptr, 0, st));
+  } else {  // each face line of every instance of a batch (instances nq apart)
+    TRY(dst_pass<double>(tb[1], fx, fx, g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[1], fx + g.ni[1], fx + g.ni[1], g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], fy, fy, g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], fy + g.ni[0], fy + g.ni[0], g.nb, 1, g.nq, nullptr, 0, st));
   }
   return ST_OK;
 }
@@ -559,11 +576,11 @@ int face_dst_q(ahoc_handle* h, double* x, hipStream_t st) {
 int precond_apply(ahoc_handle* h, const double* v, double* y, hipStream_t st) {
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
-  AHOC_HIP_TRY(hipMemcpyAsync(y, v, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
+  AHOC_HIP_TRY(hipMemcpyAsync(y, v, sizeof(double) * TQ(g), hipMemcpyDeviceToDevice, st));
   TRY(face_dst_q(h, y, st));
   TRY(precond_modes<double>(g, h->pc, h->qc, y, st));
   TRY(face_dst_q(h, y, st));
-  tend(h, AHOC_K_PRECOND, e, (double)g.nq * 16.0, st);
+  tend(h, AHOC_K_PRECOND, e, (double)TQ(g) * 16.0, st);
   return ST_OK;
 }
 
@@ -573,7 +590,7 @@ template <typename T> const T* q_in(ahoc_handle* h, Prec<T>& P, const double* q,
     *rc = ST_OK;
     return reinterpret_cast<const T*>(q);
   } else {
-    *rc = convert<double, float>(h->g.nq, q, P.qT, st);
+    *rc = convert<double, float>(TQ(h->g), q, P.qT, st);
     return P.qT;
   }
 }
@@ -589,7 +606,7 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
     TRY(usolve_spec<T>(h, P, qT, nullptr, st));
     hipEvent_t eg = tbegin(h, st);
     TRY(gather_faces<T>(h->g, P.Fx, P.Fy, P.Fz, qT, P.af, nullptr, y, st));
-    tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (3 * sizeof(T) + sizeof(double)), st);
+    tend(h, AHOC_K_GATHER, eg, (double)TQ(h->g) * (3 * sizeof(T) + sizeof(double)), st);
   } else {
     TRY(vsolve<T>(h, P, qT, nullptr, st));
     TRY(usolve<T>(h, P, qT, nullptr, st));
@@ -606,7 +623,7 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
   const double np = g.dim == 3 ? 2.0 : 1.0;
   const double vol = P.spectral ? (1.0 + 2.0 * np + 2.0 + 2.0 * np + 2.0 + 1.0) * g.nint + g.nnodal
                                 : (1.0 + 2.0 * (2.0 * np + 1.0) * 2.0 + 2.0) * g.nint + g.nnodal;
-  tend(h, AHOC_K_MATVEC, e, s * vol, st);
+  tend(h, AHOC_K_MATVEC, e, s * vol * g.nb, st);
   return ST_OK;
 }
 
@@ -621,7 +638,7 @@ int schur_rhs(ahoc_handle* h, Prec<T>& P, const T* sv, const T* su, const T* sq,
     TRY(usolve<T>(h, P, P.zq, su, st));
     TRY(gather<T>(h->g, h->w, P.bufB, P.zq, P.af, sq, h->R, st));
   }
-  return axpby(h->g.nq, -1.0, h->R, 0.0, b, st);
+  return axpby(TQ(h->g), -1.0, h->R, 0.0, b, st);
 }
 
 double read_scalar(ahoc_handle* h, const double* dptr, hipStream_t st, int* rc) {
@@ -636,9 +653,29 @@ double read_scalar(ahoc_handle* h, const double* dptr, hipStream_t st, int* rc) 
   return h->pinned[0];
 }
 
-int dot_dev(ahoc_handle* h, const double* a, const double* b, long long n, double* out, hipStream_t st) {
-  TRY(mdot_partial(a, n, 1, b, n, h->part, h->nb_dot, st));
-  return mdot_reduce(h->part, h->nb_dot, 1, out, 0, st);
+// Copy `count` doubles from the device into h->pinned and wait.
+int read_vec(ahoc_handle* h, const double* dptr, int count, hipStream_t st) {
+  hipError_t e = hipMemcpyAsync(h->pinned, dptr, sizeof(double) * count, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e), "read_vec");
+    return ST_HIP;
+  }
+  return ST_OK;
+}
+
+// Upload `count` ints from h->pinned_i (stream-ordered; the host buffer is reused only
+// after the next synchronising read).
+int write_ints(ahoc_handle* h, int* dptr, int count, hipStream_t st) {
+  AHOC_HIP_TRY(hipMemcpyAsync(dptr, h->pinned_i, sizeof(int) * count, hipMemcpyHostToDevice, st));
+  return ST_OK;
+}
+
+// Per-instance dot products of two batch vectors: out[2 s] = <a_s, b_s>.
+int dot_dev(ahoc_handle* h, const double* a, const double* b, hipStream_t st, double* out) {
+  const long long n = h->g.nq;
+  TRY(mdot_partial(a, n, 1, b, n, h->g.nb, h->part, h->nb_dot, st));
+  return mdot_reduce(h->part, h->nb_dot, 1, h->g.nb, out, 2, 0, st);
 }
 
 double absmax(ahoc_handle* h, const void* x, bool dbl, long long n, hipStream_t st, int* rc) {
@@ -665,55 +702,74 @@ struct GmresResult {
   bool converged = false;
 };
 
-// Restarted GMRES(m) on S_h x = b, x = 0 on entry, right-preconditioned by the boundary
+// Restarted GMRES(m) on S_h x = b for every instance of the handle (lock-step over a
+// batch: one matvec, one Arnoldi step and one host read of the residual estimates per
+// iteration for all instances), x = 0 on entry, right-preconditioned by the boundary
 // symbol when it is enabled (x = P^-1 y, GMRES on S P^-1 y = b; the residual it monitors
-// is the true one).  All vectors FP64 on the device.
-// With an FP32 operator the residual estimate levels off at the operator's rounding
-// level; the inner solve then stops once eight iterations gained less than a factor 2.
+// is the true one).  All vectors FP64 on the device.  An instance stops when its estimate
+// reaches tol (its later basis vectors are zero and its Krylov dimension is frozen); with
+// an FP32 operator it also stops once eight iterations gained less than a factor 2 (the
+// estimate levels off at the operator's rounding level).
 template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
-          GmresResult& res, int* matvecs, hipStream_t st) {
+          std::vector<GmresResult>& res, int* matvecs, hipStream_t st) {
   const bool inexact = sizeof(T) == 4;
   const bool pre = h->pc != nullptr;
-  std::vector<double> hist;
+  const int ns = h->g.nb;
   const long long nq = h->g.nq;
+  const long long nt = nq * ns;  // batch vector length
   const int m = h->m;
-  const int ldh = m + 1;
-  int rc = 0;
-  TRY(fill(nq, 0.0, x, st));
-  TRY(dot_dev(h, b, b, nq, h->nrm, st));
-  const double bnorm = std::sqrt(read_scalar(h, h->nrm, st, &rc));
-  TRY(rc);
-  res = GmresResult();
-  if (!(bnorm > 0)) {
-    res.converged = bnorm == 0;
-    return ST_OK;
+  res.assign(ns, GmresResult());
+  std::vector<std::vector<double>> hist(ns);
+  std::vector<double> bnorm(ns);
+  std::vector<char> conv(ns, 0), active(ns, 0), stalled(ns, 0);
+  std::vector<int> jj(ns, 0);
+  TRY(fill(nt, 0.0, x, st));
+  TRY(dot_dev(h, b, b, st, h->nrm));
+  TRY(read_vec(h, h->nrm, 2 * ns, st));
+  bool any = false;
+  for (int s = 0; s < ns; ++s) {
+    bnorm[s] = std::sqrt(std::max(h->pinned[2 * s], 0.0));
+    conv[s] = !(bnorm[s] > 0);
+    res[s].converged = conv[s];
+    any = any || !conv[s];
   }
+  if (!any) return ST_OK;
   bool first = true;
   while (true) {
     const double* r = b;
     if (!first) {
       TRY(matvec<T>(h, P, x, h->rvec, st));
       ++*matvecs;
-      TRY(axpby(nq, 1.0, b, -1.0, h->rvec, st));  // r = b - S x
+      TRY(axpby(nt, 1.0, b, -1.0, h->rvec, st));  // r = b - S x
       r = h->rvec;
     }
     first = false;
-    TRY(dot_dev(h, r, r, nq, h->nrm, st));
-    TRY(start_cycle(h->Vb, r, nq, h->nrm, h->gv, m, h->beta, st));
-    const double beta = read_scalar(h, h->beta, st, &rc);
-    TRY(rc);
-    res.relres = beta / bnorm;
-    if (beta <= tol * bnorm) {
-      res.converged = true;
-      return ST_OK;
+    TRY(dot_dev(h, r, r, st, h->nrm));
+    TRY(start_cycle(h->Vb, r, nq, ns, h->nrm, h->gv, m, h->beta, st));
+    TRY(read_vec(h, h->beta, ns, st));
+    any = false;
+    for (int s = 0; s < ns; ++s) {
+      jj[s] = 0;
+      if (conv[s]) {
+        active[s] = 0;
+        continue;
+      }
+      res[s].relres = h->pinned[s] / bnorm[s];
+      if (h->pinned[s] <= tol * bnorm[s]) {
+        conv[s] = 1;
+        res[s].converged = true;
+      }
+      active[s] = !conv[s] && res[s].iters < max_iters;
+      any = any || active[s];
     }
-    if (res.iters >= max_iters) return ST_OK;
-    int jj = 0;
-    bool done = false;
+    if (!any) return ST_OK;
+    for (int s = 0; s < ns; ++s) h->pinned_i[s] = active[s];
+    TRY(write_ints(h, h->act, ns, st));
+    int jmax = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = h->Vb + (long long)j * nq;
-      double* w = h->Vb + (long long)(j + 1) * nq;
+      double* vj = h->Vb + (long long)j * nt;
+      double* w = h->Vb + (long long)(j + 1) * nt;
       if (pre) {
         TRY(precond_apply(h, vj, h->zvec, st));
         TRY(matvec<T>(h, P, h->zvec, w, st));
@@ -722,72 +778,133 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       }
       ++*matvecs;
       hipEvent_t ek = tbegin(h, st);
-      TRY(mdot_partial(h->Vb, nq, j + 1, w, nq, h->part, h->nb_dot, st));
-      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, h->h1, 0, st));
-      TRY(maxpy(w, h->Vb, nq, j + 1, h->h1, -1.0, nq, st));
-      TRY(mdot_partial(h->Vb, nq, j + 1, w, nq, h->part, h->nb_dot, st));
-      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, h->h2, 0, st));
-      TRY(maxpy(w, h->Vb, nq, j + 1, h->h2, -1.0, nq, st));
-      TRY(dot_dev(h, w, w, nq, h->nrm, st));
-      TRY(givens_step(h->H, ldh, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
-      TRY(scale_by_inv(w, nq, h->resid, st));
+      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, h->nb_dot, st));
+      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, ns, h->h1, m + 1, 0, st));
+      TRY(maxpy(w, h->Vb, nt, j + 1, h->h1, m + 1, -1.0, nq, ns, st));
+      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, h->nb_dot, st));
+      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, ns, h->h2, m + 1, 0, st));
+      TRY(maxpy(w, h->Vb, nt, j + 1, h->h2, m + 1, -1.0, nq, ns, st));
+      TRY(dot_dev(h, w, w, st, h->nrm));
+      TRY(givens_step(ns, h->H, m, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
+      TRY(scale_by_inv(w, nq, ns, h->resid, h->act, st));
       // CGS2: 2 x (j+1) dot sweeps and 2 x (j+1) axpy sweeps over the basis, plus norm and scale
-      tend(h, AHOC_K_KRYLOV, ek, 8.0 * nq * (4.0 * (j + 1) + 2.0 * 2 + 3.0), st);
-      ++res.iters;
-      jj = j + 1;
-      const double est = read_scalar(h, h->resid, st, &rc) / bnorm;
-      TRY(rc);
-      res.relres = est;
-      if (est <= tol) {
-        done = true;
-        res.converged = true;
-        break;
+      tend(h, AHOC_K_KRYLOV, ek, 8.0 * nt * (4.0 * (j + 1) + 2.0 * 2 + 3.0), st);
+      jmax = j + 1;
+      TRY(read_vec(h, h->resid, 2 * ns, st));
+      any = false;
+      bool changed = false;
+      for (int s = 0; s < ns; ++s) {
+        if (!active[s]) continue;
+        ++res[s].iters;
+        jj[s] = j + 1;
+        const double est = h->pinned[2 * s] / bnorm[s];
+        res[s].relres = est;
+        bool stop = false;
+        if (est <= tol) {
+          conv[s] = 1;
+          res[s].converged = true;
+          stop = true;
+        } else {
+          hist[s].push_back(est);
+          const size_t hs = hist[s].size();
+          if (inexact && hs > 8 && est < 1e-2 && est > 0.5 * hist[s][hs - 9]) stop = stalled[s] = 1;
+          if (res[s].iters >= max_iters) stop = true;
+        }
+        if (stop) {
+          active[s] = 0;
+          changed = true;
+        }
+        any = any || active[s];
       }
-      hist.push_back(est);
-      if (inexact && hist.size() > 8 && est < 1e-2 && est > 0.5 * hist[hist.size() - 9]) {
-        done = true;
-        break;
+      if (!any) break;
+      if (changed) {
+        for (int s = 0; s < ns; ++s) h->pinned_i[s] = active[s];
+        TRY(write_ints(h, h->act, ns, st));
       }
-      if (res.iters >= max_iters) break;
     }
-    TRY(back_solve(h->H, ldh, h->gv, jj, h->y, st));
+    for (int s = 0; s < ns; ++s) h->pinned_i[s] = jj[s];
+    TRY(write_ints(h, h->kk, ns, st));
+    TRY(back_solve(ns, h->H, m, h->gv, h->kk, jmax, h->y, st));
     if (pre) {  // x += P^-1 (V y); the cycle's residual vector is free again
-      TRY(fill(nq, 0.0, h->rvec, st));
-      TRY(maxpy(h->rvec, h->Vb, nq, jj, h->y, 1.0, nq, st));
+      TRY(fill(nt, 0.0, h->rvec, st));
+      TRY(maxpy(h->rvec, h->Vb, nt, jmax, h->y, m + 1, 1.0, nq, ns, st));
       TRY(precond_apply(h, h->rvec, h->zvec, st));
-      TRY(axpby(nq, 1.0, h->zvec, 1.0, x, st));
+      TRY(axpby(nt, 1.0, h->zvec, 1.0, x, st));
     } else {
-      TRY(maxpy(x, h->Vb, nq, jj, h->y, 1.0, nq, st));
+      TRY(maxpy(x, h->Vb, nt, jmax, h->y, m + 1, 1.0, nq, ns, st));
     }
-    if (done || res.iters >= max_iters) return ST_OK;
+    // another cycle for the instances that neither converged, stalled nor hit the cap;
+    // the others are finished (conv = 2: stopped without convergence)
+    any = false;
+    for (int s = 0; s < ns; ++s) {
+      if (conv[s]) continue;
+      if (stalled[s] || res[s].iters >= max_iters) conv[s] = 2;
+      else any = true;
+    }
+    if (!any) return ST_OK;
   }
 }
 
-int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
+// Concatenate one nodal input field of `count` instances into a batch array (nullptr if no
+// instance has it; instances without it get zeros).
+int gather_field(ahoc_handle* h, const ahoc_problem* pbs, int count, size_t off, double** out, hipStream_t st) {
+  bool any = false;
+  for (int i = 0; i < count; ++i)
+    any = any || *reinterpret_cast<const double* const*>(reinterpret_cast<const char*>(&pbs[i]) + off);
+  *out = nullptr;
+  if (!any) return ST_OK;
+  const long long nn = h->g.nnodal;
+  TRY(alloc_t(h, out, nn * count));
+  for (int i = 0; i < count; ++i) {
+    const double* src = *reinterpret_cast<const double* const*>(reinterpret_cast<const char*>(&pbs[i]) + off);
+    if (src) {
+      AHOC_HIP_TRY(hipMemcpyAsync(*out + nn * i, src, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+    } else {
+      TRY(fill(nn, 0.0, *out + nn * i, st));
+    }
+  }
+  return ST_OK;
+}
+
+// Set up one problem, or a batch of `count` 2-D problems on the same grid (same n, lo, hi),
+// whose arrays then hold the instances one after another.
+int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* h) {
   Geom& g = h->g;
+  const ahoc_problem* pb = &pbs[0];
   make_geom(pb, g);
+  g.nb = count;
   make_weights(g, h->w);
   h->m = h->opt.restart;
+  const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD;
+  if (count > 1) {
+    double *a_, *f_, *gd_, *gn_, *lg_;
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, alpha), &a_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, f), &f_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gD), &gd_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gN), &gn_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, lapgD), &lg_, st));
+    alpha = a_, f = f_, gD = gd_, gN = gn_, lapgD = lg_;
+  }
   // FP64 data
-  TRY(alloc_t(h, &h->ia64, g.nnodal));
-  TRY(alloc_t(h, &h->af64, g.nq));
+  TRY(alloc_t(h, &h->ia64, TN(g)));
+  TRY(alloc_t(h, &h->af64, TQ(g)));
   TRY(alloc_int(h, &h->src_v, st));
-  TRY(alloc_t(h, &h->src_q, g.nq));
-  if (pb->gD) {
+  TRY(alloc_t(h, &h->src_q, TQ(g)));
+  if (gD) {
     TRY(alloc_int(h, &h->src_u, st));
-    TRY(alloc_t(h, &h->gD, g.nnodal));
-    AHOC_HIP_TRY(hipMemcpyAsync(h->gD, pb->gD, sizeof(double) * g.nnodal, hipMemcpyDeviceToDevice, st));
+    TRY(alloc_t(h, &h->gD, TN(g)));
+    AHOC_HIP_TRY(hipMemcpyAsync(h->gD, gD, sizeof(double) * TN(g), hipMemcpyDeviceToDevice, st));
   }
   TRY(alloc_t(h, &h->red, 1024));
-  TRY(alloc_t(h, &h->R, g.nq));
+  TRY(alloc_t(h, &h->R, TQ(g)));
   const bool mixed = h->opt.precision == AHOC_MIXED;
   float* ia32 = nullptr;
   float* af32 = nullptr;
   if (mixed) {
-    TRY(alloc_t(h, &ia32, g.nnodal));
-    TRY(alloc_t(h, &af32, g.nq));
+    TRY(alloc_t(h, &ia32, TN(g)));
+    TRY(alloc_t(h, &af32, TQ(g)));
   }
-  TRY(setup_inv_alpha(g.nnodal, pb->alpha, h->ia64, ia32, h->red, 1024, st));
+  TRY(setup_inv_alpha(TN(g), alpha, h->ia64, ia32, h->red, 1024, st));
   {
     std::vector<double> hb(1024);
     AHOC_HIP_TRY(hipMemcpyAsync(hb.data(), h->red, sizeof(double) * 1024, hipMemcpyDeviceToHost, st));
@@ -799,13 +916,12 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
       return ST_INVALID;
     }
   }
-  TRY(setup_face_alpha(g, pb->alpha, h->af64, af32, st));
-  TRY(setup_sources(g, h->w, pb->f, pb->alpha, pb->gD, pb->gN, pb->lapgD, h->src_v, h->src_u,
-                    h->src_q, st));
-  if (pb->lapgD) {
+  TRY(setup_face_alpha(g, alpha, h->af64, af32, st));
+  TRY(setup_sources(g, h->w, f, alpha, gD, gN, lapgD, h->src_v, h->src_u, h->src_q, st));
+  if (lapgD) {
     // V = alpha * Delta u on edges and corners (Remark 1); read there only
-    TRY(alloc_t(h, &h->vedge, g.nnodal));
-    TRY(mul(g.nnodal, pb->alpha, pb->lapgD, h->vedge, st));
+    TRY(alloc_t(h, &h->vedge, TN(g)));
+    TRY(mul(TN(g), alpha, lapgD, h->vedge, st));
   }
   // FP64 machinery (plain solve, or the refinement's reference operators)
   h->p64.ia = h->ia64;
@@ -816,37 +932,43 @@ int setup_impl(const ahoc_problem* pb, hipStream_t st, ahoc_handle* h) {
     h->p32.ia = ia32;
     h->p32.af = af32;
     TRY(prec_init<float>(h, h->p32, h->opt.tile_fp32, st));
-    TRY(alloc_t(h, &h->Q64, g.nq));
+    TRY(alloc_t(h, &h->Q64, TQ(g)));
     if (schur_ir) {
-      TRY(alloc_t(h, &h->b64, g.nq));
+      TRY(alloc_t(h, &h->b64, TQ(g)));
     } else {
       TRY(alloc_int(h, &h->U64, st));
       TRY(alloc_int(h, &h->V64, st));
       TRY(alloc_int(h, &h->ru, st));
       TRY(alloc_int(h, &h->rv, st));
-      TRY(alloc_t(h, &h->rq, g.nq));
+      TRY(alloc_t(h, &h->rq, TQ(g)));
     }
   }
-  // Krylov workspace
+  // Krylov workspace (per instance: Hessenberg, rotations, norms; one basis of batch vectors)
   const int m = h->m;
-  TRY(alloc_t(h, &h->Vb, (long long)(m + 1) * g.nq));
-  TRY(alloc_t(h, &h->H, (long long)(m + 1) * m));
-  TRY(alloc_t(h, &h->cs, m));
-  TRY(alloc_t(h, &h->sn, m));
-  TRY(alloc_t(h, &h->gv, m + 1));
-  TRY(alloc_t(h, &h->h1, m + 1));
-  TRY(alloc_t(h, &h->h2, m + 1));
-  TRY(alloc_t(h, &h->nrm, 2));
-  TRY(alloc_t(h, &h->resid, 2));
-  TRY(alloc_t(h, &h->beta, 2));
-  TRY(alloc_t(h, &h->y, m + 2));
-  TRY(alloc_t(h, &h->part, (long long)(m + 1) * h->nb_dot));
-  TRY(alloc_t(h, &h->bvec, g.nq));
-  TRY(alloc_t(h, &h->dq, g.nq));
-  TRY(alloc_t(h, &h->rvec, g.nq));
-  TRY(alloc_t(h, &h->zvec, g.nq));
-  AHOC_HIP_TRY(hipMemsetAsync(h->H, 0, sizeof(double) * (m + 1) * m, st));
-  AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned), 64, hipHostMallocDefault));
+  const long long nb = g.nb;
+  TRY(alloc_t(h, &h->Vb, (long long)(m + 1) * TQ(g)));
+  TRY(alloc_t(h, &h->H, nb * (m + 1) * m));
+  TRY(alloc_t(h, &h->cs, nb * m));
+  TRY(alloc_t(h, &h->sn, nb * m));
+  TRY(alloc_t(h, &h->gv, nb * (m + 1)));
+  TRY(alloc_t(h, &h->h1, nb * (m + 1)));
+  TRY(alloc_t(h, &h->h2, nb * (m + 1)));
+  TRY(alloc_t(h, &h->nrm, 2 * nb));
+  TRY(alloc_t(h, &h->resid, 2 * nb));
+  TRY(alloc_t(h, &h->beta, nb));
+  TRY(alloc_t(h, &h->y, nb * (m + 1)));
+  TRY(alloc_t(h, &h->part, nb * (m + 1) * h->nb_dot));
+  TRY(alloc_t(h, &h->act, nb));
+  TRY(alloc_t(h, &h->kk, nb));
+  TRY(alloc_t(h, &h->bvec, TQ(g)));
+  TRY(alloc_t(h, &h->dq, TQ(g)));
+  TRY(alloc_t(h, &h->rvec, TQ(g)));
+  TRY(alloc_t(h, &h->zvec, TQ(g)));
+  if (nb > 1) TRY(alloc_t(h, &h->ubuf, TN(g)));
+  AHOC_HIP_TRY(hipMemsetAsync(h->H, 0, sizeof(double) * nb * (m + 1) * m, st));
+  const size_t npin = (size_t)std::max<long long>(8, 2 * nb);
+  AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned), sizeof(double) * npin, hipHostMallocDefault));
+  AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_i), sizeof(int) * npin, hipHostMallocDefault));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
   if (h->opt.precond) TRY(precond_init(h, st));
   return ST_OK;
@@ -901,14 +1023,13 @@ void ahoc_destroy(ahoc_handle* h) {
   for (void* p : h->allocs) (void)hipFree(p);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
+  if (h->pinned_i) (void)hipHostFree(h->pinned_i);
   delete h;
 }
 
 size_t ahoc_nq(const ahoc_handle* h) { return h ? (size_t)h->g.nq : 0; }
 
-ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, void* stream, ahoc_handle** out) {
-  if (!pb || !out) return AHOC_E_INVALID;
-  *out = nullptr;
+static ahoc_status validate_problem(const ahoc_problem* pb) {
   if (pb->dim != 2 && pb->dim != 3) {
     ahoc::set_last_error("dim must be 2 or 3", "ahoc_setup");
     return AHOC_E_INVALID;
@@ -927,6 +1048,17 @@ ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, void* st
       return AHOC_E_UNSUPPORTED;
     }
   }
+  return AHOC_OK;
+}
+
+// count == 1: one problem; count > 1: a batch of 2-D problems on the same grid.
+static ahoc_status setup_n(const ahoc_problem* pbs, int count, const ahoc_options* opt, void* stream,
+                           ahoc_handle** out) {
+  *out = nullptr;
+  for (int i = 0; i < count; ++i) {
+    const ahoc_status v = validate_problem(&pbs[i]);
+    if (v != AHOC_OK) return v;
+  }
   ahoc_handle* h = new ahoc_handle();
   if (opt) h->opt = *opt;
   else ahoc_default_options(&h->opt);
@@ -935,13 +1067,19 @@ ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, void* st
     delete h;
     return AHOC_E_INVALID;
   }
-  const int rc = ahoc::setup_impl(pb, (hipStream_t)stream, h);
+  if (count > 1) h->opt.refine = 1;  // a batch refines on the Schur system
+  const int rc = ahoc::setup_impl(pbs, count, (hipStream_t)stream, h);
   if (rc) {
     ahoc_destroy(h);
     return (ahoc_status)rc;
   }
   *out = h;
   return AHOC_OK;
+}
+
+ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, void* stream, ahoc_handle** out) {
+  if (!pb || !out) return AHOC_E_INVALID;
+  return setup_n(pb, 1, opt, stream, out);
 }
 
 ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* stream) {
@@ -1007,87 +1145,137 @@ ahoc_status ahoc_poisson(ahoc_handle* h, const double* gin, double* wout, void* 
 namespace ahoc {
 namespace {
 
-int solve_fp64(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+// Write the nodal U of every instance to its output (through the batch buffer for nb > 1).
+int write_u(ahoc_handle* h, const double* Ui, double* const* u, hipStream_t st) {
+  const Geom& g = h->g;
+  if (g.nb == 1) return out_u<double>(g, Ui, h->gD, u[0], st);
+  TRY(out_u<double>(g, Ui, h->gD, h->ubuf, st));
+  for (int i = 0; i < g.nb; ++i)
+    AHOC_HIP_TRY(hipMemcpyAsync(u[i], h->ubuf + (long long)i * g.nnodal, sizeof(double) * g.nnodal,
+                                hipMemcpyDeviceToDevice, st));
+  return ST_OK;
+}
+
+// Zero the segments (instances) of a batch vector whose flag in h->pinned_i is 0.
+int zero_done(ahoc_handle* h, double* x, hipStream_t st) {
+  const Geom& g = h->g;
+  for (int i = 0; i < g.nb; ++i)
+    if (!h->pinned_i[i]) TRY(fill(g.nq, 0.0, x + (long long)i * g.nq, st));
+  return ST_OK;
+}
+
+// u: one output per instance; v, q only for a single instance (nb = 1).  s: nb stats.
+int solve_fp64(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
   Prec<double>& P = h->p64;
-  GmresResult gr;
+  const Geom& g = h->g;
+  std::vector<GmresResult> gr;
   int mv = 0;
   TRY(schur_rhs<double>(h, P, h->src_v, h->src_u, h->src_q, h->bvec, st));
   TRY(gmres<double>(h, P, h->bvec, h->dq, h->opt.tol, h->opt.max_iters, gr, &mv, st));
   TRY(vsolve<double>(h, P, h->dq, h->src_v, st));
   TRY(usolve<double>(h, P, h->dq, h->src_u, st));
-  TRY(out_u<double>(h->g, P.bufB, h->gD, u, st));
-  if (v) TRY(out_v<double>(h->g, P.bufA, h->dq, h->vedge, v, st));
-  if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->dq, sizeof(double) * h->g.nq, hipMemcpyDeviceToDevice, st));
+  TRY(write_u(h, P.bufB, u, st));
+  if (v) TRY(out_v<double>(g, P.bufA, h->dq, h->vedge, v, st));
+  if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->dq, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
-  s->converged = gr.converged;
-  s->gmres_iters = gr.iters;
-  s->sweeps = 1;
-  s->matvecs = mv;
-  s->schur_relres = gr.relres;
-  s->last_update = 0;
-  return gr.converged ? ST_OK : ST_NOCONV;
+  bool all = true;
+  for (int i = 0; i < g.nb; ++i) {
+    s[i].converged = gr[i].converged;
+    s[i].gmres_iters = gr[i].iters;
+    s[i].sweeps = 1;
+    s[i].matvecs = mv;
+    s[i].schur_relres = gr[i].relres;
+    s[i].last_update = 0;
+    all = all && gr[i].converged;
+  }
+  return all ? ST_OK : ST_NOCONV;
 }
 
 // Mixed precision, refinement on the Schur system: b and the residual r = b - S_h Q are
 // FP64 (FP64 operator), each correction S_h dQ = r is solved by GMRES with the FP32
 // operator (FP64 Krylov basis, Arnoldi, Givens), Q is updated in FP64, and the final
-// recovery of V and U from Q runs in FP64.  Stops when ||r|| <= tol ||b||.
-int solve_mixed_schur(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+// recovery of V and U from Q runs in FP64.  An instance stops when ||r|| <= tol ||b||
+// (its residual is then zeroed, so later sweeps leave it alone).
+int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
   Prec<float>& P = h->p32;
   Prec<double>& D = h->p64;
   const Geom& g = h->g;
+  const int nb = g.nb;
   int rc = 0;
   TRY(schur_rhs<double>(h, D, h->src_v, h->src_u, h->src_q, h->b64, st));
-  TRY(dot_dev(h, h->b64, h->b64, g.nq, h->nrm, st));
-  const double bnorm = std::sqrt(read_scalar(h, h->nrm, st, &rc));
-  TRY(rc);
-  TRY(fill(g.nq, 0.0, h->Q64, st));
-  AHOC_HIP_TRY(hipMemcpyAsync(h->bvec, h->b64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
-  int iters = 0, mv = 0, sweeps = 0;
-  double relres = bnorm > 0 ? 1.0 : 0.0, upd = 0;
-  bool conv = !(bnorm > 0);
-  for (int sw = 0; sw < h->opt.max_sweeps && !conv; ++sw) {
-    GmresResult gr;
+  TRY(dot_dev(h, h->b64, h->b64, st, h->nrm));
+  TRY(read_vec(h, h->nrm, 2 * nb, st));
+  std::vector<double> bnorm(nb), relres(nb, 0.0);
+  std::vector<int> sweeps(nb, 0), iters(nb, 0);
+  std::vector<char> conv(nb, 0);
+  bool all = true;
+  for (int i = 0; i < nb; ++i) {
+    bnorm[i] = std::sqrt(std::max(h->pinned[2 * i], 0.0));
+    conv[i] = !(bnorm[i] > 0);
+    relres[i] = conv[i] ? 0.0 : 1.0;
+    all = all && conv[i];
+  }
+  TRY(fill(TQ(g), 0.0, h->Q64, st));
+  AHOC_HIP_TRY(hipMemcpyAsync(h->bvec, h->b64, sizeof(double) * TQ(g), hipMemcpyDeviceToDevice, st));
+  int mv = 0;
+  double upd = 0;
+  for (int sw = 0; sw < h->opt.max_sweeps && !all; ++sw) {
+    std::vector<GmresResult> gr;
     TRY(gmres<float>(h, P, h->bvec, h->dq, h->opt.inner_tol, h->opt.max_iters, gr, &mv, st));
-    iters += gr.iters;
-    TRY(axpby(g.nq, 1.0, h->dq, 1.0, h->Q64, st));
-    ++sweeps;
-    const double dn = absmax(h, h->dq, true, g.nq, st, &rc);
+    for (int i = 0; i < nb; ++i)
+      if (!conv[i]) {
+        iters[i] += gr[i].iters;
+        ++sweeps[i];
+      }
+    TRY(axpby(TQ(g), 1.0, h->dq, 1.0, h->Q64, st));
+    const double dn = absmax(h, h->dq, true, TQ(g), st, &rc);
     TRY(rc);
-    const double qn = absmax(h, h->Q64, true, g.nq, st, &rc);
+    const double qn = absmax(h, h->Q64, true, TQ(g), st, &rc);
     TRY(rc);
     upd = qn > 0 ? dn / qn : 0.0;
     // FP64 residual of the Schur system at the updated Q
     hipEvent_t er = tbegin(h, st);
     TRY(matvec<double>(h, D, h->Q64, h->bvec, st));
     ++mv;
-    TRY(axpby(g.nq, 1.0, h->b64, -1.0, h->bvec, st));
-    TRY(dot_dev(h, h->bvec, h->bvec, g.nq, h->nrm, st));
-    relres = std::sqrt(read_scalar(h, h->nrm, st, &rc)) / bnorm;
-    TRY(rc);
-    tend(h, AHOC_K_RESID, er, 8.0 * (double)g.nq * 4.0, st);
-    conv = relres <= h->opt.tol;
+    TRY(axpby(TQ(g), 1.0, h->b64, -1.0, h->bvec, st));
+    TRY(dot_dev(h, h->bvec, h->bvec, st, h->nrm));
+    TRY(read_vec(h, h->nrm, 2 * nb, st));
+    tend(h, AHOC_K_RESID, er, 8.0 * (double)TQ(g) * 4.0, st);
+    all = true;
+    for (int i = 0; i < nb; ++i) {
+      if (!conv[i]) {
+        relres[i] = std::sqrt(std::max(h->pinned[2 * i], 0.0)) / bnorm[i];
+        conv[i] = relres[i] <= h->opt.tol;
+      }
+      h->pinned_i[i] = !conv[i];
+      all = all && conv[i];
+    }
+    if (!all && nb > 1) TRY(zero_done(h, h->bvec, st));
   }
   TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
   TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
-  TRY(out_u<double>(g, D.bufB, h->gD, u, st));
+  TRY(write_u(h, D.bufB, u, st));
   if (v) TRY(out_v<double>(g, D.bufA, h->Q64, h->vedge, v, st));
   if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->Q64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
-  s->converged = conv;
-  s->gmres_iters = iters;
-  s->sweeps = sweeps;
-  s->matvecs = mv;
-  s->schur_relres = relres;
-  s->last_update = upd;
-  return conv ? ST_OK : ST_NOCONV;
+  for (int i = 0; i < nb; ++i) {
+    s[i].converged = conv[i];
+    s[i].gmres_iters = iters[i];
+    s[i].sweeps = sweeps[i];
+    s[i].matvecs = mv;
+    s[i].schur_relres = relres[i];
+    s[i].last_update = upd;
+  }
+  return all ? ST_OK : ST_NOCONV;
 }
 
 // Mixed precision, refinement on the coupled system: the FP64 residual of the whole
 // augmented system (u-, v- and q-rows) drives each sweep; the correction (Schur solve
 // and recovery) runs with the FP32 operators and is accumulated into FP64 U, V, Q.
-int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
-  if (h->opt.refine == 1) return solve_mixed_schur(h, u, v, q, s, st);
+int solve_mixed(ahoc_handle* h, double* const* uo, double* v, double* q, ahoc_stats* s, hipStream_t st) {
+  if (h->opt.refine == 1) return solve_mixed_schur(h, uo, v, q, s, st);
+  if (h->g.nb != 1) return ST_INVALID;
+  double* u = uo[0];
   Prec<float>& P = h->p32;
   const Geom& g = h->g;
   int rc = 0;
@@ -1112,9 +1300,10 @@ int solve_mixed(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* s, 
       tend(h, AHOC_K_RESID, er, 8.0 * (3.0 * g.nint + g.nnodal) + 4.0 * 2.0 * g.nint, st);
     }
     // correction: Schur solve in FP32 operators with FP64 Krylov, then recovery
-    GmresResult gr;
+    std::vector<GmresResult> grv;
     TRY(schur_rhs<float>(h, P, h->rv, su, h->rq, h->bvec, st));
-    TRY(gmres<float>(h, P, h->bvec, h->dq, h->opt.inner_tol, h->opt.max_iters, gr, &mv, st));
+    TRY(gmres<float>(h, P, h->bvec, h->dq, h->opt.inner_tol, h->opt.max_iters, grv, &mv, st));
+    const GmresResult& gr = grv[0];
     iters += gr.iters;
     relres = gr.relres;
     TRY(convert<double, float>(g.nq, h->dq, P.qT, st));
@@ -1170,8 +1359,10 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   std::memset(&local, 0, sizeof(local));
   hipStream_t st = (hipStream_t)stream;
   const auto t0 = std::chrono::steady_clock::now();
-  int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, u, v, q, &local, st)
-                                          : ahoc::solve_fp64(h, u, v, q, &local, st);
+  if (h->g.nb != 1) return AHOC_E_INVALID;
+  double* const uo[1] = {u};
+  int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, uo, v, q, &local, st)
+                                          : ahoc::solve_fp64(h, uo, v, q, &local, st);
   const auto t1 = std::chrono::steady_clock::now();
   local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (stats) *stats = local;
@@ -1220,15 +1411,69 @@ ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long l
 ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_options* opt,
                                double* const* u, ahoc_stats* stats, void* stream) {
   if (count < 0 || (count > 0 && (!probs || !u))) return AHOC_E_INVALID;
-  ahoc_status first = AHOC_OK;
+  hipStream_t st = (hipStream_t)stream;
+  // buckets of 2-D problems on the same grid run as one batch (lock-step GMRES, one launch
+  // per kernel for all instances); 3-D problems and single grids run one by one
+  std::map<std::vector<double>, std::vector<int>> buckets;
+  std::vector<int> single;
   for (int i = 0; i < count; ++i) {
+    const ahoc_problem& p = probs[i];
+    if (p.dim != 2 || !u[i]) {
+      single.push_back(i);
+      continue;
+    }
+    buckets[{(double)p.n[0], (double)p.n[1], p.lo[0], p.lo[1], p.hi[0], p.hi[1]}].push_back(i);
+  }
+  ahoc_status first = AHOC_OK;
+  auto note = [&](ahoc_status rc) {
+    if (rc != AHOC_OK && first == AHOC_OK) first = rc;
+  };
+  // instances per launch: about 64 M grid nodes (FP64 work arrays of a few GB)
+  const long long node_budget = 64LL << 20;
+  for (auto& kv : buckets) {
+    std::vector<int>& idx = kv.second;
+    if (idx.size() == 1) {
+      single.push_back(idx[0]);
+      continue;
+    }
+    const long long nodes = (long long)(probs[idx[0]].n[0] + 1) * (probs[idx[0]].n[1] + 1);
+    const int chunk = (int)std::max<long long>(1, std::min<long long>(4096, node_budget / nodes));
+    for (size_t c0 = 0; c0 < idx.size(); c0 += chunk) {
+      const int k = (int)std::min<size_t>(chunk, idx.size() - c0);
+      std::vector<ahoc_problem> sub(k);
+      std::vector<double*> uo(k);
+      std::vector<ahoc_stats> so(k);
+      for (int j = 0; j < k; ++j) {
+        sub[j] = probs[idx[c0 + j]];
+        uo[j] = u[idx[c0 + j]];
+        std::memset(&so[j], 0, sizeof(ahoc_stats));
+      }
+      const auto t0 = std::chrono::steady_clock::now();
+      ahoc_handle* h = nullptr;
+      ahoc_status rc = k > 1 ? setup_n(sub.data(), k, opt, stream, &h) : setup_n(sub.data(), 1, opt, stream, &h);
+      if (rc == AHOC_OK) {
+        rc = (ahoc_status)(h->opt.precision == AHOC_MIXED
+                               ? ahoc::solve_mixed(h, uo.data(), nullptr, nullptr, so.data(), st)
+                               : ahoc::solve_fp64(h, uo.data(), nullptr, nullptr, so.data(), st));
+        ahoc_destroy(h);
+      }
+      const auto t1 = std::chrono::steady_clock::now();
+      const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      for (int j = 0; j < k; ++j) {
+        so[j].t_solve_ms = ms;  // wall time of the whole batch (setup included)
+        if (stats) stats[idx[c0 + j]] = so[j];
+      }
+      note(rc);
+    }
+  }
+  for (int i : single) {
     ahoc_handle* h = nullptr;
     ahoc_status rc = ahoc_setup(&probs[i], opt, stream, &h);
     if (rc == AHOC_OK) {
       rc = ahoc_solve(h, u[i], nullptr, nullptr, stats ? &stats[i] : nullptr, stream);
       ahoc_destroy(h);
     }
-    if (rc != AHOC_OK && first == AHOC_OK) first = rc;
+    note(rc);
   }
   return first;
 }

@@ -32,6 +32,8 @@ struct Geom {
   long long nalloc;  // px * ni[1] * ni[2]: elements of an interior array incl. row padding
   int nq;            // augmented unknowns
   int face_off[7];   // start of each face in Q, face f = 2*axis + side
+  int nb;            // instances in a batch of equal 2-D grids (1 otherwise); every array
+                     // holds nb consecutive instances of the per-instance sizes above
 };
 
 // Weights of the compact operators, by offset class.
@@ -95,6 +97,7 @@ template <typename T> struct DstFaces {
   T* out = nullptr;
   const T* w = nullptr;  // w_lo[0..L), w_hi[0..L)
   long long plane = 0;
+  long long slab = 0;    // offset of slab o's sums: out + o * slab
   int mode = 0;
 };
 
@@ -109,6 +112,7 @@ template <typename T> struct DstFaces {
 //   wp, wa, wb                    sines of the layer next to each face along the pass axis,
 //                                 axis a and axis b: [side][k-1], halves of length L, nwa, nwb
 template <typename T> struct DstGen {
+  long long pslab = 0, aslab = 0, bslab = 0;  // per-slab offsets of lp, la, lb (outer > 1)
   const T* lp = nullptr;
   long long pplane = 0;
   const T* wp = nullptr;
@@ -125,17 +129,17 @@ template <typename T> struct DstGen {
 };
 
 template <typename T>
-int dst_gen_pass(const DstTables<T>& tb, T* out, long long inner, const DstScale<T>& sc, const DstGen<T>& gen,
-                 hipStream_t st);
+int dst_gen_pass(const DstTables<T>& tb, T* out, long long outer, long long inner, const DstScale<T>& sc,
+                 const DstGen<T>& gen, hipStream_t st);
 
 // Face contractions of a scaled spectrum W stored as planes [o][ky][kx] (row pitch px,
 // nx valid columns, ny rows, `planes` planes):
-//   fx[side][o][ky] = sum_kx W[o][ky][kx] wx[side][kx]        (every plane)
-//   fy[side][o][kx] = sum_ky W[o][ky][kx] wy[side][ky]        (when fy != null)
-// fx planes are [planes][ny], fy planes [planes][px] (padding columns written as zero).
+//   fx[side * fx_side + o * fx_plane + ky] = sum_kx W[o][ky][kx] wx[side][kx]   (every plane)
+//   fy[side][o][kx] = sum_ky W[o][ky][kx] wy[side][ky]        (when fy != null; planes [px],
+//                                                              padding columns written as zero)
 template <typename T>
 int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* wx, const T* wy, T* fx, T* fy,
-                hipStream_t st);
+                long long fx_side, long long fx_plane, hipStream_t st);
 
 // One pass of the batched DST-I along an axis of an interior array viewed as
 // [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils: `outer` rows

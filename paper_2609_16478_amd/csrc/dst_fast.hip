@@ -111,13 +111,14 @@ __global__ void __launch_bounds__((cap<T, N, FUSED, ROWP>())) k_dst_fast(Args<T>
       }
       seg_sum4<T, TPS>(la, ha, lb, hb, tot, ts);
       if (ts == 0) {
+        T* fo = a.fc.out + (blockIdx.x / a.ntile_inner) * a.fc.slab;
         if (ca < a.inner) {
-          a.fc.out[ca] = la;
-          a.fc.out[a.fc.plane + ca] = ha;
+          fo[ca] = la;
+          fo[a.fc.plane + ca] = ha;
         }
         if (cb < a.inner) {
-          a.fc.out[cb] = lb;
-          a.fc.out[a.fc.plane + cb] = hb;
+          fo[cb] = lb;
+          fo[a.fc.plane + cb] = hb;
         }
       }
     }

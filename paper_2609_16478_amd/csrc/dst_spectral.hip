@@ -35,7 +35,7 @@ template <typename T> struct GenArgs {
   T* out;
   const cx<T>* tw;
   const T* sn;
-  long long inner;
+  long long inner, ntile_inner;
   int lg_nseq;
   DstScale<T> fs;
   DstGen<T> g;
@@ -72,14 +72,18 @@ __global__ void __launch_bounds__((cap<T, N, true, false>())) k_dst_gen(GenArgs<
   const int nseq = blockDim.x / TPS;
   const int lgq = a.lg_nseq;
   const int P = 2 * nseq;
-  const long long c0 = (long long)blockIdx.x * P;
+  const long long o = blockIdx.x / a.ntile_inner;  // slab (instance of a batch)
+  const long long c0 = (blockIdx.x - o * a.ntile_inner) * (long long)P;
   const long long left = a.inner - c0;
   const int ncols = left < P ? (int)left : P;
 
   // ---- generate the scaled spectrum: item (pair q, position m), q fastest, so that a
   // thread keeps one pencil pair and the lanes of a wavefront read consecutive columns
   {
-    const DstGen<T>& g = a.g;
+    DstGen<T> g = a.g;
+    g.lp += o * g.pslab;
+    g.la += o * g.aslab;
+    if (g.lb) g.lb += o * g.bslab;
     const int q = threadIdx.x & (nseq - 1);
     const long long ca = c0 + 2 * q, cb = ca + 1;
     int iaa, iba, iab, ibb;
@@ -156,7 +160,7 @@ __global__ void __launch_bounds__((cap<T, N, true, false>())) k_dst_gen(GenArgs<
   pre_lds<T, N, PL>(seq, ts, a.sn);
   fft<T, N, PL>(seq, ts, a.tw);
   post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
-  store_tile<T, N>(lds, a.out + c0, false, nseq, lgq, ncols, (int)a.inner, 1);
+  store_tile<T, N>(lds, a.out + o * (long long)L * a.inner + c0, false, nseq, lgq, ncols, (int)a.inner, 1);
 }
 
 // Face contractions of a stored scaled spectrum, one work-group per (plane, row chunk):
@@ -166,7 +170,7 @@ template <typename T, int CPT>
 __global__ void __launch_bounds__(256) k_face_reduce(const T* __restrict__ W, long long planes, int ny, int nx,
                                                      int px, int rows_per, const T* __restrict__ wx,
                                                      const T* __restrict__ wy, T* __restrict__ fx,
-                                                     T* __restrict__ fy) {
+                                                     T* __restrict__ fy, long long fx_side, long long fx_plane) {
   __shared__ T red[2][64][4];
   const int nchunk = (ny + rows_per - 1) / rows_per;
   const long long o = blockIdx.x / nchunk;
@@ -223,7 +227,7 @@ __global__ void __launch_bounds__(256) k_face_reduce(const T* __restrict__ W, lo
       const int sd = threadIdx.x >= rn;
       const int rr = threadIdx.x - sd * rn;
       const T t = red[sd][rr][0] + red[sd][rr][1] + red[sd][rr][2] + red[sd][rr][3];
-      fx[((long long)sd * planes + o) * ny + b0 + rr] = t;
+      fx[sd * fx_side + o * fx_plane + b0 + rr] = t;
     }
     __syncthreads();
   }
@@ -245,7 +249,7 @@ template <typename F> void max_lds(F* f) {
 }
 
 template <typename T, int N>
-int gen_launch(const GenArgs<T>& a0, hipStream_t st) {
+int gen_launch(const GenArgs<T>& a0, long long outer, hipStream_t st) {
   constexpr int TPS = N / Plan<N>::PPT;
   const int nseq = dst_fast_tile(N, (int)sizeof(T), DST_PASS_FUSED);
   if (nseq <= 0) return ST_UNSUPPORTED;
@@ -256,8 +260,10 @@ int gen_launch(const GenArgs<T>& a0, hipStream_t st) {
   const int ntot = nseq * 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
   const size_t lds = (size_t)(nseq * seq_stride<N>() + ntot) * sizeof(cx<T>);
   if (lds > 160 * 1024) return ST_UNSUPPORTED;
-  const long long blocks = (a.inner + 2 * nseq - 1) / (2 * nseq);
+  a.ntile_inner = (a.inner + 2 * nseq - 1) / (2 * nseq);
+  const long long blocks = a.ntile_inner * outer;
   if (blocks <= 0) return ST_OK;
+  if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
   static std::once_flag once;
   std::call_once(once, [] { max_lds(&k_dst_gen<T, N>); });
   hipLaunchKernelGGL((k_dst_gen<T, N>), dim3((unsigned)blocks), dim3(threads), lds, st, a);
@@ -268,8 +274,8 @@ int gen_launch(const GenArgs<T>& a0, hipStream_t st) {
 }  // namespace fast
 
 template <typename T>
-int dst_gen_pass(const DstTables<T>& tb, T* out, long long inner, const DstScale<T>& sc, const DstGen<T>& gen,
-                 hipStream_t st) {
+int dst_gen_pass(const DstTables<T>& tb, T* out, long long outer, long long inner, const DstScale<T>& sc,
+                 const DstGen<T>& gen, hipStream_t st) {
   if (!dst_fast_supported(tb.N)) return ST_UNSUPPORTED;
   if ((double)(tb.N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
   fast::GenArgs<T> a;
@@ -281,25 +287,25 @@ int dst_gen_pass(const DstTables<T>& tb, T* out, long long inner, const DstScale
   a.fs = sc;
   a.g = gen;
   switch (tb.N) {
-    case 32: return fast::gen_launch<T, 32>(a, st);
-    case 64: return fast::gen_launch<T, 64>(a, st);
-    case 96: return fast::gen_launch<T, 96>(a, st);
-    case 128: return fast::gen_launch<T, 128>(a, st);
-    case 192: return fast::gen_launch<T, 192>(a, st);
-    case 256: return fast::gen_launch<T, 256>(a, st);
-    case 384: return fast::gen_launch<T, 384>(a, st);
-    case 512: return fast::gen_launch<T, 512>(a, st);
-    case 768: return fast::gen_launch<T, 768>(a, st);
-    case 1024: return fast::gen_launch<T, 1024>(a, st);
-    case 2048: return fast::gen_launch<T, 2048>(a, st);
-    case 4096: return fast::gen_launch<T, 4096>(a, st);
+    case 32: return fast::gen_launch<T, 32>(a, outer, st);
+    case 64: return fast::gen_launch<T, 64>(a, outer, st);
+    case 96: return fast::gen_launch<T, 96>(a, outer, st);
+    case 128: return fast::gen_launch<T, 128>(a, outer, st);
+    case 192: return fast::gen_launch<T, 192>(a, outer, st);
+    case 256: return fast::gen_launch<T, 256>(a, outer, st);
+    case 384: return fast::gen_launch<T, 384>(a, outer, st);
+    case 512: return fast::gen_launch<T, 512>(a, outer, st);
+    case 768: return fast::gen_launch<T, 768>(a, outer, st);
+    case 1024: return fast::gen_launch<T, 1024>(a, outer, st);
+    case 2048: return fast::gen_launch<T, 2048>(a, outer, st);
+    case 4096: return fast::gen_launch<T, 4096>(a, outer, st);
     default: return ST_UNSUPPORTED;
   }
 }
 
 template <typename T>
 int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* wx, const T* wy, T* fx, T* fy,
-                hipStream_t st) {
+                long long fx_side, long long fx_plane, hipStream_t st) {
   if (planes <= 0 || ny <= 0) return ST_OK;
   const int cpt = (px + 255) / 256;
   // whole planes when column sums are formed; otherwise split rows for enough work-groups
@@ -314,7 +320,7 @@ int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* w
   if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
 #define AHOC_FR(C)                                                                                          \
   hipLaunchKernelGGL((fast::k_face_reduce<T, C>), dim3((unsigned)blocks), dim3(256), 0, st, W, planes, ny, nx, \
-                     px, rows_per, wx, wy, fx, fy)
+                     px, rows_per, wx, wy, fx, fy, fx_side, fx_plane)
   if (cpt <= 1) AHOC_FR(1);
   else if (cpt <= 2) AHOC_FR(2);
   else if (cpt <= 4) AHOC_FR(4);
@@ -326,13 +332,13 @@ int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* w
   return ST_OK;
 }
 
-template int dst_gen_pass<float>(const DstTables<float>&, float*, long long, const DstScale<float>&,
+template int dst_gen_pass<float>(const DstTables<float>&, float*, long long, long long, const DstScale<float>&,
                                  const DstGen<float>&, hipStream_t);
-template int dst_gen_pass<double>(const DstTables<double>&, double*, long long, const DstScale<double>&,
-                                  const DstGen<double>&, hipStream_t);
+template int dst_gen_pass<double>(const DstTables<double>&, double*, long long, long long,
+                                  const DstScale<double>&, const DstGen<double>&, hipStream_t);
 template int face_reduce<float>(const float*, long long, int, int, int, const float*, const float*, float*,
-                                float*, hipStream_t);
+                                float*, long long, long long, hipStream_t);
 template int face_reduce<double>(const double*, long long, int, int, int, const double*, const double*,
-                                 double*, double*, hipStream_t);
+                                 double*, double*, long long, long long, hipStream_t);
 
 }  // namespace ahoc

@@ -55,24 +55,19 @@ int fill(long long n, double v, double* x, hipStream_t st);
 
 // krylov.hip --------------------------------------------------------------------------
 // partial dot products of nvec basis vectors (row stride ld) with w: part[v * nb + b]
-int mdot_partial(const double* V, long long ld, int nvec, const double* w, long long n,
-                 double* part, int nb, hipStream_t st);
-// out[v] (+)= sum_b part[v * nb + b]
-int mdot_reduce(const double* part, int nb, int nvec, double* out, int accumulate, hipStream_t st);
-// w += sign * sum_v coef[v] V[v]
-int maxpy(double* w, const double* V, long long ld, int nvec, const double* coef, double sign,
-          long long n, hipStream_t st);
-// Arnoldi column finish + Givens update for column j (single work-item kernel)
-int givens_step(double* H, int ldh, const double* h1, const double* h2, const double* nrm2,
-                double* cs, double* sn, double* gv, int j, double* resid, hipStream_t st);
-// y = a x + b y   (b == 0: y is overwritten without being read)
+int mdot_partial(const double* V, long long ld, int nvec, const double* w, long long n, int ns, double* part,
+                 int nbk, hipStream_t st);
+int mdot_reduce(const double* part, int nbk, int nvec, int ns, double* out, int ostride, int accumulate,
+                hipStream_t st);
+int maxpy(double* w, const double* V, long long ld, int nvec, const double* coef, int cstride, double sign,
+          long long n, int ns, hipStream_t st);
+int givens_step(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2, double* cs,
+                double* sn, double* gv, int j, double* resid, hipStream_t st);
 int axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);
-// w *= 1 / H[j+1, j]  (zero if the norm vanished)
-int scale_by_inv(double* w, long long n, const double* s, hipStream_t st);
-// y = H(0:k,0:k)^{-1} g(0:k)
-int back_solve(const double* H, int ldh, const double* gv, int k, double* y, hipStream_t st);
-// v0 = r / ||r||, g = (||r||, 0, ...)
-int start_cycle(double* v0, const double* r, long long n, const double* nrm2, double* gv, int m,
+int scale_by_inv(double* w, long long n, int ns, const double* s, const int* act, hipStream_t st);
+int back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y,
+               hipStream_t st);
+int start_cycle(double* v0, const double* r, long long n, int ns, const double* nrm2, double* gv, int m,
                 double* beta, hipStream_t st);
 
 }  // namespace ahoc

@@ -24,61 +24,88 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   return r;
 }
 
+// Every kernel works on `ns` independent segments (the instances of a batch, 1 for a
+// single problem): a vector of the Krylov basis is ns consecutive segments of length n,
+// and each segment has its own dot products, Hessenberg matrix, rotations and norms.
+// Per-segment small arrays: H [ns][m][m+1] (column j at j*(m+1)), cs, sn [ns][m],
+// gv, y, h1, h2 [ns][m+1], nrm, resid [ns][2], beta [ns], act [ns].
+
+// part[(s * nvec + v) * gridDim.x + block] = partial sum of <V_v, w> over segment s
 __global__ void k_mdot_partial(const double* __restrict__ V, long long ld, int nvec,
                                const double* __restrict__ w, long long n, double* __restrict__ part) {
   __shared__ double red[TPB];
+  const long long s0 = blockIdx.y * n;
   for (int v = 0; v < nvec; ++v) {
-    const double* x = V + (long long)v * ld;
+    const double* x = V + (long long)v * ld + s0;
+    const double* ws = w + s0;
     double acc = 0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
          e += (long long)gridDim.x * blockDim.x)
-      acc += x[e] * w[e];
-    const double s = block_sum(acc, red);
-    if (threadIdx.x == 0) part[(long long)v * gridDim.x + blockIdx.x] = s;
+      acc += x[e] * ws[e];
+    const double r = block_sum(acc, red);
+    if (threadIdx.x == 0) part[((long long)blockIdx.y * nvec + v) * gridDim.x + blockIdx.x] = r;
   }
 }
 
-__global__ void k_mdot_reduce(const double* __restrict__ part, int nb, double* __restrict__ out, int accumulate) {
+// out[s * ostride + v] (+)= sum of the partials of (segment s, vector v)
+__global__ void k_mdot_reduce(const double* __restrict__ part, int nbk, int nvec, double* __restrict__ out,
+                              int ostride, int accumulate) {
   __shared__ double red[TPB];
   const int v = blockIdx.x;
+  const long long sg = blockIdx.y;
   double acc = 0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[(long long)v * nb + b];
-  const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) out[v] = accumulate ? out[v] + s : s;
+  for (int b = threadIdx.x; b < nbk; b += blockDim.x) acc += part[(sg * nvec + v) * nbk + b];
+  const double r = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    double* o = out + sg * ostride + v;
+    *o = accumulate ? *o + r : r;
+  }
 }
 
+// w_s += sign * sum_v coef[s * cstride + v] V_v  on each segment s
 __global__ void k_maxpy(double* __restrict__ w, const double* __restrict__ V, long long ld, int nvec,
-                        const double* __restrict__ coef, double sign, long long n) {
+                        const double* __restrict__ coef, int cstride, double sign, long long n) {
+  const long long s0 = blockIdx.y * n;
+  const double* c = coef + (long long)blockIdx.y * cstride;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     double acc = 0;
-    for (int v = 0; v < nvec; ++v) acc += coef[v] * V[(long long)v * ld + e];
-    w[e] += sign * acc;
+    for (int v = 0; v < nvec; ++v) acc += c[v] * V[(long long)v * ld + s0 + e];
+    w[s0 + e] += sign * acc;
   }
 }
 
-__global__ void k_givens(double* H, int ldh, const double* h1, const double* h2, const double* nrm2,
+// one thread per segment
+__global__ void k_givens(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2,
                          double* cs, double* sn, double* gv, int j, double* resid) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* col = H + (long long)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = h1[i] + h2[i];
-  col[j + 1] = sqrt(fmax(nrm2[0], 0.0));
+  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sg >= ns) return;
+  const int ldh = m + 1;
+  double* col = H + (long long)sg * m * ldh + (long long)j * ldh;
+  const double* a1 = h1 + (long long)sg * ldh;
+  const double* a2 = h2 + (long long)sg * ldh;
+  double* c_ = cs + (long long)sg * m;
+  double* s_ = sn + (long long)sg * m;
+  double* g_ = gv + (long long)sg * ldh;
+  const double nn = sqrt(fmax(nrm2[2 * sg], 0.0));
+  for (int i = 0; i <= j; ++i) col[i] = a1[i] + a2[i];
+  col[j + 1] = nn;
   for (int i = 0; i < j; ++i) {
-    const double t = cs[i] * col[i] + sn[i] * col[i + 1];
-    col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+    const double t = c_[i] * col[i] + s_[i] * col[i + 1];
+    col[i + 1] = -s_[i] * col[i] + c_[i] * col[i + 1];
     col[i] = t;
   }
   const double a = col[j], b = col[j + 1];
   const double rho = hypot(a, b);
   const double c = rho > 0 ? a / rho : 1.0, s = rho > 0 ? b / rho : 0.0;
-  cs[j] = c;
-  sn[j] = s;
+  c_[j] = c;
+  s_[j] = s;
   col[j] = rho;
-  gv[j + 1] = -s * gv[j];
-  gv[j] = c * gv[j];
-  resid[0] = fabs(gv[j + 1]);
+  g_[j + 1] = -s * g_[j];
+  g_[j] = c * g_[j];
+  resid[2 * sg] = fabs(g_[j + 1]);
   // keep the un-rotated subdiagonal for normalising v_{j+1}
-  resid[1] = sqrt(fmax(nrm2[0], 0.0));
+  resid[2 * sg + 1] = nn;
   col[j + 1] = 0.0;
 }
 
@@ -88,34 +115,49 @@ __global__ void k_axpby(long long n, double a, const double* __restrict__ x, dou
     y[e] = b == 0.0 ? a * x[e] : a * x[e] + b * y[e];
 }
 
-__global__ void k_scale_inv(double* __restrict__ w, long long n, const double* __restrict__ s) {
-  const double d = s[1];
-  const double r = d > 0 ? 1.0 / d : 0.0;
+// w_s *= 1 / resid[s][1]; segments that are no longer active (or have a zero norm) get 0,
+// so a converged instance continues with zero basis vectors
+__global__ void k_scale_inv(double* __restrict__ w, long long n, const double* __restrict__ s,
+                            const int* __restrict__ act) {
+  const double d = s[2 * blockIdx.y + 1];
+  const double r = (d > 0 && (!act || act[blockIdx.y])) ? 1.0 / d : 0.0;
+  const long long s0 = blockIdx.y * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
-    w[e] *= r;
+    w[s0 + e] *= r;
 }
 
-__global__ void k_back_solve(const double* H, int ldh, const double* gv, int k, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// one thread per segment: y_s[0..k_s) from the rotated triangle, y_s[k_s..kmax) = 0
+__global__ void k_back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y) {
+  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sg >= ns) return;
+  const int ldh = m + 1;
+  const double* Hs = H + (long long)sg * m * ldh;
+  const double* g_ = gv + (long long)sg * ldh;
+  double* ys = y + (long long)sg * ldh;
+  const int k = kk[sg];
+  for (int i = k; i < kmax; ++i) ys[i] = 0.0;
   for (int i = k - 1; i >= 0; --i) {
-    double t = gv[i];
-    for (int c = i + 1; c < k; ++c) t -= H[(long long)c * ldh + i] * y[c];
-    y[i] = t / H[(long long)i * ldh + i];
+    double t = g_[i];
+    for (int c = i + 1; c < k; ++c) t -= Hs[(long long)c * ldh + i] * ys[c];
+    ys[i] = t / Hs[(long long)i * ldh + i];
   }
 }
 
 __global__ void k_start(double* __restrict__ v0, const double* __restrict__ r, long long n,
                         const double* __restrict__ nrm2, double* gv, int m, double* beta) {
-  const double b = sqrt(fmax(nrm2[0], 0.0));
+  const long long sg = blockIdx.y;
+  const double b = sqrt(fmax(nrm2[2 * sg], 0.0));
   const double ib = b > 0 ? 1.0 / b : 0.0;
+  const long long s0 = sg * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
-    v0[e] = r[e] * ib;
+    v0[s0 + e] = r[s0 + e] * ib;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    gv[0] = b;
-    for (int i = 1; i <= m; ++i) gv[i] = 0.0;
-    beta[0] = b;
+    double* g_ = gv + sg * (m + 1);
+    g_[0] = b;
+    for (int i = 1; i <= m; ++i) g_[i] = 0.0;
+    beta[sg] = b;
   }
 }
 
@@ -127,29 +169,30 @@ inline unsigned nblk(long long n, int cap) {
 
 }  // namespace
 
-int mdot_partial(const double* V, long long ld, int nvec, const double* w, long long n, double* part,
-                 int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_mdot_partial, dim3(nb), dim3(TPB), 0, st, V, ld, nvec, w, n, part);
+int mdot_partial(const double* V, long long ld, int nvec, const double* w, long long n, int ns, double* part,
+                 int nbk, hipStream_t st) {
+  hipLaunchKernelGGL(k_mdot_partial, dim3(nbk, ns), dim3(TPB), 0, st, V, ld, nvec, w, n, part);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 
-int mdot_reduce(const double* part, int nb, int nvec, double* out, int accumulate, hipStream_t st) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nvec), dim3(TPB), 0, st, part, nb, out, accumulate);
+int mdot_reduce(const double* part, int nbk, int nvec, int ns, double* out, int ostride, int accumulate,
+                hipStream_t st) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nvec, ns), dim3(TPB), 0, st, part, nbk, nvec, out, ostride, accumulate);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 
-int maxpy(double* w, const double* V, long long ld, int nvec, const double* coef, double sign,
-          long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_maxpy, dim3(nblk(n, 65536)), dim3(TPB), 0, st, w, V, ld, nvec, coef, sign, n);
+int maxpy(double* w, const double* V, long long ld, int nvec, const double* coef, int cstride, double sign,
+          long long n, int ns, hipStream_t st) {
+  hipLaunchKernelGGL(k_maxpy, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, w, V, ld, nvec, coef, cstride, sign, n);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 
-int givens_step(double* H, int ldh, const double* h1, const double* h2, const double* nrm2,
-                double* cs, double* sn, double* gv, int j, double* resid, hipStream_t st) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, ldh, h1, h2, nrm2, cs, sn, gv, j, resid);
+int givens_step(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2, double* cs,
+                double* sn, double* gv, int j, double* resid, hipStream_t st) {
+  hipLaunchKernelGGL(k_givens, dim3((ns + 63) / 64), dim3(64), 0, st, ns, H, m, h1, h2, nrm2, cs, sn, gv, j, resid);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
@@ -160,21 +203,22 @@ int axpby(long long n, double a, const double* x, double b, double* y, hipStream
   return ST_OK;
 }
 
-int scale_by_inv(double* w, long long n, const double* s, hipStream_t st) {
-  hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 65536)), dim3(TPB), 0, st, w, n, s);
+int scale_by_inv(double* w, long long n, int ns, const double* s, const int* act, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, w, n, s, act);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 
-int back_solve(const double* H, int ldh, const double* gv, int k, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_back_solve, dim3(1), dim3(64), 0, st, H, ldh, gv, k, y);
+int back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y,
+               hipStream_t st) {
+  hipLaunchKernelGGL(k_back_solve, dim3((ns + 63) / 64), dim3(64), 0, st, ns, H, m, gv, kk, kmax, y);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 
-int start_cycle(double* v0, const double* r, long long n, const double* nrm2, double* gv, int m,
+int start_cycle(double* v0, const double* r, long long n, int ns, const double* nrm2, double* gv, int m,
                 double* beta, hipStream_t st) {
-  hipLaunchKernelGGL(k_start, dim3(nblk(n, 65536)), dim3(TPB), 0, st, v0, r, n, nrm2, gv, m, beta);
+  hipLaunchKernelGGL(k_start, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, v0, r, n, nrm2, gv, m, beta);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }

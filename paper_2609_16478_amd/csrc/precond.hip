@@ -113,9 +113,11 @@ __global__ void k_symbol(SymArgs A) {
   }
 }
 
-// In place on face spectra: (lo, hi) <- (p lo + q hi, q lo + p hi) for every low-face entry.
+// In place on face spectra: (lo, hi) <- (p lo + q hi, q lo + p hi) for every low-face entry
+// of every instance (the coefficients are shared by the instances of a batch).
 template <typename T, int DIM>
 __global__ void k_modes(Geom g, const T* __restrict__ pc, const T* __restrict__ qc, T* __restrict__ x) {
+  x += (long long)blockIdx.y * g.nq;  // instance of a batch (gridDim.y = g.nb)
   long long tot = 0;
   for (int a = 0; a < DIM; ++a) tot += g.face_off[2 * a + 1] - g.face_off[2 * a];
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
@@ -158,8 +160,8 @@ int precond_symbol(const Geom& g, const Weights& w, const double* const* tabs, d
 template <typename T>
 int precond_modes(const Geom& g, const T* pc, const T* qc, T* x, hipStream_t st) {
   const long long tot = g.nq / 2;
-  if (g.dim == 3) hipLaunchKernelGGL((k_modes<T, 3>), dim3(nblk(tot)), dim3(TPB), 0, st, g, pc, qc, x);
-  else hipLaunchKernelGGL((k_modes<T, 2>), dim3(nblk(tot)), dim3(TPB), 0, st, g, pc, qc, x);
+  if (g.dim == 3) hipLaunchKernelGGL((k_modes<T, 3>), dim3(nblk(tot), g.nb), dim3(TPB), 0, st, g, pc, qc, x);
+  else hipLaunchKernelGGL((k_modes<T, 2>), dim3(nblk(tot), g.nb), dim3(TPB), 0, st, g, pc, qc, x);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }

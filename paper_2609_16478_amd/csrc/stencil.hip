@@ -101,6 +101,10 @@ template <int DIM> __device__ __forceinline__ double lw(const Weights& w, int dx
 template <typename T, int DIM>
 __global__ void k_lift(Geom g, Weights w, const T* __restrict__ Q, const T* __restrict__ src,
                        T* __restrict__ G) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  Q += b_ * g.nq;
+  if (src) src += b_ * g.nalloc;
+  G += b_ * g.nalloc;
   // rows (j, k) across work-groups, x across threads (32-bit row decode)
   const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
   for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
@@ -134,6 +138,12 @@ __global__ void k_lift(Geom g, Weights w, const T* __restrict__ Q, const T* __re
 template <typename T, int DIM>
 __global__ void k_rhs_u(Geom g, Weights w, const T* __restrict__ V, const T* __restrict__ Q,
                         const T* __restrict__ ia, const T* __restrict__ src, T* __restrict__ G) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  V += b_ * g.nalloc;
+  Q += b_ * g.nq;
+  ia += b_ * g.nnodal;
+  if (src) src += b_ * g.nalloc;
+  G += b_ * g.nalloc;
   const T m0 = (T)w.m0, m1 = (T)w.m1;
   const int nrow = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
   for (int r = blockIdx.x; r < nrow; r += gridDim.x) {
@@ -167,6 +177,12 @@ __global__ void k_rhs_u(Geom g, Weights w, const T* __restrict__ V, const T* __r
 template <typename T, int DIM>
 __global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __restrict__ Q,
                          const T* __restrict__ af, const T* __restrict__ srcq, double* __restrict__ R) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  U += b_ * g.nalloc;
+  Q += b_ * g.nq;
+  af += b_ * g.nq;
+  if (srcq) srcq += b_ * g.nq;
+  R += b_ * g.nq;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
     int i, j, k, ax, st;
     dec_q<DIM>(g, q, i, j, k, ax, st);
@@ -226,6 +242,11 @@ __device__ __forceinline__ void face_node(const Geom& g, int f, long long t, int
 template <typename T, int DIM>
 __global__ void k_face_lift(Geom g, Weights w, const T* __restrict__ Q, T* __restrict__ Lx, T* __restrict__ Ly,
                             T* __restrict__ Lz, long long px_plane, long long py_plane, long long pz_plane) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  Q += b_ * g.nq;
+  Lx += b_ * 2 * px_plane;
+  Ly += b_ * 2 * py_plane;
+  if (Lz) Lz += b_ * 2 * pz_plane;
   const long long tot = 2 * (px_plane + py_plane + (DIM == 3 ? pz_plane : 0));
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
        e += (long long)gridDim.x * blockDim.x) {
@@ -293,6 +314,14 @@ __global__ void k_gather_faces(Geom g, const T* __restrict__ Fx, const T* __rest
   const long long px_plane = DIM == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1];
   const long long py_plane = DIM == 3 ? (long long)g.px * g.ni[2] : g.px;
   const long long pz_plane = (long long)g.px * g.ni[1];
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  Fx += b_ * 2 * px_plane;
+  Fy += b_ * 2 * py_plane;
+  if (DIM == 3) Fz += b_ * 2 * pz_plane;
+  Q += b_ * g.nq;
+  af += b_ * g.nq;
+  if (srcq) srcq += b_ * g.nq;
+  R += b_ * g.nq;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
     int i, j, k, ax, st;
     dec_q<DIM>(g, q, i, j, k, ax, st);
@@ -407,6 +436,10 @@ __global__ void k_inv_alpha(long long n, const double* __restrict__ alpha, doubl
 template <int DIM>
 __global__ void k_face_alpha(Geom g, const double* __restrict__ alpha, double* __restrict__ af64,
                              float* __restrict__ af32) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  alpha += b_ * g.nnodal;
+  af64 += b_ * g.nq;
+  if (af32) af32 += b_ * g.nq;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
     int i, j, k, ax, st;
     dec_q<DIM>(g, q, i, j, k, ax, st);
@@ -422,6 +455,13 @@ template <int DIM>
 __global__ void k_src_vol(Geom g, Weights w, const double* __restrict__ f, const double* __restrict__ alpha,
                           const double* __restrict__ gD, const double* __restrict__ lapgD,
                           double* __restrict__ src_v, double* __restrict__ src_u) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  f += b_ * g.nnodal;
+  alpha += b_ * g.nnodal;
+  if (gD) gD += b_ * g.nnodal;
+  if (lapgD) lapgD += b_ * g.nnodal;
+  src_v += b_ * g.nalloc;
+  if (src_u) src_u += b_ * g.nalloc;
   // rows (j, k) across work-groups, x across threads (32-bit row decode)
   const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
   for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
@@ -463,6 +503,12 @@ template <int DIM>
 __global__ void k_src_q(Geom g, Weights w, const double* __restrict__ alpha, const double* __restrict__ gD,
                         const double* __restrict__ gN, const double* __restrict__ lapgD,
                         double* __restrict__ src_q) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  alpha += b_ * g.nnodal;
+  if (gD) gD += b_ * g.nnodal;
+  if (gN) gN += b_ * g.nnodal;
+  if (lapgD) lapgD += b_ * g.nnodal;
+  src_q += b_ * g.nq;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
     int i, j, k, ax, st;
     dec_q<DIM>(g, q, i, j, k, ax, st);
@@ -479,6 +525,10 @@ __global__ void k_src_q(Geom g, Weights w, const double* __restrict__ alpha, con
 // nodal outputs
 template <typename T, int DIM>
 __global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restrict__ gD, double* __restrict__ u) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  Ui += b_ * g.nalloc;
+  if (gD) gD += b_ * g.nnodal;
+  u += b_ * g.nnodal;
   // nodal rows (j, k) across work-groups, x across threads
   const int nrow_ = g.nn[1] * (DIM == 3 ? g.nn[2] : 1);
   for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
@@ -494,6 +544,11 @@ __global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restri
 template <typename T, int DIM>
 __global__ void k_out_v(Geom g, const T* __restrict__ Vi, const double* __restrict__ Q,
                         const double* __restrict__ vedge, double* __restrict__ v) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  Vi += b_ * g.nalloc;
+  Q += b_ * g.nq;
+  if (vedge) vedge += b_ * g.nnodal;
+  v += b_ * g.nnodal;
   // nodal rows (j, k) across work-groups, x across threads
   const int nrow_ = g.nn[1] * (DIM == 3 ? g.nn[2] : 1);
   for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
@@ -587,7 +642,7 @@ __global__ void k_fill(long long n, double v, double* __restrict__ x) {
 
 template <typename T>
 int lift(const Geom& g, const Weights& w, const T* Q, const T* src, T* G, hipStream_t st) {
-  LAUNCH_TDIM(k_lift, T, dim3(interior_rows(g)), g, w, Q, src, G);
+  LAUNCH_TDIM(k_lift, T, dim3(interior_rows(g), g.nb), g, w, Q, src, G);
   return ST_OK;
 }
 
@@ -595,14 +650,14 @@ template <typename T>
 int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
           hipStream_t st) {
   const int nrow = g.dim == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
-  LAUNCH_TDIM(k_rhs_u, T, dim3((unsigned)(nrow < 1 ? 1 : nrow)), g, w, V, Q, ia, src, G);
+  LAUNCH_TDIM(k_rhs_u, T, dim3((unsigned)(nrow < 1 ? 1 : nrow), g.nb), g, w, V, Q, ia, src, G);
   return ST_OK;
 }
 
 template <typename T>
 int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af, const T* srcq,
            double* R, hipStream_t st) {
-  LAUNCH_TDIM(k_gather, T, dim3(nblocks(g.nq)), g, w, U, Q, af, srcq, R);
+  LAUNCH_TDIM(k_gather, T, dim3(nblocks(g.nq), g.nb), g, w, U, Q, af, srcq, R);
   return ST_OK;
 }
 
@@ -612,7 +667,7 @@ int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, 
   const long long pyp = g.dim == 3 ? (long long)g.px * g.ni[2] : g.px;
   const long long pzp = g.dim == 3 ? (long long)g.px * g.ni[1] : 0;
   const long long tot = 2 * (pxp + pyp + pzp);
-  LAUNCH_TDIM(k_face_lift, T, dim3(nblocks(tot)), g, w, Q, Lx, Ly, Lz, pxp, pyp, pzp);
+  LAUNCH_TDIM(k_face_lift, T, dim3(nblocks(tot), g.nb), g, w, Q, Lx, Ly, Lz, pxp, pyp, pzp);
   return ST_OK;
 }
 
@@ -626,7 +681,7 @@ int partial_sum(long long n, int count, long long stride, const T* in, T* out, h
 template <typename T>
 int gather_faces(const Geom& g, const T* Fx, const T* Fy, const T* Fz, const T* Q, const T* af,
                  const T* srcq, double* R, hipStream_t st) {
-  LAUNCH_TDIM(k_gather_faces, T, dim3(nblocks(g.nq)), g, Fx, Fy, Fz, Q, af, srcq, R);
+  LAUNCH_TDIM(k_gather_faces, T, dim3(nblocks(g.nq), g.nb), g, Fx, Fy, Fz, Q, af, srcq, R);
   return ST_OK;
 }
 
@@ -647,27 +702,27 @@ int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32,
 }
 
 int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st) {
-  LAUNCH_DIM(k_face_alpha, dim3(nblocks(g.nq)), g, alpha, af64, af32);
+  LAUNCH_DIM(k_face_alpha, dim3(nblocks(g.nq), g.nb), g, alpha, af64, af32);
   return ST_OK;
 }
 
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
                   const double* gD, const double* gN, const double* lapgD, double* src_v,
                   double* src_u, double* src_q, hipStream_t st) {
-  LAUNCH_DIM(k_src_vol, dim3(interior_rows(g)), g, w, f, alpha, gD, lapgD, src_v, src_u);
-  LAUNCH_DIM(k_src_q, dim3(nblocks(g.nq)), g, w, alpha, gD, gN, lapgD, src_q);
+  LAUNCH_DIM(k_src_vol, dim3(interior_rows(g), g.nb), g, w, f, alpha, gD, lapgD, src_v, src_u);
+  LAUNCH_DIM(k_src_q, dim3(nblocks(g.nq), g.nb), g, w, alpha, gD, gN, lapgD, src_q);
   return ST_OK;
 }
 
 template <typename T>
 int out_u(const Geom& g, const T* Ui, const double* gD, double* u, hipStream_t st) {
-  LAUNCH_TDIM(k_out_u, T, dim3(nodal_rows(g)), g, Ui, gD, u);
+  LAUNCH_TDIM(k_out_u, T, dim3(nodal_rows(g), g.nb), g, Ui, gD, u);
   return ST_OK;
 }
 
 template <typename T>
 int out_v(const Geom& g, const T* Vi, const double* Q, const double* vedge, double* v, hipStream_t st) {
-  LAUNCH_TDIM(k_out_v, T, dim3(nodal_rows(g)), g, Vi, Q, vedge, v);
+  LAUNCH_TDIM(k_out_v, T, dim3(nodal_rows(g), g.nb), g, Vi, Q, vedge, v);
   return ST_OK;
 }
 

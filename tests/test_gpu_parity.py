@@ -228,14 +228,53 @@ def test_fast_tier_parity_at_larger_n(ah):
     assert _rel(u.cpu().numpy(), Uf) < 1e-11
 
 
+def _batch_problems():
+    """Uneven batch: several 2-D grids (some repeated, so they run as one batched launch,
+    one with its own aspect ratio), different coefficients, data and a 3-D instance."""
+    specs = W.config4_specs(6, seed=0)
+    probs = [W.config4_instance(sp) for sp in specs]
+    for sp in specs[:3]:  # the same grids again with other coefficients
+        sp = dict(sp, c=0.5 * sp["c"] + 0.1, k=sp["k"] * 0.7)
+        probs.append(W.config4_instance(sp))
+    probs.append(W.manufactured("1 + 0.5*sin(2*pi*x)*cos(2*pi*y)", "sin(pi*x)**2*sin(pi*y)**2",
+                                (32, 24), (0.0, 0.0), (1.0, 0.75)))
+    probs.append(W.manufactured("1 + 0.5*sin(2*pi*x)*cos(2*pi*y)", "x**2*y**2*(1-x)**2*(1-y)**2*exp(x)",
+                                (32, 24), (0.0, 0.0), (1.0, 0.75)))
+    probs.append(W.config3(12))
+    probs.append(W.cavity(32))
+    probs.append(W.cavity(32))
+    return probs
+
+
 def test_batched_matches_single(ah):
-    probs = [W.config4_instance(sp) for sp in W.config4_specs(4, seed=0)]
+    probs = _batch_problems()
     outs, stats, rc = ah.solve_batched(probs, tol=1e-13)
     assert rc == ah.OK
-    for pb, u in zip(probs, outs):
+    for pb, u, st in zip(probs, outs, stats):
+        assert st.converged
         with ah.Solver(pb, tol=1e-13) as s:
             u1, *_ = s.solve()
-        assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < 1e-12
+        assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < 1e-12, pb.name
+
+
+def test_batched_mixed_matches_fp64(ah):
+    probs = _batch_problems()
+    outs64, _, rc = ah.solve_batched(probs, tol=1e-13)
+    assert rc == ah.OK
+    outs, stats, rc = ah.solve_batched(probs, precision=ah.MIXED, tol=1e-11)
+    assert rc == ah.OK
+    for pb, u, u64, st in zip(probs, outs, outs64, stats):
+        assert st.converged and st.sweeps >= 2, (pb.name, st)
+        assert _rel(u.cpu().numpy(), u64.cpu().numpy()) <= 1e-10, (pb.name, st)
+
+
+def test_batched_matches_direct(ah):
+    probs = [W.config2(32), W.config2(32), W.cavity(32), W.plate(32), W.poly_exact(32, 2)]
+    outs, stats, rc = ah.solve_batched(probs, tol=1e-14)
+    assert rc == ah.OK
+    for pb, u in zip(probs, outs):
+        U, V, Q, asm = direct.solve(pb)
+        assert _rel(u.cpu().numpy(), U) < 1e-12, pb.name
 
 
 # ------------------------------------------------------------------------------------------
