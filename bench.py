@@ -82,6 +82,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=80)
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-10,
                     help="relative Schur residual both forms solve to (FP64 GMRES tolerance and the "
                          "mixed form's refinement stop)")
@@ -194,6 +196,33 @@ def main():
                    "GBps": (v[2] / (v[0] / v[1] / 1e3) / 1e9 if v[1] and v[0] > 0 else None)}
                for k, v in kt.items() if v[1]}
 
+    # batched form: the 512-instance uneven 2-D workload, whole batch per step, both forms to
+    # the same tolerance, errors against a tight FP64 batch solve
+    batched = None
+    if not args.no_batch:
+        specs = W.config4_specs(args.batch_count)
+        bprobs = [W.config4_instance(sp, xp="torch", device=dev, with_exact=False) for sp in specs]
+        bdof = sum(sp["n"] ** 2 for sp in specs)
+        ref_b, _, _ = ah.solve_batched(bprobs, tol=1e-13)
+        bres = {}
+        for name, prec in (("mixed", ah.MIXED), ("fp64", ah.FP64)):
+            ah.solve_batched(bprobs, precision=prec, tol=args.tol)  # warm-up
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                outs, bst, rcb = ah.solve_batched(bprobs, precision=prec, tol=args.tol)
+            torch.cuda.synchronize()
+            dtb = (time.perf_counter() - t) / args.steps
+            err = max(((o - r).abs().max() / r.abs().max()).item() for o, r in zip(outs, ref_b))
+            bres[name] = {"ms_per_batch": dtb * 1e3, "dof_per_s": bdof / dtb, "max_rel_err_vs_fp64_ref": err,
+                          "mean_gmres_iters": sum(x.gmres_iters for x in bst) / len(bst),
+                          "all_converged": all(x.converged for x in bst)}
+            print(f"[bench] batched {name}: {dtb*1e3:.1f} ms per batch of {len(bprobs)}", file=sys.stderr, flush=True)
+        batched = {"workload": f"{len(bprobs)} uneven 2-D instances n in {{64..512}} (alpha=1+c sin(2pi p x)cos(2pi q y), "
+                               f"u=sin^2 sin^2 cos(k(x+y)), seeded draws), DOF {bdof}",
+                   **bres, "speedup_mixed_over_fp64": bres["fp64"]["ms_per_batch"] / bres["mixed"]["ms_per_batch"]}
+        del bprobs, ref_b
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_n)
@@ -220,7 +249,7 @@ def main():
                    "gmres_iters": st.gmres_iters, "sweeps": st.sweeps, "schur_relres": st.schur_relres,
                    "rel_err_vs_fp64_ref": err_mx_ref, "rel_err_vs_exact": err_mx_exact,
                    "fp64_ref": {"tol": 1e-13, "gmres_iters": st_ref.gmres_iters},
-                   "fp64": result_fp64, "fp32_matvec_kernels": kernels},
+                   "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_dst_fast<float,{n},false,0,false> (FP32 DST-I pass along y, strided pencils)",

@@ -45,7 +45,7 @@ template <typename T> struct Prec {
   T* zq = nullptr;    // N_q zeros
   T* wf[3] = {nullptr, nullptr, nullptr};  // per axis: one-sided face weights w_lo(k), w_hi(k)
   T* wl[3] = {nullptr, nullptr, nullptr};  // per axis: layer sines sin(pi k/N), (-1)^(k+1) sin(pi k/N)
-  // face arrays (lift layers / face sums): 3-D x faces [2][n_z'][n_y'], y faces [2][n_z'][px],
+  // face arrays (lift layers / face sums): 3-D x faces [2][n_y'][n_z'], y faces [2][n_z'][px],
   // z faces [2][n_y'][px]; 2-D x faces [2][n_y'], y faces [2][px]
   T* Fx = nullptr;
   T* Fy = nullptr;
@@ -396,8 +396,8 @@ template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) 
   if (g.dim == 3) {
     TRY(dst_pass<T>(P.tb[0], P.Fz, P.Fz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
     TRY(dst_pass<T>(P.tb[1], P.Fz, P.Fz, 2, g.px, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[2], P.Fx, P.Fx, 2, g.ni[1], g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], P.Fx, P.Fx, 2LL * g.ni[1], 1, g.ni[2], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2, g.ni[2], g.ni[2], nullptr, 0, st));
     TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
     TRY(dst_pass<T>(P.tb[2], P.Fy, P.Fy, 2, g.px, g.px, nullptr, 0, st));
   } else {
@@ -428,7 +428,8 @@ template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hi
     gen.pplane = (long long)g.px * g.ni[1];
     gen.wp = P.wl[2];
     gen.aplane = (long long)g.ni[1] * g.ni[2];
-    gen.apitch = g.ni[1];
+    gen.apitch = 1;
+    gen.arow = g.ni[2];
     gen.lb = P.Fy;
     gen.bplane = (long long)g.px * g.ni[2];
     gen.bpitch = g.px;
@@ -491,7 +492,7 @@ template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, co
     TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fp));
     hipEvent_t er = tbegin(h, st);
     TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
-                       (long long)g.ni[2] * g.ni[1], g.ni[1], st));
+                       (long long)g.ni[2] * g.ni[1], 1, g.ni[2], st));
     tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
   } else {
     fp.out = P.Fy;
@@ -502,7 +503,7 @@ template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, co
     TRY(run(AHOC_K_DST_FUSED, P.tb[1], g.nb, g.px, &P.scU, P.tile[1], &fp));
     hipEvent_t er = tbegin(h, st);
     TRY(face_reduce<T>(buf, g.nb, g.ni[1], g.ni[0], g.px, P.wf[0], nullptr, P.Fx, nullptr, g.ni[1],
-                       2LL * g.ni[1], st));
+                       2LL * g.ni[1], 1, st));
     tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * g.nb * sizeof(T), st);
   }
   hipEvent_t ef = tbegin(h, st);

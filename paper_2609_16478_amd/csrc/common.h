@@ -105,8 +105,8 @@ template <typename T> struct DstFaces {
 // spectrum of the face-layer right-hand side from 2-D face spectra.  Layouts, with
 // L = N-1 along the pass axis, side 0 = low face, 1 = high face:
 //   lp [side][col]                faces normal to the pass axis (plane pplane)
-//   la [side][m-1][ib]            faces normal to the fastest axis a (plane aplane, row
-//                                 pitch apitch; 2-D: ib = 0)
+//   la [side] at ib * arow + (m-1) * apitch   faces normal to the fastest axis a (plane
+//                                 aplane; 2-D: ib = 0)
 //   lb [side][m-1][ia]            faces normal to the middle axis b, 3-D only (plane
 //                                 bplane, row pitch bpitch)
 //   wp, wa, wb                    sines of the layer next to each face along the pass axis,
@@ -119,6 +119,7 @@ template <typename T> struct DstGen {
   const T* la = nullptr;
   long long aplane = 0;
   int apitch = 0;
+  int arow = 1;
   const T* wa = nullptr;
   int nwa = 0;
   const T* lb = nullptr;
@@ -134,12 +135,12 @@ int dst_gen_pass(const DstTables<T>& tb, T* out, long long outer, long long inne
 
 // Face contractions of a scaled spectrum W stored as planes [o][ky][kx] (row pitch px,
 // nx valid columns, ny rows, `planes` planes):
-//   fx[side * fx_side + o * fx_plane + ky] = sum_kx W[o][ky][kx] wx[side][kx]   (every plane)
+//   fx[side * fx_side + o * fx_plane + ky * fx_row] = sum_kx W[o][ky][kx] wx[side][kx]
 //   fy[side][o][kx] = sum_ky W[o][ky][kx] wy[side][ky]        (when fy != null; planes [px],
 //                                                              padding columns written as zero)
 template <typename T>
 int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* wx, const T* wy, T* fx, T* fy,
-                long long fx_side, long long fx_plane, hipStream_t st);
+                long long fx_side, long long fx_plane, long long fx_row, hipStream_t st);
 
 // One pass of the batched DST-I along an axis of an interior array viewed as
 // [outer][L][inner] (L = N-1).  inner == 1 means contiguous pencils: `outer` rows

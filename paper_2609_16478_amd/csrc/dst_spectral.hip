@@ -94,8 +94,8 @@ __global__ void __launch_bounds__((cap<T, N, true, false>())) k_dst_gen(GenArgs<
     const T plb = vb ? g.lp[cb] : T(0), phb = vb ? g.lp[g.pplane + cb] : T(0);
     const T wla = va ? g.wa[iaa] : T(0), wha = va ? g.wa[g.nwa + iaa] : T(0);
     const T wlb = vb ? g.wa[iab] : T(0), whb = vb ? g.wa[g.nwa + iab] : T(0);
-    const T* ra = g.la + (va ? iba : 0);
-    const T* rb = g.la + (vb ? ibb : 0);
+    const T* ra = g.la + (long long)(va ? iba : 0) * g.arow;
+    const T* rb = g.la + (long long)(vb ? ibb : 0) * g.arow;
     T bla = 0, bha = 0, blb = 0, bhb = 0;
     const T *sa = g.la, *sb = g.la;
     if (g.lb) {
@@ -170,7 +170,8 @@ template <typename T, int CPT>
 __global__ void __launch_bounds__(256) k_face_reduce(const T* __restrict__ W, long long planes, int ny, int nx,
                                                      int px, int rows_per, const T* __restrict__ wx,
                                                      const T* __restrict__ wy, T* __restrict__ fx,
-                                                     T* __restrict__ fy, long long fx_side, long long fx_plane) {
+                                                     T* __restrict__ fy, long long fx_side, long long fx_plane,
+                                                     long long fx_row) {
   __shared__ T red[2][64][4];
   const int nchunk = (ny + rows_per - 1) / rows_per;
   const long long o = blockIdx.x / nchunk;
@@ -227,7 +228,7 @@ __global__ void __launch_bounds__(256) k_face_reduce(const T* __restrict__ W, lo
       const int sd = threadIdx.x >= rn;
       const int rr = threadIdx.x - sd * rn;
       const T t = red[sd][rr][0] + red[sd][rr][1] + red[sd][rr][2] + red[sd][rr][3];
-      fx[sd * fx_side + o * fx_plane + b0 + rr] = t;
+      fx[sd * fx_side + o * fx_plane + (b0 + rr) * fx_row] = t;
     }
     __syncthreads();
   }
@@ -305,7 +306,7 @@ int dst_gen_pass(const DstTables<T>& tb, T* out, long long outer, long long inne
 
 template <typename T>
 int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* wx, const T* wy, T* fx, T* fy,
-                long long fx_side, long long fx_plane, hipStream_t st) {
+                long long fx_side, long long fx_plane, long long fx_row, hipStream_t st) {
   if (planes <= 0 || ny <= 0) return ST_OK;
   const int cpt = (px + 255) / 256;
   // whole planes when column sums are formed; otherwise split rows for enough work-groups
@@ -320,7 +321,7 @@ int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* w
   if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
 #define AHOC_FR(C)                                                                                          \
   hipLaunchKernelGGL((fast::k_face_reduce<T, C>), dim3((unsigned)blocks), dim3(256), 0, st, W, planes, ny, nx, \
-                     px, rows_per, wx, wy, fx, fy, fx_side, fx_plane)
+                     px, rows_per, wx, wy, fx, fy, fx_side, fx_plane, fx_row)
   if (cpt <= 1) AHOC_FR(1);
   else if (cpt <= 2) AHOC_FR(2);
   else if (cpt <= 4) AHOC_FR(4);
@@ -337,8 +338,8 @@ template int dst_gen_pass<float>(const DstTables<float>&, float*, long long, lon
 template int dst_gen_pass<double>(const DstTables<double>&, double*, long long, long long,
                                   const DstScale<double>&, const DstGen<double>&, hipStream_t);
 template int face_reduce<float>(const float*, long long, int, int, int, const float*, const float*, float*,
-                                float*, long long, long long, hipStream_t);
+                                float*, long long, long long, long long, hipStream_t);
 template int face_reduce<double>(const double*, long long, int, int, int, const double*, const double*,
-                                 double*, double*, long long, long long, hipStream_t);
+                                 double*, double*, long long, long long, long long, hipStream_t);
 
 }  // namespace ahoc

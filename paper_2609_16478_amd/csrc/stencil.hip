@@ -174,6 +174,160 @@ __global__ void k_rhs_u(Geom g, Weights w, const T* __restrict__ V, const T* __r
   }
 }
 
+// 3-D rhs_u, one work-group per interior row (j, k).  Every neighbour row of the row is
+// contiguous in x whether it is interior V or a face of Q (y faces are [k][i], z faces
+// [j][i]), and so are the rows of nodal 1/alpha; the x faces contribute one value at each
+// end.  Row pointers are resolved once per row, so an element costs its loads and FMAs.
+template <typename T>
+__global__ void k_rhs_u3(Geom g, Weights w, const T* __restrict__ V, const T* __restrict__ Q,
+                         const T* __restrict__ ia, const T* __restrict__ src, T* __restrict__ G) {
+  const T m0 = (T)w.m0, m1 = (T)w.m1;
+  const int ni0 = g.ni[0], ni1 = g.ni[1], ni2 = g.ni[2];
+  const long long plane = (long long)ni1 * g.px;
+  const long long nplane = (long long)g.nn[0] * g.nn[1];
+  const int nrow = ni1 * ni2;
+  // Work-groups are dealt to the 8 XCDs in turn; give each XCD a contiguous range of rows
+  // (in order) so that a row's j-neighbours are read through the same L2.
+  const int per = (nrow + 7) / 8;
+  const int r = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (r < nrow) {
+    const int j = r % ni1 + 1, k = r / ni1 + 1;
+    const long long e0 = (long long)r * g.px;
+    // neighbour rows of V (or Q on a face), indexed by i - 1
+    const T* vc = V + e0;
+    const T* vjm = j > 1 ? vc - g.px : Q + g.face_off[2] + (long long)(k - 1) * ni0;
+    const T* vjp = j < ni1 ? vc + g.px : Q + g.face_off[3] + (long long)(k - 1) * ni0;
+    const T* vkm = k > 1 ? vc - plane : Q + g.face_off[4] + (long long)(j - 1) * ni0;
+    const T* vkp = k < ni2 ? vc + plane : Q + g.face_off[5] + (long long)(j - 1) * ni0;
+    // rows of nodal 1/alpha, indexed by i
+    const T* ac = ia + nod(g, 0, j, k);
+    const T* ajm = ac - g.nn[0];
+    const T* ajp = ac + g.nn[0];
+    const T* akm = ac - nplane;
+    const T* akp = ac + nplane;
+    // x faces: one node at each end of the row
+    const T wl = Q[g.face_off[0] + (long long)(k - 1) * ni1 + (j - 1)] * ac[0];
+    const T wr = Q[g.face_off[1] + (long long)(k - 1) * ni1 + (j - 1)] * ac[g.n[0]];
+    for (int c = threadIdx.x; c < g.px; c += blockDim.x) {
+      const long long e = e0 + c;
+      if (c >= ni0) {
+        G[e] = T(0);
+        continue;
+      }
+      const int i = c + 1;
+      const T left = c > 0 ? vc[c - 1] * ac[i - 1] : wl;
+      const T right = c + 1 < ni0 ? vc[c + 1] * ac[i + 1] : wr;
+      T nb = vjm[c] * ajm[i] + vjp[c] * ajp[i];
+      nb += vkm[c] * akm[i] + vkp[c] * akp[i];
+      nb += left + right;
+      T acc = m0 * vc[c] * ac[i] + m1 * nb;
+      if (src) acc += src[e];
+      G[e] = acc;
+    }
+  }
+}
+
+// 3-D rhs_u marching along z: a work-group owns the x-row of one j over a chunk of planes,
+// a thread CPT columns of it.  W = V / alpha of its own row at planes k-1, k, k+1 stays in
+// registers (each V and 1/alpha value of the row is read once), the x-neighbours come
+// from an LDS copy of the row (with the two x-face values at its ends), and the rows
+// j-1, j+1 are read at plane k; work-groups are ordered so that those belong to
+// neighbouring work-groups of the same XCD, which read them at about the same time.
+template <typename T>
+__device__ __forceinline__ const T* zm_row(const Geom& g, const T* V, const T* Q, int j, int k, bool& face) {
+  // V row (j, k) of the interior, or the row of the face that (j, k) lies on; indexed by i - 1
+  face = false;
+  if (j == 0 || j == g.n[1]) {
+    face = true;
+    return Q + g.face_off[j == 0 ? 2 : 3] + (long long)(k - 1) * g.ni[0];
+  }
+  if (k == 0 || k == g.n[2]) {
+    face = true;
+    return Q + g.face_off[k == 0 ? 4 : 5] + (long long)(j - 1) * g.ni[0];
+  }
+  return V + ((long long)(k - 1) * g.ni[1] + (j - 1)) * g.px;
+}
+
+template <typename T, int CPT>
+__global__ void __launch_bounds__(256) k_rhs_u_zm(Geom g, Weights w, const T* __restrict__ V, const T* __restrict__ Q,
+                                                  const T* __restrict__ ia, const T* __restrict__ src,
+                                                  T* __restrict__ G, int kchunk) {
+  __shared__ T row[CPT * 256 + 2];
+  const T m0 = (T)w.m0, m1 = (T)w.m1;
+  const int ni0 = g.ni[0], ni1 = g.ni[1], ni2 = g.ni[2];
+  const int nkc = (ni2 + kchunk - 1) / kchunk;
+  const int total = ni1 * nkc;
+  const int per = (total + 7) / 8;
+  const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (idx >= total) return;
+  const int kc = idx / ni1, j = idx % ni1 + 1;
+  const int k0 = kc * kchunk + 1, k1 = min(ni2, k0 + kchunk - 1);
+  const long long nrowa = g.nn[0];  // nodal row length
+  auto arow = [&](int jj, int kk) { return ia + ((long long)kk * g.nn[1] + jj) * nrowa; };
+  auto wrow = [&](int kk, T* out) {  // W of the own row at plane kk (0 past the far face)
+    bool f;
+    if (kk > g.n[2]) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) out[q] = T(0);
+      return;
+    }
+    const T* v = zm_row(g, V, Q, j, kk, f);
+    const T* a = arow(j, kk);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + 256 * q;
+      out[q] = c < ni0 ? v[c] * a[c + 1] : T(0);
+    }
+  };
+  T wm[CPT], wc[CPT], wp[CPT];
+  wrow(k0 - 1, wm);
+  wrow(k0, wc);
+  wrow(k0 + 1, wp);
+  for (int k = k0; k <= k1; ++k) {
+    // neighbour rows j-1, j+1 at plane k, and the x-face ends of the own row
+    bool f;
+    const T* vjm = zm_row(g, V, Q, j - 1, k, f);
+    const T* vjp = zm_row(g, V, Q, j + 1, k, f);
+    const T* ajm = arow(j - 1, k);
+    const T* ajp = arow(j + 1, k);
+    const T* ac = arow(j, k);
+    T nj[CPT];
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + 256 * q;
+      nj[q] = c < ni0 ? vjm[c] * ajm[c + 1] + vjp[c] * ajp[c + 1] : T(0);
+    }
+    T wnext[CPT];
+    wrow(k + 2, wnext);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + 256 * q;
+      if (c < ni0) row[c + 1] = wc[q];
+    }
+    if (threadIdx.x == 0) {
+      row[0] = Q[g.face_off[0] + (long long)(k - 1) * ni1 + (j - 1)] * ac[0];
+      row[ni0 + 1] = Q[g.face_off[1] + (long long)(k - 1) * ni1 + (j - 1)] * ac[g.n[0]];
+    }
+    __syncthreads();
+    const long long e0 = ((long long)(k - 1) * ni1 + (j - 1)) * g.px;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + 256 * q;
+      if (c < ni0) {
+        T acc = m0 * wc[q] + m1 * (row[c] + row[c + 2] + nj[q] + wm[q] + wp[q]);
+        if (src) acc += src[e0 + c];
+        G[e0 + c] = acc;
+      } else if (c < g.px) {
+        G[e0 + c] = T(0);
+      }
+      wm[q] = wc[q];
+      wc[q] = wp[q];
+      wp[q] = wnext[q];
+    }
+  }
+}
+
 template <typename T, int DIM>
 __global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __restrict__ Q,
                          const T* __restrict__ af, const T* __restrict__ srcq, double* __restrict__ R) {
@@ -203,7 +357,7 @@ __global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __
 // Face layers of the homogeneous lift L_h^bnd[Q]: the value at the interior node next to
 // a face, taken from that face's own Q (its nodes inside the 19-point (3-D) or 9-point
 // (2-D) stencil of the node), in the layouts of the spectral lift
-//   3-D  Lx[s][(k-1) n_y' + (j-1)], Ly[s][(k-1) px + (i-1)], Lz[s][(j-1) px + (i-1)]
+//   3-D  Lx[s][(j-1) n_z' + (k-1)], Ly[s][(k-1) px + (i-1)], Lz[s][(j-1) px + (i-1)]
 //   2-D  Lx[s][j-1], Ly[s][i-1]   (s = 0 low face, 1 high face; row padding zeroed)
 // Each interior node's lift is the sum over the faces it touches.
 template <int DIM>
@@ -222,10 +376,10 @@ __device__ __forceinline__ void face_node(const Geom& g, int f, long long t, int
     }
     return;
   }
-  if (ax == 0) {  // [k][j]
+  if (ax == 0) {  // [j][k]
     i = sd ? g.ni[0] : 1;
-    k = (int)(t / g.ni[1]) + 1;
-    j = (int)(t % g.ni[1]) + 1;
+    j = (int)(t / g.ni[2]) + 1;
+    k = (int)(t % g.ni[2]) + 1;
   } else if (ax == 1) {  // [k][i], pitch px
     j = sd ? g.ni[1] : 1;
     k = (int)(t / g.px) + 1;
@@ -305,7 +459,7 @@ __global__ void k_partial_sum(long long n, int count, long long stride, const T*
 
 // Boundary residual from the face sums S = 6 U1 - 3/2 U2 + 2/9 U3 (formed in spectral space):
 //   R = alpha_b h^-2 S - Q - src_q
-//   3-D: x faces S = Fx[s][(k-1) n_y' + (j-1)], y faces Fy[s][(k-1) px + (i-1)],
+//   3-D: x faces S = Fx[s][(j-1) n_z' + (k-1)], y faces Fy[s][(k-1) px + (i-1)],
 //        z faces Fz[s][(j-1) px + (i-1)];  2-D: Fx[s][j-1], Fy[s][i-1]
 template <typename T, int DIM>
 __global__ void k_gather_faces(Geom g, const T* __restrict__ Fx, const T* __restrict__ Fy,
@@ -328,7 +482,7 @@ __global__ void k_gather_faces(Geom g, const T* __restrict__ Fx, const T* __rest
     const int sd = st > 0 ? 0 : 1;  // low face (step +1) -> 0
     T S;
     if (ax == 0) {
-      const long long r = DIM == 3 ? (long long)(k - 1) * g.ni[1] + (j - 1) : (j - 1);
+      const long long r = DIM == 3 ? (long long)(j - 1) * g.ni[2] + (k - 1) : (j - 1);
       S = Fx[sd * px_plane + r];
     } else if (ax == 1) {
       const long long r = DIM == 3 ? (long long)(k - 1) * g.px + (i - 1) : (i - 1);
@@ -649,7 +803,27 @@ int lift(const Geom& g, const Weights& w, const T* Q, const T* src, T* G, hipStr
 template <typename T>
 int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
           hipStream_t st) {
-  const int nrow = g.dim == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  if (g.dim == 3) {
+    const int cpt = (g.px + 255) / 256;
+    const int kchunk = 32;
+    const int total = g.ni[1] * ((g.ni[2] + kchunk - 1) / kchunk);
+    const unsigned blocks = 8u * (unsigned)((total + 7) / 8);
+#define AHOC_ZM(C) hipLaunchKernelGGL((k_rhs_u_zm<T, C>), dim3(blocks), dim3(256), 0, st, g, w, V, Q, ia, src, G, kchunk)
+    if (cpt <= 1) AHOC_ZM(1);
+    else if (cpt <= 2) AHOC_ZM(2);
+    else if (cpt <= 4) AHOC_ZM(4);
+    else if (cpt <= 8) AHOC_ZM(8);
+    else if (cpt <= 16) AHOC_ZM(16);
+    else {
+      const int nrow = g.ni[1] * g.ni[2];
+      hipLaunchKernelGGL((k_rhs_u3<T>), dim3(8u * (unsigned)((nrow + 7) / 8)), dim3(TPB), 0, st, g, w, V, Q, ia,
+                         src, G);
+    }
+#undef AHOC_ZM
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
+  }
+  const int nrow = g.ni[1];
   LAUNCH_TDIM(k_rhs_u, T, dim3((unsigned)(nrow < 1 ? 1 : nrow), g.nb), g, w, V, Q, ia, src, G);
   return ST_OK;
 }
