@@ -15,6 +15,7 @@
 #include "kernels.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -22,6 +23,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace ahoc {
@@ -100,7 +102,12 @@ struct ahoc_handle {
   double* red = nullptr;     // reduction partials
   double* pinned = nullptr;  // host-pinned scalars (2 per instance, at least 8)
   int* pinned_i = nullptr;   // host-pinned ints (one per instance)
+  // batch: device table of per-instance pointers, [6][nb] (five input fields, then the
+  // outputs u), and its host image (kept alive while copies from it may be in flight)
+  void** ptab = nullptr;
+  std::vector<void*> ptab_host;
   std::vector<void*> allocs;
+  size_t dev_bytes = 0;      // device memory held by allocs
   // optional per-kernel-class timing with HIP events on the work stream
   bool prof = false;
   std::vector<hipEvent_t> evpool;
@@ -124,6 +131,7 @@ int dalloc(ahoc_handle* h, void** p, size_t bytes) {
     return ST_NOMEM;
   }
   h->allocs.push_back(*p);
+  h->dev_bytes += bytes;
   return ST_OK;
 }
 
@@ -672,11 +680,19 @@ int write_ints(ahoc_handle* h, int* dptr, int count, hipStream_t st) {
   return ST_OK;
 }
 
+// Blocks per segment of a dot sweep: at least 2048 entries per block (8 per thread), so a
+// short segment (a small 2-D batch instance) does not launch hundreds of idle blocks.
+int dot_blocks(const ahoc_handle* h, long long n) {
+  const long long b = (n + 2047) / 2048;
+  return (int)std::max<long long>(1, std::min<long long>(h->nb_dot, b));
+}
+
 // Per-instance dot products of two batch vectors: out[2 s] = <a_s, b_s>.
 int dot_dev(ahoc_handle* h, const double* a, const double* b, hipStream_t st, double* out) {
   const long long n = h->g.nq;
-  TRY(mdot_partial(a, n, 1, b, n, h->g.nb, h->part, h->nb_dot, st));
-  return mdot_reduce(h->part, h->nb_dot, 1, h->g.nb, out, 2, 0, st);
+  const int nbk = dot_blocks(h, n);
+  TRY(mdot_partial(a, n, 1, b, n, h->g.nb, h->part, nbk, st));
+  return mdot_reduce(h->part, nbk, 1, h->g.nb, out, 2, 0, st);
 }
 
 double absmax(ahoc_handle* h, const void* x, bool dbl, long long n, hipStream_t st, int* rc) {
@@ -718,6 +734,7 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
   const bool pre = h->pc != nullptr;
   const int ns = h->g.nb;
   const long long nq = h->g.nq;
+  const int nbk = dot_blocks(h, nq);
   const long long nt = nq * ns;  // batch vector length
   const int m = h->m;
   res.assign(ns, GmresResult());
@@ -779,11 +796,11 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       }
       ++*matvecs;
       hipEvent_t ek = tbegin(h, st);
-      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, h->nb_dot, st));
-      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, ns, h->h1, m + 1, 0, st));
+      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, st));
+      TRY(mdot_reduce(h->part, nbk, j + 1, ns, h->h1, m + 1, 0, st));
       TRY(maxpy(w, h->Vb, nt, j + 1, h->h1, m + 1, -1.0, nq, ns, st));
-      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, h->nb_dot, st));
-      TRY(mdot_reduce(h->part, h->nb_dot, j + 1, ns, h->h2, m + 1, 0, st));
+      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, st));
+      TRY(mdot_reduce(h->part, nbk, j + 1, ns, h->h2, m + 1, 0, st));
       TRY(maxpy(w, h->Vb, nt, j + 1, h->h2, m + 1, -1.0, nq, ns, st));
       TRY(dot_dev(h, w, w, st, h->nrm));
       TRY(givens_step(ns, h->H, m, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
@@ -848,7 +865,8 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
 
 // Concatenate one nodal input field of `count` instances into a batch array (nullptr if no
 // instance has it; instances without it get zeros).
-int gather_field(ahoc_handle* h, const ahoc_problem* pbs, int count, size_t off, double** out, hipStream_t st) {
+int gather_field(ahoc_handle* h, const ahoc_problem* pbs, int count, size_t off, int slot, double** out,
+                 hipStream_t st) {
   bool any = false;
   for (int i = 0; i < count; ++i)
     any = any || *reinterpret_cast<const double* const*>(reinterpret_cast<const char*>(&pbs[i]) + off);
@@ -856,15 +874,13 @@ int gather_field(ahoc_handle* h, const ahoc_problem* pbs, int count, size_t off,
   if (!any) return ST_OK;
   const long long nn = h->g.nnodal;
   TRY(alloc_t(h, out, nn * count));
-  for (int i = 0; i < count; ++i) {
-    const double* src = *reinterpret_cast<const double* const*>(reinterpret_cast<const char*>(&pbs[i]) + off);
-    if (src) {
-      AHOC_HIP_TRY(hipMemcpyAsync(*out + nn * i, src, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
-    } else {
-      TRY(fill(nn, 0.0, *out + nn * i, st));
-    }
-  }
-  return ST_OK;
+  void** hp = h->ptab_host.data() + (size_t)slot * count;
+  for (int i = 0; i < count; ++i)
+    hp[i] = const_cast<double*>(
+        *reinterpret_cast<const double* const*>(reinterpret_cast<const char*>(&pbs[i]) + off));
+  AHOC_HIP_TRY(hipMemcpyAsync(h->ptab + (size_t)slot * count, hp, sizeof(void*) * count,
+                              hipMemcpyHostToDevice, st));
+  return gather_ptrs(reinterpret_cast<const double* const*>(h->ptab + (size_t)slot * count), nn, count, *out, st);
 }
 
 // Set up one problem, or a batch of `count` 2-D problems on the same grid (same n, lo, hi),
@@ -879,11 +895,13 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD;
   if (count > 1) {
     double *a_, *f_, *gd_, *gn_, *lg_;
-    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, alpha), &a_, st));
-    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, f), &f_, st));
-    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gD), &gd_, st));
-    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gN), &gn_, st));
-    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, lapgD), &lg_, st));
+    h->ptab_host.assign((size_t)6 * count, nullptr);
+    TRY(alloc_t(h, &h->ptab, 6LL * count));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, alpha), 0, &a_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, f), 1, &f_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gD), 2, &gd_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gN), 3, &gn_, st));
+    TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, lapgD), 4, &lg_, st));
     alpha = a_, f = f_, gD = gd_, gN = gn_, lapgD = lg_;
   }
   // FP64 data
@@ -1151,18 +1169,17 @@ int write_u(ahoc_handle* h, const double* Ui, double* const* u, hipStream_t st) 
   const Geom& g = h->g;
   if (g.nb == 1) return out_u<double>(g, Ui, h->gD, u[0], st);
   TRY(out_u<double>(g, Ui, h->gD, h->ubuf, st));
-  for (int i = 0; i < g.nb; ++i)
-    AHOC_HIP_TRY(hipMemcpyAsync(u[i], h->ubuf + (long long)i * g.nnodal, sizeof(double) * g.nnodal,
-                                hipMemcpyDeviceToDevice, st));
-  return ST_OK;
+  void** hp = h->ptab_host.data() + 5 * (size_t)g.nb;
+  for (int i = 0; i < g.nb; ++i) hp[i] = u[i];
+  AHOC_HIP_TRY(hipMemcpyAsync(h->ptab + 5 * (size_t)g.nb, hp, sizeof(void*) * g.nb, hipMemcpyHostToDevice, st));
+  return scatter_ptrs(h->ubuf, g.nnodal, g.nb, reinterpret_cast<double* const*>(h->ptab + 5 * (size_t)g.nb), st);
 }
 
 // Zero the segments (instances) of a batch vector whose flag in h->pinned_i is 0.
 int zero_done(ahoc_handle* h, double* x, hipStream_t st) {
   const Geom& g = h->g;
-  for (int i = 0; i < g.nb; ++i)
-    if (!h->pinned_i[i]) TRY(fill(g.nq, 0.0, x + (long long)i * g.nq, st));
-  return ST_OK;
+  TRY(write_ints(h, h->act, g.nb, st));
+  return zero_masked(x, g.nq, g.nb, h->act, st);
 }
 
 // u: one output per instance; v, q only for a single instance (nb = 1).  s: nb stats.
@@ -1413,70 +1430,143 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
                                double* const* u, ahoc_stats* stats, void* stream) {
   if (count < 0 || (count > 0 && (!probs || !u))) return AHOC_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
-  // buckets of 2-D problems on the same grid run as one batch (lock-step GMRES, one launch
-  // per kernel for all instances); 3-D problems and single grids run one by one
+  // Jobs: buckets of 2-D problems on the same grid run as one batch (lock-step GMRES, one
+  // launch per kernel for all instances, chunks of about 64 M grid nodes); 3-D problems and
+  // grids that occur once run alone.
   std::map<std::vector<double>, std::vector<int>> buckets;
-  std::vector<int> single;
+  std::vector<std::vector<int>> jobs;
   for (int i = 0; i < count; ++i) {
     const ahoc_problem& p = probs[i];
     if (p.dim != 2 || !u[i]) {
-      single.push_back(i);
+      jobs.push_back({i});
       continue;
     }
     buckets[{(double)p.n[0], (double)p.n[1], p.lo[0], p.lo[1], p.hi[0], p.hi[1]}].push_back(i);
   }
-  ahoc_status first = AHOC_OK;
-  auto note = [&](ahoc_status rc) {
-    if (rc != AHOC_OK && first == AHOC_OK) first = rc;
-  };
-  // instances per launch: about 64 M grid nodes (FP64 work arrays of a few GB)
   const long long node_budget = 64LL << 20;
   for (auto& kv : buckets) {
-    std::vector<int>& idx = kv.second;
-    if (idx.size() == 1) {
-      single.push_back(idx[0]);
-      continue;
-    }
+    const std::vector<int>& idx = kv.second;
     const long long nodes = (long long)(probs[idx[0]].n[0] + 1) * (probs[idx[0]].n[1] + 1);
-    const int chunk = (int)std::max<long long>(1, std::min<long long>(4096, node_budget / nodes));
-    for (size_t c0 = 0; c0 < idx.size(); c0 += chunk) {
-      const int k = (int)std::min<size_t>(chunk, idx.size() - c0);
+    const size_t chunk = (size_t)std::max<long long>(1, std::min<long long>(4096, node_budget / nodes));
+    for (size_t c0 = 0; c0 < idx.size(); c0 += chunk)
+      jobs.emplace_back(idx.begin() + c0, idx.begin() + std::min(idx.size(), c0 + chunk));
+  }
+  // largest jobs first, so that the small ones fill in behind them
+  auto work = [&](const std::vector<int>& jb) {
+    const ahoc_problem& p = probs[jb[0]];
+    long long nodes = 1;
+    for (int a = 0; a < p.dim; ++a) nodes *= (long long)p.n[a] + 1;
+    return nodes * (long long)jb.size();
+  };
+  std::stable_sort(jobs.begin(), jobs.end(),
+                   [&](const std::vector<int>& a, const std::vector<int>& b) { return work(a) > work(b); });
+  const int njobs = (int)jobs.size();
+  if (njobs == 0) return AHOC_OK;
+
+  // Jobs run concurrently, one host thread and one non-blocking stream per worker, so that
+  // the per-iteration host round trips and short launches of one job overlap the others.
+  int nworkers = 4;
+  if (const char* e = std::getenv("AHOC_BATCH_STREAMS")) nworkers = std::atoi(e);
+  nworkers = std::max(1, std::min(nworkers, std::min(njobs, 16)));
+  std::vector<hipStream_t> ws(nworkers, nullptr);
+  hipEvent_t ready = nullptr;
+  int dev = 0;
+  {
+    hipError_t e = hipGetDevice(&dev);  // the workers run on the caller's current device
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ready, st);  // inputs written on the caller's stream
+    for (int w = 0; w < nworkers && e == hipSuccess; ++w) {
+      e = hipStreamCreateWithFlags(&ws[w], hipStreamNonBlocking);
+      if (e == hipSuccess) e = hipStreamWaitEvent(ws[w], ready, 0);
+    }
+    if (e != hipSuccess) {
+      ahoc::set_last_error(hipGetErrorString(e), "ahoc_solve_batched");
+      for (hipStream_t s : ws)
+        if (s) (void)hipStreamDestroy(s);
+      if (ready) (void)hipEventDestroy(ready);
+      return AHOC_E_HIP;
+    }
+  }
+  // ahoc_destroy synchronises the device, which would stall the other workers: handles are
+  // kept until every worker has finished, up to a budget of device memory.
+  const size_t keep_budget = (size_t)48 << 30;
+  std::vector<ahoc_status> jrc(njobs, AHOC_OK);
+  std::vector<std::string> jerr(njobs);
+  std::vector<ahoc_handle*> kept;
+  size_t kept_bytes = 0;
+  std::mutex mu;
+  std::atomic<int> next{0};
+  auto worker = [&](int w) {
+    const hipStream_t s = ws[w];
+    const bool dev_ok = hipSetDevice(dev) == hipSuccess;
+    for (int jn = next++; jn < njobs; jn = next++) {
+      if (!dev_ok) {
+        jrc[jn] = AHOC_E_HIP;
+        jerr[jn] = "ahoc_solve_batched: hipSetDevice failed in a worker thread";
+        continue;
+      }
+      const std::vector<int>& jb = jobs[jn];
+      const int k = (int)jb.size();
       std::vector<ahoc_problem> sub(k);
       std::vector<double*> uo(k);
       std::vector<ahoc_stats> so(k);
       for (int j = 0; j < k; ++j) {
-        sub[j] = probs[idx[c0 + j]];
-        uo[j] = u[idx[c0 + j]];
+        sub[j] = probs[jb[j]];
+        uo[j] = u[jb[j]];
         std::memset(&so[j], 0, sizeof(ahoc_stats));
       }
       const auto t0 = std::chrono::steady_clock::now();
       ahoc_handle* h = nullptr;
-      ahoc_status rc = k > 1 ? setup_n(sub.data(), k, opt, stream, &h) : setup_n(sub.data(), 1, opt, stream, &h);
+      ahoc_status rc = setup_n(sub.data(), k, opt, s, &h);
       if (rc == AHOC_OK) {
         rc = (ahoc_status)(h->opt.precision == AHOC_MIXED
-                               ? ahoc::solve_mixed(h, uo.data(), nullptr, nullptr, so.data(), st)
-                               : ahoc::solve_fp64(h, uo.data(), nullptr, nullptr, so.data(), st));
-        ahoc_destroy(h);
+                               ? ahoc::solve_mixed(h, uo.data(), nullptr, nullptr, so.data(), s)
+                               : ahoc::solve_fp64(h, uo.data(), nullptr, nullptr, so.data(), s));
+        const hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess && rc == AHOC_OK) {
+          ahoc::set_last_error(hipGetErrorString(e), "ahoc_solve_batched");
+          rc = AHOC_E_HIP;
+        }
       }
-      const auto t1 = std::chrono::steady_clock::now();
-      const double ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+      const double ms =
+          std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       for (int j = 0; j < k; ++j) {
-        so[j].t_solve_ms = ms;  // wall time of the whole batch (setup included)
-        if (stats) stats[idx[c0 + j]] = so[j];
+        so[j].t_solve_ms = ms;  // wall time of the whole job (setup included)
+        if (stats) stats[jb[j]] = so[j];
       }
-      note(rc);
+      jrc[jn] = rc;
+      if (rc != AHOC_OK) jerr[jn] = ahoc::g_err;
+      if (h) {
+        bool keep = false;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          if (kept_bytes + h->dev_bytes <= keep_budget) {
+            kept.push_back(h);
+            kept_bytes += h->dev_bytes;
+            keep = true;
+          }
+        }
+        if (!keep) ahoc_destroy(h);
+      }
     }
+  };
+  if (nworkers == 1) {
+    worker(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int w = 0; w < nworkers; ++w) th.emplace_back(worker, w);
+    for (std::thread& t : th) t.join();
   }
-  for (int i : single) {
-    ahoc_handle* h = nullptr;
-    ahoc_status rc = ahoc_setup(&probs[i], opt, stream, &h);
-    if (rc == AHOC_OK) {
-      rc = ahoc_solve(h, u[i], nullptr, nullptr, stats ? &stats[i] : nullptr, stream);
-      ahoc_destroy(h);
-    }
-    note(rc);
-  }
-  return first;
+  for (ahoc_handle* h : kept) ahoc_destroy(h);
+  for (hipStream_t s : ws) (void)hipStreamDestroy(s);
+  (void)hipEventDestroy(ready);
+  // first failing job in the order of the instances
+  int first = -1;
+  for (int jn = 0; jn < njobs; ++jn)
+    if (jrc[jn] != AHOC_OK && (first < 0 || jobs[jn][0] < jobs[first][0])) first = jn;
+  if (first < 0) return AHOC_OK;
+  ahoc::g_err = jerr[first];
+  return jrc[first];
 }
 
 ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const void* in, void* out,

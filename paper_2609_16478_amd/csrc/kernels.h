@@ -65,6 +65,11 @@ int givens_step(int ns, double* H, int m, const double* h1, const double* h2, co
                 double* sn, double* gv, int j, double* resid, hipStream_t st);
 int axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);
 int scale_by_inv(double* w, long long n, int ns, const double* s, const int* act, hipStream_t st);
+// Segment-wise batch utilities (grid.y = segment): x_s = 0 where keep[s] == 0; gather of
+// per-instance arrays (device table of device pointers, null = zeros); scatter to them.
+int zero_masked(double* x, long long n, int ns, const int* keep, hipStream_t st);
+int gather_ptrs(const double* const* src, long long n, int ns, double* out, hipStream_t st);
+int scatter_ptrs(const double* in, long long n, int ns, double* const* dst, hipStream_t st);
 int back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y,
                hipStream_t st);
 int start_cycle(double* v0, const double* r, long long n, int ns, const double* nrm2, double* gv, int m,

@@ -127,6 +127,33 @@ __global__ void k_scale_inv(double* __restrict__ w, long long n, const double* _
     w[s0 + e] *= r;
 }
 
+// x_s = 0 on every segment s with keep[s] == 0
+__global__ void k_zero_masked(double* __restrict__ x, long long n, const int* __restrict__ keep) {
+  if (keep[blockIdx.y]) return;
+  const long long s0 = blockIdx.y * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    x[s0 + e] = 0.0;
+}
+
+// out_s = src[s] (or 0 where src[s] is null): concatenate per-instance arrays of length n
+__global__ void k_gather_ptrs(const double* const* __restrict__ src, long long n, double* __restrict__ out) {
+  const double* p = src[blockIdx.y];
+  double* o = out + blockIdx.y * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    o[e] = p ? p[e] : 0.0;
+}
+
+// dst[s] = in_s: split a batch array into per-instance arrays of length n
+__global__ void k_scatter_ptrs(const double* __restrict__ in, long long n, double* const* __restrict__ dst) {
+  double* p = dst[blockIdx.y];
+  const double* x = in + blockIdx.y * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    p[e] = x[e];
+}
+
 // one thread per segment: y_s[0..k_s) from the rotated triangle, y_s[k_s..kmax) = 0
 __global__ void k_back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y) {
   const int sg = blockIdx.x * blockDim.x + threadIdx.x;
@@ -205,6 +232,24 @@ int axpby(long long n, double a, const double* x, double b, double* y, hipStream
 
 int scale_by_inv(double* w, long long n, int ns, const double* s, const int* act, hipStream_t st) {
   hipLaunchKernelGGL(k_scale_inv, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, w, n, s, act);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int zero_masked(double* x, long long n, int ns, const int* keep, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_masked, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, x, n, keep);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int gather_ptrs(const double* const* src, long long n, int ns, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_ptrs, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, src, n, out);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int scatter_ptrs(const double* in, long long n, int ns, double* const* dst, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_ptrs, dim3(nblk(n, 65536), ns), dim3(TPB), 0, st, in, n, dst);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
