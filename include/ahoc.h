@@ -166,7 +166,9 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
  * 0 = automatic (length-specialised kernels for n in {32, 64, 96, 128, 192, 256, 384,
  * 512, 768, 1024, 2048, 4096}, the generic radix-2/3/4/8 kernel otherwise),
  * 1 = generic kernel for every length, 2 = specialised kernels only (other lengths
- * return AHOC_E_UNSUPPORTED).  For tuning and for testing both families. */
+ * return AHOC_E_UNSUPPORTED), 3 = as 0 but strided passes with the one-tile-per-group
+ * kernels instead of the persistent pipelined ones.  For tuning and for testing every
+ * family. */
 ahoc_status ahoc_set_dst_variant(int variant);
 
 /* Override the default work-group tile (pencil pairs per work-group, a power of two;

@@ -1392,7 +1392,7 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
 }
 
 ahoc_status ahoc_set_dst_variant(int variant) {
-  if (variant < 0 || variant > 2) return AHOC_E_INVALID;
+  if (variant < 0 || variant > 3) return AHOC_E_INVALID;
   ahoc::dst_set_variant(variant);
   return AHOC_OK;
 }

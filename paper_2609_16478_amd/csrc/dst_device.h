@@ -205,6 +205,45 @@ template <int N> __host__ __device__ constexpr int seq_stride() {
   return (N + (N >> 5) + 1) | 1;
 }
 
+// Padded offset of a compile-time displacement c from a padded base: pad(x + c) =
+// pad(x) + poff(c) whenever x mod 32 + c mod 32 < 32 (no carry into the next 32-block) or
+// c is a multiple of 32.  Then every LDS access of a stage is one base register plus an
+// immediate offset.
+__host__ __device__ constexpr int poff(int c) { return c + (c >> 5); }
+__host__ __device__ constexpr bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// A wave-uniform global address held in scalar registers; accesses through it add a
+// per-lane 32-bit byte offset, which is the global load/store form with a scalar base and a
+// 32-bit vector offset (no per-lane 64-bit address arithmetic).
+struct SBase {
+  using gchar = __attribute__((address_space(1))) char;
+  gchar* p;
+  __device__ __forceinline__ explicit SBase(const void* q) {
+    const unsigned long long v = reinterpret_cast<unsigned long long>(q);
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+    p = reinterpret_cast<gchar*>(((unsigned long long)hi << 32) | lo);
+  }
+  __device__ __forceinline__ SBase(gchar* q, long long d) : p(q + d) {}
+  __device__ __forceinline__ SBase plus(long long d) const { return SBase(p, d); }
+  // raw bits of a 4-, 8- or 16-byte value
+  template <int B> struct Raw;
+  template <typename V> using Bits = typename Raw<(int)sizeof(V)>::type;
+  template <typename V> __device__ __forceinline__ V ld(unsigned off) const {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "4, 8 or 16 bytes");
+    const Bits<V> r = *reinterpret_cast<const __attribute__((address_space(1))) Bits<V>*>(p + off);
+    return __builtin_bit_cast(V, r);
+  }
+  template <typename V> __device__ __forceinline__ void st(unsigned off, const V& v) const {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "4, 8 or 16 bytes");
+    *reinterpret_cast<__attribute__((address_space(1))) Bits<V>*>(p + off) = __builtin_bit_cast(Bits<V>, v);
+  }
+};
+template <> struct SBase::Raw<4> { using type = unsigned; };
+template <> struct SBase::Raw<8> { typedef unsigned type __attribute__((ext_vector_type(2))); };
+template <> struct SBase::Raw<16> { typedef unsigned type __attribute__((ext_vector_type(4))); };
+
+
 // One Stockham stage (radix R, input blocks Ns) over the sequence in LDS.
 template <typename T, int N, int R, int NS, int PPT>
 __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restrict__ tw) {
@@ -212,12 +251,26 @@ __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restric
   constexpr int NB = PPT / R;
   constexpr int NR = N / R;
   constexpr int TWS = N / (NS * R);
+  // reads at ts + b TPS + r NR: linear when both strides are multiples of 32
+  constexpr bool RLIN = NR % 32 == 0 && (NB == 1 || TPS % 32 == 0);
+  // writes at base + r NS, base = (j - k) R + k: base mod 32 = k < NS when R NS >= 32 (powers
+  // of two), any when NS is a multiple of 32, a multiple of R when NS = 1 and R divides 32
+  constexpr bool WLIN = is_pow2(R) && is_pow2(NS) && (NS % 32 == 0 || R * NS >= 32 || (NS == 1 && 32 % R == 0));
   cx<T> v[NB][R];
+  if constexpr (RLIN) {
+    const cx<T>* rb = seq + pad(ts);
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const int j = ts + b * TPS;
+    for (int b = 0; b < NB; ++b) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) v[b][r] = seq[pad(j + r * NR)];
+      for (int r = 0; r < R; ++r) v[b][r] = rb[poff(b * TPS + r * NR)];
+    }
+  } else {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int j = ts + b * TPS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[b][r] = seq[pad(j + r * NR)];
+    }
   }
   __syncthreads();
 #pragma unroll
@@ -235,8 +288,14 @@ __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restric
     }
     DFT<T, R>::run(v[b]);
     const int base = (j - k) * R + k;
+    if constexpr (WLIN) {
+      cx<T>* wb = seq + pad(base);
 #pragma unroll
-    for (int r = 0; r < R; ++r) seq[pad(base + r * NS)] = v[b][r];
+      for (int r = 0; r < R; ++r) wb[poff(r * NS)] = v[b][r];
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) seq[pad(base + r * NS)] = v[b][r];
+    }
   }
   __syncthreads();
 }
@@ -267,13 +326,23 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
   constexpr int PPT = P::PPT;
   constexpr int TPS = N / PPT;
   constexpr int H = PPT / 2;
+  // linear addressing (see poff): the per-thread strides are multiples of 32 and each
+  // thread's prefix chunk stays inside one 32-block
+  constexpr bool LIN = TPS % 32 == 0 && is_pow2(PPT) && PPT <= 32;
   cx<T> ev[H], cc[H];
   // (a) mirrored reads, lanes on consecutive k
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     const int k = ts + i * TPS;
-    const cx<T> w1 = seq[pad(k)];
-    const cx<T> w2 = seq[pad(k == 0 ? 0 : N - k)];
+    cx<T> w1, w2;
+    if constexpr (LIN) {
+      w1 = seq[pad(ts) + poff(i * TPS)];
+      w2 = seq[pad(N - ts) - poff(i * TPS)];  // k = 0 reads the unused slot pad(N) of the stride
+      if (k == 0) w2 = w1;
+    } else {
+      w1 = seq[pad(k)];
+      w2 = seq[pad(k == 0 ? 0 : N - k)];
+    }
     T ca = T(0.5) * (w1.x + w2.x), cb = T(0.5) * (w1.y + w2.y);
     if (k == 0) {
       ca *= T(0.5);
@@ -301,17 +370,23 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
         e.y *= scale * recip(A.y + B.y * s);
       }
     }
-    seq[pad(2 * k)] = e;
-    seq[pad(2 * k + 1)] = cc[i];
+    if constexpr (LIN) {
+      seq[pad(2 * ts) + poff(2 * i * TPS)] = e;
+      seq[pad(2 * ts + 1) + poff(2 * i * TPS)] = cc[i];
+    } else {
+      seq[pad(2 * k)] = e;
+      seq[pad(2 * k + 1)] = cc[i];
+    }
   }
   __syncthreads();
   // (c) prefix sum: serial over this thread's contiguous chunk, then lane scan of totals
   const int k0 = ts * H;
   T ax = 0, ay = 0;
   cx<T> pre[H];
+  cx<T>* chunk = seq + pad(2 * k0);  // positions 2 k0 .. 2 k0 + PPT - 1, one 32-block when LIN
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    const cx<T> c = seq[pad(2 * (k0 + i) + 1)];
+    const cx<T> c = LIN ? chunk[2 * i + 1] : seq[pad(2 * (k0 + i) + 1)];
     ax += c.x;
     ay += c.y;
     pre[i].x = ax;
@@ -356,7 +431,8 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
       o.x *= scale * recip(A.x + B.x * s);
       o.y *= scale * recip(A.y + B.y * s);
     }
-    seq[pad(2 * k + 1)] = o;
+    if constexpr (LIN) chunk[2 * i + 1] = o;
+    else seq[pad(2 * k + 1)] = o;
   }
   __syncthreads();
 }
@@ -366,12 +442,15 @@ template <typename T, int N, class P>
 __device__ __forceinline__ void pre_lds(cx<T>* seq, int ts, const T* __restrict__ sn) {
   constexpr int PPT = P::PPT;
   constexpr int TPS = N / PPT;
+  constexpr bool LIN = TPS % 32 == 0;
   cx<T> z[PPT / 2], zr[PPT / 2];
+  cx<T>* lo = seq + pad(1 + ts);
+  cx<T>* hi = seq + pad(N - 1 - ts);
 #pragma unroll
   for (int i = 0; i < PPT / 2; ++i) {
     const int m = 1 + ts + i * TPS;
-    z[i] = seq[pad(m)];
-    zr[i] = seq[pad(N - m)];
+    z[i] = LIN ? lo[poff(i * TPS)] : seq[pad(m)];
+    zr[i] = LIN ? hi[-poff(i * TPS)] : seq[pad(N - m)];
   }
   __syncthreads();
 #pragma unroll
@@ -385,8 +464,13 @@ __device__ __forceinline__ void pre_lds(cx<T>* seq, int ts, const T* __restrict_
     o1.y = sy + dy;
     o2.x = sx - dx;
     o2.y = sy - dy;
-    seq[pad(m)] = o1;
-    seq[pad(N - m)] = o2;
+    if constexpr (LIN) {
+      lo[poff(i * TPS)] = o1;
+      hi[-poff(i * TPS)] = o2;
+    } else {
+      seq[pad(m)] = o1;
+      seq[pad(N - m)] = o2;
+    }
   }
   if (ts == 0) {
     cx<T> zz;

@@ -1,0 +1,285 @@
+// Persistent, software-pipelined DST-I pass over strided pencils (gfx950).
+//
+// The strided passes (pencils along y or z, the fastest axis across pencils) hold a whole
+// tile of 2*NSEQ pencils in LDS: at N = 1024 that is ~135 KB, so one work-group fills a
+// compute unit and, in the one-tile-per-group kernel, the unit alternates between waiting
+// for the tile's loads, transforming it, and storing it.  Here each work-group loops over
+// tiles and keeps the next tile in flight in registers while the current one is
+// transformed in LDS:
+//
+//   regs <- tile t0
+//   loop: LDS <- pre-weighted regs; regs <- tile t+1 (no wait); FFT + post in LDS;
+//         store tile t from LDS
+//
+// The transform itself (two real pencils packed in one complex FFT, symmetric
+// pre-weighting, split + prefix sum) is the one of the single-tile kernels.  The tile
+// shape is a compile-time constant, so the load/store index arithmetic folds to shifts,
+// and the two pencils of a pair are adjacent columns, read and written as one 8-byte
+// (FP32) or 16-byte (FP64) vector per position.  Requires an even column count per slab.
+// Plain passes only: the fused passes (eigen scaling, face sums, second transform) carry
+// more live state per work item than the prefetched tile leaves room for, and stay with the
+// one-tile-per-group kernels.
+#include "dst_device.h"
+
+#include <mutex>
+
+namespace ahoc {
+
+namespace fast {
+
+namespace {
+
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+
+// Stage plan: 16 points per thread where a 16-point plan exists (N = 512, 1024), so that
+// the prefetched tile fits in registers next to the transform's working set.
+template <int N> using PipePlan = PlanOf<N, N == 512 || N == 1024>;
+
+// Work-group size cap: 1024 (FP32) / 512 (FP64) threads for plans of at most 16 points per
+// thread, 512 / 256 otherwise.
+template <typename T, int N> constexpr int pipe_cap() {
+  return PipePlan<N>::PPT <= 16 ? (sizeof(T) == 8 ? 512 : 1024) : (sizeof(T) == 8 ? 256 : 512);
+}
+
+// Pairs per work-group: 128-byte row segments (16 FP32 / 8 FP64 pairs), halved until the
+// tile fits the size cap and 150 KB of LDS.
+template <typename T, int N> constexpr int pipe_nseq() {
+  constexpr int TPS = N / PipePlan<N>::PPT;
+  constexpr int CAP = pipe_cap<T, N>();
+  int nseq = sizeof(T) == 8 ? 8 : 16;
+  while (nseq * TPS < 64) nseq *= 2;
+  while (nseq > 1 && (nseq * TPS > CAP || (long long)nseq * seq_stride<N>() * 2 * (long long)sizeof(T) > 150 * 1024))
+    nseq /= 2;
+  return nseq;
+}
+
+template <typename T, int N, int NSEQ>
+__global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using PL = PipePlan<N>;
+  constexpr int PPT = PL::PPT;
+  constexpr int TPS = N / PPT;
+  constexpr int L = N - 1;
+  constexpr int HN = N / 2;
+  constexpr int U = PPT / 2;  // mirrored position pairs per thread and tile
+  constexpr int LDQ = seq_stride<N>();
+  constexpr int LGQ = ilog2(NSEQ);
+  constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  static_assert((1 << LGQ) == NSEQ, "NSEQ must be a power of two");
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  // The thread index and the table pointers pass through an empty asm statement at the top
+  // of every tile, so that the compiler recomputes the (tile-invariant) LDS addresses and
+  // twiddle loads inside the loop instead of hoisting them and holding them in registers.
+  int tid;
+  int s, ts, q, mi;
+  cx<T>* seq;
+  cx<T>* tot;
+  auto remap = [&]() {
+    tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    // transform mapping: pair s, lane ts within the pair
+    s = tid / TPS;
+    ts = tid - s * TPS;
+    seq = lds + s * LDQ;
+    tot = lds + NSEQ * LDQ + s * NTOT;
+    // load/store mapping: pair q (fastest across lanes: one row segment per NSEQ lanes),
+    // position offset mi
+    q = tid & (NSEQ - 1);
+    mi = tid >> LGQ;
+  };
+  remap();
+  const long long inner = a.inner;
+  const long long ntiles = a.outer * a.ntile_inner;
+
+  cx<T> xr[U], yr[U];  // prefetched tile: positions m and N - m of both pencils
+  auto tile_base = [&](long long tile, long long& c0) {
+    const long long o = tile / a.ntile_inner;
+    c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+    return o * (long long)L * inner + c0;
+  };
+  // Global accesses: each row of positions is a uniform 64-bit base (scalar registers) plus
+  // a fixed per-lane 32-bit byte offset; the lanes of one access span at most TPS rows.
+  const long long rowb = inner * (long long)sizeof(T);  // bytes from one position to the next
+  const unsigned vlo = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
+  const unsigned vhi = (unsigned)((2 * q + (long long)(TPS - 1 - mi) * inner) * (long long)sizeof(T));
+  auto load = [&](long long tile) {
+    long long c0;
+    const SBase src(a.in + tile_base(tile, c0));
+    // columns past the slab (ragged last tile) read column 0 of the tile and are zeroed below
+    const bool ok = c0 + 2 * q < inner;
+    const unsigned dq = ok ? 0u : (unsigned)(2 * q * (int)sizeof(T));
+    unsigned vl = vlo - dq, vh = vhi - dq;
+    // keep the 32-bit offsets local to this block, so that each access is selected in the
+    // scalar-base + 32-bit-offset form
+    asm volatile("" : "+v"(vl), "+v"(vh));
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      // position m - 1 = u TPS + mi; position N - m - 1 = (N - 1 - (u + 1) TPS) + (TPS - 1 - mi)
+      // (for m = N/2 the latter is read but unused)
+      xr[u] = src.plus((long long)(u * TPS) * rowb).ld<cx<T>>(vl);
+      yr[u] = src.plus((long long)(N - 1 - (u + 1) * TPS) * rowb).ld<cx<T>>(vh);
+    }
+    if (c0 + 2 * NSEQ > inner && !ok) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        xr[u].x = xr[u].y = T(0);
+        yr[u].x = yr[u].y = T(0);
+      }
+    }
+  };
+  // positions m = 1 + mi + u TPS: with TPS a multiple of 32, one padded base per direction
+  // plus immediate offsets (see poff)
+  constexpr bool LIN = TPS % 32 == 0;
+  auto to_lds = [&]() {
+    cx<T>* sq = lds + q * LDQ;
+    cx<T>* lo = sq + pad(1 + mi);
+    cx<T>* hi = sq + pad(N - 1 - mi);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = 1 + mi + u * TPS;
+      cx<T>* plo = LIN ? lo + poff(u * TPS) : sq + pad(m);
+      cx<T>* phi = LIN ? hi - poff(u * TPS) : sq + pad(N - m);
+      if (u == U - 1 && m == HN) {  // the middle position pairs with itself: 2 z
+        cx<T> o;
+        o.x = T(2) * xr[u].x;
+        o.y = T(2) * xr[u].y;
+        *plo = o;
+      } else {
+        const T w = a.sn[m];
+        const T sx = w * (xr[u].x + yr[u].x), sy = w * (xr[u].y + yr[u].y);
+        const T dx = T(0.5) * (xr[u].x - yr[u].x), dy = T(0.5) * (xr[u].y - yr[u].y);
+        cx<T> o1, o2;
+        o1.x = sx + dx;
+        o1.y = sy + dy;
+        o2.x = sx - dx;
+        o2.y = sy - dy;
+        *plo = o1;
+        *phi = o2;
+      }
+    }
+    if (tid < NSEQ) {
+      cx<T> z;
+      z.x = T(0);
+      z.y = T(0);
+      lds[tid * LDQ] = z;
+    }
+  };
+  auto store = [&](long long tile) {
+    long long c0;
+    const SBase dst(a.out + tile_base(tile, c0));
+    if (c0 + 2 * q >= inner) return;
+    unsigned vs = vlo;
+    asm volatile("" : "+v"(vs));
+    const cx<T>* sq = lds + q * LDQ;
+    const cx<T>* lo = sq + pad(1 + mi);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int m = 1 + mi + k * TPS;
+      if (k < PPT - 1 || m < N)
+        dst.plus((long long)(k * TPS) * rowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+    }
+  };
+
+  long long tile = blockIdx.x;
+  if (tile < ntiles) load(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
+    remap();
+    const cx<T>* tw = a.tw;
+    to_lds();
+    __syncthreads();
+    const long long nxt = tile + gridDim.x;
+    if (nxt < ntiles) load(nxt);  // in flight during the transform below
+
+    cx<T> A, B;
+    A.x = A.y = T(1);
+    B.x = B.y = T(0);
+    fft<T, N, PL>(seq, ts, tw);
+    post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+    store(tile);
+    __syncthreads();  // the next tile overwrites LDS
+  }
+}
+
+template <typename T, int N> struct PipeLaunch {
+  static constexpr int NSEQ = pipe_nseq<T, N>();
+  static constexpr int TPS = N / PipePlan<N>::PPT;
+  static constexpr int THREADS = NSEQ * TPS;
+  static constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) *
+                                sizeof(cx<T>);
+
+  // resident work-groups on the device (persistent grid)
+  static int resident() {
+    static std::once_flag once;
+    static int r = 0;
+    std::call_once(once, [] {
+      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ>);
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      int dev = 0, cus = 0, per = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, THREADS, LDS) == hipSuccess && per > 0)
+        r = cus * per;
+      (void)hipGetLastError();
+    });
+    return r;
+  }
+
+  static int run(Args<T>& a, int nseq, hipStream_t st) {
+    if (nseq > 0 && nseq != NSEQ) return ST_UNSUPPORTED;
+    if (THREADS % 64 != 0 || THREADS > pipe_cap<T, N>() || LDS > 160 * 1024) return ST_UNSUPPORTED;
+    // per-lane byte offsets span TPS rows and must fit in 32 bits
+    if ((double)(TPS + 1) * (double)a.inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+    const int res = resident();
+    if (res <= 0) return ST_UNSUPPORTED;
+    a.lg_nseq = ilog2(NSEQ);
+    a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
+    const long long ntiles = a.outer * a.ntile_inner;
+    if (ntiles <= 0) return ST_OK;
+    const long long grid = ntiles < res ? ntiles : res;
+    hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
+  }
+};
+
+}  // namespace
+
+}  // namespace fast
+
+template <typename T>
+int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer, long long inner,
+                  int nseq, hipStream_t st) {
+  if (inner <= 1 || (inner & 1)) return ST_UNSUPPORTED;
+  // one slab must stay below 2^31 elements
+  if ((double)(N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
+  fast::Args<T> a;
+  a.in = in;
+  a.out = out;
+  a.tw = tw;
+  a.sn = sn;
+  a.outer = outer;
+  a.inner = inner;
+  a.pitch = inner;
+  switch (N) {
+    case 32: return fast::PipeLaunch<T, 32>::run(a, nseq, st);
+    case 64: return fast::PipeLaunch<T, 64>::run(a, nseq, st);
+    case 96: return fast::PipeLaunch<T, 96>::run(a, nseq, st);
+    case 128: return fast::PipeLaunch<T, 128>::run(a, nseq, st);
+    case 192: return fast::PipeLaunch<T, 192>::run(a, nseq, st);
+    case 256: return fast::PipeLaunch<T, 256>::run(a, nseq, st);
+    case 384: return fast::PipeLaunch<T, 384>::run(a, nseq, st);
+    case 512: return fast::PipeLaunch<T, 512>::run(a, nseq, st);
+    case 768: return fast::PipeLaunch<T, 768>::run(a, nseq, st);
+    case 1024: return fast::PipeLaunch<T, 1024>::run(a, nseq, st);
+    case 2048: return fast::PipeLaunch<T, 2048>::run(a, nseq, st);
+    case 4096: return fast::PipeLaunch<T, 4096>::run(a, nseq, st);
+    default: return ST_UNSUPPORTED;
+  }
+}
+
+template int dst_pipe_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
+                                  int, hipStream_t);
+template int dst_pipe_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
+                                   long long, int, hipStream_t);
+
+}  // namespace ahoc

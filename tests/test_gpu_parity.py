@@ -44,7 +44,7 @@ def _rel(a, b):
 # DST-I passes
 # ------------------------------------------------------------------------------------------
 
-@pytest.fixture(params=[0, 1], ids=["auto", "generic"])
+@pytest.fixture(params=[0, 1, 3], ids=["auto", "generic", "onetile"])
 def variant(request, ah):
     ah.set_dst_variant(request.param)
     yield request.param
