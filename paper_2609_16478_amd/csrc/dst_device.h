@@ -326,23 +326,13 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
   constexpr int PPT = P::PPT;
   constexpr int TPS = N / PPT;
   constexpr int H = PPT / 2;
-  // linear addressing (see poff): the per-thread strides are multiples of 32 and each
-  // thread's prefix chunk stays inside one 32-block
-  constexpr bool LIN = TPS % 32 == 0 && is_pow2(PPT) && PPT <= 32;
   cx<T> ev[H], cc[H];
   // (a) mirrored reads, lanes on consecutive k
 #pragma unroll
   for (int i = 0; i < H; ++i) {
     const int k = ts + i * TPS;
-    cx<T> w1, w2;
-    if constexpr (LIN) {
-      w1 = seq[pad(ts) + poff(i * TPS)];
-      w2 = seq[pad(N - ts) - poff(i * TPS)];  // k = 0 reads the unused slot pad(N) of the stride
-      if (k == 0) w2 = w1;
-    } else {
-      w1 = seq[pad(k)];
-      w2 = seq[pad(k == 0 ? 0 : N - k)];
-    }
+    const cx<T> w1 = seq[pad(k)];
+    const cx<T> w2 = seq[pad(k == 0 ? 0 : N - k)];
     T ca = T(0.5) * (w1.x + w2.x), cb = T(0.5) * (w1.y + w2.y);
     if (k == 0) {
       ca *= T(0.5);
@@ -370,23 +360,17 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
         e.y *= scale * recip(A.y + B.y * s);
       }
     }
-    if constexpr (LIN) {
-      seq[pad(2 * ts) + poff(2 * i * TPS)] = e;
-      seq[pad(2 * ts + 1) + poff(2 * i * TPS)] = cc[i];
-    } else {
-      seq[pad(2 * k)] = e;
-      seq[pad(2 * k + 1)] = cc[i];
-    }
+    seq[pad(2 * k)] = e;
+    seq[pad(2 * k + 1)] = cc[i];
   }
   __syncthreads();
   // (c) prefix sum: serial over this thread's contiguous chunk, then lane scan of totals
   const int k0 = ts * H;
   T ax = 0, ay = 0;
   cx<T> pre[H];
-  cx<T>* chunk = seq + pad(2 * k0);  // positions 2 k0 .. 2 k0 + PPT - 1, one 32-block when LIN
 #pragma unroll
   for (int i = 0; i < H; ++i) {
-    const cx<T> c = LIN ? chunk[2 * i + 1] : seq[pad(2 * (k0 + i) + 1)];
+    const cx<T> c = seq[pad(2 * (k0 + i) + 1)];
     ax += c.x;
     ay += c.y;
     pre[i].x = ax;
@@ -431,8 +415,7 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
       o.x *= scale * recip(A.x + B.x * s);
       o.y *= scale * recip(A.y + B.y * s);
     }
-    if constexpr (LIN) chunk[2 * i + 1] = o;
-    else seq[pad(2 * k + 1)] = o;
+    seq[pad(2 * k + 1)] = o;
   }
   __syncthreads();
 }
