@@ -132,6 +132,10 @@ template <typename T> struct DstGen {
 template <typename T>
 int dst_gen_pass(const DstTables<T>& tb, T* out, long long outer, long long inner, const DstScale<T>& sc,
                  const DstGen<T>& gen, hipStream_t st);
+// Persistent variant (dst_pipe.hip); ST_UNSUPPORTED where its layout conditions fail.
+template <typename T>
+int dst_gen_pipe_pass(const DstTables<T>& tb, T* out, long long outer, long long inner, const DstScale<T>& sc,
+                      const DstGen<T>& gen, hipStream_t st);
 
 // Face contractions of a scaled spectrum W stored as planes [o][ky][kx] (row pitch px,
 // nx valid columns, ny rows, `planes` planes):

@@ -242,6 +242,190 @@ template <typename T, int N> struct PipeLaunch {
   }
 };
 
+// ------------------------------------------------------------------------------------
+// Persistent V-solve pass along the slowest axis: generate the scaled spectrum of the
+// face-layer right-hand side from the 2-D face spectra (see dst_spectral.hip for the
+// separable form), invert along the pass axis, store.  Same tile mapping as k_dst_pipe;
+// the stores of one tile drain while the next tile is generated.  Face-array layouts as
+// DstGen (common.h); a tile must lie in one row of the column decode (na a multiple of the
+// tile width), so that the x-face row is shared by all its columns.
+// ------------------------------------------------------------------------------------
+template <typename T> struct GenPipeArgs {
+  T* out;
+  const cx<T>* tw;
+  const T* sn;
+  long long outer, inner, ntile_inner;
+  DstScale<T> fs;
+  DstGen<T> g;
+};
+
+template <typename T, int N, int NSEQ>
+__global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPipeArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using PL = PipePlan<N>;
+  constexpr int PPT = PL::PPT;
+  constexpr int TPS = N / PPT;
+  constexpr int L = N - 1;
+  constexpr int LDQ = seq_stride<N>();
+  constexpr int LGQ = ilog2(NSEQ);
+  constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  constexpr bool LIN = TPS % 32 == 0;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const long long inner = a.inner;
+  const long long ntiles = a.outer * a.ntile_inner;
+  const DstGen<T>& g = a.g;
+  const bool has_b = g.lb != nullptr;
+
+  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // thread index through an empty asm: tile-invariant addresses stay inside the loop
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int q = tid & (NSEQ - 1);
+    const int mi = tid >> LGQ;
+    const long long o = tile / a.ntile_inner;  // slab (instance of a batch)
+    const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+    // ---- per pair: column decode, eigenvalue coefficients, face weights
+    const long long ib = c0 / a.fs.na;  // one row per tile
+    const long long ca = c0 + 2 * q;
+    const int iaa = (int)(ca - ib * a.fs.na), iab = iaa + 1;
+    const bool va = ca < inner && iaa < a.fs.nva, vb = ca + 1 < inner && iab < a.fs.nva;
+    const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
+    T Aa = 1, Ba = 0, Ab = 1, Bb = 0;
+    if (va) {
+      const T sa = a.fs.s_a[iaa];
+      Aa = sa + sb + a.fs.c_ab * sa * sb;
+      Ba = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+    }
+    if (vb) {
+      const T sa = a.fs.s_a[iab];
+      Ab = sa + sb + a.fs.c_ab * sa * sb;
+      Bb = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+    }
+    const T* lp = g.lp + o * g.pslab;
+    const T* la = g.la + o * g.aslab + ib * g.arow;  // x-face rows of this tile
+    T pla = 0, pha = 0, plb = 0, phb = 0, wla = 0, wha = 0, wlb = 0, whb = 0;
+    if (va) {
+      pla = lp[ca];
+      pha = lp[g.pplane + ca];
+      wla = g.wa[iaa];
+      wha = g.wa[g.nwa + iaa];
+    }
+    if (vb) {
+      plb = lp[ca + 1];
+      phb = lp[g.pplane + ca + 1];
+      wlb = g.wa[iab];
+      whb = g.wa[g.nwa + iab];
+    }
+    T bl = 0, bh = 0;
+    const T* lb = nullptr;
+    if (has_b) {
+      bl = g.wb[ib];
+      bh = g.wb[g.nwb + ib];
+      lb = g.lb + o * g.bslab + (va ? iaa : 0);  // y-face rows: both pencils of the pair
+    }
+    const T scale = a.fs.scale;
+    // ---- generate positions m = 1 + mi + k TPS of pair q
+    cx<T>* sq = lds + q * LDQ;
+    cx<T>* lo = sq + pad(1 + mi);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int m = 1 + mi + k * TPS;
+      if (k < PPT - 1 || m < N) {
+        const T wpl = g.wp[m - 1], wph = g.wp[L + m - 1];
+        const T st = a.fs.s_this[m - 1];
+        const int oa = (m - 1) * g.apitch;
+        const T xl = la[oa], xh = la[g.aplane + oa];
+        T ga = pla * wpl + pha * wph + xl * wla + xh * wha;
+        T gb = plb * wpl + phb * wph + xl * wlb + xh * whb;
+        if (has_b) {
+          const int ob = (m - 1) * g.bpitch;
+          const cx<T> yl = *reinterpret_cast<const cx<T>*>(lb + ob);
+          const cx<T> yh = *reinterpret_cast<const cx<T>*>(lb + g.bplane + ob);
+          ga += yl.x * bl + yh.x * bh;
+          gb += yl.y * bl + yh.y * bh;
+        }
+        cx<T> v;
+        v.x = va ? ga * (scale * recip(Aa + Ba * st)) : T(0);
+        v.y = vb ? gb * (scale * recip(Ab + Bb * st)) : T(0);
+        if (LIN) lo[poff(k * TPS)] = v;
+        else sq[pad(m)] = v;
+      }
+    }
+    if (tid < NSEQ) {
+      cx<T> z;
+      z.x = T(0);
+      z.y = T(0);
+      lds[tid * LDQ] = z;
+    }
+    __syncthreads();
+    // ---- inverse transform along the pass axis
+    const int s = tid / TPS;
+    const int ts = tid - s * TPS;
+    cx<T>* seq = lds + s * LDQ;
+    cx<T>* tot = lds + NSEQ * LDQ + s * NTOT;
+    cx<T> A, B;
+    A.x = A.y = T(1);
+    B.x = B.y = T(0);
+    pre_lds<T, N, PL>(seq, ts, a.sn);
+    fft<T, N, PL>(seq, ts, a.tw);
+    post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+    // ---- store (uniform row bases, fixed per-lane byte offsets)
+    if (c0 + 2 * q < inner) {
+      const long long rowb = inner * (long long)sizeof(T);
+      const SBase dst(a.out + o * (long long)L * inner + c0);
+      unsigned vs = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
+      asm volatile("" : "+v"(vs));
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const int m = 1 + mi + k * TPS;
+        if (k < PPT - 1 || m < N) dst.plus((long long)(k * TPS) * rowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+      }
+    }
+    __syncthreads();  // the next tile overwrites LDS
+  }
+}
+
+template <typename T, int N> struct GenPipeLaunch {
+  static constexpr int NSEQ = pipe_nseq<T, N>();
+  static constexpr int TPS = N / PipePlan<N>::PPT;
+  static constexpr int THREADS = NSEQ * TPS;
+  static constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) *
+                                sizeof(cx<T>);
+
+  static int resident() {
+    static std::once_flag once;
+    static int r = 0;
+    std::call_once(once, [] {
+      const void* fn = reinterpret_cast<const void*>(&k_gen_pipe<T, N, NSEQ>);
+      (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+      int dev = 0, cus = 0, per = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, THREADS, LDS) == hipSuccess && per > 0)
+        r = cus * per;
+      (void)hipGetLastError();
+    });
+    return r;
+  }
+
+  static int run(GenPipeArgs<T>& a, hipStream_t st) {
+    if (THREADS % 64 != 0 || THREADS > pipe_cap<T, N>() || LDS > 160 * 1024) return ST_UNSUPPORTED;
+    // one row of the column decode per tile; pair loads of the y-face rows aligned
+    if (a.fs.na % (2 * NSEQ) != 0 || (a.inner & 1)) return ST_UNSUPPORTED;
+    if (a.g.lb && ((a.g.bpitch & 1) || (a.g.bplane & 1) || (a.g.bslab & 1))) return ST_UNSUPPORTED;
+    if ((double)(TPS + 1) * (double)a.inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+    const int res = resident();
+    if (res <= 0) return ST_UNSUPPORTED;
+    a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
+    const long long ntiles = a.outer * a.ntile_inner;
+    if (ntiles <= 0) return ST_OK;
+    const long long grid = ntiles < res ? ntiles : res;
+    hipLaunchKernelGGL((k_gen_pipe<T, N, NSEQ>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
+  }
+};
+
 }  // namespace
 
 }  // namespace fast
@@ -277,9 +461,44 @@ int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   }
 }
 
+template <typename T>
+int dst_gen_pipe_pass(const DstTables<T>& tb, T* out, long long outer, long long inner, const DstScale<T>& sc,
+                      const DstGen<T>& gen, hipStream_t st) {
+  if ((double)(tb.N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
+  fast::GenPipeArgs<T> a;
+  a.out = out;
+  a.tw = tb.tw;
+  a.sn = tb.sn;
+  a.outer = outer;
+  a.inner = inner;
+  a.ntile_inner = 0;
+  a.fs = sc;
+  a.g = gen;
+  switch (tb.N) {
+    case 32: return fast::GenPipeLaunch<T, 32>::run(a, st);
+    case 64: return fast::GenPipeLaunch<T, 64>::run(a, st);
+    case 96: return fast::GenPipeLaunch<T, 96>::run(a, st);
+    case 128: return fast::GenPipeLaunch<T, 128>::run(a, st);
+    case 192: return fast::GenPipeLaunch<T, 192>::run(a, st);
+    case 256: return fast::GenPipeLaunch<T, 256>::run(a, st);
+    case 384: return fast::GenPipeLaunch<T, 384>::run(a, st);
+    case 512: return fast::GenPipeLaunch<T, 512>::run(a, st);
+    case 768: return fast::GenPipeLaunch<T, 768>::run(a, st);
+    case 1024: return fast::GenPipeLaunch<T, 1024>::run(a, st);
+    case 2048: return fast::GenPipeLaunch<T, 2048>::run(a, st);
+    case 4096: return fast::GenPipeLaunch<T, 4096>::run(a, st);
+    default: return ST_UNSUPPORTED;
+  }
+}
+
 template int dst_pipe_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
                                   int, hipStream_t);
 template int dst_pipe_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
                                    long long, int, hipStream_t);
+
+template int dst_gen_pipe_pass<float>(const DstTables<float>&, float*, long long, long long,
+                                      const DstScale<float>&, const DstGen<float>&, hipStream_t);
+template int dst_gen_pipe_pass<double>(const DstTables<double>&, double*, long long, long long,
+                                       const DstScale<double>&, const DstGen<double>&, hipStream_t);
 
 }  // namespace ahoc

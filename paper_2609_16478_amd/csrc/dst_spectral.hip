@@ -279,6 +279,10 @@ int dst_gen_pass(const DstTables<T>& tb, T* out, long long outer, long long inne
                  const DstGen<T>& gen, hipStream_t st) {
   if (!dst_fast_supported(tb.N)) return ST_UNSUPPORTED;
   if ((double)(tb.N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
+  if (dst_get_variant() != 3) {  // persistent kernel where its layout conditions hold
+    const int rc = dst_gen_pipe_pass<T>(tb, out, outer, inner, sc, gen, st);
+    if (rc != ST_UNSUPPORTED) return rc;
+  }
   fast::GenArgs<T> a;
   a.out = out;
   a.tw = tb.tw;
