@@ -164,11 +164,12 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
                   long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st,
                   const DstFaces<T>* faces = nullptr);
 
-// Persistent, software-pipelined plain strided pass (dst_pipe.hip); inner must be even.
-// nseq 0 = the kernel's own tile; ST_UNSUPPORTED where no such kernel applies.
+// Persistent, software-pipelined strided pass (dst_pipe.hip): plain, or (fused with
+// faces->mode 1) forward + eigen scaling + face sums; inner must be even.  nseq 0 = the
+// kernel's own tile; ST_UNSUPPORTED where no such kernel applies.
 template <typename T>
 int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer, long long inner,
-                  int nseq, hipStream_t st);
+                  const DstScale<T>* fused, const DstFaces<T>* faces, int nseq, hipStream_t st);
 
 // 0 = automatic (specialised kernel where available), 1 = generic kernel only, 2 = specialised only
 void dst_set_variant(int v);

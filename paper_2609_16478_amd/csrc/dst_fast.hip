@@ -250,10 +250,10 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   if ((double)(N - 1) * (double)inner >= 2147483647.0 || (inner == 1 && 256.0 * pitch >= 2147483647.0))
     return ST_UNSUPPORTED;
   const int kind = fused ? DST_PASS_FUSED : (inner == 1 ? DST_PASS_ROWS : DST_PASS_STRIDED);
-  // plain strided passes with the default tile: persistent pipelined kernel (dst_pipe.hip)
-  if (kind == DST_PASS_STRIDED && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8] == 0 &&
-      dst_get_variant() != 3 && !(faces && faces->mode)) {
-    const int rc = dst_pipe_pass<T>(N, tw, sn, in, out, outer, inner, 0, st);
+  // strided passes (plain, or forward + scaling + face sums) with the default tile:
+  // persistent pipelined kernel (dst_pipe.hip)
+  if (inner > 1 && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8] == 0 && dst_get_variant() != 3) {
+    const int rc = dst_pipe_pass<T>(N, tw, sn, in, out, outer, inner, fused, faces, 0, st);
     if (rc != ST_UNSUPPORTED) return rc;
   }
   fast::Args<T> a;

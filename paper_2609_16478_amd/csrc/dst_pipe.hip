@@ -16,9 +16,9 @@
 // shape is a compile-time constant, so the load/store index arithmetic folds to shifts,
 // and the two pencils of a pair are adjacent columns, read and written as one 8-byte
 // (FP32) or 16-byte (FP64) vector per position.  Requires an even column count per slab.
-// Plain passes only: the fused passes (eigen scaling, face sums, second transform) carry
-// more live state per work item than the prefetched tile leaves room for, and stay with the
-// one-tile-per-group kernels.
+// Plain passes, and the slowest-axis forward pass of the U-solve with eigen scaling and face
+// sums; the fused pass with a second transform stays with the one-tile-per-group kernel (its
+// live state does not leave room for the prefetched tile).
 #include "dst_device.h"
 
 #include <mutex>
@@ -53,7 +53,7 @@ template <typename T, int N> constexpr int pipe_nseq() {
   return nseq;
 }
 
-template <typename T, int N, int NSEQ>
+template <typename T, int N, int NSEQ, bool FACES>
 __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   using PL = PipePlan<N>;
@@ -194,13 +194,62 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     A.x = A.y = T(1);
     B.x = B.y = T(0);
     fft<T, N, PL>(seq, ts, tw);
-    post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+    if constexpr (FACES) {
+      // forward transform of the slowest axis: eigen scaling, face sums of the scaled
+      // spectrum along the pass axis per column; the scaled spectrum itself is the output
+      const long long o = tile / a.ntile_inner;
+      const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+      const long long ca = c0 + 2 * s, cb = ca + 1;
+      auto coef = [&](long long col, T& Ao, T& Bo) {
+        const unsigned ib = (unsigned)col / (unsigned)a.fs.na;  // col < inner < 2^31
+        const long long ia = col - (long long)ib * a.fs.na;
+        if (col >= inner || ia >= a.fs.nva) {
+          Ao = 1;
+          Bo = 0;
+          return;
+        }
+        const T sa = a.fs.s_a[ia];
+        const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
+        Ao = sa + sb + a.fs.c_ab * sa * sb;
+        Bo = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+      };
+      coef(ca, A.x, B.x);
+      coef(cb, A.y, B.y);
+      post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
+      T la = 0, ha = 0, lb = 0, hb = 0;
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        const int m = 1 + ts + i * TPS;
+        if (i < PPT - 1 || m < N) {
+          const cx<T> v = LIN ? seq[pad(1 + ts) + poff(i * TPS)] : seq[pad(m)];
+          const T wl = a.fc.w[m - 1], wh = a.fc.w[L + m - 1];
+          la += v.x * wl;
+          ha += v.x * wh;
+          lb += v.y * wl;
+          hb += v.y * wh;
+        }
+      }
+      seg_sum4<T, TPS>(la, ha, lb, hb, tot, ts);
+      if (ts == 0) {
+        T* fo = a.fc.out + o * a.fc.slab;
+        if (ca < inner) {
+          fo[ca] = la;
+          fo[a.fc.plane + ca] = ha;
+        }
+        if (cb < inner) {
+          fo[cb] = lb;
+          fo[a.fc.plane + cb] = hb;
+        }
+      }
+    } else {
+      post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+    }
     store(tile);
     __syncthreads();  // the next tile overwrites LDS
   }
 }
 
-template <typename T, int N> struct PipeLaunch {
+template <typename T, int N, bool FACES> struct PipeLaunch {
   static constexpr int NSEQ = pipe_nseq<T, N>();
   static constexpr int TPS = N / PipePlan<N>::PPT;
   static constexpr int THREADS = NSEQ * TPS;
@@ -212,7 +261,7 @@ template <typename T, int N> struct PipeLaunch {
     static std::once_flag once;
     static int r = 0;
     std::call_once(once, [] {
-      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ>);
+      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ, FACES>);
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       int dev = 0, cus = 0, per = 0;
       if (hipGetDevice(&dev) == hipSuccess &&
@@ -236,7 +285,7 @@ template <typename T, int N> struct PipeLaunch {
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
     const long long grid = ntiles < res ? ntiles : res;
-    hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, FACES>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
     AHOC_HIP_TRY(hipGetLastError());
     return ST_OK;
   }
@@ -432,8 +481,11 @@ template <typename T, int N> struct GenPipeLaunch {
 
 template <typename T>
 int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer, long long inner,
-                  int nseq, hipStream_t st) {
+                  const DstScale<T>* fused, const DstFaces<T>* faces, int nseq, hipStream_t st) {
   if (inner <= 1 || (inner & 1)) return ST_UNSUPPORTED;
+  // plain passes, or the forward pass with eigen scaling and face sums (no second transform)
+  const bool fc = fused != nullptr;
+  if (fc != (faces && faces->mode == 1)) return ST_UNSUPPORTED;
   // one slab must stay below 2^31 elements
   if ((double)(N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
   fast::Args<T> a;
@@ -444,21 +496,29 @@ int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   a.outer = outer;
   a.inner = inner;
   a.pitch = inner;
+  if (fc) {
+    a.fs = *fused;
+    a.fc = *faces;
+  }
+#define AHOC_PIPE(NN)                                                                       \
+  case NN:                                                                                  \
+    return fc ? fast::PipeLaunch<T, NN, true>::run(a, nseq, st) : fast::PipeLaunch<T, NN, false>::run(a, nseq, st)
   switch (N) {
-    case 32: return fast::PipeLaunch<T, 32>::run(a, nseq, st);
-    case 64: return fast::PipeLaunch<T, 64>::run(a, nseq, st);
-    case 96: return fast::PipeLaunch<T, 96>::run(a, nseq, st);
-    case 128: return fast::PipeLaunch<T, 128>::run(a, nseq, st);
-    case 192: return fast::PipeLaunch<T, 192>::run(a, nseq, st);
-    case 256: return fast::PipeLaunch<T, 256>::run(a, nseq, st);
-    case 384: return fast::PipeLaunch<T, 384>::run(a, nseq, st);
-    case 512: return fast::PipeLaunch<T, 512>::run(a, nseq, st);
-    case 768: return fast::PipeLaunch<T, 768>::run(a, nseq, st);
-    case 1024: return fast::PipeLaunch<T, 1024>::run(a, nseq, st);
-    case 2048: return fast::PipeLaunch<T, 2048>::run(a, nseq, st);
-    case 4096: return fast::PipeLaunch<T, 4096>::run(a, nseq, st);
+    AHOC_PIPE(32);
+    AHOC_PIPE(64);
+    AHOC_PIPE(96);
+    AHOC_PIPE(128);
+    AHOC_PIPE(192);
+    AHOC_PIPE(256);
+    AHOC_PIPE(384);
+    AHOC_PIPE(512);
+    AHOC_PIPE(768);
+    AHOC_PIPE(1024);
+    AHOC_PIPE(2048);
+    AHOC_PIPE(4096);
     default: return ST_UNSUPPORTED;
   }
+#undef AHOC_PIPE
 }
 
 template <typename T>
@@ -492,9 +552,9 @@ int dst_gen_pipe_pass(const DstTables<T>& tb, T* out, long long outer, long long
 }
 
 template int dst_pipe_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
-                                  int, hipStream_t);
+                                  const DstScale<float>*, const DstFaces<float>*, int, hipStream_t);
 template int dst_pipe_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
-                                   long long, int, hipStream_t);
+                                   long long, const DstScale<double>*, const DstFaces<double>*, int, hipStream_t);
 
 template int dst_gen_pipe_pass<float>(const DstTables<float>&, float*, long long, long long,
                                       const DstScale<float>&, const DstGen<float>&, hipStream_t);
