@@ -328,6 +328,123 @@ __global__ void __launch_bounds__(256) k_rhs_u_zm(Geom g, Weights w, const T* __
   }
 }
 
+// 3-D rhs_u marching along z over a tile of TJ consecutive rows: W = V / alpha of every
+// row of the tile at planes k-1, k, k+1 (and the prefetched k+2) stays in registers, so
+// the y-neighbours inside the tile come from registers and only the two halo rows are read
+// per plane (each V and 1/alpha value is read (TJ + 2) / TJ times instead of 3 times); the
+// x-neighbours come from an LDS copy of the tile's rows with their two x-face values.
+template <typename T, int CPT, int TJ>
+__global__ void __launch_bounds__(512) k_rhs_u_tile(Geom g, Weights w, const T* __restrict__ V,
+                                                    const T* __restrict__ Q, const T* __restrict__ ia,
+                                                    const T* __restrict__ src, T* __restrict__ G, int kchunk) {
+  constexpr int NT = 512;
+  constexpr int RL = CPT * NT + 2;  // LDS row: x-face value, ni0 interior values, x-face value
+  __shared__ T row[TJ][RL];
+  const T m0 = (T)w.m0, m1 = (T)w.m1;
+  const int ni0 = g.ni[0], ni1 = g.ni[1], ni2 = g.ni[2];
+  const int ntj = (ni1 + TJ - 1) / TJ;
+  const int nkc = (ni2 + kchunk - 1) / kchunk;
+  const int total = ntj * nkc;
+  // work-groups are dealt round-robin to the 8 XCDs: give each XCD a contiguous range of
+  // tiles, so that neighbouring tiles (sharing halo rows) meet in one L2
+  const int per = (total + 7) / 8;
+  const int idx = (int)(blockIdx.x % 8) * per + (int)(blockIdx.x / 8);
+  if (idx >= total) return;
+  const int kc = idx / ntj, j0 = (idx % ntj) * TJ + 1;
+  const int k0 = kc * kchunk + 1, k1 = min(ni2, k0 + kchunk - 1);
+  const int nr = min(TJ, ni1 - j0 + 1);  // rows of this tile
+  const long long nrowa = g.nn[0];
+  auto arow = [&](int jj, int kk) { return ia + ((long long)kk * g.nn[1] + jj) * nrowa; };
+  // W of row jj at plane kk (0 past the far z face or for rows past the tile)
+  auto wload = [&](int jj, int kk, T* out) {
+    if (kk > g.n[2] || jj > g.n[1]) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) out[q] = T(0);
+      return;
+    }
+    bool f;
+    const T* v = zm_row(g, V, Q, jj, kk, f);
+    const T* a = arow(jj, kk);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int c = threadIdx.x + NT * q;
+      out[q] = c < ni0 ? v[c] * a[c + 1] : T(0);
+    }
+  };
+  T wm[TJ][CPT], wc[TJ][CPT], wp[TJ][CPT];
+#pragma unroll
+  for (int r = 0; r < TJ; ++r) {
+    if (r < nr) {
+      wload(j0 + r, k0 - 1, wm[r]);
+      wload(j0 + r, k0, wc[r]);
+      wload(j0 + r, k0 + 1, wp[r]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) wm[r][q] = wc[r][q] = wp[r][q] = T(0);
+    }
+  }
+  for (int k = k0; k <= k1; ++k) {
+    // halo rows j0 - 1 and j0 + nr at plane k (face rows at the y faces)
+    T hl[CPT], hh[CPT];
+    wload(j0 - 1, k, hl);
+    wload(j0 + nr, k, hh);
+    // prefetch plane k + 2 of the tile's rows
+    T wn[TJ][CPT];
+#pragma unroll
+    for (int r = 0; r < TJ; ++r) {
+      if (r < nr) wload(j0 + r, k + 2, wn[r]);
+      else {
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) wn[r][q] = T(0);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TJ; ++r) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        const int c = threadIdx.x + NT * q;
+        if (c < ni0) row[r][c + 1] = wc[r][q];
+      }
+    }
+    if (threadIdx.x < nr) {
+      const int r = threadIdx.x, j = j0 + r;
+      const T* ac = arow(j, k);
+      row[r][0] = Q[g.face_off[0] + (long long)(k - 1) * ni1 + (j - 1)] * ac[0];
+      row[r][ni0 + 1] = Q[g.face_off[1] + (long long)(k - 1) * ni1 + (j - 1)] * ac[g.n[0]];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < TJ; ++r) {
+      if (r < nr) {
+        const long long e0 = ((long long)(k - 1) * ni1 + (j0 + r - 1)) * g.px;
+#pragma unroll
+        for (int q = 0; q < CPT; ++q) {
+          const int c = threadIdx.x + NT * q;
+          if (c < ni0) {
+            const T ylo = r == 0 ? hl[q] : wc[r > 0 ? r - 1 : 0][q];
+            const T yhi = r == nr - 1 ? hh[q] : wc[r < TJ - 1 ? r + 1 : r][q];
+            T acc = m0 * wc[r][q] + m1 * (row[r][c] + row[r][c + 2] + ylo + yhi + wm[r][q] + wp[r][q]);
+            if (src) acc += src[e0 + c];
+            G[e0 + c] = acc;
+          } else if (c < g.px) {
+            G[e0 + c] = T(0);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < TJ; ++r) {
+#pragma unroll
+      for (int q = 0; q < CPT; ++q) {
+        wm[r][q] = wc[r][q];
+        wc[r][q] = wp[r][q];
+        wp[r][q] = wn[r][q];
+      }
+    }
+  }
+}
+
 template <typename T, int DIM>
 __global__ void k_gather(Geom g, Weights w, const T* __restrict__ U, const T* __restrict__ Q,
                          const T* __restrict__ af, const T* __restrict__ srcq, double* __restrict__ R) {
@@ -803,6 +920,20 @@ int lift(const Geom& g, const Weights& w, const T* Q, const T* src, T* G, hipStr
 template <typename T>
 int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
           hipStream_t st) {
+  if (g.dim == 3 && g.px <= 1024) {
+    // tiles of 4 rows marching along z, 512 threads, 2 columns per thread at most
+    constexpr int TJ = 4;
+    const int cpt = (g.px + 511) / 512;
+    const int kchunk = 32;
+    const int total = ((g.ni[1] + TJ - 1) / TJ) * ((g.ni[2] + kchunk - 1) / kchunk);
+    const unsigned blocks = 8u * (unsigned)((total + 7) / 8);
+    if (cpt <= 1)
+      hipLaunchKernelGGL((k_rhs_u_tile<T, 1, TJ>), dim3(blocks), dim3(512), 0, st, g, w, V, Q, ia, src, G, kchunk);
+    else
+      hipLaunchKernelGGL((k_rhs_u_tile<T, 2, TJ>), dim3(blocks), dim3(512), 0, st, g, w, V, Q, ia, src, G, kchunk);
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
+  }
   if (g.dim == 3) {
     const int cpt = (g.px + 255) / 256;
     const int kchunk = 32;
