@@ -164,6 +164,12 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
                   long long inner, long long pitch, const DstScale<T>* fused, int nseq, hipStream_t st,
                   const DstFaces<T>* faces = nullptr);
 
+// Row pass over contiguous pencils with compile-time indexing (dst_rows.hip); in may
+// equal out.  ST_UNSUPPORTED where no such kernel applies.
+template <typename T>
+int dst_rows_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
+                  hipStream_t st);
+
 // Persistent, software-pipelined strided pass (dst_pipe.hip): plain, or (fused with
 // faces->mode 1) forward + eigen scaling + face sums; inner must be even.  nseq 0 = the
 // kernel's own tile; ST_UNSUPPORTED where no such kernel applies.

@@ -250,6 +250,11 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   if ((double)(N - 1) * (double)inner >= 2147483647.0 || (inner == 1 && 256.0 * pitch >= 2147483647.0))
     return ST_UNSUPPORTED;
   const int kind = fused ? DST_PASS_FUSED : (inner == 1 ? DST_PASS_ROWS : DST_PASS_STRIDED);
+  // row passes with the default tile: compile-time row kernel (dst_rows.hip)
+  if (kind == DST_PASS_ROWS && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8] == 0 && dst_get_variant() != 3) {
+    const int rc = dst_rows_pass<T>(N, tw, sn, in, out, outer, pitch, st);
+    if (rc != ST_UNSUPPORTED) return rc;
+  }
   // strided passes (plain, or forward + scaling + face sums) with the default tile:
   // persistent pipelined kernel (dst_pipe.hip)
   if (inner > 1 && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8] == 0 && dst_get_variant() != 3) {

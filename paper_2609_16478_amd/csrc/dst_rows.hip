@@ -1,0 +1,172 @@
+// DST-I pass over contiguous pencils (rows of the fastest axis), gfx950.
+//
+// The transform is the one of the other pass kernels (two real rows packed in one complex
+// FFT, symmetric pre-weighting, split + prefix sum).  This kernel is specialised for the
+// row layout: NSEQ row pairs of TPS lanes each per work-group (at least one wavefront),
+// all index arithmetic compile-time except the work-group's base row, the rows addressed
+// through a uniform base and 32-bit per-lane offsets, and the LDS positions through one
+// padded base per direction plus immediate offsets.  Many small work-groups share a compute
+// unit, so the load, transform and store phases of different groups overlap.
+#include "dst_device.h"
+
+#include <mutex>
+
+namespace ahoc {
+
+namespace fast {
+
+namespace {
+
+template <int N> using RPlan = PlanOf<N, N == 512 || N == 1024>;
+template <int N> constexpr int rows_nseq() {
+  constexpr int TPS = N / RPlan<N>::PPT;
+  return TPS >= 64 ? 1 : 64 / TPS;
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows(const T* __restrict__ in,
+                                                                                T* __restrict__ out,
+                                                                                const cx<T>* __restrict__ tw,
+                                                                                const T* __restrict__ sn,
+                                                                                long long nrows, long long pitch) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using PL = RPlan<N>;
+  constexpr int PPT = PL::PPT;
+  constexpr int TPS = N / PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int L = N - 1;
+  constexpr int HN = N / 2;
+  constexpr int U = PPT / 2;
+  constexpr int LDQ = seq_stride<N>();
+  constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  constexpr bool LIN = TPS % 32 == 0;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int q = threadIdx.x / TPS;  // pair of this thread
+  const int t = threadIdx.x - q * TPS;
+  cx<T>* seq = lds + q * LDQ;
+  cx<T>* tot = lds + NSEQ * LDQ + q * NTOT;
+  const long long r0 = (long long)blockIdx.x * (2 * NSEQ);  // first row of the work-group
+  const long long ra = r0 + 2 * q;
+  const bool oka = ra < nrows, okb = ra + 1 < nrows;
+  // rows of the work-group from a uniform base; lane offsets (bytes) stay below 2^32
+  const SBase src(in + r0 * pitch);
+  const unsigned oa = (unsigned)((2 * q) * pitch * (long long)sizeof(T));
+  const unsigned ob = oa + (unsigned)(pitch * (long long)sizeof(T));
+
+  // ---- load + pre-weighting w_m = s_m (z_m + z_{N-m}) + (z_m - z_{N-m}) / 2
+  {
+    cx<T>* lo = seq + pad(1 + t);
+    cx<T>* hi = seq + pad(N - 1 - t);
+    T xa[U], xb[U], ya[U], yb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = 1 + t + u * TPS;
+      const unsigned e1 = (unsigned)((m - 1) * (int)sizeof(T)), e2 = (unsigned)((N - m - 1) * (int)sizeof(T));
+      xa[u] = oka ? src.ld<T>(oa + e1) : T(0);
+      xb[u] = okb ? src.ld<T>(ob + e1) : T(0);
+      const bool mid = u == U - 1 && m == HN;
+      ya[u] = (oka && !mid) ? src.ld<T>(oa + e2) : T(0);
+      yb[u] = (okb && !mid) ? src.ld<T>(ob + e2) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = 1 + t + u * TPS;
+      cx<T>* plo = LIN ? lo + poff(u * TPS) : seq + pad(m);
+      cx<T>* phi = LIN ? hi - poff(u * TPS) : seq + pad(N - m);
+      if (u == U - 1 && m == HN) {  // the middle position pairs with itself: 2 z
+        cx<T> o;
+        o.x = T(2) * xa[u];
+        o.y = T(2) * xb[u];
+        *plo = o;
+      } else {
+        const T w = sn[m];
+        const T sx = w * (xa[u] + ya[u]), sy = w * (xb[u] + yb[u]);
+        const T dx = T(0.5) * (xa[u] - ya[u]), dy = T(0.5) * (xb[u] - yb[u]);
+        cx<T> o1, o2;
+        o1.x = sx + dx;
+        o1.y = sy + dy;
+        o2.x = sx - dx;
+        o2.y = sy - dy;
+        *plo = o1;
+        *phi = o2;
+      }
+    }
+    if (t == 0) {
+      cx<T> z;
+      z.x = T(0);
+      z.y = T(0);
+      seq[0] = z;
+    }
+  }
+  __syncthreads();
+
+  cx<T> A, B;
+  A.x = A.y = T(1);
+  B.x = B.y = T(0);
+  fft<T, N, PL>(seq, t, tw);
+  post<T, N, PL, false>(seq, tot, t, A, B, nullptr, T(0));
+
+  // ---- store positions m = 1 + t + k TPS
+  const SBase dst(out + r0 * pitch);
+  const cx<T>* lo = seq + pad(1 + t);
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int m = 1 + t + k * TPS;
+    if (k < PPT - 1 || m < N) {
+      const cx<T> v = LIN ? lo[poff(k * TPS)] : seq[pad(m)];
+      const unsigned e = (unsigned)((m - 1) * (int)sizeof(T));
+      if (oka) dst.st<T>(oa + e, v.x);
+      if (okb) dst.st<T>(ob + e, v.y);
+    }
+  }
+}
+
+template <typename T, int N> int rows_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
+                                             long long pitch, hipStream_t st) {
+  constexpr int TPS = N / RPlan<N>::PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int THREADS = NSEQ * TPS;
+  constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
+  if (THREADS % 64 != 0 || THREADS > 1024 || LDS > 64 * 1024) return ST_UNSUPPORTED;
+  // per-lane byte offsets within a work-group's rows
+  if ((double)(2 * NSEQ) * (double)pitch * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+  const long long blocks = (nrows + 2 * NSEQ - 1) / (2 * NSEQ);
+  if (blocks <= 0) return ST_OK;
+  if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+  hipLaunchKernelGGL((k_dst_rows<T, N>), dim3((unsigned)blocks), dim3(THREADS), LDS, st, in, out, tw, sn, nrows,
+                     pitch);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+}  // namespace
+
+}  // namespace fast
+
+template <typename T>
+int dst_rows_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
+                  hipStream_t st) {
+  if (pitch < N - 1) return ST_INVALID;
+  switch (N) {
+    case 32: return fast::rows_launch<T, 32>(in, out, tw, sn, nrows, pitch, st);
+    case 64: return fast::rows_launch<T, 64>(in, out, tw, sn, nrows, pitch, st);
+    case 96: return fast::rows_launch<T, 96>(in, out, tw, sn, nrows, pitch, st);
+    case 128: return fast::rows_launch<T, 128>(in, out, tw, sn, nrows, pitch, st);
+    case 192: return fast::rows_launch<T, 192>(in, out, tw, sn, nrows, pitch, st);
+    case 256: return fast::rows_launch<T, 256>(in, out, tw, sn, nrows, pitch, st);
+    case 384: return fast::rows_launch<T, 384>(in, out, tw, sn, nrows, pitch, st);
+    case 512: return fast::rows_launch<T, 512>(in, out, tw, sn, nrows, pitch, st);
+    case 768: return fast::rows_launch<T, 768>(in, out, tw, sn, nrows, pitch, st);
+    case 1024: return fast::rows_launch<T, 1024>(in, out, tw, sn, nrows, pitch, st);
+    case 2048: return fast::rows_launch<T, 2048>(in, out, tw, sn, nrows, pitch, st);
+    case 4096: return fast::rows_launch<T, 4096>(in, out, tw, sn, nrows, pitch, st);
+    default: return ST_UNSUPPORTED;
+  }
+}
+
+template int dst_rows_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
+                                  hipStream_t);
+template int dst_rows_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
+                                   long long, hipStream_t);
+
+}  // namespace ahoc
