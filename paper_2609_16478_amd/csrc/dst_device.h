@@ -244,6 +244,22 @@ template <> struct SBase::Raw<8> { typedef unsigned type __attribute__((ext_vect
 template <> struct SBase::Raw<16> { typedef unsigned type __attribute__((ext_vector_type(4))); };
 
 
+// Synchronisation of the LDS exchanges inside one pencil pair's transform.  When the TPS
+// lanes of a pair lie in one wavefront (TPS <= 64, a power of two dividing 64) only that
+// wavefront exchanges data: its LDS accesses complete in order, so a wavefront-scope fence
+// (which keeps the compiler from moving accesses across it) is enough and the other
+// wavefronts of the work-group run on.  Otherwise a work-group barrier.  Phases that read
+// other pairs' data (tile loads and stores) keep their own work-group barriers.
+template <int TPS> __device__ __forceinline__ void pair_sync() {
+  if constexpr (TPS <= 64 && 64 % TPS == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham stage (radix R, input blocks Ns) over the sequence in LDS.
 template <typename T, int N, int R, int NS, int PPT>
 __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restrict__ tw) {
@@ -272,7 +288,7 @@ __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restric
       for (int r = 0; r < R; ++r) v[b][r] = seq[pad(j + r * NR)];
     }
   }
-  __syncthreads();
+  pair_sync<TPS>();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int j = ts + b * TPS;
@@ -297,7 +313,7 @@ __device__ __forceinline__ void stage(cx<T>* seq, int ts, const cx<T>* __restric
       for (int r = 0; r < R; ++r) seq[pad(base + r * NS)] = v[b][r];
     }
   }
-  __syncthreads();
+  pair_sync<TPS>();
 }
 
 template <typename T, int N, class P> __device__ __forceinline__ void fft(cx<T>* seq, int ts, const cx<T>* __restrict__ tw) {
@@ -343,7 +359,7 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
     ev[i].x = T(0.5) * (w2.y - w1.y);
     ev[i].y = T(0.5) * (w1.x - w2.x);
   }
-  __syncthreads();
+  pair_sync<TPS>();
   // (b) even outputs in place, odd slots temporarily hold the increments c_k
 #pragma unroll
   for (int i = 0; i < H; ++i) {
@@ -363,7 +379,7 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
     seq[pad(2 * k)] = e;
     seq[pad(2 * k + 1)] = cc[i];
   }
-  __syncthreads();
+  pair_sync<TPS>();
   // (c) prefix sum: serial over this thread's contiguous chunk, then lane scan of totals
   const int k0 = ts * H;
   T ax = 0, ay = 0;
@@ -417,7 +433,7 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
     }
     seq[pad(2 * k + 1)] = o;
   }
-  __syncthreads();
+  pair_sync<TPS>();
 }
 
 // Pre-weighting of a sequence already in LDS (second transform of the fused pass).
@@ -435,7 +451,7 @@ __device__ __forceinline__ void pre_lds(cx<T>* seq, int ts, const T* __restrict_
     z[i] = LIN ? lo[poff(i * TPS)] : seq[pad(m)];
     zr[i] = LIN ? hi[-poff(i * TPS)] : seq[pad(N - m)];
   }
-  __syncthreads();
+  pair_sync<TPS>();
 #pragma unroll
   for (int i = 0; i < PPT / 2; ++i) {
     const int m = 1 + ts + i * TPS;
@@ -461,7 +477,7 @@ __device__ __forceinline__ void pre_lds(cx<T>* seq, int ts, const T* __restrict_
     zz.y = 0;
     seq[0] = zz;
   }
-  __syncthreads();
+  pair_sync<TPS>();
 }
 
 template <typename T> struct Args {

@@ -131,6 +131,7 @@ __global__ void __launch_bounds__((cap<T, N, FUSED, ROWP>())) k_dst_fast(Args<T>
     post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
   }
 
+  __syncthreads();  // the store reads other pairs' sequences
   store_tile<T, N>(lds, dst, rows, nseq, lgq, ncols, es, ps);
 }
 

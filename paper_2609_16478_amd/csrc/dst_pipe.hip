@@ -244,6 +244,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     } else {
       post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
     }
+    __syncthreads();  // the store reads other pairs' sequences
     store(tile);
     __syncthreads();  // the next tile overwrites LDS
   }
@@ -418,6 +419,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     pre_lds<T, N, PL>(seq, ts, a.sn);
     fft<T, N, PL>(seq, ts, a.tw);
     post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+    __syncthreads();  // the store reads other pairs' sequences
     // ---- store (uniform row bases, fixed per-lane byte offsets)
     if (c0 + 2 * q < inner) {
       const long long rowb = inner * (long long)sizeof(T);

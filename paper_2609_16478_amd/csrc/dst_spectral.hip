@@ -160,6 +160,7 @@ __global__ void __launch_bounds__((cap<T, N, true, false>())) k_dst_gen(GenArgs<
   pre_lds<T, N, PL>(seq, ts, a.sn);
   fft<T, N, PL>(seq, ts, a.tw);
   post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+  __syncthreads();  // the store reads other pairs' sequences
   store_tile<T, N>(lds, a.out + o * (long long)L * a.inner + c0, false, nseq, lgq, ncols, (int)a.inner, 1);
 }
 
