@@ -273,6 +273,64 @@ int gen_launch(const GenArgs<T>& a0, long long outer, hipStream_t st) {
   return ST_OK;
 }
 
+// Face contractions of whole planes (x-face row dots and y-face column sums), one wavefront
+// per row: a lane holds CPL = px / 64 columns, so a row's dot needs one wavefront reduction
+// for 64 * CPL values; the column sums accumulate per wavefront in registers and are
+// combined through LDS once per plane.
+template <typename T, int CPL>
+__global__ void __launch_bounds__(256) k_face_reduce_w(const T* __restrict__ W, long long planes, int ny, int nx,
+                                                       int px, const T* __restrict__ wx, const T* __restrict__ wy,
+                                                       T* __restrict__ fx, T* __restrict__ fy, long long fx_side,
+                                                       long long fx_plane, long long fx_row) {
+  __shared__ T col[4][2][CPL * 64];
+  const long long o = blockIdx.x;
+  const T* __restrict__ Wp = W + o * (long long)ny * px;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  T wxl[CPL], wxh[CPL], accl[CPL], acch[CPL];
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    const int c = lane + 64 * j;
+    wxl[j] = c < nx ? wx[c] : T(0);
+    wxh[j] = c < nx ? wx[nx + c] : T(0);
+    accl[j] = acch[j] = T(0);
+  }
+#pragma unroll 2
+  for (int ky = wv; ky < ny; ky += 4) {
+    const T* __restrict__ row = Wp + (long long)ky * px;
+    T v[CPL];
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) v[j] = row[lane + 64 * j];
+    const T yl = wy[ky], yh = wy[ny + ky];
+    T dl = 0, dh = 0;
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      dl += v[j] * wxl[j];
+      dh += v[j] * wxh[j];
+      accl[j] += v[j] * yl;
+      acch[j] += v[j] * yh;
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      dl += __shfl_xor(dl, m, 64);
+      dh += __shfl_xor(dh, m, 64);
+    }
+    if (lane == 0) {
+      fx[o * fx_plane + ky * fx_row] = dl;
+      fx[fx_side + o * fx_plane + ky * fx_row] = dh;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < CPL; ++j) {
+    col[wv][0][lane + 64 * j] = accl[j];
+    col[wv][1][lane + 64 * j] = acch[j];
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < px; c += 256) {
+    fy[o * px + c] = col[0][0][c] + col[1][0][c] + col[2][0][c] + col[3][0][c];
+    fy[(planes + o) * px + c] = col[0][1][c] + col[1][1][c] + col[2][1][c] + col[3][1][c];
+  }
+}
+
 }  // namespace fast
 
 template <typename T>
@@ -313,6 +371,29 @@ template <typename T>
 int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* wx, const T* wy, T* fx, T* fy,
                 long long fx_side, long long fx_plane, long long fx_row, hipStream_t st) {
   if (planes <= 0 || ny <= 0) return ST_OK;
+  // FP32: one wavefront per row (the FP64 form keeps the 256-lane rows: its 16-column
+  // wavefront variant loses occupancy to registers and measured slower)
+  if (sizeof(T) == 4 && fy && px % 64 == 0 && px <= 1024 && planes <= 0x7fffffffLL) {
+#define AHOC_FRW(C)                                                                                     \
+  case C:                                                                                               \
+    hipLaunchKernelGGL((fast::k_face_reduce_w<T, C>), dim3((unsigned)planes), dim3(256), 0, st, W, planes, ny, \
+                       nx, px, wx, wy, fx, fy, fx_side, fx_plane, fx_row);                              \
+    AHOC_HIP_TRY(hipGetLastError());                                                                    \
+    return ST_OK
+    switch (px / 64) {
+      AHOC_FRW(1);
+      AHOC_FRW(2);
+      AHOC_FRW(3);
+      AHOC_FRW(4);
+      AHOC_FRW(6);
+      AHOC_FRW(8);
+      AHOC_FRW(12);
+      AHOC_FRW(16);
+      default:
+        break;
+    }
+#undef AHOC_FRW
+  }
   const int cpt = (px + 255) / 256;
   // whole planes when column sums are formed; otherwise split rows for enough work-groups
   int rows_per = ny;

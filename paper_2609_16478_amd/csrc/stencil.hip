@@ -921,7 +921,8 @@ template <typename T>
 int rhs_u(const Geom& g, const Weights& w, const T* V, const T* Q, const T* ia, const T* src, T* G,
           hipStream_t st) {
   if (g.dim == 3 && g.px <= 1024) {
-    // tiles of 4 rows marching along z, 512 threads, 2 columns per thread at most
+    // tiles of 4 rows marching along z, 512 threads, 2 columns per thread at most (8-row
+    // tiles and 64-plane chunks measured slower)
     constexpr int TJ = 4;
     const int cpt = (g.px + 511) / 512;
     const int kchunk = 32;
