@@ -252,7 +252,7 @@ def main():
                    "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_dst_pipe<float,{n},16> (FP32 DST-I pass along y, strided pencils, persistent and pipelined)",
+                     "kernel": f"k_dst_pipe<float,{n},16,false> (FP32 DST-I pass along y, strided pencils, persistent and pipelined)",
                      "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6},
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
     }
