@@ -16,9 +16,9 @@
 // shape is a compile-time constant, so the load/store index arithmetic folds to shifts,
 // and the two pencils of a pair are adjacent columns, read and written as one 8-byte
 // (FP32) or 16-byte (FP64) vector per position.  Requires an even column count per slab.
-// Plain passes, and the slowest-axis forward pass of the U-solve with eigen scaling and face
-// sums; the fused pass with a second transform stays with the one-tile-per-group kernel (its
-// live state does not leave room for the prefetched tile).
+// Plain passes, the slowest-axis forward pass of the U-solve with eigen scaling and face
+// sums, and (FP64) the whole slowest-axis Poisson pass (forward, scaling, inverse), whose
+// prefetch is issued after the first transform.
 #include "dst_device.h"
 
 #include <mutex>
@@ -53,7 +53,7 @@ template <typename T, int N> constexpr int pipe_nseq() {
   return nseq;
 }
 
-template <typename T, int N, int NSEQ, bool FACES>
+template <typename T, int N, int NSEQ, int MODE>
 __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   using PL = PipePlan<N>;
@@ -188,15 +188,20 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     to_lds();
     __syncthreads();
     const long long nxt = tile + gridDim.x;
-    if (nxt < ntiles) load(nxt);  // in flight during the transform below
+    // the next tile is in flight during the transform below (with two transforms, during
+    // the second one only: the prefetched registers are not live across both)
+    if constexpr (MODE != 2) {
+      if (nxt < ntiles) load(nxt);
+    }
 
     cx<T> A, B;
     A.x = A.y = T(1);
     B.x = B.y = T(0);
     fft<T, N, PL>(seq, ts, tw);
-    if constexpr (FACES) {
-      // forward transform of the slowest axis: eigen scaling, face sums of the scaled
-      // spectrum along the pass axis per column; the scaled spectrum itself is the output
+    if constexpr (MODE != 0) {
+      // forward transform of the slowest axis and eigen scaling; then either the face sums
+      // of the scaled spectrum along the pass axis per column (MODE 1: the scaled spectrum
+      // itself is the output) or the inverse transform (MODE 2: a whole Poisson pass)
       const long long o = tile / a.ntile_inner;
       const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
       const long long ca = c0 + 2 * s, cb = ca + 1;
@@ -216,6 +221,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       coef(ca, A.x, B.x);
       coef(cb, A.y, B.y);
       post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
+      if constexpr (MODE == 2) {
+        if (nxt < ntiles) load(nxt);
+        pre_lds<T, N, PL>(seq, ts, a.sn);
+        fft<T, N, PL>(seq, ts, tw);
+        A.x = A.y = T(1);
+        B.x = B.y = T(0);
+        post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+      } else {
       T la = 0, ha = 0, lb = 0, hb = 0;
 #pragma unroll
       for (int i = 0; i < PPT; ++i) {
@@ -241,6 +254,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
           fo[a.fc.plane + cb] = hb;
         }
       }
+      }
     } else {
       post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
     }
@@ -250,7 +264,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   }
 }
 
-template <typename T, int N, bool FACES> struct PipeLaunch {
+template <typename T, int N, int MODE> struct PipeLaunch {
   static constexpr int NSEQ = pipe_nseq<T, N>();
   static constexpr int TPS = N / PipePlan<N>::PPT;
   static constexpr int THREADS = NSEQ * TPS;
@@ -262,7 +276,7 @@ template <typename T, int N, bool FACES> struct PipeLaunch {
     static std::once_flag once;
     static int r = 0;
     std::call_once(once, [] {
-      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ, FACES>);
+      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ, MODE>);
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       int dev = 0, cus = 0, per = 0;
       if (hipGetDevice(&dev) == hipSuccess &&
@@ -286,7 +300,7 @@ template <typename T, int N, bool FACES> struct PipeLaunch {
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
     const long long grid = ntiles < res ? ntiles : res;
-    hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, FACES>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, MODE>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
     AHOC_HIP_TRY(hipGetLastError());
     return ST_OK;
   }
@@ -485,9 +499,14 @@ template <typename T>
 int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer, long long inner,
                   const DstScale<T>* fused, const DstFaces<T>* faces, int nseq, hipStream_t st) {
   if (inner <= 1 || (inner & 1)) return ST_UNSUPPORTED;
-  // plain passes, or the forward pass with eigen scaling and face sums (no second transform)
+  // plain passes (mode 0), the forward pass with eigen scaling and face sums (mode 1), or a
+  // whole slowest-axis Poisson pass: forward, scaling, inverse (mode 2)
   const bool fc = fused != nullptr;
-  if (fc != (faces && faces->mode == 1)) return ST_UNSUPPORTED;
+  if (!fc && faces && faces->mode) return ST_UNSUPPORTED;
+  const int mode = !fc ? 0 : (faces && faces->mode == 1 ? 1 : 2);
+  // the two-transform pass spills registers: at N = 1024 it is 20 % faster than the
+  // one-tile kernel in FP64 and 50 % slower in FP32, which keeps the one-tile kernel
+  if (mode == 2 && sizeof(T) == 4) return ST_UNSUPPORTED;
   // one slab must stay below 2^31 elements
   if ((double)(N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
   fast::Args<T> a;
@@ -498,13 +517,13 @@ int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   a.outer = outer;
   a.inner = inner;
   a.pitch = inner;
-  if (fc) {
-    a.fs = *fused;
-    a.fc = *faces;
-  }
+  if (fc) a.fs = *fused;
+  if (faces) a.fc = *faces;
 #define AHOC_PIPE(NN)                                                                       \
   case NN:                                                                                  \
-    return fc ? fast::PipeLaunch<T, NN, true>::run(a, nseq, st) : fast::PipeLaunch<T, NN, false>::run(a, nseq, st)
+    return mode == 1 ? fast::PipeLaunch<T, NN, 1>::run(a, nseq, st)                        \
+                     : (mode == 2 ? fast::PipeLaunch<T, NN, 2>::run(a, nseq, st)             \
+                                  : fast::PipeLaunch<T, NN, 0>::run(a, nseq, st))
   switch (N) {
     AHOC_PIPE(32);
     AHOC_PIPE(64);
