@@ -63,8 +63,10 @@ def test_dst_axis_x_y_z(ah, variant, N, prec):
     out = ah.dst1(xt, 0, p).double().cpu().numpy()
     ref = odst.dst1(x.astype(np.float32).astype(np.float64) if prec == "fp32" else x, axis=2)
     assert _rel(out, ref) < tol
-    # the same length on the strided axes (y, then z), with ragged column tiles
-    for axis, shp in ((1, (3, N - 1, 37)), (2, (N - 1, 5, 13))):
+    # the same length on the strided axes (y, then z), with ragged column tiles: odd widths
+    # (one-tile kernels) and even widths that are not a multiple of the tile width (the
+    # persistent kernels, whose last tile of each slab is partial)
+    for axis, shp in ((1, (3, N - 1, 37)), (2, (N - 1, 5, 13)), (1, (2, N - 1, 70)), (2, (N - 1, 6, 12))):
         x = rng.standard_normal(shp)
         xin = x.astype(np.float32).astype(np.float64) if prec == "fp32" else x
         out = ah.dst1(torch.from_numpy(x).cuda(), axis, p).double().cpu().numpy()
