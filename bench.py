@@ -132,6 +132,10 @@ def main():
         print(f"[bench] {args.profile_matvec} Schur matvecs done (n={n})", file=sys.stderr)
         return
 
+    # kernel classes that launch kernels themselves (the matvec and residual classes wrap them)
+    leaf = ("dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "dst_gen",
+            "face_reduce", "precond")
+
     def run(prec, steps, warmup, **opts):
         s = ah.Solver(prob, precision=prec, **opts)
         out = torch.empty(s.nodal_shape, dtype=torch.float64, device=dev)
@@ -147,8 +151,13 @@ def main():
             print(f"[bench] step prec={prec} {st}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t) / steps
+        # one more, untimed and profiled solve: algorithmic bytes of every kernel launched
+        s.profile(True)
+        s.solve(out=out)
+        kt = s.kernel_times()
+        model_bytes = sum(c * b for k, (ms, c, b) in kt.items() if k in leaf)
         s.close()
-        return out, dt, stats
+        return out, dt, stats, model_bytes
 
     # untimed FP64 reference at a tight tolerance: the accuracy yardstick of both forms
     ref = ah.Solver(prob, precision=ah.FP64, tol=1e-13)
@@ -161,16 +170,17 @@ def main():
     def errs(u):
         return (((u - u_ref).abs().max() / nrm_ref).item(), ((u - u_exact).abs().max() / nrm_exact).item())
 
-    u_mx, dt_mx, st_mx = run(ah.MIXED, args.steps, args.warmup, tol=args.tol)
+    u_mx, dt_mx, st_mx, bytes_mx = run(ah.MIXED, args.steps, args.warmup, tol=args.tol)
     err_mx_ref, err_mx_exact = errs(u_mx)
     del u_mx
     result_fp64 = None
     if not args.no_fp64:
-        u_64, dt_64, st_64 = run(ah.FP64, args.steps, args.warmup, tol=args.tol)
+        u_64, dt_64, st_64, bytes_64 = run(ah.FP64, args.steps, args.warmup, tol=args.tol)
         e64_ref, e64_exact = errs(u_64)
         result_fp64 = {"ms_per_step": dt_64 * 1e3, "dof_per_s": n ** 3 / dt_64,
                        "gmres_iters": st_64[-1].gmres_iters, "rel_err_vs_fp64_ref": e64_ref,
-                       "rel_err_vs_exact": e64_exact, "speedup_mixed_over_fp64": dt_64 / dt_mx}
+                       "rel_err_vs_exact": e64_exact, "speedup_mixed_over_fp64": dt_64 / dt_mx,
+                       "model_bytes": bytes_64, "end_to_end_hbm_frac": bytes_64 / dt_64 / (HBM_PEAK_GBS * 1e9)}
         del u_64
 
     # roofline of the dominant kernel of the FP32 matvec, timed live with HIP events on the
@@ -186,6 +196,19 @@ def main():
     s.close()
     del y, q
     ms, cnt, bytes_launch = kt["dst_strided"]
+    # reference device bandwidth: a plain 2 GiB device-to-device copy (the runtime blit
+    # kernel, read + write), HIP events
+    xc = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
+    yc = torch.empty_like(xc)
+    yc.copy_(xc)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        yc.copy_(xc)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbps = 5 * 2 * xc.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del xc, yc
     avg_s = ms / cnt / 1e3
     achieved = bytes_launch / avg_s / 1e9
     pmc = _pmc_traffic(_src_hash())
@@ -248,12 +271,14 @@ def main():
                    "n": n, "dof": n ** 3, "interior_dof": (n - 1) ** 3,
                    "gmres_iters": st.gmres_iters, "sweeps": st.sweeps, "schur_relres": st.schur_relres,
                    "rel_err_vs_fp64_ref": err_mx_ref, "rel_err_vs_exact": err_mx_exact,
+                   "model_bytes": bytes_mx, "end_to_end_hbm_frac": bytes_mx / dt_mx / (HBM_PEAK_GBS * 1e9),
                    "fp64_ref": {"tol": 1e-13, "gmres_iters": st_ref.gmres_iters},
                    "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_dst_pipe<float,{n},16,false> (FP32 DST-I pass along y, strided pencils, persistent and pipelined)",
-                     "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6},
+                     "kernel": f"k_dst_pipe<float,{n},16,0> (FP32 DST-I pass along y, strided pencils, persistent and pipelined)",
+                     "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6,
+                     "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps},
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
     }
     print(json.dumps(line), flush=True)

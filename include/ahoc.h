@@ -207,8 +207,8 @@ enum {
 ahoc_status ahoc_profile(ahoc_handle* h, int enable);
 
 /* Accumulated time (ms) and launch count of one kernel class since ahoc_profile,
- * and the algorithmic bytes one launch moves (what the operation must read and
- * write at least once).  Synchronises the device.  Any output may be NULL. */
+ * and the algorithmic bytes one launch moves on average (what the operation must
+ * read and write at least once).  Synchronises the device.  Any output may be NULL. */
 ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long long* launches,
                               double* bytes_per_launch);
 

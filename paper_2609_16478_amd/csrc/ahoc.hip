@@ -112,11 +112,11 @@ struct ahoc_handle {
   bool prof = false;
   std::vector<hipEvent_t> evpool;
   size_t evused = 0;
-  struct Pending { int kind; hipEvent_t a, b; };
+  struct Pending { int kind; hipEvent_t a, b; double bytes; };
   std::vector<Pending> pending;
   double kms[AHOC_NKIND] = {0};
   long long kcnt[AHOC_NKIND] = {0};
-  double kbytes[AHOC_NKIND] = {0};
+  double kbytes[AHOC_NKIND] = {0};  // accumulated algorithmic bytes
 };
 
 namespace ahoc {
@@ -153,8 +153,7 @@ void tend(ahoc_handle* h, int kind, hipEvent_t a, double bytes, hipStream_t st) 
   if (!h->prof || !a) return;
   hipEvent_t b = h->evpool[h->evused++];
   (void)hipEventRecord(b, st);
-  h->pending.push_back({kind, a, b});
-  h->kbytes[kind] = bytes;
+  h->pending.push_back({kind, a, b, bytes});
 }
 
 // Fold completed event pairs into the per-kind totals (the stream must be idle).
@@ -164,6 +163,7 @@ void tresolve(ahoc_handle* h) {
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       h->kms[p.kind] += ms;
       h->kcnt[p.kind] += 1;
+      h->kbytes[p.kind] += p.bytes;
     }
   }
   h->pending.clear();
@@ -1410,6 +1410,7 @@ ahoc_status ahoc_profile(ahoc_handle* h, int enable) {
   for (int k = 0; k < AHOC_NKIND; ++k) {
     h->kms[k] = 0;
     h->kcnt[k] = 0;
+    h->kbytes[k] = 0;
   }
   h->prof = enable != 0;
   return AHOC_OK;
@@ -1422,7 +1423,7 @@ ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long l
   ahoc::tresolve(h);
   if (total_ms) *total_ms = h->kms[kind];
   if (launches) *launches = h->kcnt[kind];
-  if (bytes_per_launch) *bytes_per_launch = h->kbytes[kind];
+  if (bytes_per_launch) *bytes_per_launch = h->kcnt[kind] ? h->kbytes[kind] / (double)h->kcnt[kind] : 0.0;
   return AHOC_OK;
 }
 
