@@ -94,6 +94,11 @@ typedef struct {
                          0 on the coupled system -- FP64 residual of all three equation
                          groups, corrections solved and recovered in FP32, stop on
                          sweep_tol                                                     */
+  int use_graph;      /* 1: the GMRES operator of each Krylov step (boundary-symbol
+                         preconditioner and Schur matvec) is captured once as a HIP graph
+                         and replayed; needs a stream that can be captured (not the
+                         legacy default stream: there the launches stay eager).  Ignored
+                         while ahoc_profile is on.  0 (default): eager launches        */
 } ahoc_options;
 
 typedef struct {
@@ -104,6 +109,8 @@ typedef struct {
   double schur_relres;   /* last GMRES relative residual estimate       */
   double last_update;    /* last sweep's max |dU| / max |U|             */
   double t_solve_ms;     /* wall time of ahoc_solve                     */
+  int graph_steps;       /* Krylov steps whose operator ran as a HIP graph replay
+                            (use_graph); 0 when the launches stayed eager  */
 } ahoc_stats;
 
 typedef struct ahoc_handle ahoc_handle;

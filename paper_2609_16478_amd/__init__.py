@@ -39,12 +39,13 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("tol", c_double),
                 ("inner_tol", c_double), ("sweep_tol", c_double), ("max_sweeps", c_int),
                 ("tile_fp64", c_int), ("tile_fp32", c_int), ("precond", c_int),
-                ("refine", c_int)]
+                ("refine", c_int), ("use_graph", c_int)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("converged", c_int), ("gmres_iters", c_int), ("sweeps", c_int), ("matvecs", c_int),
-                ("schur_relres", c_double), ("last_update", c_double), ("t_solve_ms", c_double)]
+                ("schur_relres", c_double), ("last_update", c_double), ("t_solve_ms", c_double),
+                ("graph_steps", c_int)]
 
 
 _H = c_void_p
@@ -146,11 +147,12 @@ class Stats:
     schur_relres: float
     last_update: float
     t_solve_ms: float
+    graph_steps: int = 0
 
 
 def _stats(s: _Stats) -> Stats:
     return Stats(bool(s.converged), s.gmres_iters, s.sweeps, s.matvecs, s.schur_relres,
-                 s.last_update, s.t_solve_ms)
+                 s.last_update, s.t_solve_ms, s.graph_steps)
 
 
 def _problem_struct(n, lo, hi, tens):

@@ -88,6 +88,15 @@ struct ahoc_handle {
   double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *part = nullptr, *y = nullptr;
   double *resid = nullptr, *beta = nullptr, *bvec = nullptr, *dq = nullptr, *rvec = nullptr, *R = nullptr;
   double* zvec = nullptr;    // preconditioned Krylov vector
+  // GMRES operator (preconditioner and Schur matvec) captured as a HIP graph per operator
+  // precision ([0] FP32, [1] FP64), replayed once per Krylov step from the fixed input gin
+  // to the fixed output gout; captured on its second use, eager when capture fails
+  hipGraphExec_t opg[2] = {nullptr, nullptr};
+  int opg_uses[2] = {0, 0};
+  bool opg_failed[2] = {false, false};
+  double* gin = nullptr;
+  double* gout = nullptr;
+  long long graph_steps = 0;  // graph replays so far (reported per solve)
   double* b64 = nullptr;     // mixed, Schur refinement: FP64 right-hand side
   // boundary-symbol preconditioner, applied in FP64 for either precision (its low modes
   // are damped ~N-fold, so FP32 rounding of the face transforms would be amplified):
@@ -271,7 +280,7 @@ bool faces_available(const Geom& g) {
 template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hipStream_t st) {
   const Geom& g = h->g;
   for (int a = 0; a < g.dim; ++a) {
-    TRY(dst_tables_init<T>(P.tb[a], g.n[a]));
+    TRY(dst_tables_init<T>(P.tb[a], g.n[a], st));
     P.tile[a] = tile_opt > 0 ? tile_opt : 0;  // 0: each kernel picks its default tile
     // eigenvalues of the 1-D second difference on sine mode k: -(4/h^2) sin^2(k pi / (2N))
     std::vector<T> s(g.ni[a]);
@@ -281,7 +290,8 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
       s[k - 1] = (T)(-4.0L * sv * sv / ((long double)g.h[a] * g.h[a]));
     }
     TRY(alloc_t(h, &P.s[a], g.ni[a]));
-    AHOC_HIP_TRY(hipMemcpy(P.s[a], s.data(), sizeof(T) * g.ni[a], hipMemcpyHostToDevice));
+    AHOC_HIP_TRY(hipMemcpyAsync(P.s[a], s.data(), sizeof(T) * g.ni[a], hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
     // 6 U_1 - 3/2 U_2 + 2/9 U_3 of a sine mode k, for the low face (nodes 1,2,3) and the
     // high face (nodes N-1, N-2, N-3, where sin(pi k (N-m)/N) = (-1)^(k+1) sin(pi k m/N))
     std::vector<T> wv(2 * g.ni[a]);
@@ -292,7 +302,8 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
       wv[g.ni[a] + k - 1] = (T)((k % 2 == 1) ? acc : -acc);
     }
     TRY(alloc_t(h, &P.wf[a], 2 * g.ni[a]));
-    AHOC_HIP_TRY(hipMemcpy(P.wf[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice));
+    AHOC_HIP_TRY(hipMemcpyAsync(P.wf[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
     // sine of mode k at the interior layer next to the low face (node 1) and the high face
     // (node N-1): the normal factor of a face layer's spectrum
     for (int k = 1; k <= g.ni[a]; ++k) {
@@ -301,7 +312,8 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
       wv[g.ni[a] + k - 1] = (T)((k % 2 == 1) ? sv : -sv);
     }
     TRY(alloc_t(h, &P.wl[a], 2 * g.ni[a]));
-    AHOC_HIP_TRY(hipMemcpy(P.wl[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice));
+    AHOC_HIP_TRY(hipMemcpyAsync(P.wl[a], wv.data(), sizeof(T) * 2 * g.ni[a], hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
   }
   if (g.dim == 3) {
     TRY(alloc_t(h, &P.Fx, 2LL * g.ni[1] * g.ni[2]));
@@ -540,7 +552,8 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
     }
     double* d = nullptr;
     TRY(alloc_t(h, &d, 4LL * L));
-    AHOC_HIP_TRY(hipMemcpy(d, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice));
+    AHOC_HIP_TRY(hipMemcpyAsync(d, tv.data(), sizeof(double) * tv.size(), hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
     for (int r = 0; r < 4; ++r) tabs[4 * a + r] = d + (long long)r * L;
   }
   TRY(alloc_t(h, &h->pc, g.nq));
@@ -551,7 +564,7 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
     h->ptb_own = false;
   } else {
     h->ptb_own = true;
-    for (int a = 0; a < g.dim; ++a) TRY(dst_tables_init<double>(h->ptb[a], g.n[a]));
+    for (int a = 0; a < g.dim; ++a) TRY(dst_tables_init<double>(h->ptb[a], g.n[a], st));
   }
   AHOC_HIP_TRY(hipStreamSynchronize(st));
   return ST_OK;
@@ -727,6 +740,52 @@ struct GmresResult {
 // reaches tol (its later basis vectors are zero and its Krylov dimension is frozen); with
 // an FP32 operator it also stops once eight iterations gained less than a factor 2 (the
 // estimate levels off at the operator's rounding level).
+// w = S_h P^-1 v (or S_h v without the preconditioner).  With use_graph the launches run
+// as one captured HIP graph from the fixed buffers gin -> gout (the copies in and out are
+// stream-ordered device copies outside the graph); the graph is captured on the second
+// application (the first runs eagerly, so one-time kernel attribute queries happen outside
+// the capture) and capture failures (e.g. on the legacy default stream) fall back to
+// eager launches for the rest of the handle's life.
+template <typename T>
+int apply_op(ahoc_handle* h, Prec<T>& P, bool pre, const double* v, double* w, hipStream_t st) {
+  const int pi = sizeof(T) == 8 ? 1 : 0;
+  auto body = [&](const double* in, double* out) -> int {
+    if (pre) {
+      TRY(precond_apply(h, in, h->zvec, st));
+      return matvec<T>(h, P, h->zvec, out, st);
+    }
+    return matvec<T>(h, P, in, out, st);
+  };
+  const bool graph = h->opt.use_graph && h->gin && !h->prof && !h->opg_failed[pi];
+  if (graph && !h->opg[pi] && h->opg_uses[pi]++ >= 1) {
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+    int rc = ST_OK;
+    if (e == hipSuccess) {
+      rc = body(h->gin, h->gout);
+      const hipError_t e2 = hipStreamEndCapture(st, &gr);
+      e = e2;
+    }
+    if (e == hipSuccess && rc == ST_OK && gr) e = hipGraphInstantiate(&h->opg[pi], gr, nullptr, nullptr, 0);
+    if (gr) (void)hipGraphDestroy(gr);
+    if (e != hipSuccess || rc != ST_OK || !h->opg[pi]) {
+      (void)hipGetLastError();
+      if (h->opg[pi]) (void)hipGraphExecDestroy(h->opg[pi]);
+      h->opg[pi] = nullptr;
+      h->opg_failed[pi] = true;
+    }
+  }
+  if (graph && h->opg[pi]) {
+    const long long n = TQ(h->g);
+    AHOC_HIP_TRY(hipMemcpyAsync(h->gin, v, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    AHOC_HIP_TRY(hipGraphLaunch(h->opg[pi], st));
+    ++h->graph_steps;
+    AHOC_HIP_TRY(hipMemcpyAsync(w, h->gout, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    return ST_OK;
+  }
+  return body(v, w);
+}
+
 template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
           std::vector<GmresResult>& res, int* matvecs, hipStream_t st) {
@@ -788,12 +847,7 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
     for (int j = 0; j < m; ++j) {
       double* vj = h->Vb + (long long)j * nt;
       double* w = h->Vb + (long long)(j + 1) * nt;
-      if (pre) {
-        TRY(precond_apply(h, vj, h->zvec, st));
-        TRY(matvec<T>(h, P, h->zvec, w, st));
-      } else {
-        TRY(matvec<T>(h, P, vj, w, st));
-      }
+      TRY(apply_op<T>(h, P, pre, vj, w, st));
       ++*matvecs;
       hipEvent_t ek = tbegin(h, st);
       TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, st));
@@ -983,6 +1037,10 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   TRY(alloc_t(h, &h->dq, TQ(g)));
   TRY(alloc_t(h, &h->rvec, TQ(g)));
   TRY(alloc_t(h, &h->zvec, TQ(g)));
+  if (h->opt.use_graph) {
+    TRY(alloc_t(h, &h->gin, TQ(g)));
+    TRY(alloc_t(h, &h->gout, TQ(g)));
+  }
   if (nb > 1) TRY(alloc_t(h, &h->ubuf, TN(g)));
   AHOC_HIP_TRY(hipMemsetAsync(h->H, 0, sizeof(double) * nb * (m + 1) * m, st));
   const size_t npin = (size_t)std::max<long long>(8, 2 * nb);
@@ -1016,6 +1074,7 @@ void ahoc_default_options(ahoc_options* o) {
   o->tile_fp32 = 0;
   o->precond = 1;
   o->refine = 1;
+  o->use_graph = 0;
 }
 
 const char* ahoc_status_string(ahoc_status s) {
@@ -1039,6 +1098,8 @@ void ahoc_destroy(ahoc_handle* h) {
   ahoc::prec_free(h->p32);
   if (h->ptb_own)
     for (int a = 0; a < 3; ++a) ahoc::dst_tables_free(h->ptb[a]);
+  for (int i = 0; i < 2; ++i)
+    if (h->opg[i]) (void)hipGraphExecDestroy(h->opg[i]);
   for (void* p : h->allocs) (void)hipFree(p);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
@@ -1379,8 +1440,10 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   const auto t0 = std::chrono::steady_clock::now();
   if (h->g.nb != 1) return AHOC_E_INVALID;
   double* const uo[1] = {u};
+  const long long g0 = h->graph_steps;
   int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, uo, v, q, &local, st)
                                           : ahoc::solve_fp64(h, uo, v, q, &local, st);
+  local.graph_steps = (int)(h->graph_steps - g0);
   const auto t1 = std::chrono::steady_clock::now();
   local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (stats) *stats = local;
@@ -1488,9 +1551,18 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
       return AHOC_E_HIP;
     }
   }
-  // ahoc_destroy synchronises the device, which would stall the other workers: handles are
-  // kept until every worker has finished, up to a budget of device memory.
+  // ahoc_destroy synchronises the device, which would stall the other workers (and is not
+  // allowed while another worker captures its GMRES operator graph): handles are kept until
+  // every worker has finished.  A batch whose handles would exceed the memory budget (about
+  // 128 B per grid node) destroys each handle after its job instead, without graphs.
   const size_t keep_budget = (size_t)48 << 30;
+  double est = 0;
+  for (const std::vector<int>& jb : jobs) est += 128.0 * (double)work(jb);
+  const bool keep_all = est <= (double)keep_budget;
+  ahoc_options jopt;
+  if (opt) jopt = *opt;
+  else ahoc_default_options(&jopt);
+  if (!keep_all) jopt.use_graph = 0;
   std::vector<ahoc_status> jrc(njobs, AHOC_OK);
   std::vector<std::string> jerr(njobs);
   std::vector<ahoc_handle*> kept;
@@ -1518,7 +1590,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
       }
       const auto t0 = std::chrono::steady_clock::now();
       ahoc_handle* h = nullptr;
-      ahoc_status rc = setup_n(sub.data(), k, opt, s, &h);
+      ahoc_status rc = setup_n(sub.data(), k, &jopt, s, &h);
       if (rc == AHOC_OK) {
         rc = (ahoc_status)(h->opt.precision == AHOC_MIXED
                                ? ahoc::solve_mixed(h, uo.data(), nullptr, nullptr, so.data(), s)
@@ -1533,6 +1605,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
           std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
       for (int j = 0; j < k; ++j) {
         so[j].t_solve_ms = ms;  // wall time of the whole job (setup included)
+        so[j].graph_steps = h ? (int)h->graph_steps : 0;
         if (stats) stats[jb[j]] = so[j];
       }
       jrc[jn] = rc;
@@ -1541,7 +1614,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
         bool keep = false;
         {
           std::lock_guard<std::mutex> lk(mu);
-          if (kept_bytes + h->dev_bytes <= keep_budget) {
+          if (keep_all || kept_bytes + h->dev_bytes <= keep_budget) {
             kept.push_back(h);
             kept_bytes += h->dev_bytes;
             keep = true;

@@ -181,7 +181,8 @@ int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
 void dst_set_variant(int v);
 int dst_get_variant();
 
-template <typename T> int dst_tables_init(DstTables<T>& tb, int N);
+// Tables for length N, uploaded on stream st (which is synchronised before returning).
+template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st = nullptr);
 template <typename T> void dst_tables_free(DstTables<T>& tb);
 bool dst_supported(int N);
 int dst_ppt(int N);

@@ -449,7 +449,7 @@ int dst_default_tile(int N, int elem_bytes) {
   return nseq;
 }
 
-template <typename T> int dst_tables_init(DstTables<T>& tb, int N) {
+template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st) {
   dst_tables_free(tb);
   const int ppt = dst_ppt(N);
   if (!ppt) return ST_UNSUPPORTED;
@@ -470,8 +470,10 @@ template <typename T> int dst_tables_init(DstTables<T>& tb, int N) {
   for (int m = 0; m <= N / 2; ++m) sn[m] = (T)sinl(pi * (long double)m / (long double)N);
   AHOC_HIP_TRY(hipMalloc(&tb.tw, sizeof(cx<T>) * N));
   AHOC_HIP_TRY(hipMalloc(&tb.sn, sizeof(T) * (N / 2 + 1)));
-  AHOC_HIP_TRY(hipMemcpy(tb.tw, tw.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice));
-  AHOC_HIP_TRY(hipMemcpy(tb.sn, sn.data(), sizeof(T) * (N / 2 + 1), hipMemcpyHostToDevice));
+  // stream-ordered uploads (no legacy-stream operation while other streams may be capturing)
+  AHOC_HIP_TRY(hipMemcpyAsync(tb.tw, tw.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice, st));
+  AHOC_HIP_TRY(hipMemcpyAsync(tb.sn, sn.data(), sizeof(T) * (N / 2 + 1), hipMemcpyHostToDevice, st));
+  AHOC_HIP_TRY(hipStreamSynchronize(st));
   return ST_OK;
 }
 
@@ -542,8 +544,8 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
   }
 }
 
-template int dst_tables_init<float>(DstTables<float>&, int);
-template int dst_tables_init<double>(DstTables<double>&, int);
+template int dst_tables_init<float>(DstTables<float>&, int, hipStream_t);
+template int dst_tables_init<double>(DstTables<double>&, int, hipStream_t);
 template void dst_tables_free<float>(DstTables<float>&);
 template void dst_tables_free<double>(DstTables<double>&);
 template int dst_pass<float>(const DstTables<float>&, const float*, float*, long long, long long,

@@ -270,6 +270,44 @@ def test_batched_mixed_matches_fp64(ah):
         assert _rel(u.cpu().numpy(), u64.cpu().numpy()) <= 1e-10, (pb.name, st)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_batched_graph_replays_match_eager(ah, prec):
+    """The batch jobs run on worker streams, where the GMRES operator is captured as a HIP
+    graph and replayed once per Krylov step, with the eager Krylov work in between: every
+    replay must give the eager launches' result, so the whole solves agree (same iteration
+    counts, same U)."""
+    p = ah.FP64 if prec == "fp64" else ah.MIXED
+    probs = _batch_problems()
+    outs_g, st_g, rc_g = ah.solve_batched(probs, precision=p, tol=1e-12, use_graph=1)
+    outs_e, st_e, rc_e = ah.solve_batched(probs, precision=p, tol=1e-12, use_graph=0)
+    assert rc_g == ah.OK and rc_e == ah.OK
+    for pb, ug, ue, sg, se in zip(probs, outs_g, outs_e, st_g, st_e):
+        assert sg.gmres_iters == se.gmres_iters and sg.sweeps == se.sweeps, (pb.name, sg, se)
+        assert se.graph_steps == 0 and sg.graph_steps >= sg.gmres_iters - 2, (pb.name, sg)
+        assert _rel(ug.cpu().numpy(), ue.cpu().numpy()) < 1e-14, pb.name
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_solve_graph_on_user_stream(ah, prec):
+    """A single solve on a created stream (capturable) with the operator graph, twice in a
+    row on the same handle (replays across solves), against eager launches."""
+    p = ah.FP64 if prec == "fp64" else ah.MIXED
+    pb = W.config3(16)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        with ah.Solver(pb, precision=p, tol=1e-12, use_graph=1) as s:
+            ua, _, _, sa = s.solve()
+            ub, _, _, sb = s.solve()
+        with ah.Solver(pb, precision=p, tol=1e-12, use_graph=0) as s:
+            ue, _, _, se = s.solve()
+    stream.synchronize()
+    assert se.graph_steps == 0
+    for u, st in ((ua, sa), (ub, sb)):
+        assert st.converged and st.gmres_iters == se.gmres_iters, (st, se)
+        assert st.graph_steps >= st.gmres_iters - 2, st
+        assert _rel(u.cpu().numpy(), ue.cpu().numpy()) < 1e-14
+
+
 def test_batched_matches_direct(ah):
     probs = [W.config2(32), W.config2(32), W.cavity(32), W.plate(32), W.poly_exact(32, 2)]
     outs, stats, rc = ah.solve_batched(probs, tol=1e-14)
