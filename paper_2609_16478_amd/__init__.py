@@ -45,7 +45,7 @@ class _Options(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("converged", c_int), ("gmres_iters", c_int), ("sweeps", c_int), ("matvecs", c_int),
                 ("schur_relres", c_double), ("last_update", c_double), ("t_solve_ms", c_double),
-                ("graph_steps", c_int)]
+                ("graph_steps", c_int), ("dst_gemm", c_int)]
 
 
 _H = c_void_p
@@ -78,6 +78,9 @@ _lib.ahoc_set_dst_variant.argtypes = [c_int]
 _lib.ahoc_set_dst_variant.restype = c_int
 _lib.ahoc_set_dst_tile.argtypes = [c_int, c_int, c_int]
 _lib.ahoc_set_dst_tile.restype = c_int
+_lib.ahoc_dst_choice.argtypes = [_H, c_int, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double),
+                                 ctypes.POINTER(c_double)]
+_lib.ahoc_dst_choice.restype = c_int
 _lib.ahoc_destroy.argtypes = [_H]
 _lib.ahoc_status_string.argtypes = [c_int]
 _lib.ahoc_status_string.restype = ctypes.c_char_p
@@ -86,7 +89,7 @@ _lib.ahoc_last_error.restype = ctypes.c_char_p
 KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "resid",
                 "matvec", "dst_gen", "face_reduce", "precond"]
 
-EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
+EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_dst_choice", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
             "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
             "ahoc_status_string", "ahoc_last_error"]
 
@@ -148,11 +151,12 @@ class Stats:
     last_update: float
     t_solve_ms: float
     graph_steps: int = 0
+    dst_gemm: int = 0
 
 
 def _stats(s: _Stats) -> Stats:
     return Stats(bool(s.converged), s.gmres_iters, s.sweeps, s.matvecs, s.schur_relres,
-                 s.last_update, s.t_solve_ms, s.graph_steps)
+                 s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm)
 
 
 def _problem_struct(n, lo, hi, tens):
@@ -228,6 +232,16 @@ class Solver:
         _check(_lib.ahoc_precond_apply(self._h, _ptr(q), _ptr(y), _stream()), "ahoc_precond_apply")
         return y
 
+    def dst_choice(self, precision, axis, kind):
+        """Setup-time FFT-or-matrix-core choice for the plain DST passes of one axis:
+        (gemm, t_fft_us, t_gemm_us), gemm 1 / 0 / -1 (not timed)."""
+        g = c_int(0)
+        tf = c_double(0.0)
+        tg = c_double(0.0)
+        _check(_lib.ahoc_dst_choice(self._h, int(precision), int(axis), int(kind), ctypes.byref(g),
+                                    ctypes.byref(tf), ctypes.byref(tg)), "ahoc_dst_choice")
+        return g.value, tf.value, tg.value
+
     def schur_rhs(self):
         torch = _torch()
         b = torch.empty(self.nq, dtype=torch.float64, device=self.device)
@@ -290,7 +304,9 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
 
 
 def set_dst_variant(variant: int):
-    """0 = automatic, 1 = generic DST kernel everywhere, 2 = length-specialised kernels only."""
+    """0 = automatic (timed FFT-or-matrix-core choice for short pencils), 1 = generic DST kernel
+    everywhere, 2 = length-specialised kernels only, 3 = one-tile strided kernels, 4 = matrix-core
+    products for every plain pass of even N <= 128, 5 = automatic without them."""
     _check(_lib.ahoc_set_dst_variant(int(variant)), "ahoc_set_dst_variant")
 
 

@@ -329,6 +329,15 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
   P.spectral = faces_available(g);
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
+  // setup-time choice between the FFT and the matrix-core pass for the plain passes of the
+  // operator, timed on their own shapes: the x (row) passes; in 3-D also the strided y passes
+  if (g.dim == 2) {
+    TRY(dst_autotune<T>(P.tb[0], P.bufA, (long long)g.nb * g.ni[1], 1, g.px, st));
+  } else {
+    TRY(dst_autotune<T>(P.tb[0], P.bufA, (long long)g.ni[1] * g.ni[2], 1, g.px, st));
+    TRY(dst_autotune<T>(P.tb[1], P.bufA, g.ni[2], g.px, g.px, st));
+  }
+  AHOC_HIP_TRY(hipMemsetAsync(P.bufA, 0, sizeof(T) * (size_t)TA(g), st));
   TRY(alloc_t(h, &P.qT, TQ(g)));
   TRY(alloc_t(h, &P.zq, TQ(g)));
   AHOC_HIP_TRY(hipMemsetAsync(P.zq, 0, sizeof(T) * TQ(g), st));
@@ -661,6 +670,19 @@ int schur_rhs(ahoc_handle* h, Prec<T>& P, const T* sv, const T* su, const T* sq,
     TRY(gather<T>(h->g, h->w, P.bufB, P.zq, P.af, sq, h->R, st));
   }
   return axpby(TQ(h->g), -1.0, h->R, 0.0, b, st);
+}
+
+// Axes and pass kinds whose plain passes run as the matrix-core product, bit 2 axis + kind,
+// for the operator of the solve's precision.
+int gemm_mask(const ahoc_handle* h) {
+  int m = 0;
+  for (int a = 0; a < h->g.dim; ++a)
+    for (int k = 0; k < 2; ++k) {
+      const bool on = h->opt.precision == AHOC_MIXED ? (h->p32.ready && h->p32.tb[a].gemm[k])
+                                                     : (h->p64.ready && h->p64.tb[a].gemm[k]);
+      if (on) m |= 1 << (2 * a + k);
+    }
+  return m;
 }
 
 double read_scalar(ahoc_handle* h, const double* dptr, hipStream_t st, int* rc) {
@@ -1109,6 +1131,27 @@ void ahoc_destroy(ahoc_handle* h) {
 
 size_t ahoc_nq(const ahoc_handle* h) { return h ? (size_t)h->g.nq : 0; }
 
+ahoc_status ahoc_dst_choice(const ahoc_handle* h, int precision, int axis, int kind, int* gemm, double* t_fft_us,
+                            double* t_gemm_us) {
+  if (!h || !gemm || (precision != AHOC_FP64 && precision != AHOC_MIXED) || axis < 0 || axis >= h->g.dim ||
+      (kind != 0 && kind != 1)) {
+    ahoc::set_last_error("bad handle, precision, axis or kind", "ahoc_dst_choice");
+    return AHOC_E_INVALID;
+  }
+  const bool dbl = precision == AHOC_FP64;
+  if (dbl ? !h->p64.ready : !h->p32.ready) {
+    ahoc::set_last_error("the handle has no operator in this precision", "ahoc_dst_choice");
+    return AHOC_E_UNSUPPORTED;
+  }
+  const double tf = dbl ? h->p64.tb[axis].t_fft_us[kind] : h->p32.tb[axis].t_fft_us[kind];
+  const double tg = dbl ? h->p64.tb[axis].t_gemm_us[kind] : h->p32.tb[axis].t_gemm_us[kind];
+  const int ch = dbl ? h->p64.tb[axis].gemm[kind] : h->p32.tb[axis].gemm[kind];
+  *gemm = tf < 0 ? -1 : ch;
+  if (t_fft_us) *t_fft_us = tf;
+  if (t_gemm_us) *t_gemm_us = tg;
+  return AHOC_OK;
+}
+
 static ahoc_status validate_problem(const ahoc_problem* pb) {
   if (pb->dim != 2 && pb->dim != 3) {
     ahoc::set_last_error("dim must be 2 or 3", "ahoc_setup");
@@ -1444,6 +1487,7 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, uo, v, q, &local, st)
                                           : ahoc::solve_fp64(h, uo, v, q, &local, st);
   local.graph_steps = (int)(h->graph_steps - g0);
+  local.dst_gemm = ahoc::gemm_mask(h);
   const auto t1 = std::chrono::steady_clock::now();
   local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
   if (stats) *stats = local;
@@ -1455,7 +1499,7 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
 }
 
 ahoc_status ahoc_set_dst_variant(int variant) {
-  if (variant < 0 || variant > 3) return AHOC_E_INVALID;
+  if (variant < 0 || variant > 5) return AHOC_E_INVALID;
   ahoc::dst_set_variant(variant);
   return AHOC_OK;
 }
@@ -1606,6 +1650,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
       for (int j = 0; j < k; ++j) {
         so[j].t_solve_ms = ms;  // wall time of the whole job (setup included)
         so[j].graph_steps = h ? (int)h->graph_steps : 0;
+        so[j].dst_gemm = h ? ahoc::gemm_mask(h) : 0;
         if (stats) stats[jb[j]] = so[j];
       }
       jrc[jn] = rc;

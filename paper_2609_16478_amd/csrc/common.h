@@ -76,6 +76,13 @@ template <typename T> struct DstTables {
   int rad[12] = {0};  // radix sequence, product N
   cx<T>* tw = nullptr;   // exp(-2 pi i k / N), k = 0..N-1
   T* sn = nullptr;       // sin(pi m / N), m = 0..N/2
+  // half sine matrices of the matrix-core pass (even N <= DST_GEMM_MAX_N), [2][HP][HP]
+  T* S = nullptr;
+  // setup-time choice per pass kind (0 rows, 1 strided): 1 = matrix-core pass; the timings
+  // (microseconds per pass, -1 = not timed) behind it
+  int gemm[2] = {0, 0};
+  double t_fft_us[2] = {-1.0, -1.0};
+  double t_gemm_us[2] = {-1.0, -1.0};
 };
 
 // Eigen-scaling parameters for the fused middle pass along the slowest axis.
@@ -177,7 +184,24 @@ template <typename T>
 int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer, long long inner,
                   const DstScale<T>* fused, const DstFaces<T>* faces, int nseq, hipStream_t st);
 
-// 0 = automatic (specialised kernel where available), 1 = generic kernel only, 2 = specialised only
+// DST-I of short pencils (even N <= DST_GEMM_MAX_N) as two half-size products with sine
+// matrices on the matrix cores (dst_gemm.hip).  Same layouts as dst_pass (plain passes
+// only); in may equal out.
+constexpr int DST_GEMM_MAX_N = 128;
+bool dst_gemm_supported(int N);
+int dst_gemm_hp(int N);
+template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st);
+template <typename T>
+int dst_gemm_pass(const T* S, int N, const T* in, T* out, long long outer, long long inner, long long pitch,
+                  hipStream_t st);
+// Times both methods for the plain pass of this shape (buf is overwritten) and records the
+// faster in tb.gemm; no-op outside automatic selection or without a sine matrix.
+template <typename T>
+int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, long long pitch, hipStream_t st);
+
+// 0 = automatic (specialised kernels; the matrix-core pass where the setup-time timing chose
+// it), 1 = generic kernel only, 2 = specialised only, 3 = one-tile specialised kernels,
+// 4 = matrix-core pass for every plain pass it supports, 5 = as 0 without the matrix-core pass
 void dst_set_variant(int v);
 int dst_get_variant();
 

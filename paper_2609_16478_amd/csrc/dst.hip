@@ -474,14 +474,21 @@ template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t s
   AHOC_HIP_TRY(hipMemcpyAsync(tb.tw, tw.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice, st));
   AHOC_HIP_TRY(hipMemcpyAsync(tb.sn, sn.data(), sizeof(T) * (N / 2 + 1), hipMemcpyHostToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
+  if (dst_gemm_supported(N)) {
+    const int rc = dst_gemm_table<T>(&tb.S, N, st);
+    if (rc != ST_OK) return rc;
+  }
   return ST_OK;
 }
 
 template <typename T> void dst_tables_free(DstTables<T>& tb) {
   if (tb.tw) (void)hipFree(tb.tw);
   if (tb.sn) (void)hipFree(tb.sn);
+  if (tb.S) (void)hipFree(tb.S);
   tb.tw = nullptr;
   tb.sn = nullptr;
+  tb.S = nullptr;
+  tb.gemm[0] = tb.gemm[1] = 0;
   tb.N = 0;
 }
 
@@ -495,6 +502,12 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
              const DstFaces<T>* faces) {
   const int N = tb.N;
   if (inner == 1 && pitch < N - 1) return ST_INVALID;
+  // plain passes of short pencils: the matrix-core product where chosen (or forced)
+  if (tb.S && !fused && !(faces && faces->mode) && tile_seqs <= 0 &&
+      (g_variant == 4 || (g_variant == 0 && tb.gemm[inner == 1 ? 0 : 1]))) {
+    const int rc = dst_gemm_pass<T>(tb.S, N, in, out, outer, inner, pitch, st);
+    if (rc != ST_UNSUPPORTED) return rc;
+  }
   if (g_variant != 1 && dst_fast_supported(N)) {
     const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, pitch, fused, tile_seqs, st, faces);
     if (rc != ST_UNSUPPORTED || g_variant == 2) return rc;
