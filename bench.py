@@ -92,6 +92,12 @@ def main():
                          "Schur matvecs, then exit (no JSON line)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling target: three plain 2 GiB device copies (counter calibration)")
+    ap.add_argument("--dst-compare", action="store_true",
+                    help="profiling target: contiguous and strided DST-I passes over 2^20 pencils of "
+                         "N-1 = 31, 63, 127 points in FP32 and FP64, three each with the FFT kernels "
+                         "and three with the matrix-core products")
+    ap.add_argument("--no-instance-loop", action="store_true",
+                    help="skip the per-instance FP64 loop over the batched workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
@@ -110,6 +116,23 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: 3 copies of {x.numel() * 8} bytes", file=sys.stderr)
+        return
+    if args.dst_compare:
+        for N in (32, 64, 128):
+            for dt, p in ((torch.float32, ah.MIXED), (torch.float64, ah.FP64)):
+                g = torch.Generator(device=dev).manual_seed(N)
+                xr = torch.randn(1024, 1024, N - 1, dtype=dt, device=dev, generator=g)
+                xs = torch.randn(1024, N - 1, 1024, dtype=dt, device=dev, generator=g)
+                for var in (5, 4):  # FFT kernels only, then the matrix-core products
+                    ah.set_dst_variant(var)
+                    for _ in range(3):
+                        ah.dst1(xr, 0, p)
+                        ah.dst1(xs, 1, p)
+                    torch.cuda.synchronize()
+                ah.set_dst_variant(0)
+                del xr, xs
+                print(f"[bench] dst compare N={N} {dt}: 2^20 pencils, contiguous and strided", file=sys.stderr,
+                      flush=True)
         return
     n = args.n
     t0 = time.perf_counter()
@@ -237,13 +260,43 @@ def main():
             torch.cuda.synchronize()
             dtb = (time.perf_counter() - t) / args.steps
             err = max(((o - r).abs().max() / r.abs().max()).item() for o, r in zip(outs, ref_b))
+            gemm = {}
+            for sp, x in zip(specs, bst):
+                gemm[sp["n"]] = x.dst_gemm
             bres[name] = {"ms_per_batch": dtb * 1e3, "dof_per_s": bdof / dtb, "max_rel_err_vs_fp64_ref": err,
                           "mean_gmres_iters": sum(x.gmres_iters for x in bst) / len(bst),
-                          "all_converged": all(x.converged for x in bst)}
+                          "all_converged": all(x.converged for x in bst),
+                          "matrix_core_dst_by_n": {str(k): bool(v & 1) for k, v in sorted(gemm.items())}}
             print(f"[bench] batched {name}: {dtb*1e3:.1f} ms per batch of {len(bprobs)}", file=sys.stderr, flush=True)
+        # the same batch with the FFT kernels only (no setup-time matrix-core choice)
+        ah.set_dst_variant(5)
+        try:
+            ah.solve_batched(bprobs, precision=ah.MIXED, tol=args.tol)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(args.steps):
+                ah.solve_batched(bprobs, precision=ah.MIXED, tol=args.tol)
+            torch.cuda.synchronize()
+            bres["mixed_fft_only_ms_per_batch"] = (time.perf_counter() - t) / args.steps * 1e3
+        finally:
+            ah.set_dst_variant(0)
+        # per-instance FP64 loop: one handle and one solve per instance, one after another
+        # (setup included, as in the batched call)
+        if not args.no_instance_loop:
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for pb in bprobs:
+                with ah.Solver(pb, precision=ah.FP64, tol=args.tol) as s1:
+                    s1.solve()
+            torch.cuda.synchronize()
+            bres["fp64_instance_loop_ms"] = (time.perf_counter() - t) * 1e3
+            print(f"[bench] per-instance FP64 loop: {bres['fp64_instance_loop_ms']:.1f} ms", file=sys.stderr,
+                  flush=True)
         batched = {"workload": f"{len(bprobs)} uneven 2-D instances n in {{64..512}} (alpha=1+c sin(2pi p x)cos(2pi q y), "
                                f"u=sin^2 sin^2 cos(k(x+y)), seeded draws), DOF {bdof}",
                    **bres, "speedup_mixed_over_fp64": bres["fp64"]["ms_per_batch"] / bres["mixed"]["ms_per_batch"]}
+        if "fp64_instance_loop_ms" in bres:
+            batched["speedup_mixed_over_instance_loop"] = bres["fp64_instance_loop_ms"] / bres["mixed"]["ms_per_batch"]
         del bprobs, ref_b
 
     cpu = None

@@ -189,8 +189,10 @@ ahoc_status ahoc_set_dst_variant(int variant);
 /* The setup-time choice between the FFT pass and the matrix-core pass (two half-size
  * sine-matrix products: odd outputs from x_m + x_{n-m}, even ones from x_m - x_{n-m}) for
  * the plain DST-I passes along one axis of the operator (the sine transforms of Sec. 2.3;
- * either gives the same transform up to rounding).  ahoc_setup
- * times both on the handle's own shape, in automatic kernel selection only.
+ * either gives the same transform up to rounding).  ahoc_setup times both on the
+ * handle's own pass shape, in automatic kernel selection only; the first timing of a
+ * shape (precision, n, pass extents) is kept for the process, so later handles with the
+ * same shape make the same choice and give bit-identical results.
  * precision: AHOC_FP64 (the FP64 operator) or AHOC_MIXED (the FP32 operator);
  * kind: 0 = contiguous (x) passes, 1 = strided passes (y, 3-D only).
  * Out: *gemm = 1 matrix-core pass chosen, 0 FFT chosen, -1 not timed (odd n or n above
