@@ -1317,7 +1317,9 @@ int solve_fp64(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stat
 // FP64 (FP64 operator), each correction S_h dQ = r is solved by GMRES with the FP32
 // operator (FP64 Krylov basis, Arnoldi, Givens), Q is updated in FP64, and the final
 // recovery of V and U from Q runs in FP64.  An instance stops when ||r|| <= tol ||b||
-// (its residual is then zeroed, so later sweeps leave it alone).
+// (its residual is then zeroed, so later sweeps leave it alone).  The sweep predicted to be
+// the last takes its residual from the recovery itself (r = -R(Q)), so a converged solve
+// runs no FP64 Schur matvec after its last correction.
 int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
   Prec<float>& P = h->p32;
   Prec<double>& D = h->p64;
@@ -1341,9 +1343,16 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
   AHOC_HIP_TRY(hipMemcpyAsync(h->bvec, h->b64, sizeof(double) * TQ(g), hipMemcpyDeviceToDevice, st));
   int mv = 0;
   double upd = 0;
+  bool recovered = false;     // D.bufA / D.bufB hold V, U of the current Q64
+  bool recover_check = true;  // cleared once a recovery-based check has not converged
   for (int sw = 0; sw < h->opt.max_sweeps && !all; ++sw) {
     std::vector<GmresResult> gr;
     TRY(gmres<float>(h, P, h->bvec, h->dq, h->opt.inner_tol, h->opt.max_iters, gr, &mv, st));
+    // this sweep is predicted to converge when its GMRES reduction times the current
+    // relative residual reaches the tolerance for every active instance
+    bool predict = recover_check;
+    for (int i = 0; i < nb; ++i)
+      if (!conv[i]) predict = predict && gr[i].relres * relres[i] <= h->opt.tol;
     for (int i = 0; i < nb; ++i)
       if (!conv[i]) {
         iters[i] += gr[i].iters;
@@ -1355,11 +1364,23 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
     const double qn = absmax(h, h->Q64, true, TQ(g), st, &rc);
     TRY(rc);
     upd = qn > 0 ? dn / qn : 0.0;
-    // FP64 residual of the Schur system at the updated Q
+    // FP64 residual of the Schur system at the updated Q.  By Lemma 1 with the data,
+    // b - S_h Q = -R(Q), R the boundary residual of the solution recovered from Q: when the
+    // sweep is predicted to converge, the FP64 recovery of V and U (which the output needs
+    // anyway) and the gather give it, instead of an FP64 Schur matvec before the recovery.
     hipEvent_t er = tbegin(h, st);
-    TRY(matvec<double>(h, D, h->Q64, h->bvec, st));
-    ++mv;
-    TRY(axpby(TQ(g), 1.0, h->b64, -1.0, h->bvec, st));
+    if (predict) {
+      TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+      TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+      TRY(gather<double>(g, h->w, D.bufB, h->Q64, D.af, h->src_q, h->R, st));
+      TRY(axpby(TQ(g), -1.0, h->R, 0.0, h->bvec, st));
+      recovered = true;
+    } else {
+      TRY(matvec<double>(h, D, h->Q64, h->bvec, st));
+      ++mv;
+      TRY(axpby(TQ(g), 1.0, h->b64, -1.0, h->bvec, st));
+      recovered = false;
+    }
     TRY(dot_dev(h, h->bvec, h->bvec, st, h->nrm));
     TRY(read_vec(h, h->nrm, 2 * nb, st));
     tend(h, AHOC_K_RESID, er, 8.0 * (double)TQ(g) * 4.0, st);
@@ -1372,10 +1393,13 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
       h->pinned_i[i] = !conv[i];
       all = all && conv[i];
     }
+    if (predict && !all) recover_check = false;
     if (!all && nb > 1) TRY(zero_done(h, h->bvec, st));
   }
-  TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
-  TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+  if (!recovered) {
+    TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+    TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+  }
   TRY(write_u(h, D.bufB, u, st));
   if (v) TRY(out_v<double>(g, D.bufA, h->Q64, h->vedge, v, st));
   if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->Q64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
