@@ -201,6 +201,26 @@ def test_solve_mixed_matches_fp64(ah, case, refine):
     assert _rel(um.cpu().numpy(), u64.cpu().numpy()) <= 1e-10, (case, st)
 
 
+@pytest.mark.parametrize("inner_tol,tol", [(1e-5, 1e-10), (1e-3, 1e-12)], ids=["default", "many_sweeps"])
+@pytest.mark.parametrize("case", ["c2_64", "c3_16"])
+def test_mixed_refinement_residual(ah, case, inner_tol, tol):
+    """The Schur residual the mixed solve reports -- from FP64 Schur matvecs, or for the sweep
+    predicted to converge from the FP64 recovery and the gather (b - S Q = -R(Q), Lemma 1) --
+    equals ||b - S_h Q|| / ||b|| formed independently from the FP64 operator at the returned
+    Q.  With a loose inner tolerance several sweeps run and predictions can miss, which
+    exercises the fallback to matvec residuals."""
+    p = W.config2(64) if case == "c2_64" else W.config3(16)
+    with ah.Solver(p, precision=ah.MIXED, tol=tol, inner_tol=inner_tol) as s:
+        u, _, q, st = s.solve(want_q=True)
+    assert st.converged and st.schur_relres <= tol, st
+    with ah.Solver(p, tol=1e-14) as s:
+        b = s.schur_rhs()
+        rel = ((b - s.schur_apply(q)).norm() / b.norm()).item()
+        u64, *_ = s.solve()
+    assert abs(rel - st.schur_relres) <= 1e-3 * rel + 1e-15, (rel, st)
+    assert _rel(u.cpu().numpy(), u64.cpu().numpy()) <= 1e-10
+
+
 @pytest.mark.parametrize("dim,n", [(2, 256), (2, 512), (3, 32), (3, 64)])
 def test_polynomial_exactness_large(ah, dim, n):
     # the discrete solution equals the sampled polynomial at any N (rounding only)
