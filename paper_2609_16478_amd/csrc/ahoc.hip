@@ -579,26 +579,29 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
   return ST_OK;
 }
 
-// 2-D DST-I of every face block of a Q-layout vector, in place.  Faces x-, x+ hold
-// [k][j], y-, y+ [k][i], z-, z+ [j][i] (lower axis fastest, no padding).
-int face_dst_q(ahoc_handle* h, double* x, hipStream_t st) {
+// 2-D DST-I of every face block of a Q-layout vector, from x into y (y may equal x; the
+// first pass of each face reads x, later ones work in place on y).  Faces x-, x+ hold
+// [k][j], y-, y+ [k][i], z-, z+ [j][i] (lower axis fastest, no padding).  A square 2-D
+// batch (N_x = N_y) is one row pass: its Q vector is 4 nb rows of N-1 entries.
+int face_dst_q(ahoc_handle* h, const double* x, double* y, hipStream_t st) {
   const Geom& g = h->g;
   const DstTables<double>* tb = h->ptb;
-  double* fx = x + g.face_off[0];
-  double* fy = x + g.face_off[2];
+  const long long ox = g.face_off[0], oy = g.face_off[2];
   if (g.dim == 3) {
-    double* fz = x + g.face_off[4];
-    TRY(dst_pass<double>(tb[1], fx, fx, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<double>(tb[2], fx, fx, 2, g.ni[1], g.ni[1], nullptr, 0, st));
-    TRY(dst_pass<double>(tb[0], fy, fy, 2LL * g.ni[2], 1, g.ni[0], nullptr, 0, st));
-    TRY(dst_pass<double>(tb[2], fy, fy, 2, g.ni[0], g.ni[0], nullptr, 0, st));
-    TRY(dst_pass<double>(tb[0], fz, fz, 2LL * g.ni[1], 1, g.ni[0], nullptr, 0, st));
-    TRY(dst_pass<double>(tb[1], fz, fz, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+    const long long oz = g.face_off[4];
+    TRY(dst_pass<double>(tb[1], x + ox, y + ox, 2LL * g.ni[2], 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[2], y + ox, y + ox, 2, g.ni[1], g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], x + oy, y + oy, 2LL * g.ni[2], 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[2], y + oy, y + oy, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], x + oz, y + oz, 2LL * g.ni[1], 1, g.ni[0], nullptr, 0, st));
+    TRY(dst_pass<double>(tb[1], y + oz, y + oz, 2, g.ni[0], g.ni[0], nullptr, 0, st));
+  } else if (g.n[0] == g.n[1] && g.nq == 4LL * g.ni[0]) {
+    TRY(dst_pass<double>(tb[0], x, y, 4LL * g.nb, 1, g.ni[0], nullptr, 0, st));
   } else {  // each face line of every instance of a batch (instances nq apart)
-    TRY(dst_pass<double>(tb[1], fx, fx, g.nb, 1, g.nq, nullptr, 0, st));
-    TRY(dst_pass<double>(tb[1], fx + g.ni[1], fx + g.ni[1], g.nb, 1, g.nq, nullptr, 0, st));
-    TRY(dst_pass<double>(tb[0], fy, fy, g.nb, 1, g.nq, nullptr, 0, st));
-    TRY(dst_pass<double>(tb[0], fy + g.ni[0], fy + g.ni[0], g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[1], x + ox, y + ox, g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[1], x + ox + g.ni[1], y + ox + g.ni[1], g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], x + oy, y + oy, g.nb, 1, g.nq, nullptr, 0, st));
+    TRY(dst_pass<double>(tb[0], x + oy + g.ni[0], y + oy + g.ni[0], g.nb, 1, g.nq, nullptr, 0, st));
   }
   return ST_OK;
 }
@@ -607,10 +610,9 @@ int face_dst_q(ahoc_handle* h, double* x, hipStream_t st) {
 int precond_apply(ahoc_handle* h, const double* v, double* y, hipStream_t st) {
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
-  AHOC_HIP_TRY(hipMemcpyAsync(y, v, sizeof(double) * TQ(g), hipMemcpyDeviceToDevice, st));
-  TRY(face_dst_q(h, y, st));
+  TRY(face_dst_q(h, v, y, st));
   TRY(precond_modes<double>(g, h->pc, h->qc, y, st));
-  TRY(face_dst_q(h, y, st));
+  TRY(face_dst_q(h, y, y, st));
   tend(h, AHOC_K_PRECOND, e, (double)TQ(g) * 16.0, st);
   return ST_OK;
 }
