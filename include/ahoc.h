@@ -114,7 +114,7 @@ typedef struct {
   int dst_gemm;          /* bit 2*axis + kind set where the operator of the solve's
                             precision (FP32 for AHOC_MIXED) runs that axis's plain
                             DST-I passes (kind 0 contiguous, 1 strided) as the
-                            matrix-core product (see ahoc_dst_choice)    */
+                            matrix-core pass (see ahoc_dst_choice)       */
 } ahoc_stats;
 
 typedef struct ahoc_handle ahoc_handle;
@@ -176,32 +176,37 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
 /* Select the DST-I pass kernel family for subsequent launches (process-wide):
  * 0 = automatic (length-specialised kernels for n in {32, 64, 96, 128, 192, 256, 384,
  * 512, 768, 1024, 2048, 4096}, the generic radix-2/3/4/8 kernel otherwise; for the plain
- * passes of even n <= 128 the matrix-core products with the half sine matrices where
- * ahoc_setup's timing found them faster, see ahoc_dst_choice),
+ * passes of an operator the kernel ahoc_setup's timing chose, see ahoc_dst_choice),
  * 1 = generic kernel for every length, 2 = specialised kernels only (other lengths
  * return AHOC_E_UNSUPPORTED), 3 = as 0 but strided passes with the one-tile-per-group
  * kernels instead of the persistent pipelined ones, 4 = the matrix-core products for every
- * plain pass of even n <= 128 (untimed), 5 = as 0 without the matrix-core products.
+ * plain pass of even n <= 128 (untimed), 5 = as 0 without setup-time choices (default
+ * kernels).
  * Handles keep the choice timed at their setup.  For tuning and for testing every
  * family. */
 ahoc_status ahoc_set_dst_variant(int variant);
 
-/* The setup-time choice between the FFT pass and the matrix-core pass (two half-size
- * sine-matrix products: odd outputs from x_m + x_{n-m}, even ones from x_m - x_{n-m}) for
- * the plain DST-I passes along one axis of the operator (the sine transforms of Sec. 2.3;
- * either gives the same transform up to rounding).  ahoc_setup times both on the
- * handle's own pass shape, in automatic kernel selection only; the first timing of a
- * shape (precision, n, pass extents) is kept for the process, so later handles with the
+/* The setup-time choice of kernel for the plain DST-I passes along one axis of the
+ * operator (the sine transforms of Sec. 2.3; every candidate gives the same transform up to
+ * rounding).  ahoc_setup times, on the handle's own pass shape and in automatic kernel
+ * selection only, the default FFT kernel (row kernel, or persistent pipelined strided
+ * kernel), the one-tile FFT kernel with half, the default and twice the default pencil pairs
+ * per work-group (for n = 512, 1024 also a 32-point-per-thread radix plan), and for even
+ * n <= 128 the matrix-core pass (two half-size sine-matrix products: odd outputs from
+ * x_m + x_{n-m}, even ones from x_m - x_{n-m}), and keeps the fastest.  The first timing of
+ * a shape (precision, n, pass extents) is kept for the process, so later handles with the
  * same shape make the same choice and give bit-identical results.
  * precision: AHOC_FP64 (the FP64 operator) or AHOC_MIXED (the FP32 operator);
  * kind: 0 = contiguous (x) passes, 1 = strided passes (y, 3-D only).
- * Out: *gemm = 1 matrix-core pass chosen, 0 FFT chosen, -1 not timed (odd n or n above
- * 128, a pass kind the operator does not run on this axis, or a non-automatic
- * variant); *t_fft_us, *t_gemm_us (each may be NULL) = measured microseconds per pass,
- * -1 when not timed.  AHOC_E_INVALID on a bad argument, AHOC_E_UNSUPPORTED when the
- * handle has no operator in that precision. */
-ahoc_status ahoc_dst_choice(const struct ahoc_handle* h, int precision, int axis, int kind, int* gemm,
-                            double* t_fft_us, double* t_gemm_us);
+ * Out: *method = 0 default FFT kernel, 1 matrix-core pass, 2 one-tile FFT kernel with *tile
+ * pencil pairs per work-group, -1 not timed (a pass kind the operator does not run on this
+ * axis, or a non-automatic variant); *tile = pairs for method 2, else 0; *t_default_us,
+ * *t_gemm_us, *t_best_us = measured microseconds per pass of the default kernel, the
+ * matrix-core pass and the chosen kernel, -1 when not timed or not applicable.  Each
+ * pointer but method may be NULL.  AHOC_E_INVALID on a bad argument, AHOC_E_UNSUPPORTED
+ * when the handle has no operator in that precision. */
+ahoc_status ahoc_dst_choice(const struct ahoc_handle* h, int precision, int axis, int kind, int* method, int* tile,
+                            double* t_default_us, double* t_gemm_us, double* t_best_us);
 
 /* Override the default work-group tile (pencil pairs per work-group, a power of two;
  * 0 restores the default) of one DST-I pass kind of the length-specialised kernels,

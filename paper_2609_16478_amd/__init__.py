@@ -78,8 +78,8 @@ _lib.ahoc_set_dst_variant.argtypes = [c_int]
 _lib.ahoc_set_dst_variant.restype = c_int
 _lib.ahoc_set_dst_tile.argtypes = [c_int, c_int, c_int]
 _lib.ahoc_set_dst_tile.restype = c_int
-_lib.ahoc_dst_choice.argtypes = [_H, c_int, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double),
-                                 ctypes.POINTER(c_double)]
+_lib.ahoc_dst_choice.argtypes = [_H, c_int, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
+                                 ctypes.POINTER(c_double), ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
 _lib.ahoc_dst_choice.restype = c_int
 _lib.ahoc_destroy.argtypes = [_H]
 _lib.ahoc_status_string.argtypes = [c_int]
@@ -233,14 +233,14 @@ class Solver:
         return y
 
     def dst_choice(self, precision, axis, kind):
-        """Setup-time FFT-or-matrix-core choice for the plain DST passes of one axis:
-        (gemm, t_fft_us, t_gemm_us), gemm 1 / 0 / -1 (not timed)."""
-        g = c_int(0)
-        tf = c_double(0.0)
-        tg = c_double(0.0)
-        _check(_lib.ahoc_dst_choice(self._h, int(precision), int(axis), int(kind), ctypes.byref(g),
-                                    ctypes.byref(tf), ctypes.byref(tg)), "ahoc_dst_choice")
-        return g.value, tf.value, tg.value
+        """Setup-time kernel choice for the plain DST passes of one axis (kind 0 contiguous,
+        1 strided): (method, tile, t_default_us, t_gemm_us, t_best_us); method 0 default FFT
+        kernel, 1 matrix-core pass, 2 one-tile FFT kernel with `tile` pairs, -1 not timed."""
+        m, t = c_int(0), c_int(0)
+        td, tg, tb = c_double(0.0), c_double(0.0), c_double(0.0)
+        _check(_lib.ahoc_dst_choice(self._h, int(precision), int(axis), int(kind), ctypes.byref(m), ctypes.byref(t),
+                                    ctypes.byref(td), ctypes.byref(tg), ctypes.byref(tb)), "ahoc_dst_choice")
+        return m.value, t.value, td.value, tg.value, tb.value
 
     def schur_rhs(self):
         torch = _torch()
@@ -304,9 +304,9 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
 
 
 def set_dst_variant(variant: int):
-    """0 = automatic (timed FFT-or-matrix-core choice for short pencils), 1 = generic DST kernel
+    """0 = automatic (plain passes of an operator use the kernel its setup timed fastest), 1 = generic DST kernel
     everywhere, 2 = length-specialised kernels only, 3 = one-tile strided kernels, 4 = matrix-core
-    products for every plain pass of even N <= 128, 5 = automatic without them."""
+    products for every plain pass of even N <= 128, 5 = automatic without setup-time choices."""
     _check(_lib.ahoc_set_dst_variant(int(variant)), "ahoc_set_dst_variant")
 
 

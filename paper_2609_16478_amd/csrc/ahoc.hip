@@ -680,8 +680,8 @@ int gemm_mask(const ahoc_handle* h) {
   int m = 0;
   for (int a = 0; a < h->g.dim; ++a)
     for (int k = 0; k < 2; ++k) {
-      const bool on = h->opt.precision == AHOC_MIXED ? (h->p32.ready && h->p32.tb[a].gemm[k])
-                                                     : (h->p64.ready && h->p64.tb[a].gemm[k]);
+      const bool on = h->opt.precision == AHOC_MIXED ? (h->p32.ready && h->p32.tb[a].method[k] == DST_M_GEMM)
+                                                     : (h->p64.ready && h->p64.tb[a].method[k] == DST_M_GEMM);
       if (on) m |= 1 << (2 * a + k);
     }
   return m;
@@ -1133,9 +1133,9 @@ void ahoc_destroy(ahoc_handle* h) {
 
 size_t ahoc_nq(const ahoc_handle* h) { return h ? (size_t)h->g.nq : 0; }
 
-ahoc_status ahoc_dst_choice(const ahoc_handle* h, int precision, int axis, int kind, int* gemm, double* t_fft_us,
-                            double* t_gemm_us) {
-  if (!h || !gemm || (precision != AHOC_FP64 && precision != AHOC_MIXED) || axis < 0 || axis >= h->g.dim ||
+ahoc_status ahoc_dst_choice(const ahoc_handle* h, int precision, int axis, int kind, int* method, int* tile,
+                            double* t_default_us, double* t_gemm_us, double* t_best_us) {
+  if (!h || !method || (precision != AHOC_FP64 && precision != AHOC_MIXED) || axis < 0 || axis >= h->g.dim ||
       (kind != 0 && kind != 1)) {
     ahoc::set_last_error("bad handle, precision, axis or kind", "ahoc_dst_choice");
     return AHOC_E_INVALID;
@@ -1145,12 +1145,15 @@ ahoc_status ahoc_dst_choice(const ahoc_handle* h, int precision, int axis, int k
     ahoc::set_last_error("the handle has no operator in this precision", "ahoc_dst_choice");
     return AHOC_E_UNSUPPORTED;
   }
-  const double tf = dbl ? h->p64.tb[axis].t_fft_us[kind] : h->p32.tb[axis].t_fft_us[kind];
-  const double tg = dbl ? h->p64.tb[axis].t_gemm_us[kind] : h->p32.tb[axis].t_gemm_us[kind];
-  const int ch = dbl ? h->p64.tb[axis].gemm[kind] : h->p32.tb[axis].gemm[kind];
-  *gemm = tf < 0 ? -1 : ch;
-  if (t_fft_us) *t_fft_us = tf;
-  if (t_gemm_us) *t_gemm_us = tg;
+  auto get = [&](const auto& tb) {
+    *method = tb.method[kind];
+    if (tile) *tile = tb.method[kind] == DST_M_TILE ? tb.tile[kind] : 0;
+    if (t_default_us) *t_default_us = tb.t_default_us[kind];
+    if (t_gemm_us) *t_gemm_us = tb.t_gemm_us[kind];
+    if (t_best_us) *t_best_us = tb.t_best_us[kind];
+  };
+  if (dbl) get(h->p64.tb[axis]);
+  else get(h->p32.tb[axis]);
   return AHOC_OK;
 }
 

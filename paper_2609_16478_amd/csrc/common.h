@@ -78,12 +78,17 @@ template <typename T> struct DstTables {
   T* sn = nullptr;       // sin(pi m / N), m = 0..N/2
   // half sine matrices of the matrix-core pass (even N <= DST_GEMM_MAX_N), [2][HP][HP]
   T* S = nullptr;
-  // setup-time choice per pass kind (0 rows, 1 strided): 1 = matrix-core pass; the timings
-  // (microseconds per pass, -1 = not timed) behind it
-  int gemm[2] = {0, 0};
-  double t_fft_us[2] = {-1.0, -1.0};
+  // setup-time choice per plain pass kind (0 rows, 1 strided), dst_tune.hip: method
+  // DST_M_DEFAULT (the default FFT kernel), DST_M_GEMM (matrix-core products) or
+  // DST_M_TILE (the one-tile FFT kernel with `tile` pencil pairs per work-group), -1 = not
+  // timed; the microseconds per pass behind it (-1 = not timed / not applicable)
+  int method[2] = {-1, -1};
+  int tile[2] = {0, 0};
+  double t_default_us[2] = {-1.0, -1.0};
   double t_gemm_us[2] = {-1.0, -1.0};
+  double t_best_us[2] = {-1.0, -1.0};
 };
+enum { DST_M_DEFAULT = 0, DST_M_GEMM = 1, DST_M_TILE = 2 };
 
 // Eigen-scaling parameters for the fused middle pass along the slowest axis.
 template <typename T> struct DstScale {
@@ -194,14 +199,15 @@ template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st);
 template <typename T>
 int dst_gemm_pass(const T* S, int N, const T* in, T* out, long long outer, long long inner, long long pitch,
                   hipStream_t st);
-// Times both methods for the plain pass of this shape (buf is overwritten) and records the
-// faster in tb.gemm; no-op outside automatic selection or without a sine matrix.
+// Times the candidate kernels for the plain pass of this shape (buf is overwritten) and
+// records the fastest in tb.method / tb.tile (dst_tune.hip); no-op outside automatic
+// selection.
 template <typename T>
 int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, long long pitch, hipStream_t st);
 
-// 0 = automatic (specialised kernels; the matrix-core pass where the setup-time timing chose
-// it), 1 = generic kernel only, 2 = specialised only, 3 = one-tile specialised kernels,
-// 4 = matrix-core pass for every plain pass it supports, 5 = as 0 without the matrix-core pass
+// 0 = automatic (specialised kernels; for plain passes the kernel the setup-time timing
+// chose), 1 = generic kernel only, 2 = specialised only, 3 = one-tile specialised kernels,
+// 4 = matrix-core pass for every plain pass it supports, 5 = as 0 without setup-time choices
 void dst_set_variant(int v);
 int dst_get_variant();
 

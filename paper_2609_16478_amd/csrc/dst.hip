@@ -488,7 +488,7 @@ template <typename T> void dst_tables_free(DstTables<T>& tb) {
   tb.tw = nullptr;
   tb.sn = nullptr;
   tb.S = nullptr;
-  tb.gemm[0] = tb.gemm[1] = 0;
+  tb.method[0] = tb.method[1] = -1;
   tb.N = 0;
 }
 
@@ -502,11 +502,14 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
              const DstFaces<T>* faces) {
   const int N = tb.N;
   if (inner == 1 && pitch < N - 1) return ST_INVALID;
-  // plain passes of short pencils: the matrix-core product where chosen (or forced)
-  if (tb.S && !fused && !(faces && faces->mode) && tile_seqs <= 0 &&
-      (g_variant == 4 || (g_variant == 0 && tb.gemm[inner == 1 ? 0 : 1]))) {
-    const int rc = dst_gemm_pass<T>(tb.S, N, in, out, outer, inner, pitch, st);
-    if (rc != ST_UNSUPPORTED) return rc;
+  // plain passes: the kernel chosen at setup (or the matrix-core product where forced)
+  if (!fused && !(faces && faces->mode) && tile_seqs <= 0) {
+    const int k = inner == 1 ? 0 : 1;
+    if (tb.S && (g_variant == 4 || (g_variant == 0 && tb.method[k] == DST_M_GEMM))) {
+      const int rc = dst_gemm_pass<T>(tb.S, N, in, out, outer, inner, pitch, st);
+      if (rc != ST_UNSUPPORTED) return rc;
+    }
+    if (g_variant == 0 && tb.method[k] == DST_M_TILE) tile_seqs = tb.tile[k];
   }
   if (g_variant != 1 && dst_fast_supported(N)) {
     const int rc = dst_fast_pass<T>(N, tb.tw, tb.sn, in, out, outer, inner, pitch, fused, tile_seqs, st, faces);

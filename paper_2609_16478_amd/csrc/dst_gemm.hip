@@ -11,14 +11,11 @@
 // 16 columns of the half matrix in registers as one MFMA operand for the work-group's
 // (persistent) lifetime, and streams tiles of pencils through LDS as the other, the
 // combinations e, o formed while loading.  Accumulation is in the working precision
-// (v_mfma_f32_16x16x4_f32, v_mfma_f64_16x16x4_f64).  Which method a pass uses is decided
-// at setup by timing both on the actual shape.
+// (v_mfma_f32_16x16x4_f32, v_mfma_f64_16x16x4_f64).  Whether a pass uses it is decided at
+// setup by timing it against the FFT kernels on the actual shape (dst_tune.hip).
 #include "common.h"
 
 #include <cmath>
-#include <map>
-#include <mutex>
-#include <tuple>
 #include <vector>
 
 namespace ahoc {
@@ -248,89 +245,11 @@ int dst_gemm_pass(const T* S, int N, const T* in, T* out, long long outer, long 
   }
 }
 
-namespace {
-// Choices already timed in this process, by (element size, N, outer, inner, pitch): every
-// later setup with the same pass shape reuses the first measurement, so that handles of one
-// process run the same kernels (and give bit-identical results) for the same problem.
-struct Timed {
-  int gemm;
-  double t_fft_us, t_gemm_us;
-};
-std::mutex g_tuned_mu;
-std::map<std::tuple<int, int, long long, long long, long long>, Timed> g_tuned;
-}  // namespace
-
-// Times the FFT pass and the GEMM pass on the given shape (in place on buf, which is
-// zeroed first: the timings do not depend on the values) and records the faster one in
-// tb.gemm[kind].  Only in automatic kernel selection (variant 0).
-template <typename T>
-int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, long long pitch, hipStream_t st) {
-  const int kind = inner == 1 ? 0 : 1;
-  tb.gemm[kind] = 0;
-  tb.t_fft_us[kind] = tb.t_gemm_us[kind] = -1.0;
-  if (!tb.S || dst_get_variant() != 0 || outer <= 0) return ST_OK;
-  const auto key = std::make_tuple((int)sizeof(T), tb.N, outer, inner, inner == 1 ? pitch : 0LL);
-  {
-    std::lock_guard<std::mutex> lk(g_tuned_mu);
-    const auto it = g_tuned.find(key);
-    if (it != g_tuned.end()) {
-      tb.gemm[kind] = it->second.gemm;
-      tb.t_fft_us[kind] = it->second.t_fft_us;
-      tb.t_gemm_us[kind] = it->second.t_gemm_us;
-      return ST_OK;
-    }
-  }
-  const int L = tb.N - 1;
-  const long long extent = inner == 1 ? (outer - 1) * pitch + L : outer * (long long)L * inner;
-  AHOC_HIP_TRY(hipMemsetAsync(buf, 0, sizeof(T) * (size_t)extent, st));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  AHOC_HIP_TRY(hipEventCreate(&e0));
-  hipError_t he = hipEventCreate(&e1);
-  if (he != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    set_last_error(hipGetErrorString(he), "dst_autotune");
-    return ST_HIP;
-  }
-  constexpr int REPS = 5;
-  float ms[2] = {0.f, 0.f};
-  int rc = ST_OK;
-  for (int method = 0; method < 2 && rc == ST_OK; ++method) {
-    for (int i = 0; i <= REPS && rc == ST_OK; ++i) {  // one untimed warm-up launch
-      if (i == 1 && hipEventRecord(e0, st) != hipSuccess) rc = ST_HIP;
-      if (rc == ST_OK)
-        rc = method == 0 ? dst_pass<T>(tb, buf, buf, outer, inner, pitch, nullptr, 0, st)
-                         : dst_gemm_pass<T>(tb.S, tb.N, buf, buf, outer, inner, pitch, st);
-    }
-    if (rc == ST_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms[method], e0, e1) != hipSuccess))
-      rc = ST_HIP;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (rc == ST_HIP) set_last_error("event timing failed", "dst_autotune");
-  if (rc != ST_OK) return rc;
-  Timed tm;
-  tm.t_fft_us = 1e3 * ms[0] / REPS;
-  tm.t_gemm_us = 1e3 * ms[1] / REPS;
-  tm.gemm = tm.t_gemm_us < tm.t_fft_us ? 1 : 0;
-  {
-    // a concurrent setup of the same shape may have stored its own timing first: keep that one
-    std::lock_guard<std::mutex> lk(g_tuned_mu);
-    tm = g_tuned.emplace(key, tm).first->second;
-  }
-  tb.gemm[kind] = tm.gemm;
-  tb.t_fft_us[kind] = tm.t_fft_us;
-  tb.t_gemm_us[kind] = tm.t_gemm_us;
-  return ST_OK;
-}
-
 template int dst_gemm_table<float>(float**, int, hipStream_t);
 template int dst_gemm_table<double>(double**, int, hipStream_t);
 template int dst_gemm_pass<float>(const float*, int, const float*, float*, long long, long long, long long,
                                   hipStream_t);
 template int dst_gemm_pass<double>(const double*, int, const double*, double*, long long, long long, long long,
                                    hipStream_t);
-template int dst_autotune<float>(DstTables<float>&, float*, long long, long long, long long, hipStream_t);
-template int dst_autotune<double>(DstTables<double>&, double*, long long, long long, long long, hipStream_t);
 
 }  // namespace ahoc

@@ -140,32 +140,66 @@ def test_gemm_batched_matches_fft(ah):
         assert _rel(u.cpu().numpy(), r.cpu().numpy()) < 1e-11, pb.name
 
 
-def test_setup_times_both_methods(ah):
+def test_setup_time_kernel_choice(ah):
+    """ahoc_setup times the candidate kernels of each plain pass shape and keeps the fastest;
+    the statistics report where the matrix-core pass won."""
     ah.set_dst_variant(0)
     # 2-D, x = 64 intervals: the contiguous passes of x are timed; y runs only fused passes
     p = W.manufactured("1 + 0.5*sin(2*pi*x)*cos(2*pi*y)", "sin(pi*x)**2*sin(pi*y)**2", (64, 48),
                        (0.0, 0.0), (1.0, 0.75))
     with ah.Solver(p, tol=1e-12) as s:
-        g, tf, tg = s.dst_choice(ah.FP64, 0, 0)
-        assert g in (0, 1) and tf > 0 and tg > 0
-        assert g == (1 if tg < tf else 0)
+        m, tile, td, tg, tb = s.dst_choice(ah.FP64, 0, 0)
+        assert m in (0, 1, 2) and td > 0 and tg > 0 and 0 < tb <= min(td, tg)
+        assert (m == 2) == (tile > 0)
+        assert tb == {0: td, 1: tg}.get(m, tb)
         assert s.dst_choice(ah.FP64, 1, 0)[0] == -1
         assert s.dst_choice(ah.FP64, 0, 1)[0] == -1
         _, _, _, st = s.solve()
-        assert st.converged and st.dst_gemm == (1 if g else 0)
-    # 3-D: contiguous x and strided y timed; a long axis (256) never
+        assert st.converged and st.dst_gemm == (1 if m == 1 else 0)
+    # 3-D: contiguous x and strided y timed (x = 256 has no matrix-core pass); z only fused
     p = W.poly_exact((256, 24, 16), 3)
     with ah.Solver(p, precision=ah.MIXED) as s:
-        assert s.dst_choice(ah.MIXED, 0, 0)[0] == -1
-        gy, tf, tg = s.dst_choice(ah.MIXED, 1, 1)
-        assert gy in (0, 1) and tf > 0 and tg > 0
+        mx, _, td, tg, tb = s.dst_choice(ah.MIXED, 0, 0)
+        assert mx in (0, 2) and tg == -1 and 0 < tb <= td
+        my, _, td, tg, tb = s.dst_choice(ah.MIXED, 1, 1)
+        assert my in (0, 1, 2) and td > 0 and tg > 0 and 0 < tb <= min(td, tg)
         assert s.dst_choice(ah.MIXED, 2, 1)[0] == -1
         _, _, _, st = s.solve()
-        assert st.converged and st.dst_gemm == (8 if gy else 0)
+        assert st.converged and st.dst_gemm == (8 if my == 1 else 0)
+    # a second handle with the same shapes makes the same choices (kept for the process)
+    with ah.Solver(p, precision=ah.MIXED) as s:
+        assert s.dst_choice(ah.MIXED, 0, 0)[0] == mx and s.dst_choice(ah.MIXED, 1, 1)[0] == my
     # forced or disabled selections are not timed
     ah.set_dst_variant(5)
     try:
         with ah.Solver(W.config1(32), tol=1e-12) as s:
-            assert s.dst_choice(ah.FP64, 0, 0) == (-1, -1.0, -1.0)
+            assert s.dst_choice(ah.FP64, 0, 0) == (-1, 0, -1.0, -1.0, -1.0)
+    finally:
+        ah.set_dst_variant(0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_tuned_one_tile_solves_match_default(ah, prec):
+    """Solves whose plain passes run the one-tile kernels at every tile the tuner may pick
+    (through the explicit-tile override) agree with the default kernels to rounding."""
+    p = ah.FP64 if prec == "fp64" else ah.MIXED
+    pb = W.config3(32)
+    ah.set_dst_variant(5)
+    try:
+        with ah.Solver(pb, precision=p, tol=1e-12) as s:
+            ref, *_ = s.solve()
+        for tile in (1, 2, 4, 8, 16):
+            for kind in (0, 1):
+                ah.set_dst_tile(kind, p, tile)
+            try:
+                with ah.Solver(pb, precision=p, tol=1e-12) as s:
+                    u, _, _, st = s.solve()
+            except ah.AhocError:
+                continue  # a tile the kernel cannot launch at this length
+            finally:
+                for kind in (0, 1):
+                    ah.set_dst_tile(kind, p, 0)
+            assert st.converged
+            assert _rel(u.cpu().numpy(), ref.cpu().numpy()) < 1e-10, tile
     finally:
         ah.set_dst_variant(0)
