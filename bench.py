@@ -159,8 +159,16 @@ def main():
     leaf = ("dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "dst_gen",
             "face_reduce", "precond")
 
+    choices = {}
+
     def run(prec, steps, warmup, **opts):
         s = ah.Solver(prob, precision=prec, **opts)
+        # setup-time kernel choice of the operator's plain DST passes (x rows, y strided)
+        for name, axis, kind in (("x_rows", 0, 0), ("y_strided", 1, 1)):
+            m, tile, td, tg, tb = s.dst_choice(prec, axis, kind)
+            choices[f"{'mixed' if prec == ah.MIXED else 'fp64'}_{name}"] = {
+                "method": {0: "fft_default", 1: "matrix_core", 2: f"fft_one_tile_{tile}"}.get(m, "untimed"),
+                "us_default": td, "us_chosen": tb}
         out = torch.empty(s.nodal_shape, dtype=torch.float64, device=dev)
         for i in range(warmup):
             _, _, _, st = s.solve(out=out)
@@ -326,7 +334,8 @@ def main():
                    "rel_err_vs_fp64_ref": err_mx_ref, "rel_err_vs_exact": err_mx_exact,
                    "model_bytes": bytes_mx, "end_to_end_hbm_frac": bytes_mx / dt_mx / (HBM_PEAK_GBS * 1e9),
                    "fp64_ref": {"tol": 1e-13, "gmres_iters": st_ref.gmres_iters},
-                   "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels},
+                   "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels,
+                   "dst_kernel_choice": choices},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_dst_pipe<float,{n},16,0> (FP32 DST-I pass along y, strided pencils, persistent and pipelined)",
