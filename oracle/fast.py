@@ -33,6 +33,20 @@ def _f(arr, shape):
     return np.zeros(shape) if arr is None else np.asarray(arr, dtype=np.float64)
 
 
+def laplacian_symbol(n, h, k):
+    """Eigenvalue of the compact L_h (homogeneous Dirichlet) on the sine mode with indices
+    k = (k_x, k_y[, k_z]) (arrays broadcast together) of a grid with n intervals and spacings
+    h: sum_a s_a + sum_{a<b} (h_a^2 + h_b^2)/12 s_a s_b with s_a = -(4/h_a^2) sin^2(k_a pi /
+    (2 n_a)), the 1-D second-difference symbol (Sec. 2.2 stencils, App. A recurrence)."""
+    dim = len(n)
+    S = [-(4.0 / h[a] ** 2) * np.sin(np.asarray(k[a]) * np.pi / (2 * n[a])) ** 2 for a in range(dim)]
+    lam = sum(S)
+    for a in range(dim):
+        for b in range(a + 1, dim):
+            lam = lam + (h[a] ** 2 + h[b] ** 2) / 12.0 * S[a] * S[b]
+    return lam
+
+
 class FastTier:
     def __init__(self, problem, workers=None):
         g = Grid(problem.n, problem.lo, problem.hi)
@@ -55,17 +69,8 @@ class FastTier:
     # -- fast Poisson solver --------------------------------------------------------------
     def _eigen(self):
         g = self.g
-        s = []
-        for a in range(g.dim):
-            k = np.arange(1, g.n[a])
-            s.append(-(4.0 / g.h[a] ** 2) * np.sin(k * np.pi / (2 * g.n[a])) ** 2)
-        grids = np.meshgrid(*[s[a] for a in reversed(range(g.dim))], indexing="ij")
-        S = list(reversed(grids))  # S[a] broadcast over interior (memory order)
-        lam = sum(S)
-        for a in range(g.dim):
-            for b in range(a + 1, g.dim):
-                lam = lam + (g.h[a] ** 2 + g.h[b] ** 2) / 12.0 * S[a] * S[b]
-        return lam
+        grids = np.meshgrid(*[np.arange(1, g.n[a]) for a in reversed(range(g.dim))], indexing="ij")
+        return laplacian_symbol(g.n, g.h, list(reversed(grids)))
 
     def poisson(self, G):
         """Interior W with L_int W = G (homogeneous Dirichlet), by DST-I in every axis."""
