@@ -73,6 +73,29 @@ def cpu_baseline(n=80):
             "time_s": dt}
 
 
+def _pitch(n):
+    return (n - 1 + 31) // 32 * 32
+
+
+def _pattern_copies(ah, torch, dev, n, reps=5):
+    """GB/s (read + write) of the library's calibration copies over an FP32 volume of the
+    solver's interior work-array shape [n-1][n-1][pitch]: linear, y-pass tiles, z-pass tiles."""
+    x = torch.zeros(n - 1, n - 1, _pitch(n), dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    out = {}
+    for name, pattern in (("linear", 0), ("y_tiles", 1), ("z_tiles", 2)):
+        ah.copy_bandwidth(pattern, x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ah.copy_bandwidth(pattern, x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        out[name] = reps * 2 * x.numel() * 4 / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del x, y
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +139,9 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(f"[bench] copy calibration: 3 copies of {x.numel() * 8} bytes", file=sys.stderr)
+        gb = _pattern_copies(ah, torch, dev, args.n)
+        print(f"[bench] calibration copies of the {args.n - 1}^2 x {_pitch(args.n)} FP32 volume: "
+              + ", ".join(f"{k} {v:.0f} GB/s" for k, v in gb.items()), file=sys.stderr)
         return
     if args.dst_compare:
         for N in (32, 64, 128):
@@ -227,19 +253,11 @@ def main():
     s.close()
     del y, q
     ms, cnt, bytes_launch = kt["dst_strided"]
-    # reference device bandwidth: a plain 2 GiB device-to-device copy (the runtime blit
-    # kernel, read + write), HIP events
-    xc = torch.empty(2 ** 28, dtype=torch.float64, device=dev)
-    yc = torch.empty_like(xc)
-    yc.copy_(xc)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        yc.copy_(xc)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbps = 5 * 2 * xc.numel() * 8 / (e0.elapsed_time(e1) / 1e3) / 1e9
-    del xc, yc
+    # reference device bandwidth: the library's calibration copies of a volume of the work
+    # arrays' shape (read + write, HIP events): linear, and with the strided y pass's access
+    # pattern (its roofline on this device)
+    gb = _pattern_copies(ah, torch, dev, n)
+    copy_gbps, pattern_gbps = gb["linear"], gb["y_tiles"]
     avg_s = ms / cnt / 1e3
     achieved = bytes_launch / avg_s / 1e9
     pmc = _pmc_traffic(_src_hash())
@@ -340,7 +358,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_dst_pipe<float,{n},16,0> (FP32 DST-I pass along y, strided pencils, persistent and pipelined)",
                      "bytes_per_launch": bytes_launch, "avg_launch_us": avg_s * 1e6,
-                     "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps},
+                     "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
+                     "pattern_copy_GBps": pattern_gbps, "frac_of_pattern_copy": achieved / pattern_gbps,
+                     "z_pattern_copy_GBps": gb["z_tiles"]},
         "cpu_baseline": ({k: cpu[k] for k in ("value", "unit", "cores", "kind", "sample")} if cpu else None),
     }
     print(json.dumps(line), flush=True)

@@ -186,6 +186,16 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
  * family. */
 ahoc_status ahoc_set_dst_variant(int variant);
 
+/* Calibration copies (no arithmetic): out = in for an [nz][ny][nx] FP32 volume, with the
+ * global access pattern of pattern 0 = a linear copy (16-byte accesses), 1 = the strided DST
+ * passes along y (persistent work-groups of 1024 threads, tiles of 32 columns = 128-byte row
+ * segments across the ny rows of a plane), 2 = the strided passes along z (the same tiles
+ * across the nz planes).  They measure the bandwidth the passes' access patterns allow on
+ * the device (the roofline the DST kernels are compared with).  in, out: device pointers to
+ * nx*ny*nz floats, owned by the caller (in == out allowed); nx must be a multiple of 32.
+ * Asynchronous on the stream.  AHOC_E_INVALID on a bad argument. */
+ahoc_status ahoc_copy_bandwidth(int pattern, const float* in, float* out, int nx, int ny, int nz, void* stream);
+
 /* The setup-time choice of kernel for the plain DST-I passes along one axis of the
  * operator (the sine transforms of Sec. 2.3; every candidate gives the same transform up to
  * rounding).  ahoc_setup times, on the handle's own pass shape and in automatic kernel

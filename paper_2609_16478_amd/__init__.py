@@ -81,6 +81,8 @@ _lib.ahoc_set_dst_tile.restype = c_int
 _lib.ahoc_dst_choice.argtypes = [_H, c_int, c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),
                                  ctypes.POINTER(c_double), ctypes.POINTER(c_double), ctypes.POINTER(c_double)]
 _lib.ahoc_dst_choice.restype = c_int
+_lib.ahoc_copy_bandwidth.argtypes = [c_int, c_void_p, c_void_p, c_int, c_int, c_int, c_void_p]
+_lib.ahoc_copy_bandwidth.restype = c_int
 _lib.ahoc_destroy.argtypes = [_H]
 _lib.ahoc_status_string.argtypes = [c_int]
 _lib.ahoc_status_string.restype = ctypes.c_char_p
@@ -89,7 +91,7 @@ _lib.ahoc_last_error.restype = ctypes.c_char_p
 KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "resid",
                 "matvec", "dst_gen", "face_reduce", "precond"]
 
-EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_dst_choice", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
+EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_dst_choice", "ahoc_copy_bandwidth", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
             "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
             "ahoc_status_string", "ahoc_last_error"]
 
@@ -314,6 +316,14 @@ def set_dst_tile(pass_kind: int, precision: int, pairs: int):
     """Default work-group tile (pencil pairs) of one DST pass kind: 0 rows, 1 strided, 2 fused;
     pairs = 0 restores the built-in choice."""
     _check(_lib.ahoc_set_dst_tile(int(pass_kind), int(precision), int(pairs)), "ahoc_set_dst_tile")
+
+
+def copy_bandwidth(pattern, x, out):
+    """Calibration copy out <- x of a float32 [nz][ny][nx] tensor (nx % 32 == 0): pattern 0
+    linear, 1 the strided DST passes' tiles along y, 2 along z (asynchronous, current stream)."""
+    assert x.dtype == out.dtype and x.dim() == 3 and x.is_contiguous() and out.is_contiguous()
+    nz, ny, nx = x.shape
+    _check(_lib.ahoc_copy_bandwidth(int(pattern), _ptr(x), _ptr(out), nx, ny, nz, _stream()), "ahoc_copy_bandwidth")
 
 
 def dst1(x, axis, precision=FP64):

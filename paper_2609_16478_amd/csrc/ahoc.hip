@@ -1133,6 +1133,12 @@ void ahoc_destroy(ahoc_handle* h) {
 
 size_t ahoc_nq(const ahoc_handle* h) { return h ? (size_t)h->g.nq : 0; }
 
+ahoc_status ahoc_copy_bandwidth(int pattern, const float* in, float* out, int nx, int ny, int nz, void* stream) {
+  const int rc = ahoc::copy_bandwidth(pattern, in, out, nx, ny, nz, (hipStream_t)stream);
+  if (rc == ahoc::ST_INVALID) ahoc::set_last_error("bad pattern, pointer or size (nx % 32)", "ahoc_copy_bandwidth");
+  return (ahoc_status)rc;
+}
+
 ahoc_status ahoc_dst_choice(const ahoc_handle* h, int precision, int axis, int kind, int* method, int* tile,
                             double* t_default_us, double* t_gemm_us, double* t_best_us) {
   if (!h || !method || (precision != AHOC_FP64 && precision != AHOC_MIXED) || axis < 0 || axis >= h->g.dim ||

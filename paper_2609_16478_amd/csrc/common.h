@@ -205,6 +205,10 @@ int dst_gemm_pass(const T* S, int N, const T* in, T* out, long long outer, long 
 template <typename T>
 int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, long long pitch, hipStream_t st);
 
+// Calibration copies of an [nz][ny][nx] FP32 volume (calib.hip): pattern 0 linear, 1 the
+// strided passes' tiles along y, 2 along z.
+int copy_bandwidth(int pattern, const float* in, float* out, int nx, int ny, int nz, hipStream_t st);
+
 // 0 = automatic (specialised kernels; for plain passes the kernel the setup-time timing
 // chose), 1 = generic kernel only, 2 = specialised only, 3 = one-tile specialised kernels,
 // 4 = matrix-core pass for every plain pass it supports, 5 = as 0 without setup-time choices

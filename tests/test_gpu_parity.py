@@ -397,3 +397,21 @@ def test_precond_rejected_when_disabled(ah):
     with ah.Solver(W.config2(16), precond=0) as s:
         with pytest.raises(ah.AhocError):
             s.precond_apply(np.zeros(s.nq))
+
+
+# ------------------------------------------------------------------------------------------
+# calibration copies (the bandwidth references of the DST passes)
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(17, 33, 64), (5, 1023, 1024), (70, 3, 32)])
+def test_copy_bandwidth_patterns_are_exact_copies(ah, shape):
+    x = torch.randn(*shape, dtype=torch.float32, device="cuda")
+    for pattern in (0, 1, 2):
+        y = torch.full_like(x, float("nan"))
+        ah.copy_bandwidth(pattern, x, y)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y), (shape, pattern)
+    with pytest.raises(ah.AhocError):
+        ah.copy_bandwidth(1, x[:, :, :16].contiguous(), torch.empty_like(x[:, :, :16]))
+    with pytest.raises(ah.AhocError):
+        ah.copy_bandwidth(3, x, torch.empty_like(x))
