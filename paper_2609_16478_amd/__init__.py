@@ -285,7 +285,11 @@ class Solver:
 
 
 def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
-    """Solve independent problems with shared options; returns (list of u, list of Stats, status)."""
+    """Solve independent problems with shared options; returns (list of u, list of Stats, status).
+
+    An instance that is rejected (E_INVALID, E_UNSUPPORTED) or does not converge does not
+    stop the others: the call returns the first such status and that instance's Stats say
+    converged=False; device or memory failures raise AhocError."""
     torch = _torch()
     dev = torch.device(device)
     keep, structs, outs = [], [], []
@@ -300,7 +304,7 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
     sarr = (_Stats * cnt)()
     o = default_options(precision, **opts)
     rc = _lib.ahoc_solve_batched(cnt, parr, ctypes.byref(o), uarr, sarr, _stream())
-    if rc not in (OK, E_NOCONV):
+    if rc not in (OK, E_NOCONV, E_INVALID, E_UNSUPPORTED):
         _check(rc, "ahoc_solve_batched")
     return outs, [_stats(s) for s in sarr], rc
 

@@ -43,3 +43,38 @@ def test_host_only_entry_points():
     assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID
     p.dim = 2
     assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID  # NULL alpha
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libahoc.so not built")
+def test_argument_errors_before_device_work():
+    """Every rejected argument is caught on the host (the pointers below are never read)."""
+    import paper_2609_16478_amd as ah
+    fake = ctypes.c_void_p(64)
+
+    def problem(n, lo=(0.0, 0.0), hi=(1.0, 1.0)):
+        p = ah._Problem()
+        p.dim = 2
+        for a in range(2):
+            p.n[a], p.lo[a], p.hi[a] = n[a], lo[a], hi[a]
+        p.alpha = fake
+        p.f = fake
+        return p
+
+    h = ctypes.c_void_p()
+    for p, code in ((problem((7, 16)), ah.E_INVALID),                         # n < 8
+                    (problem((16, 16), hi=(1.0, 0.0)), ah.E_INVALID),         # hi <= lo
+                    (problem((40, 16)), ah.E_UNSUPPORTED)):                   # no transform plan
+        assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == code
+    o = ah.default_options()
+    o.precision = 7
+    p = problem((16, 16))
+    assert ah._lib.ahoc_setup(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == ah.E_INVALID
+    # batches: a negative count is rejected, an empty batch is a no-op
+    assert ah._lib.ahoc_solve_batched(-1, None, None, None, None, None) == ah.E_INVALID
+    assert ah._lib.ahoc_solve_batched(0, None, None, None, None, None) == ah.OK
+    # calibration copies: unknown pattern, rows not a multiple of 32 columns
+    assert ah._lib.ahoc_copy_bandwidth(3, fake, fake, 64, 4, 4, None) == ah.E_INVALID
+    assert ah._lib.ahoc_copy_bandwidth(1, fake, fake, 48, 4, 4, None) == ah.E_INVALID
+    # kernel-choice query without a handle
+    m = ctypes.c_int()
+    assert ah._lib.ahoc_dst_choice(None, ah.FP64, 0, 0, ctypes.byref(m), None, None, None, None) == ah.E_INVALID

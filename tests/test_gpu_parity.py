@@ -415,3 +415,46 @@ def test_copy_bandwidth_patterns_are_exact_copies(ah, shape):
         ah.copy_bandwidth(1, x[:, :, :16].contiguous(), torch.empty_like(x[:, :, :16]))
     with pytest.raises(ah.AhocError):
         ah.copy_bandwidth(3, x, torch.empty_like(x))
+
+
+# ------------------------------------------------------------------------------------------
+# edge cases: minimum grids, rejected coefficients, a batch with a failing instance
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [(8, 8), (8, 16), (8, 8, 8)])
+def test_minimum_grids_match_direct(ah, n):
+    p = W.poly_exact(n, len(n))
+    U, V, Q, asm = direct.solve(p)
+    for prec in (ah.FP64, ah.MIXED):
+        with ah.Solver(p, precision=prec, tol=1e-14) as s:
+            u, _, _, st = s.solve()
+        assert st.converged
+        assert _rel(u.cpu().numpy(), U) < (1e-12 if prec == ah.FP64 else 1e-10), (n, prec)
+
+
+def test_nonpositive_alpha_rejected(ah):
+    p = W.config2(16)
+    a = np.array(p.alpha, copy=True)
+    a[5, 7] = 0.0
+    p.alpha = a
+    with pytest.raises(ah.AhocError) as e:
+        ah.Solver(p)
+    assert e.value.code == ah.E_INVALID
+
+
+def test_batch_with_a_rejected_instance(ah):
+    """A rejected instance does not stop the others: the call returns its status and the
+    valid instances are solved as if alone."""
+    probs = [W.config4_instance(sp) for sp in W.config4_specs(4, seed=2)]
+    bad = W.config2(16)
+    a = np.array(bad.alpha, copy=True)
+    a[3, 3] = -1.0
+    bad.alpha = a
+    outs, stats, rc = ah.solve_batched(probs[:2] + [bad] + probs[2:], tol=1e-13)
+    assert rc == ah.E_INVALID
+    good = [0, 1, 3, 4]
+    for k, pb in zip(good, probs):
+        assert stats[k].converged, pb.name
+        with ah.Solver(pb, tol=1e-13) as s:
+            u1, *_ = s.solve()
+        assert _rel(outs[k].cpu().numpy(), u1.cpu().numpy()) < 1e-12, pb.name
