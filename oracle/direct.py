@@ -4,14 +4,15 @@ Test infrastructure only (see the package docstring).
 
 Unknowns (Section 2.2, block system eq-coupled): U at interior nodes, V at
 interior nodes, Q at face-interior nodes (Remark 1).  Rows, for a fully
-clamped box with beta = 0:
+clamped box and a constant beta:
 
 * u-rows (Sec. 2.2, L_h U = M(V/alpha)): at every interior node,
   L_h U - M(V/alpha) = 0, with U = g_D on the boundary.  M reaches the
   face-interior boundary nodes, where V = Q, so the u-rows couple to Q.
-* v-rows (Sec. 2.2, -L_h V + M(beta V/alpha) = M f, beta = 0): at every interior
-  node -L_h V = M f, with V = Q on face-interior nodes and, on edges and
-  corners, V = alpha * (Delta u from the Dirichlet data) (Remark 1).
+* v-rows (Sec. 2.2, -L_h V + M(beta V/alpha) = M f): at every interior node,
+  with V = Q on face-interior nodes and, on edges and corners, V = alpha * (Delta u
+  from the Dirichlet data) (Remark 1).  M reaches face-interior nodes only, so
+  the beta term couples to interior V and to Q.
 * q-rows (Lemma 1, boundary residual R): at every face-interior node,
   alpha_b [ (delta_nn U)_b + (tangential part of Delta u)_b ] - Q_b = 0 with the
   one-sided formula of Sec. 2.2, written for the face's outward normal.
@@ -75,6 +76,7 @@ def assemble(problem) -> Assembled:
     lapgD = _field(problem.lapgD, g)
     if alpha.min() <= 0:
         raise ValueError("alpha must be positive")
+    beta = float(getattr(problem, "beta", 0.0) or 0.0)
     L = laplacian(g.h)
     M = weighting(g.dim)
     n = g.n_int
@@ -109,7 +111,7 @@ def assemble(problem) -> Assembled:
                 add(ru, 2 * n + g.q_of[q], -w * inv_a)
             else:
                 raise AssertionError("M never reaches an edge or corner node")
-        # v-row: -L_h V = M f
+        # v-row: -L_h V + M(beta V / alpha) = M f
         for o, w in L.items():
             q = shift(p, o)
             if g.is_interior(q):
@@ -119,7 +121,16 @@ def assemble(problem) -> Assembled:
             else:
                 F[rv] += w * g.at(alpha, q) * g.at(lapgD, q)
         for o, w in M.items():
-            F[rv] += w * g.at(f, shift(p, o))
+            q = shift(p, o)
+            F[rv] += w * g.at(f, q)
+            if beta != 0.0:
+                c = w * beta / g.at(alpha, q)
+                if g.is_interior(q):
+                    add(rv, n + g.interior_index(q), c)
+                elif g.is_face_interior(q):
+                    add(rv, 2 * n + g.q_of[q], c)
+                else:
+                    raise AssertionError("M never reaches an edge or corner node")
     # q-rows: alpha_b [ delta_nn U + 11 g_N / (3h) + lapgD ] - Q = 0
     for pq, b in enumerate(g.q_nodes):
         r = 2 * n + pq

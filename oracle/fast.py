@@ -47,12 +47,36 @@ def laplacian_symbol(n, h, k):
     return lam
 
 
+def weighting_symbol(n, k):
+    """Eigenvalue of the weighting operator M (homogeneous Dirichlet) on the sine mode with
+    indices k (arrays broadcast together) of a grid with n intervals: sum over M's offsets o
+    of w_o prod_a cos(pi k_a o_a / n_a) (M is symmetric, so each pair of opposite offsets
+    turns the mode's shift into a cosine)."""
+    dim = len(n)
+    out = 0.0
+    for o, w in weighting(dim).items():
+        term = w
+        for a in range(dim):
+            if o[a]:
+                term = term * np.cos(np.pi * np.asarray(k[a]) * o[a] / n[a])
+        out = out + term
+    return out
+
+
 class FastTier:
+    """Algorithm 1 with library sine transforms.  A nonzero beta needs a constant alpha:
+    the v-equation -L_h V + (beta/alpha) M V = M f is then diagonal in the sine basis with
+    the eigenvalue lambda_L - (beta/alpha) mu_M."""
+
     def __init__(self, problem, workers=None):
         g = Grid(problem.n, problem.lo, problem.hi)
         self.g = g
         self.workers = workers
         self.alpha = _f(problem.alpha, g.nodal_shape)
+        self.beta = float(getattr(problem, "beta", 0.0) or 0.0)
+        if self.beta != 0.0 and np.ptp(self.alpha) > 1e-14 * np.abs(self.alpha).max():
+            raise ValueError("a nonzero beta needs a constant alpha in the fast tier")
+        self.c = self.beta / float(self.alpha.flat[0])
         self.f = _f(problem.f, g.nodal_shape)
         self.gD = _f(problem.gD, g.nodal_shape)
         self.gN = _f(problem.gN, g.nodal_shape)
@@ -60,6 +84,10 @@ class FastTier:
         self.L = laplacian(g.h)
         self.M = weighting(g.dim)
         self.lam = self._eigen()
+        self.lam_v = self.lam
+        if self.c != 0.0:
+            grids = np.meshgrid(*[np.arange(1, g.n[a]) for a in reversed(range(g.dim))], indexing="ij")
+            self.lam_v = self.lam - self.c * weighting_symbol(g.n, list(reversed(grids)))
         self.inner = tuple(slice(1, m) for m in reversed(g.n))
         # face-interior node coordinates in Q order, per face, as index arrays
         self._qidx = np.array([tuple(reversed(idx)) for idx in g.q_nodes], dtype=np.int64)
@@ -87,11 +115,16 @@ class FastTier:
 
     # -- the two subproblems ----------------------------------------------------------------
     def v_solve(self, Q):
-        """-L_h V = M f at interior nodes with boundary V from Q (Algorithm 1, v-equation)."""
+        """-L_h V + (beta/alpha) M V = M f at interior nodes with boundary V from Q
+        (Algorithm 1, v-equation)."""
         Vb = self._v_boundary(Q)
         Lb = apply(self.L, Vb, self.g)       # boundary contributions of L_h
+        rhs = -self.Mf - Lb
+        if self.c != 0.0:
+            rhs = rhs + self.c * apply(self.M, Vb, self.g)  # and of (beta/alpha) M
         V = Vb.copy()
-        V[self.inner] = self.poisson(-self.Mf - Lb)
+        Gh = sfft.dstn(rhs, type=1, workers=self.workers)
+        V[self.inner] = sfft.idstn(Gh / self.lam_v, type=1, workers=self.workers)
         return V
 
     def u_solve(self, V):

@@ -1,0 +1,92 @@
+"""Pins for the oracle's beta term (CPU): -Delta(alpha Delta u) + beta Delta u = f, beta constant.
+
+With v = alpha Delta u the v-equation becomes -Delta v + beta v / alpha = f, discretised
+(Sec. 2.2) as -L_h V + M(beta V / alpha) = M f.  Pins, none of which restates that line:
+
+* polynomial exactness of the whole coupled system with beta (the compact operators are
+  exact for the degree-5 V of a degree-4 u and degree-3 alpha, so f = -Delta V + beta V/alpha
+  is reproduced exactly), variable and constant alpha, positive and negative beta; and a
+  planted omission (the beta term dropped while f keeps it) that breaks it;
+* fourth-order convergence of a singularly perturbed case in the spirit of Example 1
+  (alpha = eps constant, beta = 1);
+* the fast tier (sine transforms with the shifted eigenvalue lambda_L - (beta/alpha) mu_M)
+  against the direct tier;
+* the weighting operator's symbol against its stencil applied to sine modes.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import direct, fast
+from oracle.grid import Grid
+from oracle.stencils import weighting, apply
+
+
+@pytest.mark.parametrize("n,beta", [(8, 3.0), ((13, 9), -2.0), (16, 40.0)])
+def test_polynomial_exactness_with_beta_2d(n, beta):
+    p = W.poly_exact(n, 2, beta=beta)
+    U, V, Q, asm = direct.solve(p)
+    assert np.abs(U - p.u_exact).max() < 1e-12
+    assert np.abs(V - p.v_exact).max() < 1e-9
+
+
+@pytest.mark.parametrize("n,beta", [(5, 1.5), ((6, 4, 5), -0.7)])
+def test_polynomial_exactness_with_beta_3d(n, beta):
+    p = W.poly_exact(n, 3, beta=beta)
+    U, V, Q, asm = direct.solve(p)
+    assert np.abs(U - p.u_exact).max() < 1e-12
+    assert np.abs(V - p.v_exact).max() < 1e-9
+
+
+def test_dropped_beta_term_breaks_exactness():
+    p = W.poly_exact(8, 2, beta=3.0)
+    p.beta = 0.0  # f still carries beta Delta u
+    U, *_ = direct.solve(p)
+    assert np.abs(U - p.u_exact).max() > 1e-6
+
+
+def test_fourth_order_singularly_perturbed():
+    # alpha = eps, beta = 1: -eps Delta^2 u + Delta u = f (the operator of Example 1)
+    errs = []
+    for n in (16, 32, 64, 128):
+        p = W.manufactured("0.01", "sin(pi*x)**2*sin(pi*y)**2*exp(x + y)", (n, n), beta=1.0)
+        U, *_ = direct.solve(p)
+        errs.append(np.abs(U - p.u_exact).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(14.0 < r < 19.0 for r in ratios), (errs, ratios)
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: W.manufactured("0.5", "sin(pi*x)**2*sin(pi*y)**2*exp(x + y)", (16, 12), (0.0, 0.0), (1.0, 0.75),
+                           beta=2.0),
+    lambda: W.manufactured("2", "sin(pi*x)**2*sin(pi*y)**2", (16, 16), beta=-5.0),
+    lambda: W.manufactured("1", "sin(pi*x)**2*sin(pi*y)**2*sin(pi*z)**2", (8, 6, 10), beta=3.0),
+], ids=["2d_aniso", "2d_negative", "3d"])
+def test_fast_tier_with_beta_equals_direct(maker):
+    p = maker()
+    U, V, Q, _ = direct.solve(p)
+    U2, V2, Q2, info = fast.FastTier(p).solve(tol=1e-14, restart=60)
+    assert np.abs(U2 - U).max() <= 1e-12 * np.abs(U).max()
+    assert np.abs(Q2 - Q).max() <= 1e-11 * np.abs(Q).max()
+
+
+def test_fast_tier_rejects_variable_alpha_with_beta():
+    with pytest.raises(ValueError):
+        fast.FastTier(W.poly_exact(8, 2, beta=1.0))
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_weighting_symbol_matches_stencil_on_sine_modes(dim):
+    n = (6, 5, 7)[:dim]
+    g = Grid(n, (0.0,) * dim, (1.0, 0.7, 1.3)[:dim])
+    M = weighting(dim)
+    for k in ((1, 1, 1), (2, 4, 3), (5, 2, 6)):
+        k = k[:dim]
+        mode = np.ones(g.nodal_shape)
+        for a in range(dim):
+            shape = [1] * dim
+            shape[dim - 1 - a] = n[a] + 1
+            mode = mode * np.sin(np.pi * k[a] * np.arange(n[a] + 1) / n[a]).reshape(shape)
+        mu = fast.weighting_symbol(n, k)
+        inner = tuple(slice(1, m) for m in reversed(n))
+        assert np.abs(apply(M, mode, g) - mu * mode[inner]).max() < 1e-14

@@ -4,7 +4,7 @@ This module holds the *inputs* only: analytic coefficient fields alpha, the
 manufactured solutions u, and the data that the model problem of Section 2
 (eq. (1) with the clamped conditions (eq-bc)) derives from them:
 
-    f      = -div(alpha grad-free Laplacian): f = -Delta(alpha Delta u) + beta Delta u, beta = 0
+    f      = -Delta(alpha Delta u) + beta Delta u  (beta a constant, 0 unless given)
     g_D    = u on the boundary
     g_N    = outward normal derivative of u on the relative interior of each face
     lapgD  = on face-interior nodes, the tangential part of Delta u (what the
@@ -34,7 +34,9 @@ __all__ = [
 
 @dataclass
 class Problem:
-    """One clamped problem on a box: grid, coefficient and data (nodal arrays).
+    """One clamped problem on a box: grid, coefficients and data (nodal arrays).
+
+    The equation is -Delta(alpha Delta u) + beta Delta u = f with beta a constant.
 
     n: intervals per axis, axis order (x, y[, z]).  lo/hi: box corners.
     Arrays are numpy (host) or torch tensors; None means identically zero.
@@ -53,6 +55,7 @@ class Problem:
     v_exact: Any = None
     name: str = ""
     meta: dict = field(default_factory=dict)
+    beta: float = 0.0
 
     @property
     def dim(self) -> int:
@@ -216,11 +219,12 @@ def _boundary_data(ev: _Eval, n, c1d):
 
 def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None, *,
                  params=(), pvals=(), xp="numpy", device=None, with_exact=True,
-                 chunk=None, name=""):
+                 chunk=None, name="", beta=0.0):
     """Sample a manufactured clamped problem.
 
     alpha_src/u_src: expressions in x, y[, z] (and `params`).  f follows the
-    paper's sign convention of eq. (1) with beta = 0.  xp = "numpy" gives host
+    paper's sign convention of eq. (1), f = -Delta(alpha Delta u) + beta Delta u with the
+    constant beta.  xp = "numpy" gives host
     arrays; xp = "torch" builds the nodal fields on `device` (in z-chunks of
     `chunk` planes for large 3-D grids).
     """
@@ -230,7 +234,7 @@ def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None,
     ev = _Eval(alpha_src, u_src, dim, params, pvals, xp, device)
     c1d = node_coords(n, lo, hi)
     shape = tuple(n[a] + 1 for a in reversed(range(dim)))
-    keys = ["alpha", "f"] + (["u", "v"] if with_exact else [])
+    keys = ["alpha", "f"] + (["u", "v"] if with_exact else []) + (["lapu"] if beta else [])
     out = {}
     if dim == 3 and chunk is not None:
         for k in keys:
@@ -244,10 +248,13 @@ def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None,
         cs = [ev.coords(c1d[a], a) for a in range(dim)]
         for k in keys:
             out[k] = ev(k, cs)
+    if beta:
+        out["f"] = out["f"] + float(beta) * out.pop("lapu")
     gD, gN, lap = _boundary_data(ev, n, c1d)
     return Problem(tuple(n), lo, hi, out["alpha"], out["f"], gD, gN, lap,
                    out.get("u"), out.get("v"), name=name,
-                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals))})
+                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals)), "beta": float(beta)},
+                   beta=float(beta))
 
 
 # --------------------------------------------------------------------------------------
