@@ -53,9 +53,14 @@ typedef enum {
                      residual, Krylov vectors, Arnoldi, Givens, updates in FP64   */
 } ahoc_precision;
 
-/* One clamped problem.  alpha and f are required; gD, gN, lapgD may be NULL (= 0).
+/* One clamped problem of eq. (1), -Delta(alpha Delta u) + beta Delta u = f.  alpha and f
+ * are required; gD, gN, lapgD may be NULL (= 0).
  *   alpha  nodal coefficient, must satisfy alpha > 0 everywhere (checked)
- *   f      nodal right-hand side in the sign of eq. (1): f = -Delta(alpha Delta u)
+ *   f      nodal right-hand side in the sign of eq. (1)
+ *   beta   a constant; 0 for the biharmonic-type problem.  beta != 0 needs a constant
+ *          alpha (the v-equation -L_h V + (beta/alpha) M V = M f is then solved by the
+ *          sine transforms with a shifted eigenvalue) and, in MIXED precision, the Schur
+ *          refinement (refine = 1); otherwise AHOC_E_UNSUPPORTED
  *   gD     nodal; boundary entries are the Dirichlet data u = g_D
  *   gN     nodal; on face-interior nodes the OUTWARD normal derivative of u
  *   lapgD  nodal; on face-interior nodes the tangential part of Delta u fixed by
@@ -71,6 +76,7 @@ typedef struct {
   const double* gD;
   const double* gN;
   const double* lapgD;
+  double beta;
 } ahoc_problem;
 
 typedef struct {

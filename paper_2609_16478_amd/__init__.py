@@ -32,7 +32,7 @@ c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_vo
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int * 3), ("lo", c_double * 3), ("hi", c_double * 3),
                 ("alpha", c_void_p), ("f", c_void_p), ("gD", c_void_p), ("gN", c_void_p),
-                ("lapgD", c_void_p)]
+                ("lapgD", c_void_p), ("beta", c_double)]
 
 
 class _Options(ctypes.Structure):
@@ -161,10 +161,11 @@ def _stats(s: _Stats) -> Stats:
                  s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm)
 
 
-def _problem_struct(n, lo, hi, tens):
+def _problem_struct(n, lo, hi, tens, beta=0.0):
     dim = len(n)
     p = _Problem()
     p.dim = dim
+    p.beta = float(beta or 0.0)
     for a in range(3):
         p.n[a] = int(n[a]) if a < dim else 0
         p.lo[a] = float(lo[a]) if a < dim else 0.0
@@ -176,8 +177,8 @@ def _problem_struct(n, lo, hi, tens):
 class Solver:
     """One problem set up on the GPU (wraps an ahoc_handle).
 
-    `problem` carries n, lo, hi and nodal alpha, f, gD, gN, lapgD (numpy or torch,
-    memory order z, y, x), e.g. a workloads.Problem.
+    `problem` carries n, lo, hi, nodal alpha, f, gD, gN, lapgD (numpy or torch, memory
+    order z, y, x) and optionally a constant beta, e.g. a workloads.Problem.
     """
 
     def __init__(self, problem, precision=FP64, device="cuda:0", **opts):
@@ -186,7 +187,7 @@ class Solver:
         self.n = tuple(problem.n)
         self.dim = len(self.n)
         tens = [_dev(getattr(problem, k), self.device) for k in ("alpha", "f", "gD", "gN", "lapgD")]
-        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens)
+        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, getattr(problem, "beta", 0.0))
         self.options = default_options(precision, **opts)
         h = _H()
         with torch.cuda.device(self.device):
@@ -296,7 +297,7 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
     for pb in problems:
         tens = [_dev(getattr(pb, k), dev) for k in ("alpha", "f", "gD", "gN", "lapgD")]
         keep.append(tens)
-        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens))
+        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, getattr(pb, "beta", 0.0)))
         outs.append(torch.empty(tuple(m + 1 for m in reversed(pb.n)), dtype=torch.float64, device=dev))
     cnt = len(problems)
     parr = (_Problem * cnt)(*structs)

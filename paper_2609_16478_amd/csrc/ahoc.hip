@@ -67,6 +67,8 @@ using namespace ahoc;
 struct ahoc_handle {
   Geom g;
   Weights w;
+  Weights wv;          // the v-equation's lift weights (normal weight shifted by -c m1)
+  double cshift = 0;   // the v-equation's shift c = beta/alpha (constant alpha), 0 for beta = 0
   ahoc_options opt;
   // FP64 problem data
   double* ia64 = nullptr;
@@ -362,6 +364,14 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
   }
   P.scV = sc;
   P.scV.scale = (T)(-norm);  // V = -L^{-1}(...)
+  if (h->cshift != 0.0) {
+    // V = -(L - c M)^{-1}(...): lambda_L - c mu_M, mu_M = m0 + 2 m1 sum_a (1 + h_a^2 s_a / 2)
+    const double c = h->cshift, m0 = h->w.m0, m1 = h->w.m1;
+    P.scV.a0 = (T)(-c * (m0 + 2.0 * m1 * g.dim));
+    P.scV.ka = (T)(-c * m1 * g.h[0] * g.h[0]);
+    P.scV.kb = g.dim == 3 ? (T)(-c * m1 * g.h[1] * g.h[1]) : (T)0;
+    P.scV.kt = (T)(-c * m1 * g.h[t] * g.h[t]);
+  }
   P.scU = sc;
   P.scU.scale = (T)norm;     // U = +L^{-1}(...)
   P.scP = P.scU;
@@ -404,7 +414,7 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
 // V = -L^{-1}(src + L_bnd[Q])  into P.bufA
 template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
   hipEvent_t e = tbegin(h, st);
-  TRY(lift<T>(h->g, h->w, Q, src, P.bufA, st));
+  TRY(lift<T>(h->g, h->wv, Q, src, P.bufA, st));
   tend(h, AHOC_K_LIFT, e, (double)h->g.nint * h->g.nb * sizeof(T) * (src ? 2 : 1), st);
   return poisson<T>(h, P, P.bufA, P.scV, st);
 }
@@ -442,7 +452,7 @@ template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) 
 template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st) {
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
-  TRY(face_lift<T>(g, h->w, Q, P.Fx, P.Fy, P.Fz, st));
+  TRY(face_lift<T>(g, h->wv, Q, P.Fx, P.Fy, P.Fz, st));
   TRY(face_dst2<T>(h, P, st));
   tend(h, AHOC_K_LIFT, e, (double)TQ(g) * 2.0 * sizeof(T), st);
   const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);
@@ -567,7 +577,7 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
   }
   TRY(alloc_t(h, &h->pc, g.nq));
   TRY(alloc_t(h, &h->qc, g.nq));
-  TRY(precond_symbol(g, h->w, tabs.data(), h->pc, h->qc, st));
+  TRY(precond_symbol(g, h->wv, h->cshift, tabs.data(), h->pc, h->qc, st));
   if (h->p64.ready) {
     for (int a = 0; a < g.dim; ++a) h->ptb[a] = h->p64.tb[a];
     h->ptb_own = false;
@@ -969,6 +979,7 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   make_geom(pb, g);
   g.nb = count;
   make_weights(g, h->w);
+  h->wv = h->w;
   h->m = h->opt.restart;
   const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD;
   if (count > 1) {
@@ -1011,6 +1022,23 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
     if (!(mn > 0.0)) {
       set_last_error("alpha must be positive everywhere", "ahoc_setup");
       return ST_INVALID;
+    }
+    if (pb->beta != 0.0) {
+      // the v-equation -L_h V + (beta/alpha) M V = M f is solved by the sine transforms only
+      // for a constant shift beta/alpha
+      int rc = 0;
+      const double mx = absmax(h, alpha, true, TN(g), st, &rc);
+      TRY(rc);
+      if (count != 1 || mx - mn > 1e-14 * mx) {
+        set_last_error("beta != 0 needs a constant alpha (and a single problem per handle)", "ahoc_setup");
+        return ST_UNSUPPORTED;
+      }
+      if (h->opt.precision == AHOC_MIXED && h->opt.refine != 1) {
+        set_last_error("beta != 0 in MIXED precision needs refine = 1", "ahoc_setup");
+        return ST_UNSUPPORTED;
+      }
+      h->cshift = pb->beta / mx;
+      for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
     }
   }
   TRY(setup_face_alpha(g, alpha, h->af64, af32, st));
@@ -1580,7 +1608,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
   std::vector<std::vector<int>> jobs;
   for (int i = 0; i < count; ++i) {
     const ahoc_problem& p = probs[i];
-    if (p.dim != 2 || !u[i]) {
+    if (p.dim != 2 || !u[i] || p.beta != 0.0) {  // a problem with beta runs alone
       jobs.push_back({i});
       continue;
     }

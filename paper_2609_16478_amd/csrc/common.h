@@ -99,6 +99,10 @@ template <typename T> struct DstScale {
   int nva = 1;                // valid ia < nva (columns ia >= nva are row padding)
   T c_ta = 0, c_tb = 0, c_ab = 0;
   T scale = 0;                // sign * prod_a 2/N_a
+  // the v-equation's shift by the constant c = beta/alpha (zero otherwise): lambda_L - c mu_M
+  // with mu_M = m0 + 2 m1 sum_a cos(theta_a) and cos(theta_a) = 1 + h_a^2 s_a / 2 adds
+  // a0 + ka s_a + kb s_b to A and kt to B (lambda = A + B s_this)
+  T a0 = 0, ka = 0, kb = 0, kt = 0;
 };
 
 // Optional face sums of a fused pass (one-sided normal combination along the pass axis):

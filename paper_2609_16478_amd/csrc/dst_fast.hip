@@ -89,6 +89,8 @@ __global__ void __launch_bounds__((cap<T, N, FUSED, ROWP>())) k_dst_fast(Args<T>
       const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
       Ao = sa + sb + a.fs.c_ab * sa * sb;
       Bo = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+      Ao += a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb;  // v-equation shift (zero otherwise)
+      Bo += a.fs.kt;
     };
     coef(ca, A.x, B.x);
     coef(cb, A.y, B.y);

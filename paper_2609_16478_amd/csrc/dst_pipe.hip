@@ -217,6 +217,8 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
         Ao = sa + sb + a.fs.c_ab * sa * sb;
         Bo = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+        Ao += a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb;  // v-equation shift (zero otherwise)
+        Bo += a.fs.kt;
       };
       coef(ca, A.x, B.x);
       coef(cb, A.y, B.y);
@@ -357,13 +359,13 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     T Aa = 1, Ba = 0, Ab = 1, Bb = 0;
     if (va) {
       const T sa = a.fs.s_a[iaa];
-      Aa = sa + sb + a.fs.c_ab * sa * sb;
-      Ba = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+      Aa = sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb);
+      Ba = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt;
     }
     if (vb) {
       const T sa = a.fs.s_a[iab];
-      Ab = sa + sb + a.fs.c_ab * sa * sb;
-      Bb = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
+      Ab = sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb);
+      Bb = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt;
     }
     const T* lp = g.lp + o * g.pslab;
     const T* la = g.la + o * g.aslab + ib * g.arow;  // x-face rows of this tile

@@ -54,8 +54,8 @@ __device__ __forceinline__ bool col_coef(const DstScale<T>& fs, long long inner,
   }
   const T sa = fs.s_a[ia];
   const T sb = fs.s_b ? fs.s_b[ib] : T(0);
-  A = sa + sb + fs.c_ab * sa * sb;
-  B = T(1) + fs.c_ta * sa + fs.c_tb * sb;
+  A = sa + sb + fs.c_ab * sa * sb + (fs.a0 + fs.ka * sa + fs.kb * sb);  // + v-equation shift
+  B = T(1) + fs.c_ta * sa + fs.c_tb * sb + fs.kt;
   return true;
 }
 

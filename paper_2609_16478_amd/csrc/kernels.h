@@ -22,7 +22,7 @@ int partial_sum(long long n, int count, long long stride, const T* in, T* out, h
 // boundary-symbol preconditioner (precond.hip): inverse 2x2 block coefficients per face
 // mode from per-axis FP64 tables {s, cos, sin, w_lo} x 3 axes, and their application to
 // face spectra of a Q-layout vector
-int precond_symbol(const Geom& g, const Weights& w, const double* const* tabs, double* pc, double* qc,
+int precond_symbol(const Geom& g, const Weights& w, double c, const double* const* tabs, double* pc, double* qc,
                    hipStream_t st);
 template <typename T>
 int precond_modes(const Geom& g, const T* pc, const T* qc, T* x, hipStream_t st);

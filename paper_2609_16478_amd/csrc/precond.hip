@@ -13,6 +13,9 @@
 //              layer (the lift), and m1 sin(pi k_a/N_a) the face value seen by M,
 //   w(k_a)     the one-sided combination 6 u_1 - 3/2 u_2 + 2/9 u_3 of mode k_a at the low
 //              face (w_lo) or the high face (w_hi = (-1)^(k_a+1) w_lo).
+// With beta != 0 (constant alpha) the V-solve divides by lambda - c mu (c = beta/alpha) and
+// its lift's normal weight is lowered by c m1, so the term reads (m1 - mu T'/(lambda - c mu)) /
+// lambda with T' the shifted lift symbol.
 // Low-low gives sigma = F_lo - 1 (the -Q of the residual), low-high gives tau = F_hi;
 // by symmetry the 2x2 block per mode is [[sigma, tau], [tau, sigma]].  Applying the
 // preconditioner is a 2-D DST of every face array, one 2x2 solve per mode and pair,
@@ -43,7 +46,8 @@ struct AxisTab {
 
 struct SymArgs {
   Geom g;
-  Weights w;
+  Weights w;   // the lift stencil of the v-equation (with the shift in its normal weight)
+  double c;    // the v-equation's shift beta/alpha (0 for beta = 0)
   AxisTab t[3];
   double* pc;  // per Q entry: diagonal coefficient of the inverse 2x2 block
   double* qc;  // per Q entry: off-diagonal coefficient
@@ -93,7 +97,8 @@ __global__ void k_symbol(SymArgs A) {
       const double sa = A.t[a].s[k];
       const double lam = sa + sb + sc + cab * sa * sb + cac * sa * sc + cbc * sb * sc;
       const double mu = mt + 2.0 * A.w.m1 * A.t[a].c[k];
-      const double term = A.t[a].sn[k] * (A.w.m1 - mu * T / lam) / lam;
+      // V-solve with the shifted eigenvalue lambda - c mu, U-solve with lambda
+      const double term = A.t[a].sn[k] * (A.w.m1 - mu * T / (lam - A.c * mu)) / lam;
       const double wl = A.t[a].wl[k];
       sig += wl * term;
       tau += ((k & 1) ? -wl : wl) * term;  // w_hi(k) = (-1)^(k+1) w_lo(k), k = index + 1
@@ -137,11 +142,12 @@ __global__ void k_modes(Geom g, const T* __restrict__ pc, const T* __restrict__ 
 
 }  // namespace
 
-int precond_symbol(const Geom& g, const Weights& w, const double* const* tabs, double* pc, double* qc,
+int precond_symbol(const Geom& g, const Weights& w, double c, const double* const* tabs, double* pc, double* qc,
                    hipStream_t st) {
   SymArgs A;
   A.g = g;
   A.w = w;
+  A.c = c;
   for (int a = 0; a < 3; ++a) {
     A.t[a].s = tabs[4 * a];
     A.t[a].c = tabs[4 * a + 1];
