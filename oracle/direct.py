@@ -13,9 +13,10 @@ clamped box and a constant beta:
   with V = Q on face-interior nodes and, on edges and corners, V = alpha * (Delta u
   from the Dirichlet data) (Remark 1).  M reaches face-interior nodes only, so
   the beta term couples to interior V and to Q.
-* q-rows (Lemma 1, boundary residual R): at every face-interior node,
-  alpha_b [ (delta_nn U)_b + (tangential part of Delta u)_b ] - Q_b = 0 with the
-  one-sided formula of Sec. 2.2, written for the face's outward normal.
+* q-rows (Lemma 1, boundary residual R): at every face-interior node of a clamped
+  face, alpha_b [ (delta_nn U)_b + (tangential part of Delta u)_b ] - Q_b = 0 with the
+  one-sided formula of Sec. 2.2, written for the face's outward normal; on a Navier
+  face (Delta u = g_L given, eq-bc) V = alpha g_L there, i.e. alpha_b g_L,b - Q_b = 0.
 
 The sign of the Q block follows Lemma 1 (R = alpha[...] - Q, so A22 = -I);
 eq-coupled draws that block as +I.  Either sign gives the same solution.
@@ -131,10 +132,17 @@ def assemble(problem) -> Assembled:
                     add(rv, 2 * n + g.q_of[q], c)
                 else:
                     raise AssertionError("M never reaches an edge or corner node")
-    # q-rows: alpha_b [ delta_nn U + 11 g_N / (3h) + lapgD ] - Q = 0
+    # q-rows: alpha_b [ delta_nn U + 11 g_N / (3h) + lapgD ] - Q = 0 (clamped face),
+    # alpha_b g_L - Q = 0 (Navier face)
+    navier = tuple(getattr(problem, "navier", ()) or ())
+    gL = _field(getattr(problem, "gL", None), g)
     for pq, b in enumerate(g.q_nodes):
         r = 2 * n + pq
         a, s = g.face_of(b)
+        if navier and navier[2 * a + s]:
+            add(r, r, -1.0)
+            F[r] = -g.at(alpha, b) * g.at(gL, b)
+            continue
         step = 1 if s == 0 else -1
         ha = g.h[a]
         ab = g.at(alpha, b)

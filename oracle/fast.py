@@ -81,6 +81,8 @@ class FastTier:
         self.gD = _f(problem.gD, g.nodal_shape)
         self.gN = _f(problem.gN, g.nodal_shape)
         self.lapgD = _f(problem.lapgD, g.nodal_shape)
+        self.navier = tuple(getattr(problem, "navier", ()) or ())
+        self.gL = _f(getattr(problem, "gL", None), g.nodal_shape)
         self.L = laplacian(g.h)
         self.M = weighting(g.dim)
         self.lam = self._eigen()
@@ -138,11 +140,15 @@ class FastTier:
         return U
 
     def residual(self, U, Q):
-        """R(Q) of Lemma 1 on every face-interior node, in Q order."""
+        """R(Q) of Lemma 1 on every face-interior node, in Q order (alpha g_L - Q on a Navier
+        face, where V is given)."""
         g = self.g
         R = np.empty(g.n_q)
         for p, b in enumerate(g.q_nodes):
             a, s = g.face_of(b)
+            if self.navier and self.navier[2 * a + s]:
+                R[p] = g.at(self.alpha, b) * g.at(self.gL, b) - Q[p]
+                continue
             step = 1 if s == 0 else -1
             vals = []
             for kk in range(4):

@@ -28,7 +28,7 @@ import numpy as np
 
 __all__ = [
     "Problem", "manufactured", "config1", "config2", "config3", "config4_specs",
-    "config4_instance", "cavity", "plate", "poly_exact", "node_coords",
+    "config4_instance", "cavity", "plate", "poly_exact", "node_coords", "example1",
 ]
 
 
@@ -36,7 +36,9 @@ __all__ = [
 class Problem:
     """One clamped problem on a box: grid, coefficients and data (nodal arrays).
 
-    The equation is -Delta(alpha Delta u) + beta Delta u = f with beta a constant.
+    The equation is -Delta(alpha Delta u) + beta Delta u = f with beta a constant.  Every face
+    carries u = g_D; a clamped face also u_n = g_N, a Navier face (navier[f]) Delta u = g_L
+    instead (the boundary conditions eq-bc, with the Navier part of the boundary).
 
     n: intervals per axis, axis order (x, y[, z]).  lo/hi: box corners.
     Arrays are numpy (host) or torch tensors; None means identically zero.
@@ -56,6 +58,8 @@ class Problem:
     name: str = ""
     meta: dict = field(default_factory=dict)
     beta: float = 0.0
+    navier: tuple = ()   # per face (x-, x+, y-, y+[, z-, z+]): True = Navier (Delta u = g_L), else clamped
+    gL: Any = None       # nodal Delta u, read on the face-interior nodes of Navier faces
 
     @property
     def dim(self) -> int:
@@ -87,7 +91,7 @@ def _derive(alpha_src: str, u_src: str, dim: int, params: tuple = ()):
     X = _symbols(dim)
     ns = {s.name: s for s in X}
     ns.update({p: sp.Symbol(p) for p in params})
-    ns.update({"pi": sp.pi, "sin": sp.sin, "cos": sp.cos, "exp": sp.exp})
+    ns.update({"pi": sp.pi, "sin": sp.sin, "cos": sp.cos, "exp": sp.exp, "sqrt": sp.sqrt})
     alpha = sp.sympify(alpha_src, locals=ns)
     u = sp.sympify(u_src, locals=ns)
     lap = lambda w: sum(sp.diff(w, s, 2) for s in X)
@@ -166,8 +170,9 @@ def _zeros(ev, shape):
     return np.zeros(shape)
 
 
-def _boundary_data(ev: _Eval, n, c1d):
-    """Nodal g_D, g_N, lapgD built from boundary evaluations only (O(N^{d-1}) work).
+def _boundary_data(ev: _Eval, n, c1d, want_gl=False):
+    """Nodal g_D, g_N, lapgD (and with want_gl the full Delta u on every boundary node, the
+    Navier data g_L) built from boundary evaluations only (O(N^{d-1}) work).
 
     Returns None for fields that vanish identically on the boundary."""
     dim = len(n)
@@ -175,6 +180,7 @@ def _boundary_data(ev: _Eval, n, c1d):
     gD = _zeros(ev, shape)
     gN = _zeros(ev, shape)
     lap = _zeros(ev, shape)
+    gl = _zeros(ev, shape) if want_gl else None
     mod = ev.xp == "torch"
 
     def sl(axis, idx):
@@ -208,23 +214,28 @@ def _boundary_data(ev: _Eval, n, c1d):
             lsub[...] = lapu
             lsub[inner] = tang[inner]
             lap[tgt] = lsub
+            if want_gl:
+                gl[tgt] = lapu
     # Fields whose boundary values are pure rounding noise (e.g. sin(pi*1.0) ~ 1e-16
     # instead of 0) are reported as identically zero.
     out = []
     for arr in (gD, gN, lap):
         mx = float(arr.abs().max()) if mod else float(np.abs(arr).max())
         out.append(None if mx < 1e-12 else arr)
+    if want_gl:
+        out.append(gl)
     return out
 
 
 def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None, *,
                  params=(), pvals=(), xp="numpy", device=None, with_exact=True,
-                 chunk=None, name="", beta=0.0):
+                 chunk=None, name="", beta=0.0, navier=()):
     """Sample a manufactured clamped problem.
 
     alpha_src/u_src: expressions in x, y[, z] (and `params`).  f follows the
     paper's sign convention of eq. (1), f = -Delta(alpha Delta u) + beta Delta u with the
-    constant beta.  xp = "numpy" gives host
+    constant beta.  navier: per face, True for a Navier face (g_L = Delta u sampled).
+    xp = "numpy" gives host
     arrays; xp = "torch" builds the nodal fields on `device` (in z-chunks of
     `chunk` planes for large 3-D grids).
     """
@@ -250,11 +261,17 @@ def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None,
             out[k] = ev(k, cs)
     if beta:
         out["f"] = out["f"] + float(beta) * out.pop("lapu")
-    gD, gN, lap = _boundary_data(ev, n, c1d)
+    nav = tuple(bool(v) for v in navier) if any(navier) else ()
+    if nav and len(nav) != 2 * dim:
+        raise ValueError("navier needs one flag per face")
+    bd = _boundary_data(ev, n, c1d, want_gl=bool(nav))
+    gD, gN, lap = bd[:3]
+    gL = bd[3] if nav else None
     return Problem(tuple(n), lo, hi, out["alpha"], out["f"], gD, gN, lap,
                    out.get("u"), out.get("v"), name=name,
-                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals)), "beta": float(beta)},
-                   beta=float(beta))
+                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals)), "beta": float(beta),
+                         "navier": nav},
+                   beta=float(beta), navier=nav, gL=gL)
 
 
 # --------------------------------------------------------------------------------------
@@ -307,6 +324,17 @@ def config4_instance(spec, **kw):
     return manufactured(C4_ALPHA, C4_U, (spec["n"], spec["n"]), params=("c", "p", "q", "k"),
                         pvals=(spec["c"], spec["p"], spec["q"], spec["k"]),
                         name=f"c4_n{spec['n']}", **kw)
+
+
+EX1_U = "256*(x**2 + eps*(1 - exp(-x/sqrt(eps)))**2)*(x - 1)**2*y**2*(y - 1)**2"
+
+
+def example1(n=256, eps=1e-4, **kw):
+    """The 2-D singularly perturbed test of the paper's first convergence experiment:
+    -eps Delta^2 u + Delta u = f (alpha = eps, beta = 1) on the unit square, clamped at
+    x = 0 and Navier on the other faces, with the manufactured boundary-layer solution EX1_U."""
+    return manufactured(repr(float(eps)), EX1_U.replace("eps", repr(float(eps))), (n, n), beta=1.0,
+                        navier=(False, True, True, True), name=f"ex1_n{n}_eps{eps:g}", **kw)
 
 
 def cavity(n=64):
