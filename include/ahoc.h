@@ -2,9 +2,11 @@
  * ahoc.h -- C ABI of the MI355X (gfx950) augmented high-order-compact solver
  * for clamped, variable-coefficient biharmonic problems.
  *
- * Problem (Section 2, eq. (1) with the clamped conditions eq-bc, beta = 0):
- *     -Delta( alpha Delta u ) = f    in the box  [lo_0,hi_0] x ... (dim = 2 or 3)
- *     u = g_D,  du/dn = g_N          on every face (fully clamped)
+ * Problem (Section 2, eq. (1) with the boundary conditions eq-bc):
+ *     -Delta( alpha Delta u ) + beta Delta u = f   in the box [lo_0,hi_0] x ... (dim 2 or 3)
+ *     u = g_D,  du/dn = g_N          on clamped faces (all faces by default)
+ *     u = g_D,  Delta u = g_L        on Navier faces (ahoc_problem.navier)
+ * with beta a constant (0 by default)
  * discretised by the fourth-order compact scheme of Sec. 2.2 (19-point L_h and
  * 7-point M in 3-D, 9-point L_h and 5-point M in 2-D) on a uniform grid with
  * n[a] intervals per axis.  The unknown boundary values Q of v = alpha Delta u
@@ -53,8 +55,8 @@ typedef enum {
                      residual, Krylov vectors, Arnoldi, Givens, updates in FP64   */
 } ahoc_precision;
 
-/* One clamped problem of eq. (1), -Delta(alpha Delta u) + beta Delta u = f.  alpha and f
- * are required; gD, gN, lapgD may be NULL (= 0).
+/* One problem of eq. (1), -Delta(alpha Delta u) + beta Delta u = f, clamped on every face
+ * unless `navier` marks it.  alpha and f are required; gD, gN, lapgD, gL may be NULL (= 0).
  *   alpha  nodal coefficient, must satisfy alpha > 0 everywhere (checked)
  *   f      nodal right-hand side in the sign of eq. (1)
  *   beta   a constant; 0 for the biharmonic-type problem.  beta != 0 needs a constant
@@ -65,7 +67,15 @@ typedef enum {
  *   gN     nodal; on face-interior nodes the OUTWARD normal derivative of u
  *   lapgD  nodal; on face-interior nodes the tangential part of Delta u fixed by
  *          g_D (Sec. 2.2 boundary Laplacian decomposition); on edges and corners
- *          the full Delta u (Remark 1) */
+ *          the full Delta u (Remark 1)
+ *   navier bit f (f = 2*axis + side, side 0 = low face; axes x, y[, z]) set: face f is a
+ *          Navier face, u = g_D and Delta u = g_L there instead of du/dn = g_N (the
+ *          boundary conditions eq-bc on the Navier part of the boundary).  Then v = alpha
+ *          g_L is known on that face, and its rows of the Schur system read
+ *          alpha g_L - Q = 0.  Bits beyond the 2*dim faces: AHOC_E_INVALID.  A problem
+ *          with Navier faces is set up alone (ahoc_solve_batched runs it by itself)
+ *   gL     nodal; on face-interior nodes of Navier faces the given Delta u (read there
+ *          only) */
 typedef struct {
   int dim;       /* 2 or 3 */
   int n[3];      /* intervals per axis, n[a] >= 8 (unused axis ignored) */
@@ -77,6 +87,8 @@ typedef struct {
   const double* gN;
   const double* lapgD;
   double beta;
+  int navier;
+  const double* gL;
 } ahoc_problem;
 
 typedef struct {

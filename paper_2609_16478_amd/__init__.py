@@ -32,7 +32,7 @@ c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_vo
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int * 3), ("lo", c_double * 3), ("hi", c_double * 3),
                 ("alpha", c_void_p), ("f", c_void_p), ("gD", c_void_p), ("gN", c_void_p),
-                ("lapgD", c_void_p), ("beta", c_double)]
+                ("lapgD", c_void_p), ("beta", c_double), ("navier", c_int), ("gL", c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -161,16 +161,27 @@ def _stats(s: _Stats) -> Stats:
                  s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm)
 
 
-def _problem_struct(n, lo, hi, tens, beta=0.0):
+_FIELDS = ("alpha", "f", "gD", "gN", "lapgD", "gL")
+
+
+def _navier_mask(navier) -> int:
+    """Per-face flags (x-, x+, y-, y+[, z-, z+]) or an int bitmask -> bitmask."""
+    if isinstance(navier, int):
+        return navier
+    return sum(1 << f for f, v in enumerate(navier or ()) if v)
+
+
+def _problem_struct(n, lo, hi, tens, beta=0.0, navier=()):
     dim = len(n)
     p = _Problem()
     p.dim = dim
     p.beta = float(beta or 0.0)
+    p.navier = _navier_mask(navier)
     for a in range(3):
         p.n[a] = int(n[a]) if a < dim else 0
         p.lo[a] = float(lo[a]) if a < dim else 0.0
         p.hi[a] = float(hi[a]) if a < dim else 0.0
-    p.alpha, p.f, p.gD, p.gN, p.lapgD = [(t.data_ptr() if t is not None else None) for t in tens]
+    p.alpha, p.f, p.gD, p.gN, p.lapgD, p.gL = [(t.data_ptr() if t is not None else None) for t in tens]
     return p
 
 
@@ -178,7 +189,8 @@ class Solver:
     """One problem set up on the GPU (wraps an ahoc_handle).
 
     `problem` carries n, lo, hi, nodal alpha, f, gD, gN, lapgD (numpy or torch, memory
-    order z, y, x) and optionally a constant beta, e.g. a workloads.Problem.
+    order z, y, x) and optionally a constant beta and Navier faces (navier: per-face flags
+    or a bitmask, gL: nodal Delta u read on them), e.g. a workloads.Problem.
     """
 
     def __init__(self, problem, precision=FP64, device="cuda:0", **opts):
@@ -186,8 +198,9 @@ class Solver:
         self.device = torch.device(device)
         self.n = tuple(problem.n)
         self.dim = len(self.n)
-        tens = [_dev(getattr(problem, k), self.device) for k in ("alpha", "f", "gD", "gN", "lapgD")]
-        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, getattr(problem, "beta", 0.0))
+        tens = [_dev(getattr(problem, k, None), self.device) for k in _FIELDS]
+        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, getattr(problem, "beta", 0.0),
+                                  getattr(problem, "navier", ()))
         self.options = default_options(precision, **opts)
         h = _H()
         with torch.cuda.device(self.device):
@@ -295,9 +308,10 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
     dev = torch.device(device)
     keep, structs, outs = [], [], []
     for pb in problems:
-        tens = [_dev(getattr(pb, k), dev) for k in ("alpha", "f", "gD", "gN", "lapgD")]
+        tens = [_dev(getattr(pb, k, None), dev) for k in _FIELDS]
         keep.append(tens)
-        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, getattr(pb, "beta", 0.0)))
+        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, getattr(pb, "beta", 0.0),
+                                       getattr(pb, "navier", ())))
         outs.append(torch.empty(tuple(m + 1 for m in reversed(pb.n)), dtype=torch.float64, device=dev))
     cnt = len(problems)
     parr = (_Problem * cnt)(*structs)

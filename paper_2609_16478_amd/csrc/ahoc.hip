@@ -69,6 +69,7 @@ struct ahoc_handle {
   Weights w;
   Weights wv;          // the v-equation's lift weights (normal weight shifted by -c m1)
   double cshift = 0;   // the v-equation's shift c = beta/alpha (constant alpha), 0 for beta = 0
+  int navier = 0;      // bit f set: face f (2 axis + side) is a Navier face
   ahoc_options opt;
   // FP64 problem data
   double* ia64 = nullptr;
@@ -577,7 +578,7 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
   }
   TRY(alloc_t(h, &h->pc, g.nq));
   TRY(alloc_t(h, &h->qc, g.nq));
-  TRY(precond_symbol(g, h->wv, h->cshift, tabs.data(), h->pc, h->qc, st));
+  TRY(precond_symbol(g, h->wv, h->cshift, h->navier, tabs.data(), h->pc, h->qc, st));
   if (h->p64.ready) {
     for (int a = 0; a < g.dim; ++a) h->ptb[a] = h->p64.tb[a];
     h->ptb_own = false;
@@ -982,6 +983,12 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   h->wv = h->w;
   h->m = h->opt.restart;
   const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD;
+  for (int i = 0; i < count; ++i)
+    if (pbs[i].navier && count > 1) {
+      set_last_error("a problem with Navier faces is set up alone", "ahoc_setup");
+      return ST_UNSUPPORTED;
+    }
+  h->navier = pb->navier;
   if (count > 1) {
     double *a_, *f_, *gd_, *gn_, *lg_;
     h->ptab_host.assign((size_t)6 * count, nullptr);
@@ -1043,6 +1050,7 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   }
   TRY(setup_face_alpha(g, alpha, h->af64, af32, st));
   TRY(setup_sources(g, h->w, f, alpha, gD, gN, lapgD, h->src_v, h->src_u, h->src_q, st));
+  if (h->navier) TRY(setup_navier(g, h->navier, alpha, pb->gL, h->af64, af32, h->src_q, st));
   if (lapgD) {
     // V = alpha * Delta u on edges and corners (Remark 1); read there only
     TRY(alloc_t(h, &h->vedge, TN(g)));
@@ -1198,6 +1206,10 @@ static ahoc_status validate_problem(const ahoc_problem* pb) {
   }
   if (!pb->alpha || !pb->f) {
     ahoc::set_last_error("alpha and f are required", "ahoc_setup");
+    return AHOC_E_INVALID;
+  }
+  if (pb->navier & ~((1 << (2 * pb->dim)) - 1)) {
+    ahoc::set_last_error("navier has a bit beyond the 2*dim faces", "ahoc_setup");
     return AHOC_E_INVALID;
   }
   for (int a = 0; a < pb->dim; ++a) {
@@ -1608,7 +1620,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
   std::vector<std::vector<int>> jobs;
   for (int i = 0; i < count; ++i) {
     const ahoc_problem& p = probs[i];
-    if (p.dim != 2 || !u[i] || p.beta != 0.0) {  // a problem with beta runs alone
+    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.navier) {  // beta or Navier faces: alone
       jobs.push_back({i});
       continue;
     }

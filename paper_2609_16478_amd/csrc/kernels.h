@@ -22,8 +22,8 @@ int partial_sum(long long n, int count, long long stride, const T* in, T* out, h
 // boundary-symbol preconditioner (precond.hip): inverse 2x2 block coefficients per face
 // mode from per-axis FP64 tables {s, cos, sin, w_lo} x 3 axes, and their application to
 // face spectra of a Q-layout vector
-int precond_symbol(const Geom& g, const Weights& w, double c, const double* const* tabs, double* pc, double* qc,
-                   hipStream_t st);
+int precond_symbol(const Geom& g, const Weights& w, double c, int navier, const double* const* tabs, double* pc,
+                   double* qc, hipStream_t st);
 template <typename T>
 int precond_modes(const Geom& g, const T* pc, const T* qc, T* x, hipStream_t st);
 // boundary residual from face sums formed in spectral space
@@ -37,6 +37,9 @@ int resid64(const Geom& g, const Weights& w, const double* U, const double* V, c
 int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32, double* bmin,
                     int nb, hipStream_t st);
 int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st);
+// Navier faces of a single problem: af = 0 and src_q = -alpha g_L on their q-rows
+int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL, double* af64, float* af32,
+                 double* src_q, hipStream_t st);
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
                   const double* gD, const double* gN, const double* lapgD, double* src_v,
                   double* src_u, double* src_q, hipStream_t st);

@@ -17,7 +17,9 @@
 // its lift's normal weight is lowered by c m1, so the term reads (m1 - mu T'/(lambda - c mu)) /
 // lambda with T' the shifted lift symbol.
 // Low-low gives sigma = F_lo - 1 (the -Q of the residual), low-high gives tau = F_hi;
-// by symmetry the 2x2 block per mode is [[sigma, tau], [tau, sigma]].  Applying the
+// by symmetry the 2x2 block per mode is [[sigma, tau], [tau, sigma]].  A Navier face's rows
+// are alpha g_L - Q, so its row of the block is (0, -1) (the opposite face's row keeps
+// sigma, tau): the block becomes triangular, or -I with both faces Navier.  Applying the
 // preconditioner is a 2-D DST of every face array, one 2x2 solve per mode and pair,
 // and the inverse 2-D DST: O(N^(d-1) log N), negligible next to a matvec.
 #include "common.h"
@@ -48,9 +50,13 @@ struct SymArgs {
   Geom g;
   Weights w;   // the lift stencil of the v-equation (with the shift in its normal weight)
   double c;    // the v-equation's shift beta/alpha (0 for beta = 0)
+  int navier;  // bit f set: face f (2 axis + side) is a Navier face
   AxisTab t[3];
-  double* pc;  // per Q entry: diagonal coefficient of the inverse 2x2 block
-  double* qc;  // per Q entry: off-diagonal coefficient
+  // the inverse 2x2 block [[a, b], [c, d]] of a mode (rows and columns: low face, high
+  // face) is stored at the mode's low entry lo and high entry hi as
+  // pc[lo] = a, qc[lo] = b, qc[hi] = c, pc[hi] = d
+  double* pc;
+  double* qc;
 };
 
 __device__ __forceinline__ int pair_ce(int a, int b) {
@@ -108,18 +114,37 @@ __global__ void k_symbol(SymArgs A) {
     tau = f * tau;
     double norm = 2.0 / g.n[b];
     if (DIM == 3) norm *= 2.0 / g.n[c];
-    const double det = sig * sig - tau * tau;
     const long long lo = g.face_off[2 * a] + t, hi = g.face_off[2 * a + 1] + t;
-    const double p = norm * sig / det, q = -norm * tau / det;
-    A.pc[lo] = p;
-    A.pc[hi] = p;
-    A.qc[lo] = q;
-    A.qc[hi] = q;
+    const bool nl = (A.navier >> (2 * a)) & 1, nh = (A.navier >> (2 * a + 1)) & 1;
+    double ia, ib, ic, id;  // inverse of the block
+    if (!nl && !nh) {  // [[sig, tau], [tau, sig]]
+      const double det = sig * sig - tau * tau;
+      ia = id = sig / det;
+      ib = ic = -tau / det;
+    } else if (nl && nh) {  // -I
+      ia = id = -1.0;
+      ib = ic = 0.0;
+    } else if (nh) {  // [[sig, tau], [0, -1]]
+      ia = 1.0 / sig;
+      ib = tau / sig;
+      ic = 0.0;
+      id = -1.0;
+    } else {  // [[-1, 0], [tau, sig]]
+      ia = -1.0;
+      ib = 0.0;
+      ic = tau / sig;
+      id = 1.0 / sig;
+    }
+    A.pc[lo] = norm * ia;
+    A.qc[lo] = norm * ib;
+    A.qc[hi] = norm * ic;
+    A.pc[hi] = norm * id;
   }
 }
 
-// In place on face spectra: (lo, hi) <- (p lo + q hi, q lo + p hi) for every low-face entry
-// of every instance (the coefficients are shared by the instances of a batch).
+// In place on face spectra: (lo, hi) <- (pc[lo] lo + qc[lo] hi, qc[hi] lo + pc[hi] hi) for
+// every low-face entry of every instance (the coefficients are shared by the instances of a
+// batch).
 template <typename T, int DIM>
 __global__ void k_modes(Geom g, const T* __restrict__ pc, const T* __restrict__ qc, T* __restrict__ x) {
   x += (long long)blockIdx.y * g.nq;  // instance of a batch (gridDim.y = g.nb)
@@ -134,20 +159,21 @@ __global__ void k_modes(Geom g, const T* __restrict__ pc, const T* __restrict__ 
       ++a;
     }
     const long long lo = g.face_off[2 * a] + t, hi = g.face_off[2 * a + 1] + t;
-    const T xl = x[lo], xh = x[hi], p = pc[lo], q = qc[lo];
-    x[lo] = p * xl + q * xh;
-    x[hi] = q * xl + p * xh;
+    const T xl = x[lo], xh = x[hi];
+    x[lo] = pc[lo] * xl + qc[lo] * xh;
+    x[hi] = qc[hi] * xl + pc[hi] * xh;
   }
 }
 
 }  // namespace
 
-int precond_symbol(const Geom& g, const Weights& w, double c, const double* const* tabs, double* pc, double* qc,
-                   hipStream_t st) {
+int precond_symbol(const Geom& g, const Weights& w, double c, int navier, const double* const* tabs, double* pc,
+                   double* qc, hipStream_t st) {
   SymArgs A;
   A.g = g;
   A.w = w;
   A.c = c;
+  A.navier = navier;
   for (int a = 0; a < 3; ++a) {
     A.t[a].s = tabs[4 * a];
     A.t[a].c = tabs[4 * a + 1];

@@ -793,6 +793,24 @@ __global__ void k_src_q(Geom g, Weights w, const double* __restrict__ alpha, con
   }
 }
 
+// Navier faces (bit f of `mask`, f = 2 axis + side): Delta u = g_L is given there, so V =
+// alpha g_L is known and the face's q-rows read R = alpha g_L - Q.  The gather's one-sided
+// term is switched off (af = 0) and the known part becomes src_q = -alpha g_L.
+template <int DIM>
+__global__ void k_navier(Geom g, int mask, const double* __restrict__ alpha, const double* __restrict__ gL,
+                         double* __restrict__ af64, float* __restrict__ af32, double* __restrict__ src_q) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    const int f = 2 * ax + (st > 0 ? 0 : 1);  // low face (step +1) -> side 0
+    if (!((mask >> f) & 1)) continue;
+    const long long b = nod(g, i, j, k);
+    af64[q] = 0.0;
+    if (af32) af32[q] = 0.0f;
+    src_q[q] = gL ? -alpha[b] * gL[b] : 0.0;
+  }
+}
+
 // nodal outputs
 template <typename T, int DIM>
 __global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restrict__ gD, double* __restrict__ u) {
@@ -1009,6 +1027,13 @@ int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32,
 
 int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st) {
   LAUNCH_DIM(k_face_alpha, dim3(nblocks(g.nq), g.nb), g, alpha, af64, af32);
+  return ST_OK;
+}
+
+int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL, double* af64, float* af32,
+                 double* src_q, hipStream_t st) {
+  if (g.nb != 1) return ST_UNSUPPORTED;
+  LAUNCH_DIM(k_navier, dim3(nblocks(g.nq)), g, mask, alpha, gL, af64, af32, src_q);
   return ST_OK;
 }
 

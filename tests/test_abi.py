@@ -43,6 +43,10 @@ def test_host_only_entry_points():
     assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID
     p.dim = 2
     assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID  # NULL alpha
+    # Navier flags per face (x-, x+, y-, y+[, z-, z+]) -> bit 2 axis + side
+    assert ah._navier_mask((False, True, True, True)) == 0b1110
+    assert ah._navier_mask((True, False, False, False, False, True)) == 0b100001
+    assert ah._navier_mask(()) == 0 and ah._navier_mask(5) == 5
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libahoc.so not built")
@@ -65,6 +69,9 @@ def test_argument_errors_before_device_work():
                     (problem((16, 16), hi=(1.0, 0.0)), ah.E_INVALID),         # hi <= lo
                     (problem((40, 16)), ah.E_UNSUPPORTED)):                   # no transform plan
         assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == code
+    p = problem((16, 16))
+    p.navier = 1 << 4  # a z face of a 2-D problem
+    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID
     o = ah.default_options()
     o.precision = 7
     p = problem((16, 16))
