@@ -75,7 +75,12 @@ typedef enum {
  *          alpha g_L - Q = 0.  Bits beyond the 2*dim faces: AHOC_E_INVALID.  A problem
  *          with Navier faces is set up alone (ahoc_solve_batched runs it by itself)
  *   gL     nodal; on face-interior nodes of Navier faces the given Delta u (read there
- *          only) */
+ *          only)
+ *   beta_nodal  nodal; when not NULL a variable beta (the constant `beta` is then
+ *          ignored): the v-equation -L_h V + M(beta V / alpha) = M f is no longer diagonal
+ *          in the sine basis and each V-solve runs BiCGSTAB preconditioned by the sine
+ *          transform solve with the constant shift (min + max)/2 of beta/alpha (Remark 2).
+ *          FP64 precision only (AHOC_MIXED: AHOC_E_UNSUPPORTED); set up alone */
 typedef struct {
   int dim;       /* 2 or 3 */
   int n[3];      /* intervals per axis, n[a] >= 8 (unused axis ignored) */
@@ -89,6 +94,7 @@ typedef struct {
   double beta;
   int navier;
   const double* gL;
+  const double* beta_nodal;
 } ahoc_problem;
 
 typedef struct {
@@ -133,6 +139,8 @@ typedef struct {
                             precision (FP32 for AHOC_MIXED) runs that axis's plain
                             DST-I passes (kind 0 contiguous, 1 strided) as the
                             matrix-core pass (see ahoc_dst_choice)       */
+  int vsolve_iters;      /* variable beta: BiCGSTAB iterations over all V-solves
+                            (0 otherwise)                                  */
 } ahoc_stats;
 
 typedef struct ahoc_handle ahoc_handle;

@@ -3,8 +3,8 @@
 Test infrastructure only (see the package docstring).
 
 Unknowns (Section 2.2, block system eq-coupled): U at interior nodes, V at
-interior nodes, Q at face-interior nodes (Remark 1).  Rows, for a fully
-clamped box and a constant beta:
+interior nodes, Q at face-interior nodes (Remark 1).  Rows, for a box with
+clamped or Navier faces and a constant or nodal beta:
 
 * u-rows (Sec. 2.2, L_h U = M(V/alpha)): at every interior node,
   L_h U - M(V/alpha) = 0, with U = g_D on the boundary.  M reaches the
@@ -77,7 +77,12 @@ def assemble(problem) -> Assembled:
     lapgD = _field(problem.lapgD, g)
     if alpha.min() <= 0:
         raise ValueError("alpha must be positive")
-    beta = float(getattr(problem, "beta", 0.0) or 0.0)
+    beta_in = getattr(problem, "beta", 0.0)
+    if beta_in is None or np.isscalar(beta_in):
+        beta_const = float(beta_in or 0.0)
+        beta = None if beta_const == 0.0 else np.full(g.nodal_shape, beta_const)
+    else:  # a variable beta, nodal
+        beta = _field(beta_in, g)
     L = laplacian(g.h)
     M = weighting(g.dim)
     n = g.n_int
@@ -124,8 +129,8 @@ def assemble(problem) -> Assembled:
         for o, w in M.items():
             q = shift(p, o)
             F[rv] += w * g.at(f, q)
-            if beta != 0.0:
-                c = w * beta / g.at(alpha, q)
+            if beta is not None:
+                c = w * g.at(beta, q) / g.at(alpha, q)
                 if g.is_interior(q):
                     add(rv, n + g.interior_index(q), c)
                 elif g.is_face_interior(q):

@@ -73,7 +73,13 @@ class FastTier:
         self.g = g
         self.workers = workers
         self.alpha = _f(problem.alpha, g.nodal_shape)
-        self.beta = float(getattr(problem, "beta", 0.0) or 0.0)
+        beta = getattr(problem, "beta", 0.0)
+        if beta is not None and not np.isscalar(beta):
+            beta = np.asarray(beta, dtype=np.float64)
+            if np.ptp(beta) > 1e-14 * np.abs(beta).max():
+                raise ValueError("a variable beta needs the direct tier")
+            beta = float(beta.flat[0])
+        self.beta = float(beta or 0.0)
         if self.beta != 0.0 and np.ptp(self.alpha) > 1e-14 * np.abs(self.alpha).max():
             raise ValueError("a nonzero beta needs a constant alpha in the fast tier")
         self.c = self.beta / float(self.alpha.flat[0])

@@ -32,7 +32,8 @@ c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_vo
 class _Problem(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int * 3), ("lo", c_double * 3), ("hi", c_double * 3),
                 ("alpha", c_void_p), ("f", c_void_p), ("gD", c_void_p), ("gN", c_void_p),
-                ("lapgD", c_void_p), ("beta", c_double), ("navier", c_int), ("gL", c_void_p)]
+                ("lapgD", c_void_p), ("beta", c_double), ("navier", c_int), ("gL", c_void_p),
+                ("beta_nodal", c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -45,7 +46,7 @@ class _Options(ctypes.Structure):
 class _Stats(ctypes.Structure):
     _fields_ = [("converged", c_int), ("gmres_iters", c_int), ("sweeps", c_int), ("matvecs", c_int),
                 ("schur_relres", c_double), ("last_update", c_double), ("t_solve_ms", c_double),
-                ("graph_steps", c_int), ("dst_gemm", c_int)]
+                ("graph_steps", c_int), ("dst_gemm", c_int), ("vsolve_iters", c_int)]
 
 
 _H = c_void_p
@@ -154,11 +155,12 @@ class Stats:
     t_solve_ms: float
     graph_steps: int = 0
     dst_gemm: int = 0
+    vsolve_iters: int = 0
 
 
 def _stats(s: _Stats) -> Stats:
     return Stats(bool(s.converged), s.gmres_iters, s.sweeps, s.matvecs, s.schur_relres,
-                 s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm)
+                 s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm, s.vsolve_iters)
 
 
 _FIELDS = ("alpha", "f", "gD", "gN", "lapgD", "gL")
@@ -171,6 +173,16 @@ def _navier_mask(navier) -> int:
     return sum(1 << f for f, v in enumerate(navier or ()) if v)
 
 
+def _problem_tensors(problem, device):
+    """Device tensors of the nodal fields (_FIELDS, then a variable beta or None) and the
+    constant beta (0 when beta is nodal)."""
+    beta = getattr(problem, "beta", 0.0)
+    scalar = beta is None or np.isscalar(beta) or (hasattr(beta, "ndim") and beta.ndim == 0)
+    tens = [_dev(getattr(problem, k, None), device) for k in _FIELDS]
+    tens.append(None if scalar else _dev(beta, device))
+    return tens, (float(beta or 0.0) if scalar else 0.0)
+
+
 def _problem_struct(n, lo, hi, tens, beta=0.0, navier=()):
     dim = len(n)
     p = _Problem()
@@ -181,7 +193,8 @@ def _problem_struct(n, lo, hi, tens, beta=0.0, navier=()):
         p.n[a] = int(n[a]) if a < dim else 0
         p.lo[a] = float(lo[a]) if a < dim else 0.0
         p.hi[a] = float(hi[a]) if a < dim else 0.0
-    p.alpha, p.f, p.gD, p.gN, p.lapgD, p.gL = [(t.data_ptr() if t is not None else None) for t in tens]
+    p.alpha, p.f, p.gD, p.gN, p.lapgD, p.gL, p.beta_nodal = [(t.data_ptr() if t is not None else None)
+                                                             for t in tens]
     return p
 
 
@@ -189,8 +202,9 @@ class Solver:
     """One problem set up on the GPU (wraps an ahoc_handle).
 
     `problem` carries n, lo, hi, nodal alpha, f, gD, gN, lapgD (numpy or torch, memory
-    order z, y, x) and optionally a constant beta and Navier faces (navier: per-face flags
-    or a bitmask, gL: nodal Delta u read on them), e.g. a workloads.Problem.
+    order z, y, x) and optionally beta (a constant, or a nodal array: FP64 only) and Navier
+    faces (navier: per-face flags or a bitmask, gL: nodal Delta u read on them), e.g. a
+    workloads.Problem.
     """
 
     def __init__(self, problem, precision=FP64, device="cuda:0", **opts):
@@ -198,9 +212,8 @@ class Solver:
         self.device = torch.device(device)
         self.n = tuple(problem.n)
         self.dim = len(self.n)
-        tens = [_dev(getattr(problem, k, None), self.device) for k in _FIELDS]
-        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, getattr(problem, "beta", 0.0),
-                                  getattr(problem, "navier", ()))
+        tens, beta = _problem_tensors(problem, self.device)
+        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, beta, getattr(problem, "navier", ()))
         self.options = default_options(precision, **opts)
         h = _H()
         with torch.cuda.device(self.device):
@@ -308,10 +321,9 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
     dev = torch.device(device)
     keep, structs, outs = [], [], []
     for pb in problems:
-        tens = [_dev(getattr(pb, k, None), dev) for k in _FIELDS]
+        tens, beta = _problem_tensors(pb, dev)
         keep.append(tens)
-        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, getattr(pb, "beta", 0.0),
-                                       getattr(pb, "navier", ())))
+        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, beta, getattr(pb, "navier", ())))
         outs.append(torch.empty(tuple(m + 1 for m in reversed(pb.n)), dtype=torch.float64, device=dev))
     cnt = len(problems)
     parr = (_Problem * cnt)(*structs)

@@ -20,7 +20,10 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <initializer_list>
 #include <map>
+#include <type_traits>
+#include <utility>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -70,6 +73,15 @@ struct ahoc_handle {
   Weights wv;          // the v-equation's lift weights (normal weight shifted by -c m1)
   double cshift = 0;   // the v-equation's shift c = beta/alpha (constant alpha), 0 for beta = 0
   int navier = 0;      // bit f set: face f (2 axis + side) is a Navier face
+  // variable beta: nodal c = beta / alpha, the V-solve by BiCGSTAB preconditioned by the
+  // sine-transform solve with the constant shift cshift = (min c + max c) / 2
+  bool cvar = false;
+  double* cnod = nullptr;
+  double* bk[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* bdot = nullptr;    // device scalars of the BiCGSTAB dot products
+  double* bpart = nullptr;   // their partial sums
+  double* bpin = nullptr;    // host-pinned copies
+  long long vs_iters = 0;    // BiCGSTAB iterations so far (reported per solve)
   ahoc_options opt;
   // FP64 problem data
   double* ia64 = nullptr;
@@ -412,8 +424,96 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
   return ST_OK;
 }
 
+// Variable beta (Remark 2): the interior V of -L_h V + M(c V) = src with V = Q on the face
+// interiors, c = beta / alpha nodal, into P.bufA.  BiCGSTAB on A x = src - A_IB Q (A the
+// interior operator), right-preconditioned by K = -L_h + cshift M, whose inverse is one
+// sine-transform solve.  Stops at ||r|| <= 1e-14 ||rhs|| (the FP64 rounding level of the
+// preconditioned operator), after 200 iterations, or when four iterations gained less
+// than a factor 2.
+int dot_blocks(const ahoc_handle* h, long long n);
+
+int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* src, hipStream_t st) {
+  const Geom& g = h->g;
+  const long long n = TA(g);
+  double *x = P.bufA, *r = h->bk[0], *rh = h->bk[1], *p = h->bk[2], *v = h->bk[3], *t = h->bk[4],
+         *y = h->bk[5], *z = h->bk[6];
+  const int nbk = dot_blocks(h, n);
+  // dots into bdot[k0..k0+cnt) and one synchronising read into bpin
+  auto dots = [&](std::initializer_list<std::pair<const double*, const double*>> ab) -> int {
+    int k = 0;
+    for (const auto& pr : ab) {
+      TRY(mdot_partial(pr.first, n, 1, pr.second, n, 1, h->bpart, nbk, st));
+      TRY(mdot_reduce(h->bpart, nbk, 1, 1, h->bdot + k, 1, 0, st));
+      ++k;
+    }
+    AHOC_HIP_TRY(hipMemcpyAsync(h->bpin, h->bdot, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
+    return ST_OK;
+  };
+  auto apply = [&](const double* in, double* out) { return vapply(g, h->w, in, nullptr, h->cnod, nullptr, out, st); };
+  auto precond = [&](const double* in, double* out) -> int {
+    AHOC_HIP_TRY(hipMemcpyAsync(out, in, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    return poisson<double>(h, P, out, P.scV, st);
+  };
+  hipEvent_t e = tbegin(h, st);
+  // r = src - A_IB Q  (x = 0)
+  TRY(fill(n, 0.0, x, st));
+  TRY(vapply(g, h->w, x, Q, h->cnod, src, r, st));
+  TRY(axpby(n, 0.0, r, -1.0, r, st));
+  TRY(dots({{r, r}}));
+  const double bnorm = std::sqrt(h->bpin[0]);
+  if (bnorm == 0.0) {
+    tend(h, AHOC_K_LIFT, e, 0.0, st);
+    return ST_OK;
+  }
+  AHOC_HIP_TRY(hipMemcpyAsync(rh, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  TRY(fill(n, 0.0, p, st));
+  TRY(fill(n, 0.0, v, st));
+  double rho = 1.0, alpha = 1.0, omega = 1.0, best = bnorm;
+  int since = 0;
+  for (int it = 0; it < 200; ++it) {
+    TRY(dots({{rh, r}}));
+    const double rho1 = h->bpin[0];
+    const double beta = (rho1 / rho) * (alpha / omega);
+    TRY(axpby(n, -omega, v, 1.0, p, st));  // p = r + beta (p - omega v)
+    TRY(axpby(n, 1.0, r, beta, p, st));
+    TRY(precond(p, y));
+    TRY(apply(y, v));
+    TRY(dots({{rh, v}}));
+    alpha = rho1 / h->bpin[0];
+    TRY(axpby(n, -alpha, v, 1.0, r, st));  // s = r - alpha v, in r
+    TRY(axpby(n, alpha, y, 1.0, x, st));   // x += alpha y
+    ++h->vs_iters;
+    TRY(dots({{r, r}}));
+    double rn = std::sqrt(h->bpin[0]);
+    if (rn <= 1e-14 * bnorm) break;
+    TRY(precond(r, z));
+    TRY(apply(z, t));
+    TRY(dots({{t, r}, {t, t}}));
+    omega = h->bpin[0] / h->bpin[1];
+    TRY(axpby(n, omega, z, 1.0, x, st));   // x += omega z
+    TRY(axpby(n, -omega, t, 1.0, r, st));  // r = s - omega t
+    TRY(dots({{r, r}}));
+    rn = std::sqrt(h->bpin[0]);
+    rho = rho1;
+    if (rn <= 1e-14 * bnorm) break;
+    if (rn < 0.5 * best) {
+      best = rn;
+      since = 0;
+    } else if (++since >= 4) {
+      break;
+    }
+  }
+  tend(h, AHOC_K_LIFT, e, 0.0, st);
+  return ST_OK;
+}
+
 // V = -L^{-1}(src + L_bnd[Q])  into P.bufA
 template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  if (h->cvar) {
+    if constexpr (std::is_same<T, double>::value) return vsolve_var(h, P, Q, src, st);
+    else return ST_UNSUPPORTED;
+  }
   hipEvent_t e = tbegin(h, st);
   TRY(lift<T>(h->g, h->wv, Q, src, P.bufA, st));
   tend(h, AHOC_K_LIFT, e, (double)h->g.nint * h->g.nb * sizeof(T) * (src ? 2 : 1), st);
@@ -1030,7 +1130,30 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
       set_last_error("alpha must be positive everywhere", "ahoc_setup");
       return ST_INVALID;
     }
-    if (pb->beta != 0.0) {
+    if (pb->beta_nodal) {
+      if (count != 1 || h->opt.precision != AHOC_FP64) {
+        set_last_error("a variable beta needs FP64 precision and a single problem per handle", "ahoc_setup");
+        return ST_UNSUPPORTED;
+      }
+      h->cvar = true;
+      TRY(alloc_t(h, &h->cnod, TN(g)));
+      TRY(mul(TN(g), pb->beta_nodal, h->ia64, h->cnod, st));
+      TRY(minmax_partial(TN(g), h->cnod, h->red, 512, st));
+      std::vector<double> hb(1024);
+      AHOC_HIP_TRY(hipMemcpyAsync(hb.data(), h->red, sizeof(double) * 1024, hipMemcpyDeviceToHost, st));
+      AHOC_HIP_TRY(hipStreamSynchronize(st));
+      double cmin = 1e300, cmax = -1e300;
+      for (int b = 0; b < 512; ++b) {
+        cmin = std::min(cmin, hb[2 * b]);
+        cmax = std::max(cmax, hb[2 * b + 1]);
+      }
+      h->cshift = 0.5 * (cmin + cmax);
+      for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
+      for (int k = 0; k < 7; ++k) TRY(alloc_int(h, &h->bk[k], st));
+      TRY(alloc_t(h, &h->bdot, 8));
+      TRY(alloc_t(h, &h->bpart, (long long)h->nb_dot));
+      AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->bpin), sizeof(double) * 8, hipHostMallocDefault));
+    } else if (pb->beta != 0.0) {
       // the v-equation -L_h V + (beta/alpha) M V = M f is solved by the sine transforms only
       // for a constant shift beta/alpha
       int rc = 0;
@@ -1061,6 +1184,7 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   h->p64.af = h->af64;
   const bool schur_ir = mixed && h->opt.refine == 1;
   if (!mixed || schur_ir) TRY(prec_init<double>(h, h->p64, h->opt.tile_fp64, st));
+  if (h->cvar) h->p64.spectral = false;  // the V-solve is iterative: physical lift, U and gather
   if (mixed) {
     h->p32.ia = ia32;
     h->p32.af = af32;
@@ -1164,6 +1288,7 @@ void ahoc_destroy(ahoc_handle* h) {
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->pinned_i) (void)hipHostFree(h->pinned_i);
+  if (h->bpin) (void)hipHostFree(h->bpin);
   delete h;
 }
 
@@ -1558,10 +1683,11 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   const auto t0 = std::chrono::steady_clock::now();
   if (h->g.nb != 1) return AHOC_E_INVALID;
   double* const uo[1] = {u};
-  const long long g0 = h->graph_steps;
+  const long long g0 = h->graph_steps, v0 = h->vs_iters;
   int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, uo, v, q, &local, st)
                                           : ahoc::solve_fp64(h, uo, v, q, &local, st);
   local.graph_steps = (int)(h->graph_steps - g0);
+  local.vsolve_iters = (int)(h->vs_iters - v0);
   local.dst_gemm = ahoc::gemm_mask(h);
   const auto t1 = std::chrono::steady_clock::now();
   local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -1620,7 +1746,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
   std::vector<std::vector<int>> jobs;
   for (int i = 0; i < count; ++i) {
     const ahoc_problem& p = probs[i];
-    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.navier) {  // beta or Navier faces: alone
+    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.navier || p.beta_nodal) {  // beta or Navier faces: alone
       jobs.push_back({i});
       continue;
     }

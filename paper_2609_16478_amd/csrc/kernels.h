@@ -37,6 +37,11 @@ int resid64(const Geom& g, const Weights& w, const double* U, const double* V, c
 int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32, double* bmin,
                     int nb, hipStream_t st);
 int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st);
+// variable shift c (nodal): y = -L_h[V] + M(c V) - src on the interior of a single problem
+int vapply(const Geom& g, const Weights& w, const double* X, const double* Q, const double* c, const double* src,
+           double* y, hipStream_t st);
+// per-block min and max (part[2 b], part[2 b + 1]) of n doubles
+int minmax_partial(long long n, const double* x, double* part, int nblocks, hipStream_t st);
 // Navier faces of a single problem: af = 0 and src_q = -alpha g_L on their q-rows
 int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL, double* af64, float* af32,
                  double* src_q, hipStream_t st);

@@ -793,6 +793,67 @@ __global__ void k_src_q(Geom g, Weights w, const double* __restrict__ alpha, con
   }
 }
 
+// The v-equation's operator with a variable shift c = beta / alpha (nodal), on the interior:
+//   y = -L_h[V] + M(c V) - src
+// with V = X at interior nodes, Q at face-interior nodes (Q may be null: zero there) and 0
+// on edges and corners (their known values are part of src); src may be null.
+template <int DIM>
+__global__ void k_vapply(Geom g, Weights w, const double* __restrict__ X, const double* __restrict__ Q,
+                         const double* __restrict__ c, const double* __restrict__ src, double* __restrict__ y) {
+  const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i0_ = threadIdx.x; i0_ < g.px; i0_ += blockDim.x) {
+    const long long e = (long long)r_ * g.px + i0_;
+    const int i = i0_ + 1, j = (DIM == 3 ? r_ % g.ni[1] : r_) + 1, k = DIM == 3 ? r_ / g.ni[1] + 1 : 0;
+    if (i > g.ni[0]) {
+      y[e] = 0.0;
+      continue;
+    }
+    double lv = 0, mv = 0;
+    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wt = lw<DIM>(w, dx, dy, dz);
+          if (wt == 0.0) continue;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          const int nb = nbnd<DIM>(g, qi, qj, qk);
+          double vq = 0;
+          if (nb == 0) vq = X[inr(g, qi, qj, DIM == 3 ? qk : 1)];
+          else if (nb == 1 && Q) vq = Q[qidx<DIM>(g, qi, qj, qk)];
+          lv += wt * vq;
+          const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
+          if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * c[nod(g, qi, qj, qk)] * vq;
+        }
+    y[e] = mv - lv - (src ? src[e] : 0.0);
+  }
+}
+
+// per-block minimum and maximum of x: part[2 b] = min, part[2 b + 1] = max
+__global__ void k_minmax(long long n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double rmin[TPB], rmax[TPB];
+  double mn = 1e300, mx = -1e300;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    mn = fmin(mn, x[e]);
+    mx = fmax(mx, x[e]);
+  }
+  rmin[threadIdx.x] = mn;
+  rmax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      rmin[threadIdx.x] = fmin(rmin[threadIdx.x], rmin[threadIdx.x + s]);
+      rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = rmin[0];
+    part[2 * blockIdx.x + 1] = rmax[0];
+  }
+}
+
 // Navier faces (bit f of `mask`, f = 2 axis + side): Delta u = g_L is given there, so V =
 // alpha g_L is known and the face's q-rows read R = alpha g_L - Q.  The gather's one-sided
 // term is switched off (af = 0) and the known part becomes src_q = -alpha g_L.
@@ -1027,6 +1088,19 @@ int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32,
 
 int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st) {
   LAUNCH_DIM(k_face_alpha, dim3(nblocks(g.nq), g.nb), g, alpha, af64, af32);
+  return ST_OK;
+}
+
+int vapply(const Geom& g, const Weights& w, const double* X, const double* Q, const double* c, const double* src,
+           double* y, hipStream_t st) {
+  if (g.nb != 1) return ST_UNSUPPORTED;
+  LAUNCH_DIM(k_vapply, dim3(interior_rows(g)), g, w, X, Q, c, src, y);
+  return ST_OK;
+}
+
+int minmax_partial(long long n, const double* x, double* part, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_minmax, dim3(nblocks), dim3(TPB), 0, st, n, x, part);
+  AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
 

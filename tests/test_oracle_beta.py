@@ -16,7 +16,9 @@ With v = alpha Delta u the v-equation becomes -Delta v + beta v / alpha = f, dis
 * Navier faces: Table 1 of the paper (Example 1, clamped at x = 0 and Navier elsewhere,
   alpha = eps, beta = 1) reproduced at 256 x 256 to its three printed digits for both eps;
   polynomial exactness with Navier faces in 2-D and 3-D; a planted loss of the Navier
-  flags that breaks the solution; the fast tier against the direct tier.
+  flags that breaks the solution; the fast tier against the direct tier;
+* the high-wavenumber problem (beta = -k^2, indefinite v-equation): fourth order against a
+  finer grid.
 """
 import numpy as np
 import pytest
@@ -153,3 +155,57 @@ def test_fast_tier_with_navier_equals_direct(maker):
     U, V, Q, _ = direct.solve(p)
     U2, V2, Q2, info = fast.FastTier(p).solve(tol=1e-14, restart=60)
     assert np.abs(U2 - U).max() <= 1e-11 * np.abs(U).max()
+
+
+def test_high_wavenumber_fourth_order():
+    """The high-wavenumber problem of Sec. 4.2 (alpha = 1, beta = -k^2: an indefinite
+    v-equation) with a resolved source (k = 10, sigma = 0.1): the max-norm error against a
+    256 x 256 solution falls at fourth order (ratio 15.2 between 64 and 128)."""
+    ref = direct.solve(W.high_wavenumber(256, 2, k=10.0, sigma=0.1))[0]
+    errs = []
+    for n in (64, 128):
+        U = direct.solve(W.high_wavenumber(n, 2, k=10.0, sigma=0.1))[0]
+        errs.append(np.abs(U - ref[::256 // n, ::256 // n]).max())
+    assert 13.0 < errs[0] / errs[1] < 19.0, errs
+
+
+# ------------------------------------------------------------------------------------------
+# variable beta (Remark 2: the v-equation is then iterated) and the paper's Example 2
+# ------------------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,n,beta", [(2, (12, 9), "x + 2*y + 10"), (2, 10, "3 + x*y - y**2"),
+                                        (3, (6, 5, 7), "x + y + z + 10")])
+def test_polynomial_exactness_with_variable_beta(dim, n, beta):
+    """With beta varying, M(beta V / alpha) must take beta at each neighbour of the stencil;
+    the scheme then stays exact for u of degree 4 (the beta term of f is sampled, not
+    discretised, and cancels only if the rows use the same nodal values)."""
+    p = W.poly_exact(n, dim, beta=beta)
+    assert not np.isscalar(p.beta)
+    U, V, Q, asm = direct.solve(p)
+    assert np.abs(U - p.u_exact).max() < 1e-11
+    assert np.abs(V - p.v_exact).max() < 1e-8
+
+
+def test_variable_beta_replaced_by_its_mean_breaks_exactness():
+    # planted: the nodal beta replaced by its mean while f keeps the variable beta
+    p = W.poly_exact((12, 9), 2, beta="x + 2*y + 10")
+    p.beta = float(np.mean(p.beta))
+    U, *_ = direct.solve(p)
+    assert np.abs(U - p.u_exact).max() > 1e-6
+
+
+def test_example2_fourth_order_small():
+    """Example 2 (Sec. 4.1; variable alpha and beta, clamped at x = 0, Navier elsewhere) with
+    (q, p) = (5, 1): the error falls by 14-17 from 8^3 to 16^3 (Table 2 starts at 32^3 with
+    6.86e-4; the oracle's 32^3 solve, 6.848e-4, is stored by tests/golden/make_example2_oracle.py)."""
+    errs = []
+    for n in (8, 16):
+        p = W.example2(n, 5.0, 1.0)
+        U, *_ = direct.solve(p)
+        errs.append(np.abs(U - p.u_exact).max())
+    assert 12.0 < errs[0] / errs[1] < 17.0, errs
+
+
+def test_fast_tier_rejects_variable_beta():
+    with pytest.raises(ValueError):
+        fast.FastTier(W.manufactured("1", "sin(pi*x)**2*sin(pi*y)**2", (8, 8), beta="1 + x"))

@@ -29,6 +29,7 @@ import numpy as np
 __all__ = [
     "Problem", "manufactured", "config1", "config2", "config3", "config4_specs",
     "config4_instance", "cavity", "plate", "poly_exact", "node_coords", "example1",
+    "high_wavenumber", "example2",
 ]
 
 
@@ -36,7 +37,8 @@ __all__ = [
 class Problem:
     """One clamped problem on a box: grid, coefficients and data (nodal arrays).
 
-    The equation is -Delta(alpha Delta u) + beta Delta u = f with beta a constant.  Every face
+    The equation is -Delta(alpha Delta u) + beta Delta u = f with beta a constant or a nodal
+    array.  Every face
     carries u = g_D; a clamped face also u_n = g_N, a Navier face (navier[f]) Delta u = g_L
     instead (the boundary conditions eq-bc, with the Navier part of the boundary).
 
@@ -57,7 +59,7 @@ class Problem:
     v_exact: Any = None
     name: str = ""
     meta: dict = field(default_factory=dict)
-    beta: float = 0.0
+    beta: Any = 0.0      # constant, or a nodal array (variable beta)
     navier: tuple = ()   # per face (x-, x+, y-, y+[, z-, z+]): True = Navier (Delta u = g_L), else clamped
     gL: Any = None       # nodal Delta u, read on the face-interior nodes of Navier faces
 
@@ -118,6 +120,16 @@ def _lambdify(expr, X, P, xp_name):
 
 
 @functools.lru_cache(maxsize=None)
+def _expr_fn(src, dim, xp_name):
+    """A plain expression in x, y[, z] (no derivatives), e.g. a variable beta."""
+    import sympy as sp
+    X = _symbols(dim)
+    ns = {s.name: s for s in X}
+    ns.update({"pi": sp.pi, "sin": sp.sin, "cos": sp.cos, "exp": sp.exp, "sqrt": sp.sqrt})
+    return _lambdify(sp.sympify(src, locals=ns), X, (), xp_name)
+
+
+@functools.lru_cache(maxsize=None)
 def _fn(alpha_src, u_src, dim, params, key, xp_name):
     X, P, exprs = _derive(alpha_src, u_src, dim, params)
     return _lambdify(exprs[key], X, P, xp_name)
@@ -146,6 +158,16 @@ class _Eval:
     def __call__(self, key, cs):
         fn = _fn(self.a, self.u, self.dim, self.params, key, self.xp)
         out = fn(*cs, *self.pvals)
+        if self.xp == "torch":
+            import torch
+            shape = tuple(torch.broadcast_shapes(*[tuple(c.shape) for c in cs]))
+        else:
+            shape = np.broadcast_shapes(*[c.shape for c in cs])
+        return self._full(out, shape)
+
+    def expr(self, src, cs):
+        """Sample a plain expression (e.g. a variable beta) on the coordinates cs."""
+        out = _expr_fn(src, self.dim, self.xp)(*cs)
         if self.xp == "torch":
             import torch
             shape = tuple(torch.broadcast_shapes(*[tuple(c.shape) for c in cs]))
@@ -233,8 +255,9 @@ def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None,
     """Sample a manufactured clamped problem.
 
     alpha_src/u_src: expressions in x, y[, z] (and `params`).  f follows the
-    paper's sign convention of eq. (1), f = -Delta(alpha Delta u) + beta Delta u with the
-    constant beta.  navier: per face, True for a Navier face (g_L = Delta u sampled).
+    paper's sign convention of eq. (1), f = -Delta(alpha Delta u) + beta Delta u; beta is a
+    constant or an expression in x, y[, z] (then Problem.beta is its nodal sample).
+    navier: per face, True for a Navier face (g_L = Delta u sampled).
     xp = "numpy" gives host
     arrays; xp = "torch" builds the nodal fields on `device` (in z-chunks of
     `chunk` planes for large 3-D grids).
@@ -245,22 +268,29 @@ def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None,
     ev = _Eval(alpha_src, u_src, dim, params, pvals, xp, device)
     c1d = node_coords(n, lo, hi)
     shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+    var_beta = isinstance(beta, str)
+    beta_src = beta
     keys = ["alpha", "f"] + (["u", "v"] if with_exact else []) + (["lapu"] if beta else [])
     out = {}
-    if dim == 3 and chunk is not None:
+
+    def sample(cs, sl):
         for k in keys:
-            out[k] = _zeros(ev, shape)
+            out[k][sl] = ev(k, cs)
+        if var_beta:
+            out["beta"][sl] = ev.expr(beta, cs)
+
+    for k in keys + (["beta"] if var_beta else []):
+        out[k] = _zeros(ev, shape)
+    if dim == 3 and chunk is not None:
         for z0 in range(0, n[2] + 1, chunk):
             z1 = min(n[2] + 1, z0 + chunk)
-            cs = [ev.coords(c1d[0], 0), ev.coords(c1d[1], 1), ev.coords(c1d[2][z0:z1], 2)]
-            for k in keys:
-                out[k][z0:z1] = ev(k, cs)
+            sample([ev.coords(c1d[0], 0), ev.coords(c1d[1], 1), ev.coords(c1d[2][z0:z1], 2)], slice(z0, z1))
     else:
-        cs = [ev.coords(c1d[a], a) for a in range(dim)]
-        for k in keys:
-            out[k] = ev(k, cs)
+        sample([ev.coords(c1d[a], a) for a in range(dim)], slice(None))
     if beta:
-        out["f"] = out["f"] + float(beta) * out.pop("lapu")
+        bval = out.pop("beta") if var_beta else float(beta)
+        out["f"] = out["f"] + bval * out.pop("lapu")
+        beta = bval
     nav = tuple(bool(v) for v in navier) if any(navier) else ()
     if nav and len(nav) != 2 * dim:
         raise ValueError("navier needs one flag per face")
@@ -269,9 +299,9 @@ def manufactured(alpha_src: str, u_src: str, n: Sequence[int], lo=None, hi=None,
     gL = bd[3] if nav else None
     return Problem(tuple(n), lo, hi, out["alpha"], out["f"], gD, gN, lap,
                    out.get("u"), out.get("v"), name=name,
-                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals)), "beta": float(beta),
-                         "navier": nav},
-                   beta=float(beta), navier=nav, gL=gL)
+                   meta={"alpha": alpha_src, "u": u_src, "params": dict(zip(params, pvals)),
+                         "beta": beta_src if var_beta else float(beta), "navier": nav},
+                   beta=beta if var_beta else float(beta), navier=nav, gL=gL)
 
 
 # --------------------------------------------------------------------------------------
@@ -337,6 +367,20 @@ def example1(n=256, eps=1e-4, **kw):
                         navier=(False, True, True, True), name=f"ex1_n{n}_eps{eps:g}", **kw)
 
 
+EX2_U = "(x**2 - x)*(y**2 - y)*(z**2 - z)*exp(q*((x - 0.5)**2 + (y - 0.5)**2 + (z - p)**2))"
+EX2_ALPHA = "x**2 + y**2 + z**2 + 1"
+EX2_BETA = "x + y + z + 10"
+
+
+def example2(n=32, q=10.0, p=0.2, **kw):
+    """The 3-D peaked test of the paper's second convergence experiment: alpha = x^2 + y^2 +
+    z^2 + 1, beta = x + y + z + 10 (variable), clamped at x = 0 and Navier on the other faces,
+    with the manufactured solution EX2_U (peak sharpness q, peak height p along z)."""
+    nn = tuple(n) if isinstance(n, (tuple, list)) else (n, n, n)
+    return manufactured(EX2_ALPHA, EX2_U, nn, params=("q", "p"), pvals=(float(q), float(p)), beta=EX2_BETA,
+                        navier=(False, True, True, True, True, True), name=f"ex2_n{nn[0]}_q{q:g}_p{p:g}", **kw)
+
+
 def cavity(n=64):
     """Lid-driven cavity stream function: Delta^2 psi = 0, psi = 0, psi_n = 1 on y = 1."""
     dim = 2
@@ -369,6 +413,37 @@ def plate(n=64):
         load[mask] = 1.0 / (4 * h * h)
     return Problem((n, n), (0.0, 0.0), (1.0, 1.0), np.ones((n + 1, n + 1)), -load,
                    name=f"plate_n{n}")
+
+
+def high_wavenumber(n, dim=2, k=50.0, sigma=0.02, xp="numpy", device=None):
+    """The high-wavenumber test of Sec. 4.2: -Delta^2 u - k^2 Delta u = (1e5 / (pi sigma^2))
+    exp(-|x - 1/2|^2 / sigma^2) on the unit box with homogeneous clamped conditions, i.e.
+    alpha = 1, beta = -k^2 in -Delta(alpha Delta u) + beta Delta u = f.  No closed-form
+    solution: errors are measured against a finer grid."""
+    n = tuple(n) if isinstance(n, (tuple, list)) else (int(n),) * dim
+    dim = len(n)
+    c1d = node_coords(n, (0.0,) * dim, (1.0,) * dim)
+    shape = tuple(m + 1 for m in reversed(n))
+    if xp == "torch":
+        import torch
+        r2 = torch.zeros(shape, dtype=torch.float64, device=device)
+        for a in range(dim):
+            ax = torch.as_tensor(c1d[a], dtype=torch.float64, device=device)
+            sh = [1] * dim
+            sh[dim - 1 - a] = n[a] + 1
+            r2 = r2 + ((ax - 0.5) ** 2).reshape(sh)
+        f = 1e5 / (np.pi * sigma ** 2) * torch.exp(-r2 / sigma ** 2)
+        alpha = torch.ones(shape, dtype=torch.float64, device=device)
+    else:
+        r2 = np.zeros(shape)
+        for a in range(dim):
+            sh = [1] * dim
+            sh[dim - 1 - a] = n[a] + 1
+            r2 = r2 + ((c1d[a] - 0.5) ** 2).reshape(sh)
+        f = 1e5 / (np.pi * sigma ** 2) * np.exp(-r2 / sigma ** 2)
+        alpha = np.ones(shape)
+    return Problem(n, (0.0,) * dim, (1.0,) * dim, alpha, f, beta=-float(k) ** 2,
+                   name=f"hwp{dim}d_n{n[0]}_k{k:g}", meta={"k": float(k), "sigma": float(sigma)})
 
 
 def poly_exact(n, dim=2, **kw):
