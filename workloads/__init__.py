@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "Problem", "manufactured", "config1", "config2", "config3", "config4_specs",
     "config4_instance", "cavity", "plate", "poly_exact", "node_coords", "example1",
-    "high_wavenumber", "example2",
+    "high_wavenumber", "example2", "example3",
 ]
 
 
@@ -379,6 +379,20 @@ def example2(n=32, q=10.0, p=0.2, **kw):
     nn = tuple(n) if isinstance(n, (tuple, list)) else (n, n, n)
     return manufactured(EX2_ALPHA, EX2_U, nn, params=("q", "p"), pvals=(float(q), float(p)), beta=EX2_BETA,
                         navier=(False, True, True, True, True, True), name=f"ex2_n{nn[0]}_q{q:g}_p{p:g}", **kw)
+
+
+EX3_U = "sin(k1*x)*cos(k2*y)*sin(k3*z)"
+
+
+def example3(n=32, k=(5.0, 1.0, 5.0), **kw):
+    """The 3-D oscillatory test of the paper (Table 3): u = sin(k1 x) cos(k2 y) sin(k3 z) with
+    the coefficients of Example 2 (alpha = x^2 + y^2 + z^2 + 1, beta = x + y + z + 10), clamped
+    at x = 0 and Navier on the other faces; all boundary data inhomogeneous."""
+    nn = tuple(n) if isinstance(n, (tuple, list)) else (n, n, n)
+    k = tuple(float(v) for v in k)
+    return manufactured(EX2_ALPHA, EX3_U, nn, params=("k1", "k2", "k3"), pvals=k, beta=EX2_BETA,
+                        navier=(False, True, True, True, True, True),
+                        name=f"ex3_n{nn[0]}_k{k[0]:g}_{k[1]:g}_{k[2]:g}", **kw)
 
 
 def cavity(n=64):
