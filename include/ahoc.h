@@ -122,7 +122,8 @@ typedef struct {
                          preconditioner and Schur matvec) is captured once as a HIP graph
                          and replayed; needs a stream that can be captured (not the
                          legacy default stream: there the launches stay eager).  Ignored
-                         while ahoc_profile is on.  0 (default): eager launches        */
+                         while ahoc_profile is on and with a variable beta (its V-solve
+                         synchronises on dot products).  0 (default): eager launches   */
 } ahoc_options;
 
 typedef struct {

@@ -1136,6 +1136,7 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
         return ST_UNSUPPORTED;
       }
       h->cvar = true;
+      h->opt.use_graph = 0;  // the BiCGSTAB V-solve reads its dot products on the host
       TRY(alloc_t(h, &h->cnod, TN(g)));
       TRY(mul(TN(g), pb->beta_nodal, h->ia64, h->cnod, st));
       TRY(minmax_partial(TN(g), h->cnod, h->red, 512, st));

@@ -172,3 +172,15 @@ def test_example3_table3_on_gpu(ah, n, k):
     print(f"example3 {k} n={n}: {err:.6e} (Table 3: {ref:.2e}) gmres {st.gmres_iters} "
           f"bicgstab {st.vsolve_iters} {st.t_solve_ms:.0f} ms", flush=True)
     assert abs(err - ref) <= _printed_tol(ref, n, p.u_exact.abs().max().item()), (err, ref)
+
+
+def test_varbeta_graph_option_stays_eager(ah):
+    """use_graph is ignored with a variable beta (the V-solve reads dot products on the host):
+    the solve runs eagerly and equals the default one."""
+    p = CASES["2d"]()
+    with ah.Solver(p, tol=1e-13) as s:
+        u0, _, _, st0 = s.solve()
+    with ah.Solver(p, tol=1e-13, use_graph=1) as s:
+        u1, _, _, st1 = s.solve()
+    assert st1.converged and st1.graph_steps == 0
+    assert torch.equal(u0, u1)
