@@ -428,8 +428,8 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
 // interiors, c = beta / alpha nodal, into P.bufA.  BiCGSTAB on A x = src - A_IB Q (A the
 // interior operator), right-preconditioned by K = -L_h + cshift M, whose inverse is one
 // sine-transform solve.  Stops at ||r|| <= 1e-14 ||rhs|| (the FP64 rounding level of the
-// preconditioned operator), after 200 iterations, or when four iterations gained less
-// than a factor 2.
+// preconditioned operator), after 200 iterations, when four iterations gained less than a
+// factor 2, or on a breakdown (a zero or non-finite rho or step), keeping the last iterate.
 int dot_blocks(const ahoc_handle* h, long long n);
 
 int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* src, hipStream_t st) {
@@ -474,12 +474,14 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
   for (int it = 0; it < 200; ++it) {
     TRY(dots({{rh, r}}));
     const double rho1 = h->bpin[0];
+    if (rho1 == 0.0 || !std::isfinite(rho1)) break;
     const double beta = (rho1 / rho) * (alpha / omega);
     TRY(axpby(n, -omega, v, 1.0, p, st));  // p = r + beta (p - omega v)
     TRY(axpby(n, 1.0, r, beta, p, st));
     TRY(precond(p, y));
     TRY(apply(y, v));
     TRY(dots({{rh, v}}));
+    if (h->bpin[0] == 0.0 || !std::isfinite(h->bpin[0])) break;
     alpha = rho1 / h->bpin[0];
     TRY(axpby(n, -alpha, v, 1.0, r, st));  // s = r - alpha v, in r
     TRY(axpby(n, alpha, y, 1.0, x, st));   // x += alpha y
@@ -490,6 +492,7 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
     TRY(precond(r, z));
     TRY(apply(z, t));
     TRY(dots({{t, r}, {t, t}}));
+    if (h->bpin[1] == 0.0 || !std::isfinite(h->bpin[0] / h->bpin[1])) break;
     omega = h->bpin[0] / h->bpin[1];
     TRY(axpby(n, omega, z, 1.0, x, st));   // x += omega z
     TRY(axpby(n, -omega, t, 1.0, r, st));  // r = s - omega t

@@ -184,3 +184,32 @@ def test_varbeta_graph_option_stays_eager(ah):
         u1, _, _, st1 = s.solve()
     assert st1.converged and st1.graph_steps == 0
     assert torch.equal(u0, u1)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_nodal_constant_beta_equals_shifted_transform(ah, dim):
+    """A nodal beta that happens to be constant takes the BiCGSTAB V-solve; a scalar beta takes
+    the shifted transform solve.  The two are different algorithms for the same discrete
+    problem and must agree (U to 1e-11)."""
+    if dim == 2:
+        p = W.manufactured("0.5", U2, (32, 24), beta=3.0, navier=(False, True, False, True))
+    else:
+        p = W.manufactured("2", "sin(pi*x)*sin(pi*y)**2*sin(pi*z)", (12, 8, 16), beta=-1.5)
+    with ah.Solver(p, tol=1e-13) as s:
+        u0, _, _, st0 = s.solve()
+    p.beta = np.full(tuple(m + 1 for m in reversed(p.n)), p.beta)
+    with ah.Solver(p, tol=1e-13) as s:
+        u1, _, _, st1 = s.solve()
+    assert st0.converged and st1.converged and st0.vsolve_iters == 0 and st1.vsolve_iters > 0, (st0, st1)
+    assert _rel(u1.cpu().numpy(), u0.cpu().numpy()) < 1e-11
+
+
+def test_varbeta_in_a_batch(ah):
+    probs = [W.config2(32), CASES["2d"](), W.config2(32), CASES["3d_ex2"]()]
+    outs, stats, rc = ah.solve_batched(probs, tol=1e-13)
+    assert rc == ah.OK
+    for pb, u, st in zip(probs, outs, stats):
+        assert st.converged, pb.name
+        with ah.Solver(pb, tol=1e-13) as s:
+            u1, *_ = s.solve()
+        assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < 1e-12, pb.name
