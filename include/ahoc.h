@@ -273,7 +273,9 @@ enum {
   AHOC_K_FACE_REDUCE = 10, /* U-solve: face sums along the two fastest axes from the stored
                               scaled spectrum (reads the volume only)                      */
   AHOC_K_PRECOND = 11,     /* one application of the boundary-symbol preconditioner       */
-  AHOC_NKIND = 12
+  AHOC_K_VSOLVE = 12,      /* variable beta: one BiCGSTAB V-solve with its transform solves
+                              and stencil applications (bytes not modelled)               */
+  AHOC_NKIND = 13
 };
 
 /* Enable (1) or disable (0) per-kernel-class timing of the handle's solves with

@@ -463,7 +463,7 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
   TRY(dots({{r, r}}));
   const double bnorm = std::sqrt(h->bpin[0]);
   if (bnorm == 0.0) {
-    tend(h, AHOC_K_LIFT, e, 0.0, st);
+    tend(h, AHOC_K_VSOLVE, e, 0.0, st);
     return ST_OK;
   }
   AHOC_HIP_TRY(hipMemcpyAsync(rh, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
@@ -507,7 +507,7 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
       break;
     }
   }
-  tend(h, AHOC_K_LIFT, e, 0.0, st);
+  tend(h, AHOC_K_VSOLVE, e, 0.0, st);
   return ST_OK;
 }
 

@@ -213,3 +213,16 @@ def test_varbeta_in_a_batch(ah):
         with ah.Solver(pb, tol=1e-13) as s:
             u1, *_ = s.solve()
         assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < 1e-12, pb.name
+
+
+def test_varbeta_kernel_class_timing(ah):
+    """With profiling on, every BiCGSTAB V-solve is timed as one 'vsolve' launch (its transform
+    passes under their own classes), one per matvec plus the right-hand side and recovery."""
+    p = CASES["3d_ex2"]()
+    with ah.Solver(p, tol=1e-12) as s:
+        s.profile(True)
+        u, _, _, st = s.solve()
+        kt = s.kernel_times()
+    assert st.converged
+    assert kt["vsolve"][1] == st.matvecs + 2, (kt["vsolve"], st)
+    assert kt["dst_fused"][1] > 0 and kt["vsolve"][0] > 0.0
