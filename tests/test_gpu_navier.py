@@ -179,3 +179,16 @@ def test_navier_graph_replays_match_eager(ah, case):
     assert st1.converged and st1.gmres_iters == st0.gmres_iters, (st0, st1)
     assert st0.graph_steps == 0 and st1.graph_steps >= st1.gmres_iters - 2, st1
     assert _rel(u1.cpu().numpy(), u0.cpu().numpy()) < 1e-14
+
+
+@pytest.mark.parametrize("eps", ["1e-4", "1e-5"])
+def test_example1_4096_mixed_vs_fp64(ah, eps):
+    """Mixed precision on the singularly perturbed Navier problem at its largest size: U within
+    1e-10 of the FP64 solve (max norm, relative)."""
+    p = W.example1(4096, float(eps), xp="torch", device=torch.device("cuda:0"))
+    with ah.Solver(p, tol=1e-13) as s:
+        u0, _, _, st0 = s.solve()
+    with ah.Solver(p, precision=ah.MIXED, tol=1e-10) as s:
+        u1, _, _, st1 = s.solve()
+    assert st0.converged and st1.converged, (st0, st1)
+    assert ((u1 - u0).abs().max() / u0.abs().max()).item() <= 1e-10
