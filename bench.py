@@ -96,6 +96,29 @@ def _pattern_copies(ah, torch, dev, n, reps=5):
     return out
 
 
+def _varbeta(ah, W, torch, dev, n):
+    """One FP64 solve of Example 2 with its variable alpha and beta (BiCGSTAB V-solves), a
+    warm-up solve first; the kernel-class times come from HIP events on the solve stream."""
+    prob = W.example2(n, 5.0, 1.0, xp="torch", device=dev, chunk=32)
+    prob.v_exact = None
+    with ah.Solver(prob, precision=ah.FP64, tol=1e-12) as s:
+        s.solve()
+        s.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        u, _, _, st = s.solve()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kt = s.kernel_times()
+    err = (u - prob.u_exact).abs().max().item()
+    print(f"[bench] variable beta n={n}: {1e3 * (t1 - t0):.1f} ms, {st.gmres_iters} GMRES, {st.vsolve_iters} "
+          f"BiCGSTAB, err {err:.3e}", file=sys.stderr, flush=True)
+    return {"metric": "FP64 solve time, Example 2 with variable alpha and beta", "n": n, "ms": 1e3 * (t1 - t0),
+            "gmres_iters": st.gmres_iters, "bicgstab_iters": st.vsolve_iters, "err_u_inf": err,
+            "kernel_classes_ms": {k: v[0] for k, v in kt.items() if v[1]},
+            "kernel_classes_launches": {k: v[1] for k, v in kt.items() if v[1]}}
+
+
 def _paper_timing(ah, W, torch, dev):
     """The workloads of the paper's timing table: the classical biharmonic equation (alpha = 1,
     beta = 0) with the solutions of Example 2 ((q, p) = (5, 1)) and of the oscillatory example
@@ -163,6 +186,10 @@ def main():
                          "and three with the matrix-core products")
     ap.add_argument("--no-instance-loop", action="store_true",
                     help="skip the per-instance FP64 loop over the batched workload")
+    ap.add_argument("--varbeta", type=int, default=0,
+                    help="separate target: one FP64 solve of Example 2 with its variable alpha and beta "
+                         "((q, p) = (5, 1), the workload of Table 2) at this n^3, tolerance 1e-12, with the "
+                         "kernel-class times; prints one JSON line")
     ap.add_argument("--paper-timing", action="store_true",
                     help="separate target: the workloads of the paper's timing table (the classical "
                          "biharmonic equation, alpha = 1, beta = 0, with the solutions of Example 2, (q, p) "
@@ -210,6 +237,9 @@ def main():
         return
     if args.paper_timing:
         print(json.dumps(_paper_timing(ah, W, torch, dev)))
+        return
+    if args.varbeta:
+        print(json.dumps(_varbeta(ah, W, torch, dev, args.varbeta)))
         return
     n = args.n
     t0 = time.perf_counter()

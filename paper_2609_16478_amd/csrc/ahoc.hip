@@ -397,14 +397,18 @@ template <typename T> void prec_free(Prec<T>& P) {
   P.ready = false;
 }
 
-// In-place Dirichlet solve on an interior array: buf <- scale * S (S buf / lambda).
-template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st) {
+// Dirichlet solve on an interior array: buf <- scale * S (S in / lambda), in place unless
+// `in` is given (then the first pass reads it and `in` is left unchanged).
+template <typename T>
+int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st, const T* in = nullptr) {
   const Geom& g = h->g;
   const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);  // one read + one write of the array
+  const T* src = in ? in : buf;
   auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner,
                  const DstScale<T>* f, int tile) -> int {
     hipEvent_t e = tbegin(h, st);
-    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, f, tile, st);
+    const int rc = dst_pass<T>(tb, src, buf, outer, inner, g.px, f, tile, st);
+    src = buf;
     tend(h, kind, e, pass_bytes, st);
     return rc;
   };
@@ -430,75 +434,69 @@ template <typename T> int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstS
 // sine-transform solve.  Stops at ||r|| <= 1e-14 ||rhs|| (the FP64 rounding level of the
 // preconditioned operator), after 200 iterations, when four iterations gained less than a
 // factor 2, or on a breakdown (a zero or non-finite rho or step), keeping the last iterate.
-int dot_blocks(const ahoc_handle* h, long long n);
+constexpr int VS_DOT_BLOCKS = 2048;  // work-groups of the V-solve's dot sweeps (>= 2048 entries each)
 
 int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* src, hipStream_t st) {
   const Geom& g = h->g;
   const long long n = TA(g);
-  double *x = P.bufA, *r = h->bk[0], *rh = h->bk[1], *p = h->bk[2], *v = h->bk[3], *t = h->bk[4],
+  // rh, r, t are consecutive n-vectors so that <rh, r>, <r, r> and <r, t>, <t, t> are one
+  // two-vector sweep each
+  double *x = P.bufA, *rh = h->bk[0], *r = h->bk[1], *t = h->bk[2], *p = h->bk[3], *v = h->bk[4],
          *y = h->bk[5], *z = h->bk[6];
-  const int nbk = dot_blocks(h, n);
-  // dots into bdot[k0..k0+cnt) and one synchronising read into bpin
-  auto dots = [&](std::initializer_list<std::pair<const double*, const double*>> ab) -> int {
-    int k = 0;
-    for (const auto& pr : ab) {
-      TRY(mdot_partial(pr.first, n, 1, pr.second, n, 1, h->bpart, nbk, st));
-      TRY(mdot_reduce(h->bpart, nbk, 1, 1, h->bdot + k, 1, 0, st));
-      ++k;
-    }
-    AHOC_HIP_TRY(hipMemcpyAsync(h->bpin, h->bdot, sizeof(double) * k, hipMemcpyDeviceToHost, st));
+  const int nbk = (int)std::max<long long>(1, std::min<long long>(VS_DOT_BLOCKS, n / 2048));
+  // <V_j, w> for the nv consecutive vectors V_0.. (n apart) into bpin[0..nv) (synchronising)
+  auto dots = [&](const double* V, int nv, const double* w) -> int {
+    TRY(mdot_partial(V, n, nv, w, n, 1, h->bpart, nbk, st));
+    TRY(mdot_reduce(h->bpart, nbk, nv, 1, h->bdot, nv, 0, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(h->bpin, h->bdot, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
     AHOC_HIP_TRY(hipStreamSynchronize(st));
     return ST_OK;
   };
   auto apply = [&](const double* in, double* out) { return vapply(g, h->w, in, nullptr, h->cnod, nullptr, out, st); };
-  auto precond = [&](const double* in, double* out) -> int {
-    AHOC_HIP_TRY(hipMemcpyAsync(out, in, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    return poisson<double>(h, P, out, P.scV, st);
-  };
+  auto precond = [&](const double* in, double* out) { return poisson<double>(h, P, out, P.scV, st, in); };
   hipEvent_t e = tbegin(h, st);
   // r = src - A_IB Q  (x = 0)
   TRY(fill(n, 0.0, x, st));
   TRY(vapply(g, h->w, x, Q, h->cnod, src, r, st));
   TRY(axpby(n, 0.0, r, -1.0, r, st));
-  TRY(dots({{r, r}}));
-  const double bnorm = std::sqrt(h->bpin[0]);
+  AHOC_HIP_TRY(hipMemcpyAsync(rh, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+  TRY(dots(rh, 2, r));  // <rh, r> = <r, r>
+  const double bnorm = std::sqrt(h->bpin[1]);
   if (bnorm == 0.0) {
     tend(h, AHOC_K_VSOLVE, e, 0.0, st);
     return ST_OK;
   }
-  AHOC_HIP_TRY(hipMemcpyAsync(rh, r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
   TRY(fill(n, 0.0, p, st));
   TRY(fill(n, 0.0, v, st));
-  double rho = 1.0, alpha = 1.0, omega = 1.0, best = bnorm;
+  double rho = 1.0, alpha = 1.0, omega = 1.0, best = bnorm, rho1 = h->bpin[0];
   int since = 0;
   for (int it = 0; it < 200; ++it) {
-    TRY(dots({{rh, r}}));
-    const double rho1 = h->bpin[0];
     if (rho1 == 0.0 || !std::isfinite(rho1)) break;
     const double beta = (rho1 / rho) * (alpha / omega);
     TRY(axpby(n, -omega, v, 1.0, p, st));  // p = r + beta (p - omega v)
     TRY(axpby(n, 1.0, r, beta, p, st));
     TRY(precond(p, y));
     TRY(apply(y, v));
-    TRY(dots({{rh, v}}));
+    TRY(dots(v, 1, rh));
     if (h->bpin[0] == 0.0 || !std::isfinite(h->bpin[0])) break;
     alpha = rho1 / h->bpin[0];
     TRY(axpby(n, -alpha, v, 1.0, r, st));  // s = r - alpha v, in r
     TRY(axpby(n, alpha, y, 1.0, x, st));   // x += alpha y
     ++h->vs_iters;
-    TRY(dots({{r, r}}));
+    TRY(dots(r, 1, r));
     double rn = std::sqrt(h->bpin[0]);
     if (rn <= 1e-14 * bnorm) break;
     TRY(precond(r, z));
     TRY(apply(z, t));
-    TRY(dots({{t, r}, {t, t}}));
+    TRY(dots(r, 2, t));  // <s, t>, <t, t>
     if (h->bpin[1] == 0.0 || !std::isfinite(h->bpin[0] / h->bpin[1])) break;
     omega = h->bpin[0] / h->bpin[1];
     TRY(axpby(n, omega, z, 1.0, x, st));   // x += omega z
     TRY(axpby(n, -omega, t, 1.0, r, st));  // r = s - omega t
-    TRY(dots({{r, r}}));
-    rn = std::sqrt(h->bpin[0]);
+    TRY(dots(rh, 2, r));                   // <rh, r> for the next step, <r, r>
+    rn = std::sqrt(h->bpin[1]);
     rho = rho1;
+    rho1 = h->bpin[0];
     if (rn <= 1e-14 * bnorm) break;
     if (rn < 0.5 * best) {
       best = rn;
@@ -1153,9 +1151,14 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
       }
       h->cshift = 0.5 * (cmin + cmax);
       for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
-      for (int k = 0; k < 7; ++k) TRY(alloc_int(h, &h->bk[k], st));
+      {  // one block of seven interior vectors, TA(g) apart (the dot sweeps rely on it)
+        double* blk = nullptr;
+        TRY(alloc_t(h, &blk, 7 * TA(g)));
+        AHOC_HIP_TRY(hipMemsetAsync(blk, 0, sizeof(double) * 7 * (size_t)TA(g), st));  // zero padding
+        for (int k = 0; k < 7; ++k) h->bk[k] = blk + k * TA(g);
+      }
       TRY(alloc_t(h, &h->bdot, 8));
-      TRY(alloc_t(h, &h->bpart, (long long)h->nb_dot));
+      TRY(alloc_t(h, &h->bpart, 2LL * VS_DOT_BLOCKS));
       AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->bpin), sizeof(double) * 8, hipHostMallocDefault));
     } else if (pb->beta != 0.0) {
       // the v-equation -L_h V + (beta/alpha) M V = M f is solved by the sine transforms only

@@ -639,7 +639,8 @@ __global__ void k_resid_vol(Geom g, Weights w, const double* __restrict__ U, con
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
           const double wt = lw<DIM>(w, dx, dy, dz);
-          if (wt == 0.0) continue;
+          const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
+          if (wt == 0.0 && nzo > 1) continue;  // outside both stencils (M also reads nzo <= 1)
           const int qi = i + dx, qj = j + dy, qk = k + dz;
           const int nb = nbnd<DIM>(g, qi, qj, qk);
           double vq = 0, uq = 0;
@@ -652,7 +653,6 @@ __global__ void k_resid_vol(Geom g, Weights w, const double* __restrict__ U, con
           }
           lv += wt * vq;
           lu += wt * uq;
-          const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
           if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * vq * ia[nod(g, qi, qj, qk)];
         }
     rv[e] = (T)(src_v[e] + lv);
@@ -810,21 +810,40 @@ __global__ void k_vapply(Geom g, Weights w, const double* __restrict__ X, const 
       continue;
     }
     double lv = 0, mv = 0;
-    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
-    for (int dz = zlo; dz <= zhi; ++dz)
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const double wt = lw<DIM>(w, dx, dy, dz);
-          if (wt == 0.0) continue;
-          const int qi = i + dx, qj = j + dy, qk = k + dz;
-          const int nb = nbnd<DIM>(g, qi, qj, qk);
-          double vq = 0;
-          if (nb == 0) vq = X[inr(g, qi, qj, DIM == 3 ? qk : 1)];
-          else if (nb == 1 && Q) vq = Q[qidx<DIM>(g, qi, qj, qk)];
-          lv += wt * vq;
-          const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
-          if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * c[nod(g, qi, qj, qk)] * vq;
-        }
+    constexpr int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    const bool inner = i >= 2 && i < g.ni[0] && j >= 2 && j < g.ni[1] && (DIM == 2 || (k >= 2 && k < g.ni[2]));
+    if (inner) {
+      // every neighbour is an interior node: fixed offsets, no classification
+      const long long ip = (long long)g.ni[1] * g.px, np = (long long)g.nn[1] * g.nn[0];
+      const long long b0 = nod(g, i, j, k);
+#pragma unroll
+      for (int dz = zlo; dz <= zhi; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+          for (int dx = -1; dx <= 1; ++dx) {
+            const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
+            if (nzo == 3) continue;
+            const double vq = X[e + dz * ip + dy * g.px + dx];
+            lv += lw<DIM>(w, dx, dy, dz) * vq;
+            if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * c[b0 + dz * np + dy * g.nn[0] + dx] * vq;
+          }
+    } else {
+      for (int dz = zlo; dz <= zhi; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dx = -1; dx <= 1; ++dx) {
+            const double wt = lw<DIM>(w, dx, dy, dz);
+            const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
+            if (wt == 0.0 && nzo > 1) continue;  // outside both stencils
+            const int qi = i + dx, qj = j + dy, qk = k + dz;
+            const int nb = nbnd<DIM>(g, qi, qj, qk);
+            double vq = 0;
+            if (nb == 0) vq = X[inr(g, qi, qj, DIM == 3 ? qk : 1)];
+            else if (nb == 1 && Q) vq = Q[qidx<DIM>(g, qi, qj, qk)];
+            lv += wt * vq;
+            if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * c[nod(g, qi, qj, qk)] * vq;
+          }
+    }
     y[e] = mv - lv - (src ? src[e] : 0.0);
   }
 }

@@ -16,6 +16,8 @@ one by one, or properties that hold at any size:
 * The second and third workloads at their other sizes (2-D n = 256, 1024, 4096; 3-D n = 128,
   256): mixed vs FP64 within 1e-10.
 * The 512-instance batch: sampled instances against single solves.
+* The timing-table workloads of the paper at 1024^3 (Navier faces, inhomogeneous data):
+  FP64 against mixed at the paper's tolerance h^3.5, and against the exact solution.
 
 Tolerances: FP64 transforms 1e-12 relative to the largest output (as at small sizes; the
 naive sum is exact to ~1e-15); FP32 transforms 2e-5 (unit roundoff times the O(sqrt(N)
@@ -168,3 +170,30 @@ def test_batch_512_sampled_instances(ah):
             u1, *_ = s.solve()
         err = ((outs[i] - u1).abs().max() / u1.abs().max()).item()
         assert err <= 1e-10, (i, specs[i], err)
+
+
+@pytest.mark.parametrize("which", ["example2_q5_p1", "example3_k25_5_25"])
+def test_timing_table_workloads_1024(ah, which):
+    """The workloads of the paper's timing table at 1024^3 (classical biharmonic with the
+    solutions of Example 2 and of the oscillatory example; clamped at x = 0, Navier
+    elsewhere): FP64 and mixed to the paper's Schur tolerance h^3.5 agree within 1e-10
+    (max norm; max |u| is 0.02 and 1), and the FP64 error against the exact solution is the
+    fourth-order one: below 1/16 of the 512^3 error (1.26e-8 and 7.47e-8) times 1.25."""
+    dev = torch.device("cuda:0")
+    n = 1024
+    if which == "example2_q5_p1":
+        prob = W.example2(n, 5.0, 1.0, alpha="1", beta=0.0, xp="torch", device=dev, chunk=32)
+    else:
+        prob = W.example3(n, (25.0, 5.0, 25.0), alpha="1", beta=0.0, xp="torch", device=dev, chunk=32)
+    prob.v_exact = None
+    tol = (1.0 / n) ** 3.5
+    with ah.Solver(prob, precision=ah.FP64, tol=tol) as s:
+        u0, _, _, st0 = s.solve()
+    with ah.Solver(prob, precision=ah.MIXED, tol=tol) as s:
+        u1, _, _, st1 = s.solve()
+    assert st0.converged and st1.converged, (st0, st1)
+    err512 = {"example2_q5_p1": 1.257e-8, "example3_k25_5_25": 7.466e-8}[which]
+    assert (u1 - u0).abs().max().item() <= 1e-10
+    assert (u0 - prob.u_exact).abs().max().item() < 1.25 * err512 / 16
+    del u0, u1, prob
+    torch.cuda.empty_cache()
