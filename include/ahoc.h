@@ -72,8 +72,9 @@ typedef enum {
  *          Navier face, u = g_D and Delta u = g_L there instead of du/dn = g_N (the
  *          boundary conditions eq-bc on the Navier part of the boundary).  Then v = alpha
  *          g_L is known on that face, and its rows of the Schur system read
- *          alpha g_L - Q = 0.  Bits beyond the 2*dim faces: AHOC_E_INVALID.  A problem
- *          with Navier faces is set up alone (ahoc_solve_batched runs it by itself)
+ *          alpha g_L - Q = 0.  Bits beyond the 2*dim faces: AHOC_E_INVALID.
+ *          ahoc_solve_batched batches 2-D problems of equal grids and equal Navier faces
+ *          (beta = 0) together
  *   gL     nodal; on face-interior nodes of Navier faces the given Delta u (read there
  *          only)
  *   beta_nodal  nodal; when not NULL a variable beta (the constant `beta` is then

@@ -126,8 +126,8 @@ struct ahoc_handle {
   double* red = nullptr;     // reduction partials
   double* pinned = nullptr;  // host-pinned scalars (2 per instance, at least 8)
   int* pinned_i = nullptr;   // host-pinned ints (one per instance)
-  // batch: device table of per-instance pointers, [6][nb] (five input fields, then the
-  // outputs u), and its host image (kept alive while copies from it may be in flight)
+  // batch: device table of per-instance pointers, [7][nb] (five input fields, the outputs u,
+  // then the Navier data g_L;  // outputs u), and its host image (kept alive while copies from it may be in flight)
   void** ptab = nullptr;
   std::vector<void*> ptab_host;
   std::vector<void*> allocs;
@@ -1083,23 +1083,24 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   make_weights(g, h->w);
   h->wv = h->w;
   h->m = h->opt.restart;
-  const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD;
+  const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD, *gL = pb->gL;
   for (int i = 0; i < count; ++i)
-    if (pbs[i].navier && count > 1) {
-      set_last_error("a problem with Navier faces is set up alone", "ahoc_setup");
+    if (pbs[i].navier != pb->navier) {
+      set_last_error("the instances of a batch must share their Navier faces", "ahoc_setup");
       return ST_UNSUPPORTED;
     }
   h->navier = pb->navier;
   if (count > 1) {
-    double *a_, *f_, *gd_, *gn_, *lg_;
-    h->ptab_host.assign((size_t)6 * count, nullptr);
-    TRY(alloc_t(h, &h->ptab, 6LL * count));
+    double *a_, *f_, *gd_, *gn_, *lg_, *gl_ = nullptr;
+    h->ptab_host.assign((size_t)7 * count, nullptr);
+    TRY(alloc_t(h, &h->ptab, 7LL * count));
     TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, alpha), 0, &a_, st));
     TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, f), 1, &f_, st));
     TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gD), 2, &gd_, st));
     TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gN), 3, &gn_, st));
     TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, lapgD), 4, &lg_, st));
-    alpha = a_, f = f_, gD = gd_, gN = gn_, lapgD = lg_;
+    if (pb->navier) TRY(gather_field(h, pbs, count, offsetof(ahoc_problem, gL), 6, &gl_, st));
+    alpha = a_, f = f_, gD = gd_, gN = gn_, lapgD = lg_, gL = gl_;
   }
   // FP64 data
   TRY(alloc_t(h, &h->ia64, TN(g)));
@@ -1180,7 +1181,7 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   }
   TRY(setup_face_alpha(g, alpha, h->af64, af32, st));
   TRY(setup_sources(g, h->w, f, alpha, gD, gN, lapgD, h->src_v, h->src_u, h->src_q, st));
-  if (h->navier) TRY(setup_navier(g, h->navier, alpha, pb->gL, h->af64, af32, h->src_q, st));
+  if (h->navier) TRY(setup_navier(g, h->navier, alpha, gL, h->af64, af32, h->src_q, st));
   if (lapgD) {
     // V = alpha * Delta u on edges and corners (Remark 1); read there only
     TRY(alloc_t(h, &h->vedge, TN(g)));
@@ -1753,11 +1754,12 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
   std::vector<std::vector<int>> jobs;
   for (int i = 0; i < count; ++i) {
     const ahoc_problem& p = probs[i];
-    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.navier || p.beta_nodal) {  // beta or Navier faces: alone
+    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.beta_nodal) {  // beta: alone
       jobs.push_back({i});
       continue;
     }
-    buckets[{(double)p.n[0], (double)p.n[1], p.lo[0], p.lo[1], p.hi[0], p.hi[1]}].push_back(i);
+    // equal grids and equal Navier faces share a batch (and its preconditioner)
+    buckets[{(double)p.n[0], (double)p.n[1], p.lo[0], p.lo[1], p.hi[0], p.hi[1], (double)p.navier}].push_back(i);
   }
   const long long node_budget = 64LL << 20;
   for (auto& kv : buckets) {

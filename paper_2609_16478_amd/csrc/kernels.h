@@ -42,7 +42,8 @@ int vapply(const Geom& g, const Weights& w, const double* X, const double* Q, co
            double* y, hipStream_t st);
 // per-block min and max (part[2 b], part[2 b + 1]) of n doubles
 int minmax_partial(long long n, const double* x, double* part, int nblocks, hipStream_t st);
-// Navier faces of a single problem: af = 0 and src_q = -alpha g_L on their q-rows
+// Navier faces (the same on every instance of a batch): af = 0 and src_q = -alpha g_L on
+// their q-rows
 int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL, double* af64, float* af32,
                  double* src_q, hipStream_t st);
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,

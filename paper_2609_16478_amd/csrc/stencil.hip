@@ -879,6 +879,12 @@ __global__ void k_minmax(long long n, const double* __restrict__ x, double* __re
 template <int DIM>
 __global__ void k_navier(Geom g, int mask, const double* __restrict__ alpha, const double* __restrict__ gL,
                          double* __restrict__ af64, float* __restrict__ af32, double* __restrict__ src_q) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  alpha += b_ * g.nnodal;
+  if (gL) gL += b_ * g.nnodal;
+  af64 += b_ * g.nq;
+  if (af32) af32 += b_ * g.nq;
+  src_q += b_ * g.nq;
   for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
     int i, j, k, ax, st;
     dec_q<DIM>(g, q, i, j, k, ax, st);
@@ -1125,8 +1131,7 @@ int minmax_partial(long long n, const double* x, double* part, int nblocks, hipS
 
 int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL, double* af64, float* af32,
                  double* src_q, hipStream_t st) {
-  if (g.nb != 1) return ST_UNSUPPORTED;
-  LAUNCH_DIM(k_navier, dim3(nblocks(g.nq)), g, mask, alpha, gL, af64, af32, src_q);
+  LAUNCH_DIM(k_navier, dim3(nblocks(g.nq), g.nb), g, mask, alpha, gL, af64, af32, src_q);
   return ST_OK;
 }
 

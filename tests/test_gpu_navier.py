@@ -192,3 +192,29 @@ def test_example1_4096_mixed_vs_fp64(ah, eps):
         u1, _, _, st1 = s.solve()
     assert st0.converged and st1.converged, (st0, st1)
     assert ((u1 - u0).abs().max() / u0.abs().max()).item() <= 1e-10
+
+
+def _navier_batch():
+    a, b = (True, False, False, True), (False, True, True, True)
+    mk = lambda al, u, nav: W.manufactured(al, u, (32, 32), navier=nav)
+    return [mk("1 + 0.5*x*y", U2, a), mk("2 + x", "sin(pi*x)*sin(pi*y)**2", a), W.config2(32),
+            mk("1.5", U2, b), mk("1 + 0.3*sin(pi*x)", "exp(x - y)*sin(pi*y)", a), W.config2(32),
+            mk("1 + y", U2, b)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_navier_lockstep_batch(ah, prec):
+    """2-D problems of one grid and equal Navier faces run as one lock-step batch (here three
+    with faces x-, y+, two with x+, y-, y+, and two clamped ones): each instance equals its
+    single solve, and one equals the direct oracle."""
+    p = ah.FP64 if prec == "fp64" else ah.MIXED
+    probs = _navier_batch()
+    outs, stats, rc = ah.solve_batched(probs, precision=p, tol=1e-13 if prec == "fp64" else 1e-11)
+    assert rc == ah.OK
+    for pb, u, st in zip(probs, outs, stats):
+        assert st.converged, (pb.name, st)
+        with ah.Solver(pb, tol=1e-13) as s:
+            u1, *_ = s.solve()
+        assert _rel(u.cpu().numpy(), u1.cpu().numpy()) < (1e-12 if prec == "fp64" else 1e-10), pb.name
+    U, *_ = direct.solve(probs[0])
+    assert _rel(outs[0].cpu().numpy(), U) < (1e-12 if prec == "fp64" else 1e-10)
