@@ -473,25 +473,29 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
   for (int it = 0; it < 200; ++it) {
     if (rho1 == 0.0 || !std::isfinite(rho1)) break;
     const double beta = (rho1 / rho) * (alpha / omega);
-    TRY(axpby(n, -omega, v, 1.0, p, st));  // p = r + beta (p - omega v)
-    TRY(axpby(n, 1.0, r, beta, p, st));
+    TRY(lin3(n, 1.0, r, -beta * omega, v, beta, p, st));  // p = r + beta (p - omega v)
     TRY(precond(p, y));
     TRY(apply(y, v));
     TRY(dots(v, 1, rh));
     if (h->bpin[0] == 0.0 || !std::isfinite(h->bpin[0])) break;
     alpha = rho1 / h->bpin[0];
     TRY(axpby(n, -alpha, v, 1.0, r, st));  // s = r - alpha v, in r
-    TRY(axpby(n, alpha, y, 1.0, x, st));   // x += alpha y
     ++h->vs_iters;
     TRY(dots(r, 1, r));
     double rn = std::sqrt(h->bpin[0]);
-    if (rn <= 1e-14 * bnorm) break;
+    if (rn <= 1e-14 * bnorm) {
+      TRY(axpby(n, alpha, y, 1.0, x, st));  // x += alpha y
+      break;
+    }
     TRY(precond(r, z));
     TRY(apply(z, t));
     TRY(dots(r, 2, t));  // <s, t>, <t, t>
-    if (h->bpin[1] == 0.0 || !std::isfinite(h->bpin[0] / h->bpin[1])) break;
+    if (h->bpin[1] == 0.0 || !std::isfinite(h->bpin[0] / h->bpin[1])) {
+      TRY(axpby(n, alpha, y, 1.0, x, st));  // keep the half step
+      break;
+    }
     omega = h->bpin[0] / h->bpin[1];
-    TRY(axpby(n, omega, z, 1.0, x, st));   // x += omega z
+    TRY(lin3(n, alpha, y, omega, z, 1.0, x, st));  // x += alpha y + omega z
     TRY(axpby(n, -omega, t, 1.0, r, st));  // r = s - omega t
     TRY(dots(rh, 2, r));                   // <rh, r> for the next step, <r, r>
     rn = std::sqrt(h->bpin[1]);

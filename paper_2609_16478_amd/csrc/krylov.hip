@@ -115,6 +115,14 @@ __global__ void k_axpby(long long n, double a, const double* __restrict__ x, dou
     y[e] = b == 0.0 ? a * x[e] : a * x[e] + b * y[e];
 }
 
+// w = a x + b y + c w
+__global__ void k_lin3(long long n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
+                       double c, double* __restrict__ w) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    w[e] = a * x[e] + b * y[e] + c * w[e];
+}
+
 // w_s *= 1 / resid[s][1]; segments that are no longer active (or have a zero norm) get 0,
 // so a converged instance continues with zero basis vectors
 __global__ void k_scale_inv(double* __restrict__ w, long long n, const double* __restrict__ s,
@@ -226,6 +234,12 @@ int givens_step(int ns, double* H, int m, const double* h1, const double* h2, co
 
 int axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 65536)), dim3(TPB), 0, st, n, a, x, b, y);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int lin3(long long n, double a, const double* x, double b, const double* y, double c, double* w, hipStream_t st) {
+  hipLaunchKernelGGL(k_lin3, dim3(nblk(n, 65536)), dim3(TPB), 0, st, n, a, x, b, y, c, w);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
