@@ -38,6 +38,7 @@ int setup_inv_alpha(long long n, const double* alpha, double* ia64, float* ia32,
                     int nb, hipStream_t st);
 int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af32, hipStream_t st);
 // variable shift c (nodal): y = -L_h[V] + M(c V) - src on the interior of a single problem
+// (3-D with Q and src null: tiled, and y's row padding is left as it is)
 int vapply(const Geom& g, const Weights& w, const double* X, const double* Q, const double* c, const double* src,
            double* y, hipStream_t st);
 // per-block min and max (part[2 b], part[2 b + 1]) of n doubles

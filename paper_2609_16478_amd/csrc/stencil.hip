@@ -848,6 +848,131 @@ __global__ void k_vapply(Geom g, Weights w, const double* __restrict__ X, const 
   }
 }
 
+// The same operator on the nodes whose whole stencil is interior (2 <= i <= n_x'-1, likewise
+// j, k; 3-D, homogeneous: no Q, no src), tiled: a work-group owns VTX x VTY columns and
+// marches along z over VKC planes, with the planes k-1, k, k+1 of its columns and their halo
+// in LDS and c X of plane k beside them, so every value is read from memory about once per
+// plane instead of once per stencil point.
+constexpr int VTX = 64, VTY = 8, VKC = 32;
+__global__ void __launch_bounds__(VTX * VTY) k_vapply_tile(Geom g, Weights w, const double* __restrict__ X,
+                                                           const double* __restrict__ c, double* __restrict__ y) {
+  constexpr int HX = VTX + 2, HY = VTY + 2;
+  __shared__ double xs[3][HY][HX];
+  __shared__ double cs[HY][HX];
+  const int ni0 = g.ni[0], ni1 = g.ni[1], ni2 = g.ni[2];
+  const int nx = ni0 - 2, ny = ni1 - 2, nz = ni2 - 2;  // extents of the region
+  const int tx = (nx + VTX - 1) / VTX, ty = (ny + VTY - 1) / VTY, tz = (nz + VKC - 1) / VKC;
+  long long t = blockIdx.x;
+  if (t >= (long long)tx * ty * tz) return;
+  const int bx = (int)(t % tx);
+  t /= tx;
+  const int by = (int)(t % ty), bz = (int)(t / ty);
+  const int lx = threadIdx.x % VTX, ly = threadIdx.x / VTX;
+  const int ib = 2 + bx * VTX, jb = 2 + by * VTY;  // first column of the tile
+  const int i = ib + lx, j = jb + ly;
+  const bool mine = i <= ni0 - 1 && j <= ni1 - 1;
+  const int k0 = 2 + bz * VKC, k1 = min(ni2 - 1, k0 + VKC - 1);
+  const long long npl = (long long)g.nn[1] * g.nn[0];
+  // halo position (hx, hy) -> node (ib - 1 + hx, jb - 1 + hy), clamped into the interior
+  // (clamped positions feed only columns outside the region, whose outputs are not written)
+  auto hnode = [&](int h, int& gi, int& gj) {
+    gi = min(ib - 1 + h % HX, ni0);
+    gj = min(jb - 1 + h / HX, ni1);
+  };
+  auto load_plane = [&](int kk, int slot) {
+    for (int h = threadIdx.x; h < HX * HY; h += VTX * VTY) {
+      int gi, gj;
+      hnode(h, gi, gj);
+      xs[slot][h / HX][h % HX] = X[((long long)(kk - 1) * ni1 + (gj - 1)) * g.px + (gi - 1)];
+    }
+  };
+  int s0 = 0, s1 = 1, s2 = 2;  // slots of planes k-1, k, k+1
+  load_plane(k0 - 1, s0);
+  load_plane(k0, s1);
+  load_plane(k0 + 1, s2);
+  for (int k = k0; k <= k1; ++k) {
+    __syncthreads();  // planes loaded; the previous plane's cs no longer read
+    for (int h = threadIdx.x; h < HX * HY; h += VTX * VTY) {
+      int gi, gj;
+      hnode(h, gi, gj);
+      cs[h / HX][h % HX] = c[((long long)k * g.nn[1] + gj) * g.nn[0] + gi] * xs[s1][h / HX][h % HX];
+    }
+    __syncthreads();
+    if (mine) {
+      const int hx = lx + 1, hy = ly + 1;
+      const double (*pm)[HX] = xs[s0];
+      const double (*pc)[HX] = xs[s1];
+      const double (*pp)[HX] = xs[s2];
+      double lv = w.c0 * pc[hy][hx];
+      lv += w.cf[0] * (pc[hy][hx - 1] + pc[hy][hx + 1]);
+      lv += w.cf[1] * (pc[hy - 1][hx] + pc[hy + 1][hx]);
+      lv += w.cf[2] * (pm[hy][hx] + pp[hy][hx]);
+      lv += w.ce[0] * (pc[hy - 1][hx - 1] + pc[hy - 1][hx + 1] + pc[hy + 1][hx - 1] + pc[hy + 1][hx + 1]);
+      lv += w.ce[1] * (pm[hy][hx - 1] + pm[hy][hx + 1] + pp[hy][hx - 1] + pp[hy][hx + 1]);
+      lv += w.ce[2] * (pm[hy - 1][hx] + pm[hy + 1][hx] + pp[hy - 1][hx] + pp[hy + 1][hx]);
+      const long long b0 = ((long long)k * g.nn[1] + j) * g.nn[0] + i;
+      double mv = w.m0 * cs[hy][hx] + w.m1 * (cs[hy][hx - 1] + cs[hy][hx + 1] + cs[hy - 1][hx] + cs[hy + 1][hx]);
+      mv += w.m1 * (c[b0 - npl] * pm[hy][hx] + c[b0 + npl] * pp[hy][hx]);
+      y[((long long)(k - 1) * ni1 + (j - 1)) * g.px + (i - 1)] = mv - lv;
+    }
+    if (k < k1) {
+      __syncthreads();  // slot s0 (plane k-1) no longer read
+      load_plane(k + 2, s0);
+      const int tmp = s0;
+      s0 = s1;
+      s1 = s2;
+      s2 = tmp;
+    }
+  }
+}
+
+// The nodes of the layer next to the boundary that k_vapply_tile leaves out (3-D,
+// homogeneous), one thread each: the full rows of the planes k = 1, n_z' and of the rows
+// j = 1, n_y' in between (padding columns skipped: they stay zero), then the nodes i = 1
+// and i = n_x' of every other row.
+__global__ void k_vapply_shell(Geom g, Weights w, const double* __restrict__ X, const double* __restrict__ c,
+                               double* __restrict__ y) {
+  const int ni0 = g.ni[0], ni1 = g.ni[1], ni2 = g.ni[2];
+  const long long full_rows = 2LL * ni1 + 2LL * (ni2 - 2);
+  const long long nfull = full_rows * ni0, nside = 2LL * (ni1 - 2) * (ni2 - 2);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nfull + nside;
+       e += (long long)gridDim.x * blockDim.x) {
+    int i, j, k;
+    if (e < nfull) {
+      const long long r = e / ni0;
+      i = (int)(e - r * ni0) + 1;
+      if (r < 2LL * ni1) {  // planes k = 1 and k = n_z'
+        k = r < ni1 ? 1 : ni2;
+        j = (int)(r % ni1) + 1;
+      } else {              // rows j = 1 and j = n_y' of the planes between
+        const long long q = r - 2LL * ni1;
+        k = (int)(q / 2) + 2;
+        j = (q & 1) ? ni1 : 1;
+      }
+    } else {
+      const long long q = e - nfull;
+      const long long rr = q / 2;  // row (j, k) with j in [2, n_y'-1], k in [2, n_z'-1]
+      i = (q & 1) ? ni0 : 1;
+      j = (int)(rr % (ni1 - 2)) + 2;
+      k = (int)(rr / (ni1 - 2)) + 2;
+    }
+    double lv = 0, mv = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wt = lw<3>(w, dx, dy, dz);
+          const int nzo = (dx != 0) + (dy != 0) + (dz != 0);
+          if (wt == 0.0 && nzo > 1) continue;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          if (nbnd<3>(g, qi, qj, qk) != 0) continue;  // homogeneous: boundary values are zero
+          const double vq = X[inr(g, qi, qj, qk)];
+          lv += wt * vq;
+          if (nzo <= 1) mv += (nzo == 0 ? w.m0 : w.m1) * c[nod(g, qi, qj, qk)] * vq;
+        }
+    y[inr(g, i, j, k)] = mv - lv;
+  }
+}
+
 // per-block minimum and maximum of x: part[2 b] = min, part[2 b + 1] = max
 __global__ void k_minmax(long long n, const double* __restrict__ x, double* __restrict__ part) {
   __shared__ double rmin[TPB], rmax[TPB];
@@ -1119,6 +1244,18 @@ int setup_face_alpha(const Geom& g, const double* alpha, double* af64, float* af
 int vapply(const Geom& g, const Weights& w, const double* X, const double* Q, const double* c, const double* src,
            double* y, hipStream_t st) {
   if (g.nb != 1) return ST_UNSUPPORTED;
+  if (g.dim == 3 && !Q && !src) {
+    // interior nodes tiled, then the layer next to the boundary (the row padding of y is
+    // never written: the callers' output arrays keep it zero)
+    const long long tiles = (long long)((g.ni[0] - 2 + VTX - 1) / VTX) * ((g.ni[1] - 2 + VTY - 1) / VTY) *
+                            ((g.ni[2] - 2 + VKC - 1) / VKC);
+    hipLaunchKernelGGL(k_vapply_tile, dim3((unsigned)tiles), dim3(VTX * VTY), 0, st, g, w, X, c, y);
+    AHOC_HIP_TRY(hipGetLastError());
+    const long long shell = (2LL * g.ni[1] + 2LL * (g.ni[2] - 2)) * g.ni[0] + 2LL * (g.ni[1] - 2) * (g.ni[2] - 2);
+    hipLaunchKernelGGL(k_vapply_shell, dim3(nblocks(shell)), dim3(TPB), 0, st, g, w, X, c, y);
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
+  }
   LAUNCH_DIM(k_vapply, dim3(interior_rows(g)), g, w, X, Q, c, src, y);
   return ST_OK;
 }
