@@ -452,6 +452,14 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
     AHOC_HIP_TRY(hipStreamSynchronize(st));
     return ST_OK;
   };
+  // y += a x and the reduced <u, y>, <y, y> into bpin[0], bpin[1] (synchronising)
+  auto update_dots = [&](double a, const double* xv, double* yv, const double* u) -> int {
+    TRY(axpy_dot2(n, a, xv, yv, u, h->bpart, nbk, st));
+    TRY(mdot_reduce(h->bpart, nbk, 2, 1, h->bdot, 2, 0, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(h->bpin, h->bdot, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
+    return ST_OK;
+  };
   auto apply = [&](const double* in, double* out) { return vapply(g, h->w, in, nullptr, h->cnod, nullptr, out, st); };
   auto precond = [&](const double* in, double* out) { return poisson<double>(h, P, out, P.scV, st, in); };
   hipEvent_t e = tbegin(h, st);
@@ -479,10 +487,9 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
     TRY(dots(v, 1, rh));
     if (h->bpin[0] == 0.0 || !std::isfinite(h->bpin[0])) break;
     alpha = rho1 / h->bpin[0];
-    TRY(axpby(n, -alpha, v, 1.0, r, st));  // s = r - alpha v, in r
+    TRY(update_dots(-alpha, v, r, nullptr));  // s = r - alpha v, in r; <s, s>
     ++h->vs_iters;
-    TRY(dots(r, 1, r));
-    double rn = std::sqrt(h->bpin[0]);
+    double rn = std::sqrt(h->bpin[1]);
     if (rn <= 1e-14 * bnorm) {
       TRY(axpby(n, alpha, y, 1.0, x, st));  // x += alpha y
       break;
@@ -496,8 +503,7 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
     }
     omega = h->bpin[0] / h->bpin[1];
     TRY(lin3(n, alpha, y, omega, z, 1.0, x, st));  // x += alpha y + omega z
-    TRY(axpby(n, -omega, t, 1.0, r, st));  // r = s - omega t
-    TRY(dots(rh, 2, r));                   // <rh, r> for the next step, <r, r>
+    TRY(update_dots(-omega, t, r, rh));  // r = s - omega t; <rh, r> for the next step, <r, r>
     rn = std::sqrt(h->bpin[1]);
     rho = rho1;
     rho1 = h->bpin[0];

@@ -74,6 +74,10 @@ int maxpy(double* w, const double* V, long long ld, int nvec, const double* coef
 int givens_step(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2, double* cs,
                 double* sn, double* gv, int j, double* resid, hipStream_t st);
 int axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st);
+// y += a x with the per-work-group partial sums of <u, y> (u null: 0) and <y, y>, in part[0..nbk)
+// and part[nbk..2 nbk) (reduce with mdot_reduce, nvec 2)
+int axpy_dot2(long long n, double a, const double* x, double* y, const double* u, double* part, int nbk,
+              hipStream_t st);
 // w = a x + b y + c w
 int lin3(long long n, double a, const double* x, double b, const double* y, double c, double* w, hipStream_t st);
 int scale_by_inv(double* w, long long n, int ns, const double* s, const int* act, hipStream_t st);

@@ -115,6 +115,27 @@ __global__ void k_axpby(long long n, double a, const double* __restrict__ x, dou
     y[e] = b == 0.0 ? a * x[e] : a * x[e] + b * y[e];
 }
 
+// y += a x, with the partial sums of <u, y> (u may be null: 0) and <y, y> of the updated y:
+// part[b] and part[gridDim.x + b] for work-group b
+__global__ void k_axpy_dot2(long long n, double a, const double* __restrict__ x, double* __restrict__ y,
+                            const double* __restrict__ u, double* __restrict__ part) {
+  __shared__ double red[TPB];
+  double su = 0, sy = 0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double v = y[e] + a * x[e];
+    y[e] = v;
+    if (u) su += u[e] * v;
+    sy += v * v;
+  }
+  const double r0 = block_sum(su, red);
+  const double r1 = block_sum(sy, red);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = r0;
+    part[gridDim.x + blockIdx.x] = r1;
+  }
+}
+
 // w = a x + b y + c w
 __global__ void k_lin3(long long n, double a, const double* __restrict__ x, double b, const double* __restrict__ y,
                        double c, double* __restrict__ w) {
@@ -234,6 +255,13 @@ int givens_step(int ns, double* H, int m, const double* h1, const double* h2, co
 
 int axpby(long long n, double a, const double* x, double b, double* y, hipStream_t st) {
   hipLaunchKernelGGL(k_axpby, dim3(nblk(n, 65536)), dim3(TPB), 0, st, n, a, x, b, y);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int axpy_dot2(long long n, double a, const double* x, double* y, const double* u, double* part, int nbk,
+              hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy_dot2, dim3(nbk), dim3(TPB), 0, st, n, a, x, y, u, part);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
