@@ -209,3 +209,24 @@ def test_example2_fourth_order_small():
 def test_fast_tier_rejects_variable_beta():
     with pytest.raises(ValueError):
         fast.FastTier(W.manufactured("1", "sin(pi*x)**2*sin(pi*y)**2", (8, 8), beta="1 + x"))
+
+
+def test_stored_oracle_solutions_against_the_paper():
+    """The oracle's stored large-size solutions (written by the committed scripts in
+    tests/golden/) against what the paper prints: Tables 2 and 3 at 32^3 within 0.5 % (the
+    paper's own GMRES tolerance, proportional to h^3.5, is loosest there), and the 4096^2
+    solutions of Example 1 falling from Table 1's 2048^2 values at fourth order (ratios
+    13-17; the printed 4096 entries are not used, see the design notes)."""
+    g = os.path.join(os.path.dirname(__file__), "golden")
+    ex1 = json.load(open(os.path.join(g, "example1_oracle.json")))
+    ex2 = json.load(open(os.path.join(g, "example2_oracle.json")))
+    ex3 = json.load(open(os.path.join(g, "example3_oracle.json")))
+    t2 = GOLD["example2_table2"]["err_u_inf"]
+    for key, case in ex2["cases"].items():
+        assert abs(case["err_u_inf"] - t2[key]["32"]) <= 5e-3 * t2[key]["32"], key
+    t3 = GOLD["example3_table3"]["err_u_inf"]
+    for key, case in ex3["cases"].items():
+        assert abs(case["err_u_inf"] - t3[key]["32"]) <= 5e-3 * t3[key]["32"], key
+    t1 = GOLD["example1_table1"]["err_u_inf"]
+    for eps, case in ex1["eps"].items():
+        assert 13.0 < t1[eps]["2048"] / case["err_u_inf"] < 17.0, eps
