@@ -186,6 +186,9 @@ def main():
                          "and three with the matrix-core products")
     ap.add_argument("--no-instance-loop", action="store_true",
                     help="skip the per-instance FP64 loop over the batched workload")
+    ap.add_argument("--batch-profile", type=int, default=0,
+                    help="profiling target: set up the 512-instance 2-D batch and run this many mixed "
+                         "batched solves after a warm-up, then exit (no JSON line)")
     ap.add_argument("--varbeta", type=int, default=0,
                     help="separate target: one FP64 solve of Example 2 with its variable alpha and beta "
                          "((q, p) = (5, 1), the workload of Table 2) at this n^3, tolerance 1e-12, with the "
@@ -240,6 +243,18 @@ def main():
         return
     if args.varbeta:
         print(json.dumps(_varbeta(ah, W, torch, dev, args.varbeta)))
+        return
+    if args.batch_profile:
+        specs = W.config4_specs(args.batch_count)
+        bprobs = [W.config4_instance(sp, xp="torch", device=dev, with_exact=False) for sp in specs]
+        ah.solve_batched(bprobs, precision=ah.MIXED, tol=args.tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.batch_profile):
+            ah.solve_batched(bprobs, precision=ah.MIXED, tol=args.tol)
+        torch.cuda.synchronize()
+        print(f"[bench] {args.batch_profile} mixed batched solves: "
+              f"{(time.perf_counter() - t) / args.batch_profile * 1e3:.1f} ms each", file=sys.stderr)
         return
     n = args.n
     t0 = time.perf_counter()
