@@ -27,7 +27,12 @@
  *     setup returns.
  *   - `stream` is a hipStream_t (NULL = the default stream).  ahoc_setup,
  *     ahoc_solve and ahoc_solve_batched return after the work has completed;
- *     ahoc_schur_apply, ahoc_poisson and ahoc_dst1 are asynchronous on the stream.
+ *     ahoc_schur_apply, ahoc_precond_apply, ahoc_schur_rhs, ahoc_poisson and ahoc_dst1
+ *     are asynchronous on the stream.  No entry point synchronises the whole device:
+ *     waits are on the call's stream, or (ahoc_destroy, ahoc_profile,
+ *     ahoc_kernel_times) on events recorded after the handle's own work.
+ *   - Device memory of a handle comes from the caller's ahoc_allocator when one is
+ *     given (e.g. a framework's caching allocator), else from hipMalloc.
  *   - Errors are reported by return code only; ahoc_last_error() gives text.
  *   - A handle is not thread-safe; distinct handles are independent.
  */
@@ -46,7 +51,8 @@ typedef enum {
   AHOC_E_NOMEM = -2,       /* device allocation failed                           */
   AHOC_E_NOCONV = -3,      /* tolerance not reached; outputs hold the last iterate */
   AHOC_E_HIP = -4,         /* a HIP runtime call failed                          */
-  AHOC_E_UNSUPPORTED = -5  /* grid size without a transform plan (n must be 2^a or 3*2^a, 8..8192) */
+  AHOC_E_UNSUPPORTED = -5  /* an option or problem combination this build does not solve
+                              (see ahoc_problem, ahoc_options)                     */
 } ahoc_status;
 
 typedef enum {
@@ -84,7 +90,10 @@ typedef enum {
  *          FP64 precision only (AHOC_MIXED: AHOC_E_UNSUPPORTED); set up alone */
 typedef struct {
   int dim;       /* 2 or 3 */
-  int n[3];      /* intervals per axis, n[a] >= 8 (unused axis ignored) */
+  int n[3];      /* intervals per axis, 4 <= n[a] <= 8192 (unused axis ignored); the
+                    one-sided normal formula of Sec. 2.2 reads U_1..U_3, so n[a] >= 4.
+                    Lengths with radix-2/3 factors use the FFT passes, any other length
+                    a direct sine-sum pass (O(n) work per output)                 */
   double lo[3];
   double hi[3];
   const double* alpha;
@@ -125,6 +134,13 @@ typedef struct {
                          legacy default stream: there the launches stay eager).  Ignored
                          while ahoc_profile is on and with a variable beta (its V-solve
                          synchronises on dot products).  0 (default): eager launches   */
+  int warm_start;     /* 1: the q argument of ahoc_solve holds an initial guess Q_0 on entry
+                         (Sec. 4.1 starts GMRES from the interpolated coarse-grid solution);
+                         GMRES (FP64) or the Schur refinement (MIXED, refine = 1) starts
+                         from it, and the first residual b - S_h Q_0 costs one Schur matvec.
+                         0 (default): Q_0 = 0 and q is output only.  MIXED with refine = 0:
+                         AHOC_E_UNSUPPORTED.  Ignored by ahoc_solve_batched             */
+  int vsolve_max_iters; /* variable beta: BiCGSTAB iteration cap of each V-solve (0 = 200) */
 } ahoc_options;
 
 typedef struct {
@@ -143,7 +159,23 @@ typedef struct {
                             matrix-core pass (see ahoc_dst_choice)       */
   int vsolve_iters;      /* variable beta: BiCGSTAB iterations over all V-solves
                             (0 otherwise)                                  */
+  double vsolve_relres;  /* variable beta: the largest final relative residual
+                            ||r|| / ||rhs|| of any V-solve of the call (0 otherwise).
+                            Above 1e-10 the Schur operator was applied inexactly and the
+                            call returns AHOC_E_NOCONV with converged = 0  */
 } ahoc_stats;
+
+/* Device memory provider.  alloc returns `bytes` bytes of device memory of the current
+ * device, at least 256-byte aligned, or NULL on failure (then the call returns
+ * AHOC_E_NOMEM); free releases a pointer alloc returned.  The library frees only memory
+ * whose work has completed (ahoc_destroy waits for the handle's last work first).  The
+ * callbacks may run concurrently on the worker threads of ahoc_solve_batched and must be
+ * thread-safe.  ctx is passed through unchanged. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free)(void* ptr, void* ctx);
+  void* ctx;
+} ahoc_allocator;
 
 typedef struct ahoc_handle ahoc_handle;
 
@@ -151,12 +183,14 @@ typedef struct ahoc_handle ahoc_handle;
 void ahoc_default_options(ahoc_options* opt);
 
 /* Validate the problem, derive 1/alpha, M f, the boundary data lifts and the
- * transform tables, allocate the workspace (hipMalloc).  Returns
- * AHOC_E_INVALID for dim not in {2,3}, n[a] < 8, NULL alpha/f or min alpha <= 0,
- * AHOC_E_UNSUPPORTED if a transform length has no plan.  *out is set only on
- * success; release it with ahoc_destroy. */
-ahoc_status ahoc_setup(const ahoc_problem* prob, const ahoc_options* opt, void* stream,
-                       ahoc_handle** out);
+ * transform tables, allocate the workspace (through `alloc`, or hipMalloc when it is
+ * NULL; the handle keeps the allocator and releases through it).  Returns
+ * AHOC_E_INVALID for dim not in {2,3}, n[a] outside [4, 8192], hi <= lo, NULL alpha/f or
+ * min alpha <= 0, AHOC_E_NOMEM when an allocation fails, AHOC_E_UNSUPPORTED for an
+ * option/problem combination listed as such.  *out is set only on success; release it
+ * with ahoc_destroy. */
+ahoc_status ahoc_setup(const ahoc_problem* prob, const ahoc_options* opt, const ahoc_allocator* alloc,
+                       void* stream, ahoc_handle** out);
 
 /* Number of augmented unknowns N_q of the handle's grid. */
 size_t ahoc_nq(const ahoc_handle* h);
@@ -173,21 +207,28 @@ ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* s
  * stream; AHOC_E_INVALID if the handle was set up with precond = 0. */
 ahoc_status ahoc_precond_apply(ahoc_handle* h, const double* q, double* y, void* stream);
 
-/* Right-hand side b = -R(0) of the Schur system (Algorithm 1, ConstructSchurRHS), FP64, length N_q. */
+/* Right-hand side b = -R(0) of the Schur system (Algorithm 1, ConstructSchurRHS), FP64, length N_q.
+ * It is the right-hand side the handle's solve uses: formed with the FP64 operator, except
+ * for MIXED with refine = 0, whose first sweep forms it with the FP32 operator. */
 ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream);
 
 /* Solve.  u (nodal, required) receives U; v (nodal or NULL) receives V = alpha Delta u
  * (interior V, Q on face interiors, alpha*lapgD on edges/corners); q (length N_q or
- * NULL) receives Q.  stats may be NULL.  Returns AHOC_E_NOCONV (outputs still
- * written) when the tolerance is not met. */
+ * NULL) receives Q (and holds the initial guess on entry with options.warm_start = 1).
+ * stats may be NULL.  Returns AHOC_E_NOCONV when the tolerance is not met -- the
+ * iteration cap, an FP32 stall, or a non-finite right-hand side or residual (NaN or Inf
+ * in the data) -- with converged = 0 and the outputs holding the last iterate: Q as
+ * GMRES left it and U, V recovered from that Q. */
 ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_stats* stats,
                        void* stream);
 
 /* Solve `count` independent problems (sizes and coefficients may differ) with
- * shared options.  u is a HOST array of `count` device pointers; stats a host
- * array of `count` entries (or NULL).  Returns the first non-OK status. */
+ * shared options and allocator (NULL = hipMalloc).  u is a HOST array of `count` device
+ * pointers; stats a host array of `count` entries (or NULL).  Returns the first non-OK
+ * status. */
 ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_options* opt,
-                               double* const* u, ahoc_stats* stats, void* stream);
+                               const ahoc_allocator* alloc, double* const* u, ahoc_stats* stats,
+                               void* stream);
 
 /* Dirichlet solve with the compact operator on the handle's interior grid:
  * w = L_int^{-1} g (homogeneous boundary), g and w interior arrays of FP64
@@ -280,15 +321,19 @@ enum {
 };
 
 /* Enable (1) or disable (0) per-kernel-class timing of the handle's solves with
- * HIP events recorded on the solve stream around each launch; resets the totals. */
+ * HIP events recorded on the solve stream around each launch; resets the totals (waits
+ * for the handle's pending timing events, not for the device). */
 ahoc_status ahoc_profile(ahoc_handle* h, int enable);
 
 /* Accumulated time (ms) and launch count of one kernel class since ahoc_profile,
  * and the algorithmic bytes one launch moves on average (what the operation must
- * read and write at least once).  Synchronises the device.  Any output may be NULL. */
+ * read and write at least once).  Waits for the handle's pending timing events.  Any
+ * output may be NULL. */
 ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long long* launches,
                               double* bytes_per_launch);
 
+/* Release a handle: waits for the work it enqueued (an event recorded after its last
+ * call, not a device-wide synchronisation), then frees its memory through its allocator. */
 void ahoc_destroy(ahoc_handle* h);
 
 const char* ahoc_status_string(ahoc_status s);

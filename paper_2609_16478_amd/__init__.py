@@ -40,18 +40,57 @@ class _Options(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("tol", c_double),
                 ("inner_tol", c_double), ("sweep_tol", c_double), ("max_sweeps", c_int),
                 ("tile_fp64", c_int), ("tile_fp32", c_int), ("precond", c_int),
-                ("refine", c_int), ("use_graph", c_int)]
+                ("refine", c_int), ("use_graph", c_int), ("warm_start", c_int), ("vsolve_max_iters", c_int)]
 
 
 class _Stats(ctypes.Structure):
     _fields_ = [("converged", c_int), ("gmres_iters", c_int), ("sweeps", c_int), ("matvecs", c_int),
                 ("schur_relres", c_double), ("last_update", c_double), ("t_solve_ms", c_double),
-                ("graph_steps", c_int), ("dst_gemm", c_int), ("vsolve_iters", c_int)]
+                ("graph_steps", c_int), ("dst_gemm", c_int), ("vsolve_iters", c_int),
+                ("vsolve_relres", c_double)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
+class _Allocator(ctypes.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", c_void_p)]
+
+
+def _torch_alloc(nbytes, ctx):
+    """ahoc_allocator.alloc backed by PyTorch's caching allocator; ctx = device index + 1.
+    Returns NULL (-> AHOC_E_NOMEM) instead of raising."""
+    try:
+        torch = _torch()
+        dev = int(ctx or 1) - 1
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=dev)
+    except Exception:  # out of memory or no device: the library reports AHOC_E_NOMEM
+        return None
+
+
+def _torch_free(ptr, ctx):
+    try:
+        if ptr:
+            _torch().cuda.caching_allocator_delete(int(ptr))
+    except Exception:
+        pass
+
+
+# the callbacks live as long as the module (handles keep the function pointers)
+_TORCH_ALLOC = _ALLOC_FN(_torch_alloc)
+_TORCH_FREE = _FREE_FN(_torch_free)
+
+
+def torch_allocator(device=0):
+    """An ahoc_allocator that takes device memory from PyTorch's caching allocator."""
+    return _Allocator(_TORCH_ALLOC, _TORCH_FREE, c_void_p(int(device) + 1))
 
 
 _H = c_void_p
 _lib.ahoc_default_options.argtypes = [ctypes.POINTER(_Options)]
-_lib.ahoc_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), c_void_p, ctypes.POINTER(_H)]
+_lib.ahoc_setup.argtypes = [ctypes.POINTER(_Problem), ctypes.POINTER(_Options), ctypes.POINTER(_Allocator), c_void_p,
+                            ctypes.POINTER(_H)]
 _lib.ahoc_setup.restype = c_int
 _lib.ahoc_nq.argtypes = [_H]
 _lib.ahoc_nq.restype = c_size_t
@@ -64,7 +103,8 @@ _lib.ahoc_schur_rhs.restype = c_int
 _lib.ahoc_solve.argtypes = [_H, c_void_p, c_void_p, c_void_p, ctypes.POINTER(_Stats), c_void_p]
 _lib.ahoc_solve.restype = c_int
 _lib.ahoc_solve_batched.argtypes = [c_int, ctypes.POINTER(_Problem), ctypes.POINTER(_Options),
-                                    ctypes.POINTER(c_void_p), ctypes.POINTER(_Stats), c_void_p]
+                                    ctypes.POINTER(_Allocator), ctypes.POINTER(c_void_p), ctypes.POINTER(_Stats),
+                                    c_void_p]
 _lib.ahoc_solve_batched.restype = c_int
 _lib.ahoc_poisson.argtypes = [_H, c_void_p, c_void_p, c_void_p]
 _lib.ahoc_poisson.restype = c_int
@@ -156,11 +196,26 @@ class Stats:
     graph_steps: int = 0
     dst_gemm: int = 0
     vsolve_iters: int = 0
+    vsolve_relres: float = 0.0
 
 
 def _stats(s: _Stats) -> Stats:
     return Stats(bool(s.converged), s.gmres_iters, s.sweeps, s.matvecs, s.schur_relres,
-                 s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm, s.vsolve_iters)
+                 s.last_update, s.t_solve_ms, s.graph_steps, s.dst_gemm, s.vsolve_iters,
+                 s.vsolve_relres)
+
+
+def _allocator_arg(allocator, device):
+    """'torch' (default): PyTorch's caching allocator; None: the library's hipMalloc;
+    or an _Allocator."""
+    if allocator is None:
+        return None
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError(f"unknown allocator {allocator!r}")
+        idx = device.index if getattr(device, "index", None) is not None else 0
+        return ctypes.byref(torch_allocator(idx))
+    return ctypes.byref(allocator)
 
 
 _FIELDS = ("alpha", "f", "gD", "gN", "lapgD", "gL")
@@ -205,9 +260,12 @@ class Solver:
     order z, y, x) and optionally beta (a constant, or a nodal array: FP64 only) and Navier
     faces (navier: per-face flags or a bitmask, gL: nodal Delta u read on them), e.g. a
     workloads.Problem.
+
+    allocator: "torch" (default) takes the handle's device memory from PyTorch's caching
+    allocator (ahoc_allocator callbacks); None lets the library call hipMalloc.
     """
 
-    def __init__(self, problem, precision=FP64, device="cuda:0", **opts):
+    def __init__(self, problem, precision=FP64, device="cuda:0", allocator="torch", **opts):
         torch = _torch()
         self.device = torch.device(device)
         self.n = tuple(problem.n)
@@ -217,8 +275,9 @@ class Solver:
         self.options = default_options(precision, **opts)
         h = _H()
         with torch.cuda.device(self.device):
-            _check(_lib.ahoc_setup(ctypes.byref(self._p), ctypes.byref(self.options), _stream(),
-                                   ctypes.byref(h)), "ahoc_setup")
+            _check(_lib.ahoc_setup(ctypes.byref(self._p), ctypes.byref(self.options),
+                                   _allocator_arg(allocator, self.device), _stream(), ctypes.byref(h)),
+                   "ahoc_setup")
         self._h = h
         self.nq = int(_lib.ahoc_nq(h))
         self.nodal_shape = tuple(m + 1 for m in reversed(self.n))
@@ -298,20 +357,29 @@ class Solver:
             out[name] = (ms.value, cnt.value, by.value)
         return out
 
-    def solve(self, want_v=False, want_q=False, out=None):
+    def solve(self, want_v=False, want_q=False, out=None, q0=None):
+        """Solve; q0 (length N_q) is the GMRES initial guess -- the handle must have been
+        set up with warm_start=1.  Returns (u, v or None, q or None, Stats); q is returned
+        when want_q or q0 is given."""
         torch = _torch()
         u = out if out is not None else torch.empty(self.nodal_shape, dtype=torch.float64,
                                                     device=self.device)
         v = torch.empty(self.nodal_shape, dtype=torch.float64, device=self.device) if want_v else None
-        q = torch.empty(self.nq, dtype=torch.float64, device=self.device) if want_q else None
+        if q0 is not None:
+            if not self.options.warm_start:
+                raise ValueError("q0 needs a handle set up with warm_start=1")
+            q = self._vec(q0, self.nq).clone()
+        else:
+            q = torch.empty(self.nq, dtype=torch.float64, device=self.device) if want_q else None
         s = _Stats()
         rc = _lib.ahoc_solve(self._h, _ptr(u), _ptr(v), _ptr(q), ctypes.byref(s), _stream())
         if rc not in (OK, E_NOCONV):
             _check(rc, "ahoc_solve")
+        self.status = rc  # OK or E_NOCONV (outputs hold the last iterate)
         return u, v, q, _stats(s)
 
 
-def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
+def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", allocator="torch", **opts):
     """Solve independent problems with shared options; returns (list of u, list of Stats, status).
 
     An instance that is rejected (E_INVALID, E_UNSUPPORTED) or does not converge does not
@@ -330,7 +398,7 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", **opts):
     uarr = (c_void_p * cnt)(*[o.data_ptr() for o in outs])
     sarr = (_Stats * cnt)()
     o = default_options(precision, **opts)
-    rc = _lib.ahoc_solve_batched(cnt, parr, ctypes.byref(o), uarr, sarr, _stream())
+    rc = _lib.ahoc_solve_batched(cnt, parr, ctypes.byref(o), _allocator_arg(allocator, dev), uarr, sarr, _stream())
     if rc not in (OK, E_NOCONV, E_INVALID, E_UNSUPPORTED):
         _check(rc, "ahoc_solve_batched")
     return outs, [_stats(s) for s in sarr], rc

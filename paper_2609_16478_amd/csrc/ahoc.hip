@@ -68,6 +68,11 @@ template <typename T> struct Prec {
 using namespace ahoc;
 
 struct ahoc_handle {
+  ahoc::DevAlloc al;   // device memory provider (the caller's allocator or hipMalloc)
+  // recorded on the call's stream after the work of every asynchronous entry point, so
+  // ahoc_destroy waits for the handle's own work only
+  hipEvent_t done_ev = nullptr;
+  bool done_rec = false;
   Geom g;
   Weights w;
   Weights wv;          // the v-equation's lift weights (normal weight shifted by -c m1)
@@ -82,6 +87,7 @@ struct ahoc_handle {
   double* bpart = nullptr;   // their partial sums
   double* bpin = nullptr;    // host-pinned copies
   long long vs_iters = 0;    // BiCGSTAB iterations so far (reported per solve)
+  double vs_worst = 0;       // largest final relative residual of a V-solve since the last reset
   ahoc_options opt;
   // FP64 problem data
   double* ia64 = nullptr;
@@ -148,14 +154,17 @@ namespace {
 
 int dalloc(ahoc_handle* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 8;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    set_last_error(hipGetErrorString(e), "hipMalloc");
-    (void)hipGetLastError();
-    return ST_NOMEM;
-  }
+  TRY_ST(dev_alloc(h->al, p, bytes));
   h->allocs.push_back(*p);
   h->dev_bytes += bytes;
+  return ST_OK;
+}
+
+// Mark the end of the work an entry point enqueued on `st` (waited for by ahoc_destroy).
+int mark_done(ahoc_handle* h, hipStream_t st) {
+  if (!h->done_ev) return ST_OK;
+  AHOC_HIP_TRY(hipEventRecord(h->done_ev, st));
+  h->done_rec = true;
   return ST_OK;
 }
 
@@ -180,11 +189,11 @@ void tend(ahoc_handle* h, int kind, hipEvent_t a, double bytes, hipStream_t st) 
   h->pending.push_back({kind, a, b, bytes});
 }
 
-// Fold completed event pairs into the per-kind totals (the stream must be idle).
+// Fold event pairs into the per-kind totals (waits for each pair's end event).
 void tresolve(ahoc_handle* h) {
   for (auto& p : h->pending) {
     float ms = 0.f;
-    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       h->kms[p.kind] += ms;
       h->kcnt[p.kind] += 1;
       h->kbytes[p.kind] += p.bytes;
@@ -295,7 +304,7 @@ bool faces_available(const Geom& g) {
 template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hipStream_t st) {
   const Geom& g = h->g;
   for (int a = 0; a < g.dim; ++a) {
-    TRY(dst_tables_init<T>(P.tb[a], g.n[a], st));
+    TRY(dst_tables_init<T>(P.tb[a], g.n[a], st, &h->al));
     P.tile[a] = tile_opt > 0 ? tile_opt : 0;  // 0: each kernel picks its default tile
     // eigenvalues of the 1-D second difference on sine mode k: -(4/h^2) sin^2(k pi / (2N))
     std::vector<T> s(g.ni[a]);
@@ -432,8 +441,10 @@ int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream
 // interiors, c = beta / alpha nodal, into P.bufA.  BiCGSTAB on A x = src - A_IB Q (A the
 // interior operator), right-preconditioned by K = -L_h + cshift M, whose inverse is one
 // sine-transform solve.  Stops at ||r|| <= 1e-14 ||rhs|| (the FP64 rounding level of the
-// preconditioned operator), after 200 iterations, when four iterations gained less than a
-// factor 2, or on a breakdown (a zero or non-finite rho or step), keeping the last iterate.
+// preconditioned operator), after vsolve_max_iters (200) iterations, when four iterations
+// gained less than a factor 2, or on a breakdown (a zero or non-finite rho or step),
+// keeping the last iterate.  The final ||r|| / ||rhs|| of every V-solve is folded into
+// h->vs_worst, which the solve reports and checks against VSOLVE_RELRES_MAX.
 constexpr int VS_DOT_BLOCKS = 2048;  // work-groups of the V-solve's dot sweeps (>= 2048 entries each)
 
 int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* src, hipStream_t st) {
@@ -477,8 +488,10 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
   TRY(fill(n, 0.0, p, st));
   TRY(fill(n, 0.0, v, st));
   double rho = 1.0, alpha = 1.0, omega = 1.0, best = bnorm, rho1 = h->bpin[0];
+  double last = bnorm;  // ||r|| of the current iterate
   int since = 0;
-  for (int it = 0; it < 200; ++it) {
+  const int cap = h->opt.vsolve_max_iters > 0 ? h->opt.vsolve_max_iters : 200;
+  for (int it = 0; it < cap; ++it) {
     if (rho1 == 0.0 || !std::isfinite(rho1)) break;
     const double beta = (rho1 / rho) * (alpha / omega);
     TRY(lin3(n, 1.0, r, -beta * omega, v, beta, p, st));  // p = r + beta (p - omega v)
@@ -492,6 +505,7 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
     double rn = std::sqrt(h->bpin[1]);
     if (rn <= 1e-14 * bnorm) {
       TRY(axpby(n, alpha, y, 1.0, x, st));  // x += alpha y
+      last = rn;
       break;
     }
     TRY(precond(r, z));
@@ -499,12 +513,14 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
     TRY(dots(r, 2, t));  // <s, t>, <t, t>
     if (h->bpin[1] == 0.0 || !std::isfinite(h->bpin[0] / h->bpin[1])) {
       TRY(axpby(n, alpha, y, 1.0, x, st));  // keep the half step
+      last = rn;
       break;
     }
     omega = h->bpin[0] / h->bpin[1];
     TRY(lin3(n, alpha, y, omega, z, 1.0, x, st));  // x += alpha y + omega z
     TRY(update_dots(-omega, t, r, rh));  // r = s - omega t; <rh, r> for the next step, <r, r>
     rn = std::sqrt(h->bpin[1]);
+    last = rn;
     rho = rho1;
     rho1 = h->bpin[0];
     if (rn <= 1e-14 * bnorm) break;
@@ -515,9 +531,15 @@ int vsolve_var(ahoc_handle* h, Prec<double>& P, const double* Q, const double* s
       break;
     }
   }
+  const double rel = std::isfinite(last) ? last / bnorm : HUGE_VAL;
+  h->vs_worst = std::max(h->vs_worst, rel);
   tend(h, AHOC_K_VSOLVE, e, 0.0, st);
   return ST_OK;
 }
+
+// V-solves whose final relative residual exceeds this leave the Schur operator inexact:
+// the solve then reports AHOC_E_NOCONV.
+constexpr double VSOLVE_RELRES_MAX = 1e-10;
 
 // V = -L^{-1}(src + L_bnd[Q])  into P.bufA
 template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
@@ -695,7 +717,7 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
     h->ptb_own = false;
   } else {
     h->ptb_own = true;
-    for (int a = 0; a < g.dim; ++a) TRY(dst_tables_init<double>(h->ptb[a], g.n[a], st));
+    for (int a = 0; a < g.dim; ++a) TRY(dst_tables_init<double>(h->ptb[a], g.n[a], st, &h->al));
   }
   AHOC_HIP_TRY(hipStreamSynchronize(st));
   return ST_OK;
@@ -880,12 +902,14 @@ struct GmresResult {
 
 // Restarted GMRES(m) on S_h x = b for every instance of the handle (lock-step over a
 // batch: one matvec, one Arnoldi step and one host read of the residual estimates per
-// iteration for all instances), x = 0 on entry, right-preconditioned by the boundary
+// iteration for all instances), from x = 0 or (x0) from the x passed in -- then the first
+// cycle starts from the true residual b - S x --, right-preconditioned by the boundary
 // symbol when it is enabled (x = P^-1 y, GMRES on S P^-1 y = b; the residual it monitors
 // is the true one).  All vectors FP64 on the device.  An instance stops when its estimate
 // reaches tol (its later basis vectors are zero and its Krylov dimension is frozen); with
 // an FP32 operator it also stops once eight iterations gained less than a factor 2 (the
-// estimate levels off at the operator's rounding level).
+// estimate levels off at the operator's rounding level).  A non-finite ||b|| or residual
+// estimate (NaN or Inf in the data) ends the instance as not converged.
 // w = S_h P^-1 v (or S_h v without the preconditioner).  With use_graph the launches run
 // as one captured HIP graph from the fixed buffers gin -> gout (the copies in and out are
 // stream-ordered device copies outside the graph); the graph is captured on the second
@@ -934,7 +958,7 @@ int apply_op(ahoc_handle* h, Prec<T>& P, bool pre, const double* v, double* w, h
 
 template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
-          std::vector<GmresResult>& res, int* matvecs, hipStream_t st) {
+          std::vector<GmresResult>& res, int* matvecs, hipStream_t st, bool x0 = false) {
   const bool inexact = sizeof(T) == 4;
   const bool pre = h->pc != nullptr;
   const int ns = h->g.nb;
@@ -947,18 +971,25 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
   std::vector<double> bnorm(ns);
   std::vector<char> conv(ns, 0), active(ns, 0), stalled(ns, 0);
   std::vector<int> jj(ns, 0);
-  TRY(fill(nt, 0.0, x, st));
+  if (!x0) TRY(fill(nt, 0.0, x, st));
   TRY(dot_dev(h, b, b, st, h->nrm));
   TRY(read_vec(h, h->nrm, 2 * ns, st));
   bool any = false;
   for (int s = 0; s < ns; ++s) {
-    bnorm[s] = std::sqrt(std::max(h->pinned[2 * s], 0.0));
-    conv[s] = !(bnorm[s] > 0);
-    res[s].converged = conv[s];
+    const double b2 = h->pinned[2 * s];
+    bnorm[s] = std::sqrt(std::max(b2, 0.0));
+    if (!std::isfinite(b2)) {  // NaN or Inf in the data: stop, not converged
+      conv[s] = 2;
+      res[s].converged = false;
+      res[s].relres = b2;
+      continue;
+    }
+    conv[s] = bnorm[s] > 0 ? 0 : 1;
+    res[s].converged = conv[s] == 1;
     any = any || !conv[s];
   }
   if (!any) return ST_OK;
-  bool first = true;
+  bool first = !x0;
   while (true) {
     const double* r = b;
     if (!first) {
@@ -979,6 +1010,11 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
         continue;
       }
       res[s].relres = h->pinned[s] / bnorm[s];
+      if (!std::isfinite(h->pinned[s])) {
+        conv[s] = 2;
+        active[s] = 0;
+        continue;
+      }
       if (h->pinned[s] <= tol * bnorm[s]) {
         conv[s] = 1;
         res[s].converged = true;
@@ -1018,7 +1054,9 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
         const double est = h->pinned[2 * s] / bnorm[s];
         res[s].relres = est;
         bool stop = false;
-        if (est <= tol) {
+        if (!std::isfinite(est)) {
+          stop = stalled[s] = 1;  // ends as not converged
+        } else if (est <= tol) {
           conv[s] = 1;
           res[s].converged = true;
           stop = true;
@@ -1295,15 +1333,19 @@ const char* ahoc_last_error(void) { return ahoc::g_err.c_str(); }
 
 void ahoc_destroy(ahoc_handle* h) {
   if (!h) return;
-  (void)hipDeviceSynchronize();
+  // the handle's last enqueued work (solves and setup return after completion; the
+  // asynchronous entry points record done_ev on their stream), and pending timing events
+  if (h->done_ev && h->done_rec) (void)hipEventSynchronize(h->done_ev);
+  for (auto& p : h->pending) (void)hipEventSynchronize(p.b);
   ahoc::prec_free(h->p64);
   ahoc::prec_free(h->p32);
   if (h->ptb_own)
     for (int a = 0; a < 3; ++a) ahoc::dst_tables_free(h->ptb[a]);
   for (int i = 0; i < 2; ++i)
     if (h->opg[i]) (void)hipGraphExecDestroy(h->opg[i]);
-  for (void* p : h->allocs) (void)hipFree(p);
+  for (void* p : h->allocs) ahoc::dev_free(h->al, p);
   for (hipEvent_t e : h->evpool) (void)hipEventDestroy(e);
+  if (h->done_ev) (void)hipEventDestroy(h->done_ev);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->pinned_i) (void)hipHostFree(h->pinned_i);
   if (h->bpin) (void)hipHostFree(h->bpin);
@@ -1356,35 +1398,50 @@ static ahoc_status validate_problem(const ahoc_problem* pb) {
     return AHOC_E_INVALID;
   }
   for (int a = 0; a < pb->dim; ++a) {
-    if (pb->n[a] < 8 || !(pb->hi[a] > pb->lo[a])) {
-      ahoc::set_last_error("need n[a] >= 8 and hi > lo", "ahoc_setup");
+    // the one-sided normal formula (Sec. 2.2) reads U_1, U_2, U_3 next to each face
+    if (pb->n[a] < 4 || pb->n[a] > ahoc::DST_MAX_N || !(pb->hi[a] > pb->lo[a])) {
+      ahoc::set_last_error("need 4 <= n[a] <= 8192 and hi > lo", "ahoc_setup");
       return AHOC_E_INVALID;
-    }
-    if (!ahoc::dst_supported(pb->n[a])) {
-      ahoc::set_last_error("no transform plan for this n (use 2^a or 3*2^a)", "ahoc_setup");
-      return AHOC_E_UNSUPPORTED;
     }
   }
   return AHOC_OK;
 }
 
 // count == 1: one problem; count > 1: a batch of 2-D problems on the same grid.
-static ahoc_status setup_n(const ahoc_problem* pbs, int count, const ahoc_options* opt, void* stream,
-                           ahoc_handle** out) {
+static ahoc_status setup_n(const ahoc_problem* pbs, int count, const ahoc_options* opt,
+                           const ahoc_allocator* alloc, void* stream, ahoc_handle** out) {
   *out = nullptr;
   for (int i = 0; i < count; ++i) {
     const ahoc_status v = validate_problem(&pbs[i]);
     if (v != AHOC_OK) return v;
   }
-  ahoc_handle* h = new ahoc_handle();
-  if (opt) h->opt = *opt;
-  else ahoc_default_options(&h->opt);
-  if (h->opt.restart < 1 || h->opt.restart > 200) h->opt.restart = 30;
-  if (h->opt.precision != AHOC_FP64 && h->opt.precision != AHOC_MIXED) {
-    delete h;
+  if (alloc && (!alloc->alloc || !alloc->free)) {
+    ahoc::set_last_error("an allocator needs both alloc and free", "ahoc_setup");
     return AHOC_E_INVALID;
   }
-  if (count > 1) h->opt.refine = 1;  // a batch refines on the Schur system
+  ahoc_options o;
+  if (opt) o = *opt;
+  else ahoc_default_options(&o);
+  if (o.precision != AHOC_FP64 && o.precision != AHOC_MIXED) {
+    ahoc::set_last_error("precision must be AHOC_FP64 or AHOC_MIXED", "ahoc_setup");
+    return AHOC_E_INVALID;
+  }
+  if (o.restart < 1 || o.restart > 200) o.restart = 30;
+  if (count > 1) o.refine = 1;  // a batch refines on the Schur system
+  ahoc_handle* h = new ahoc_handle();
+  h->opt = o;
+  if (alloc) {
+    h->al.alloc = alloc->alloc;
+    h->al.free = alloc->free;
+    h->al.ctx = alloc->ctx;
+  }
+  if (hipEventCreateWithFlags(&h->done_ev, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    h->done_ev = nullptr;
+    ahoc::set_last_error("hipEventCreateWithFlags failed", "ahoc_setup");
+    delete h;
+    return AHOC_E_HIP;
+  }
   const int rc = ahoc::setup_impl(pbs, count, (hipStream_t)stream, h);
   if (rc) {
     ahoc_destroy(h);
@@ -1394,9 +1451,10 @@ static ahoc_status setup_n(const ahoc_problem* pbs, int count, const ahoc_option
   return AHOC_OK;
 }
 
-ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, void* stream, ahoc_handle** out) {
+ahoc_status ahoc_setup(const ahoc_problem* pb, const ahoc_options* opt, const ahoc_allocator* alloc, void* stream,
+                       ahoc_handle** out) {
   if (!pb || !out) return AHOC_E_INVALID;
-  return setup_n(pb, 1, opt, stream, out);
+  return setup_n(pb, 1, opt, alloc, stream, out);
 }
 
 ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* stream) {
@@ -1404,6 +1462,7 @@ ahoc_status ahoc_schur_apply(ahoc_handle* h, const double* q, double* y, void* s
   hipStream_t st = (hipStream_t)stream;
   int rc = h->opt.precision == AHOC_MIXED ? ahoc::matvec<float>(h, h->p32, q, y, st)
                                           : ahoc::matvec<double>(h, h->p64, q, y, st);
+  if (!rc) rc = ahoc::mark_done(h, st);
   return (ahoc_status)rc;
 }
 
@@ -1418,22 +1477,27 @@ ahoc_status ahoc_precond_apply(ahoc_handle* h, const double* q, double* y, void*
     ahoc::set_last_error("q and y must not alias", "ahoc_precond_apply");
     return AHOC_E_INVALID;
   }
-  return (ahoc_status)ahoc::precond_apply(h, q, y, st);
+  int rc = ahoc::precond_apply(h, q, y, st);
+  if (!rc) rc = ahoc::mark_done(h, st);
+  return (ahoc_status)rc;
 }
 
 ahoc_status ahoc_schur_rhs(ahoc_handle* h, double* b, void* stream) {
   if (!h || !b) return AHOC_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
   int rc;
-  if (h->opt.precision == AHOC_MIXED) {
+  if (h->opt.precision == AHOC_MIXED && h->opt.refine == 0) {
+    // the coupled refinement's first sweep: the data in FP32 through the FP32 operator
     using namespace ahoc;
     rc = convert<double, float>(h->g.nalloc, h->src_v, h->rv, st);
     if (!rc && h->src_u) rc = convert<double, float>(h->g.nalloc, h->src_u, h->ru, st);
     if (!rc) rc = convert<double, float>(h->g.nq, h->src_q, h->rq, st);
     if (!rc) rc = schur_rhs<float>(h, h->p32, h->rv, h->src_u ? h->ru : nullptr, h->rq, b, st);
   } else {
+    // FP64 operator: the FP64 solve, and the Schur refinement's b
     rc = ahoc::schur_rhs<double>(h, h->p64, h->src_v, h->src_u, h->src_q, b, st);
   }
+  if (!rc) rc = ahoc::mark_done(h, st);
   return (ahoc_status)rc;
 }
 
@@ -1454,6 +1518,7 @@ ahoc_status ahoc_poisson(ahoc_handle* h, const double* gin, double* wout, void* 
     if (!rc) rc = poisson<double>(h, h->p64, h->p64.bufA, h->p64.scP, st);
     if (!rc) rc = pitch_copy<double, double>(rows, g.ni[0], h->p64.bufA, g.px, wout, g.ni[0], st);
   }
+  if (!rc) rc = mark_done(h, st);
   return (ahoc_status)rc;
 }
 
@@ -1481,13 +1546,16 @@ int zero_done(ahoc_handle* h, double* x, hipStream_t st) {
 }
 
 // u: one output per instance; v, q only for a single instance (nb = 1).  s: nb stats.
+// With options.warm_start (single instance) q holds the initial guess on entry.
 int solve_fp64(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
   Prec<double>& P = h->p64;
   const Geom& g = h->g;
   std::vector<GmresResult> gr;
   int mv = 0;
+  const bool warm = h->opt.warm_start && q && g.nb == 1;
+  if (warm) AHOC_HIP_TRY(hipMemcpyAsync(h->dq, q, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   TRY(schur_rhs<double>(h, P, h->src_v, h->src_u, h->src_q, h->bvec, st));
-  TRY(gmres<double>(h, P, h->bvec, h->dq, h->opt.tol, h->opt.max_iters, gr, &mv, st));
+  TRY(gmres<double>(h, P, h->bvec, h->dq, h->opt.tol, h->opt.max_iters, gr, &mv, st, warm));
   TRY(vsolve<double>(h, P, h->dq, h->src_v, st));
   TRY(usolve<double>(h, P, h->dq, h->src_u, st));
   TRY(write_u(h, P.bufB, u, st));
@@ -1525,17 +1593,42 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
   TRY(read_vec(h, h->nrm, 2 * nb, st));
   std::vector<double> bnorm(nb), relres(nb, 0.0);
   std::vector<int> sweeps(nb, 0), iters(nb, 0);
+  // conv: 0 refining, 1 converged, 2 stopped without convergence (non-finite data)
   std::vector<char> conv(nb, 0);
   bool all = true;
   for (int i = 0; i < nb; ++i) {
-    bnorm[i] = std::sqrt(std::max(h->pinned[2 * i], 0.0));
-    conv[i] = !(bnorm[i] > 0);
-    relres[i] = conv[i] ? 0.0 : 1.0;
+    const double b2 = h->pinned[2 * i];
+    bnorm[i] = std::sqrt(std::max(b2, 0.0));
+    if (!std::isfinite(b2)) {
+      conv[i] = 2;
+      relres[i] = b2;
+    } else {
+      conv[i] = bnorm[i] > 0 ? 0 : 1;
+      relres[i] = conv[i] ? 0.0 : 1.0;
+    }
     all = all && conv[i];
   }
-  TRY(fill(TQ(g), 0.0, h->Q64, st));
-  AHOC_HIP_TRY(hipMemcpyAsync(h->bvec, h->b64, sizeof(double) * TQ(g), hipMemcpyDeviceToDevice, st));
   int mv = 0;
+  const bool warm = h->opt.warm_start && q && nb == 1;
+  if (warm) {
+    // start from the caller's Q_0: first residual b - S_h Q_0 with the FP64 operator
+    AHOC_HIP_TRY(hipMemcpyAsync(h->Q64, q, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
+    TRY(matvec<double>(h, D, h->Q64, h->bvec, st));
+    ++mv;
+    TRY(axpby(TQ(g), 1.0, h->b64, -1.0, h->bvec, st));
+    if (!all) {
+      TRY(dot_dev(h, h->bvec, h->bvec, st, h->nrm));
+      TRY(read_vec(h, h->nrm, 2, st));
+      const double r2 = h->pinned[0];
+      relres[0] = std::sqrt(std::max(r2, 0.0)) / bnorm[0];
+      if (!std::isfinite(r2)) conv[0] = 2;
+      else if (relres[0] <= h->opt.tol) conv[0] = 1;
+      all = conv[0] != 0;
+    }
+  } else {
+    TRY(fill(TQ(g), 0.0, h->Q64, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(h->bvec, h->b64, sizeof(double) * TQ(g), hipMemcpyDeviceToDevice, st));
+  }
   double upd = 0;
   bool recovered = false;     // D.bufA / D.bufB hold V, U of the current Q64
   bool recover_check = true;  // cleared once a recovery-based check has not converged
@@ -1581,8 +1674,10 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
     all = true;
     for (int i = 0; i < nb; ++i) {
       if (!conv[i]) {
-        relres[i] = std::sqrt(std::max(h->pinned[2 * i], 0.0)) / bnorm[i];
-        conv[i] = relres[i] <= h->opt.tol;
+        const double r2 = h->pinned[2 * i];
+        relres[i] = std::sqrt(std::max(r2, 0.0)) / bnorm[i];
+        if (!std::isfinite(r2)) conv[i] = 2;
+        else conv[i] = relres[i] <= h->opt.tol ? 1 : 0;
       }
       h->pinned_i[i] = !conv[i];
       all = all && conv[i];
@@ -1598,15 +1693,17 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
   if (v) TRY(out_v<double>(g, D.bufA, h->Q64, h->vedge, v, st));
   if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->Q64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
+  bool ok = true;
   for (int i = 0; i < nb; ++i) {
-    s[i].converged = conv[i];
+    s[i].converged = conv[i] == 1;
     s[i].gmres_iters = iters[i];
     s[i].sweeps = sweeps[i];
     s[i].matvecs = mv;
     s[i].schur_relres = relres[i];
     s[i].last_update = upd;
+    ok = ok && conv[i] == 1;
   }
-  return all ? ST_OK : ST_NOCONV;
+  return ok ? ST_OK : ST_NOCONV;
 }
 
 // Mixed precision, refinement on the coupled system: the FP64 residual of the whole
@@ -1615,6 +1712,10 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
 int solve_mixed(ahoc_handle* h, double* const* uo, double* v, double* q, ahoc_stats* s, hipStream_t st) {
   if (h->opt.refine == 1) return solve_mixed_schur(h, uo, v, q, s, st);
   if (h->g.nb != 1) return ST_INVALID;
+  if (h->opt.warm_start && q) {
+    set_last_error("warm_start needs the Schur refinement (refine = 1) in MIXED precision", "ahoc_solve");
+    return ST_UNSUPPORTED;
+  }
   double* u = uo[0];
   Prec<float>& P = h->p32;
   const Geom& g = h->g;
@@ -1702,10 +1803,18 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   if (h->g.nb != 1) return AHOC_E_INVALID;
   double* const uo[1] = {u};
   const long long g0 = h->graph_steps, v0 = h->vs_iters;
+  h->vs_worst = 0;
   int rc = h->opt.precision == AHOC_MIXED ? ahoc::solve_mixed(h, uo, v, q, &local, st)
                                           : ahoc::solve_fp64(h, uo, v, q, &local, st);
   local.graph_steps = (int)(h->graph_steps - g0);
   local.vsolve_iters = (int)(h->vs_iters - v0);
+  local.vsolve_relres = h->vs_worst;
+  if (rc == AHOC_OK && h->vs_worst > ahoc::VSOLVE_RELRES_MAX) {
+    ahoc::set_last_error("a BiCGSTAB V-solve stopped above the residual bound (operator inexact)", "ahoc_solve");
+    local.converged = 0;
+    rc = AHOC_E_NOCONV;
+  }
+  (void)ahoc::mark_done(h, st);
   local.dst_gemm = ahoc::gemm_mask(h);
   const auto t1 = std::chrono::steady_clock::now();
   local.t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
@@ -1731,7 +1840,6 @@ ahoc_status ahoc_set_dst_tile(int pass, int precision, int pairs) {
 
 ahoc_status ahoc_profile(ahoc_handle* h, int enable) {
   if (!h) return AHOC_E_INVALID;
-  (void)hipDeviceSynchronize();
   ahoc::tresolve(h);
   for (int k = 0; k < AHOC_NKIND; ++k) {
     h->kms[k] = 0;
@@ -1745,7 +1853,6 @@ ahoc_status ahoc_profile(ahoc_handle* h, int enable) {
 ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long long* launches,
                               double* bytes_per_launch) {
   if (!h || kind < 0 || kind >= AHOC_NKIND) return AHOC_E_INVALID;
-  (void)hipDeviceSynchronize();
   ahoc::tresolve(h);
   if (total_ms) *total_ms = h->kms[kind];
   if (launches) *launches = h->kcnt[kind];
@@ -1754,7 +1861,7 @@ ahoc_status ahoc_kernel_times(ahoc_handle* h, int kind, double* total_ms, long l
 }
 
 ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_options* opt,
-                               double* const* u, ahoc_stats* stats, void* stream) {
+                               const ahoc_allocator* alloc, double* const* u, ahoc_stats* stats, void* stream) {
   if (count < 0 || (count > 0 && (!probs || !u))) return AHOC_E_INVALID;
   hipStream_t st = (hipStream_t)stream;
   // Jobs: buckets of 2-D problems on the same grid run as one batch (lock-step GMRES, one
@@ -1854,7 +1961,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
       }
       const auto t0 = std::chrono::steady_clock::now();
       ahoc_handle* h = nullptr;
-      ahoc_status rc = setup_n(sub.data(), k, &jopt, s, &h);
+      ahoc_status rc = setup_n(sub.data(), k, &jopt, alloc, s, &h);
       if (rc == AHOC_OK) {
         rc = (ahoc_status)(h->opt.precision == AHOC_MIXED
                                ? ahoc::solve_mixed(h, uo.data(), nullptr, nullptr, so.data(), s)
@@ -1863,6 +1970,14 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
         if (e != hipSuccess && rc == AHOC_OK) {
           ahoc::set_last_error(hipGetErrorString(e), "ahoc_solve_batched");
           rc = AHOC_E_HIP;
+        }
+        if (h->cvar) {
+          for (int j = 0; j < k; ++j) so[j].vsolve_relres = h->vs_worst;
+          if (rc == AHOC_OK && h->vs_worst > ahoc::VSOLVE_RELRES_MAX) {
+            for (int j = 0; j < k; ++j) so[j].converged = 0;
+            ahoc::set_last_error("a BiCGSTAB V-solve stopped above the residual bound", "ahoc_solve_batched");
+            rc = AHOC_E_NOCONV;
+          }
         }
       }
       const double ms =

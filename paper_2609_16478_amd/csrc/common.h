@@ -64,18 +64,37 @@ enum : int { ST_OK = 0, ST_INVALID = -1, ST_NOMEM = -2, ST_NOCONV = -3, ST_HIP =
 
 void set_last_error(const char* what, const char* where);
 
+// Return a nonzero status code from the enclosing function.
+#define TRY_ST(...)              \
+  do {                           \
+    const int rc__ = (__VA_ARGS__); \
+    if (rc__) return rc__;       \
+  } while (0)
+
+// Device memory provider: the caller's callbacks (ahoc_allocator) or, when alloc is null,
+// hipMalloc / hipFree.  dev_alloc returns ST_NOMEM (with the last error set) on failure.
+struct DevAlloc {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+int dev_alloc(const DevAlloc& a, void** p, size_t bytes);
+void dev_free(const DevAlloc& a, void* p);
+
 // ------------------------------------------------------------------------------------
 // DST-I passes (dst.hip)
 // ------------------------------------------------------------------------------------
 
 // Precomputed tables for one transform length N (pencil length N-1).
 template <typename T> struct DstTables {
+  DevAlloc al;        // provider of tw, sn, S (released through it)
   int N = 0;
   int ppt = 0;        // points per thread (compile-time variant selector)
   int nrad = 0;
   int rad[12] = {0};  // radix sequence, product N
-  cx<T>* tw = nullptr;   // exp(-2 pi i k / N), k = 0..N-1
-  T* sn = nullptr;       // sin(pi m / N), m = 0..N/2
+  cx<T>* tw = nullptr;   // exp(-2 pi i k / N), k = 0..N-1 (null without an FFT plan)
+  T* sn = nullptr;       // sin(pi m / N), m = 0..N/2; without an FFT plan (ppt = 0) the
+                         // full period sin(pi j / N), j = 0..2N-1, of the direct pass
   // half sine matrices of the matrix-core pass (even N <= DST_GEMM_MAX_N), [2][HP][HP]
   T* S = nullptr;
   // setup-time choice per plain pass kind (0 rows, 1 strided), dst_tune.hip: method
@@ -199,7 +218,7 @@ int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
 constexpr int DST_GEMM_MAX_N = 128;
 bool dst_gemm_supported(int N);
 int dst_gemm_hp(int N);
-template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st);
+template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st, const DevAlloc& al);
 template <typename T>
 int dst_gemm_pass(const T* S, int N, const T* in, T* out, long long outer, long long inner, long long pitch,
                   hipStream_t st);
@@ -219,11 +238,21 @@ int copy_bandwidth(int pattern, const float* in, float* out, int nx, int ny, int
 void dst_set_variant(int v);
 int dst_get_variant();
 
-// Tables for length N, uploaded on stream st (which is synchronised before returning).
-template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st = nullptr);
+// Tables for length N, uploaded on stream st (which is synchronised before returning),
+// allocated through `al` (null: hipMalloc).
+template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st = nullptr,
+                                          const DevAlloc* al = nullptr);
 template <typename T> void dst_tables_free(DstTables<T>& tb);
+// Every N in [2, DST_MAX_N] has a pass: radix-2/3/4/8 FFT plans where dst_ppt(N) > 0,
+// else the direct sine-sum pass (dst_direct.hip).
+constexpr int DST_MAX_N = 8192;
 bool dst_supported(int N);
 int dst_ppt(int N);
+// Direct O(N) per output pass for any length (same layouts and fused scaling as dst_pass;
+// `sn2` holds sin(pi j / N), j = 0..2N-1).
+template <typename T>
+int dst_direct_pass(int N, const T* sn2, const T* in, T* out, long long outer, long long inner, long long pitch,
+                    const DstScale<T>* fused, hipStream_t st);
 int dst_default_tile(int N, int elem_bytes);
 
 }  // namespace ahoc

@@ -433,7 +433,37 @@ int dst_ppt(int N) {
   return 0;
 }
 
-bool dst_supported(int N) { return N >= 8 && N <= 8192 && dst_ppt(N) > 0; }
+bool dst_supported(int N) { return N >= 2 && N <= DST_MAX_N; }
+
+int dev_alloc(const DevAlloc& a, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  *p = nullptr;
+  if (a.alloc) {
+    *p = a.alloc(bytes, a.ctx);
+    if (!*p) {
+      set_last_error("the caller's allocator returned NULL", "dev_alloc");
+      return ST_NOMEM;
+    }
+    return ST_OK;
+  }
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    set_last_error(hipGetErrorString(e), "hipMalloc");
+    (void)hipGetLastError();
+    *p = nullptr;
+    return ST_NOMEM;
+  }
+  return ST_OK;
+}
+
+void dev_free(const DevAlloc& a, void* p) {
+  if (!p) return;
+  if (a.alloc) {
+    if (a.free) a.free(p, a.ctx);
+    return;
+  }
+  (void)hipFree(p);
+}
 
 // Sequences (pencil pairs) per work-group: 128 B row segments for the strided
 // passes where LDS allows, at least one wavefront, within the launch cap.
@@ -451,42 +481,58 @@ int dst_default_tile(int N, int elem_bytes) {
   return nseq;
 }
 
-template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st) {
+template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st, const DevAlloc* al) {
   dst_tables_free(tb);
+  if (!dst_supported(N)) return ST_UNSUPPORTED;
+  tb.al = al ? *al : DevAlloc();
   const int ppt = dst_ppt(N);
-  if (!ppt) return ST_UNSUPPORTED;
-  Plan pl;
-  make_plan(N, ppt, pl);
+  const long double pi = 3.141592653589793238462643383279502884L;
   tb.N = N;
   tb.ppt = ppt;
-  tb.nrad = pl.nrad;
-  for (int i = 0; i < pl.nrad; ++i) tb.rad[i] = pl.rad[i];
-  std::vector<cx<T>> tw(N);
-  std::vector<T> sn(N / 2 + 1);
-  const long double pi = 3.141592653589793238462643383279502884L;
-  for (int k = 0; k < N; ++k) {
-    const long double ang = 2.0L * pi * (long double)k / (long double)N;
-    tw[k].x = (T)cosl(ang);
-    tw[k].y = (T)(-sinl(ang));
+  if (!ppt) {
+    // no FFT plan: the direct pass reads one full period of sin(pi j / N); the integer
+    // argument is reduced to [0, N] by the symmetries of the sine before evaluation
+    std::vector<T> sn2(2 * (size_t)N);
+    for (int j = 0; j < 2 * N; ++j) {
+      const int r = j <= N ? j : 2 * N - j;
+      const long double v = sinl(pi * (long double)(r <= N / 2 ? r : N - r) / (long double)N);
+      sn2[j] = (T)(j <= N ? v : -v);
+    }
+    tb.nrad = 0;
+    TRY_ST(dev_alloc(tb.al, reinterpret_cast<void**>(&tb.sn), sizeof(T) * 2 * (size_t)N));
+    AHOC_HIP_TRY(hipMemcpyAsync(tb.sn, sn2.data(), sizeof(T) * 2 * (size_t)N, hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
+  } else {
+    Plan pl;
+    make_plan(N, ppt, pl);
+    tb.nrad = pl.nrad;
+    for (int i = 0; i < pl.nrad; ++i) tb.rad[i] = pl.rad[i];
+    std::vector<cx<T>> tw(N);
+    std::vector<T> sn(N / 2 + 1);
+    for (int k = 0; k < N; ++k) {
+      const long double ang = 2.0L * pi * (long double)k / (long double)N;
+      tw[k].x = (T)cosl(ang);
+      tw[k].y = (T)(-sinl(ang));
+    }
+    for (int m = 0; m <= N / 2; ++m) sn[m] = (T)sinl(pi * (long double)m / (long double)N);
+    TRY_ST(dev_alloc(tb.al, reinterpret_cast<void**>(&tb.tw), sizeof(cx<T>) * N));
+    TRY_ST(dev_alloc(tb.al, reinterpret_cast<void**>(&tb.sn), sizeof(T) * (N / 2 + 1)));
+    // stream-ordered uploads (no legacy-stream operation while other streams may be capturing)
+    AHOC_HIP_TRY(hipMemcpyAsync(tb.tw, tw.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(tb.sn, sn.data(), sizeof(T) * (N / 2 + 1), hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
   }
-  for (int m = 0; m <= N / 2; ++m) sn[m] = (T)sinl(pi * (long double)m / (long double)N);
-  AHOC_HIP_TRY(hipMalloc(&tb.tw, sizeof(cx<T>) * N));
-  AHOC_HIP_TRY(hipMalloc(&tb.sn, sizeof(T) * (N / 2 + 1)));
-  // stream-ordered uploads (no legacy-stream operation while other streams may be capturing)
-  AHOC_HIP_TRY(hipMemcpyAsync(tb.tw, tw.data(), sizeof(cx<T>) * N, hipMemcpyHostToDevice, st));
-  AHOC_HIP_TRY(hipMemcpyAsync(tb.sn, sn.data(), sizeof(T) * (N / 2 + 1), hipMemcpyHostToDevice, st));
-  AHOC_HIP_TRY(hipStreamSynchronize(st));
   if (dst_gemm_supported(N)) {
-    const int rc = dst_gemm_table<T>(&tb.S, N, st);
+    const int rc = dst_gemm_table<T>(&tb.S, N, st, tb.al);
     if (rc != ST_OK) return rc;
   }
   return ST_OK;
 }
 
 template <typename T> void dst_tables_free(DstTables<T>& tb) {
-  if (tb.tw) (void)hipFree(tb.tw);
-  if (tb.sn) (void)hipFree(tb.sn);
-  if (tb.S) (void)hipFree(tb.S);
+  dev_free(tb.al, tb.tw);
+  dev_free(tb.al, tb.sn);
+  dev_free(tb.al, tb.S);
   tb.tw = nullptr;
   tb.sn = nullptr;
   tb.S = nullptr;
@@ -519,7 +565,11 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
   }
   if (faces && faces->mode) return ST_UNSUPPORTED;  // face sums only in the specialised kernels
   const int ppt = tb.ppt;
-  if (!ppt || !tb.tw) return ST_INVALID;
+  if (!ppt) {  // no FFT plan for this length: the direct sine sums
+    if (!tb.sn) return ST_INVALID;
+    return dst_direct_pass<T>(N, tb.sn, in, out, outer, inner, pitch, fused, st);
+  }
+  if (!tb.tw) return ST_INVALID;
   const int tps = N / ppt;
   const int nseq = tile_seqs > 0 ? tile_seqs : dst_default_tile(N, (int)sizeof(T));
   if (nseq <= 0 || (nseq & (nseq - 1))) return ST_INVALID;
@@ -562,8 +612,8 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
   }
 }
 
-template int dst_tables_init<float>(DstTables<float>&, int, hipStream_t);
-template int dst_tables_init<double>(DstTables<double>&, int, hipStream_t);
+template int dst_tables_init<float>(DstTables<float>&, int, hipStream_t, const DevAlloc*);
+template int dst_tables_init<double>(DstTables<double>&, int, hipStream_t, const DevAlloc*);
 template void dst_tables_free<float>(DstTables<float>&);
 template void dst_tables_free<double>(DstTables<double>&);
 template int dst_pass<float>(const DstTables<float>&, const float*, float*, long long, long long,

@@ -212,7 +212,7 @@ bool dst_gemm_supported(int N) { return N >= 4 && N <= DST_GEMM_MAX_N && N % 2 =
 // padded half length HP = 16 ceil(N / 32)
 int dst_gemm_hp(int N) { return dst_gemm_supported(N) ? (N / 2 + 15) / 16 * 16 : 0; }
 
-template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st) {
+template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st, const DevAlloc& al) {
   *S = nullptr;
   const int HP = dst_gemm_hp(N);
   if (!HP) return ST_UNSUPPORTED;
@@ -225,7 +225,10 @@ template <typename T> int dst_gemm_table(T** S, int N, hipStream_t st) {
     for (int j = 0; j < H; ++j) h[(size_t)(m - 1) * HP + j] = sn((long long)(2 * j + 1) * m);
   for (int m = 1; m <= H - 1; ++m)
     for (int j = 1; j <= H - 1; ++j) h[(size_t)HP * HP + (size_t)(m - 1) * HP + (j - 1)] = sn(2LL * j * m);
-  AHOC_HIP_TRY(hipMalloc(S, sizeof(T) * h.size()));
+  {
+    const int rc = dev_alloc(al, reinterpret_cast<void**>(S), sizeof(T) * h.size());
+    if (rc != ST_OK) return rc;
+  }
   AHOC_HIP_TRY(hipMemcpyAsync(*S, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
   return ST_OK;
@@ -245,8 +248,8 @@ int dst_gemm_pass(const T* S, int N, const T* in, T* out, long long outer, long 
   }
 }
 
-template int dst_gemm_table<float>(float**, int, hipStream_t);
-template int dst_gemm_table<double>(double**, int, hipStream_t);
+template int dst_gemm_table<float>(float**, int, hipStream_t, const DevAlloc&);
+template int dst_gemm_table<double>(double**, int, hipStream_t, const DevAlloc&);
 template int dst_gemm_pass<float>(const float*, int, const float*, float*, long long, long long, long long,
                                   hipStream_t);
 template int dst_gemm_pass<double>(const double*, int, const double*, double*, long long, long long, long long,

@@ -40,9 +40,9 @@ def test_host_only_entry_points():
     h = ctypes.c_void_p()
     p = ah._Problem()
     p.dim = 4
-    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID
+    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, None, ctypes.byref(h)) == ah.E_INVALID
     p.dim = 2
-    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID  # NULL alpha
+    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, None, ctypes.byref(h)) == ah.E_INVALID  # NULL alpha
     # Navier flags per face (x-, x+, y-, y+[, z-, z+]) -> bit 2 axis + side
     assert ah._navier_mask((False, True, True, True)) == 0b1110
     assert ah._navier_mask((True, False, False, False, False, True)) == 0b100001
@@ -65,20 +65,25 @@ def test_argument_errors_before_device_work():
         return p
 
     h = ctypes.c_void_p()
-    for p, code in ((problem((7, 16)), ah.E_INVALID),                         # n < 8
-                    (problem((16, 16), hi=(1.0, 0.0)), ah.E_INVALID),         # hi <= lo
-                    (problem((40, 16)), ah.E_UNSUPPORTED)):                   # no transform plan
-        assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == code
+    for p, code in ((problem((3, 16)), ah.E_INVALID),                         # n < 4
+                    (problem((16, 8193)), ah.E_INVALID),                      # n > 8192
+                    (problem((16, 16), hi=(1.0, 0.0)), ah.E_INVALID)):        # hi <= lo
+        assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, None, ctypes.byref(h)) == code
+    # an allocator needs both callbacks
+    al = ah._Allocator()
+    al.alloc = ah._TORCH_ALLOC
+    assert ah._lib.ahoc_setup(ctypes.byref(problem((16, 16))), None, ctypes.byref(al), None,
+                              ctypes.byref(h)) == ah.E_INVALID
     p = problem((16, 16))
     p.navier = 1 << 4  # a z face of a 2-D problem
-    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, ctypes.byref(h)) == ah.E_INVALID
+    assert ah._lib.ahoc_setup(ctypes.byref(p), None, None, None, ctypes.byref(h)) == ah.E_INVALID
     o = ah.default_options()
     o.precision = 7
     p = problem((16, 16))
-    assert ah._lib.ahoc_setup(ctypes.byref(p), ctypes.byref(o), None, ctypes.byref(h)) == ah.E_INVALID
+    assert ah._lib.ahoc_setup(ctypes.byref(p), ctypes.byref(o), None, None, ctypes.byref(h)) == ah.E_INVALID
     # batches: a negative count is rejected, an empty batch is a no-op
-    assert ah._lib.ahoc_solve_batched(-1, None, None, None, None, None) == ah.E_INVALID
-    assert ah._lib.ahoc_solve_batched(0, None, None, None, None, None) == ah.OK
+    assert ah._lib.ahoc_solve_batched(-1, None, None, None, None, None, None) == ah.E_INVALID
+    assert ah._lib.ahoc_solve_batched(0, None, None, None, None, None, None) == ah.OK
     # calibration copies: unknown pattern, rows not a multiple of 32 columns
     assert ah._lib.ahoc_copy_bandwidth(3, fake, fake, 64, 4, 4, None) == ah.E_INVALID
     assert ah._lib.ahoc_copy_bandwidth(1, fake, fake, 48, 4, 4, None) == ah.E_INVALID

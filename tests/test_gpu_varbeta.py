@@ -15,14 +15,17 @@ and a planted constant beta):
   nodes to 1e-10 of max |U|), and at 64^3 ... 512^3 against Table 2's printed errors;
 * the 3-D oscillatory example (Table 3: inhomogeneous data on every face) at 32^3 against
   the oracle and at 64^3 ... 512^3 against the printed errors.
-  The paper stops GMRES at a relative Schur residual proportional to h^3.5, which leaves an
-  iteration error of about h^3.5 max |u| in its printed errors (the tests here solve to
-  1e-12).  A printed error is matched to half a unit of its last digit plus h^3.5 max |u|:
-  all but two entries agree to the half unit alone; Table 3's (5, 1, 5) at 512^3 (1.0965e-10
-  against 1.05e-10, h^3.5 = 3.4e-10) and (25, 5, 25) at 64^3 (2.8340e-4 against 2.84e-4,
-  h^3.5 = 4.7e-7) need the allowance.  At 32^3 the printed (5, 1) entry of Table 2 (6.86e-4)
-  lies 1.2e-6 above the oracle's own direct solve (6.848e-4), so 32^3 is compared with the
-  oracle only;
+  A printed error is matched to half a unit of its last printed digit.  Two entries are
+  named exceptions with bounds of their own: the paper stops GMRES at a relative Schur
+  residual proportional to h^3.5 (Sec. 4.1), which can leave iteration error in its last
+  digit, while the tests here solve to 1e-12.  Table 3's (5, 1, 5) at 512^3 (1.0965e-10
+  against 1.05e-10: within 5 % of it) and (25, 5, 25) at 64^3 (2.8340e-4 against 2.84e-4:
+  within 0.5 %).  At 32^3 the printed (5, 1) entry of Table 2 (6.86e-4) lies 1.2e-6 above the
+  oracle's own direct solve (6.848e-4), so 32^3 is compared with the oracle only;
+* the BiCGSTAB V-solve's status: with its iterations capped the solve reports
+  AHOC_E_NOCONV and the final relative residual of the worst V-solve;
+* the tiled stencil application's seams between x tiles and z chunks (a 3-D grid of 192 x 96
+  x 96 against the shifted-transform solve of the same problem);
 * MIXED precision with a variable beta is rejected.
 """
 import json
@@ -111,10 +114,18 @@ def _half_unit(x):
     return 0.5 * 10.0 ** (math.floor(math.log10(x)) - 2)
 
 
-def _printed_tol(ref, n, umax):
-    """Half a unit of the printed digits plus the iteration error h^3.5 max |u| that the
-    paper's GMRES stopping rule leaves in its printed errors."""
-    return _half_unit(ref) + (1.0 / n) ** 3.5 * umax
+# Named exceptions (table, parameters, n) -> relative bound around the printed value.  The
+# paper's GMRES stops at a relative Schur residual proportional to h^3.5 (Sec. 4.1), so its
+# printed error can carry iteration error in its last digit; these two entries are the ones
+# where our discrete solution (solved to 1e-12) differs from the printed digits by more than
+# half a unit.
+PRINTED_EXCEPTIONS = {("table3", "5,1,5", 512): 0.05, ("table3", "25,5,25", 64): 0.005}
+
+
+def _printed_tol(ref, table, key, n):
+    """Half a unit of the printed digits, or a named exception's own relative bound."""
+    rel = PRINTED_EXCEPTIONS.get((table, key, n))
+    return rel * ref if rel is not None else _half_unit(ref)
 
 
 @pytest.mark.parametrize("n", [64, 128, 256, 512])
@@ -129,7 +140,7 @@ def test_example2_table2_on_gpu(ah, n, qp):
     err = (u - p.u_exact).abs().max().item()
     print(f"example2 {qp} n={n}: {err:.6e} (Table 2: {ref:.2e}) gmres {st.gmres_iters} "
           f"bicgstab {st.vsolve_iters} {st.t_solve_ms:.0f} ms", flush=True)
-    assert abs(err - ref) <= _printed_tol(ref, n, p.u_exact.abs().max().item()), (err, ref)
+    assert abs(err - ref) <= _printed_tol(ref, "table2", qp, n), (err, ref)
 
 
 def test_varbeta_rejected_in_mixed_precision(ah):
@@ -171,7 +182,7 @@ def test_example3_table3_on_gpu(ah, n, k):
     err = (u - p.u_exact).abs().max().item()
     print(f"example3 {k} n={n}: {err:.6e} (Table 3: {ref:.2e}) gmres {st.gmres_iters} "
           f"bicgstab {st.vsolve_iters} {st.t_solve_ms:.0f} ms", flush=True)
-    assert abs(err - ref) <= _printed_tol(ref, n, p.u_exact.abs().max().item()), (err, ref)
+    assert abs(err - ref) <= _printed_tol(ref, "table3", k, n), (err, ref)
 
 
 def test_varbeta_graph_option_stays_eager(ah):
@@ -186,15 +197,20 @@ def test_varbeta_graph_option_stays_eager(ah):
     assert torch.equal(u0, u1)
 
 
-@pytest.mark.parametrize("dim", [2, 3])
-def test_nodal_constant_beta_equals_shifted_transform(ah, dim):
+@pytest.mark.parametrize("case", ["2d", "3d", "3d_seams"])
+def test_nodal_constant_beta_equals_shifted_transform(ah, case):
     """A nodal beta that happens to be constant takes the BiCGSTAB V-solve; a scalar beta takes
     the shifted transform solve.  The two are different algorithms for the same discrete
-    problem and must agree (U to 1e-11)."""
-    if dim == 2:
+    problem and must agree (U to 1e-11).  The 192 x 96 x 96 grid has three x tiles (64
+    columns) and three z chunks (32 planes) of the tiled stencil application, so its seams
+    are inside the comparison."""
+    if case == "2d":
         p = W.manufactured("0.5", U2, (32, 24), beta=3.0, navier=(False, True, False, True))
-    else:
+    elif case == "3d":
         p = W.manufactured("2", "sin(pi*x)*sin(pi*y)**2*sin(pi*z)", (12, 8, 16), beta=-1.5)
+    else:
+        p = W.manufactured("2", "sin(pi*x)*sin(pi*y)**2*sin(pi*z)*exp(x)", (192, 96, 96), (0.0, 0.0, 0.0),
+                           (1.0, 0.6, 0.5), beta=-1.5)
     with ah.Solver(p, tol=1e-13) as s:
         u0, _, _, st0 = s.solve()
     p.beta = np.full(tuple(m + 1 for m in reversed(p.n)), p.beta)
@@ -226,3 +242,18 @@ def test_varbeta_kernel_class_timing(ah):
     assert st.converged
     assert kt["vsolve"][1] == st.matvecs + 2, (kt["vsolve"], st)
     assert kt["dst_fused"][1] > 0 and kt["vsolve"][0] > 0.0
+
+
+def test_vsolve_cap_reports_noconv(ah):
+    """With the BiCGSTAB iterations of each V-solve capped at 1 the Schur operator is inexact:
+    the solve returns AHOC_E_NOCONV with converged = 0 and the worst V-solve's final relative
+    residual (above the 1e-10 bound); uncapped, that residual is at the 1e-14 stop."""
+    p = CASES["3d_ex2"]()
+    with ah.Solver(p, tol=1e-12) as s:
+        _, _, _, st = s.solve()
+        assert s.status == ah.OK and st.converged, st
+    assert 0.0 < st.vsolve_relres <= 1e-12, st
+    with ah.Solver(p, tol=1e-12, vsolve_max_iters=1, max_iters=40) as s:
+        _, _, _, st = s.solve()
+        assert s.status == ah.E_NOCONV and not st.converged, st
+    assert st.vsolve_relres > 1e-10, st
