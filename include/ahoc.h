@@ -235,6 +235,22 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
  * ((n_z-1)(n_y-1)(n_x-1), x fastest), in the handle's precision internally. */
 ahoc_status ahoc_poisson(ahoc_handle* h, const double* g, double* w, void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc -- the Dirichlet solve of ahoc_poisson
+ * without a handle: w = L_int^{-1} g on the interior of a dim-D box grid with n[a]
+ * intervals (4 <= n[a] <= 8192) and spacings (hi[a] - lo[a]) / n[a], homogeneous boundary;
+ * g and w interior FP64 arrays ((n_z-1)(n_y-1)(n_x-1), x fastest, no padding; w may equal g),
+ * computed in FP64 (AHOC_FP64) or with FP32 transforms (AHOC_MIXED).  The work array and
+ * the transform tables live in one fixed device array of 64 MiB per GPU, held by the
+ * library until the process ends (1 MiB of tables, then the interior padded to rows of a
+ * multiple of 32 elements): a grid whose padded interior exceeds 63 MiB in the working
+ * precision returns AHOC_E_INVALID.  Allocates nothing (no hipMalloc, hipFree or allocating
+ * library call) and copies nothing from the host; asynchronous on the stream.  Every call on
+ * a GPU shares that GPU's array and leaves its contents behind: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller. */
+ahoc_status ahoc_poisson_noalloc(int precision, int dim, const int* n, const double* lo, const double* hi,
+                                 const double* g, double* w, void* stream);
+
 /* Stand-alone batched DST-I along one axis of an interior-shaped array:
  * out[..., k, ...] = sum_{m=1}^{N-1} in[..., m, ...] sin(pi k m / N), N = nint[axis]+1.
  * precision: AHOC_FP64 (double arrays) or AHOC_MIXED (float arrays).

@@ -108,6 +108,9 @@ _lib.ahoc_solve_batched.argtypes = [c_int, ctypes.POINTER(_Problem), ctypes.POIN
 _lib.ahoc_solve_batched.restype = c_int
 _lib.ahoc_poisson.argtypes = [_H, c_void_p, c_void_p, c_void_p]
 _lib.ahoc_poisson.restype = c_int
+_lib.ahoc_poisson_noalloc.argtypes = [c_int, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_double),
+                                      ctypes.POINTER(c_double), c_void_p, c_void_p, c_void_p]
+_lib.ahoc_poisson_noalloc.restype = c_int
 _lib.ahoc_dst1.argtypes = [c_int, c_int, ctypes.POINTER(c_int), c_int, c_void_p, c_void_p, c_void_p]
 _lib.ahoc_dst1.restype = c_int
 _lib.ahoc_profile.argtypes = [_H, c_int]
@@ -133,7 +136,7 @@ KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather
                 "matvec", "dst_gen", "face_reduce", "precond", "vsolve"]
 
 EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_dst_choice", "ahoc_copy_bandwidth", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
-            "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_dst1", "ahoc_destroy",
+            "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_poisson_noalloc", "ahoc_dst1", "ahoc_destroy",
             "ahoc_status_string", "ahoc_last_error"]
 
 
@@ -423,6 +426,24 @@ def copy_bandwidth(pattern, x, out):
     assert x.dtype == out.dtype and x.dim() == 3 and x.is_contiguous() and out.is_contiguous()
     nz, ny, nx = x.shape
     _check(_lib.ahoc_copy_bandwidth(int(pattern), _ptr(x), _ptr(out), nx, ny, nz, _stream()), "ahoc_copy_bandwidth")
+
+
+def poisson_noalloc(n, lo, hi, g, precision=FP64, out=None):
+    """w = L_int^{-1} g on the interior of a box grid (homogeneous Dirichlet) through
+    ahoc_poisson_noalloc: no handle, and the library allocates nothing (its work array and
+    tables live in a fixed per-GPU device array).  g: interior-shaped float64 tensor on the
+    device (memory order z, y, x); out: optional preallocated result of the same shape."""
+    torch = _torch()
+    dim = len(n)
+    g = g.to(dtype=torch.float64).contiguous()
+    w = out if out is not None else torch.empty_like(g)
+    assert w.shape == g.shape and w.dtype == torch.float64 and w.is_contiguous()
+    na = (c_int * 3)(*([int(v) for v in n] + [0] * (3 - dim)))
+    lo_ = (c_double * 3)(*([float(v) for v in lo] + [0.0] * (3 - dim)))
+    hi_ = (c_double * 3)(*([float(v) for v in hi] + [0.0] * (3 - dim)))
+    _check(_lib.ahoc_poisson_noalloc(int(precision), dim, na, lo_, hi_, _ptr(g), _ptr(w), _stream()),
+           "ahoc_poisson_noalloc")
+    return w
 
 
 def dst1(x, axis, precision=FP64):

@@ -243,6 +243,8 @@ int dst_get_variant();
 template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t st = nullptr,
                                           const DevAlloc* al = nullptr);
 template <typename T> void dst_tables_free(DstTables<T>& tb);
+// Only the radix plan of an FFT length (N, ppt, nrad, rad): no device memory.
+template <typename T> int dst_plan_only(DstTables<T>& tb, int N);
 // Every N in [2, DST_MAX_N] has a pass: radix-2/3/4/8 FFT plans where dst_ppt(N) > 0,
 // else the direct sine-sum pass (dst_direct.hip).
 constexpr int DST_MAX_N = 8192;

@@ -529,6 +529,18 @@ template <typename T> int dst_tables_init(DstTables<T>& tb, int N, hipStream_t s
   return ST_OK;
 }
 
+template <typename T> int dst_plan_only(DstTables<T>& tb, int N) {
+  const int ppt = dst_ppt(N);
+  if (!ppt) return ST_UNSUPPORTED;
+  Plan pl;
+  make_plan(N, ppt, pl);
+  tb.N = N;
+  tb.ppt = ppt;
+  tb.nrad = pl.nrad;
+  for (int i = 0; i < pl.nrad; ++i) tb.rad[i] = pl.rad[i];
+  return ST_OK;
+}
+
 template <typename T> void dst_tables_free(DstTables<T>& tb) {
   dev_free(tb.al, tb.tw);
   dev_free(tb.al, tb.sn);
@@ -614,6 +626,8 @@ int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long 
 
 template int dst_tables_init<float>(DstTables<float>&, int, hipStream_t, const DevAlloc*);
 template int dst_tables_init<double>(DstTables<double>&, int, hipStream_t, const DevAlloc*);
+template int dst_plan_only<float>(DstTables<float>&, int);
+template int dst_plan_only<double>(DstTables<double>&, int);
 template void dst_tables_free<float>(DstTables<float>&);
 template void dst_tables_free<double>(DstTables<double>&);
 template int dst_pass<float>(const DstTables<float>&, const float*, float*, long long, long long,
