@@ -178,6 +178,8 @@ def main():
     ap.add_argument("--profile-matvec", type=int, default=0,
                     help="profiling target: set up the mixed-precision handle and run this many "
                          "Schur matvecs, then exit (no JSON line)")
+    ap.add_argument("--profile-prec", choices=("mixed", "fp64"), default="mixed",
+                    help="operator precision of --profile-matvec (mixed = the FP32 operator)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="profiling target: three plain 2 GiB device copies (counter calibration)")
     ap.add_argument("--dst-compare", action="store_true",
@@ -267,14 +269,14 @@ def main():
     print(f"[bench] n={n} inputs generated on device in {t_gen:.1f}s", file=sys.stderr, flush=True)
 
     if args.profile_matvec:
-        s = ah.Solver(prob, precision=ah.MIXED)
+        s = ah.Solver(prob, precision=ah.MIXED if args.profile_prec == "mixed" else ah.FP64)
         q = torch.randn(s.nq, dtype=torch.float64, device=dev)
         for _ in range(args.profile_matvec):
             q = s.schur_apply(q)
             q = q / q.norm()
         torch.cuda.synchronize()
         s.close()
-        print(f"[bench] {args.profile_matvec} Schur matvecs done (n={n})", file=sys.stderr)
+        print(f"[bench] {args.profile_matvec} Schur matvecs done (n={n}, {args.profile_prec})", file=sys.stderr)
         return
 
     # kernel classes that launch kernels themselves (the matvec and residual classes wrap them)

@@ -21,6 +21,7 @@
 // prefetch is issued after the first transform.
 #include "dst_device.h"
 
+#include <algorithm>
 #include <mutex>
 
 namespace ahoc {
@@ -311,10 +312,22 @@ template <typename T, int N, int MODE> struct PipeLaunch {
 // ------------------------------------------------------------------------------------
 // Persistent V-solve pass along the slowest axis: generate the scaled spectrum of the
 // face-layer right-hand side from the 2-D face spectra (see dst_spectral.hip for the
-// separable form), invert along the pass axis, store.  Same tile mapping as k_dst_pipe;
-// the stores of one tile drain while the next tile is generated.  Face-array layouts as
-// DstGen (common.h); a tile must lie in one row of the column decode (na a multiple of the
-// tile width), so that the x-face row is shared by all its columns.
+// separable form), invert along the pass axis, store.  Same tile mapping as k_dst_pipe.
+// Face-array layouts as DstGen (common.h); a tile must lie in one row of the column decode
+// (na a multiple of the tile width), so that the x-face row is shared by all its columns.
+//
+// Mode k of the layer next to the high face carries the layer sine of the low face times
+// (-1)^(k+1) (sin(pi k (N-1)/N)), so a face pair enters mode k only through lo + hi (k odd)
+// or lo - hi (k even).  k_face_pm turns every face pair into that sum and difference in
+// place first; then a term is one face value times one layer sine:
+//   z faces  P(kx, ky) at the position parity of the pass axis (fixed per thread, since a
+//            thread's positions are TPS apart and TPS is even)
+//   x faces  X(ky, kz): the pair's even column (odd mode) the sum, its odd column the
+//            difference; one row per tile, staged in LDS
+//   y faces  Y(kx, kz) at the parity of ky (fixed per tile); prefetched into registers
+//            for the next tile while the current one is transformed
+// The layer sines and eigenvalue tables of the pass axis are tile-invariant: LDS where
+// it has room, else registers (512-thread groups) or the caches.
 // ------------------------------------------------------------------------------------
 template <typename T> struct GenPipeArgs {
   T* out;
@@ -325,24 +338,132 @@ template <typename T> struct GenPipeArgs {
   DstGen<T> g;
 };
 
+// (lo, hi) -> (lo + hi, lo - hi) for `count` entries of each of `nslab` slabs:
+// lo = f[o slab + j], hi = f[o slab + plane + j]
+template <typename T>
+__global__ void k_face_pm(T* f, long long plane, long long slab, long long count, long long nslab) {
+  const long long n = count * nslab;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x) {
+    const long long o = e / count;
+    const long long j = e - o * count;
+    T* lo = f + o * slab + j;
+    const T a = lo[0], b = lo[plane];
+    lo[0] = a + b;
+    lo[plane] = a - b;
+  }
+}
+
+template <typename T> int face_pm(T* f, long long plane, long long slab, long long count, long long nslab, hipStream_t st) {
+  if (!f || count <= 0 || nslab <= 0) return ST_OK;
+  const long long n = count * nslab;
+  const unsigned blocks = (unsigned)std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL((k_face_pm<T>), dim3(blocks), dim3(256), 0, st, f, plane, slab, count, nslab);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+template <typename T, int N, int NSEQ> struct GenShape {
+  using PL = PipePlan<N>;
+  static constexpr int PPT = PL::PPT;
+  static constexpr int TPS = N / PPT;
+  static constexpr int L = N - 1;
+  static constexpr int THREADS = NSEQ * TPS;
+  static constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  static constexpr size_t TILE_B = (size_t)(NSEQ * seq_stride<N>() + NSEQ * NTOT) * sizeof(cx<T>);
+  static constexpr size_t LDS_MAX = 160 * 1024;
+  // x-face row [2][L] in LDS; tables (layer sines, eigenvalues) [2][L] in LDS after it
+  static constexpr bool XLDS = TILE_B + 2 * (size_t)L * sizeof(T) <= LDS_MAX;
+  static constexpr bool TLDS = XLDS && TILE_B + 4 * (size_t)L * sizeof(T) <= LDS_MAX;
+  static constexpr bool TREG = false;  // (registers: FP64 at N = 1024 spills)
+  static constexpr int XR = (L + THREADS - 1) / THREADS;  // x-face entries per thread and side
+  static constexpr size_t LDS = TILE_B + (XLDS ? 2 * (size_t)L * sizeof(T) : 0) + (TLDS ? 2 * (size_t)L * sizeof(T) : 0);
+};
+
 template <typename T, int N, int NSEQ>
 __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPipeArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  using PL = PipePlan<N>;
-  constexpr int PPT = PL::PPT;
-  constexpr int TPS = N / PPT;
-  constexpr int L = N - 1;
+  using SH = GenShape<T, N, NSEQ>;
+  using PL = typename SH::PL;
+  constexpr int PPT = SH::PPT;
+  constexpr int TPS = SH::TPS;
+  constexpr int L = SH::L;
+  constexpr int THREADS = SH::THREADS;
   constexpr int LDQ = seq_stride<N>();
   constexpr int LGQ = ilog2(NSEQ);
-  constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  constexpr int NTOT = SH::NTOT;
   constexpr bool LIN = TPS % 32 == 0;
+  constexpr bool XLDS = SH::XLDS, TLDS = SH::TLDS, TREG = SH::TREG;
+  constexpr int XR = SH::XR;
+  static_assert(TPS % 2 == 0, "positions of a thread must share their parity");
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  T* xrow = reinterpret_cast<T*>(smem + SH::TILE_B);  // [0, L): sum, [L, 2L): difference
+  T* tab = xrow + 2 * L;                               // [0, L): layer sine, [L, 2L): eigenvalue
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
   const DstGen<T>& g = a.g;
   const bool has_b = g.lb != nullptr;
 
-  for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  const int tid0 = threadIdx.x;
+  const int q0 = tid0 & (NSEQ - 1);
+  const int mi0 = tid0 >> LGQ;
+  // every position m = 1 + mi + k TPS of this thread has the parity of 1 + mi
+  const bool modd = ((1 + mi0) & 1) != 0;
+
+  // tile-invariant tables of the pass axis
+  T wpr[TREG ? PPT : 1], str[TREG ? PPT : 1];
+  if constexpr (TLDS) {
+    for (int j = tid0; j < L; j += THREADS) {
+      tab[j] = g.wp[j];
+      tab[L + j] = a.fs.s_this[j];
+    }
+  }
+  if constexpr (TREG) {
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int m = 1 + mi0 + k * TPS;
+      wpr[k] = m < N ? g.wp[m - 1] : T(0);
+      str[k] = m < N ? a.fs.s_this[m - 1] : T(1);
+    }
+  }
+
+  // prefetched face data of a tile: y-face values at the thread's positions (both pencils of
+  // its pair) and the tile's x-face row
+  cx<T> yb[PPT];
+  T xr[2][XR];
+  const long long rowb = (long long)g.bpitch * (long long)sizeof(T);
+  auto prefetch = [&](long long tile) {
+    const long long o = tile / a.ntile_inner;
+    const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+    const long long ib = c0 / a.fs.na;
+    if (has_b) {
+      const long long ia0 = c0 - ib * a.fs.na;  // first column of the tile in its row
+      // ky even (odd mode) -> sums, ky odd -> differences
+      const T* yrow = g.lb + o * g.bslab + ((ib & 1) ? g.bplane : 0) + ia0;
+      const SBase src(yrow);
+      unsigned vo = (unsigned)((2 * q0 + (long long)mi0 * g.bpitch) * (long long)sizeof(T));
+      asm volatile("" : "+v"(vo));
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const int m = 1 + mi0 + k * TPS;
+        if (k < PPT - 1 || m < N) yb[k] = src.plus((long long)(k * TPS) * rowb).ld<cx<T>>(vo);
+      }
+    }
+    if constexpr (XLDS) {
+      const T* la = g.la + o * g.aslab + ib * g.arow;
+#pragma unroll
+      for (int r = 0; r < XR; ++r) {
+        const int j = tid0 + r * THREADS;
+        if (j < L) {
+          xr[0][r] = la[(long long)j * g.apitch];
+          xr[1][r] = la[g.aplane + (long long)j * g.apitch];
+        }
+      }
+    }
+  };
+
+  long long tile = blockIdx.x;
+  if (tile < ntiles) prefetch(tile);
+  for (; tile < ntiles; tile += gridDim.x) {
     // thread index through an empty asm: tile-invariant addresses stay inside the loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
@@ -350,46 +471,47 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     const int mi = tid >> LGQ;
     const long long o = tile / a.ntile_inner;  // slab (instance of a batch)
     const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
-    // ---- per pair: column decode, eigenvalue coefficients, face weights
+    // ---- per pair: column decode, eigenvalue coefficients (divided by the scale), face values
     const long long ib = c0 / a.fs.na;  // one row per tile
     const long long ca = c0 + 2 * q;
     const int iaa = (int)(ca - ib * a.fs.na), iab = iaa + 1;
     const bool va = ca < inner && iaa < a.fs.nva, vb = ca + 1 < inner && iab < a.fs.nva;
     const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
+    const T isc = T(1) / a.fs.scale;
     T Aa = 1, Ba = 0, Ab = 1, Bb = 0;
     if (va) {
       const T sa = a.fs.s_a[iaa];
-      Aa = sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb);
-      Ba = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt;
+      Aa = (sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb)) * isc;
+      Ba = (T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt) * isc;
     }
     if (vb) {
       const T sa = a.fs.s_a[iab];
-      Ab = sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb);
-      Bb = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt;
+      Ab = (sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb)) * isc;
+      Bb = (T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt) * isc;
     }
-    const T* lp = g.lp + o * g.pslab;
-    const T* la = g.la + o * g.aslab + ib * g.arow;  // x-face rows of this tile
-    T pla = 0, pha = 0, plb = 0, phb = 0, wla = 0, wha = 0, wlb = 0, whb = 0;
+    const T* lp = g.lp + o * g.pslab + (modd ? 0 : g.pplane);
+    T pa = 0, pb = 0, wla = 0, wlb = 0;
     if (va) {
-      pla = lp[ca];
-      pha = lp[g.pplane + ca];
+      pa = lp[ca];
       wla = g.wa[iaa];
-      wha = g.wa[g.nwa + iaa];
     }
     if (vb) {
-      plb = lp[ca + 1];
-      phb = lp[g.pplane + ca + 1];
+      pb = lp[ca + 1];
       wlb = g.wa[iab];
-      whb = g.wa[g.nwa + iab];
     }
-    T bl = 0, bh = 0;
-    const T* lb = nullptr;
-    if (has_b) {
-      bl = g.wb[ib];
-      bh = g.wb[g.nwb + ib];
-      lb = g.lb + o * g.bslab + (va ? iaa : 0);  // y-face rows: both pencils of the pair
+    const T wbl = has_b ? g.wb[ib] : T(0);
+    const T* la = g.la + o * g.aslab + ib * g.arow;
+    if constexpr (XLDS) {
+#pragma unroll
+      for (int r = 0; r < XR; ++r) {
+        const int j = tid + r * THREADS;
+        if (j < L) {
+          xrow[j] = xr[0][r];
+          xrow[L + j] = xr[1][r];
+        }
+      }
     }
-    const T scale = a.fs.scale;
+    __syncthreads();  // x-face row (and, first time round, the tables) visible
     // ---- generate positions m = 1 + mi + k TPS of pair q
     cx<T>* sq = lds + q * LDQ;
     cx<T>* lo = sq + pad(1 + mi);
@@ -397,22 +519,34 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     for (int k = 0; k < PPT; ++k) {
       const int m = 1 + mi + k * TPS;
       if (k < PPT - 1 || m < N) {
-        const T wpl = g.wp[m - 1], wph = g.wp[L + m - 1];
-        const T st = a.fs.s_this[m - 1];
-        const int oa = (m - 1) * g.apitch;
-        const T xl = la[oa], xh = la[g.aplane + oa];
-        T ga = pla * wpl + pha * wph + xl * wla + xh * wha;
-        T gb = plb * wpl + phb * wph + xl * wlb + xh * whb;
+        T wpl, st;
+        if constexpr (TLDS) {
+          wpl = tab[m - 1];
+          st = tab[L + m - 1];
+        } else if constexpr (TREG) {
+          wpl = wpr[k];
+          st = str[k];
+        } else {
+          wpl = g.wp[m - 1];
+          st = a.fs.s_this[m - 1];
+        }
+        T xa, xb;
+        if constexpr (XLDS) {
+          xa = xrow[m - 1];
+          xb = xrow[L + m - 1];
+        } else {
+          xa = la[(long long)(m - 1) * g.apitch];
+          xb = la[g.aplane + (long long)(m - 1) * g.apitch];
+        }
+        T ga = pa * wpl + xa * wla;
+        T gb = pb * wpl + xb * wlb;
         if (has_b) {
-          const int ob = (m - 1) * g.bpitch;
-          const cx<T> yl = *reinterpret_cast<const cx<T>*>(lb + ob);
-          const cx<T> yh = *reinterpret_cast<const cx<T>*>(lb + g.bplane + ob);
-          ga += yl.x * bl + yh.x * bh;
-          gb += yl.y * bl + yh.y * bh;
+          ga += yb[k].x * wbl;
+          gb += yb[k].y * wbl;
         }
         cx<T> v;
-        v.x = va ? ga * (scale * recip(Aa + Ba * st)) : T(0);
-        v.y = vb ? gb * (scale * recip(Ab + Bb * st)) : T(0);
+        v.x = va ? ga * recip(Aa + Ba * st) : T(0);
+        v.y = vb ? gb * recip(Ab + Bb * st) : T(0);
         if (LIN) lo[poff(k * TPS)] = v;
         else sq[pad(m)] = v;
       }
@@ -424,6 +558,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       lds[tid * LDQ] = z;
     }
     __syncthreads();
+    // the next tile's face data is in flight during the transform below
+    const long long nxt = tile + gridDim.x;
+    if (nxt < ntiles) prefetch(nxt);
     // ---- inverse transform along the pass axis
     const int s = tid / TPS;
     const int ts = tid - s * TPS;
@@ -438,14 +575,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     __syncthreads();  // the store reads other pairs' sequences
     // ---- store (uniform row bases, fixed per-lane byte offsets)
     if (c0 + 2 * q < inner) {
-      const long long rowb = inner * (long long)sizeof(T);
+      const long long orowb = inner * (long long)sizeof(T);
       const SBase dst(a.out + o * (long long)L * inner + c0);
       unsigned vs = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
       asm volatile("" : "+v"(vs));
 #pragma unroll
       for (int k = 0; k < PPT; ++k) {
         const int m = 1 + mi + k * TPS;
-        if (k < PPT - 1 || m < N) dst.plus((long long)(k * TPS) * rowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+        if (k < PPT - 1 || m < N) dst.plus((long long)(k * TPS) * orowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
       }
     }
     __syncthreads();  // the next tile overwrites LDS
@@ -456,8 +593,7 @@ template <typename T, int N> struct GenPipeLaunch {
   static constexpr int NSEQ = pipe_nseq<T, N>();
   static constexpr int TPS = N / PipePlan<N>::PPT;
   static constexpr int THREADS = NSEQ * TPS;
-  static constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) *
-                                sizeof(cx<T>);
+  static constexpr size_t LDS = GenShape<T, N, NSEQ>::LDS;
 
   static int resident() {
     static std::once_flag once;
@@ -481,11 +617,20 @@ template <typename T, int N> struct GenPipeLaunch {
     if (a.fs.na % (2 * NSEQ) != 0 || (a.inner & 1)) return ST_UNSUPPORTED;
     if (a.g.lb && ((a.g.bpitch & 1) || (a.g.bplane & 1) || (a.g.bslab & 1))) return ST_UNSUPPORTED;
     if ((double)(TPS + 1) * (double)a.inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+    if (a.g.lb && (double)(TPS + 1) * (double)a.g.bpitch * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
     const int res = resident();
     if (res <= 0) return ST_UNSUPPORTED;
     a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
+    // the face pairs into their sums and differences (in place; the arrays are this pass's
+    // input only).  Per slab: z faces pplane, x faces aplane, y faces bplane entries.
+    T* lp = const_cast<T*>(a.g.lp);
+    T* la = const_cast<T*>(a.g.la);
+    T* lb = const_cast<T*>(a.g.lb);
+    TRY_ST(face_pm<T>(lp, a.g.pplane, a.outer > 1 ? a.g.pslab : 0, a.g.pplane, a.outer, st));
+    TRY_ST(face_pm<T>(la, a.g.aplane, a.outer > 1 ? a.g.aslab : 0, a.g.aplane, a.outer, st));
+    if (lb) TRY_ST(face_pm<T>(lb, a.g.bplane, a.outer > 1 ? a.g.bslab : 0, a.g.bplane, a.outer, st));
     const long long grid = ntiles < res ? ntiles : res;
     hipLaunchKernelGGL((k_gen_pipe<T, N, NSEQ>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
     AHOC_HIP_TRY(hipGetLastError());
