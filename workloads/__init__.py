@@ -29,7 +29,7 @@ import numpy as np
 __all__ = [
     "Problem", "manufactured", "config1", "config2", "config3", "config4_specs",
     "config4_instance", "cavity", "plate", "poly_exact", "node_coords", "example1",
-    "high_wavenumber", "example2", "example3",
+    "high_wavenumber", "example2", "example3", "TriProblem", "triharmonic", "example3_tri",
 ]
 
 
@@ -481,3 +481,155 @@ def poly_exact(n, dim=2, **kw):
         lo, hi = (-0.3, 0.1, 0.2), (0.9, 1.4, 1.1)
     return manufactured(a, u, n if isinstance(n, (tuple, list)) else (n,) * dim, lo, hi,
                         name=f"poly{dim}d", **kw)
+
+
+# --------------------------------------------------------------------------------------
+# the triharmonic extension (Sec. 4.2): Delta^3 u = f
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class TriProblem:
+    """One triharmonic problem Delta^3 u = f on a box (Sec. 4.2, "Triharmonic equation").
+
+    Clamped faces carry u = g_D, u_n = g_N, u_nn = g_NN; Navier faces (navier[f]) u = g_D,
+    Delta u and Delta^2 u.  Nodal arrays (memory order z, y, x), None = identically zero:
+      f      the right-hand side Delta^3 u
+      gD     u on boundary nodes
+      gN     outward normal derivative on face-interior nodes of clamped faces
+      gNN    second normal derivative on face-interior nodes of clamped faces
+      lapu   Delta u on every boundary node (the boundary values of v = Delta u, which the
+             data fix on every face: u_nn plus the tangential Laplacian of g_D on a clamped
+             face, given on a Navier face)
+      bilap  Delta^2 u on boundary nodes (read on Navier faces, edges and corners, where w =
+             Delta v is known)
+      tang4  on face-interior nodes of clamped faces, Delta^2 u minus its pure normal part
+             u_nnnn (what the Dirichlet data and g_NN fix: 2 Delta_tau u_nn + Delta_tau^2 u)
+    """
+    n: tuple
+    lo: tuple
+    hi: tuple
+    f: Any
+    gD: Any = None
+    gN: Any = None
+    gNN: Any = None
+    lapu: Any = None
+    bilap: Any = None
+    tang4: Any = None
+    u_exact: Any = None
+    name: str = ""
+    navier: tuple = ()
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def dim(self) -> int:
+        return len(self.n)
+
+    @property
+    def h(self) -> tuple:
+        return tuple((b - a) / m for a, b, m in zip(self.lo, self.hi, self.n))
+
+
+@functools.lru_cache(maxsize=None)
+def _derive_tri(u_src: str, dim: int, params: tuple = ()):
+    import sympy as sp
+    X = _symbols(dim)
+    ns = {s.name: s for s in X}
+    ns.update({p: sp.Symbol(p) for p in params})
+    ns.update({"pi": sp.pi, "sin": sp.sin, "cos": sp.cos, "exp": sp.exp, "sqrt": sp.sqrt})
+    u = sp.sympify(u_src, locals=ns)
+    lap = lambda w: sum(sp.diff(w, s, 2) for s in X)
+    v = lap(u)
+    w = lap(v)
+    ex = {"u": u, "v": v, "w": w, "f": lap(w)}
+    for a in range(dim):
+        ex[f"d1u{a}"] = sp.diff(u, X[a])
+        ex[f"d2u{a}"] = sp.diff(u, X[a], 2)
+        ex[f"d4u{a}"] = sp.diff(u, X[a], 4)
+    return X, tuple(sp.Symbol(p) for p in params), ex
+
+
+def triharmonic(u_src: str, n: Sequence[int], lo=None, hi=None, *, params=(), pvals=(), navier=(),
+                xp="numpy", device=None, chunk=None, name=""):
+    """Sample a manufactured triharmonic problem: f = Delta^3 u and the boundary data of
+    TriProblem from the expression u_src (in x, y[, z] and `params`)."""
+    dim = len(n)
+    lo = tuple(lo) if lo is not None else (0.0,) * dim
+    hi = tuple(hi) if hi is not None else (1.0,) * dim
+    X, P, ex = _derive_tri(u_src, dim, tuple(params))
+    fns = {k: _lambdify(e, X, P, xp) for k, e in ex.items()}
+    ev = _Eval("1", u_src, dim, params, pvals, xp, device)
+    c1d = node_coords(n, lo, hi)
+    shape = tuple(n[a] + 1 for a in reversed(range(dim)))
+
+    def at(key, cs):
+        out = fns[key](*cs, *pvals)
+        if xp == "torch":
+            import torch
+            shp = tuple(torch.broadcast_shapes(*[tuple(c.shape) for c in cs]))
+        else:
+            shp = np.broadcast_shapes(*[c.shape for c in cs])
+        return ev._full(out, shp)
+
+    f = _zeros(ev, shape)
+    ue = _zeros(ev, shape)
+    if dim == 3 and chunk is not None:
+        for z0 in range(0, n[2] + 1, chunk):
+            z1 = min(n[2] + 1, z0 + chunk)
+            cs = [ev.coords(c1d[0], 0), ev.coords(c1d[1], 1), ev.coords(c1d[2][z0:z1], 2)]
+            f[z0:z1] = at("f", cs)
+            ue[z0:z1] = at("u", cs)
+    else:
+        cs = [ev.coords(c1d[a], a) for a in range(dim)]
+        f[...] = at("f", cs)
+        ue[...] = at("u", cs)
+    nav = tuple(bool(v) for v in navier) if any(navier) else (False,) * (2 * dim)
+    if len(nav) != 2 * dim:
+        raise ValueError("navier needs one flag per face")
+    gD, gN, gNN, lapu, bilap, tang4 = (_zeros(ev, shape) for _ in range(6))
+
+    def sl(axis, idx):
+        s_ = [slice(None)] * dim
+        s_[dim - 1 - axis] = slice(idx, idx + 1)
+        return tuple(s_)
+
+    for a in range(dim):
+        for side, idx in ((0, 0), (1, n[a])):
+            cs = [ev.coords(c1d[b], b) if b != a else ev.coords(c1d[a][idx:idx + 1], a) for b in range(dim)]
+            tgt = sl(a, idx)
+            gD[tgt] = at("u", cs)
+            lapu[tgt] = at("v", cs)
+            bilap[tgt] = at("w", cs)
+            if nav[2 * a + side]:
+                continue
+            inner = [slice(None)] * dim
+            for b in range(dim):
+                if b != a:
+                    inner[dim - 1 - b] = slice(1, n[b])
+            inner = tuple(inner)
+            du = at(f"d1u{a}", cs)
+            vals = {"gN": -du if side == 0 else du, "gNN": at(f"d2u{a}", cs),
+                    "tang4": at("w", cs) - at(f"d4u{a}", cs)}
+            for key, arr in (("gN", gN), ("gNN", gNN), ("tang4", tang4)):
+                sub = arr[tgt]
+                sub[inner] = vals[key][inner]
+                arr[tgt] = sub
+    out = []
+    for arr in (gD, gN, gNN, lapu, bilap, tang4):
+        mx = float(arr.abs().max()) if xp == "torch" else float(np.abs(arr).max())
+        out.append(None if mx < 1e-12 else arr)
+    return TriProblem(tuple(n), lo, hi, f, *out, u_exact=ue, name=name or f"tri{dim}d",
+                      navier=nav, meta={"u": u_src, "params": dict(zip(params, pvals))})
+
+
+EX3_TRI_U = "sin(k1*x)*cos(k2*y)*sin(k3*z)"
+
+
+def example3_tri(n=32, k=(5.0, 1.0, 5.0), **kw):
+    """The triharmonic test of Sec. 4.2 (Table 5): the solution of the 3-D oscillatory example,
+    u = sin(k1 x) cos(k2 y) sin(k3 z), on the unit cube, clamped at x = 0 and Navier on the
+    other faces (the boundary setting of the paper's convergence tests)."""
+    nn = tuple(n) if isinstance(n, (tuple, list)) else (n, n, n)
+    k = tuple(float(v) for v in k)
+    return triharmonic(EX3_TRI_U, nn, params=("k1", "k2", "k3"), pvals=k,
+                       navier=(False, True, True, True, True, True),
+                       name=f"tri_ex3_n{nn[0]}_k{k[0]:g}_{k[1]:g}_{k[2]:g}", **kw)
