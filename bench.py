@@ -53,9 +53,10 @@ def _src_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(n=80):
-    """The oracle's Algorithm-1 tier (scipy DST-I, numpy stencils, FP64 GMRES) on the same
-    problem family at n^3, timed on this host."""
+def cpu_baseline(n=128, tol=1e-10):
+    """The oracle's Algorithm-1 tier (scipy DST-I, numpy stencils, FP64 GMRES(30), no
+    preconditioner) on the benchmark's 3-D problem at n^3 -- the same configuration the line
+    also reports GPU times for (gpu_same_config) -- timed on this host's cores."""
     import numpy as np
     import workloads as W
     from oracle import fast
@@ -63,14 +64,33 @@ def cpu_baseline(n=80):
     p = W.config3(n)
     t0 = time.perf_counter()
     ft = fast.FastTier(p, workers=cores)
-    U, V, Q, info = ft.solve(tol=1e-11)
+    U, V, Q, info = ft.solve(tol=tol)
     dt = time.perf_counter() - t0
     err = float(np.abs(U - p.u_exact).max() / np.abs(p.u_exact).max())
     return {"value": n ** 3 / dt, "unit": "DOF/s", "cores": cores, "kind": "oracle",
-            "sample": f"one FP64 fast-tier solve (scipy DST-I + own GMRES(30), tol 1e-11) of the "
-                      f"same 3-D problem at n={n} ({info['iters']} GMRES iterations, {dt:.1f} s, "
-                      f"rel err vs exact {err:.2e}); DOF = n^3",
-            "time_s": dt}
+            "sample": f"one whole FP64 fast-tier solve (scipy DST-I with workers={cores}, numpy stencils, "
+                      f"own GMRES(30) without preconditioner, Schur tol {tol:g}) of the benchmark's 3-D problem "
+                      f"at n={n} ({info['iters']} GMRES iterations, {dt:.1f} s, rel err vs exact {err:.2e}); "
+                      f"DOF = n^3; the GPU's times for this configuration are in config.gpu_same_config",
+            "time_s": dt, "n": n}
+
+
+def gpu_same_config(ah, W, torch, dev, n, tol, steps=3):
+    """GPU solve times of the CPU baseline's configuration (the 3-D problem at n^3, the same
+    Schur tolerance), both forms, after a warm-up solve; setup excluded."""
+    prob = W.config3(n, xp="torch", device=dev)
+    out = {"n": n, "tol": tol}
+    for name, prec in (("mixed", ah.MIXED), ("fp64", ah.FP64)):
+        with ah.Solver(prob, precision=prec, tol=tol) as s:
+            s.solve()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(steps):
+                _, _, _, st = s.solve()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / steps
+        out[name] = {"ms": dt * 1e3, "dof_per_s": n ** 3 / dt, "gmres_iters": st.gmres_iters}
+    return out
 
 
 def _pitch(n):
@@ -169,7 +189,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=80)
+    ap.add_argument("--cpu-n", type=int, default=128,
+                    help="grid of the CPU oracle baseline (and of the GPU times reported beside it)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-10,
@@ -285,8 +306,14 @@ def main():
 
     choices = {}
 
+    setup_ms = {}
+
     def run(prec, steps, warmup, **opts):
+        torch.cuda.synchronize()
+        t_s = time.perf_counter()
         s = ah.Solver(prob, precision=prec, **opts)
+        torch.cuda.synchronize()
+        setup_ms["mixed" if prec == ah.MIXED else "fp64"] = (time.perf_counter() - t_s) * 1e3
         # setup-time kernel choice of the operator's plain DST passes (x rows, y strided)
         for name, axis, kind in (("x_rows", 0, 0), ("y_strided", 1, 1)):
             m, tile, td, tg, tb = s.dst_choice(prec, axis, kind)
@@ -424,8 +451,14 @@ def main():
         del bprobs, ref_b
 
     cpu = None
+    same = None
     if not args.no_cpu:
-        cpu = cpu_baseline(args.cpu_n)
+        cpu = cpu_baseline(args.cpu_n, args.tol)
+        same = gpu_same_config(ah, W, torch, dev, args.cpu_n, args.tol)
+        same["cpu_oracle_s"] = cpu["time_s"]
+        same["gpu_mixed_speedup_over_cpu_oracle"] = cpu["time_s"] * 1e3 / same["mixed"]["ms"]
+        print(f"[bench] CPU oracle n={args.cpu_n}: {cpu['time_s']:.1f} s; GPU mixed {same['mixed']['ms']:.1f} ms, "
+              f"FP64 {same['fp64']['ms']:.1f} ms", file=sys.stderr, flush=True)
 
     st = st_mx[-1]
     line = {
@@ -449,6 +482,11 @@ def main():
                    "gmres_iters": st.gmres_iters, "sweeps": st.sweeps, "schur_relres": st.schur_relres,
                    "rel_err_vs_fp64_ref": err_mx_ref, "rel_err_vs_exact": err_mx_exact,
                    "model_bytes": bytes_mx, "end_to_end_hbm_frac": bytes_mx / dt_mx / (HBM_PEAK_GBS * 1e9),
+                   "setup_ms": setup_ms,
+                   "time_to_solution_incl_setup_ms": {k: v + (dt_mx * 1e3 if k == "mixed" else
+                                                              (result_fp64["ms_per_step"] if result_fp64 else 0.0))
+                                                      for k, v in setup_ms.items()},
+                   "gpu_same_config": same,
                    "fp64_ref": {"tol": 1e-13, "gmres_iters": st_ref.gmres_iters},
                    "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels,
                    "dst_kernel_choice": choices},

@@ -105,7 +105,31 @@ typedef struct {
   int navier;
   const double* gL;
   const double* beta_nodal;
+  /* equation: AHOC_BIHARMONIC (0) for eq. (1) above, or AHOC_TRIHARMONIC (1) for the
+   * sixth-order problem of Sec. 4.2, Delta^3 u = f (f in that sign; alpha, beta, lapgD, gL
+   * and beta_nodal unused), solved as Delta u = v, Delta v = w, Delta w = f with the compact
+   * scheme and w = Q on the face interiors.  Clamped faces carry u = g_D, u_n = g_N,
+   * u_nn = gNN; Navier faces u = g_D, Delta u = lapu, Delta^2 u = bilap.  The q-row of a
+   * clamped face is the augmented equation q = Delta^2 u with the one-sided fourth normal
+   * derivative of U from U_1..U_4 and u, u_n, u_nn (so n[a] >= 5), plus tang4.  The
+   * boundary-symbol preconditioner (precond = 1) takes the triharmonic chain's face-pair
+   * symbol; MIXED needs refine = 1; v outputs and batches of lock-step instances are not
+   * offered (AHOC_E_UNSUPPORTED for v, solo jobs in ahoc_solve_batched).  Arrays nodal,
+   * NULL = 0:
+   *   gNN    on face-interior nodes of clamped faces: the second normal derivative of u
+   *   lapu   on every boundary node: Delta u (on a clamped face u_nn plus the tangential
+   *          Laplacian of g_D)
+   *   bilap  on Navier faces, edges and corners: Delta^2 u
+   *   tang4  on face-interior nodes of clamped faces: Delta^2 u minus its pure normal part
+   *          u_nnnn (what g_D and gNN fix) */
+  int equation;
+  const double* gNN;
+  const double* lapu;
+  const double* bilap;
+  const double* tang4;
 } ahoc_problem;
+
+enum { AHOC_BIHARMONIC = 0, AHOC_TRIHARMONIC = 1 };
 
 typedef struct {
   int precision;      /* ahoc_precision                                              */

@@ -25,6 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_INVALID, E_NOMEM, E_NOCONV, E_HIP, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 FP64, MIXED = 0, 1
+BIHARMONIC, TRIHARMONIC = 0, 1
 
 c_int, c_double, c_void_p, c_size_t = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -33,7 +34,8 @@ class _Problem(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int * 3), ("lo", c_double * 3), ("hi", c_double * 3),
                 ("alpha", c_void_p), ("f", c_void_p), ("gD", c_void_p), ("gN", c_void_p),
                 ("lapgD", c_void_p), ("beta", c_double), ("navier", c_int), ("gL", c_void_p),
-                ("beta_nodal", c_void_p)]
+                ("beta_nodal", c_void_p), ("equation", c_int), ("gNN", c_void_p), ("lapu", c_void_p),
+                ("bilap", c_void_p), ("tang4", c_void_p)]
 
 
 class _Options(ctypes.Structure):
@@ -222,6 +224,12 @@ def _allocator_arg(allocator, device):
 
 
 _FIELDS = ("alpha", "f", "gD", "gN", "lapgD", "gL")
+_TRI_FIELDS = ("gNN", "lapu", "bilap", "tang4")
+
+
+def _equation(problem) -> int:
+    """TRIHARMONIC for a workloads.TriProblem-like object (it carries bilap), else BIHARMONIC."""
+    return TRIHARMONIC if hasattr(problem, "bilap") else BIHARMONIC
 
 
 def _navier_mask(navier) -> int:
@@ -232,27 +240,29 @@ def _navier_mask(navier) -> int:
 
 
 def _problem_tensors(problem, device):
-    """Device tensors of the nodal fields (_FIELDS, then a variable beta or None) and the
-    constant beta (0 when beta is nodal)."""
+    """Device tensors of the nodal fields (_FIELDS, a variable beta or None, then _TRI_FIELDS)
+    and the constant beta (0 when beta is nodal)."""
     beta = getattr(problem, "beta", 0.0)
     scalar = beta is None or np.isscalar(beta) or (hasattr(beta, "ndim") and beta.ndim == 0)
     tens = [_dev(getattr(problem, k, None), device) for k in _FIELDS]
     tens.append(None if scalar else _dev(beta, device))
+    tens += [_dev(getattr(problem, k, None), device) for k in _TRI_FIELDS]
     return tens, (float(beta or 0.0) if scalar else 0.0)
 
 
-def _problem_struct(n, lo, hi, tens, beta=0.0, navier=()):
+def _problem_struct(n, lo, hi, tens, beta=0.0, navier=(), equation=BIHARMONIC):
     dim = len(n)
     p = _Problem()
     p.dim = dim
     p.beta = float(beta or 0.0)
     p.navier = _navier_mask(navier)
+    p.equation = int(equation)
     for a in range(3):
         p.n[a] = int(n[a]) if a < dim else 0
         p.lo[a] = float(lo[a]) if a < dim else 0.0
         p.hi[a] = float(hi[a]) if a < dim else 0.0
-    p.alpha, p.f, p.gD, p.gN, p.lapgD, p.gL, p.beta_nodal = [(t.data_ptr() if t is not None else None)
-                                                             for t in tens]
+    (p.alpha, p.f, p.gD, p.gN, p.lapgD, p.gL, p.beta_nodal,
+     p.gNN, p.lapu, p.bilap, p.tang4) = [(t.data_ptr() if t is not None else None) for t in tens]
     return p
 
 
@@ -262,7 +272,8 @@ class Solver:
     `problem` carries n, lo, hi, nodal alpha, f, gD, gN, lapgD (numpy or torch, memory
     order z, y, x) and optionally beta (a constant, or a nodal array: FP64 only) and Navier
     faces (navier: per-face flags or a bitmask, gL: nodal Delta u read on them), e.g. a
-    workloads.Problem.
+    workloads.Problem; or, for the triharmonic equation Delta^3 u = f, f, gD, gN, gNN, lapu,
+    bilap, tang4 and navier (a workloads.TriProblem).
 
     allocator: "torch" (default) takes the handle's device memory from PyTorch's caching
     allocator (ahoc_allocator callbacks); None lets the library call hipMalloc.
@@ -274,7 +285,8 @@ class Solver:
         self.n = tuple(problem.n)
         self.dim = len(self.n)
         tens, beta = _problem_tensors(problem, self.device)
-        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, beta, getattr(problem, "navier", ()))
+        self._p = _problem_struct(self.n, problem.lo, problem.hi, tens, beta, getattr(problem, "navier", ()),
+                                  _equation(problem))
         self.options = default_options(precision, **opts)
         h = _H()
         with torch.cuda.device(self.device):
@@ -394,7 +406,7 @@ def solve_batched(problems: Sequence, precision=FP64, device="cuda:0", allocator
     for pb in problems:
         tens, beta = _problem_tensors(pb, dev)
         keep.append(tens)
-        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, beta, getattr(pb, "navier", ())))
+        structs.append(_problem_struct(pb.n, pb.lo, pb.hi, tens, beta, getattr(pb, "navier", ()), _equation(pb)))
         outs.append(torch.empty(tuple(m + 1 for m in reversed(pb.n)), dtype=torch.float64, device=dev))
     cnt = len(problems)
     parr = (_Problem * cnt)(*structs)

@@ -76,6 +76,9 @@ struct ahoc_handle {
   Geom g;
   Weights w;
   Weights wv;          // the v-equation's lift weights (normal weight shifted by -c m1)
+  // triharmonic extension: src_v, src_u and src_t are the sources of the W-, V- and U-solves
+  bool tri = false;
+  double* src_t = nullptr;
   double cshift = 0;   // the v-equation's shift c = beta/alpha (constant alpha), 0 for beta = 0
   int navier = 0;      // bit f set: face f (2 axis + side) is a Navier face
   // variable beta: nodal c = beta / alpha, the V-solve by BiCGSTAB preconditioned by the
@@ -700,7 +703,12 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
       tv[L + k - 1] = (double)cosl(pi * k / (long double)g.n[a]);
       tv[2 * L + k - 1] = (double)sinl(pi * k / (long double)g.n[a]);
       long double acc = 0;
-      for (int m = 1; m <= 3; ++m) acc += (long double)h->w.os[m] * sinl(pi * k * m / (long double)g.n[a]);
+      if (h->tri) {  // the triharmonic q-row's fourth-derivative combination of U_1..U_4
+        const long double a4[4] = {-104.0L, 57.0L / 2.0L, -56.0L / 9.0L, 11.0L / 16.0L};
+        for (int m = 1; m <= 4; ++m) acc += a4[m - 1] * sinl(pi * k * m / (long double)g.n[a]);
+      } else {
+        for (int m = 1; m <= 3; ++m) acc += (long double)h->w.os[m] * sinl(pi * k * m / (long double)g.n[a]);
+      }
       tv[3 * L + k - 1] = (double)acc;
     }
     double* d = nullptr;
@@ -711,7 +719,7 @@ int precond_init(ahoc_handle* h, hipStream_t st) {
   }
   TRY(alloc_t(h, &h->pc, g.nq));
   TRY(alloc_t(h, &h->qc, g.nq));
-  TRY(precond_symbol(g, h->wv, h->cshift, h->navier, tabs.data(), h->pc, h->qc, st));
+  TRY(precond_symbol(g, h->wv, h->cshift, h->navier, tabs.data(), h->pc, h->qc, st, h->tri));
   if (h->p64.ready) {
     for (int a = 0; a < g.dim; ++a) h->ptb[a] = h->p64.tb[a];
     h->ptb_own = false;
@@ -772,12 +780,40 @@ template <typename T> const T* q_in(ahoc_handle* h, Prec<T>& P, const double* q,
   }
 }
 
+// Triharmonic extension: the three chained Dirichlet solves from the face values Q of W
+// (sources sw, sv, su of the W-, V- and U-solves, or none for the homogeneous form):
+// W into P.bufA, V = L^-1(M W + sv) into P.bufB, then U = L^-1(M V + su) into P.bufA.
+// Without sources the W-solve takes the spectral lift when the grid has it.
+template <typename T>
+int tri_fields(ahoc_handle* h, Prec<T>& P, const T* Q, const T* sw, const T* sv, const T* su, hipStream_t st) {
+  if (!sw && P.spectral) TRY(vsolve_spec<T>(h, P, Q, st));
+  else TRY(vsolve<T>(h, P, Q, sw, st));
+  TRY(usolve<T>(h, P, Q, sv, st));
+  hipEvent_t e = tbegin(h, st);
+  TRY(rhs_u<T>(h->g, h->w, P.bufB, P.zq, P.ia, su, P.bufA, st));
+  tend(h, AHOC_K_RHS_U, e, (double)sizeof(T) * (2.0 * h->g.nint + h->g.nnodal), st);
+  return poisson<T>(h, P, P.bufA, P.scU, st);
+}
+
+template <typename T> int tri_gather(ahoc_handle* h, Prec<T>& P, const T* Q, const T* srcq, double* R, hipStream_t st) {
+  hipEvent_t eg = tbegin(h, st);
+  TRY(gather_tri<T>(h->g, P.bufA, Q, P.af, srcq, R, st));
+  tend(h, AHOC_K_GATHER, eg, (double)h->g.nq * (5 * sizeof(T) + sizeof(double)), st);
+  return ST_OK;
+}
+
 // y = S_h q  (homogeneous Lemma-1 form)
 template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, double* y, hipStream_t st) {
   int rc = 0;
   hipEvent_t e = tbegin(h, st);
   const T* qT = q_in<T>(h, P, q, st, &rc);
   TRY(rc);
+  if (h->tri) {
+    TRY(tri_fields<T>(h, P, qT, nullptr, nullptr, nullptr, st));
+    TRY(tri_gather<T>(h, P, qT, nullptr, y, st));
+    tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (34.0 * h->g.nint + 2.0 * h->g.nnodal), st);
+    return ST_OK;
+  }
   if (P.spectral) {
     TRY(vsolve_spec<T>(h, P, qT, st));
     TRY(usolve_spec<T>(h, P, qT, nullptr, st));
@@ -807,6 +843,15 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
 // b = -R(0) for sources (src_v, src_u, src_q) in precision T
 template <typename T>
 int schur_rhs(ahoc_handle* h, Prec<T>& P, const T* sv, const T* su, const T* sq, double* b, hipStream_t st) {
+  if (h->tri) {
+    if constexpr (sizeof(T) == 8) {
+      TRY(tri_fields<T>(h, P, P.zq, sv, su, h->src_t, st));
+      TRY(tri_gather<T>(h, P, P.zq, sq, h->R, st));
+      return axpby(TQ(h->g), -1.0, h->R, 0.0, b, st);
+    } else {
+      return ST_UNSUPPORTED;
+    }
+  }
   TRY(vsolve<T>(h, P, P.zq, sv, st));
   if (P.spectral) {
     TRY(usolve_spec<T>(h, P, P.zq, su, st));
@@ -1131,6 +1176,17 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   make_weights(g, h->w);
   h->wv = h->w;
   h->m = h->opt.restart;
+  h->tri = pb->equation == AHOC_TRIHARMONIC;
+  if (h->tri) {
+    if (count != 1) {
+      set_last_error("triharmonic problems are set up one per handle", "ahoc_setup");
+      return ST_UNSUPPORTED;
+    }
+    if (h->opt.precision == AHOC_MIXED && h->opt.refine != 1) {
+      set_last_error("the triharmonic equation in MIXED precision needs refine = 1", "ahoc_setup");
+      return ST_UNSUPPORTED;
+    }
+  }
   const double *alpha = pb->alpha, *f = pb->f, *gD = pb->gD, *gN = pb->gN, *lapgD = pb->lapgD, *gL = pb->gL;
   for (int i = 0; i < count; ++i)
     if (pbs[i].navier != pb->navier) {
@@ -1169,71 +1225,82 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
     TRY(alloc_t(h, &ia32, TN(g)));
     TRY(alloc_t(h, &af32, TQ(g)));
   }
-  TRY(setup_inv_alpha(TN(g), alpha, h->ia64, ia32, h->red, 1024, st));
-  {
-    std::vector<double> hb(1024);
-    AHOC_HIP_TRY(hipMemcpyAsync(hb.data(), h->red, sizeof(double) * 1024, hipMemcpyDeviceToHost, st));
-    AHOC_HIP_TRY(hipStreamSynchronize(st));
-    double mn = 1e300;
-    for (double v : hb) mn = v < mn ? v : mn;
-    if (!(mn > 0.0)) {
-      set_last_error("alpha must be positive everywhere", "ahoc_setup");
-      return ST_INVALID;
-    }
-    if (pb->beta_nodal) {
-      if (count != 1 || h->opt.precision != AHOC_FP64) {
-        set_last_error("a variable beta needs FP64 precision and a single problem per handle", "ahoc_setup");
-        return ST_UNSUPPORTED;
-      }
-      h->cvar = true;
-      h->opt.use_graph = 0;  // the BiCGSTAB V-solve reads its dot products on the host
-      TRY(alloc_t(h, &h->cnod, TN(g)));
-      TRY(mul(TN(g), pb->beta_nodal, h->ia64, h->cnod, st));
-      TRY(minmax_partial(TN(g), h->cnod, h->red, 512, st));
+  if (h->tri) {
+    // Delta^3 u = f: no coefficient (1/alpha = 1 in the weighting-operator kernels); the
+    // sources of the W-, V- and U-solves and the q-rows' known part
+    TRY(fill(TN(g), 1.0, h->ia64, st));
+    if (ia32) TRY(convert<double, float>(TN(g), h->ia64, ia32, st));
+    if (!h->src_u) TRY(alloc_int(h, &h->src_u, st));
+    TRY(alloc_int(h, &h->src_t, st));
+    TRY(tri_sources(g, h->w, f, gD, pb->lapu, pb->bilap, h->src_v, h->src_u, h->src_t, st));
+    TRY(tri_srcq(g, h->navier, gD, gN, pb->gNN, pb->tang4, pb->bilap, h->src_q, h->af64, af32, st));
+  } else {
+    TRY(setup_inv_alpha(TN(g), alpha, h->ia64, ia32, h->red, 1024, st));
+    {
       std::vector<double> hb(1024);
       AHOC_HIP_TRY(hipMemcpyAsync(hb.data(), h->red, sizeof(double) * 1024, hipMemcpyDeviceToHost, st));
       AHOC_HIP_TRY(hipStreamSynchronize(st));
-      double cmin = 1e300, cmax = -1e300;
-      for (int b = 0; b < 512; ++b) {
-        cmin = std::min(cmin, hb[2 * b]);
-        cmax = std::max(cmax, hb[2 * b + 1]);
+      double mn = 1e300;
+      for (double v : hb) mn = v < mn ? v : mn;
+      if (!(mn > 0.0)) {
+        set_last_error("alpha must be positive everywhere", "ahoc_setup");
+        return ST_INVALID;
       }
-      h->cshift = 0.5 * (cmin + cmax);
-      for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
-      {  // one block of seven interior vectors, TA(g) apart (the dot sweeps rely on it)
-        double* blk = nullptr;
-        TRY(alloc_t(h, &blk, 7 * TA(g)));
-        AHOC_HIP_TRY(hipMemsetAsync(blk, 0, sizeof(double) * 7 * (size_t)TA(g), st));  // zero padding
-        for (int k = 0; k < 7; ++k) h->bk[k] = blk + k * TA(g);
+      if (pb->beta_nodal) {
+        if (count != 1 || h->opt.precision != AHOC_FP64) {
+          set_last_error("a variable beta needs FP64 precision and a single problem per handle", "ahoc_setup");
+          return ST_UNSUPPORTED;
+        }
+        h->cvar = true;
+        h->opt.use_graph = 0;  // the BiCGSTAB V-solve reads its dot products on the host
+        TRY(alloc_t(h, &h->cnod, TN(g)));
+        TRY(mul(TN(g), pb->beta_nodal, h->ia64, h->cnod, st));
+        TRY(minmax_partial(TN(g), h->cnod, h->red, 512, st));
+        std::vector<double> hb(1024);
+        AHOC_HIP_TRY(hipMemcpyAsync(hb.data(), h->red, sizeof(double) * 1024, hipMemcpyDeviceToHost, st));
+        AHOC_HIP_TRY(hipStreamSynchronize(st));
+        double cmin = 1e300, cmax = -1e300;
+        for (int b = 0; b < 512; ++b) {
+          cmin = std::min(cmin, hb[2 * b]);
+          cmax = std::max(cmax, hb[2 * b + 1]);
+        }
+        h->cshift = 0.5 * (cmin + cmax);
+        for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
+        {  // one block of seven interior vectors, TA(g) apart (the dot sweeps rely on it)
+          double* blk = nullptr;
+          TRY(alloc_t(h, &blk, 7 * TA(g)));
+          AHOC_HIP_TRY(hipMemsetAsync(blk, 0, sizeof(double) * 7 * (size_t)TA(g), st));  // zero padding
+          for (int k = 0; k < 7; ++k) h->bk[k] = blk + k * TA(g);
+        }
+        TRY(alloc_t(h, &h->bdot, 8));
+        TRY(alloc_t(h, &h->bpart, 2LL * VS_DOT_BLOCKS));
+        AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->bpin), sizeof(double) * 8, hipHostMallocDefault));
+      } else if (pb->beta != 0.0) {
+        // the v-equation -L_h V + (beta/alpha) M V = M f is solved by the sine transforms only
+        // for a constant shift beta/alpha
+        int rc = 0;
+        const double mx = absmax(h, alpha, true, TN(g), st, &rc);
+        TRY(rc);
+        if (count != 1 || mx - mn > 1e-14 * mx) {
+          set_last_error("beta != 0 needs a constant alpha (and a single problem per handle)", "ahoc_setup");
+          return ST_UNSUPPORTED;
+        }
+        if (h->opt.precision == AHOC_MIXED && h->opt.refine != 1) {
+          set_last_error("beta != 0 in MIXED precision needs refine = 1", "ahoc_setup");
+          return ST_UNSUPPORTED;
+        }
+        h->cshift = pb->beta / mx;
+        for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
       }
-      TRY(alloc_t(h, &h->bdot, 8));
-      TRY(alloc_t(h, &h->bpart, 2LL * VS_DOT_BLOCKS));
-      AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->bpin), sizeof(double) * 8, hipHostMallocDefault));
-    } else if (pb->beta != 0.0) {
-      // the v-equation -L_h V + (beta/alpha) M V = M f is solved by the sine transforms only
-      // for a constant shift beta/alpha
-      int rc = 0;
-      const double mx = absmax(h, alpha, true, TN(g), st, &rc);
-      TRY(rc);
-      if (count != 1 || mx - mn > 1e-14 * mx) {
-        set_last_error("beta != 0 needs a constant alpha (and a single problem per handle)", "ahoc_setup");
-        return ST_UNSUPPORTED;
-      }
-      if (h->opt.precision == AHOC_MIXED && h->opt.refine != 1) {
-        set_last_error("beta != 0 in MIXED precision needs refine = 1", "ahoc_setup");
-        return ST_UNSUPPORTED;
-      }
-      h->cshift = pb->beta / mx;
-      for (int a = 0; a < 3; ++a) h->wv.cf[a] = h->w.cf[a] - h->cshift * h->w.m1;
     }
-  }
-  TRY(setup_face_alpha(g, alpha, h->af64, af32, st));
-  TRY(setup_sources(g, h->w, f, alpha, gD, gN, lapgD, h->src_v, h->src_u, h->src_q, st));
-  if (h->navier) TRY(setup_navier(g, h->navier, alpha, gL, h->af64, af32, h->src_q, st));
-  if (lapgD) {
-    // V = alpha * Delta u on edges and corners (Remark 1); read there only
-    TRY(alloc_t(h, &h->vedge, TN(g)));
-    TRY(mul(TN(g), alpha, lapgD, h->vedge, st));
+    TRY(setup_face_alpha(g, alpha, h->af64, af32, st));
+    TRY(setup_sources(g, h->w, f, alpha, gD, gN, lapgD, h->src_v, h->src_u, h->src_q, st));
+    if (h->navier) TRY(setup_navier(g, h->navier, alpha, gL, h->af64, af32, h->src_q, st));
+    if (lapgD) {
+      // V = alpha * Delta u on edges and corners (Remark 1); read there only
+      TRY(alloc_t(h, &h->vedge, TN(g)));
+      TRY(mul(TN(g), alpha, lapgD, h->vedge, st));
+    }
   }
   // FP64 machinery (plain solve, or the refinement's reference operators)
   h->p64.ia = h->ia64;
@@ -1389,8 +1456,17 @@ static ahoc_status validate_problem(const ahoc_problem* pb) {
     ahoc::set_last_error("dim must be 2 or 3", "ahoc_setup");
     return AHOC_E_INVALID;
   }
-  if (!pb->alpha || !pb->f) {
-    ahoc::set_last_error("alpha and f are required", "ahoc_setup");
+  if (pb->equation != AHOC_BIHARMONIC && pb->equation != AHOC_TRIHARMONIC) {
+    ahoc::set_last_error("equation must be AHOC_BIHARMONIC or AHOC_TRIHARMONIC", "ahoc_setup");
+    return AHOC_E_INVALID;
+  }
+  const bool tri = pb->equation == AHOC_TRIHARMONIC;
+  if (!pb->f || (!tri && !pb->alpha)) {
+    ahoc::set_last_error(tri ? "f is required" : "alpha and f are required", "ahoc_setup");
+    return AHOC_E_INVALID;
+  }
+  if (tri && (pb->beta != 0.0 || pb->beta_nodal)) {
+    ahoc::set_last_error("the triharmonic equation has no beta term", "ahoc_setup");
     return AHOC_E_INVALID;
   }
   if (pb->navier & ~((1 << (2 * pb->dim)) - 1)) {
@@ -1398,9 +1474,11 @@ static ahoc_status validate_problem(const ahoc_problem* pb) {
     return AHOC_E_INVALID;
   }
   for (int a = 0; a < pb->dim; ++a) {
-    // the one-sided normal formula (Sec. 2.2) reads U_1, U_2, U_3 next to each face
-    if (pb->n[a] < 4 || pb->n[a] > ahoc::DST_MAX_N || !(pb->hi[a] > pb->lo[a])) {
-      ahoc::set_last_error("need 4 <= n[a] <= 8192 and hi > lo", "ahoc_setup");
+    // the one-sided normal formula (Sec. 2.2) reads U_1, U_2, U_3 next to each face (the
+    // triharmonic q-row U_1..U_4)
+    if (pb->n[a] < (tri ? 5 : 4) || pb->n[a] > ahoc::DST_MAX_N || !(pb->hi[a] > pb->lo[a])) {
+      ahoc::set_last_error(tri ? "need 5 <= n[a] <= 8192 and hi > lo" : "need 4 <= n[a] <= 8192 and hi > lo",
+                           "ahoc_setup");
       return AHOC_E_INVALID;
     }
   }
@@ -1556,9 +1634,14 @@ int solve_fp64(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stat
   if (warm) AHOC_HIP_TRY(hipMemcpyAsync(h->dq, q, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   TRY(schur_rhs<double>(h, P, h->src_v, h->src_u, h->src_q, h->bvec, st));
   TRY(gmres<double>(h, P, h->bvec, h->dq, h->opt.tol, h->opt.max_iters, gr, &mv, st, warm));
-  TRY(vsolve<double>(h, P, h->dq, h->src_v, st));
-  TRY(usolve<double>(h, P, h->dq, h->src_u, st));
-  TRY(write_u(h, P.bufB, u, st));
+  if (h->tri) {
+    TRY(tri_fields<double>(h, P, h->dq, h->src_v, h->src_u, h->src_t, st));
+    TRY(write_u(h, P.bufA, u, st));
+  } else {
+    TRY(vsolve<double>(h, P, h->dq, h->src_v, st));
+    TRY(usolve<double>(h, P, h->dq, h->src_u, st));
+    TRY(write_u(h, P.bufB, u, st));
+  }
   if (v) TRY(out_v<double>(g, P.bufA, h->dq, h->vedge, v, st));
   if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->dq, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
@@ -1657,9 +1740,14 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
     // anyway) and the gather give it, instead of an FP64 Schur matvec before the recovery.
     hipEvent_t er = tbegin(h, st);
     if (predict) {
-      TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
-      TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
-      TRY(gather<double>(g, h->w, D.bufB, h->Q64, D.af, h->src_q, h->R, st));
+      if (h->tri) {
+        TRY(tri_fields<double>(h, D, h->Q64, h->src_v, h->src_u, h->src_t, st));
+        TRY(tri_gather<double>(h, D, h->Q64, h->src_q, h->R, st));
+      } else {
+        TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+        TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+        TRY(gather<double>(g, h->w, D.bufB, h->Q64, D.af, h->src_q, h->R, st));
+      }
       TRY(axpby(TQ(g), -1.0, h->R, 0.0, h->bvec, st));
       recovered = true;
     } else {
@@ -1686,10 +1774,14 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
     if (!all && nb > 1) TRY(zero_done(h, h->bvec, st));
   }
   if (!recovered) {
-    TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
-    TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+    if (h->tri) {
+      TRY(tri_fields<double>(h, D, h->Q64, h->src_v, h->src_u, h->src_t, st));
+    } else {
+      TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+      TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
+    }
   }
-  TRY(write_u(h, D.bufB, u, st));
+  TRY(write_u(h, h->tri ? D.bufA : D.bufB, u, st));
   if (v) TRY(out_v<double>(g, D.bufA, h->Q64, h->vedge, v, st));
   if (q) AHOC_HIP_TRY(hipMemcpyAsync(q, h->Q64, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
@@ -1801,6 +1893,10 @@ ahoc_status ahoc_solve(ahoc_handle* h, double* u, double* v, double* q, ahoc_sta
   hipStream_t st = (hipStream_t)stream;
   const auto t0 = std::chrono::steady_clock::now();
   if (h->g.nb != 1) return AHOC_E_INVALID;
+  if (h->tri && v) {
+    ahoc::set_last_error("the triharmonic solve returns u and q only (v must be NULL)", "ahoc_solve");
+    return AHOC_E_UNSUPPORTED;
+  }
   double* const uo[1] = {u};
   const long long g0 = h->graph_steps, v0 = h->vs_iters;
   h->vs_worst = 0;
@@ -1871,7 +1967,7 @@ ahoc_status ahoc_solve_batched(int count, const ahoc_problem* probs, const ahoc_
   std::vector<std::vector<int>> jobs;
   for (int i = 0; i < count; ++i) {
     const ahoc_problem& p = probs[i];
-    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.beta_nodal) {  // beta: alone
+    if (p.dim != 2 || !u[i] || p.beta != 0.0 || p.beta_nodal || p.equation != AHOC_BIHARMONIC) {  // alone
       jobs.push_back({i});
       continue;
     }

@@ -22,8 +22,10 @@ int partial_sum(long long n, int count, long long stride, const T* in, T* out, h
 // boundary-symbol preconditioner (precond.hip): inverse 2x2 block coefficients per face
 // mode from per-axis FP64 tables {s, cos, sin, w_lo} x 3 axes, and their application to
 // face spectra of a Q-layout vector
+// (tri: the triharmonic chain and q-row; tabs then hold its fourth-derivative combination
+// a_1 sin(pi k/N) + ... + a_4 sin(4 pi k/N) in place of w_lo)
 int precond_symbol(const Geom& g, const Weights& w, double c, int navier, const double* const* tabs, double* pc,
-                   double* qc, hipStream_t st);
+                   double* qc, hipStream_t st, bool tri = false);
 template <typename T>
 int precond_modes(const Geom& g, const T* pc, const T* qc, T* x, hipStream_t st);
 // boundary residual from face sums formed in spectral space
@@ -47,6 +49,14 @@ int minmax_partial(long long n, const double* x, double* part, int nblocks, hipS
 // their q-rows
 int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL, double* af64, float* af32,
                  double* src_q, hipStream_t st);
+// triharmonic extension: interior sources of the W-, V- and U-solves, the q-rows' known part
+// and face coefficient, and the boundary residual R = af h^-4 sum a_k U_k - Q - src_q
+int tri_sources(const Geom& g, const Weights& w, const double* f, const double* gD, const double* lapu,
+                const double* bilap, double* sw, double* sv, double* su, hipStream_t st);
+int tri_srcq(const Geom& g, int mask, const double* gD, const double* gN, const double* gNN, const double* tang4,
+             const double* bilap, double* src_q, double* af64, float* af32, hipStream_t st);
+template <typename T>
+int gather_tri(const Geom& g, const T* U, const T* Q, const T* af, const T* srcq, double* R, hipStream_t st);
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
                   const double* gD, const double* gN, const double* lapgD, double* src_v,
                   double* src_u, double* src_q, hipStream_t st);

@@ -16,6 +16,11 @@
 // With beta != 0 (constant alpha) the V-solve divides by lambda - c mu (c = beta/alpha) and
 // its lift's normal weight is lowered by c m1, so the term reads (m1 - mu T'/(lambda - c mu)) /
 // lambda with T' the shifted lift symbol.
+// The triharmonic extension (Sec. 4.2) has constant coefficients; its chain is W from Q
+// (the lift, as the V-solve above), V = L^-1 M W (the U-solve above) and U = L^-1 M V, closed
+// by the fourth-derivative q-row: the same mode gives
+//   F(k_b, k_c) = h_a^-4 (2/N_a) sum_{k_a} w4(k_a) sin(pi k_a/N_a) mu (m1 - mu T / lambda) / lambda^2
+// with w4 the row's combination a_1 u_1 + ... + a_4 u_4 of mode k_a.
 // Low-low gives sigma = F_lo - 1 (the -Q of the residual), low-high gives tau = F_hi;
 // by symmetry the 2x2 block per mode is [[sigma, tau], [tau, sigma]].  A Navier face's rows
 // are alpha g_L - Q, so its row of the block is (0, -1) (the opposite face's row keeps
@@ -51,6 +56,7 @@ struct SymArgs {
   Weights w;   // the lift stencil of the v-equation (with the shift in its normal weight)
   double c;    // the v-equation's shift beta/alpha (0 for beta = 0)
   int navier;  // bit f set: face f (2 axis + side) is a Navier face
+  int tri;     // 1: the triharmonic chain (one more solve, h^-4 fourth-derivative row)
   AxisTab t[3];
   // the inverse 2x2 block [[a, b], [c, d]] of a mode (rows and columns: low face, high
   // face) is stored at the mode's low entry lo and high entry hi as
@@ -103,13 +109,15 @@ __global__ void k_symbol(SymArgs A) {
       const double sa = A.t[a].s[k];
       const double lam = sa + sb + sc + cab * sa * sb + cac * sa * sc + cbc * sb * sc;
       const double mu = mt + 2.0 * A.w.m1 * A.t[a].c[k];
-      // V-solve with the shifted eigenvalue lambda - c mu, U-solve with lambda
-      const double term = A.t[a].sn[k] * (A.w.m1 - mu * T / (lam - A.c * mu)) / lam;
+      // V-solve with the shifted eigenvalue lambda - c mu, U-solve with lambda (the
+      // triharmonic chain: one more solve with M, mu / lambda)
+      double term = A.t[a].sn[k] * (A.w.m1 - mu * T / (lam - A.c * mu)) / lam;
+      if (A.tri) term *= mu / lam;
       const double wl = A.t[a].wl[k];
       sig += wl * term;
       tau += ((k & 1) ? -wl : wl) * term;  // w_hi(k) = (-1)^(k+1) w_lo(k), k = index + 1
     }
-    const double f = 2.0 / (ha2 * g.n[a]);
+    const double f = A.tri ? 2.0 / (ha2 * ha2 * g.n[a]) : 2.0 / (ha2 * g.n[a]);
     sig = f * sig - 1.0;
     tau = f * tau;
     double norm = 2.0 / g.n[b];
@@ -168,12 +176,13 @@ __global__ void k_modes(Geom g, const T* __restrict__ pc, const T* __restrict__ 
 }  // namespace
 
 int precond_symbol(const Geom& g, const Weights& w, double c, int navier, const double* const* tabs, double* pc,
-                   double* qc, hipStream_t st) {
+                   double* qc, hipStream_t st, bool tri) {
   SymArgs A;
   A.g = g;
   A.w = w;
   A.c = c;
   A.navier = navier;
+  A.tri = tri ? 1 : 0;
   for (int a = 0; a < 3; ++a) {
     A.t[a].s = tabs[4 * a];
     A.t[a].c = tabs[4 * a + 1];

@@ -1022,6 +1022,125 @@ __global__ void k_navier(Geom g, int mask, const double* __restrict__ alpha, con
   }
 }
 
+// ---------------------------------------------------------------------------------
+// Triharmonic extension (Sec. 4.2): Delta u = v, Delta v = w, Delta w = f, each by the
+// compact scheme L_h X = M rhs, with w = Q on the face interiors (a Navier face's q-rows fix
+// Q to Delta^2 u there).  The Schur matvec chains three Dirichlet solves (W from Q, V from W,
+// U from V) and closes with the q-row of a clamped face,
+//   R = h^-4 (a_1 U_1 + a_2 U_2 + a_3 U_3 + a_4 U_4) + (data) - Q,
+// the one-sided fourth normal derivative that uses u, u_n, u_nn and the four nearest
+// interior nodes: its weights solve the Taylor moment conditions through degree 6, i.e.
+// h^4 d4u = a_0 u_0 + sum_k a_k U_k + c_1 h du + c_2 h^2 d2u + O(h^7) along the inward normal
+// (du, d2u, d4u its derivatives) with a = (11669/144, -104, 57/2, -56/9, 11/16),
+// c_1 = 755/12, c_2 = 35/2.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double tri_a(int k) {
+  return k == 1 ? -104.0 : (k == 2 ? 57.0 / 2.0 : (k == 3 ? -56.0 / 9.0 : 11.0 / 16.0));
+}
+
+// Interior sources of the three solves (known boundary values moved to the right-hand side):
+//   sw = L_h[W on edges and corners] - M f     (the W-solve as W = -L^-1(sw + L_h^bnd[Q]))
+//   sv = -L_h[V on the boundary]               (V = L^-1(M W + sv), W = Q on face interiors)
+//   su = M[V on face interiors] - L_h[g_D]     (U = L^-1(M V + su))
+// with V = lapu (Delta u) on every boundary node and W = bilap on edges and corners.
+template <int DIM>
+__global__ void k_tri_src(Geom g, Weights w, const double* __restrict__ f, const double* __restrict__ gD,
+                          const double* __restrict__ lapu, const double* __restrict__ bilap,
+                          double* __restrict__ sw, double* __restrict__ sv, double* __restrict__ su) {
+  const int nrow_ = DIM == 3 ? g.ni[1] * g.ni[2] : g.ni[1];
+  for (int r_ = blockIdx.x; r_ < nrow_; r_ += gridDim.x)
+  for (int i0_ = threadIdx.x; i0_ < g.px; i0_ += blockDim.x) {
+    const long long e = (long long)r_ * g.px + i0_;
+    const int i = i0_ + 1, j = (DIM == 3 ? r_ % g.ni[1] : r_) + 1, k = DIM == 3 ? r_ / g.ni[1] + 1 : 0;
+    if (i > g.ni[0]) {
+      sw[e] = sv[e] = su[e] = 0.0;
+      continue;
+    }
+    double mf = f ? w.m0 * f[nod(g, i, j, k)] : 0.0, mv = 0.0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+#pragma unroll
+      for (int s = -1; s <= 1; s += 2) {
+        const int qi = i + (a == 0 ? s : 0), qj = j + (a == 1 ? s : 0), qk = k + (a == 2 ? s : 0);
+        const long long qn = nod(g, qi, qj, qk);
+        if (f) mf += w.m1 * f[qn];
+        if (lapu && nbnd<DIM>(g, qi, qj, qk) == 1) mv += w.m1 * lapu[qn];
+      }
+    double lw_ = 0, lv = 0, lu = 0;
+    const int zlo = DIM == 3 ? -1 : 0, zhi = DIM == 3 ? 1 : 0;
+    for (int dz = zlo; dz <= zhi; ++dz)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const double wt = lw<DIM>(w, dx, dy, dz);
+          if (wt == 0.0) continue;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          const int nb = nbnd<DIM>(g, qi, qj, qk);
+          if (nb == 0) continue;
+          const long long qn = nod(g, qi, qj, qk);
+          if (nb >= 2 && bilap) lw_ += wt * bilap[qn];
+          if (lapu) lv += wt * lapu[qn];
+          if (gD) lu += wt * gD[qn];
+        }
+    sw[e] = lw_ - mf;
+    sv[e] = -lv;
+    su[e] = mv - lu;
+  }
+}
+
+// Known part of the q-rows and the face coefficient: on a clamped face
+//   src_q = -[ h^-4 (a_0 g_D - c_1 h g_N + c_2 h^2 g_NN) + tang4 ]   (g_N outward = -du),
+//   af = 1;  on a Navier face (bit 2 axis + side of mask) src_q = -bilap, af = 0.
+template <int DIM>
+__global__ void k_tri_srcq(Geom g, int mask, const double* __restrict__ gD, const double* __restrict__ gN,
+                           const double* __restrict__ gNN, const double* __restrict__ tang4,
+                           const double* __restrict__ bilap, double* __restrict__ src_q, double* __restrict__ af64,
+                           float* __restrict__ af32) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    const int f = 2 * ax + (st > 0 ? 0 : 1);
+    const long long b = nod(g, i, j, k);
+    double sq, a;
+    if ((mask >> f) & 1) {
+      sq = bilap ? -bilap[b] : 0.0;
+      a = 0.0;
+    } else {
+      const double h = g.h[ax];
+      double t = 0;
+      if (gD) t += (11669.0 / 144.0) * gD[b];
+      if (gN) t -= (755.0 / 12.0) * h * gN[b];
+      if (gNN) t += (35.0 / 2.0) * h * h * gNN[b];
+      t /= h * h * h * h;
+      if (tang4) t += tang4[b];
+      sq = -t;
+      a = 1.0;
+    }
+    src_q[q] = sq;
+    af64[q] = a;
+    if (af32) af32[q] = (float)a;
+  }
+}
+
+// R = af h^-4 sum_{k=1..4} a_k U_k - Q - src_q at every face-interior node
+template <typename T, int DIM>
+__global__ void k_gather_tri(Geom g, const T* __restrict__ U, const T* __restrict__ Q, const T* __restrict__ af,
+                             const T* __restrict__ srcq, double* __restrict__ R) {
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    T acc = 0;
+#pragma unroll
+    for (int m = 1; m <= 4; ++m) {
+      const int ui = i + (ax == 0 ? st * m : 0), uj = j + (ax == 1 ? st * m : 0), uk = k + (ax == 2 ? st * m : 0);
+      acc += (T)tri_a(m) * U[inr(g, ui, uj, DIM == 3 ? uk : 1)];
+    }
+    const double h = g.h[ax];
+    T r = af[q] * (T)(1.0 / (h * h * h * h)) * acc - Q[q];
+    if (srcq) r -= srcq[q];
+    R[q] = (double)r;
+  }
+}
+
 // nodal outputs
 template <typename T, int DIM>
 __global__ void k_out_u(Geom g, const T* __restrict__ Ui, const double* __restrict__ gD, double* __restrict__ u) {
@@ -1271,6 +1390,31 @@ int setup_navier(const Geom& g, int mask, const double* alpha, const double* gL,
   LAUNCH_DIM(k_navier, dim3(nblocks(g.nq), g.nb), g, mask, alpha, gL, af64, af32, src_q);
   return ST_OK;
 }
+
+int tri_sources(const Geom& g, const Weights& w, const double* f, const double* gD, const double* lapu,
+                const double* bilap, double* sw, double* sv, double* su, hipStream_t st) {
+  if (g.nb != 1) return ST_INVALID;
+  LAUNCH_DIM(k_tri_src, dim3(interior_rows(g)), g, w, f, gD, lapu, bilap, sw, sv, su);
+  return ST_OK;
+}
+
+int tri_srcq(const Geom& g, int mask, const double* gD, const double* gN, const double* gNN, const double* tang4,
+             const double* bilap, double* src_q, double* af64, float* af32, hipStream_t st) {
+  if (g.nb != 1) return ST_INVALID;
+  LAUNCH_DIM(k_tri_srcq, dim3(nblocks(g.nq)), g, mask, gD, gN, gNN, tang4, bilap, src_q, af64, af32);
+  return ST_OK;
+}
+
+template <typename T>
+int gather_tri(const Geom& g, const T* U, const T* Q, const T* af, const T* srcq, double* R, hipStream_t st) {
+  if (g.nb != 1) return ST_INVALID;
+  LAUNCH_TDIM(k_gather_tri, T, dim3(nblocks(g.nq)), g, U, Q, af, srcq, R);
+  return ST_OK;
+}
+template int gather_tri<float>(const Geom&, const float*, const float*, const float*, const float*, double*,
+                               hipStream_t);
+template int gather_tri<double>(const Geom&, const double*, const double*, const double*, const double*, double*,
+                                hipStream_t);
 
 int setup_sources(const Geom& g, const Weights& w, const double* f, const double* alpha,
                   const double* gD, const double* gN, const double* lapgD, double* src_v,
