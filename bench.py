@@ -271,10 +271,16 @@ def main():
         specs = W.config4_specs(args.batch_count)
         bprobs = [W.config4_instance(sp, xp="torch", device=dev, with_exact=False) for sp in specs]
         ah.solve_batched(bprobs, precision=ah.MIXED, tol=args.tol)
+        # a calibration copy (kernel k_copy_linear) before each timed batch and after the last
+        # marks the batch windows in a kernel trace
+        mark = torch.zeros(1, 1, 32, dtype=torch.float32, device=dev)
+        mark_out = torch.empty_like(mark)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(args.batch_profile):
+            ah.copy_bandwidth(0, mark, mark_out)
             ah.solve_batched(bprobs, precision=ah.MIXED, tol=args.tol)
+        ah.copy_bandwidth(0, mark, mark_out)
         torch.cuda.synchronize()
         print(f"[bench] {args.batch_profile} mixed batched solves: "
               f"{(time.perf_counter() - t) / args.batch_profile * 1e3:.1f} ms each", file=sys.stderr)

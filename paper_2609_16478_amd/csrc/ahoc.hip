@@ -129,8 +129,13 @@ struct ahoc_handle {
   double* qc = nullptr;
   ahoc::DstTables<double> ptb[3];
   bool ptb_own = false;
-  int* act = nullptr;        // per instance: still iterating (device)
-  int* kk = nullptr;         // per instance: Krylov dimension of the cycle (device)
+  int* act = nullptr;        // per instance: a mask (device; zeroing finished segments)
+  int* ist = nullptr;        // GMRES state per instance (device): [act | kk | nit | flag | hcnt]
+  double* hist = nullptr;    // last 16 residual estimates per instance (device; FP32 stall rule)
+  double* eres = nullptr;    // last residual estimate of each instance while active (device)
+  double* bn = nullptr;      // ||b|| per instance (device)
+  int* pinned_s = nullptr;   // host-pinned image of [act | kk | nit | flag]
+  double* pinned_b = nullptr;  // host-pinned ||b|| for the upload
   double* ubuf = nullptr;    // batch: nodal U of all instances before the copy-out
   double* red = nullptr;     // reduction partials
   double* pinned = nullptr;  // host-pinned scalars (2 per instance, at least 8)
@@ -1001,6 +1006,15 @@ int apply_op(ahoc_handle* h, Prec<T>& P, bool pre, const double* v, double* w, h
   return body(v, w);
 }
 
+// AHOC_GMRES_CHECK=1: read the device state after every Arnoldi step (for comparisons).
+bool check_every_step() {
+  static const bool v = [] {
+    const char* e = std::getenv("AHOC_GMRES_CHECK");
+    return e && std::atoi(e) == 1;
+  }();
+  return v;
+}
+
 template <typename T>
 int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, int max_iters,
           std::vector<GmresResult>& res, int* matvecs, hipStream_t st, bool x0 = false) {
@@ -1011,11 +1025,13 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
   const int nbk = dot_blocks(h, nq);
   const long long nt = nq * ns;  // batch vector length
   const int m = h->m;
+  // device state per instance: [act | kk | nit | flag | hcnt] (see step_update)
+  int* act = h->ist;
+  int* kk = h->ist + ns;
+  const int* hst = h->pinned_s;  // host image of [act | kk | nit | flag]
   res.assign(ns, GmresResult());
-  std::vector<std::vector<double>> hist(ns);
   std::vector<double> bnorm(ns);
-  std::vector<char> conv(ns, 0), active(ns, 0), stalled(ns, 0);
-  std::vector<int> jj(ns, 0);
+  std::vector<char> conv(ns, 0);  // 0 iterating, 1 converged, 2 stopped without convergence
   if (!x0) TRY(fill(nt, 0.0, x, st));
   TRY(dot_dev(h, b, b, st, h->nrm));
   TRY(read_vec(h, h->nrm, 2 * ns, st));
@@ -1034,6 +1050,10 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
     any = any || !conv[s];
   }
   if (!any) return ST_OK;
+  for (int s = 0; s < ns; ++s) h->pinned_b[s] = bnorm[s] > 0 && std::isfinite(bnorm[s]) ? bnorm[s] : 1.0;
+  AHOC_HIP_TRY(hipMemcpyAsync(h->bn, h->pinned_b, sizeof(double) * ns, hipMemcpyHostToDevice, st));
+  TRY(fill_int(h->ist + 2 * ns, 3LL * ns, 0, st));  // nit, flag, hcnt
+  std::vector<double> est_prev(ns, 0.0);
   bool first = !x0;
   while (true) {
     const double* r = b;
@@ -1049,28 +1069,32 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
     TRY(read_vec(h, h->beta, ns, st));
     any = false;
     for (int s = 0; s < ns; ++s) {
-      jj[s] = 0;
-      if (conv[s]) {
-        active[s] = 0;
-        continue;
-      }
+      h->pinned_i[s] = 0;
+      h->pinned_i[ns + s] = 0;  // Krylov dimension of the cycle
+      if (conv[s]) continue;
       res[s].relres = h->pinned[s] / bnorm[s];
       if (!std::isfinite(h->pinned[s])) {
         conv[s] = 2;
-        active[s] = 0;
         continue;
       }
       if (h->pinned[s] <= tol * bnorm[s]) {
         conv[s] = 1;
         res[s].converged = true;
+        continue;
       }
-      active[s] = !conv[s] && res[s].iters < max_iters;
-      any = any || active[s];
+      if (res[s].iters >= max_iters) {
+        conv[s] = 2;
+        continue;
+      }
+      h->pinned_i[s] = 1;
+      any = true;
     }
     if (!any) return ST_OK;
-    for (int s = 0; s < ns; ++s) h->pinned_i[s] = active[s];
-    TRY(write_ints(h, h->act, ns, st));
-    int jmax = 0;
+    TRY(write_ints(h, h->ist, 2 * ns, st));  // act, kk (the host buffer is reused after the next read)
+    // The steps run without host reads; the host checks the device state after the step at
+    // which the slowest active instance is predicted to converge (from its observed
+    // contraction), at most 8 steps (and never past an iteration cap) apart.
+    int jmax = 0, next = 0, jprev = -1;
     for (int j = 0; j < m; ++j) {
       double* vj = h->Vb + (long long)j * nt;
       double* w = h->Vb + (long long)(j + 1) * nt;
@@ -1085,47 +1109,41 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       TRY(maxpy(w, h->Vb, nt, j + 1, h->h2, m + 1, -1.0, nq, ns, st));
       TRY(dot_dev(h, w, w, st, h->nrm));
       TRY(givens_step(ns, h->H, m, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
-      TRY(scale_by_inv(w, nq, ns, h->resid, h->act, st));
+      TRY(step_update(ns, j, h->resid, h->bn, tol, max_iters, inexact, h->ist, h->hist, h->eres, st));
+      TRY(scale_by_inv(w, nq, ns, h->resid, act, st));
       // CGS2: 2 x (j+1) dot sweeps and 2 x (j+1) axpy sweeps over the basis, plus norm and scale
       tend(h, AHOC_K_KRYLOV, ek, 8.0 * nt * (4.0 * (j + 1) + 2.0 * 2 + 3.0), st);
       jmax = j + 1;
-      TRY(read_vec(h, h->resid, 2 * ns, st));
+      if (j < next && j < m - 1) continue;
+      // one host round trip: [act | kk | nit | flag] and the last active estimates
+      AHOC_HIP_TRY(hipMemcpyAsync(h->pinned_s, h->ist, sizeof(int) * 4 * ns, hipMemcpyDeviceToHost, st));
+      TRY(read_vec(h, h->eres, ns, st));
       any = false;
-      bool changed = false;
+      double need = 1.0;
+      int cap = 8;
       for (int s = 0; s < ns; ++s) {
-        if (!active[s]) continue;
-        ++res[s].iters;
-        jj[s] = j + 1;
-        const double est = h->pinned[2 * s] / bnorm[s];
+        if (conv[s]) continue;
+        res[s].iters = hst[2 * ns + s];
+        const double est = h->pinned[s];
         res[s].relres = est;
-        bool stop = false;
-        if (!std::isfinite(est)) {
-          stop = stalled[s] = 1;  // ends as not converged
-        } else if (est <= tol) {
+        if (hst[s]) {
+          any = true;
+          cap = std::min(cap, std::max(1, max_iters - res[s].iters));
+          if (jprev >= 0 && est_prev[s] > est && est > 0) {
+            const double rate = std::pow(est / est_prev[s], 1.0 / (j - jprev));
+            need = std::max(need, std::log(tol / est) / std::log(rate));
+          }
+          est_prev[s] = est;
+        } else if (hst[3 * ns + s] == 1) {
           conv[s] = 1;
           res[s].converged = true;
-          stop = true;
-        } else {
-          hist[s].push_back(est);
-          const size_t hs = hist[s].size();
-          if (inexact && hs > 8 && est < 1e-2 && est > 0.5 * hist[s][hs - 9]) stop = stalled[s] = 1;
-          if (res[s].iters >= max_iters) stop = true;
         }
-        if (stop) {
-          active[s] = 0;
-          changed = true;
-        }
-        any = any || active[s];
       }
       if (!any) break;
-      if (changed) {
-        for (int s = 0; s < ns; ++s) h->pinned_i[s] = active[s];
-        TRY(write_ints(h, h->act, ns, st));
-      }
+      next = j + (check_every_step() ? 1 : std::max(1, std::min(cap, (int)std::floor(0.9 * need))));
+      jprev = j;
     }
-    for (int s = 0; s < ns; ++s) h->pinned_i[s] = jj[s];
-    TRY(write_ints(h, h->kk, ns, st));
-    TRY(back_solve(ns, h->H, m, h->gv, h->kk, jmax, h->y, st));
+    TRY(back_solve(ns, h->H, m, h->gv, kk, jmax, h->y, st));
     if (pre) {  // x += P^-1 (V y); the cycle's residual vector is free again
       TRY(fill(nt, 0.0, h->rvec, st));
       TRY(maxpy(h->rvec, h->Vb, nt, jmax, h->y, m + 1, 1.0, nq, ns, st));
@@ -1134,12 +1152,12 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
     } else {
       TRY(maxpy(x, h->Vb, nt, jmax, h->y, m + 1, 1.0, nq, ns, st));
     }
-    // another cycle for the instances that neither converged, stalled nor hit the cap;
-    // the others are finished (conv = 2: stopped without convergence)
+    // another cycle for the instances that neither converged, stalled (flag 2) nor hit the
+    // cap; the state is the last check's, taken after the cycle's last step
     any = false;
     for (int s = 0; s < ns; ++s) {
       if (conv[s]) continue;
-      if (stalled[s] || res[s].iters >= max_iters) conv[s] = 2;
+      if (hst[3 * ns + s] == 2 || res[s].iters >= max_iters) conv[s] = 2;
       else any = true;
     }
     if (!any) return ST_OK;
@@ -1339,7 +1357,10 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   TRY(alloc_t(h, &h->y, nb * (m + 1)));
   TRY(alloc_t(h, &h->part, nb * (m + 1) * h->nb_dot));
   TRY(alloc_t(h, &h->act, nb));
-  TRY(alloc_t(h, &h->kk, nb));
+  TRY(alloc_t(h, &h->ist, 5 * nb));
+  TRY(alloc_t(h, &h->hist, 16 * nb));
+  TRY(alloc_t(h, &h->eres, nb));
+  TRY(alloc_t(h, &h->bn, nb));
   TRY(alloc_t(h, &h->bvec, TQ(g)));
   TRY(alloc_t(h, &h->dq, TQ(g)));
   TRY(alloc_t(h, &h->rvec, TQ(g)));
@@ -1353,6 +1374,8 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   const size_t npin = (size_t)std::max<long long>(8, 2 * nb);
   AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned), sizeof(double) * npin, hipHostMallocDefault));
   AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_i), sizeof(int) * npin, hipHostMallocDefault));
+  AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_s), sizeof(int) * 4 * nb, hipHostMallocDefault));
+  AHOC_HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&h->pinned_b), sizeof(double) * nb, hipHostMallocDefault));
   AHOC_HIP_TRY(hipStreamSynchronize(st));
   if (h->opt.precond) TRY(precond_init(h, st));
   return ST_OK;
@@ -1415,6 +1438,8 @@ void ahoc_destroy(ahoc_handle* h) {
   if (h->done_ev) (void)hipEventDestroy(h->done_ev);
   if (h->pinned) (void)hipHostFree(h->pinned);
   if (h->pinned_i) (void)hipHostFree(h->pinned_i);
+  if (h->pinned_s) (void)hipHostFree(h->pinned_s);
+  if (h->pinned_b) (void)hipHostFree(h->pinned_b);
   if (h->bpin) (void)hipHostFree(h->bpin);
   delete h;
 }

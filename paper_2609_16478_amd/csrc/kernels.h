@@ -98,6 +98,11 @@ int gather_ptrs(const double* const* src, long long n, int ns, double* out, hipS
 int scatter_ptrs(const double* in, long long n, int ns, double* const* dst, hipStream_t st);
 int back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y,
                hipStream_t st);
+// device-side convergence bookkeeping of Arnoldi step j (see krylov.hip); ist = [act | kk |
+// nit | flag | hcnt], ns ints each; hist: 16 doubles per instance; eres: last active estimate
+int step_update(int ns, int j, const double* resid, const double* bnorm, double tol, int max_iters, bool inexact,
+                int* ist, double* hist, double* eres, hipStream_t st);
+int fill_int(int* p, long long n, int v, hipStream_t st);
 int start_cycle(double* v0, const double* r, long long n, int ns, const double* nrm2, double* gv, int m,
                 double* beta, hipStream_t st);
 

@@ -217,6 +217,56 @@ __global__ void k_start(double* __restrict__ v0, const double* __restrict__ r, l
   }
 }
 
+// Per-instance bookkeeping after the Givens update of Arnoldi step j, on the device, so
+// that the host need not read the residual estimates every step.  ist = [act | kk | nit |
+// flag | hcnt] (ns ints each): an active instance counts the step, records its Krylov
+// dimension j + 1 and stops -- flag 1 -- when |g_{j+1}| <= tol ||b||, with flag 2 when the
+// estimate is not finite or, for an FP32 operator (inexact), when eight steps gained less
+// than a factor 2 below 1e-2 (ring of its last 16 estimates in hist), and without a flag at
+// the iteration cap.  eres keeps each instance's estimate of its last active step.
+__global__ void k_step_update(int ns, int j, const double* __restrict__ resid, const double* __restrict__ bnorm,
+                              double tol, int max_iters, int inexact, int* __restrict__ ist,
+                              double* __restrict__ hist, double* __restrict__ eres) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  int* act = ist;
+  int* kk = ist + ns;
+  int* nit = ist + 2 * ns;
+  int* flag = ist + 3 * ns;
+  int* hcnt = ist + 4 * ns;
+  if (!act[s]) return;
+  const int it = ++nit[s];
+  kk[s] = j + 1;
+  const double est = resid[2 * s] / bnorm[s];
+  eres[s] = est;
+  bool stop = false;
+  if (!isfinite(est)) {
+    flag[s] = 2;
+    stop = true;
+  } else if (est <= tol) {
+    flag[s] = 1;
+    stop = true;
+  } else {
+    if (inexact) {
+      double* hs = hist + 16LL * s;
+      const int hc = hcnt[s] + 1;
+      hs[(hc - 1) & 15] = est;
+      hcnt[s] = hc;
+      if (hc > 8 && est < 1e-2 && est > 0.5 * hs[(hc - 9) & 15]) {
+        flag[s] = 2;
+        stop = true;
+      }
+    }
+    if (it >= max_iters) stop = true;
+  }
+  if (stop) act[s] = 0;
+}
+
+__global__ void k_fill_int(int* __restrict__ p, long long n, int v) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
 inline unsigned nblk(long long n, int cap) {
   long long b = (n + TPB - 1) / TPB;
   if (b > cap) b = cap;
@@ -299,6 +349,21 @@ int scatter_ptrs(const double* in, long long n, int ns, double* const* dst, hipS
 int back_solve(int ns, const double* H, int m, const double* gv, const int* kk, int kmax, double* y,
                hipStream_t st) {
   hipLaunchKernelGGL(k_back_solve, dim3((ns + 63) / 64), dim3(64), 0, st, ns, H, m, gv, kk, kmax, y);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int step_update(int ns, int j, const double* resid, const double* bnorm, double tol, int max_iters, bool inexact,
+                int* ist, double* hist, double* eres, hipStream_t st) {
+  hipLaunchKernelGGL(k_step_update, dim3((ns + 63) / 64), dim3(64), 0, st, ns, j, resid, bnorm, tol, max_iters,
+                     inexact ? 1 : 0, ist, hist, eres);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int fill_int(int* p, long long n, int v, hipStream_t st) {
+  if (n <= 0) return ST_OK;
+  hipLaunchKernelGGL(k_fill_int, dim3(nblk(n, 4096)), dim3(TPB), 0, st, p, n, v);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
