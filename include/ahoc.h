@@ -357,7 +357,9 @@ enum {
   AHOC_K_PRECOND = 11,     /* one application of the boundary-symbol preconditioner       */
   AHOC_K_VSOLVE = 12,      /* variable beta: one BiCGSTAB V-solve with its transform solves
                               and stencil applications (bytes not modelled)               */
-  AHOC_NKIND = 13
+  AHOC_K_DST_XMUL = 13,    /* 3-D matvec: the V-solve's inverse and the U-solve's forward
+                              DST-I along x with the product by 1/alpha between them      */
+  AHOC_NKIND = 14
 };
 
 /* Enable (1) or disable (0) per-kernel-class timing of the handle's solves with

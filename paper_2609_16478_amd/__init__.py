@@ -135,7 +135,7 @@ _lib.ahoc_status_string.restype = ctypes.c_char_p
 _lib.ahoc_last_error.restype = ctypes.c_char_p
 
 KERNEL_KINDS = ["dst_rows", "dst_strided", "dst_fused", "lift", "rhs_u", "gather", "krylov", "resid",
-                "matvec", "dst_gen", "face_reduce", "precond", "vsolve"]
+                "matvec", "dst_gen", "face_reduce", "precond", "vsolve", "dst_xmul"]
 
 EXPORTED = ["ahoc_set_dst_variant", "ahoc_set_dst_tile", "ahoc_dst_choice", "ahoc_copy_bandwidth", "ahoc_profile", "ahoc_kernel_times", "ahoc_default_options", "ahoc_setup", "ahoc_nq", "ahoc_schur_apply", "ahoc_precond_apply", "ahoc_schur_rhs",
             "ahoc_solve", "ahoc_solve_batched", "ahoc_poisson", "ahoc_poisson_noalloc", "ahoc_dst1", "ahoc_destroy",

@@ -57,6 +57,14 @@ template <typename T> struct Prec {
   T* Fz = nullptr;
   // spectral entry/exit of the matvec (when every axis has a specialised kernel)
   bool spectral = false;
+  // 3-D spectral matvec with the weighting operator M in spectral form: the U-solve's face
+  // layers m1 Q_b / alpha_b (layouts as Fx, Fy, Fz) and the scale with the symbol of M
+  bool mspec = false;
+  T* ptab = nullptr;  // per z position: s_z, layer sine, face weights low/high
+  T* Ux = nullptr;
+  T* Uy = nullptr;
+  T* Uz = nullptr;
+  DstScale<T> scM;
 
   DstScale<T> scV, scU, scP;
   bool ready = false;
@@ -359,6 +367,28 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.nb * g.px, st));
   }
   P.spectral = faces_available(g);
+  if (P.spectral && g.dim == 3 && !h->tri) {
+    TRY(alloc_t(h, &P.Ux, 2LL * g.ni[1] * g.ni[2]));
+    TRY(alloc_t(h, &P.Uy, 2LL * g.ni[0] * g.ni[2]));
+    TRY(alloc_t(h, &P.Uz, 2LL * g.px * g.ni[1]));
+    // (s, layer sine, face weight low, high) per z position, from the tables above
+    const int nz = g.ni[2];
+    std::vector<T> hs(nz), hl(2 * nz), hw(2 * nz), pt(4 * (size_t)nz);
+    AHOC_HIP_TRY(hipMemcpyAsync(hs.data(), P.s[2], sizeof(T) * nz, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(hl.data(), P.wl[2], sizeof(T) * 2 * nz, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(hw.data(), P.wf[2], sizeof(T) * 2 * nz, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
+    for (int k = 0; k < nz; ++k) {
+      pt[4 * k] = hs[k];
+      pt[4 * k + 1] = hl[k];
+      pt[4 * k + 2] = hw[k];
+      pt[4 * k + 3] = hw[nz + k];
+    }
+    TRY(alloc_t(h, &P.ptab, 4LL * nz));
+    AHOC_HIP_TRY(hipMemcpyAsync(P.ptab, pt.data(), sizeof(T) * 4 * nz, hipMemcpyHostToDevice, st));
+    AHOC_HIP_TRY(hipStreamSynchronize(st));
+    P.mspec = dst_pipe_mpass_ok<T>(g.n[2], (long long)g.px * g.ni[1], g.px, mspec_gen<T>(g, P));
+  }
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
   // setup-time choice between the FFT and the matrix-core pass for the plain passes of the
@@ -405,6 +435,12 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
   P.scU = sc;
   P.scU.scale = (T)norm;     // U = +L^{-1}(...)
   P.scP = P.scU;
+  // the U-solve with spectral M: mu_M = m0 + 2 dim m1 + m1 sum_a h_a^2 s_a
+  P.scM = P.scU;
+  P.scM.mc0 = (T)(h->w.m0 + 2.0 * g.dim * h->w.m1);
+  P.scM.mca = (T)(h->w.m1 * g.h[0] * g.h[0]);
+  P.scM.mcb = g.dim == 3 ? (T)(h->w.m1 * g.h[1] * g.h[1]) : (T)0;
+  P.scM.mct = (T)(h->w.m1 * g.h[t] * g.h[t]);
   P.ready = true;
   return ST_OK;
 }
@@ -572,26 +608,29 @@ template <typename T> int usolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T
 
 // 2-D DST-I of every face array, in place (the unnormalised transform is its own inverse
 // up to the factor folded into the eigen scaling).
-template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) {
+template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, T* Fx, T* Fy, T* Fz, hipStream_t st) {
   const Geom& g = h->g;
   if (g.dim == 3) {
-    TRY(dst_pass<T>(P.tb[0], P.Fz, P.Fz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], P.Fz, P.Fz, 2, g.px, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[2], P.Fx, P.Fx, 2LL * g.ni[1], 1, g.ni[2], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2, g.ni[2], g.ni[2], nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[2], P.Fy, P.Fy, 2, g.px, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], Fz, Fz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], Fz, Fz, 2, g.px, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], Fx, Fx, 2LL * g.ni[1], 1, g.ni[2], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], Fx, Fx, 2, g.ni[2], g.ni[2], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], Fy, Fy, 2LL * g.ni[2], 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], Fy, Fy, 2, g.px, g.px, nullptr, 0, st));
   } else {
-    TRY(dst_pass<T>(P.tb[0], P.Fy, P.Fy, 2LL * g.nb, 1, g.px, nullptr, 0, st));
-    TRY(dst_pass<T>(P.tb[1], P.Fx, P.Fx, 2LL * g.nb, 1, g.ni[1], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], Fy, Fy, 2LL * g.nb, 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], Fx, Fx, 2LL * g.nb, 1, g.ni[1], nullptr, 0, st));
   }
   return ST_OK;
+}
+template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) {
+  return face_dst2<T>(h, P, P.Fx, P.Fy, P.Fz, st);
 }
 
 // Homogeneous V-solve V = -L^{-1} L_h^bnd[Q] into P.bufA through the spectral lift: face
 // layers of the lift, their 2-D spectra, then the slowest-axis pass generates the 3-D
 // spectrum, scales it and inverts along its axis; the other axes are inverted as usual.
-template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st) {
+template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st, bool skip_x = false) {
   const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
   TRY(face_lift<T>(g, h->wv, Q, P.Fx, P.Fy, P.Fz, st));
@@ -636,10 +675,84 @@ template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hi
   };
   if (g.dim == 3) {
     TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, P.tile[1]));
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, P.tile[0]));
-  } else {
+    if (!skip_x) TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, P.tile[0]));
+  } else if (!skip_x) {
     TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, P.tile[0]));
   }
+  return ST_OK;
+}
+
+// Face-array arguments of the U-solve pass with spectral M (layouts as the V-solve's lift)
+template <typename T> DstGen<T> mspec_gen(const Geom& g, Prec<T>& P) {
+  DstGen<T> gen;
+  gen.lp = P.Uz;
+  gen.pplane = (long long)g.px * g.ni[1];
+  gen.wp = P.wl[2];
+  gen.la = P.Ux;
+  gen.aplane = (long long)g.ni[1] * g.ni[2];
+  gen.apitch = 1;
+  gen.arow = g.ni[2];
+  gen.wa = P.wl[0];
+  gen.nwa = g.ni[0];
+  gen.lb = P.Uy;  // [side][i][k], k fastest
+  gen.bplane = (long long)g.ni[0] * g.ni[2];
+  gen.bpitch = g.ni[2];
+  gen.wb = P.wl[1];
+  gen.nwb = g.ni[1];
+  gen.ptab = P.ptab;
+  return gen;
+}
+
+// Homogeneous 3-D Schur matvec with the weighting operator M in spectral form.  M is
+// diagonalised by the sine transforms: on the interior values W = V / alpha (zero on the
+// boundary) it is the symbol mu_M = m0 + 2 m1 sum_a cos(theta_a), and its coupling of the
+// layers next to the faces to the face values W_b = Q_b / alpha_b is a face-layer source
+// m1 W_b, whose spectrum is one layer sine times a 2-D face spectrum (as the V-solve's
+// lift).  So U = L^-1 M (V / alpha) in spectral form is (mu_M W^ + G^) / lambda_L:
+//   V-solve: spectral lift, generated z inverse, y inverse;
+//   x: inverse of the V-solve, times 1/alpha, forward of the U-solve (one pass);
+//   y forward; z forward with mu_M / lambda_L, the face-layer term and the z-face sums;
+//   x/y-face sums of the scaled spectrum; 2-D inverse transforms of the face sums; gather.
+// The volume is read and written in place in bufA.
+template <typename T> int matvec_mspec(ahoc_handle* h, Prec<T>& P, const T* Q, double* y, hipStream_t st) {
+  const Geom& g = h->g;
+  TRY(vsolve_spec<T>(h, P, Q, st, true));
+  hipEvent_t el = tbegin(h, st);
+  TRY(face_lift_m<T>(g, h->w, Q, P.ia, P.Ux, P.Uy, P.Uz, st));
+  // 2-D spectra: x and z faces as the lift's; y faces [2][n_x'][n_z'] (z rows, x strided)
+  TRY(dst_pass<T>(P.tb[0], P.Uz, P.Uz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
+  TRY(dst_pass<T>(P.tb[1], P.Uz, P.Uz, 2, g.px, g.px, nullptr, 0, st));
+  TRY(dst_pass<T>(P.tb[2], P.Ux, P.Ux, 2LL * g.ni[1], 1, g.ni[2], nullptr, 0, st));
+  TRY(dst_pass<T>(P.tb[1], P.Ux, P.Ux, 2, g.ni[2], g.ni[2], nullptr, 0, st));
+  TRY(dst_pass<T>(P.tb[2], P.Uy, P.Uy, 2LL * g.ni[0], 1, g.ni[2], nullptr, 0, st));
+  TRY(dst_pass<T>(P.tb[0], P.Uy, P.Uy, 2, g.ni[2], g.ni[2], nullptr, 0, st));
+  tend(h, AHOC_K_LIFT, el, (double)TQ(g) * 3.0 * sizeof(T), st);
+  T* buf = P.bufA;
+  const double vol = (double)g.nint * sizeof(T);
+  hipEvent_t ex = tbegin(h, st);
+  TRY(dst_rows_mul_pass<T>(g.n[0], P.tb[0].tw, P.tb[0].sn, buf, buf, (long long)g.ni[1] * g.ni[2], g.px, P.ia,
+                           g.ni[1], 1, g.nn[0], g.nn[1], st));
+  tend(h, AHOC_K_DST_XMUL, ex, 2.0 * vol + (double)g.nnodal * sizeof(T), st);
+  hipEvent_t ey = tbegin(h, st);
+  TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.px, g.px, nullptr, P.tile[1], st));
+  tend(h, AHOC_K_DST_STRIDED, ey, 2.0 * vol, st);
+  DstFaces<T> fp;
+  fp.mode = 1;
+  fp.out = P.Fz;
+  fp.w = P.wf[2];
+  fp.plane = (long long)g.px * g.ni[1];
+  hipEvent_t ez = tbegin(h, st);
+  TRY(dst_pipe_mpass<T>(g.n[2], P.tb[2].tw, P.tb[2].sn, buf, 1, (long long)g.px * g.ni[1], P.scM, fp,
+                        mspec_gen<T>(g, P), st));
+  tend(h, AHOC_K_DST_FUSED, ez, 2.0 * vol, st);
+  hipEvent_t er = tbegin(h, st);
+  TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
+                     (long long)g.ni[2] * g.ni[1], 1, g.ni[2], st));
+  tend(h, AHOC_K_FACE_REDUCE, er, vol, st);
+  hipEvent_t ef = tbegin(h, st);
+  TRY(face_dst2<T>(h, P, st));
+  TRY(gather_faces<T>(g, P.Fx, P.Fy, P.Fz, Q, P.af, nullptr, y, st));
+  tend(h, AHOC_K_GATHER, ef, (double)TQ(g) * (5 * sizeof(T) + sizeof(double)), st);
   return ST_OK;
 }
 
@@ -817,6 +930,13 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
     TRY(tri_fields<T>(h, P, qT, nullptr, nullptr, nullptr, st));
     TRY(tri_gather<T>(h, P, qT, nullptr, y, st));
     tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (34.0 * h->g.nint + 2.0 * h->g.nnodal), st);
+    return ST_OK;
+  }
+  if (P.mspec) {
+    TRY(matvec_mspec<T>(h, P, qT, y, st));
+    // algorithmic bytes: generated pass (write), y inverse, x pass (read, 1/alpha, write),
+    // y forward, z forward, face reduction (read)
+    tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (9.0 * h->g.nint + h->g.nnodal), st);
     return ST_OK;
   }
   if (P.spectral) {
@@ -1325,7 +1445,10 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   h->p64.af = h->af64;
   const bool schur_ir = mixed && h->opt.refine == 1;
   if (!mixed || schur_ir) TRY(prec_init<double>(h, h->p64, h->opt.tile_fp64, st));
-  if (h->cvar) h->p64.spectral = false;  // the V-solve is iterative: physical lift, U and gather
+  if (h->cvar) {  // the V-solve is iterative: physical lift, U and gather
+    h->p64.spectral = false;
+    h->p64.mspec = false;
+  }
   if (mixed) {
     h->p32.ia = ia32;
     h->p32.af = af32;

@@ -122,6 +122,10 @@ template <typename T> struct DstScale {
   // with mu_M = m0 + 2 m1 sum_a cos(theta_a) and cos(theta_a) = 1 + h_a^2 s_a / 2 adds
   // a0 + ka s_a + kb s_b to A and kt to B (lambda = A + B s_this)
   T a0 = 0, ka = 0, kb = 0, kt = 0;
+  // symbol of the weighting operator M, mu_M = mc0 + mca s_a + mcb s_b + mct s_this, by
+  // which the U-solve's pass with spectral M multiplies the spectrum (m0 + 2 dim m1 and
+  // m1 h_a^2 from cos(theta_a) = 1 + h_a^2 s_a / 2)
+  T mc0 = 1, mca = 0, mcb = 0, mct = 0;
 };
 
 // Optional face sums of a fused pass (one-sided normal combination along the pass axis):
@@ -162,6 +166,9 @@ template <typename T> struct DstGen {
   int bpitch = 0;
   const T* wb = nullptr;
   int nwb = 0;
+  // U-solve pass with spectral M: per position m - 1 of the pass axis the 4-tuple
+  // (s_this, layer sine wp, face weights w_lo, w_hi), one vector load per position
+  const T* ptab = nullptr;
 };
 
 template <typename T>
@@ -205,12 +212,33 @@ template <typename T>
 int dst_rows_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
                   hipStream_t st);
 
+// Two transforms of each row with a pointwise product between them (dst_rows.hip):
+// out_row = S (c_row .* (S in_row)), c nodal with the row of interior row
+// r = (j - 1) + p ni1 at c + ((p + kofs) nn1 + j) nn0 (position i at offset i); in may
+// equal out.  ST_UNSUPPORTED where no such kernel applies.
+template <typename T>
+int dst_rows_mul_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
+                      const T* c, int ni1, int kofs, int nn0, int nn1, hipStream_t st);
+
 // Persistent, software-pipelined strided pass (dst_pipe.hip): plain, or (fused with
 // faces->mode 1) forward + eigen scaling + face sums; inner must be even.  nseq 0 = the
 // kernel's own tile; ST_UNSUPPORTED where no such kernel applies.
 template <typename T>
 int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long outer, long long inner,
                   const DstScale<T>* fused, const DstFaces<T>* faces, int nseq, hipStream_t st);
+
+// The U-solve's slowest-axis pass with the weighting operator in spectral form
+// (dst_pipe.hip), in place on buf: forward transform; spectrum times scale mu_M / lambda_L
+// (sc, with the mc* fields) plus the spectrum of the face-layer source generated from the
+// 2-D face spectra of gen times scale / lambda_L; face sums along the pass axis (faces,
+// mode 1); store.  gen's layouts as for dst_gen_pass, except lb: [side][ia][m-1] (row pitch
+// bpitch, plane bplane).  The face arrays of gen are turned into their sums and differences
+// in place.  ST_UNSUPPORTED where the persistent kernel's layout conditions fail (checked
+// before anything is launched).
+template <typename T>
+int dst_pipe_mpass(int N, const cx<T>* tw, const T* sn, T* buf, long long outer, long long inner,
+                   const DstScale<T>& sc, const DstFaces<T>& faces, const DstGen<T>& gen, hipStream_t st);
+template <typename T> bool dst_pipe_mpass_ok(int N, long long inner, long long na, const DstGen<T>& gen);
 
 // DST-I of short pencils (even N <= DST_GEMM_MAX_N) as two half-size products with sine
 // matrices on the matrix cores (dst_gemm.hip).  Same layouts as dst_pass (plain passes

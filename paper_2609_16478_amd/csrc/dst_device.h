@@ -335,10 +335,12 @@ __device__ __forceinline__ double recip(double x) {
 }
 
 // Split the pair and form the DST-I outputs in place (positions 1..N-1, 0 -> 0).
-// With SCALE, output m of pencil a (b) is multiplied by scale / (A.x + B.x s[m-1]).
-template <typename T, int N, class P, bool SCALE>
+// With SCALE, output m of pencil a (b) is multiplied by scale / (A.x + B.x s[m-1]); with
+// MSYM also by the weighting operator's symbol C.x + D.x s[m-1].
+template <typename T, int N, class P, bool SCALE, bool MSYM = false>
 __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx<T> B,
-                                     const T* __restrict__ s_this, T scale) {
+                                     const T* __restrict__ s_this, T scale, cx<T> C = cx<T>{},
+                                     cx<T> D = cx<T>{}) {
   constexpr int PPT = P::PPT;
   constexpr int TPS = N / PPT;
   constexpr int H = PPT / 2;
@@ -372,8 +374,13 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
     if constexpr (SCALE) {
       if (k > 0) {
         const T s = s_this[2 * k - 1];
-        e.x *= scale * recip(A.x + B.x * s);
-        e.y *= scale * recip(A.y + B.y * s);
+        if constexpr (MSYM) {
+          e.x *= scale * (C.x + D.x * s) * recip(A.x + B.x * s);
+          e.y *= scale * (C.y + D.y * s) * recip(A.y + B.y * s);
+        } else {
+          e.x *= scale * recip(A.x + B.x * s);
+          e.y *= scale * recip(A.y + B.y * s);
+        }
       }
     }
     seq[pad(2 * k)] = e;
@@ -428,8 +435,13 @@ __device__ __forceinline__ void post(cx<T>* seq, cx<T>* tot, int ts, cx<T> A, cx
     o.y = pre[i].y + offy;
     if constexpr (SCALE) {
       const T s = s_this[2 * k];
-      o.x *= scale * recip(A.x + B.x * s);
-      o.y *= scale * recip(A.y + B.y * s);
+      if constexpr (MSYM) {
+        o.x *= scale * (C.x + D.x * s) * recip(A.x + B.x * s);
+        o.y *= scale * (C.y + D.y * s) * recip(A.y + B.y * s);
+      } else {
+        o.x *= scale * recip(A.x + B.x * s);
+        o.y *= scale * recip(A.y + B.y * s);
+      }
     }
     seq[pad(2 * k + 1)] = o;
   }
@@ -489,6 +501,7 @@ template <typename T> struct Args {
   int lg_nseq;
   DstScale<T> fs;
   DstFaces<T> fc;
+  DstGen<T> gn;  // face-layer spectra added after the scaling (U-solve with spectral M)
 };
 
 // sum over the TPS lanes of one pencil pair (all lanes receive the total)

@@ -91,6 +91,27 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   remap();
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
+  // MODE 3: the tile's row of the face spectra normal to the fastest axis, [0, L) sums and
+  // [L, 2L) differences, in LDS after the tile (prefetched one tile ahead in registers)
+  T* xrow = reinterpret_cast<T*>(smem + (size_t)(NSEQ * LDQ + NSEQ * NTOT) * sizeof(cx<T>));
+  constexpr int XR = MODE == 3 ? (L + NSEQ * TPS - 1) / (NSEQ * TPS) : 1;
+  T xf[2][XR];
+  auto xload = [&](long long tile) {
+    if constexpr (MODE == 3) {
+      const long long o = tile / a.ntile_inner;
+      const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+      const long long ib = c0 / a.fs.na;
+      const T* la = a.gn.la + o * a.gn.aslab + ib * a.gn.arow;
+#pragma unroll
+      for (int r = 0; r < XR; ++r) {
+        const int j = (int)threadIdx.x + r * NSEQ * TPS;
+        if (j < L) {
+          xf[0][r] = la[(long long)j * a.gn.apitch];
+          xf[1][r] = la[a.gn.aplane + (long long)j * a.gn.apitch];
+        }
+      }
+    }
+  };
 
   cx<T> xr[U], yr[U];  // prefetched tile: positions m and N - m of both pencils
   auto tile_base = [&](long long tile, long long& c0) {
@@ -187,6 +208,17 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     remap();
     const cx<T>* tw = a.tw;
     to_lds();
+    if constexpr (MODE == 3) {
+      xload(tile);
+#pragma unroll
+      for (int r = 0; r < XR; ++r) {
+        const int j = tid + r * NSEQ * TPS;
+        if (j < L) {
+          xrow[j] = xf[0][r];
+          xrow[L + j] = xf[1][r];
+        }
+      }
+    }
     __syncthreads();
     const long long nxt = tile + gridDim.x;
     // the next tile is in flight during the transform below (with two transforms, during
@@ -223,7 +255,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       };
       coef(ca, A.x, B.x);
       coef(cb, A.y, B.y);
-      post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
+      // MODE 3 scales in the face loop below, after adding the face-layer term
+      if constexpr (MODE == 3) post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
+      else post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
       if constexpr (MODE == 2) {
         if (nxt < ntiles) load(nxt);
         pre_lds<T, N, PL>(seq, ts, a.sn);
@@ -233,12 +267,73 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
       } else {
       T la = 0, ha = 0, lb = 0, hb = 0;
-#pragma unroll
+      // MODE 3: U = scale (mu_M W + G) / lambda_L at (column, position m), with the
+      // symbol of the weighting operator mu_M = Ca + D s (pencil a), Cb + D s (pencil b) and
+      // G the face-layer source's spectrum: one face value times one layer sine per face
+      // pair (faces as sums/differences, selected by the parity of the mode across the
+      // face; see k_gen_pipe)
+      [[maybe_unused]] T ga0 = 0, gb0 = 0, wla = 0, wlb = 0, wbl = 0, Ca = 1, Cb = 1, D = 0;
+      // y-face values of the pair at position m (face spectra stored [side][column][position],
+      // so the lanes of a pair read consecutive positions): the face plane of the mode's
+      // parity as a uniform base, the pair's two rows as 32-bit offsets
+      [[maybe_unused]] const T* ybase = nullptr;
+      [[maybe_unused]] unsigned yoff = 0, ystep = 0;
+      [[maybe_unused]] const bool va = ca < inner && (ca - (ca / a.fs.na) * a.fs.na) < a.fs.nva;
+      [[maybe_unused]] const bool vb = cb < inner && (cb - (cb / a.fs.na) * a.fs.na) < a.fs.nva;
+      if constexpr (MODE == 3) {
+        const long long ib = c0 / a.fs.na;
+        const long long iaa = ca - ib * a.fs.na;
+        // every position of this thread has the parity of 1 + ts (TPS is even)
+        const bool modd = ((1 + ts) & 1) != 0;
+        const T* lp = a.gn.lp + o * a.gn.pslab + (modd ? 0 : a.gn.pplane);
+        if (va) {
+          ga0 = lp[ca];
+          wla = a.gn.wa[iaa];
+        }
+        if (vb) {
+          gb0 = lp[cb];
+          wlb = a.gn.wa[iaa + 1];
+        }
+        if (a.gn.lb) {
+          wbl = a.gn.wb[ib];
+          ybase = a.gn.lb + o * a.gn.bslab + ((ib & 1) ? a.gn.bplane : 0);
+          yoff = (unsigned)((iaa * a.gn.bpitch + ts) * (long long)sizeof(T));
+          ystep = (unsigned)(a.gn.bpitch * (long long)sizeof(T));
+        }
+        const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
+        if (va) Ca = a.fs.mc0 + a.fs.mca * a.fs.s_a[iaa] + a.fs.mcb * sb;
+        if (vb) Cb = a.fs.mc0 + a.fs.mca * a.fs.s_a[iaa + 1] + a.fs.mcb * sb;
+        D = a.fs.mct;
+      }
+      // MODE 3: four positions at a time (the next tile's prefetch is live here; unrolled,
+      // the face loads of all positions would be hoisted and spill registers)
+#pragma unroll (MODE == 3 ? 4 : PPT)
       for (int i = 0; i < PPT; ++i) {
         const int m = 1 + ts + i * TPS;
         if (i < PPT - 1 || m < N) {
-          const cx<T> v = LIN ? seq[pad(1 + ts) + poff(i * TPS)] : seq[pad(m)];
-          const T wl = a.fc.w[m - 1], wh = a.fc.w[L + m - 1];
+          cx<T>* pv = LIN ? seq + pad(1 + ts) + poff(i * TPS) : seq + pad(m);
+          cx<T> v = *pv;
+          [[maybe_unused]] T wl3 = 0, wh3 = 0;
+          if constexpr (MODE == 3) {
+            const cx<T>* pt = reinterpret_cast<const cx<T>*>(a.gn.ptab) + 2 * (m - 1);
+            const cx<T> t0 = pt[0], t1 = pt[1];
+            const T st = t0.x, wpl = t0.y;
+            wl3 = t1.x;
+            wh3 = t1.y;
+            T ga = ga0 * wpl + xrow[m - 1] * wla;
+            T gb = gb0 * wpl + xrow[L + m - 1] * wlb;
+            if (ybase) {
+              // byte offsets below 2^32 (checked at launch)
+              const SBase ys(ybase);
+              const unsigned off = yoff + (unsigned)(i * TPS * (int)sizeof(T));
+              ga += ys.template ld<T>(off) * wbl;
+              gb += ys.template ld<T>(off + ystep) * wbl;
+            }
+            v.x = (v.x * (Ca + D * st) + (va ? ga : T(0))) * (a.fs.scale * recip(A.x + B.x * st));
+            v.y = (v.y * (Cb + D * st) + (vb ? gb : T(0))) * (a.fs.scale * recip(A.y + B.y * st));
+            *pv = v;
+          }
+          const T wl = MODE == 3 ? wl3 : a.fc.w[m - 1], wh = MODE == 3 ? wh3 : a.fc.w[L + m - 1];
           la += v.x * wl;
           ha += v.x * wh;
           lb += v.y * wl;
@@ -272,7 +367,8 @@ template <typename T, int N, int MODE> struct PipeLaunch {
   static constexpr int TPS = N / PipePlan<N>::PPT;
   static constexpr int THREADS = NSEQ * TPS;
   static constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) *
-                                sizeof(cx<T>);
+                                    sizeof(cx<T>) +
+                                (MODE == 3 ? 2 * (size_t)(N - 1) * sizeof(T) : 0);
 
   // resident work-groups on the device (persistent grid)
   static int resident() {
@@ -718,6 +814,88 @@ int dst_gen_pipe_pass(const DstTables<T>& tb, T* out, long long outer, long long
     default: return ST_UNSUPPORTED;
   }
 }
+
+namespace fast {
+namespace {
+
+// Launch conditions of the U-solve pass with spectral M (k_dst_pipe MODE 3)
+template <typename T, int N> int mpass_check(long long inner, long long na, const DstGen<T>& g) {
+  using PLc = PipeLaunch<T, N, 3>;
+  if (inner <= 1 || (inner & 1)) return ST_UNSUPPORTED;
+  if ((double)(N - 1) * (double)inner >= 2147483647.0) return ST_UNSUPPORTED;
+  if (PLc::THREADS % 64 != 0 || PLc::THREADS > pipe_cap<T, N>() || PLc::LDS > 160 * 1024) return ST_UNSUPPORTED;
+  if ((double)(PLc::TPS + 1) * (double)inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+  // a tile lies in one row of the column decode (one row of the face spectra normal to the
+  // fastest axis); the y-face values of a pair are read as one aligned vector
+  if (na <= 0 || na % (2 * PLc::NSEQ) != 0) return ST_UNSUPPORTED;
+  if (!g.lp || !g.la || !g.wp || !g.wa || !g.ptab) return ST_UNSUPPORTED;
+  // y-face spectra [side][column][position] with row pitch bpitch >= N - 1 (byte offsets
+  // within one face plane fit 32 bits)
+  if (g.lb && (!g.wb || g.bpitch < N - 1 || (double)g.bplane * sizeof(T) >= 4294967295.0)) return ST_UNSUPPORTED;
+  if (PLc::resident() <= 0) return ST_UNSUPPORTED;
+  return ST_OK;
+}
+
+template <typename T, int N>
+int mpass_run(const cx<T>* tw, const T* sn, T* buf, long long outer, long long inner, const DstScale<T>& sc,
+              const DstFaces<T>& faces, const DstGen<T>& gen, hipStream_t st) {
+  TRY_ST((mpass_check<T, N>(inner, sc.na, gen)));
+  T* lp = const_cast<T*>(gen.lp);
+  T* la = const_cast<T*>(gen.la);
+  T* lb = const_cast<T*>(gen.lb);
+  TRY_ST(face_pm<T>(lp, gen.pplane, outer > 1 ? gen.pslab : 0, gen.pplane, outer, st));
+  TRY_ST(face_pm<T>(la, gen.aplane, outer > 1 ? gen.aslab : 0, gen.aplane, outer, st));
+  if (lb) TRY_ST(face_pm<T>(lb, gen.bplane, outer > 1 ? gen.bslab : 0, gen.bplane, outer, st));
+  Args<T> a;
+  a.in = buf;
+  a.out = buf;
+  a.tw = tw;
+  a.sn = sn;
+  a.outer = outer;
+  a.inner = inner;
+  a.pitch = inner;
+  a.fs = sc;
+  a.fc = faces;
+  a.fc.mode = 1;
+  a.gn = gen;
+  return PipeLaunch<T, N, 3>::run(a, 0, st);
+}
+
+}  // namespace
+}  // namespace fast
+
+#define AHOC_MPASS_CASES(X) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024) X(2048) X(4096)
+
+template <typename T> bool dst_pipe_mpass_ok(int N, long long inner, long long na, const DstGen<T>& gen) {
+  switch (N) {
+#define AHOC_MCHK(NN) \
+  case NN: return fast::mpass_check<T, NN>(inner, na, gen) == ST_OK;
+    AHOC_MPASS_CASES(AHOC_MCHK)
+#undef AHOC_MCHK
+    default: return false;
+  }
+}
+
+template <typename T>
+int dst_pipe_mpass(int N, const cx<T>* tw, const T* sn, T* buf, long long outer, long long inner,
+                   const DstScale<T>& sc, const DstFaces<T>& faces, const DstGen<T>& gen, hipStream_t st) {
+  switch (N) {
+#define AHOC_MRUN(NN) \
+  case NN: return fast::mpass_run<T, NN>(tw, sn, buf, outer, inner, sc, faces, gen, st);
+    AHOC_MPASS_CASES(AHOC_MRUN)
+#undef AHOC_MRUN
+    default: return ST_UNSUPPORTED;
+  }
+}
+#undef AHOC_MPASS_CASES
+
+template bool dst_pipe_mpass_ok<float>(int, long long, long long, const DstGen<float>&);
+template bool dst_pipe_mpass_ok<double>(int, long long, long long, const DstGen<double>&);
+template int dst_pipe_mpass<float>(int, const cx<float>*, const float*, float*, long long, long long,
+                                   const DstScale<float>&, const DstFaces<float>&, const DstGen<float>&, hipStream_t);
+template int dst_pipe_mpass<double>(int, const cx<double>*, const double*, double*, long long, long long,
+                                    const DstScale<double>&, const DstFaces<double>&, const DstGen<double>&,
+                                    hipStream_t);
 
 template int dst_pipe_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
                                   const DstScale<float>*, const DstFaces<float>*, int, hipStream_t);

@@ -121,6 +121,169 @@ __global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows
   }
 }
 
+// Two DST-I transforms of each row with a pointwise product between them,
+//   out_row = S (c_row .* (S in_row)),
+// c a nodal array: row r = (j - 1) + (p - kofs) ni1 of the interior (j = 1..ni1, plane or
+// instance p) reads c[(p nn1 + j) nn0 + i] at position i = 1..N-1.  The x pass of the Schur
+// matvec: the V-solve's last inverse transform, V / alpha, and the U-solve's first forward
+// transform in one read and one write of the volume.  The multiplier rows are fetched after
+// the first transform; between the transforms every position stays with the thread that
+// the store mapping gives it, then the pre-weighting of the second transform reads the
+// mirrored positions from LDS.
+template <typename T, int N>
+__global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows_mul(
+    const T* __restrict__ in, T* __restrict__ out, const cx<T>* __restrict__ tw, const T* __restrict__ sn,
+    long long nrows, long long pitch, const T* __restrict__ c, int ni1, int kofs, int nn0, int nn1) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  using PL = RPlan<N>;
+  constexpr int PPT = PL::PPT;
+  constexpr int TPS = N / PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int HN = N / 2;
+  constexpr int U = PPT / 2;
+  constexpr int LDQ = seq_stride<N>();
+  constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
+  constexpr bool LIN = TPS % 32 == 0;
+  cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
+  const int q = threadIdx.x / TPS;
+  const int t = threadIdx.x - q * TPS;
+  cx<T>* seq = lds + q * LDQ;
+  cx<T>* tot = lds + NSEQ * LDQ + q * NTOT;
+  const long long r0 = (long long)blockIdx.x * (2 * NSEQ);
+  const long long ra = r0 + 2 * q;
+  const bool oka = ra < nrows, okb = ra + 1 < nrows;
+  const SBase src(in + r0 * pitch);
+  const unsigned oa = (unsigned)((2 * q) * pitch * (long long)sizeof(T));
+  const unsigned ob = oa + (unsigned)(pitch * (long long)sizeof(T));
+
+  // ---- load + pre-weighting (as k_dst_rows)
+  {
+    cx<T>* lo = seq + pad(1 + t);
+    cx<T>* hi = seq + pad(N - 1 - t);
+    T xa[U], xb[U], ya[U], yb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = 1 + t + u * TPS;
+      const unsigned e1 = (unsigned)((m - 1) * (int)sizeof(T)), e2 = (unsigned)((N - m - 1) * (int)sizeof(T));
+      xa[u] = oka ? src.ld<T>(oa + e1) : T(0);
+      xb[u] = okb ? src.ld<T>(ob + e1) : T(0);
+      const bool mid = u == U - 1 && m == HN;
+      ya[u] = (oka && !mid) ? src.ld<T>(oa + e2) : T(0);
+      yb[u] = (okb && !mid) ? src.ld<T>(ob + e2) : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int m = 1 + t + u * TPS;
+      cx<T>* plo = LIN ? lo + poff(u * TPS) : seq + pad(m);
+      cx<T>* phi = LIN ? hi - poff(u * TPS) : seq + pad(N - m);
+      if (u == U - 1 && m == HN) {
+        cx<T> o;
+        o.x = T(2) * xa[u];
+        o.y = T(2) * xb[u];
+        *plo = o;
+      } else {
+        const T w = sn[m];
+        const T sx = w * (xa[u] + ya[u]), sy = w * (xb[u] + yb[u]);
+        const T dx = T(0.5) * (xa[u] - ya[u]), dy = T(0.5) * (xb[u] - yb[u]);
+        cx<T> o1, o2;
+        o1.x = sx + dx;
+        o1.y = sy + dy;
+        o2.x = sx - dx;
+        o2.y = sy - dy;
+        *plo = o1;
+        *phi = o2;
+      }
+    }
+    if (t == 0) {
+      cx<T> z;
+      z.x = T(0);
+      z.y = T(0);
+      seq[0] = z;
+    }
+  }
+  __syncthreads();
+
+  cx<T> A, B;
+  A.x = A.y = T(1);
+  B.x = B.y = T(0);
+  fft<T, N, PL>(seq, t, tw);
+  post<T, N, PL, false>(seq, tot, t, A, B, nullptr, T(0));
+
+  // ---- multiplier rows at the store positions m = 1 + t + k TPS (fetched here, not
+  // before the first transform: held across it they cost occupancy)
+  T ma[PPT], mb[PPT];
+  {
+    const T* rowa = c;
+    const T* rowb = c;
+    if (oka) {
+      const long long p = ra / ni1;
+      rowa = c + ((p + kofs) * nn1 + (ra - p * ni1 + 1)) * (long long)nn0;
+    }
+    if (okb) {
+      const long long p = (ra + 1) / ni1;
+      rowb = c + ((p + kofs) * nn1 + (ra + 1 - p * ni1 + 1)) * (long long)nn0;
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int m = 1 + t + k * TPS;
+      const bool in_n = k < PPT - 1 || m < N;
+      ma[k] = (oka && in_n) ? rowa[m] : T(0);
+      mb[k] = (okb && in_n) ? rowb[m] : T(0);
+    }
+  }
+
+  // ---- pointwise product at the thread's own positions, then the second transform
+  {
+    cx<T>* lo = seq + pad(1 + t);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int m = 1 + t + k * TPS;
+      if (k < PPT - 1 || m < N) {
+        cx<T>* pv = LIN ? lo + poff(k * TPS) : seq + pad(m);
+        cx<T> v = *pv;
+        v.x *= ma[k];
+        v.y *= mb[k];
+        *pv = v;
+      }
+    }
+  }
+  pair_sync<TPS>();
+  pre_lds<T, N, PL>(seq, t, sn);
+  fft<T, N, PL>(seq, t, tw);
+  post<T, N, PL, false>(seq, tot, t, A, B, nullptr, T(0));
+
+  const SBase dst(out + r0 * pitch);
+  const cx<T>* lo = seq + pad(1 + t);
+#pragma unroll
+  for (int k = 0; k < PPT; ++k) {
+    const int m = 1 + t + k * TPS;
+    if (k < PPT - 1 || m < N) {
+      const cx<T> v = LIN ? lo[poff(k * TPS)] : seq[pad(m)];
+      const unsigned e = (unsigned)((m - 1) * (int)sizeof(T));
+      if (oka) dst.st<T>(oa + e, v.x);
+      if (okb) dst.st<T>(ob + e, v.y);
+    }
+  }
+}
+
+template <typename T, int N> int rows_mul_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
+                                                 long long pitch, const T* c, int ni1, int kofs, int nn0, int nn1,
+                                                 hipStream_t st) {
+  constexpr int TPS = N / RPlan<N>::PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int THREADS = NSEQ * TPS;
+  constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
+  if (THREADS % 64 != 0 || THREADS > 1024 || LDS > 64 * 1024) return ST_UNSUPPORTED;
+  if ((double)(2 * NSEQ) * (double)pitch * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+  const long long blocks = (nrows + 2 * NSEQ - 1) / (2 * NSEQ);
+  if (blocks <= 0) return ST_OK;
+  if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+  hipLaunchKernelGGL((k_dst_rows_mul<T, N>), dim3((unsigned)blocks), dim3(THREADS), LDS, st, in, out, tw, sn, nrows,
+                     pitch, c, ni1, kofs, nn0, nn1);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
 template <typename T, int N> int rows_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
                                              long long pitch, hipStream_t st) {
   constexpr int TPS = N / RPlan<N>::PPT;
@@ -163,6 +326,32 @@ int dst_rows_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
     default: return ST_UNSUPPORTED;
   }
 }
+
+template <typename T>
+int dst_rows_mul_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
+                      const T* c, int ni1, int kofs, int nn0, int nn1, hipStream_t st) {
+  if (pitch < N - 1 || ni1 <= 0 || nn0 < N + 1) return ST_INVALID;
+  switch (N) {
+    case 32: return fast::rows_mul_launch<T, 32>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 64: return fast::rows_mul_launch<T, 64>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 96: return fast::rows_mul_launch<T, 96>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 128: return fast::rows_mul_launch<T, 128>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 192: return fast::rows_mul_launch<T, 192>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 256: return fast::rows_mul_launch<T, 256>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 384: return fast::rows_mul_launch<T, 384>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 512: return fast::rows_mul_launch<T, 512>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 768: return fast::rows_mul_launch<T, 768>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 1024: return fast::rows_mul_launch<T, 1024>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 2048: return fast::rows_mul_launch<T, 2048>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    case 4096: return fast::rows_mul_launch<T, 4096>(in, out, tw, sn, nrows, pitch, c, ni1, kofs, nn0, nn1, st);
+    default: return ST_UNSUPPORTED;
+  }
+}
+
+template int dst_rows_mul_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
+                                      const float*, int, int, int, int, hipStream_t);
+template int dst_rows_mul_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
+                                       long long, const double*, int, int, int, int, hipStream_t);
 
 template int dst_rows_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
                                   hipStream_t);

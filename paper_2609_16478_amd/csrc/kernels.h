@@ -17,6 +17,10 @@ int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af,
 // face layers of the homogeneous lift (input of the spectral lift); fixed-order sums of partials
 template <typename T>
 int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, hipStream_t st);
+// face layers m1 Q_b / alpha_b of the U-solve's source (spectral M), layouts as face_lift
+// except the 3-D y faces, [2][n_x'][n_z'] (z fastest)
+template <typename T>
+int face_lift_m(const Geom& g, const Weights& w, const T* Q, const T* ia, T* Lx, T* Ly, T* Lz, hipStream_t st);
 template <typename T>
 int partial_sum(long long n, int count, long long stride, const T* in, T* out, hipStream_t st);
 // boundary-symbol preconditioner (precond.hip): inverse 2x2 block coefficients per face

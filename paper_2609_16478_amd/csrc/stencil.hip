@@ -562,6 +562,63 @@ __global__ void k_face_lift(Geom g, Weights w, const T* __restrict__ Q, T* __res
   }
 }
 
+// Face layers of the U-solve's source M(V / alpha) in the homogeneous matvec: the 7-point M
+// couples an interior node next to a face only to the face node along the normal, where
+// V = Q, so the layer value is m1 Q_b / alpha_b (alpha_b from the nodal 1/alpha).  Layouts as
+// k_face_lift, except the 3-D y faces: [side][i][k] with k fastest (pitch n_z', no padding),
+// the order in which the slowest-axis pass reads them.  Padding entries are written as zero.
+template <typename T, int DIM>
+__global__ void k_face_lift_m(Geom g, T m1, const T* __restrict__ Q, const T* __restrict__ ia, T* __restrict__ Lx,
+                              T* __restrict__ Ly, T* __restrict__ Lz, long long px_plane, long long py_plane,
+                              long long pz_plane) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  Q += b_ * g.nq;
+  ia += b_ * g.nnodal;
+  Lx += b_ * 2 * px_plane;
+  Ly += b_ * 2 * py_plane;
+  if (Lz) Lz += b_ * 2 * pz_plane;
+  const long long tot = 2 * (px_plane + py_plane + (DIM == 3 ? pz_plane : 0));
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < tot;
+       e += (long long)gridDim.x * blockDim.x) {
+    int f;
+    long long t;
+    T* out;
+    if (e < 2 * px_plane) {
+      f = (int)(e / px_plane);
+      t = e - f * px_plane;
+      out = Lx + e;
+    } else if (e < 2 * (px_plane + py_plane)) {
+      const long long r = e - 2 * px_plane;
+      f = 2 + (int)(r / py_plane);
+      t = r - (f - 2) * py_plane;
+      out = Ly + r;
+    } else {
+      const long long r = e - 2 * (px_plane + py_plane);
+      f = 4 + (int)(r / pz_plane);
+      t = r - (f - 4) * pz_plane;
+      out = Lz + r;
+    }
+    int i, j, k, valid;
+    if (DIM == 3 && (f >> 1) == 1) {  // y faces transposed: t = (i - 1) n_z' + (k - 1)
+      j = (f & 1) ? g.ni[1] : 1;
+      i = (int)(t / g.ni[2]) + 1;
+      k = (int)(t % g.ni[2]) + 1;
+      valid = 1;
+    } else {
+      face_node<DIM>(g, f, t, i, j, k, valid);
+    }
+    T acc = 0;
+    if (valid) {
+      const int ax = f >> 1;
+      const int dn = (f & 1) ? 1 : -1;
+      const int qi = i + (ax == 0 ? dn : 0), qj = j + (ax == 1 ? dn : 0), qk = k + (ax == 2 ? dn : 0);
+      const long long nod = DIM == 3 ? ((long long)qk * g.nn[1] + qj) * g.nn[0] + qi : (long long)qj * g.nn[0] + qi;
+      acc = m1 * Q[qidx<DIM>(g, qi, qj, qk)] * ia[nod];
+    }
+    *out = acc;
+  }
+}
+
 // out[e] = sum_{b < count} in[b * stride + e], e < n, in a fixed order
 template <typename T>
 __global__ void k_partial_sum(long long n, int count, long long stride, const T* __restrict__ in,
@@ -1326,6 +1383,16 @@ int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, 
 }
 
 template <typename T>
+int face_lift_m(const Geom& g, const Weights& w, const T* Q, const T* ia, T* Lx, T* Ly, T* Lz, hipStream_t st) {
+  const long long pxp = g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1];
+  const long long pyp = g.dim == 3 ? (long long)g.ni[0] * g.ni[2] : g.px;
+  const long long pzp = g.dim == 3 ? (long long)g.px * g.ni[1] : 0;
+  const long long tot = 2 * (pxp + pyp + pzp);
+  LAUNCH_TDIM(k_face_lift_m, T, dim3(nblocks(tot), g.nb), g, (T)w.m1, Q, ia, Lx, Ly, Lz, pxp, pyp, pzp);
+  return ST_OK;
+}
+
+template <typename T>
 int partial_sum(long long n, int count, long long stride, const T* in, T* out, hipStream_t st) {
   hipLaunchKernelGGL((k_partial_sum<T>), dim3(nblocks(n)), dim3(TPB), 0, st, n, count, stride, in, out);
   AHOC_HIP_TRY(hipGetLastError());
@@ -1477,6 +1544,7 @@ int fill(long long n, double v, double* x, hipStream_t st) {
 
 #define INST_T(T)                                                                                  \
   template int face_lift<T>(const Geom&, const Weights&, const T*, T*, T*, T*, hipStream_t);       \
+  template int face_lift_m<T>(const Geom&, const Weights&, const T*, const T*, T*, T*, T*, hipStream_t); \
   template int partial_sum<T>(long long, int, long long, const T*, T*, hipStream_t);               \
   template int gather_faces<T>(const Geom&, const T*, const T*, const T*, const T*, const T*,       \
                                const T*, double*, hipStream_t);                                    \
