@@ -238,6 +238,18 @@ struct SBase {
     static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "4, 8 or 16 bytes");
     *reinterpret_cast<__attribute__((address_space(1))) Bits<V>*>(p + off) = __builtin_bit_cast(Bits<V>, v);
   }
+  // streaming (non-temporal) forms: data touched once, kept from displacing reused lines
+  template <typename V> __device__ __forceinline__ V ld_nt(unsigned off) const {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "4, 8 or 16 bytes");
+    const Bits<V> r =
+        __builtin_nontemporal_load(reinterpret_cast<const __attribute__((address_space(1))) Bits<V>*>(p + off));
+    return __builtin_bit_cast(V, r);
+  }
+  template <typename V> __device__ __forceinline__ void st_nt(unsigned off, const V& v) const {
+    static_assert(sizeof(V) == 4 || sizeof(V) == 8 || sizeof(V) == 16, "4, 8 or 16 bytes");
+    __builtin_nontemporal_store(__builtin_bit_cast(Bits<V>, v),
+                                reinterpret_cast<__attribute__((address_space(1))) Bits<V>*>(p + off));
+  }
 };
 template <> struct SBase::Raw<4> { using type = unsigned; };
 template <> struct SBase::Raw<8> { typedef unsigned type __attribute__((ext_vector_type(2))); };
@@ -502,7 +514,13 @@ template <typename T> struct Args {
   DstScale<T> fs;
   DstFaces<T> fc;
   DstGen<T> gn;  // face-layer spectra added after the scaling (U-solve with spectral M)
+  int ntst;      // non-temporal loads and stores (arrays larger than the caches)
 };
+
+// Arrays of at least this size stream through the caches: their passes load and store
+// with the non-temporal policy.  Smaller ones (batches of small instances) are re-read from
+// the caches by the next pass, which the non-temporal policy would prevent.
+constexpr double NT_STORE_MIN_BYTES = 256.0 * 1024 * 1024;
 
 // sum over the TPS lanes of one pencil pair (all lanes receive the total)
 template <typename T, int TPS>

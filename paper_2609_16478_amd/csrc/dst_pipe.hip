@@ -54,7 +54,24 @@ template <typename T, int N> constexpr int pipe_nseq() {
   return nseq;
 }
 
-template <typename T, int N, int NSEQ, int MODE>
+// LDS of a tile (sequences and segment totals) and, in MODE 3, the face row and (where it
+// fits) the per-position table after it
+template <typename T, int N, int NSEQ> constexpr size_t pipe_tile_bytes() {
+  constexpr int TPS = N / PipePlan<N>::PPT;
+  return (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
+}
+template <typename T, int N, int NSEQ> constexpr bool pipe_ptab_lds() {
+  return pipe_tile_bytes<T, N, NSEQ>() + 6 * (size_t)(N - 1) * sizeof(T) <= 160 * 1024;
+}
+template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_lds_bytes() {
+  return pipe_tile_bytes<T, N, NSEQ>() +
+         (MODE == 3 ? (2 + (pipe_ptab_lds<T, N, NSEQ>() ? 4 : 0)) * (size_t)(N - 1) * sizeof(T) : 0);
+}
+
+// NT: the volume is loaded and stored with the non-temporal policy (arrays larger than the
+// caches, see NT_STORE_MIN_BYTES); a compile-time choice, so that the prefetched registers
+// do not meet at a branch join, which would wait for the loads in flight
+template <typename T, int N, int NSEQ, int MODE, bool NT>
 __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   using PL = PipePlan<N>;
@@ -91,9 +108,17 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   remap();
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
-  // MODE 3: the tile's row of the face spectra normal to the fastest axis, [0, L) sums and
-  // [L, 2L) differences, in LDS after the tile (prefetched one tile ahead in registers)
-  T* xrow = reinterpret_cast<T*>(smem + (size_t)(NSEQ * LDQ + NSEQ * NTOT) * sizeof(cx<T>));
+  // MODE 3: the tile's row of the face spectra normal to the fastest axis as (sum,
+  // difference) pairs per position, in LDS after the tile (prefetched one tile ahead in
+  // registers); then, where LDS has room, the per-position table (s, layer sine, face
+  // weights), loaded once
+  cx<T>* xrow = reinterpret_cast<cx<T>*>(smem + (size_t)(NSEQ * LDQ + NSEQ * NTOT) * sizeof(cx<T>));
+  constexpr bool PTL = MODE == 3 && pipe_ptab_lds<T, N, NSEQ>();
+  cx<T>* ptl = xrow + L;  // [m - 1][2]
+  if constexpr (PTL) {
+    const cx<T>* pg = reinterpret_cast<const cx<T>*>(a.gn.ptab);
+    for (int j = threadIdx.x; j < 2 * L; j += NSEQ * TPS) ptl[j] = pg[j];
+  }
   constexpr int XR = MODE == 3 ? (L + NSEQ * TPS - 1) / (NSEQ * TPS) : 1;
   T xf[2][XR];
   auto xload = [&](long long tile) {
@@ -134,12 +159,22 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     // keep the 32-bit offsets local to this block, so that each access is selected in the
     // scalar-base + 32-bit-offset form
     asm volatile("" : "+v"(vl), "+v"(vh));
+    // position m - 1 = u TPS + mi; position N - m - 1 = (N - 1 - (u + 1) TPS) + (TPS - 1 - mi)
+    // (for m = N/2 the latter is read but unused).  A volume larger than the caches streams
+    // through once: non-temporal, so that it does not displace the tables and (MODE 3) the
+    // re-read face spectra in L2
+    if constexpr (NT) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      // position m - 1 = u TPS + mi; position N - m - 1 = (N - 1 - (u + 1) TPS) + (TPS - 1 - mi)
-      // (for m = N/2 the latter is read but unused)
-      xr[u] = src.plus((long long)(u * TPS) * rowb).ld<cx<T>>(vl);
-      yr[u] = src.plus((long long)(N - 1 - (u + 1) * TPS) * rowb).ld<cx<T>>(vh);
+      for (int u = 0; u < U; ++u) {
+        xr[u] = src.plus((long long)(u * TPS) * rowb).ld_nt<cx<T>>(vl);
+        yr[u] = src.plus((long long)(N - 1 - (u + 1) * TPS) * rowb).ld_nt<cx<T>>(vh);
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        xr[u] = src.plus((long long)(u * TPS) * rowb).ld<cx<T>>(vl);
+        yr[u] = src.plus((long long)(N - 1 - (u + 1) * TPS) * rowb).ld<cx<T>>(vh);
+      }
     }
     if (c0 + 2 * NSEQ > inner && !ok) {
 #pragma unroll
@@ -194,11 +229,20 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     asm volatile("" : "+v"(vs));
     const cx<T>* sq = lds + q * LDQ;
     const cx<T>* lo = sq + pad(1 + mi);
+    if constexpr (NT) {
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int m = 1 + mi + k * TPS;
-      if (k < PPT - 1 || m < N)
-        dst.plus((long long)(k * TPS) * rowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+      for (int k = 0; k < PPT; ++k) {
+        const int m = 1 + mi + k * TPS;
+        if (k < PPT - 1 || m < N)
+          dst.plus((long long)(k * TPS) * rowb).st_nt<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < PPT; ++k) {
+        const int m = 1 + mi + k * TPS;
+        if (k < PPT - 1 || m < N)
+          dst.plus((long long)(k * TPS) * rowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+      }
     }
   };
 
@@ -214,8 +258,10 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * NSEQ * TPS;
         if (j < L) {
-          xrow[j] = xf[0][r];
-          xrow[L + j] = xf[1][r];
+          cx<T> xv;
+          xv.x = xf[0][r];
+          xv.y = xf[1][r];
+          xrow[j] = xv;
         }
       }
     }
@@ -307,7 +353,8 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       }
       // MODE 3: four positions at a time (the next tile's prefetch is live here; unrolled,
       // the face loads of all positions would be hoisted and spill registers)
-#pragma unroll (MODE == 3 ? 4 : PPT)
+      constexpr int FLU = MODE == 3 ? 4 : PPT;
+#pragma unroll FLU
       for (int i = 0; i < PPT; ++i) {
         const int m = 1 + ts + i * TPS;
         if (i < PPT - 1 || m < N) {
@@ -315,13 +362,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
           cx<T> v = *pv;
           [[maybe_unused]] T wl3 = 0, wh3 = 0;
           if constexpr (MODE == 3) {
-            const cx<T>* pt = reinterpret_cast<const cx<T>*>(a.gn.ptab) + 2 * (m - 1);
+            const cx<T>* pt = (PTL ? ptl : reinterpret_cast<const cx<T>*>(a.gn.ptab)) + 2 * (m - 1);
             const cx<T> t0 = pt[0], t1 = pt[1];
             const T st = t0.x, wpl = t0.y;
             wl3 = t1.x;
             wh3 = t1.y;
-            T ga = ga0 * wpl + xrow[m - 1] * wla;
-            T gb = gb0 * wpl + xrow[L + m - 1] * wlb;
+            const cx<T> xv = xrow[m - 1];
+            T ga = ga0 * wpl + xv.x * wla;
+            T gb = gb0 * wpl + xv.y * wlb;
             if (ybase) {
               // byte offsets below 2^32 (checked at launch)
               const SBase ys(ybase);
@@ -366,16 +414,17 @@ template <typename T, int N, int MODE> struct PipeLaunch {
   static constexpr int NSEQ = pipe_nseq<T, N>();
   static constexpr int TPS = N / PipePlan<N>::PPT;
   static constexpr int THREADS = NSEQ * TPS;
-  static constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) *
-                                    sizeof(cx<T>) +
-                                (MODE == 3 ? 2 * (size_t)(N - 1) * sizeof(T) : 0);
+  static constexpr size_t LDS = pipe_lds_bytes<T, N, NSEQ, MODE>();
+
+  // the non-temporal form exists where a volume can exceed the caches (N >= 384)
+  static constexpr bool HAS_NT = N >= 384;
 
   // resident work-groups on the device (persistent grid)
-  static int resident() {
+  template <bool NT> static int resident() {
     static std::once_flag once;
     static int r = 0;
     std::call_once(once, [] {
-      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ, MODE>);
+      const void* fn = reinterpret_cast<const void*>(&k_dst_pipe<T, N, NSEQ, MODE, NT && HAS_NT>);
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       int dev = 0, cus = 0, per = 0;
       if (hipGetDevice(&dev) == hipSuccess &&
@@ -392,14 +441,19 @@ template <typename T, int N, int MODE> struct PipeLaunch {
     if (THREADS % 64 != 0 || THREADS > pipe_cap<T, N>() || LDS > 160 * 1024) return ST_UNSUPPORTED;
     // per-lane byte offsets span TPS rows and must fit in 32 bits
     if ((double)(TPS + 1) * (double)a.inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
-    const int res = resident();
+    const bool nt = HAS_NT && (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
+    const int res = nt ? resident<true>() : resident<false>();
     if (res <= 0) return ST_UNSUPPORTED;
     a.lg_nseq = ilog2(NSEQ);
     a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
+    a.ntst = nt;
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
     const long long grid = ntiles < res ? ntiles : res;
-    hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, MODE>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    if (nt)
+      hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, MODE, HAS_NT>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    else
+      hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, MODE, false>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
     AHOC_HIP_TRY(hipGetLastError());
     return ST_OK;
   }
@@ -432,6 +486,7 @@ template <typename T> struct GenPipeArgs {
   long long outer, inner, ntile_inner;
   DstScale<T> fs;
   DstGen<T> g;
+  int ntst;  // non-temporal stores (arrays larger than the caches)
 };
 
 // (lo, hi) -> (lo + hi, lo - hi) for `count` entries of each of `nslab` slabs:
@@ -675,10 +730,20 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       const SBase dst(a.out + o * (long long)L * inner + c0);
       unsigned vs = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
       asm volatile("" : "+v"(vs));
+      if (a.ntst) {
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const int m = 1 + mi + k * TPS;
-        if (k < PPT - 1 || m < N) dst.plus((long long)(k * TPS) * orowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+        for (int k = 0; k < PPT; ++k) {
+          const int m = 1 + mi + k * TPS;
+          if (k < PPT - 1 || m < N)
+            dst.plus((long long)(k * TPS) * orowb).st_nt<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+          const int m = 1 + mi + k * TPS;
+          if (k < PPT - 1 || m < N)
+            dst.plus((long long)(k * TPS) * orowb).st<cx<T>>(vs, LIN ? lo[poff(k * TPS)] : sq[pad(m)]);
+        }
       }
     }
     __syncthreads();  // the next tile overwrites LDS
@@ -728,6 +793,7 @@ template <typename T, int N> struct GenPipeLaunch {
     TRY_ST(face_pm<T>(la, a.g.aplane, a.outer > 1 ? a.g.aslab : 0, a.g.aplane, a.outer, st));
     if (lb) TRY_ST(face_pm<T>(lb, a.g.bplane, a.outer > 1 ? a.g.bslab : 0, a.g.bplane, a.outer, st));
     const long long grid = ntiles < res ? ntiles : res;
+    a.ntst = (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
     hipLaunchKernelGGL((k_gen_pipe<T, N, NSEQ>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
     AHOC_HIP_TRY(hipGetLastError());
     return ST_OK;
@@ -832,7 +898,7 @@ template <typename T, int N> int mpass_check(long long inner, long long na, cons
   // y-face spectra [side][column][position] with row pitch bpitch >= N - 1 (byte offsets
   // within one face plane fit 32 bits)
   if (g.lb && (!g.wb || g.bpitch < N - 1 || (double)g.bplane * sizeof(T) >= 4294967295.0)) return ST_UNSUPPORTED;
-  if (PLc::resident() <= 0) return ST_UNSUPPORTED;
+  if (PLc::template resident<false>() <= 0 || PLc::template resident<true>() <= 0) return ST_UNSUPPORTED;
   return ST_OK;
 }
 

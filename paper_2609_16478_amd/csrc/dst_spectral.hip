@@ -299,7 +299,7 @@ __global__ void __launch_bounds__(256) k_face_reduce_w(const T* __restrict__ W, 
     const T* __restrict__ row = Wp + (long long)ky * px;
     T v[CPL];
 #pragma unroll
-    for (int j = 0; j < CPL; ++j) v[j] = row[lane + 64 * j];
+    for (int j = 0; j < CPL; ++j) v[j] = __builtin_nontemporal_load(row + lane + 64 * j);  // read once
     const T yl = wy[ky], yh = wy[ny + ky];
     T dl = 0, dh = 0;
 #pragma unroll
