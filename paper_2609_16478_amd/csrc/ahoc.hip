@@ -934,9 +934,9 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
   }
   if (P.mspec) {
     TRY(matvec_mspec<T>(h, P, qT, y, st));
-    // algorithmic bytes: generated pass (write), y inverse, x pass (read, 1/alpha, write),
-    // y forward, z forward, face reduction (read)
-    tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (9.0 * h->g.nint + h->g.nnodal), st);
+    // algorithmic bytes: generated pass (write 1), y inverse (2), x pass (read, write: 2,
+    // and the nodal 1/alpha), y forward (2), z forward (2), face reduction (read 1)
+    tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (10.0 * h->g.nint + h->g.nnodal), st);
     return ST_OK;
   }
   if (P.spectral) {
