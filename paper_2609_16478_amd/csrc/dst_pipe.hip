@@ -522,10 +522,10 @@ template <typename T, int N, int NSEQ> struct GenShape {
   static constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
   static constexpr size_t TILE_B = (size_t)(NSEQ * seq_stride<N>() + NSEQ * NTOT) * sizeof(cx<T>);
   static constexpr size_t LDS_MAX = 160 * 1024;
-  // x-face row [2][L] in LDS; tables (layer sines, eigenvalues) [2][L] in LDS after it
+  // x-face row as (sum, difference) per position in LDS; then the tables as (layer sine,
+  // eigenvalue) per position
   static constexpr bool XLDS = TILE_B + 2 * (size_t)L * sizeof(T) <= LDS_MAX;
   static constexpr bool TLDS = XLDS && TILE_B + 4 * (size_t)L * sizeof(T) <= LDS_MAX;
-  static constexpr bool TREG = false;  // (registers: FP64 at N = 1024 spills)
   static constexpr int XR = (L + THREADS - 1) / THREADS;  // x-face entries per thread and side
   static constexpr size_t LDS = TILE_B + (XLDS ? 2 * (size_t)L * sizeof(T) : 0) + (TLDS ? 2 * (size_t)L * sizeof(T) : 0);
 };
@@ -538,17 +538,19 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
   constexpr int PPT = SH::PPT;
   constexpr int TPS = SH::TPS;
   constexpr int L = SH::L;
+  constexpr int HN = N / 2;
+  constexpr int U = PPT / 2;
   constexpr int THREADS = SH::THREADS;
   constexpr int LDQ = seq_stride<N>();
   constexpr int LGQ = ilog2(NSEQ);
   constexpr int NTOT = SH::NTOT;
   constexpr bool LIN = TPS % 32 == 0;
-  constexpr bool XLDS = SH::XLDS, TLDS = SH::TLDS, TREG = SH::TREG;
+  constexpr bool XLDS = SH::XLDS, TLDS = SH::TLDS;
   constexpr int XR = SH::XR;
   static_assert(TPS % 2 == 0, "positions of a thread must share their parity");
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
-  T* xrow = reinterpret_cast<T*>(smem + SH::TILE_B);  // [0, L): sum, [L, 2L): difference
-  T* tab = xrow + 2 * L;                               // [0, L): layer sine, [L, 2L): eigenvalue
+  cx<T>* xrow = reinterpret_cast<cx<T>*>(smem + SH::TILE_B);  // (sum, difference) per position
+  cx<T>* tab = xrow + L;                                       // (layer sine, eigenvalue) per position
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
   const DstGen<T>& g = a.g;
@@ -557,29 +559,22 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
   const int tid0 = threadIdx.x;
   const int q0 = tid0 & (NSEQ - 1);
   const int mi0 = tid0 >> LGQ;
-  // every position m = 1 + mi + k TPS of this thread has the parity of 1 + mi
+  // the thread's positions m = 1 + mi + u TPS and N - m all have the parity of 1 + mi
   const bool modd = ((1 + mi0) & 1) != 0;
 
   // tile-invariant tables of the pass axis
-  T wpr[TREG ? PPT : 1], str[TREG ? PPT : 1];
   if constexpr (TLDS) {
     for (int j = tid0; j < L; j += THREADS) {
-      tab[j] = g.wp[j];
-      tab[L + j] = a.fs.s_this[j];
-    }
-  }
-  if constexpr (TREG) {
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int m = 1 + mi0 + k * TPS;
-      wpr[k] = m < N ? g.wp[m - 1] : T(0);
-      str[k] = m < N ? a.fs.s_this[m - 1] : T(1);
+      cx<T> t;
+      t.x = g.wp[j];
+      t.y = a.fs.s_this[j];
+      tab[j] = t;
     }
   }
 
-  // prefetched face data of a tile: y-face values at the thread's positions (both pencils of
-  // its pair) and the tile's x-face row
-  cx<T> yb[PPT];
+  // prefetched face data of a tile: the y-face values at the thread's mirrored positions
+  // (both pencils of its pair) and the tile's x-face row
+  cx<T> ylo[U], yhi[U];
   T xr[2][XR];
   const long long rowb = (long long)g.bpitch * (long long)sizeof(T);
   auto prefetch = [&](long long tile) {
@@ -591,12 +586,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       // ky even (odd mode) -> sums, ky odd -> differences
       const T* yrow = g.lb + o * g.bslab + ((ib & 1) ? g.bplane : 0) + ia0;
       const SBase src(yrow);
-      unsigned vo = (unsigned)((2 * q0 + (long long)mi0 * g.bpitch) * (long long)sizeof(T));
-      asm volatile("" : "+v"(vo));
+      unsigned vlo = (unsigned)((2 * q0 + (long long)mi0 * g.bpitch) * (long long)sizeof(T));
+      unsigned vhi = (unsigned)((2 * q0 + (long long)(TPS - 1 - mi0) * g.bpitch) * (long long)sizeof(T));
+      asm volatile("" : "+v"(vlo), "+v"(vhi));
 #pragma unroll
-      for (int k = 0; k < PPT; ++k) {
-        const int m = 1 + mi0 + k * TPS;
-        if (k < PPT - 1 || m < N) yb[k] = src.plus((long long)(k * TPS) * rowb).ld<cx<T>>(vo);
+      for (int u = 0; u < U; ++u) {
+        // position m - 1 = u TPS + mi; position N - m - 1 = (N - 1 - (u + 1) TPS) + (TPS - 1 - mi)
+        ylo[u] = src.plus((long long)(u * TPS) * rowb).ld<cx<T>>(vlo);
+        yhi[u] = src.plus((long long)(N - 1 - (u + 1) * TPS) * rowb).ld<cx<T>>(vhi);
       }
     }
     if constexpr (XLDS) {
@@ -657,49 +654,73 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * THREADS;
         if (j < L) {
-          xrow[j] = xr[0][r];
-          xrow[L + j] = xr[1][r];
+          cx<T> xv;
+          xv.x = xr[0][r];
+          xv.y = xr[1][r];
+          xrow[j] = xv;
         }
       }
     }
     __syncthreads();  // x-face row (and, first time round, the tables) visible
-    // ---- generate positions m = 1 + mi + k TPS of pair q
+    // ---- generate the scaled spectrum at the mirrored positions m, N - m of pair q and
+    // pre-weight them for the inverse transform: w_m = s_m (z_m + z_{N-m}) + (z_m - z_{N-m}) / 2
+    auto gen_at = [&](int m, const cx<T>& y, T& ga, T& gb) {
+      T wpl, st, xa, xb;
+      if constexpr (TLDS) {
+        const cx<T> t = tab[m - 1];
+        wpl = t.x;
+        st = t.y;
+      } else {
+        wpl = g.wp[m - 1];
+        st = a.fs.s_this[m - 1];
+      }
+      if constexpr (XLDS) {
+        const cx<T> xv = xrow[m - 1];
+        xa = xv.x;
+        xb = xv.y;
+      } else {
+        xa = la[(long long)(m - 1) * g.apitch];
+        xb = la[g.aplane + (long long)(m - 1) * g.apitch];
+      }
+      ga = pa * wpl + xa * wla;
+      gb = pb * wpl + xb * wlb;
+      if (has_b) {
+        ga += y.x * wbl;
+        gb += y.y * wbl;
+      }
+      ga = va ? ga * recip(Aa + Ba * st) : T(0);
+      gb = vb ? gb * recip(Ab + Bb * st) : T(0);
+    };
     cx<T>* sq = lds + q * LDQ;
-    cx<T>* lo = sq + pad(1 + mi);
+    {
+      cx<T>* lo = sq + pad(1 + mi);
+      cx<T>* hi = sq + pad(N - 1 - mi);
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-      const int m = 1 + mi + k * TPS;
-      if (k < PPT - 1 || m < N) {
-        T wpl, st;
-        if constexpr (TLDS) {
-          wpl = tab[m - 1];
-          st = tab[L + m - 1];
-        } else if constexpr (TREG) {
-          wpl = wpr[k];
-          st = str[k];
-        } else {
-          wpl = g.wp[m - 1];
-          st = a.fs.s_this[m - 1];
-        }
+      for (int u = 0; u < U; ++u) {
+        const int m = 1 + mi + u * TPS;
+        cx<T>* plo = LIN ? lo + poff(u * TPS) : sq + pad(m);
+        cx<T>* phi = LIN ? hi - poff(u * TPS) : sq + pad(N - m);
         T xa, xb;
-        if constexpr (XLDS) {
-          xa = xrow[m - 1];
-          xb = xrow[L + m - 1];
+        gen_at(m, ylo[u], xa, xb);
+        if (u == U - 1 && m == HN) {  // the middle position pairs with itself: 2 z
+          cx<T> v;
+          v.x = T(2) * xa;
+          v.y = T(2) * xb;
+          *plo = v;
         } else {
-          xa = la[(long long)(m - 1) * g.apitch];
-          xb = la[g.aplane + (long long)(m - 1) * g.apitch];
+          T ya, yb;
+          gen_at(N - m, yhi[u], ya, yb);
+          const T w = a.sn[m];
+          const T sx = w * (xa + ya), sy = w * (xb + yb);
+          const T dx = T(0.5) * (xa - ya), dy = T(0.5) * (xb - yb);
+          cx<T> o1, o2;
+          o1.x = sx + dx;
+          o1.y = sy + dy;
+          o2.x = sx - dx;
+          o2.y = sy - dy;
+          *plo = o1;
+          *phi = o2;
         }
-        T ga = pa * wpl + xa * wla;
-        T gb = pb * wpl + xb * wlb;
-        if (has_b) {
-          ga += yb[k].x * wbl;
-          gb += yb[k].y * wbl;
-        }
-        cx<T> v;
-        v.x = va ? ga * recip(Aa + Ba * st) : T(0);
-        v.y = vb ? gb * recip(Ab + Bb * st) : T(0);
-        if (LIN) lo[poff(k * TPS)] = v;
-        else sq[pad(m)] = v;
       }
     }
     if (tid < NSEQ) {
@@ -720,7 +741,6 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     cx<T> A, B;
     A.x = A.y = T(1);
     B.x = B.y = T(0);
-    pre_lds<T, N, PL>(seq, ts, a.sn);
     fft<T, N, PL>(seq, ts, a.tw);
     post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
     __syncthreads();  // the store reads other pairs' sequences
@@ -730,6 +750,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       const SBase dst(a.out + o * (long long)L * inner + c0);
       unsigned vs = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
       asm volatile("" : "+v"(vs));
+      const cx<T>* lo = sq + pad(1 + mi);
       if (a.ntst) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
