@@ -367,27 +367,35 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
     AHOC_HIP_TRY(hipMemsetAsync(P.Fy, 0, sizeof(T) * 2 * g.nb * g.px, st));
   }
   P.spectral = faces_available(g);
-  if (P.spectral && g.dim == 3 && !h->tri) {
-    TRY(alloc_t(h, &P.Ux, 2LL * g.ni[1] * g.ni[2]));
-    TRY(alloc_t(h, &P.Uy, 2LL * g.ni[0] * g.ni[2]));
-    TRY(alloc_t(h, &P.Uz, 2LL * g.px * g.ni[1]));
-    // (s, layer sine, face weight low, high) per z position, from the tables above
-    const int nz = g.ni[2];
-    std::vector<T> hs(nz), hl(2 * nz), hw(2 * nz), pt(4 * (size_t)nz);
-    AHOC_HIP_TRY(hipMemcpyAsync(hs.data(), P.s[2], sizeof(T) * nz, hipMemcpyDeviceToHost, st));
-    AHOC_HIP_TRY(hipMemcpyAsync(hl.data(), P.wl[2], sizeof(T) * 2 * nz, hipMemcpyDeviceToHost, st));
-    AHOC_HIP_TRY(hipMemcpyAsync(hw.data(), P.wf[2], sizeof(T) * 2 * nz, hipMemcpyDeviceToHost, st));
+  if (P.spectral && !h->tri) {
+    const int t = g.dim - 1;  // the slowest axis
+    if (g.dim == 3) {
+      TRY(alloc_t(h, &P.Ux, 2LL * g.ni[1] * g.ni[2]));
+      TRY(alloc_t(h, &P.Uy, 2LL * g.ni[0] * g.ni[2]));
+      TRY(alloc_t(h, &P.Uz, 2LL * g.px * g.ni[1]));
+    } else {  // per instance [2][n_y'] and [2][px]
+      TRY(alloc_t(h, &P.Ux, 2LL * g.nb * g.ni[1]));
+      TRY(alloc_t(h, &P.Uy, 2LL * g.nb * g.px));
+    }
+    // (s, layer sine, face weight low, high) per position of the slowest axis, from the
+    // tables above
+    const int nt = g.ni[t];
+    std::vector<T> hs(nt), hl(2 * nt), hw(2 * nt), pt(4 * (size_t)nt);
+    AHOC_HIP_TRY(hipMemcpyAsync(hs.data(), P.s[t], sizeof(T) * nt, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(hl.data(), P.wl[t], sizeof(T) * 2 * nt, hipMemcpyDeviceToHost, st));
+    AHOC_HIP_TRY(hipMemcpyAsync(hw.data(), P.wf[t], sizeof(T) * 2 * nt, hipMemcpyDeviceToHost, st));
     AHOC_HIP_TRY(hipStreamSynchronize(st));
-    for (int k = 0; k < nz; ++k) {
+    for (int k = 0; k < nt; ++k) {
       pt[4 * k] = hs[k];
       pt[4 * k + 1] = hl[k];
       pt[4 * k + 2] = hw[k];
-      pt[4 * k + 3] = hw[nz + k];
+      pt[4 * k + 3] = hw[nt + k];
     }
-    TRY(alloc_t(h, &P.ptab, 4LL * nz));
-    AHOC_HIP_TRY(hipMemcpyAsync(P.ptab, pt.data(), sizeof(T) * 4 * nz, hipMemcpyHostToDevice, st));
+    TRY(alloc_t(h, &P.ptab, 4LL * nt));
+    AHOC_HIP_TRY(hipMemcpyAsync(P.ptab, pt.data(), sizeof(T) * 4 * nt, hipMemcpyHostToDevice, st));
     AHOC_HIP_TRY(hipStreamSynchronize(st));
-    P.mspec = dst_pipe_mpass_ok<T>(g.n[2], (long long)g.px * g.ni[1], g.px, mspec_gen<T>(g, P));
+    const long long inner = g.dim == 3 ? (long long)g.px * g.ni[1] : g.px;
+    P.mspec = dst_pipe_mpass_ok<T>(g.n[t], inner, g.px, mspec_gen<T>(g, P));
   }
   TRY(alloc_int(h, &P.bufA, st));
   TRY(alloc_int(h, &P.bufB, st));
@@ -685,21 +693,30 @@ template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hi
 // Face-array arguments of the U-solve pass with spectral M (layouts as the V-solve's lift)
 template <typename T> DstGen<T> mspec_gen(const Geom& g, Prec<T>& P) {
   DstGen<T> gen;
-  gen.lp = P.Uz;
-  gen.pplane = (long long)g.px * g.ni[1];
-  gen.wp = P.wl[2];
-  gen.la = P.Ux;
-  gen.aplane = (long long)g.ni[1] * g.ni[2];
-  gen.apitch = 1;
-  gen.arow = g.ni[2];
   gen.wa = P.wl[0];
   gen.nwa = g.ni[0];
-  gen.lb = P.Uy;  // [side][i][k], k fastest
-  gen.bplane = (long long)g.ni[0] * g.ni[2];
-  gen.bpitch = g.ni[2];
-  gen.wb = P.wl[1];
-  gen.nwb = g.ni[1];
+  gen.la = P.Ux;
+  gen.apitch = 1;
   gen.ptab = P.ptab;
+  if (g.dim == 3) {
+    gen.lp = P.Uz;
+    gen.pplane = (long long)g.px * g.ni[1];
+    gen.wp = P.wl[2];
+    gen.aplane = (long long)g.ni[1] * g.ni[2];
+    gen.arow = g.ni[2];
+    gen.lb = P.Uy;  // [side][i][k], k fastest
+    gen.bplane = (long long)g.ni[0] * g.ni[2];
+    gen.bpitch = g.ni[2];
+    gen.wb = P.wl[1];
+    gen.nwb = g.ni[1];
+  } else {  // instance o of a batch: y faces [o][2][px], x faces [o][2][n_y']
+    gen.lp = P.Uy;
+    gen.pplane = g.px;
+    gen.pslab = 2LL * g.px;
+    gen.wp = P.wl[1];
+    gen.aplane = g.ni[1];
+    gen.aslab = 2LL * g.ni[1];
+  }
   return gen;
 }
 
@@ -716,93 +733,63 @@ template <typename T> DstGen<T> mspec_gen(const Geom& g, Prec<T>& P) {
 // The volume is read and written in place in bufA.
 template <typename T> int matvec_mspec(ahoc_handle* h, Prec<T>& P, const T* Q, double* y, hipStream_t st) {
   const Geom& g = h->g;
+  const bool d3 = g.dim == 3;
   TRY(vsolve_spec<T>(h, P, Q, st, true));
   hipEvent_t el = tbegin(h, st);
   TRY(face_lift_m<T>(g, h->w, Q, P.ia, P.Ux, P.Uy, P.Uz, st));
-  // 2-D spectra: x and z faces as the lift's; y faces [2][n_x'][n_z'] (z rows, x strided)
-  TRY(dst_pass<T>(P.tb[0], P.Uz, P.Uz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
-  TRY(dst_pass<T>(P.tb[1], P.Uz, P.Uz, 2, g.px, g.px, nullptr, 0, st));
-  TRY(dst_pass<T>(P.tb[2], P.Ux, P.Ux, 2LL * g.ni[1], 1, g.ni[2], nullptr, 0, st));
-  TRY(dst_pass<T>(P.tb[1], P.Ux, P.Ux, 2, g.ni[2], g.ni[2], nullptr, 0, st));
-  TRY(dst_pass<T>(P.tb[2], P.Uy, P.Uy, 2LL * g.ni[0], 1, g.ni[2], nullptr, 0, st));
-  TRY(dst_pass<T>(P.tb[0], P.Uy, P.Uy, 2, g.ni[2], g.ni[2], nullptr, 0, st));
+  if (d3) {
+    // 2-D spectra: x and z faces as the lift's; y faces [2][n_x'][n_z'] (z rows, x strided)
+    TRY(dst_pass<T>(P.tb[0], P.Uz, P.Uz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Uz, P.Uz, 2, g.px, g.px, nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], P.Ux, P.Ux, 2LL * g.ni[1], 1, g.ni[2], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[1], P.Ux, P.Ux, 2, g.ni[2], g.ni[2], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[2], P.Uy, P.Uy, 2LL * g.ni[0], 1, g.ni[2], nullptr, 0, st));
+    TRY(dst_pass<T>(P.tb[0], P.Uy, P.Uy, 2, g.ni[2], g.ni[2], nullptr, 0, st));
+  } else {
+    TRY(face_dst2<T>(h, P, P.Ux, P.Uy, nullptr, st));
+  }
   tend(h, AHOC_K_LIFT, el, (double)TQ(g) * 3.0 * sizeof(T), st);
   T* buf = P.bufA;
-  const double vol = (double)g.nint * sizeof(T);
+  const double vol = (double)g.nint * g.nb * sizeof(T);
+  const long long rows = d3 ? (long long)g.ni[1] * g.ni[2] : (long long)g.nb * g.ni[1];
   hipEvent_t ex = tbegin(h, st);
-  TRY(dst_rows_mul_pass<T>(g.n[0], P.tb[0].tw, P.tb[0].sn, buf, buf, (long long)g.ni[1] * g.ni[2], g.px, P.ia,
-                           g.ni[1], 1, g.nn[0], g.nn[1], st));
-  tend(h, AHOC_K_DST_XMUL, ex, 2.0 * vol + (double)g.nnodal * sizeof(T), st);
-  hipEvent_t ey = tbegin(h, st);
-  TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.px, g.px, nullptr, P.tile[1], st));
-  tend(h, AHOC_K_DST_STRIDED, ey, 2.0 * vol, st);
+  TRY(dst_rows_mul_pass<T>(g.n[0], P.tb[0].tw, P.tb[0].sn, buf, buf, rows, g.px, P.ia, g.ni[1], d3 ? 1 : 0,
+                           g.nn[0], g.nn[1], st));
+  tend(h, AHOC_K_DST_XMUL, ex, 2.0 * vol + (double)g.nnodal * g.nb * sizeof(T), st);
+  if (d3) {
+    hipEvent_t ey = tbegin(h, st);
+    TRY(dst_pass<T>(P.tb[1], buf, buf, g.ni[2], g.px, g.px, nullptr, P.tile[1], st));
+    tend(h, AHOC_K_DST_STRIDED, ey, 2.0 * vol, st);
+  }
   DstFaces<T> fp;
   fp.mode = 1;
-  fp.out = P.Fz;
-  fp.w = P.wf[2];
-  fp.plane = (long long)g.px * g.ni[1];
-  hipEvent_t ez = tbegin(h, st);
-  TRY(dst_pipe_mpass<T>(g.n[2], P.tb[2].tw, P.tb[2].sn, buf, 1, (long long)g.px * g.ni[1], P.scM, fp,
-                        mspec_gen<T>(g, P), st));
-  tend(h, AHOC_K_DST_FUSED, ez, 2.0 * vol, st);
-  hipEvent_t er = tbegin(h, st);
-  TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
-                     (long long)g.ni[2] * g.ni[1], 1, g.ni[2], st));
-  tend(h, AHOC_K_FACE_REDUCE, er, vol, st);
-  hipEvent_t ef = tbegin(h, st);
-  TRY(face_dst2<T>(h, P, st));
-  TRY(gather_faces<T>(g, P.Fx, P.Fy, P.Fz, Q, P.af, nullptr, y, st));
-  tend(h, AHOC_K_GATHER, ef, (double)TQ(g) * (5 * sizeof(T) + sizeof(double)), st);
-  return ST_OK;
-}
-
-// U-solve for the boundary residual only: U = L^{-1}(M(V/alpha) + src) is never formed.
-// The forward transforms run as usual; the slowest-axis pass scales the spectrum, forms
-// the face sums along its own axis and stores the scaled spectrum; one streaming
-// reduction forms the sums along the other two axes, and 2-D inverse transforms of the
-// face arrays give the combination 6 U_1 - 3/2 U_2 + 2/9 U_3 next to each face.
-template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
-  const Geom& g = h->g;
-  hipEvent_t e = tbegin(h, st);
-  TRY(rhs_u<T>(g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
-  tend(h, AHOC_K_RHS_U, e, g.nb * ((double)sizeof(T) * (2.0 * g.nint + g.nnodal) + (src ? g.nint * sizeof(T) : 0)), st);
-  T* buf = P.bufB;
-  const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);
-  auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner, const DstScale<T>* f,
-                 int tile, const DstFaces<T>* fc) -> int {
-    hipEvent_t ev = tbegin(h, st);
-    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, f, tile, st, fc);
-    tend(h, kind, ev, pass_bytes, st);
-    return rc;
-  };
-  DstFaces<T> fp;
-  fp.mode = 1;
-  if (g.dim == 3) {
+  if (d3) {
     fp.out = P.Fz;
     fp.w = P.wf[2];
     fp.plane = (long long)g.px * g.ni[1];
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, nullptr, P.tile[0], nullptr));
-    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, nullptr, P.tile[1], nullptr));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fp));
-    hipEvent_t er = tbegin(h, st);
-    TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
-                       (long long)g.ni[2] * g.ni[1], 1, g.ni[2], st));
-    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
   } else {
     fp.out = P.Fy;
     fp.w = P.wf[1];
     fp.plane = g.px;
     fp.slab = 2LL * g.px;  // instance o of a batch
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, nullptr, P.tile[0], nullptr));
-    TRY(run(AHOC_K_DST_FUSED, P.tb[1], g.nb, g.px, &P.scU, P.tile[1], &fp));
-    hipEvent_t er = tbegin(h, st);
+  }
+  const int t = g.dim - 1;
+  hipEvent_t ez = tbegin(h, st);
+  TRY(dst_pipe_mpass<T>(g.n[t], P.tb[t].tw, P.tb[t].sn, buf, d3 ? 1 : g.nb, d3 ? (long long)g.px * g.ni[1] : g.px,
+                        P.scM, fp, mspec_gen<T>(g, P), st));
+  tend(h, AHOC_K_DST_FUSED, ez, 2.0 * vol, st);
+  hipEvent_t er = tbegin(h, st);
+  if (d3)
+    TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
+                       (long long)g.ni[2] * g.ni[1], 1, g.ni[2], st));
+  else
     TRY(face_reduce<T>(buf, g.nb, g.ni[1], g.ni[0], g.px, P.wf[0], nullptr, P.Fx, nullptr, g.ni[1],
                        2LL * g.ni[1], 1, st));
-    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * g.nb * sizeof(T), st);
-  }
+  tend(h, AHOC_K_FACE_REDUCE, er, vol, st);
   hipEvent_t ef = tbegin(h, st);
   TRY(face_dst2<T>(h, P, st));
-  tend(h, AHOC_K_GATHER, ef, (double)TQ(g) * 2.0 * sizeof(T), st);
+  TRY(gather_faces<T>(g, P.Fx, P.Fy, P.Fz, Q, P.af, nullptr, y, st));
+  tend(h, AHOC_K_GATHER, ef, (double)TQ(g) * (5 * sizeof(T) + sizeof(double)), st);
   return ST_OK;
 }
 
@@ -934,9 +921,11 @@ template <typename T> int matvec(ahoc_handle* h, Prec<T>& P, const double* q, do
   }
   if (P.mspec) {
     TRY(matvec_mspec<T>(h, P, qT, y, st));
-    // algorithmic bytes: generated pass (write 1), y inverse (2), x pass (read, write: 2,
-    // and the nodal 1/alpha), y forward (2), z forward (2), face reduction (read 1)
-    tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (10.0 * h->g.nint + h->g.nnodal), st);
+    // algorithmic bytes: generated pass (write 1), 3-D: y inverse (2), x pass (read, write:
+    // 2, and the nodal 1/alpha), 3-D: y forward (2), slowest-axis forward (2), face reduction
+    // (read 1)
+    const double nv = h->g.dim == 3 ? 10.0 : 6.0;
+    tend(h, AHOC_K_MATVEC, e, (double)sizeof(T) * (nv * h->g.nint + h->g.nnodal) * h->g.nb, st);
     return ST_OK;
   }
   if (P.spectral) {
