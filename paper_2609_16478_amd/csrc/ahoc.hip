@@ -793,6 +793,56 @@ template <typename T> int matvec_mspec(ahoc_handle* h, Prec<T>& P, const T* Q, d
   return ST_OK;
 }
 
+// U-solve for the boundary residual only: U = L^{-1}(M(V/alpha) + src) is never formed.
+// The forward transforms run as usual; the slowest-axis pass scales the spectrum, forms
+// the face sums along its own axis and stores the scaled spectrum; one streaming
+// reduction forms the sums along the other two axes, and 2-D inverse transforms of the
+// face arrays give the combination 6 U_1 - 3/2 U_2 + 2/9 U_3 next to each face.
+template <typename T> int usolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, const T* src, hipStream_t st) {
+  const Geom& g = h->g;
+  hipEvent_t e = tbegin(h, st);
+  TRY(rhs_u<T>(g, h->w, P.bufA, Q, P.ia, src, P.bufB, st));
+  tend(h, AHOC_K_RHS_U, e, g.nb * ((double)sizeof(T) * (2.0 * g.nint + g.nnodal) + (src ? g.nint * sizeof(T) : 0)), st);
+  T* buf = P.bufB;
+  const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);
+  auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner, const DstScale<T>* f,
+                 int tile, const DstFaces<T>* fc) -> int {
+    hipEvent_t ev = tbegin(h, st);
+    const int rc = dst_pass<T>(tb, buf, buf, outer, inner, g.px, f, tile, st, fc);
+    tend(h, kind, ev, pass_bytes, st);
+    return rc;
+  };
+  DstFaces<T> fp;
+  fp.mode = 1;
+  if (g.dim == 3) {
+    fp.out = P.Fz;
+    fp.w = P.wf[2];
+    fp.plane = (long long)g.px * g.ni[1];
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, nullptr, P.tile[0], nullptr));
+    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, nullptr, P.tile[1], nullptr));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[2], 1, (long long)g.px * g.ni[1], &P.scU, P.tile[2], &fp));
+    hipEvent_t er = tbegin(h, st);
+    TRY(face_reduce<T>(buf, g.ni[2], g.ni[1], g.ni[0], g.px, P.wf[0], P.wf[1], P.Fx, P.Fy,
+                       (long long)g.ni[2] * g.ni[1], 1, g.ni[2], st));
+    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * sizeof(T), st);
+  } else {
+    fp.out = P.Fy;
+    fp.w = P.wf[1];
+    fp.plane = g.px;
+    fp.slab = 2LL * g.px;  // instance o of a batch
+    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, nullptr, P.tile[0], nullptr));
+    TRY(run(AHOC_K_DST_FUSED, P.tb[1], g.nb, g.px, &P.scU, P.tile[1], &fp));
+    hipEvent_t er = tbegin(h, st);
+    TRY(face_reduce<T>(buf, g.nb, g.ni[1], g.ni[0], g.px, P.wf[0], nullptr, P.Fx, nullptr, g.ni[1],
+                       2LL * g.ni[1], 1, st));
+    tend(h, AHOC_K_FACE_REDUCE, er, (double)g.nint * g.nb * sizeof(T), st);
+  }
+  hipEvent_t ef = tbegin(h, st);
+  TRY(face_dst2<T>(h, P, st));
+  tend(h, AHOC_K_GATHER, ef, (double)TQ(g) * 2.0 * sizeof(T), st);
+  return ST_OK;
+}
+
 // Boundary-symbol preconditioner: FP64 symbol tables, the inverse block coefficients
 // and FP64 DST tables for the face transforms (shared with the FP64 operator if any).
 int precond_init(ahoc_handle* h, hipStream_t st) {
