@@ -461,14 +461,19 @@ template <typename T> void prec_free(Prec<T>& P) {
 // Dirichlet solve on an interior array: buf <- scale * S (S in / lambda), in place unless
 // `in` is given (then the first pass reads it and `in` is left unchanged).
 template <typename T>
-int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st, const T* in = nullptr) {
+int poisson(ahoc_handle* h, Prec<T>& P, T* buf, const DstScale<T>& sc, hipStream_t st, const T* in = nullptr,
+            const RowLift<T>* lf = nullptr) {
   const Geom& g = h->g;
   const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);  // one read + one write of the array
   const T* src = in ? in : buf;
+  bool first = true;
   auto run = [&](int kind, const DstTables<T>& tb, long long outer, long long inner,
                  const DstScale<T>* f, int tile) -> int {
     hipEvent_t e = tbegin(h, st);
-    const int rc = dst_pass<T>(tb, src, buf, outer, inner, g.px, f, tile, st);
+    // with lf, the first (row) pass adds the lift's face layers to its input while loading
+    const int rc = (first && lf) ? dst_rows_lift_pass<T>(tb.N, tb.tw, tb.sn, src, buf, outer, g.px, *lf, st)
+                                 : dst_pass<T>(tb, src, buf, outer, inner, g.px, f, tile, st);
+    first = false;
     src = buf;
     tend(h, kind, e, pass_bytes, st);
     return rc;
@@ -599,9 +604,29 @@ template <typename T> int vsolve(ahoc_handle* h, Prec<T>& P, const T* Q, const T
     if constexpr (std::is_same<T, double>::value) return vsolve_var(h, P, Q, src, st);
     else return ST_UNSUPPORTED;
   }
+  const Geom& g = h->g;
   hipEvent_t e = tbegin(h, st);
-  TRY(lift<T>(h->g, h->wv, Q, src, P.bufA, st));
-  tend(h, AHOC_K_LIFT, e, (double)h->g.nint * h->g.nb * sizeof(T) * (src ? 2 : 1), st);
+  const long long rows = g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : (long long)g.nb * g.ni[1];
+  if (src && P.spectral && dst_get_variant() != 4 && dst_rows_lift_supported<T>(g.n[0], rows, g.px)) {
+    // the lift as face layers (the spectral path's kernel), added to the source by the
+    // Poisson solve's first row pass while it loads: no lift pass over the volume
+    TRY(face_lift<T>(g, h->wv, Q, P.Fx, P.Fy, P.Fz, st));
+    tend(h, AHOC_K_LIFT, e, (double)TQ(g) * 2.0 * sizeof(T), st);
+    RowLift<T> lf;
+    lf.dim = g.dim;
+    lf.ni1 = g.ni[1];
+    lf.ni2 = g.dim == 3 ? g.ni[2] : 1;
+    lf.px = g.px;
+    lf.lx = P.Fx;
+    lf.ly = P.Fy;
+    lf.lz = g.dim == 3 ? P.Fz : nullptr;
+    lf.xplane = g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1];
+    lf.yplane = g.dim == 3 ? (long long)g.ni[2] * g.px : g.px;
+    lf.zplane = g.dim == 3 ? (long long)g.ni[1] * g.px : 0;
+    return poisson<T>(h, P, P.bufA, P.scV, st, src, &lf);
+  }
+  TRY(lift<T>(g, h->wv, Q, src, P.bufA, st));
+  tend(h, AHOC_K_LIFT, e, (double)g.nint * g.nb * sizeof(T) * (src ? 2 : 1), st);
   return poisson<T>(h, P, P.bufA, P.scV, st);
 }
 

@@ -212,6 +212,24 @@ template <typename T>
 int dst_rows_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
                   hipStream_t st);
 
+// Face layers of the V-solve's lift added to the first (row) pass of a Poisson solve with a
+// source (dst_rows.hip): layouts of face_lift (3-D: lx [2][n_y'][n_z'], ly [2][n_z'][px],
+// lz [2][n_y'][px]; 2-D per instance b: lx [b][2][n_y'], ly [b][2][px]).
+template <typename T> struct RowLift {
+  const T* lx = nullptr;
+  const T* ly = nullptr;
+  const T* lz = nullptr;
+  long long xplane = 0, yplane = 0, zplane = 0;  // offset of the high face's array (3-D)
+  int dim = 3, ni1 = 0, ni2 = 1, px = 0;
+};
+// Row pass whose input is in + the lift's face layers (no lift pass); in may equal out.
+// dst_rows_lift_supported: whether the pass exists for this length and shape (checked
+// before anything is launched).
+template <typename T> bool dst_rows_lift_supported(int N, long long nrows, long long pitch);
+template <typename T>
+int dst_rows_lift_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
+                       const RowLift<T>& lf, hipStream_t st);
+
 // Two transforms of each row with a pointwise product between them (dst_rows.hip):
 // out_row = S (c_row .* (S in_row)), c nodal with the row of interior row
 // r = (j - 1) + p ni1 at c + ((p + kofs) nn1 + j) nn0 (position i at offset i); in may

@@ -36,12 +36,17 @@ template <int N> constexpr int rows_nseq() {
   return TPS >= 64 ? 1 : 64 / TPS;
 }
 
-template <typename T, int N, bool NT>
+// LIFT: the input rows are a source plus the face layers of the V-solve's lift, added while
+// loading (the lift pass is not run): row r = (j - 1) + (k - 1) n_y' (3-D) or
+// (j - 1) + b n_y' (2-D, instance b) gets Lx[side] at its first and last position, and the
+// whole row of Ly[side] (Lz[side]) when it lies next to a y (z) face.  Layouts of face_lift.
+template <typename T, int N, bool NT, bool LIFT = false>
 __global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows(const T* __restrict__ in,
                                                                                 T* __restrict__ out,
                                                                                 const cx<T>* __restrict__ tw,
                                                                                 const T* __restrict__ sn,
-                                                                                long long nrows, long long pitch) {
+                                                                                long long nrows, long long pitch,
+                                                                                RowLift<T> lf = RowLift<T>{}) {
   extern __shared__ __align__(16) unsigned char smem[];
   using PL = RPlan<N>;
   constexpr int PPT = PL::PPT;
@@ -80,6 +85,43 @@ __global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows
       const bool mid = u == U - 1 && m == HN;
       ya[u] = (oka && !mid) ? ldr<T, NT>(src, oa + e2) : T(0);
       yb[u] = (okb && !mid) ? ldr<T, NT>(src, ob + e2) : T(0);
+    }
+    if constexpr (LIFT) {
+      // the lift's face layers of both rows: x faces at positions 1 and N - 1 (thread 0,
+      // u = 0: m = 1 and N - m = N - 1), y and z faces on whole rows next to those faces
+      auto add_row = [&](long long r, bool ok, T* x, T* y) {
+        if (!ok) return;
+        const int j = (int)(r % lf.ni1) + 1;
+        const int k = lf.dim == 3 ? (int)(r / lf.ni1) + 1 : 0;
+        const long long b = lf.dim == 3 ? 0 : r / lf.ni1;
+        if (t == 0) {
+          const long long xo = lf.dim == 3 ? (long long)(j - 1) * lf.ni2 + (k - 1) : b * 2 * lf.ni1 + (j - 1);
+          x[0] += lf.lx[xo];
+          y[0] += lf.lx[xo + lf.xplane];
+        }
+        const T* rows[2] = {nullptr, nullptr};
+        if (lf.dim == 3) {
+          if (j == 1) rows[0] = lf.ly + (long long)(k - 1) * lf.px;
+          else if (j == lf.ni1) rows[0] = lf.ly + lf.yplane + (long long)(k - 1) * lf.px;
+          if (k == 1) rows[1] = lf.lz + (long long)(j - 1) * lf.px;
+          else if (k == lf.ni2) rows[1] = lf.lz + lf.zplane + (long long)(j - 1) * lf.px;
+        } else {
+          if (j == 1) rows[0] = lf.ly + b * 2 * lf.px;
+          else if (j == lf.ni1) rows[0] = lf.ly + b * 2 * lf.px + lf.px;
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+          if (!rows[f]) continue;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const int m = 1 + t + u * TPS;
+            x[u] += rows[f][m - 1];
+            if (!(u == U - 1 && m == HN)) y[u] += rows[f][N - m - 1];
+          }
+        }
+      };
+      add_row(ra, oka, xa, ya);
+      add_row(ra + 1, okb, xb, yb);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -301,6 +343,27 @@ template <typename T, int N> int rows_mul_launch(const T* in, T* out, const cx<T
   return ST_OK;
 }
 
+template <typename T, int N> int rows_lift_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
+                                                  long long pitch, const RowLift<T>& lf, hipStream_t st) {
+  constexpr int TPS = N / RPlan<N>::PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int THREADS = NSEQ * TPS;
+  constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
+  if (THREADS % 64 != 0 || THREADS > 1024 || LDS > 64 * 1024) return ST_UNSUPPORTED;
+  if ((double)(2 * NSEQ) * (double)pitch * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+  const long long blocks = (nrows + 2 * NSEQ - 1) / (2 * NSEQ);
+  if (blocks <= 0) return ST_OK;
+  if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+  if (sizeof(T) == 4 && (double)nrows * (double)pitch * sizeof(T) >= NT_STORE_MIN_BYTES)
+    hipLaunchKernelGGL((k_dst_rows<T, N, true, true>), dim3((unsigned)blocks), dim3(THREADS), LDS, st, in, out, tw,
+                       sn, nrows, pitch, lf);
+  else
+    hipLaunchKernelGGL((k_dst_rows<T, N, false, true>), dim3((unsigned)blocks), dim3(THREADS), LDS, st, in, out,
+                       tw, sn, nrows, pitch, lf);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
 template <typename T, int N> int rows_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
                                              long long pitch, hipStream_t st) {
   constexpr int TPS = N / RPlan<N>::PPT;
@@ -347,6 +410,66 @@ int dst_rows_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
     default: return ST_UNSUPPORTED;
   }
 }
+
+namespace fast {
+namespace {
+template <typename T, int N> bool rows_lift_ok(long long nrows, long long pitch) {
+  constexpr int TPS = N / RPlan<N>::PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int THREADS = NSEQ * TPS;
+  constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
+  return THREADS % 64 == 0 && THREADS <= 1024 && LDS <= 64 * 1024 &&
+         (double)(2 * NSEQ) * (double)pitch * (double)sizeof(T) < 4294967295.0 &&
+         (nrows + 2 * NSEQ - 1) / (2 * NSEQ) <= 0x7fffffffLL;
+}
+}  // namespace
+}  // namespace fast
+
+template <typename T> bool dst_rows_lift_supported(int N, long long nrows, long long pitch) {
+  if (pitch < N - 1) return false;
+  switch (N) {
+    case 32: return fast::rows_lift_ok<T, 32>(nrows, pitch);
+    case 64: return fast::rows_lift_ok<T, 64>(nrows, pitch);
+    case 96: return fast::rows_lift_ok<T, 96>(nrows, pitch);
+    case 128: return fast::rows_lift_ok<T, 128>(nrows, pitch);
+    case 192: return fast::rows_lift_ok<T, 192>(nrows, pitch);
+    case 256: return fast::rows_lift_ok<T, 256>(nrows, pitch);
+    case 384: return fast::rows_lift_ok<T, 384>(nrows, pitch);
+    case 512: return fast::rows_lift_ok<T, 512>(nrows, pitch);
+    case 768: return fast::rows_lift_ok<T, 768>(nrows, pitch);
+    case 1024: return fast::rows_lift_ok<T, 1024>(nrows, pitch);
+    case 2048: return fast::rows_lift_ok<T, 2048>(nrows, pitch);
+    case 4096: return fast::rows_lift_ok<T, 4096>(nrows, pitch);
+    default: return false;
+  }
+}
+template bool dst_rows_lift_supported<float>(int, long long, long long);
+template bool dst_rows_lift_supported<double>(int, long long, long long);
+
+template <typename T>
+int dst_rows_lift_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
+                       const RowLift<T>& lf, hipStream_t st) {
+  if (pitch < N - 1 || lf.ni1 <= 0 || (lf.dim != 2 && lf.dim != 3)) return ST_INVALID;
+  switch (N) {
+    case 32: return fast::rows_lift_launch<T, 32>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 64: return fast::rows_lift_launch<T, 64>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 96: return fast::rows_lift_launch<T, 96>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 128: return fast::rows_lift_launch<T, 128>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 192: return fast::rows_lift_launch<T, 192>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 256: return fast::rows_lift_launch<T, 256>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 384: return fast::rows_lift_launch<T, 384>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 512: return fast::rows_lift_launch<T, 512>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 768: return fast::rows_lift_launch<T, 768>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 1024: return fast::rows_lift_launch<T, 1024>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 2048: return fast::rows_lift_launch<T, 2048>(in, out, tw, sn, nrows, pitch, lf, st);
+    case 4096: return fast::rows_lift_launch<T, 4096>(in, out, tw, sn, nrows, pitch, lf, st);
+    default: return ST_UNSUPPORTED;
+  }
+}
+template int dst_rows_lift_pass<float>(int, const cx<float>*, const float*, const float*, float*, long long, long long,
+                                       const RowLift<float>&, hipStream_t);
+template int dst_rows_lift_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
+                                        long long, const RowLift<double>&, hipStream_t);
 
 template <typename T>
 int dst_rows_mul_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
