@@ -53,33 +53,37 @@ def _src_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(n=128, tol=1e-10):
+def cpu_baseline(n=128, tol=1e-10, dim=3):
     """The oracle's Algorithm-1 tier (scipy DST-I, numpy stencils, FP64 GMRES(30), no
-    preconditioner) on the benchmark's 3-D problem at n^3 -- the same configuration the line
-    also reports GPU times for (gpu_same_config) -- timed on this host's cores."""
+    preconditioner) on the benchmark's 3-D problem at n^3 (dim = 2: the 2-D variable-
+    coefficient problem at n^2) -- a configuration the line also reports GPU times for
+    (gpu_same_config) -- timed on this host's cores."""
     import numpy as np
     import workloads as W
     from oracle import fast
     cores = len(os.sched_getaffinity(0))
-    p = W.config3(n)
+    p = W.config3(n) if dim == 3 else W.config2(n)
     t0 = time.perf_counter()
     ft = fast.FastTier(p, workers=cores)
     U, V, Q, info = ft.solve(tol=tol)
     dt = time.perf_counter() - t0
     err = float(np.abs(U - p.u_exact).max() / np.abs(p.u_exact).max())
-    return {"value": n ** 3 / dt, "unit": "DOF/s", "cores": cores, "kind": "oracle",
+    what = "the benchmark's 3-D problem" if dim == 3 else "the 2-D variable-coefficient problem"
+    return {"value": n ** dim / dt, "unit": "DOF/s", "cores": cores, "kind": "oracle",
             "sample": f"one whole FP64 fast-tier solve (scipy DST-I with workers={cores}, numpy stencils, "
-                      f"own GMRES(30) without preconditioner, Schur tol {tol:g}) of the benchmark's 3-D problem "
+                      f"own GMRES(30) without preconditioner, Schur tol {tol:g}) of {what} "
                       f"at n={n} ({info['iters']} GMRES iterations, {dt:.1f} s, rel err vs exact {err:.2e}); "
-                      f"DOF = n^3; the GPU's times for this configuration are in config.gpu_same_config",
+                      f"DOF = n^{dim}; the GPU's times for this configuration are in config.gpu_same_config"
+                      + ("" if dim == 3 else "_2d"),
             "time_s": dt, "n": n}
 
 
-def gpu_same_config(ah, W, torch, dev, n, tol, steps=3):
-    """GPU solve times of the CPU baseline's configuration (the 3-D problem at n^3, the same
-    Schur tolerance), both forms, after a warm-up solve; setup excluded."""
-    prob = W.config3(n, xp="torch", device=dev)
-    out = {"n": n, "tol": tol}
+def gpu_same_config(ah, W, torch, dev, n, tol, steps=3, dim=3):
+    """GPU solve times of a CPU baseline's configuration (the 3-D problem at n^3, or with
+    dim = 2 the 2-D one at n^2, the same Schur tolerance), both forms, after a warm-up solve;
+    setup excluded."""
+    prob = W.config3(n, xp="torch", device=dev) if dim == 3 else W.config2(n, xp="torch", device=dev)
+    out = {"n": n, "dim": dim, "tol": tol}
     for name, prec in (("mixed", ah.MIXED), ("fp64", ah.FP64)):
         with ah.Solver(prob, precision=prec, tol=tol) as s:
             s.solve()
@@ -89,7 +93,7 @@ def gpu_same_config(ah, W, torch, dev, n, tol, steps=3):
                 _, _, _, st = s.solve()
             torch.cuda.synchronize()
             dt = (time.perf_counter() - t) / steps
-        out[name] = {"ms": dt * 1e3, "dof_per_s": n ** 3 / dt, "gmres_iters": st.gmres_iters}
+        out[name] = {"ms": dt * 1e3, "dof_per_s": n ** dim / dt, "gmres_iters": st.gmres_iters}
     return out
 
 
@@ -189,6 +193,8 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-n2d", type=int, default=1024,
+                    help="grid of the second CPU-vs-GPU configuration (2-D variable-coefficient problem)")
     ap.add_argument("--cpu-n", type=int, default=128,
                     help="grid of the CPU oracle baseline (and of the GPU times reported beside it)")
     ap.add_argument("--no-batch", action="store_true")
@@ -458,6 +464,7 @@ def main():
 
     cpu = None
     same = None
+    same2 = None
     if not args.no_cpu:
         cpu = cpu_baseline(args.cpu_n, args.tol)
         same = gpu_same_config(ah, W, torch, dev, args.cpu_n, args.tol)
@@ -465,6 +472,14 @@ def main():
         same["gpu_mixed_speedup_over_cpu_oracle"] = cpu["time_s"] * 1e3 / same["mixed"]["ms"]
         print(f"[bench] CPU oracle n={args.cpu_n}: {cpu['time_s']:.1f} s; GPU mixed {same['mixed']['ms']:.1f} ms, "
               f"FP64 {same['fp64']['ms']:.1f} ms", file=sys.stderr, flush=True)
+        # a second configuration both sides report: the 2-D variable-coefficient problem
+        cpu2 = cpu_baseline(args.cpu_n2d, args.tol, dim=2)
+        same2 = gpu_same_config(ah, W, torch, dev, args.cpu_n2d, args.tol, dim=2)
+        same2["cpu_oracle_s"] = cpu2["time_s"]
+        same2["cpu_oracle_sample"] = cpu2["sample"]
+        same2["gpu_mixed_speedup_over_cpu_oracle"] = cpu2["time_s"] * 1e3 / same2["mixed"]["ms"]
+        print(f"[bench] CPU oracle 2-D n={args.cpu_n2d}: {cpu2['time_s']:.1f} s; GPU mixed {same2['mixed']['ms']:.1f} "
+              f"ms, FP64 {same2['fp64']['ms']:.1f} ms", file=sys.stderr, flush=True)
 
     st = st_mx[-1]
     line = {
@@ -493,6 +508,7 @@ def main():
                                                               (result_fp64["ms_per_step"] if result_fp64 else 0.0))
                                                       for k, v in setup_ms.items()},
                    "gpu_same_config": same,
+                   "gpu_same_config_2d": same2,
                    "fp64_ref": {"tol": 1e-13, "gmres_iters": st_ref.gmres_iters},
                    "fp64": result_fp64, "batched": batched, "fp32_matvec_kernels": kernels,
                    "dst_kernel_choice": choices},

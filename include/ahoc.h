@@ -292,7 +292,9 @@ ahoc_status ahoc_dst1(int precision, int dim, const int* nint, int axis, const v
  * plain pass of even n <= 128 (untimed), 5 = as 0 without setup-time choices (default
  * kernels).
  * Handles keep the choice timed at their setup.  For tuning and for testing every
- * family. */
+ * family: a process-wide switch read by every pass launched after the call (atomically;
+ * passes that other threads launch while it changes may run either family), not a
+ * per-handle setting.  Production callers leave it at 0. */
 ahoc_status ahoc_set_dst_variant(int variant);
 
 /* Calibration copies (no arithmetic): out = in for an [nz][ny][nx] FP32 volume, with the
@@ -333,7 +335,8 @@ ahoc_status ahoc_dst_choice(const struct ahoc_handle* h, int precision, int axis
  * forward/scale/inverse pass; precision selects the FP64 or the FP32 (AHOC_MIXED)
  * kernels.  A tile whose work-group exceeds the kernel's size or LDS limits makes the
  * launch return AHOC_E_UNSUPPORTED; the fused pass clamps it to its default.  The
- * per-handle ahoc_options.tile_* fields take precedence.  For tuning. */
+ * per-handle ahoc_options.tile_* fields take precedence.  For tuning: process-wide and
+ * read atomically by every pass launched after the call, as ahoc_set_dst_variant. */
 ahoc_status ahoc_set_dst_tile(int pass, int precision, int pairs);
 
 /* Kernel classes for ahoc_kernel_times. */

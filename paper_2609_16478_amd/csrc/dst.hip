@@ -23,6 +23,7 @@
 // (k_x, k_y, k_z) by scale / lambda(k), and applies the DST again, before one
 // store: lambda = sum_a s_a + sum_{a<b} (h_a^2 + h_b^2)/12 s_a s_b with
 // s_a(k) = -(4/h_a^2) sin^2(k pi / (2 N_a)).
+#include <atomic>
 #include "common.h"
 
 #include <cmath>
@@ -552,15 +553,19 @@ template <typename T> void dst_tables_free(DstTables<T>& tb) {
   tb.N = 0;
 }
 
-static int g_variant = 0;
-void dst_set_variant(int v) { g_variant = v; }
-int dst_get_variant() { return g_variant; }
+// Process-wide kernel-family switch (a test and tuning hook, read at every pass; relaxed
+// atomic so that setting it while other threads run passes is not a data race -- which
+// family those passes use is then unspecified)
+static std::atomic<int> g_variant_{0};
+void dst_set_variant(int v) { g_variant_.store(v, std::memory_order_relaxed); }
+int dst_get_variant() { return g_variant_.load(std::memory_order_relaxed); }
 
 template <typename T>
 int dst_pass(const DstTables<T>& tb, const T* in, T* out, long long outer, long long inner,
              long long pitch, const DstScale<T>* fused, int tile_seqs, hipStream_t st,
              const DstFaces<T>* faces) {
   const int N = tb.N;
+  const int g_variant = dst_get_variant();
   if (inner == 1 && pitch < N - 1) return ST_INVALID;
   // plain passes: the kernel chosen at setup (or the matrix-core product where forced)
   if (!fused && !(faces && faces->mode) && tile_seqs <= 0) {

@@ -16,6 +16,7 @@
 //    bank conflicts;
 //  * the odd outputs' prefix sum runs as a serial sum over a contiguous chunk
 //    per thread plus a segmented lane scan of the chunk totals (shuffles).
+#include <atomic>
 #include "dst_device.h"
 
 #include <mutex>
@@ -211,12 +212,14 @@ static int fast_tps(int N, int kind) {
   }
 }
 
-static int g_tile_override[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+// Process-wide tile override per pass kind and precision (a tuning hook, relaxed atomics as
+// the kernel-family switch)
+static std::atomic<int> g_tile_override[3][2] = {{{0}, {0}}, {{0}, {0}}, {{0}, {0}}};
 
 int dst_set_tile(int kind, int elem_bytes, int pairs) {
   if (kind < 0 || kind > 2 || (elem_bytes != 4 && elem_bytes != 8) || pairs < 0 || (pairs & (pairs - 1)))
     return ST_INVALID;
-  g_tile_override[kind][elem_bytes == 8] = pairs;
+  g_tile_override[kind][elem_bytes == 8].store(pairs, std::memory_order_relaxed);
   return ST_OK;
 }
 
@@ -254,13 +257,13 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
     return ST_UNSUPPORTED;
   const int kind = fused ? DST_PASS_FUSED : (inner == 1 ? DST_PASS_ROWS : DST_PASS_STRIDED);
   // row passes with the default tile: compile-time row kernel (dst_rows.hip)
-  if (kind == DST_PASS_ROWS && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8] == 0 && dst_get_variant() != 3) {
+  if (kind == DST_PASS_ROWS && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8].load(std::memory_order_relaxed) == 0 && dst_get_variant() != 3) {
     const int rc = dst_rows_pass<T>(N, tw, sn, in, out, outer, pitch, st);
     if (rc != ST_UNSUPPORTED) return rc;
   }
   // strided passes (plain, or forward + scaling + face sums) with the default tile:
   // persistent pipelined kernel (dst_pipe.hip)
-  if (inner > 1 && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8] == 0 && dst_get_variant() != 3) {
+  if (inner > 1 && nseq <= 0 && g_tile_override[kind][sizeof(T) == 8].load(std::memory_order_relaxed) == 0 && dst_get_variant() != 3) {
     const int rc = dst_pipe_pass<T>(N, tw, sn, in, out, outer, inner, fused, faces, 0, st);
     if (rc != ST_UNSUPPORTED) return rc;
   }
@@ -273,7 +276,7 @@ int dst_fast_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
   a.inner = inner;
   a.pitch = pitch;
   const int dflt = dst_fast_tile(N, (int)sizeof(T), kind);
-  const int ovr = g_tile_override[kind][sizeof(T) == 8];
+  const int ovr = g_tile_override[kind][sizeof(T) == 8].load(std::memory_order_relaxed);
   if (nseq <= 0) nseq = ovr > 0 ? ovr : dflt;
   if (fused && nseq > dflt) nseq = dflt;  // the fused pass has a lower size cap
   if (nseq <= 0 || (nseq & (nseq - 1))) return ST_UNSUPPORTED;
