@@ -250,7 +250,7 @@ int dst_pipe_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long
 // (sc, with the mc* fields) plus the spectrum of the face-layer source generated from the
 // 2-D face spectra of gen times scale / lambda_L; face sums along the pass axis (faces,
 // mode 1); store.  gen's layouts as for dst_gen_pass, except lb: [side][ia][m-1] (row pitch
-// bpitch, plane bplane).  The face arrays of gen are turned into their sums and differences
+// bpitch, plane bplane).  gen's y-face array (lb) is turned into its sums and differences
 // in place.  ST_UNSUPPORTED where the persistent kernel's layout conditions fail (checked
 // before anything is launched).
 template <typename T>

@@ -258,9 +258,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * NSEQ * TPS;
         if (j < L) {
-          cx<T> xv;
-          xv.x = xf[0][r];
-          xv.y = xf[1][r];
+          cx<T> xv;  // the face pair as (sum, difference)
+          xv.x = xf[0][r] + xf[1][r];
+          xv.y = xf[0][r] - xf[1][r];
           xrow[j] = xv;
         }
       }
@@ -331,13 +331,15 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         const long long iaa = ca - ib * a.fs.na;
         // every position of this thread has the parity of 1 + ts (TPS is even)
         const bool modd = ((1 + ts) & 1) != 0;
-        const T* lp = a.gn.lp + o * a.gn.pslab + (modd ? 0 : a.gn.pplane);
+        // z-face pair as its sum (odd mode) or difference (even mode)
+        const T* lp = a.gn.lp + o * a.gn.pslab;
+        const T sg = modd ? T(1) : T(-1);
         if (va) {
-          ga0 = lp[ca];
+          ga0 = lp[ca] + sg * lp[a.gn.pplane + ca];
           wla = a.gn.wa[iaa];
         }
         if (vb) {
-          gb0 = lp[cb];
+          gb0 = lp[cb] + sg * lp[a.gn.pplane + cb];
           wlb = a.gn.wa[iaa + 1];
         }
         if (a.gn.lb) {
@@ -468,8 +470,10 @@ template <typename T, int N, int MODE> struct PipeLaunch {
 //
 // Mode k of the layer next to the high face carries the layer sine of the low face times
 // (-1)^(k+1) (sin(pi k (N-1)/N)), so a face pair enters mode k only through lo + hi (k odd)
-// or lo - hi (k even).  k_face_pm turns every face pair into that sum and difference in
-// place first; then a term is one face value times one layer sine:
+// or lo - hi (k even).  The x- and z-face pairs are combined where they are read (two
+// loads per tile and column); the y-face pairs, read at every position, are turned into
+// their sum and difference in place by k_face_pm first.  Then a term is one face value
+// times one layer sine:
 //   z faces  P(kx, ky) at the position parity of the pass axis (fixed per thread, since a
 //            thread's positions are TPS apart and TPS is even)
 //   x faces  X(ky, kz): the pair's even column (odd mode) the sum, its odd column the
@@ -637,14 +641,16 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       Ab = (sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb)) * isc;
       Bb = (T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt) * isc;
     }
-    const T* lp = g.lp + o * g.pslab + (modd ? 0 : g.pplane);
+    // z-face pair as its sum (odd mode) or difference (even mode)
+    const T* lp = g.lp + o * g.pslab;
+    const T sg = modd ? T(1) : T(-1);
     T pa = 0, pb = 0, wla = 0, wlb = 0;
     if (va) {
-      pa = lp[ca];
+      pa = lp[ca] + sg * lp[g.pplane + ca];
       wla = g.wa[iaa];
     }
     if (vb) {
-      pb = lp[ca + 1];
+      pb = lp[ca + 1] + sg * lp[g.pplane + ca + 1];
       wlb = g.wa[iab];
     }
     const T wbl = has_b ? g.wb[ib] : T(0);
@@ -654,9 +660,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * THREADS;
         if (j < L) {
-          cx<T> xv;
-          xv.x = xr[0][r];
-          xv.y = xr[1][r];
+          cx<T> xv;  // the face pair as (sum, difference)
+          xv.x = xr[0][r] + xr[1][r];
+          xv.y = xr[0][r] - xr[1][r];
           xrow[j] = xv;
         }
       }
@@ -679,8 +685,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
         xa = xv.x;
         xb = xv.y;
       } else {
-        xa = la[(long long)(m - 1) * g.apitch];
-        xb = la[g.aplane + (long long)(m - 1) * g.apitch];
+        const T lo = la[(long long)(m - 1) * g.apitch], hi = la[g.aplane + (long long)(m - 1) * g.apitch];
+        xa = lo + hi;
+        xb = lo - hi;
       }
       ga = pa * wpl + xa * wla;
       gb = pb * wpl + xb * wlb;
@@ -805,13 +812,9 @@ template <typename T, int N> struct GenPipeLaunch {
     a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
-    // the face pairs into their sums and differences (in place; the arrays are this pass's
-    // input only).  Per slab: z faces pplane, x faces aplane, y faces bplane entries.
-    T* lp = const_cast<T*>(a.g.lp);
-    T* la = const_cast<T*>(a.g.la);
+    // the y-face pairs into their sums and differences (in place; the arrays are this
+    // pass's input only)
     T* lb = const_cast<T*>(a.g.lb);
-    TRY_ST(face_pm<T>(lp, a.g.pplane, a.outer > 1 ? a.g.pslab : 0, a.g.pplane, a.outer, st));
-    TRY_ST(face_pm<T>(la, a.g.aplane, a.outer > 1 ? a.g.aslab : 0, a.g.aplane, a.outer, st));
     if (lb) TRY_ST(face_pm<T>(lb, a.g.bplane, a.outer > 1 ? a.g.bslab : 0, a.g.bplane, a.outer, st));
     const long long grid = ntiles < res ? ntiles : res;
     a.ntst = (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
@@ -927,11 +930,7 @@ template <typename T, int N>
 int mpass_run(const cx<T>* tw, const T* sn, T* buf, long long outer, long long inner, const DstScale<T>& sc,
               const DstFaces<T>& faces, const DstGen<T>& gen, hipStream_t st) {
   TRY_ST((mpass_check<T, N>(inner, sc.na, gen)));
-  T* lp = const_cast<T*>(gen.lp);
-  T* la = const_cast<T*>(gen.la);
   T* lb = const_cast<T*>(gen.lb);
-  TRY_ST(face_pm<T>(lp, gen.pplane, outer > 1 ? gen.pslab : 0, gen.pplane, outer, st));
-  TRY_ST(face_pm<T>(la, gen.aplane, outer > 1 ? gen.aslab : 0, gen.aplane, outer, st));
   if (lb) TRY_ST(face_pm<T>(lb, gen.bplane, outer > 1 ? gen.bslab : 0, gen.bplane, outer, st));
   Args<T> a;
   a.in = buf;
