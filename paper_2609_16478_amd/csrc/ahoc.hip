@@ -64,6 +64,7 @@ template <typename T> struct Prec {
   T* Ux = nullptr;
   T* Uy = nullptr;
   T* Uz = nullptr;
+  T* mq = nullptr;  // 3-D: m1 / alpha at the boundary node of each face node (Q layout)
   DstScale<T> scM;
 
   DstScale<T> scV, scU, scP;
@@ -373,6 +374,10 @@ template <typename T> int prec_init(ahoc_handle* h, Prec<T>& P, int tile_opt, hi
       TRY(alloc_t(h, &P.Ux, 2LL * g.ni[1] * g.ni[2]));
       TRY(alloc_t(h, &P.Uy, 2LL * g.ni[0] * g.ni[2]));
       TRY(alloc_t(h, &P.Uz, 2LL * g.px * g.ni[1]));
+      if (g.nb == 1) {  // m1 / alpha_b in Q layout, for the tiled face-layer pass
+        TRY(alloc_t(h, &P.mq, TQ(g)));
+        TRY(nodal_to_q<T>(g, h->w.m1, P.ia, P.mq, st));
+      }
     } else {  // per instance [2][n_y'] and [2][px]
       TRY(alloc_t(h, &P.Ux, 2LL * g.nb * g.ni[1]));
       TRY(alloc_t(h, &P.Uy, 2LL * g.nb * g.px));
@@ -663,12 +668,15 @@ template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) 
 // Homogeneous V-solve V = -L^{-1} L_h^bnd[Q] into P.bufA through the spectral lift: face
 // layers of the lift, their 2-D spectra, then the slowest-axis pass generates the 3-D
 // spectrum, scales it and inverts along its axis; the other axes are inverted as usual.
-template <typename T> int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st, bool skip_x = false) {
+template <typename T>
+int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st, bool skip_x = false, bool lifted = false) {
   const Geom& g = h->g;
-  hipEvent_t e = tbegin(h, st);
-  TRY(face_lift<T>(g, h->wv, Q, P.Fx, P.Fy, P.Fz, st));
-  TRY(face_dst2<T>(h, P, st));
-  tend(h, AHOC_K_LIFT, e, (double)TQ(g) * 2.0 * sizeof(T), st);
+  if (!lifted) {  // (else the face layers are in Fx, Fy, Fz already)
+    hipEvent_t e = tbegin(h, st);
+    TRY(face_lift<T>(g, h->wv, Q, P.Fx, P.Fy, P.Fz, st));
+    TRY(face_dst2<T>(h, P, st));
+    tend(h, AHOC_K_LIFT, e, (double)TQ(g) * 2.0 * sizeof(T), st);
+  }
   const double pass_bytes = 2.0 * (double)g.nint * g.nb * sizeof(T);
   T* buf = P.bufA;
   DstGen<T> gen;
@@ -759,9 +767,17 @@ template <typename T> DstGen<T> mspec_gen(const Geom& g, Prec<T>& P) {
 template <typename T> int matvec_mspec(ahoc_handle* h, Prec<T>& P, const T* Q, double* y, hipStream_t st) {
   const Geom& g = h->g;
   const bool d3 = g.dim == 3;
-  TRY(vsolve_spec<T>(h, P, Q, st, true));
+  const bool tiled = d3 && P.mq;
+  if (tiled) {
+    // both face-layer sets in one pass over Q, then the V-solve's layer spectra
+    hipEvent_t e = tbegin(h, st);
+    TRY(face_lifts3<T>(g, h->wv, Q, P.mq, P.Fx, P.Fy, P.Fz, P.Ux, P.Uy, P.Uz, st));
+    TRY(face_dst2<T>(h, P, st));
+    tend(h, AHOC_K_LIFT, e, (double)TQ(g) * 4.0 * sizeof(T), st);
+  }
+  TRY(vsolve_spec<T>(h, P, Q, st, true, tiled));
   hipEvent_t el = tbegin(h, st);
-  TRY(face_lift_m<T>(g, h->w, Q, P.ia, P.Ux, P.Uy, P.Uz, st));
+  if (!tiled) TRY(face_lift_m<T>(g, h->w, Q, P.ia, P.Ux, P.Uy, P.Uz, st));
   if (d3) {
     // 2-D spectra: x and z faces as the lift's; y faces [2][n_x'][n_z'] (z rows, x strided)
     TRY(dst_pass<T>(P.tb[0], P.Uz, P.Uz, 2LL * g.ni[1], 1, g.px, nullptr, 0, st));

@@ -17,6 +17,18 @@ int gather(const Geom& g, const Weights& w, const T* U, const T* Q, const T* af,
 // face layers of the homogeneous lift (input of the spectral lift); fixed-order sums of partials
 template <typename T>
 int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, hipStream_t st);
+// 3-D: the V-solve's lift layers (weights wv, layouts of face_lift) and the U-solve's
+// layers mq Q_b (mq = m1 / alpha_b in Q layout, layouts of face_lift_m) in one tiled pass
+// over Q
+template <typename T> struct FaceLiftW {
+  T w0[3], wf[3], ws[3];  // per face axis: normal, faster and slower tangential couplings
+};
+template <typename T>
+int face_lifts3(const Geom& g, const Weights& wv, const T* Q, const T* mq, T* Lx, T* Ly, T* Lz, T* Ux, T* Uy,
+                T* Uz, hipStream_t st);
+// out[q] = s * nodal(boundary node of q): a nodal field in Q layout
+template <typename T>
+int nodal_to_q(const Geom& g, double s, const T* nodal, T* out, hipStream_t st);
 // face layers m1 Q_b / alpha_b of the U-solve's source (spectral M), layouts as face_lift
 // except the 3-D y faces, [2][n_x'][n_z'] (z fastest)
 template <typename T>

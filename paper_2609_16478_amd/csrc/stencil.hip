@@ -619,6 +619,105 @@ __global__ void k_face_lift_m(Geom g, T m1, const T* __restrict__ Q, const T* __
   }
 }
 
+// out[q] = s * nodal(boundary node of q), a nodal field in Q's layout
+template <typename T, int DIM>
+__global__ void k_nodal_to_q(Geom g, T s, const T* __restrict__ nodal, T* __restrict__ out) {
+  const long long b_ = blockIdx.y;  // instance of a batch (gridDim.y = g.nb)
+  nodal += b_ * g.nnodal;
+  out += b_ * g.nq;
+  for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < g.nq; q += gridDim.x * blockDim.x) {
+    int i, j, k, ax, st;
+    dec_q<DIM>(g, q, i, j, k, ax, st);
+    out[q] = s * nodal[nod(g, i, j, k)];
+  }
+}
+
+// Both face-layer sets of the 3-D homogeneous matvec in one pass over Q, by 32 x 32 tiles of
+// each face in Q's own layout (rows along the face's slower tangential axis, the faster one
+// contiguous):
+//   V-solve lift  Lf = w0 Q + w_fast (Q(s, f-1) + Q(s, f+1)) + w_slow (Q(s-1, f) + Q(s+1, f)),
+//                 the 19-point operator's couplings of a layer node to the face (face normal
+//                 weight w0, edge weights to the tangential neighbours; Q = 0 past the face's
+//                 interior)
+//   U-solve layer Uf = (m1 / alpha_b) Q, the factor from the nodal alpha in Q's layout (mq)
+// The tile (with a one-node halo) is read coalesced into LDS; each output is written in its
+// own layout -- along the same axis as Q for the y/z-face V layers and the z-face U layer,
+// transposed (through LDS) for the x faces and the y-face U layer.  Layouts of face_lift and
+// face_lift_m.
+template <typename T>
+__global__ void __launch_bounds__(256) k_face_lifts3(Geom g, const T* __restrict__ Q, const T* __restrict__ mq,
+                                                      FaceLiftW<T> lw, T* __restrict__ Lx, T* __restrict__ Ly,
+                                                      T* __restrict__ Lz, T* __restrict__ Ux, T* __restrict__ Uy,
+                                                      T* __restrict__ Uz) {
+  constexpr int TS = 32;
+  __shared__ T qt[TS + 2][TS + 3];
+  __shared__ T vt[TS][TS + 1];
+  __shared__ T ut[TS][TS + 1];
+  // work-group -> (face, slow tile, fast tile)
+  int b = blockIdx.x, f = 0;
+  int nf = 0, ns = 0, tf = 0, ts = 0;
+  for (f = 0; f < 6; ++f) {
+    const int a = f >> 1;
+    nf = a == 0 ? g.ni[1] : g.ni[0];  // faster tangential axis: y for x faces, x otherwise
+    ns = a == 2 ? g.ni[1] : g.ni[2];  // slower: z for x and y faces, y for z faces
+    tf = (nf + TS - 1) / TS;
+    ts = (ns + TS - 1) / TS;
+    if (b < tf * ts) break;
+    b -= tf * ts;
+  }
+  if (f >= 6) return;
+  const int a = f >> 1, sd = f & 1;
+  const int s0 = (b / tf) * TS, f0 = (b % tf) * TS;
+  const T* Qf = Q + g.face_off[f];
+  const T* Mf = mq + g.face_off[f];
+  const int lx = threadIdx.x & 31, ly = threadIdx.x >> 5;  // 32 x 8
+  // Q tile with halo, zero past the face interior
+  for (int r = ly; r < TS + 2; r += 8)
+    for (int c = lx; c < TS + 2; c += 32) {
+      const int ss = s0 + r - 1, ff = f0 + c - 1;
+      qt[r][c] = (ss >= 0 && ss < ns && ff >= 0 && ff < nf) ? Qf[(long long)ss * nf + ff] : T(0);
+    }
+  __syncthreads();
+  const T w0 = lw.w0[a], wf = lw.wf[a], ws = lw.ws[a];
+  for (int r = ly; r < TS; r += 8) {
+    const int ss = s0 + r, ff = f0 + lx;
+    T v = 0, u = 0;
+    if (ss < ns && ff < nf) {
+      const T q = qt[r + 1][lx + 1];
+      v = w0 * q + wf * (qt[r + 1][lx] + qt[r + 1][lx + 2]) + ws * (qt[r][lx + 1] + qt[r + 2][lx + 1]);
+      u = q * Mf[(long long)ss * nf + ff];
+    }
+    vt[r][lx] = v;
+    ut[r][lx] = u;
+  }
+  __syncthreads();
+  // along Q's axes: row ss (slower axis), column ff (faster), pitch px; the padding columns
+  // (px - n_x' < 32, all in the last tile, whose entries there are zero) are written too
+  auto direct = [&](T* out, const T (*tile)[TS + 1], long long pitch) {
+    for (int r = ly; r < TS; r += 8) {
+      const int ss = s0 + r, ff = f0 + lx;
+      if (ss < ns && ff < pitch) out[(long long)ss * pitch + ff] = tile[r][lx];
+    }
+  };
+  // transposed: row ff, column ss, pitch ns
+  auto transposed = [&](T* out, const T (*tile)[TS + 1]) {
+    for (int r = ly; r < TS; r += 8) {
+      const int ff = f0 + r, ss = s0 + lx;
+      if (ff < nf && ss < ns) out[(long long)ff * ns + ss] = tile[lx][r];
+    }
+  };
+  if (a == 0) {  // x faces: [side][j][k]
+    transposed(Lx + (long long)sd * g.ni[1] * g.ni[2], vt);
+    transposed(Ux + (long long)sd * g.ni[1] * g.ni[2], ut);
+  } else if (a == 1) {  // y faces: V [side][k][px], U [side][i][k]
+    direct(Ly + (long long)sd * g.ni[2] * g.px, vt, g.px);
+    transposed(Uy + (long long)sd * g.ni[0] * g.ni[2], ut);
+  } else {  // z faces: [side][j][px]
+    direct(Lz + (long long)sd * g.ni[1] * g.px, vt, g.px);
+    direct(Uz + (long long)sd * g.ni[1] * g.px, ut, g.px);
+  }
+}
+
 // out[e] = sum_{b < count} in[b * stride + e], e < n, in a fixed order
 template <typename T>
 __global__ void k_partial_sum(long long n, int count, long long stride, const T* __restrict__ in,
@@ -1383,6 +1482,42 @@ int face_lift(const Geom& g, const Weights& w, const T* Q, T* Lx, T* Ly, T* Lz, 
 }
 
 template <typename T>
+int face_lifts3(const Geom& g, const Weights& wv, const T* Q, const T* mq, T* Lx, T* Ly, T* Lz, T* Ux, T* Uy,
+                T* Uz, hipStream_t st) {
+  if (g.dim != 3 || g.nb != 1 || g.px - g.ni[0] >= 32) return ST_UNSUPPORTED;
+  // the V lift's couplings per face axis a: normal, then edge weights to the faster and the
+  // slower tangential neighbour (xy = ce[0], xz = ce[1], yz = ce[2])
+  FaceLiftW<T> lw;
+  lw.w0[0] = (T)wv.cf[0];
+  lw.wf[0] = (T)wv.ce[0];
+  lw.ws[0] = (T)wv.ce[1];
+  lw.w0[1] = (T)wv.cf[1];
+  lw.wf[1] = (T)wv.ce[0];
+  lw.ws[1] = (T)wv.ce[2];
+  lw.w0[2] = (T)wv.cf[2];
+  lw.wf[2] = (T)wv.ce[1];
+  lw.ws[2] = (T)wv.ce[2];
+  long long blocks = 0;
+  for (int f = 0; f < 6; ++f) {
+    const int a = f >> 1;
+    const int nf = a == 0 ? g.ni[1] : g.ni[0], ns = a == 2 ? g.ni[1] : g.ni[2];
+    blocks += (long long)((nf + 31) / 32) * ((ns + 31) / 32);
+  }
+  if (blocks <= 0) return ST_OK;
+  if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+  hipLaunchKernelGGL((k_face_lifts3<T>), dim3((unsigned)blocks), dim3(256), 0, st, g, Q, mq, lw, Lx, Ly, Lz, Ux,
+                     Uy, Uz);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+template <typename T>
+int nodal_to_q(const Geom& g, double s, const T* nodal, T* out, hipStream_t st) {
+  LAUNCH_TDIM(k_nodal_to_q, T, dim3(nblocks(g.nq), g.nb), g, (T)s, nodal, out);
+  return ST_OK;
+}
+
+template <typename T>
 int face_lift_m(const Geom& g, const Weights& w, const T* Q, const T* ia, T* Lx, T* Ly, T* Lz, hipStream_t st) {
   const long long pxp = g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : g.ni[1];
   const long long pyp = g.dim == 3 ? (long long)g.ni[0] * g.ni[2] : g.px;
@@ -1545,6 +1680,9 @@ int fill(long long n, double v, double* x, hipStream_t st) {
 #define INST_T(T)                                                                                  \
   template int face_lift<T>(const Geom&, const Weights&, const T*, T*, T*, T*, hipStream_t);       \
   template int face_lift_m<T>(const Geom&, const Weights&, const T*, const T*, T*, T*, T*, hipStream_t); \
+  template int face_lifts3<T>(const Geom&, const Weights&, const T*, const T*, T*, T*, T*, T*, T*, T*,        \
+                              hipStream_t);                                                        \
+  template int nodal_to_q<T>(const Geom&, double, const T*, T*, hipStream_t);                      \
   template int partial_sum<T>(long long, int, long long, const T*, T*, hipStream_t);               \
   template int gather_faces<T>(const Geom&, const T*, const T*, const T*, const T*, const T*,       \
                                const T*, double*, hipStream_t);                                    \
