@@ -60,12 +60,39 @@ template <typename T, int N, int NSEQ> constexpr size_t pipe_tile_bytes() {
   constexpr int TPS = N / PipePlan<N>::PPT;
   return (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
 }
+// The transform's tile-invariant tables (twiddles exp(-2 pi i k / N), k < N, and the
+// pre-weighting sines sin(pi m / N), m <= N/2) in LDS after everything else, where it has
+// room.  Read from global memory, they would be loads issued after the next tile's prefetch
+// (and after the previous tile's stores), and a wavefront's memory operations complete in
+// issue order: the first wait for a table value would also wait for the whole prefetch.
+template <typename T, int N> constexpr size_t pipe_tab_bytes() {
+  return (size_t)N * sizeof(cx<T>) + (((size_t)(N / 2 + 1) * sizeof(T) + 15) / 16) * 16;
+}
+constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+// MODE 3 data after the tile: the face row (2 (N - 1) values), then the per-position table
+// (4 (N - 1) values) where it fits; the transform tables take precedence over the latter
+template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_face_bytes() {
+  return MODE == 3 ? 2 * (size_t)(N - 1) * sizeof(T) : 0;
+}
+template <typename T, int N, int NSEQ, int MODE> constexpr bool pipe_tab_lds() {
+  return align16(pipe_tile_bytes<T, N, NSEQ>() + pipe_face_bytes<T, N, NSEQ, MODE>()) + pipe_tab_bytes<T, N>() <=
+         160 * 1024;
+}
 template <typename T, int N, int NSEQ> constexpr bool pipe_ptab_lds() {
-  return pipe_tile_bytes<T, N, NSEQ>() + 6 * (size_t)(N - 1) * sizeof(T) <= 160 * 1024;
+  return align16(pipe_tile_bytes<T, N, NSEQ>() + 6 * (size_t)(N - 1) * sizeof(T)) +
+             (pipe_tab_lds<T, N, NSEQ, 3>() ? pipe_tab_bytes<T, N>() : 0) <=
+         160 * 1024;
+}
+// offset of the transform tables
+template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_tab_off() {
+  return align16(pipe_tile_bytes<T, N, NSEQ>() + pipe_face_bytes<T, N, NSEQ, MODE>() +
+                 (MODE == 3 && pipe_ptab_lds<T, N, NSEQ>() ? 4 * (size_t)(N - 1) * sizeof(T) : 0));
 }
 template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_lds_bytes() {
-  return pipe_tile_bytes<T, N, NSEQ>() +
-         (MODE == 3 ? (2 + (pipe_ptab_lds<T, N, NSEQ>() ? 4 : 0)) * (size_t)(N - 1) * sizeof(T) : 0);
+  return pipe_tab_lds<T, N, NSEQ, MODE>()
+             ? pipe_tab_off<T, N, NSEQ, MODE>() + pipe_tab_bytes<T, N>()
+             : pipe_tile_bytes<T, N, NSEQ>() + pipe_face_bytes<T, N, NSEQ, MODE>() +
+                   (MODE == 3 && pipe_ptab_lds<T, N, NSEQ>() ? 4 * (size_t)(N - 1) * sizeof(T) : 0);
 }
 
 // NT: the volume is loaded and stored with the non-temporal policy (arrays larger than the
@@ -108,6 +135,23 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   remap();
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
+  // tile -> (slab o, first column c0 in the slab, MODE 3: row ib of the column decode), in
+  // 32-bit arithmetic (tile counts and columns below 2^30, checked at launch); one decode per
+  // tile, carried from the prefetch to the transform and the store
+  struct TileAt {
+    long long o, c0;
+    unsigned ib;
+  };
+  auto at = [&](long long tile) {
+    TileAt d;
+    const unsigned t = (unsigned)tile, nti = (unsigned)a.ntile_inner;
+    const unsigned ou = t / nti;
+    const unsigned c0 = (t - ou * nti) * (unsigned)(2 * NSEQ);
+    d.o = ou;
+    d.c0 = c0;
+    d.ib = MODE == 3 ? c0 / (unsigned)a.fs.na : 0u;
+    return d;
+  };
   // MODE 3: the tile's row of the face spectra normal to the fastest axis as (sum,
   // difference) pairs per position, in LDS after the tile (prefetched one tile ahead in
   // registers); then, where LDS has room, the per-position table (s, layer sine, face
@@ -119,14 +163,19 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     const cx<T>* pg = reinterpret_cast<const cx<T>*>(a.gn.ptab);
     for (int j = threadIdx.x; j < 2 * L; j += NSEQ * TPS) ptl[j] = pg[j];
   }
+  constexpr bool TWL = pipe_tab_lds<T, N, NSEQ, MODE>();
+  cx<T>* twl = reinterpret_cast<cx<T>*>(smem + pipe_tab_off<T, N, NSEQ, MODE>());
+  T* snl = reinterpret_cast<T*>(twl + N);
+  if constexpr (TWL) {
+    for (int j = threadIdx.x; j < N; j += NSEQ * TPS) twl[j] = a.tw[j];
+    for (int j = threadIdx.x; j <= HN; j += NSEQ * TPS) snl[j] = a.sn[j];
+    __syncthreads();
+  }
   constexpr int XR = MODE == 3 ? (L + NSEQ * TPS - 1) / (NSEQ * TPS) : 1;
   T xf[2][XR];
-  auto xload = [&](long long tile) {
+  auto xload = [&](const TileAt& d) {
     if constexpr (MODE == 3) {
-      const long long o = tile / a.ntile_inner;
-      const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
-      const long long ib = c0 / a.fs.na;
-      const T* la = a.gn.la + o * a.gn.aslab + ib * a.gn.arow;
+      const T* la = a.gn.la + d.o * a.gn.aslab + (long long)d.ib * a.gn.arow;
 #pragma unroll
       for (int r = 0; r < XR; ++r) {
         const int j = (int)threadIdx.x + r * NSEQ * TPS;
@@ -139,19 +188,15 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   };
 
   cx<T> xr[U], yr[U];  // prefetched tile: positions m and N - m of both pencils
-  auto tile_base = [&](long long tile, long long& c0) {
-    const long long o = tile / a.ntile_inner;
-    c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
-    return o * (long long)L * inner + c0;
-  };
+  auto tile_base = [&](const TileAt& d) { return d.o * (long long)L * inner + d.c0; };
   // Global accesses: each row of positions is a uniform 64-bit base (scalar registers) plus
   // a fixed per-lane 32-bit byte offset; the lanes of one access span at most TPS rows.
   const long long rowb = inner * (long long)sizeof(T);  // bytes from one position to the next
   const unsigned vlo = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
   const unsigned vhi = (unsigned)((2 * q + (long long)(TPS - 1 - mi) * inner) * (long long)sizeof(T));
-  auto load = [&](long long tile) {
-    long long c0;
-    const SBase src(a.in + tile_base(tile, c0));
+  auto load = [&](const TileAt& d) {
+    const long long c0 = d.c0;
+    const SBase src(a.in + tile_base(d));
     // columns past the slab (ragged last tile) read column 0 of the tile and are zeroed below
     const bool ok = c0 + 2 * q < inner;
     const unsigned dq = ok ? 0u : (unsigned)(2 * q * (int)sizeof(T));
@@ -202,7 +247,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         o.y = T(2) * xr[u].y;
         *plo = o;
       } else {
-        const T w = a.sn[m];
+        const T w = TWL ? snl[m] : a.sn[m];
         const T sx = w * (xr[u].x + yr[u].x), sy = w * (xr[u].y + yr[u].y);
         const T dx = T(0.5) * (xr[u].x - yr[u].x), dy = T(0.5) * (xr[u].y - yr[u].y);
         cx<T> o1, o2;
@@ -221,10 +266,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       lds[tid * LDQ] = z;
     }
   };
-  auto store = [&](long long tile) {
-    long long c0;
-    const SBase dst(a.out + tile_base(tile, c0));
-    if (c0 + 2 * q >= inner) return;
+  auto store = [&](const TileAt& d) {
+    const SBase dst(a.out + tile_base(d));
+    if (d.c0 + 2 * q >= inner) return;
     unsigned vs = vlo;
     asm volatile("" : "+v"(vs));
     const cx<T>* sq = lds + q * LDQ;
@@ -247,13 +291,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   };
 
   long long tile = blockIdx.x;
-  if (tile < ntiles) load(tile);
+  TileAt cur = at(tile);
+  if (tile < ntiles) load(cur);
   for (; tile < ntiles; tile += gridDim.x) {
     remap();
-    const cx<T>* tw = a.tw;
+    const cx<T>* tw = TWL ? twl : a.tw;
     to_lds();
     if constexpr (MODE == 3) {
-      xload(tile);
+      xload(cur);
 #pragma unroll
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * NSEQ * TPS;
@@ -267,10 +312,11 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     }
     __syncthreads();
     const long long nxt = tile + gridDim.x;
+    const TileAt nd = at(nxt);
     // the next tile is in flight during the transform below (with two transforms, during
     // the second one only: the prefetched registers are not live across both)
     if constexpr (MODE != 2) {
-      if (nxt < ntiles) load(nxt);
+      if (nxt < ntiles) load(nd);
     }
 
     cx<T> A, B;
@@ -281,8 +327,8 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       // forward transform of the slowest axis and eigen scaling; then either the face sums
       // of the scaled spectrum along the pass axis per column (MODE 1: the scaled spectrum
       // itself is the output) or the inverse transform (MODE 2: a whole Poisson pass)
-      const long long o = tile / a.ntile_inner;
-      const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+      const long long o = cur.o;
+      const long long c0 = cur.c0;
       const long long ca = c0 + 2 * s, cb = ca + 1;
       auto coef = [&](long long col, T& Ao, T& Bo) {
         const unsigned ib = (unsigned)col / (unsigned)a.fs.na;  // col < inner < 2^31
@@ -305,8 +351,8 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       if constexpr (MODE == 3) post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
       else post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
       if constexpr (MODE == 2) {
-        if (nxt < ntiles) load(nxt);
-        pre_lds<T, N, PL>(seq, ts, a.sn);
+        if (nxt < ntiles) load(nd);
+        pre_lds<T, N, PL>(seq, ts, TWL ? snl : a.sn);
         fft<T, N, PL>(seq, ts, tw);
         A.x = A.y = T(1);
         B.x = B.y = T(0);
@@ -324,11 +370,13 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       // parity as a uniform base, the pair's two rows as 32-bit offsets
       [[maybe_unused]] const T* ybase = nullptr;
       [[maybe_unused]] unsigned yoff = 0, ystep = 0;
-      [[maybe_unused]] const bool va = ca < inner && (ca - (ca / a.fs.na) * a.fs.na) < a.fs.nva;
-      [[maybe_unused]] const bool vb = cb < inner && (cb - (cb / a.fs.na) * a.fs.na) < a.fs.nva;
+      // MODE 3: the tile lies in row ib of the column decode (na a multiple of the tile
+      // width, checked at launch), so the pair's columns are iaa and iaa + 1 of that row
+      [[maybe_unused]] const long long ib = cur.ib;
+      [[maybe_unused]] const long long iaa = ca - ib * a.fs.na;
+      [[maybe_unused]] const bool va = MODE == 3 && ca < inner && iaa < a.fs.nva;
+      [[maybe_unused]] const bool vb = MODE == 3 && cb < inner && iaa + 1 < a.fs.nva;
       if constexpr (MODE == 3) {
-        const long long ib = c0 / a.fs.na;
-        const long long iaa = ca - ib * a.fs.na;
         // every position of this thread has the parity of 1 + ts (TPS is even)
         const bool modd = ((1 + ts) & 1) != 0;
         // z-face pair as its sum (odd mode) or difference (even mode)
@@ -407,8 +455,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
     }
     __syncthreads();  // the store reads other pairs' sequences
-    store(tile);
+    store(cur);
     __syncthreads();  // the next tile overwrites LDS
+    cur = nd;
   }
 }
 
@@ -451,6 +500,9 @@ template <typename T, int N, int MODE> struct PipeLaunch {
     a.ntst = nt;
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
+    // the kernel decodes tiles and columns in 32-bit arithmetic
+    if (a.inner >= (1LL << 30) || ntiles >= (1LL << 30)) return ST_UNSUPPORTED;
+    if (MODE == 3 && (a.fs.na <= 0 || a.fs.na % (2 * NSEQ) != 0)) return ST_UNSUPPORTED;
     const long long grid = ntiles < res ? ntiles : res;
     if (nt)
       hipLaunchKernelGGL((k_dst_pipe<T, N, NSEQ, MODE, HAS_NT>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
@@ -531,7 +583,11 @@ template <typename T, int N, int NSEQ> struct GenShape {
   static constexpr bool XLDS = TILE_B + 2 * (size_t)L * sizeof(T) <= LDS_MAX;
   static constexpr bool TLDS = XLDS && TILE_B + 4 * (size_t)L * sizeof(T) <= LDS_MAX;
   static constexpr int XR = (L + THREADS - 1) / THREADS;  // x-face entries per thread and side
-  static constexpr size_t LDS = TILE_B + (XLDS ? 2 * (size_t)L * sizeof(T) : 0) + (TLDS ? 2 * (size_t)L * sizeof(T) : 0);
+  static constexpr size_t BASE = TILE_B + (XLDS ? 2 * (size_t)L * sizeof(T) : 0) + (TLDS ? 2 * (size_t)L * sizeof(T) : 0);
+  // then the transform's twiddles and pre-weighting sines (as in k_dst_pipe), where they fit
+  static constexpr size_t TAB_OFF = align16(BASE);
+  static constexpr bool TWL = TAB_OFF + pipe_tab_bytes<T, N>() <= LDS_MAX;
+  static constexpr size_t LDS = TWL ? TAB_OFF + pipe_tab_bytes<T, N>() : BASE;
 };
 
 template <typename T, int N, int NSEQ>
@@ -555,6 +611,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   cx<T>* xrow = reinterpret_cast<cx<T>*>(smem + SH::TILE_B);  // (sum, difference) per position
   cx<T>* tab = xrow + L;                                       // (layer sine, eigenvalue) per position
+  constexpr bool TWL = SH::TWL;
+  cx<T>* twl = reinterpret_cast<cx<T>*>(smem + SH::TAB_OFF);
+  T* snl = reinterpret_cast<T*>(twl + N);
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
   const DstGen<T>& g = a.g;
@@ -575,16 +634,34 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       tab[j] = t;
     }
   }
+  if constexpr (TWL) {
+    for (int j = tid0; j < N; j += THREADS) twl[j] = a.tw[j];
+    for (int j = tid0; j <= HN; j += THREADS) snl[j] = a.sn[j];
+  }
 
+  // tile -> (slab o, first column c0 in the slab, row ib of the column decode), in 32-bit
+  // arithmetic (tile counts and columns below 2^30, checked at launch); one decode per tile,
+  // carried from the prefetch to the generation and the store
+  struct TileAt {
+    long long o, c0, ib;
+  };
+  auto at = [&](long long tile) {
+    TileAt d;
+    const unsigned t = (unsigned)tile, nti = (unsigned)a.ntile_inner;
+    const unsigned ou = t / nti;
+    const unsigned c0 = (t - ou * nti) * (unsigned)(2 * NSEQ);
+    d.o = ou;
+    d.c0 = c0;
+    d.ib = c0 / (unsigned)a.fs.na;
+    return d;
+  };
   // prefetched face data of a tile: the y-face values at the thread's mirrored positions
   // (both pencils of its pair) and the tile's x-face row
   cx<T> ylo[U], yhi[U];
   T xr[2][XR];
   const long long rowb = (long long)g.bpitch * (long long)sizeof(T);
-  auto prefetch = [&](long long tile) {
-    const long long o = tile / a.ntile_inner;
-    const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
-    const long long ib = c0 / a.fs.na;
+  auto prefetch = [&](const TileAt& d) {
+    const long long o = d.o, c0 = d.c0, ib = d.ib;
     if (has_b) {
       const long long ia0 = c0 - ib * a.fs.na;  // first column of the tile in its row
       // ky even (odd mode) -> sums, ky odd -> differences
@@ -614,17 +691,18 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
   };
 
   long long tile = blockIdx.x;
-  if (tile < ntiles) prefetch(tile);
+  TileAt cur = at(tile);
+  if (tile < ntiles) prefetch(cur);
   for (; tile < ntiles; tile += gridDim.x) {
     // thread index through an empty asm: tile-invariant addresses stay inside the loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int q = tid & (NSEQ - 1);
     const int mi = tid >> LGQ;
-    const long long o = tile / a.ntile_inner;  // slab (instance of a batch)
-    const long long c0 = (tile - o * a.ntile_inner) * (2LL * NSEQ);
+    const long long o = cur.o;  // slab (instance of a batch)
+    const long long c0 = cur.c0;
     // ---- per pair: column decode, eigenvalue coefficients (divided by the scale), face values
-    const long long ib = c0 / a.fs.na;  // one row per tile
+    const long long ib = cur.ib;  // one row per tile
     const long long ca = c0 + 2 * q;
     const int iaa = (int)(ca - ib * a.fs.na), iab = iaa + 1;
     const bool va = ca < inner && iaa < a.fs.nva, vb = ca + 1 < inner && iab < a.fs.nva;
@@ -717,7 +795,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
         } else {
           T ya, yb;
           gen_at(N - m, yhi[u], ya, yb);
-          const T w = a.sn[m];
+          const T w = TWL ? snl[m] : a.sn[m];
           const T sx = w * (xa + ya), sy = w * (xb + yb);
           const T dx = T(0.5) * (xa - ya), dy = T(0.5) * (xb - yb);
           cx<T> o1, o2;
@@ -739,7 +817,8 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     __syncthreads();
     // the next tile's face data is in flight during the transform below
     const long long nxt = tile + gridDim.x;
-    if (nxt < ntiles) prefetch(nxt);
+    const TileAt nd = at(nxt);
+    if (nxt < ntiles) prefetch(nd);
     // ---- inverse transform along the pass axis
     const int s = tid / TPS;
     const int ts = tid - s * TPS;
@@ -748,7 +827,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     cx<T> A, B;
     A.x = A.y = T(1);
     B.x = B.y = T(0);
-    fft<T, N, PL>(seq, ts, a.tw);
+    fft<T, N, PL>(seq, ts, TWL ? twl : a.tw);
     post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
     __syncthreads();  // the store reads other pairs' sequences
     // ---- store (uniform row bases, fixed per-lane byte offsets)
@@ -775,6 +854,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       }
     }
     __syncthreads();  // the next tile overwrites LDS
+    cur = nd;
   }
 }
 
@@ -812,6 +892,8 @@ template <typename T, int N> struct GenPipeLaunch {
     a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
     const long long ntiles = a.outer * a.ntile_inner;
     if (ntiles <= 0) return ST_OK;
+    // the kernel decodes tiles and columns in 32-bit arithmetic
+    if (a.inner >= (1LL << 30) || ntiles >= (1LL << 30) || a.fs.na <= 0) return ST_UNSUPPORTED;
     // the y-face pairs into their sums and differences (in place; the arrays are this
     // pass's input only)
     T* lb = const_cast<T*>(a.g.lb);
