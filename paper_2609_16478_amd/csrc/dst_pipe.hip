@@ -97,7 +97,12 @@ template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_lds_bytes
 
 // NT: the volume is loaded and stored with the non-temporal policy (arrays larger than the
 // caches, see NT_STORE_MIN_BYTES); a compile-time choice, so that the prefetched registers
-// do not meet at a branch join, which would wait for the loads in flight
+// do not meet at a branch join, which would wait for the loads in flight.  NT launches also
+// have whole tiles only (columns a multiple of the tile width), so their loads and stores
+// have no ragged-tile branches: the next tile's sequences are written to LDS right after the
+// current tile's stores, and the wait for the prefetched registers there leaves the stores
+// in flight (a wavefront's memory operations complete in issue order, and a branch around
+// the stores would make the compiler wait for them too).
 template <typename T, int N, int NSEQ, int MODE, bool NT>
 __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -111,6 +116,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   constexpr int LGQ = ilog2(NSEQ);
   constexpr int NTOT = 2 * (TPS / 64 > 0 ? TPS / 64 : 1);
   static_assert((1 << LGQ) == NSEQ, "NSEQ must be a power of two");
+  constexpr bool FULL = NT;  // whole tiles only (checked at launch)
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   // The thread index and the table pointers pass through an empty asm statement at the top
   // of every tile, so that the compiler recomputes the (tile-invariant) LDS addresses and
@@ -198,7 +204,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     const long long c0 = d.c0;
     const SBase src(a.in + tile_base(d));
     // columns past the slab (ragged last tile) read column 0 of the tile and are zeroed below
-    const bool ok = c0 + 2 * q < inner;
+    const bool ok = FULL || c0 + 2 * q < inner;
     const unsigned dq = ok ? 0u : (unsigned)(2 * q * (int)sizeof(T));
     unsigned vl = vlo - dq, vh = vhi - dq;
     // keep the 32-bit offsets local to this block, so that each access is selected in the
@@ -221,11 +227,13 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         yr[u] = src.plus((long long)(N - 1 - (u + 1) * TPS) * rowb).ld<cx<T>>(vh);
       }
     }
-    if (c0 + 2 * NSEQ > inner && !ok) {
+    if constexpr (!FULL) {
+      if (c0 + 2 * NSEQ > inner && !ok) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        xr[u].x = xr[u].y = T(0);
-        yr[u].x = yr[u].y = T(0);
+        for (int u = 0; u < U; ++u) {
+          xr[u].x = xr[u].y = T(0);
+          yr[u].x = yr[u].y = T(0);
+        }
       }
     }
   };
@@ -268,7 +276,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   };
   auto store = [&](const TileAt& d) {
     const SBase dst(a.out + tile_base(d));
-    if (d.c0 + 2 * q >= inner) return;
+    if constexpr (!FULL) {
+      if (d.c0 + 2 * q >= inner) return;
+    }
     unsigned vs = vlo;
     asm volatile("" : "+v"(vs));
     const cx<T>* sq = lds + q * LDQ;
@@ -290,33 +300,43 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     }
   };
 
-  long long tile = blockIdx.x;
-  TileAt cur = at(tile);
-  if (tile < ntiles) load(cur);
-  for (; tile < ntiles; tile += gridDim.x) {
-    remap();
-    const cx<T>* tw = TWL ? twl : a.tw;
-    to_lds();
+  // MODE 3: the face row of the tile from the prefetched registers, as (sum, difference)
+  auto stage_x = [&]() {
     if constexpr (MODE == 3) {
-      xload(cur);
 #pragma unroll
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * NSEQ * TPS;
         if (j < L) {
-          cx<T> xv;  // the face pair as (sum, difference)
+          cx<T> xv;
           xv.x = xf[0][r] + xf[1][r];
           xv.y = xf[0][r] - xf[1][r];
           xrow[j] = xv;
         }
       }
     }
-    __syncthreads();
+  };
+
+  long long tile = blockIdx.x;
+  TileAt cur = at(tile);
+  if (tile < ntiles) {
+    load(cur);
+    xload(cur);
+    to_lds();
+    stage_x();
+  }
+  for (; tile < ntiles; tile += gridDim.x) {
+    remap();
+    const cx<T>* tw = TWL ? twl : a.tw;
+    __syncthreads();  // the tile's sequences (and face row) in LDS
     const long long nxt = tile + gridDim.x;
     const TileAt nd = at(nxt);
     // the next tile is in flight during the transform below (with two transforms, during
     // the second one only: the prefetched registers are not live across both)
     if constexpr (MODE != 2) {
-      if (nxt < ntiles) load(nd);
+      if (nxt < ntiles) {
+        load(nd);
+        xload(nd);
+      }
     }
 
     cx<T> A, B;
@@ -457,6 +477,10 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     __syncthreads();  // the store reads other pairs' sequences
     store(cur);
     __syncthreads();  // the next tile overwrites LDS
+    if (nxt < ntiles) {
+      to_lds();
+      stage_x();
+    }
     cur = nd;
   }
 }
@@ -492,7 +516,9 @@ template <typename T, int N, int MODE> struct PipeLaunch {
     if (THREADS % 64 != 0 || THREADS > pipe_cap<T, N>() || LDS > 160 * 1024) return ST_UNSUPPORTED;
     // per-lane byte offsets span TPS rows and must fit in 32 bits
     if ((double)(TPS + 1) * (double)a.inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
-    const bool nt = HAS_NT && (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
+    // (the non-temporal form takes whole tiles only)
+    const bool nt = HAS_NT && a.inner % (2 * NSEQ) == 0 &&
+                    (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
     const int res = nt ? resident<true>() : resident<false>();
     if (res <= 0) return ST_UNSUPPORTED;
     a.lg_nseq = ilog2(NSEQ);
@@ -542,7 +568,6 @@ template <typename T> struct GenPipeArgs {
   long long outer, inner, ntile_inner;
   DstScale<T> fs;
   DstGen<T> g;
-  int ntst;  // non-temporal stores (arrays larger than the caches)
 };
 
 // (lo, hi) -> (lo + hi, lo - hi) for `count` entries of each of `nslab` slabs:
@@ -590,7 +615,8 @@ template <typename T, int N, int NSEQ> struct GenShape {
   static constexpr size_t LDS = TWL ? TAB_OFF + pipe_tab_bytes<T, N>() : BASE;
 };
 
-template <typename T, int N, int NSEQ>
+// NT: non-temporal stores and whole tiles only (as in k_dst_pipe)
+template <typename T, int N, int NSEQ, bool NT>
 __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPipeArgs<T> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   using SH = GenShape<T, N, NSEQ>;
@@ -607,6 +633,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
   constexpr bool LIN = TPS % 32 == 0;
   constexpr bool XLDS = SH::XLDS, TLDS = SH::TLDS;
   constexpr int XR = SH::XR;
+  constexpr bool FULL = NT;  // whole tiles only (checked at launch)
   static_assert(TPS % 2 == 0, "positions of a thread must share their parity");
   cx<T>* lds = reinterpret_cast<cx<T>*>(smem);
   cx<T>* xrow = reinterpret_cast<cx<T>*>(smem + SH::TILE_B);  // (sum, difference) per position
@@ -690,48 +717,67 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     }
   };
 
-  long long tile = blockIdx.x;
-  TileAt cur = at(tile);
-  if (tile < ntiles) prefetch(cur);
-  for (; tile < ntiles; tile += gridDim.x) {
+  // per-tile coefficients, prefetched with the face data (loads issued before the stores
+  // of the tile in flight): the pair's column sines, the row sine, the z-face pair at both
+  // columns, the layer weights of the x and y faces.  Indices clamped into the tables; the
+  // validity flags select the values where they are used.
+  struct Coef {
+    T saa, sab, sb, pa0, pa1, pb0, pb1, wla, wlb, wbl;
+  };
+  Coef cf;
+  auto cload = [&](const TileAt& d) {
+    const long long ca = d.c0 + 2 * q0;
+    const int iaa = (int)(ca - d.ib * a.fs.na);
+    const int ia = iaa < a.fs.nva ? iaa : a.fs.nva - 1;
+    const int ib_ = iaa + 1 < a.fs.nva ? iaa + 1 : a.fs.nva - 1;
+    const long long cc = ca < inner - 2 ? ca : inner - 2;
+    const T* lp = g.lp + d.o * g.pslab;
+    cf.saa = a.fs.s_a[ia];
+    cf.sab = a.fs.s_a[ib_];
+    // (loads without a branch: a missing table reads entry 0 of another and is zeroed where used)
+    cf.sb = a.fs.s_b ? a.fs.s_b[d.ib] : a.fs.s_a[0];
+    cf.pa0 = lp[cc];
+    cf.pa1 = lp[g.pplane + cc];
+    cf.pb0 = lp[cc + 1];
+    cf.pb1 = lp[g.pplane + cc + 1];
+    cf.wla = g.wa[ia];
+    cf.wlb = g.wa[ib_];
+    cf.wbl = has_b ? g.wb[d.ib] : g.wa[0];
+  };
+
+  // Generate the scaled spectrum of tile d into LDS and pre-weight it for the inverse
+  // transform, from the prefetched registers
+  auto generate = [&](const TileAt& d) {
     // thread index through an empty asm: tile-invariant addresses stay inside the loop
     int tid = threadIdx.x;
     asm volatile("" : "+v"(tid));
     const int q = tid & (NSEQ - 1);
     const int mi = tid >> LGQ;
-    const long long o = cur.o;  // slab (instance of a batch)
-    const long long c0 = cur.c0;
+    const long long o = d.o;  // slab (instance of a batch)
+    const long long c0 = d.c0;
     // ---- per pair: column decode, eigenvalue coefficients (divided by the scale), face values
-    const long long ib = cur.ib;  // one row per tile
+    const long long ib = d.ib;  // one row per tile
     const long long ca = c0 + 2 * q;
     const int iaa = (int)(ca - ib * a.fs.na), iab = iaa + 1;
     const bool va = ca < inner && iaa < a.fs.nva, vb = ca + 1 < inner && iab < a.fs.nva;
-    const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
+    const T sb = a.fs.s_b ? cf.sb : T(0);
     const T isc = T(1) / a.fs.scale;
     T Aa = 1, Ba = 0, Ab = 1, Bb = 0;
     if (va) {
-      const T sa = a.fs.s_a[iaa];
+      const T sa = cf.saa;
       Aa = (sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb)) * isc;
       Ba = (T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt) * isc;
     }
     if (vb) {
-      const T sa = a.fs.s_a[iab];
+      const T sa = cf.sab;
       Ab = (sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb)) * isc;
       Bb = (T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt) * isc;
     }
     // z-face pair as its sum (odd mode) or difference (even mode)
-    const T* lp = g.lp + o * g.pslab;
     const T sg = modd ? T(1) : T(-1);
-    T pa = 0, pb = 0, wla = 0, wlb = 0;
-    if (va) {
-      pa = lp[ca] + sg * lp[g.pplane + ca];
-      wla = g.wa[iaa];
-    }
-    if (vb) {
-      pb = lp[ca + 1] + sg * lp[g.pplane + ca + 1];
-      wlb = g.wa[iab];
-    }
-    const T wbl = has_b ? g.wb[ib] : T(0);
+    const T pa = va ? cf.pa0 + sg * cf.pa1 : T(0), pb = vb ? cf.pb0 + sg * cf.pb1 : T(0);
+    const T wla = va ? cf.wla : T(0), wlb = vb ? cf.wlb : T(0);
+    const T wbl = has_b ? cf.wbl : T(0);
     const T* la = g.la + o * g.aslab + ib * g.arow;
     if constexpr (XLDS) {
 #pragma unroll
@@ -777,35 +823,33 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       gb = vb ? gb * recip(Ab + Bb * st) : T(0);
     };
     cx<T>* sq = lds + q * LDQ;
-    {
-      cx<T>* lo = sq + pad(1 + mi);
-      cx<T>* hi = sq + pad(N - 1 - mi);
+    cx<T>* lo = sq + pad(1 + mi);
+    cx<T>* hi = sq + pad(N - 1 - mi);
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int m = 1 + mi + u * TPS;
-        cx<T>* plo = LIN ? lo + poff(u * TPS) : sq + pad(m);
-        cx<T>* phi = LIN ? hi - poff(u * TPS) : sq + pad(N - m);
-        T xa, xb;
-        gen_at(m, ylo[u], xa, xb);
-        if (u == U - 1 && m == HN) {  // the middle position pairs with itself: 2 z
-          cx<T> v;
-          v.x = T(2) * xa;
-          v.y = T(2) * xb;
-          *plo = v;
-        } else {
-          T ya, yb;
-          gen_at(N - m, yhi[u], ya, yb);
-          const T w = TWL ? snl[m] : a.sn[m];
-          const T sx = w * (xa + ya), sy = w * (xb + yb);
-          const T dx = T(0.5) * (xa - ya), dy = T(0.5) * (xb - yb);
-          cx<T> o1, o2;
-          o1.x = sx + dx;
-          o1.y = sy + dy;
-          o2.x = sx - dx;
-          o2.y = sy - dy;
-          *plo = o1;
-          *phi = o2;
-        }
+    for (int u = 0; u < U; ++u) {
+      const int m = 1 + mi + u * TPS;
+      cx<T>* plo = LIN ? lo + poff(u * TPS) : sq + pad(m);
+      cx<T>* phi = LIN ? hi - poff(u * TPS) : sq + pad(N - m);
+      T xa, xb;
+      gen_at(m, ylo[u], xa, xb);
+      if (u == U - 1 && m == HN) {  // the middle position pairs with itself: 2 z
+        cx<T> v;
+        v.x = T(2) * xa;
+        v.y = T(2) * xb;
+        *plo = v;
+      } else {
+        T ya, yb;
+        gen_at(N - m, yhi[u], ya, yb);
+        const T w = TWL ? snl[m] : a.sn[m];
+        const T sx = w * (xa + ya), sy = w * (xb + yb);
+        const T dx = T(0.5) * (xa - ya), dy = T(0.5) * (xb - yb);
+        cx<T> o1, o2;
+        o1.x = sx + dx;
+        o1.y = sy + dy;
+        o2.x = sx - dx;
+        o2.y = sy - dy;
+        *plo = o1;
+        *phi = o2;
       }
     }
     if (tid < NSEQ) {
@@ -814,11 +858,32 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       z.y = T(0);
       lds[tid * LDQ] = z;
     }
-    __syncthreads();
+  };
+
+  // Loop order: the tile's spectrum is generated at the end of the previous iteration,
+  // after that tile's stores, from registers prefetched before its transform; with whole
+  // tiles (FULL) the stores have no branch, so the wait for the prefetched registers there
+  // leaves the stores in flight (memory operations complete in issue order).
+  long long tile = blockIdx.x;
+  TileAt cur = at(tile);
+  if (tile < ntiles) {
+    prefetch(cur);
+    cload(cur);
+    generate(cur);
+  }
+  for (; tile < ntiles; tile += gridDim.x) {
+    int tid = threadIdx.x;
+    asm volatile("" : "+v"(tid));
+    const int q = tid & (NSEQ - 1);
+    const int mi = tid >> LGQ;
+    __syncthreads();  // the tile's generated sequences in LDS
     // the next tile's face data is in flight during the transform below
     const long long nxt = tile + gridDim.x;
     const TileAt nd = at(nxt);
-    if (nxt < ntiles) prefetch(nd);
+    if (nxt < ntiles) {
+      prefetch(nd);
+      cload(nd);
+    }
     // ---- inverse transform along the pass axis
     const int s = tid / TPS;
     const int ts = tid - s * TPS;
@@ -831,13 +896,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
     __syncthreads();  // the store reads other pairs' sequences
     // ---- store (uniform row bases, fixed per-lane byte offsets)
-    if (c0 + 2 * q < inner) {
+    if (FULL || cur.c0 + 2 * q < inner) {
       const long long orowb = inner * (long long)sizeof(T);
-      const SBase dst(a.out + o * (long long)L * inner + c0);
+      const SBase dst(a.out + cur.o * (long long)L * inner + cur.c0);
       unsigned vs = (unsigned)((2 * q + (long long)mi * inner) * (long long)sizeof(T));
       asm volatile("" : "+v"(vs));
+      const cx<T>* sq = lds + q * LDQ;
       const cx<T>* lo = sq + pad(1 + mi);
-      if (a.ntst) {
+      if constexpr (NT) {
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
           const int m = 1 + mi + k * TPS;
@@ -854,6 +920,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
       }
     }
     __syncthreads();  // the next tile overwrites LDS
+    if (nxt < ntiles) generate(nd);
     cur = nd;
   }
 }
@@ -863,12 +930,14 @@ template <typename T, int N> struct GenPipeLaunch {
   static constexpr int TPS = N / PipePlan<N>::PPT;
   static constexpr int THREADS = NSEQ * TPS;
   static constexpr size_t LDS = GenShape<T, N, NSEQ>::LDS;
+  // the non-temporal form exists where a volume can exceed the caches (N >= 384)
+  static constexpr bool HAS_NT = N >= 384;
 
-  static int resident() {
+  template <bool NT> static int resident() {
     static std::once_flag once;
     static int r = 0;
     std::call_once(once, [] {
-      const void* fn = reinterpret_cast<const void*>(&k_gen_pipe<T, N, NSEQ>);
+      const void* fn = reinterpret_cast<const void*>(&k_gen_pipe<T, N, NSEQ, NT && HAS_NT>);
       (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
       int dev = 0, cus = 0, per = 0;
       if (hipGetDevice(&dev) == hipSuccess &&
@@ -887,7 +956,11 @@ template <typename T, int N> struct GenPipeLaunch {
     if (a.g.lb && ((a.g.bpitch & 1) || (a.g.bplane & 1) || (a.g.bslab & 1))) return ST_UNSUPPORTED;
     if ((double)(TPS + 1) * (double)a.inner * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
     if (a.g.lb && (double)(TPS + 1) * (double)a.g.bpitch * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
-    const int res = resident();
+    // the coefficient prefetch clamps its column indices into the tables (nva >= 1 entries)
+    if (a.fs.nva < 1 || a.inner < 2) return ST_UNSUPPORTED;
+    const bool nt = HAS_NT && a.inner % (2 * NSEQ) == 0 &&
+                    (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
+    const int res = nt ? resident<true>() : resident<false>();
     if (res <= 0) return ST_UNSUPPORTED;
     a.ntile_inner = (a.inner + 2LL * NSEQ - 1) / (2LL * NSEQ);
     const long long ntiles = a.outer * a.ntile_inner;
@@ -899,8 +972,10 @@ template <typename T, int N> struct GenPipeLaunch {
     T* lb = const_cast<T*>(a.g.lb);
     if (lb) TRY_ST(face_pm<T>(lb, a.g.bplane, a.outer > 1 ? a.g.bslab : 0, a.g.bplane, a.outer, st));
     const long long grid = ntiles < res ? ntiles : res;
-    a.ntst = (double)a.outer * (double)a.inner * (double)(N - 1) * sizeof(T) >= NT_STORE_MIN_BYTES;
-    hipLaunchKernelGGL((k_gen_pipe<T, N, NSEQ>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    if (nt)
+      hipLaunchKernelGGL((k_gen_pipe<T, N, NSEQ, HAS_NT>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
+    else
+      hipLaunchKernelGGL((k_gen_pipe<T, N, NSEQ, false>), dim3((unsigned)grid), dim3(THREADS), LDS, st, a);
     AHOC_HIP_TRY(hipGetLastError());
     return ST_OK;
   }
