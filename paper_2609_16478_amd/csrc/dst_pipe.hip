@@ -69,6 +69,12 @@ template <typename T, int N> constexpr size_t pipe_tab_bytes() {
   return (size_t)N * sizeof(cx<T>) + (((size_t)(N / 2 + 1) * sizeof(T) + 15) / 16) * 16;
 }
 constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+// A load through a pointer chosen between two kernel arguments, kept in the global address
+// space (a generic pointer would be a flat load, which the compiler waits for with every
+// memory operation in flight)
+template <typename T> __device__ __forceinline__ T gload(const T* p) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) T*>(reinterpret_cast<unsigned long long>(p));
+}
 // MODE 3 data after the tile: the face row (2 (N - 1) values), then the per-position table
 // (4 (N - 1) values) where it fits; the transform tables take precedence over the latter
 template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_face_bytes() {
@@ -182,13 +188,13 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   auto xload = [&](const TileAt& d) {
     if constexpr (MODE == 3) {
       const T* la = a.gn.la + d.o * a.gn.aslab + (long long)d.ib * a.gn.arow;
+      // (without a branch: positions past the row read its last one, unused)
 #pragma unroll
       for (int r = 0; r < XR; ++r) {
-        const int j = (int)threadIdx.x + r * NSEQ * TPS;
-        if (j < L) {
-          xf[0][r] = la[(long long)j * a.gn.apitch];
-          xf[1][r] = la[a.gn.aplane + (long long)j * a.gn.apitch];
-        }
+        const int j0 = (int)threadIdx.x + r * NSEQ * TPS;
+        const int j = j0 < L ? j0 : L - 1;
+        xf[0][r] = la[(long long)j * a.gn.apitch];
+        xf[1][r] = la[a.gn.aplane + (long long)j * a.gn.apitch];
       }
     }
   };
@@ -316,6 +322,38 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     }
   };
 
+  // MODE 3: the pair's per-tile coefficients (column sines, row sine, z-face pair at both
+  // columns, face-layer weights), loaded without branches (indices clamped into the tables,
+  // a missing table read at another's entry 0; the validity flags select where they are
+  // used) at the top of the tile, before the next tile's prefetch: a wait for them does not
+  // wait for the prefetch
+  struct Coef3 {
+    T saa, sab, sb, pa0, pa1, pb0, pb1, wla, wlb, wbl;
+  };
+  [[maybe_unused]] Coef3 c3;
+  auto cload3 = [&](const TileAt& d) {
+    if constexpr (MODE == 3) {
+      const long long ca = d.c0 + 2 * s;
+      const long long iaa = ca - (long long)d.ib * a.fs.na;
+      const int ia = (int)(iaa < a.fs.nva ? iaa : a.fs.nva - 1);
+      const int ia1 = (int)(iaa + 1 < a.fs.nva ? iaa + 1 : a.fs.nva - 1);
+      const long long cc = ca < inner - 2 ? ca : inner - 2;
+      const T* lp = a.gn.lp + d.o * a.gn.pslab;
+      const T* sbp = a.fs.s_b ? a.fs.s_b + d.ib : a.fs.s_a;
+      const T* wbp = a.gn.lb ? a.gn.wb + d.ib : a.gn.wa;
+      c3.saa = a.fs.s_a[ia];
+      c3.sab = a.fs.s_a[ia1];
+      c3.sb = gload(sbp);
+      c3.pa0 = lp[cc];
+      c3.pa1 = lp[a.gn.pplane + cc];
+      c3.pb0 = lp[cc + 1];
+      c3.pb1 = lp[a.gn.pplane + cc + 1];
+      c3.wla = a.gn.wa[ia];
+      c3.wlb = a.gn.wa[ia1];
+      c3.wbl = gload(wbp);
+    }
+  };
+
   long long tile = blockIdx.x;
   TileAt cur = at(tile);
   if (tile < ntiles) {
@@ -328,15 +366,16 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     remap();
     const cx<T>* tw = TWL ? twl : a.tw;
     __syncthreads();  // the tile's sequences (and face row) in LDS
+    cload3(cur);
     const long long nxt = tile + gridDim.x;
-    const TileAt nd = at(nxt);
     // the next tile is in flight during the transform below (with two transforms, during
-    // the second one only: the prefetched registers are not live across both)
+    // the second one only: the prefetched registers are not live across both).  The last
+    // tile of a work-group prefetches itself (unused): a prefetch without a branch, so that
+    // waits for loads issued before it are not taken as waits for it
+    const TileAt nd = at(nxt < ntiles ? nxt : tile);
     if constexpr (MODE != 2) {
-      if (nxt < ntiles) {
-        load(nd);
-        xload(nd);
-      }
+      load(nd);
+      xload(nd);
     }
 
     cx<T> A, B;
@@ -365,13 +404,24 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         Ao += a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb;  // v-equation shift (zero otherwise)
         Bo += a.fs.kt;
       };
-      coef(ca, A.x, B.x);
-      coef(cb, A.y, B.y);
+      if constexpr (MODE == 3) {
+        const long long iaa = ca - (long long)cur.ib * a.fs.na;
+        const T sb = a.fs.s_b ? c3.sb : T(0);
+        auto coef3 = [&](bool v, T sa, T& Ao, T& Bo) {
+          Ao = v ? sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb) : T(1);
+          Bo = v ? T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt : T(0);
+        };
+        coef3(ca < inner && iaa < a.fs.nva, c3.saa, A.x, B.x);
+        coef3(cb < inner && iaa + 1 < a.fs.nva, c3.sab, A.y, B.y);
+      } else {
+        coef(ca, A.x, B.x);
+        coef(cb, A.y, B.y);
+      }
       // MODE 3 scales in the face loop below, after adding the face-layer term
       if constexpr (MODE == 3) post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
       else post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
       if constexpr (MODE == 2) {
-        if (nxt < ntiles) load(nd);
+        load(nd);
         pre_lds<T, N, PL>(seq, ts, TWL ? snl : a.sn);
         fft<T, N, PL>(seq, ts, tw);
         A.x = A.y = T(1);
@@ -400,63 +450,90 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         // every position of this thread has the parity of 1 + ts (TPS is even)
         const bool modd = ((1 + ts) & 1) != 0;
         // z-face pair as its sum (odd mode) or difference (even mode)
-        const T* lp = a.gn.lp + o * a.gn.pslab;
         const T sg = modd ? T(1) : T(-1);
-        if (va) {
-          ga0 = lp[ca] + sg * lp[a.gn.pplane + ca];
-          wla = a.gn.wa[iaa];
-        }
-        if (vb) {
-          gb0 = lp[cb] + sg * lp[a.gn.pplane + cb];
-          wlb = a.gn.wa[iaa + 1];
-        }
+        ga0 = va ? c3.pa0 + sg * c3.pa1 : T(0);
+        gb0 = vb ? c3.pb0 + sg * c3.pb1 : T(0);
+        wla = va ? c3.wla : T(0);
+        wlb = vb ? c3.wlb : T(0);
+        // y faces: without them the loads below read the per-position table (any array of at
+        // least N values) with weight zero, so that the face loop has no branch
         if (a.gn.lb) {
-          wbl = a.gn.wb[ib];
+          wbl = c3.wbl;
           ybase = a.gn.lb + o * a.gn.bslab + ((ib & 1) ? a.gn.bplane : 0);
           yoff = (unsigned)((iaa * a.gn.bpitch + ts) * (long long)sizeof(T));
           ystep = (unsigned)(a.gn.bpitch * (long long)sizeof(T));
+        } else {
+          wbl = T(0);
+          ybase = a.gn.ptab;
+          yoff = (unsigned)(ts * (int)sizeof(T));
+          ystep = 0;
         }
-        const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
-        if (va) Ca = a.fs.mc0 + a.fs.mca * a.fs.s_a[iaa] + a.fs.mcb * sb;
-        if (vb) Cb = a.fs.mc0 + a.fs.mca * a.fs.s_a[iaa + 1] + a.fs.mcb * sb;
+        const T sb = a.fs.s_b ? c3.sb : T(0);
+        Ca = va ? a.fs.mc0 + a.fs.mca * c3.saa + a.fs.mcb * sb : T(1);
+        Cb = vb ? a.fs.mc0 + a.fs.mca * c3.sab + a.fs.mcb * sb : T(1);
         D = a.fs.mct;
       }
-      // MODE 3: four positions at a time (the next tile's prefetch is live here; unrolled,
-      // the face loads of all positions would be hoisted and spill registers)
-      constexpr int FLU = MODE == 3 ? 4 : PPT;
-#pragma unroll FLU
+      if constexpr (MODE == 3) {
+        // groups of G positions: the group's table and y-face loads are all issued before
+        // its arithmetic (a scheduling barrier keeps the compiler from interleaving them,
+        // which it otherwise does to save registers, one load round trip per position).
+        // Positions past the transform (the last thread's last one) read position N - 1.
+        constexpr int G = N >= 2048 ? 2 : 4;  // (longer transforms hold more registers)
+        static_assert(PPT % G == 0, "whole groups of positions");
+        const cx<T>* ptb = PTL ? ptl : reinterpret_cast<const cx<T>*>(a.gn.ptab);
+        const SBase ys(ybase);  // byte offsets below 2^32 (checked at launch)
+#pragma unroll 1
+        for (int i0 = 0; i0 < PPT; i0 += G) {
+          cx<T> t0[G], t1[G];
+          T y0[G], y1[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int m = 1 + ts + (i0 + g) * TPS;
+            const int mc = m < N ? m : N - 1;
+            t0[g] = ptb[2 * (mc - 1)];
+            t1[g] = ptb[2 * (mc - 1) + 1];
+            const unsigned off = yoff + (unsigned)((mc - 1 - ts) * (int)sizeof(T));
+            y0[g] = ys.template ld<T>(off);
+            y1[g] = ys.template ld<T>(off + ystep);
+          }
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const int i = i0 + g;
+            const int m = 1 + ts + i * TPS;
+            if (i < PPT - 1 || m < N) {
+              cx<T>* pv = LIN ? seq + pad(1 + ts) + poff(i * TPS) : seq + pad(m);
+              cx<T> v = *pv;
+              const T st = t0[g].x, wpl = t0[g].y;
+              const cx<T> xv = xrow[m - 1];
+              const T ga = ga0 * wpl + xv.x * wla + y0[g] * wbl;
+              const T gb = gb0 * wpl + xv.y * wlb + y1[g] * wbl;
+              v.x = (v.x * (Ca + D * st) + (va ? ga : T(0))) * (a.fs.scale * recip(A.x + B.x * st));
+              v.y = (v.y * (Cb + D * st) + (vb ? gb : T(0))) * (a.fs.scale * recip(A.y + B.y * st));
+              *pv = v;
+              const T wl = t1[g].x, wh = t1[g].y;
+              la += v.x * wl;
+              ha += v.x * wh;
+              lb += v.y * wl;
+              hb += v.y * wh;
+            }
+          }
+          __builtin_amdgcn_sched_barrier(0);  // (the next group's loads after this one)
+        }
+      } else {
+#pragma unroll
       for (int i = 0; i < PPT; ++i) {
         const int m = 1 + ts + i * TPS;
         if (i < PPT - 1 || m < N) {
           cx<T>* pv = LIN ? seq + pad(1 + ts) + poff(i * TPS) : seq + pad(m);
-          cx<T> v = *pv;
-          [[maybe_unused]] T wl3 = 0, wh3 = 0;
-          if constexpr (MODE == 3) {
-            const cx<T>* pt = (PTL ? ptl : reinterpret_cast<const cx<T>*>(a.gn.ptab)) + 2 * (m - 1);
-            const cx<T> t0 = pt[0], t1 = pt[1];
-            const T st = t0.x, wpl = t0.y;
-            wl3 = t1.x;
-            wh3 = t1.y;
-            const cx<T> xv = xrow[m - 1];
-            T ga = ga0 * wpl + xv.x * wla;
-            T gb = gb0 * wpl + xv.y * wlb;
-            if (ybase) {
-              // byte offsets below 2^32 (checked at launch)
-              const SBase ys(ybase);
-              const unsigned off = yoff + (unsigned)(i * TPS * (int)sizeof(T));
-              ga += ys.template ld<T>(off) * wbl;
-              gb += ys.template ld<T>(off + ystep) * wbl;
-            }
-            v.x = (v.x * (Ca + D * st) + (va ? ga : T(0))) * (a.fs.scale * recip(A.x + B.x * st));
-            v.y = (v.y * (Cb + D * st) + (vb ? gb : T(0))) * (a.fs.scale * recip(A.y + B.y * st));
-            *pv = v;
-          }
-          const T wl = MODE == 3 ? wl3 : a.fc.w[m - 1], wh = MODE == 3 ? wh3 : a.fc.w[L + m - 1];
+          const cx<T> v = *pv;
+          const T wl = a.fc.w[m - 1], wh = a.fc.w[L + m - 1];
           la += v.x * wl;
           ha += v.x * wh;
           lb += v.y * wl;
           hb += v.y * wh;
         }
+      }
       }
       seg_sum4<T, TPS>(la, ha, lb, hb, tot, ts);
       if (ts == 0) {
@@ -735,14 +812,14 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     cf.saa = a.fs.s_a[ia];
     cf.sab = a.fs.s_a[ib_];
     // (loads without a branch: a missing table reads entry 0 of another and is zeroed where used)
-    cf.sb = a.fs.s_b ? a.fs.s_b[d.ib] : a.fs.s_a[0];
+    cf.sb = gload(a.fs.s_b ? a.fs.s_b + d.ib : a.fs.s_a);
     cf.pa0 = lp[cc];
     cf.pa1 = lp[g.pplane + cc];
     cf.pb0 = lp[cc + 1];
     cf.pb1 = lp[g.pplane + cc + 1];
     cf.wla = g.wa[ia];
     cf.wlb = g.wa[ib_];
-    cf.wbl = has_b ? g.wb[d.ib] : g.wa[0];
+    cf.wbl = gload(has_b ? g.wb + d.ib : g.wa);
   };
 
   // Generate the scaled spectrum of tile d into LDS and pre-weight it for the inverse
@@ -877,13 +954,12 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     const int q = tid & (NSEQ - 1);
     const int mi = tid >> LGQ;
     __syncthreads();  // the tile's generated sequences in LDS
-    // the next tile's face data is in flight during the transform below
+    // the next tile's face data is in flight during the transform below (the last tile of
+    // a work-group prefetches itself, unused: no branch around the prefetch)
     const long long nxt = tile + gridDim.x;
-    const TileAt nd = at(nxt);
-    if (nxt < ntiles) {
-      prefetch(nd);
-      cload(nd);
-    }
+    const TileAt nd = at(nxt < ntiles ? nxt : tile);
+    prefetch(nd);
+    cload(nd);
     // ---- inverse transform along the pass axis
     const int s = tid / TPS;
     const int ts = tid - s * TPS;
