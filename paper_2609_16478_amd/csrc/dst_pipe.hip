@@ -60,15 +60,23 @@ template <typename T, int N, int NSEQ> constexpr size_t pipe_tile_bytes() {
   constexpr int TPS = N / PipePlan<N>::PPT;
   return (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
 }
-// The transform's tile-invariant tables (twiddles exp(-2 pi i k / N), k < N, and the
-// pre-weighting sines sin(pi m / N), m <= N/2) in LDS after everything else, where it has
-// room.  Read from global memory, they would be loads issued after the next tile's prefetch
-// (and after the previous tile's stores), and a wavefront's memory operations complete in
-// issue order: the first wait for a table value would also wait for the whole prefetch.
-template <typename T, int N> constexpr size_t pipe_tab_bytes() {
-  return (size_t)N * sizeof(cx<T>) + (((size_t)(N / 2 + 1) * sizeof(T) + 15) / 16) * 16;
-}
 constexpr size_t align16(size_t b) { return (b + 15) / 16 * 16; }
+// Twiddles a transform reads: stage 2 (radix R1 over blocks of R0) reads exp(-2 pi i k / N) at
+// r k N / (R0 R1), stage 3 (radix R2 over blocks of R0 R1) at r k, r < R, k < the block length
+template <int N> constexpr int pipe_ntw() {
+  using P = PipePlan<N>;
+  int m = (P::R1 - 1) * (P::R0 - 1) * (N / (P::R0 * P::R1));
+  if (P::S == 3 && (P::R2 - 1) * (P::R0 * P::R1 - 1) > m) m = (P::R2 - 1) * (P::R0 * P::R1 - 1);
+  return (m + 2) & ~1;  // (entries 0..m, rounded to an even count)
+}
+// The transform's tile-invariant tables (those twiddles, and the pre-weighting sines
+// sin(pi m / N), m <= N/2) in LDS after everything else, where it has room.  Read from global
+// memory, they would be loads issued after the next tile's prefetch (and after the previous
+// tile's stores), and a wavefront's memory operations complete in issue order: the first wait
+// for a table value would also wait for the whole prefetch.
+template <typename T, int N> constexpr size_t pipe_tab_bytes() {
+  return align16((size_t)pipe_ntw<N>() * sizeof(cx<T>)) + align16((size_t)(N / 2 + 1) * sizeof(T));
+}
 // A load through a pointer chosen between two kernel arguments, kept in the global address
 // space (a generic pointer would be a flat load, which the compiler waits for with every
 // memory operation in flight)
@@ -94,9 +102,24 @@ template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_tab_off()
   return align16(pipe_tile_bytes<T, N, NSEQ>() + pipe_face_bytes<T, N, NSEQ, MODE>() +
                  (MODE == 3 && pipe_ptab_lds<T, N, NSEQ>() ? 4 * (size_t)(N - 1) * sizeof(T) : 0));
 }
+// MODES 1 and 2, after the transform tables where they fit: the eigenvalue sines of the pass
+// axis (N - 1 values), then (MODE 1) the face-sum weights (2 (N - 1) values)
+template <typename T, int N, int NSEQ, int MODE> constexpr bool pipe_stab_lds() {
+  return (MODE == 1 || MODE == 2) && pipe_tab_lds<T, N, NSEQ, MODE>() &&
+         pipe_tab_off<T, N, NSEQ, MODE>() + pipe_tab_bytes<T, N>() + align16((size_t)(N - 1) * sizeof(T)) <=
+             160 * 1024;
+}
+template <typename T, int N, int NSEQ, int MODE> constexpr bool pipe_wtab_lds() {
+  return MODE == 1 && pipe_stab_lds<T, N, NSEQ, MODE>() &&
+         pipe_tab_off<T, N, NSEQ, MODE>() + pipe_tab_bytes<T, N>() + align16((size_t)(N - 1) * sizeof(T)) +
+                 align16(2 * (size_t)(N - 1) * sizeof(T)) <=
+             160 * 1024;
+}
 template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_lds_bytes() {
   return pipe_tab_lds<T, N, NSEQ, MODE>()
-             ? pipe_tab_off<T, N, NSEQ, MODE>() + pipe_tab_bytes<T, N>()
+             ? pipe_tab_off<T, N, NSEQ, MODE>() + pipe_tab_bytes<T, N>() +
+                   (pipe_stab_lds<T, N, NSEQ, MODE>() ? align16((size_t)(N - 1) * sizeof(T)) : 0) +
+                   (pipe_wtab_lds<T, N, NSEQ, MODE>() ? align16(2 * (size_t)(N - 1) * sizeof(T)) : 0)
              : pipe_tile_bytes<T, N, NSEQ>() + pipe_face_bytes<T, N, NSEQ, MODE>() +
                    (MODE == 3 && pipe_ptab_lds<T, N, NSEQ>() ? 4 * (size_t)(N - 1) * sizeof(T) : 0);
 }
@@ -176,13 +199,24 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     for (int j = threadIdx.x; j < 2 * L; j += NSEQ * TPS) ptl[j] = pg[j];
   }
   constexpr bool TWL = pipe_tab_lds<T, N, NSEQ, MODE>();
+  constexpr bool STL = pipe_stab_lds<T, N, NSEQ, MODE>();
+  constexpr bool WTL = pipe_wtab_lds<T, N, NSEQ, MODE>();
+  constexpr int NTW = pipe_ntw<N>();
   cx<T>* twl = reinterpret_cast<cx<T>*>(smem + pipe_tab_off<T, N, NSEQ, MODE>());
-  T* snl = reinterpret_cast<T*>(twl + N);
+  T* snl = reinterpret_cast<T*>(smem + pipe_tab_off<T, N, NSEQ, MODE>() + align16((size_t)NTW * sizeof(cx<T>)));
+  T* stl = reinterpret_cast<T*>(smem + pipe_tab_off<T, N, NSEQ, MODE>() + pipe_tab_bytes<T, N>());
+  T* wtl = stl + align16((size_t)L * sizeof(T)) / sizeof(T);
   if constexpr (TWL) {
-    for (int j = threadIdx.x; j < N; j += NSEQ * TPS) twl[j] = a.tw[j];
+    for (int j = threadIdx.x; j < NTW; j += NSEQ * TPS) twl[j] = a.tw[j];
     for (int j = threadIdx.x; j <= HN; j += NSEQ * TPS) snl[j] = a.sn[j];
+    if constexpr (STL)
+      for (int j = threadIdx.x; j < L; j += NSEQ * TPS) stl[j] = a.fs.s_this[j];
+    if constexpr (WTL)
+      for (int j = threadIdx.x; j < 2 * L; j += NSEQ * TPS) wtl[j] = a.fc.w[j];
     __syncthreads();
   }
+  const T* s_tab = STL ? stl : a.fs.s_this;
+  const T* w_tab = WTL ? wtl : a.fc.w;
   constexpr int XR = MODE == 3 ? (L + NSEQ * TPS - 1) / (NSEQ * TPS) : 1;
   T xf[2][XR];
   auto xload = [&](const TileAt& d) {
@@ -354,6 +388,27 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     }
   };
 
+  // MODES 1 and 2: the pair's column and row sines, loaded the same way (a tile may span two
+  // rows of the column decode here)
+  struct Coef12 {
+    T saa, sab, sba, sbb;
+  };
+  [[maybe_unused]] Coef12 c12;
+  auto cload12 = [&](const TileAt& d) {
+    if constexpr (MODE == 1 || MODE == 2) {
+      const long long ca = d.c0 + 2 * s;
+      auto one = [&](long long col, T& sa, T& sb) {
+        const unsigned cc = (unsigned)(col < inner ? col : inner - 1);
+        const unsigned ib = cc / (unsigned)a.fs.na;
+        const unsigned ia = cc - ib * (unsigned)a.fs.na;
+        sa = a.fs.s_a[ia < (unsigned)a.fs.nva ? ia : (unsigned)a.fs.nva - 1];
+        sb = gload(a.fs.s_b ? a.fs.s_b + ib : a.fs.s_a);
+      };
+      one(ca, c12.saa, c12.sba);
+      one(ca + 1, c12.sab, c12.sbb);
+    }
+  };
+
   long long tile = blockIdx.x;
   TileAt cur = at(tile);
   if (tile < ntiles) {
@@ -367,6 +422,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
     const cx<T>* tw = TWL ? twl : a.tw;
     __syncthreads();  // the tile's sequences (and face row) in LDS
     cload3(cur);
+    cload12(cur);
     const long long nxt = tile + gridDim.x;
     // the next tile is in flight during the transform below (with two transforms, during
     // the second one only: the prefetched registers are not live across both).  The last
@@ -389,21 +445,6 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
       const long long o = cur.o;
       const long long c0 = cur.c0;
       const long long ca = c0 + 2 * s, cb = ca + 1;
-      auto coef = [&](long long col, T& Ao, T& Bo) {
-        const unsigned ib = (unsigned)col / (unsigned)a.fs.na;  // col < inner < 2^31
-        const long long ia = col - (long long)ib * a.fs.na;
-        if (col >= inner || ia >= a.fs.nva) {
-          Ao = 1;
-          Bo = 0;
-          return;
-        }
-        const T sa = a.fs.s_a[ia];
-        const T sb = a.fs.s_b ? a.fs.s_b[ib] : T(0);
-        Ao = sa + sb + a.fs.c_ab * sa * sb;
-        Bo = T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb;
-        Ao += a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb;  // v-equation shift (zero otherwise)
-        Bo += a.fs.kt;
-      };
       if constexpr (MODE == 3) {
         const long long iaa = ca - (long long)cur.ib * a.fs.na;
         const T sb = a.fs.s_b ? c3.sb : T(0);
@@ -414,12 +455,21 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         coef3(ca < inner && iaa < a.fs.nva, c3.saa, A.x, B.x);
         coef3(cb < inner && iaa + 1 < a.fs.nva, c3.sab, A.y, B.y);
       } else {
-        coef(ca, A.x, B.x);
-        coef(cb, A.y, B.y);
+        // the prefetched sines, selected by the column's validity
+        auto coef12 = [&](long long col, T sa, T sbv, T& Ao, T& Bo) {
+          const unsigned ib = (unsigned)col / (unsigned)a.fs.na;  // col < inner < 2^31
+          const long long ia = col - (long long)ib * a.fs.na;
+          const bool v = col < inner && ia < a.fs.nva;
+          const T sb = a.fs.s_b ? sbv : T(0);
+          Ao = v ? sa + sb + a.fs.c_ab * sa * sb + (a.fs.a0 + a.fs.ka * sa + a.fs.kb * sb) : T(1);
+          Bo = v ? T(1) + a.fs.c_ta * sa + a.fs.c_tb * sb + a.fs.kt : T(0);
+        };
+        coef12(ca, c12.saa, c12.sba, A.x, B.x);
+        coef12(cb, c12.sab, c12.sbb, A.y, B.y);
       }
       // MODE 3 scales in the face loop below, after adding the face-layer term
       if constexpr (MODE == 3) post<T, N, PL, false>(seq, tot, ts, A, B, nullptr, T(0));
-      else post<T, N, PL, true>(seq, tot, ts, A, B, a.fs.s_this, a.fs.scale);
+      else post<T, N, PL, true>(seq, tot, ts, A, B, s_tab, a.fs.scale);
       if constexpr (MODE == 2) {
         load(nd);
         pre_lds<T, N, PL>(seq, ts, TWL ? snl : a.sn);
@@ -527,7 +577,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         if (i < PPT - 1 || m < N) {
           cx<T>* pv = LIN ? seq + pad(1 + ts) + poff(i * TPS) : seq + pad(m);
           const cx<T> v = *pv;
-          const T wl = a.fc.w[m - 1], wh = a.fc.w[L + m - 1];
+          const T wl = w_tab[m - 1], wh = w_tab[L + m - 1];
           la += v.x * wl;
           ha += v.x * wh;
           lb += v.y * wl;
@@ -716,8 +766,9 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
   cx<T>* xrow = reinterpret_cast<cx<T>*>(smem + SH::TILE_B);  // (sum, difference) per position
   cx<T>* tab = xrow + L;                                       // (layer sine, eigenvalue) per position
   constexpr bool TWL = SH::TWL;
+  constexpr int NTW = pipe_ntw<N>();
   cx<T>* twl = reinterpret_cast<cx<T>*>(smem + SH::TAB_OFF);
-  T* snl = reinterpret_cast<T*>(twl + N);
+  T* snl = reinterpret_cast<T*>(smem + SH::TAB_OFF + align16((size_t)NTW * sizeof(cx<T>)));
   const long long inner = a.inner;
   const long long ntiles = a.outer * a.ntile_inner;
   const DstGen<T>& g = a.g;
@@ -739,7 +790,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
     }
   }
   if constexpr (TWL) {
-    for (int j = tid0; j < N; j += THREADS) twl[j] = a.tw[j];
+    for (int j = tid0; j < NTW; j += THREADS) twl[j] = a.tw[j];
     for (int j = tid0; j <= HN; j += THREADS) snl[j] = a.sn[j];
   }
 
