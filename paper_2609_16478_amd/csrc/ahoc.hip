@@ -103,6 +103,9 @@ struct ahoc_handle {
   ahoc_options opt;
   // FP64 problem data
   double* ia64 = nullptr;
+  // FP64 V of the V-solve with Q = 0 (the right-hand side's), kept for the recovery: V(Q) is
+  // that plus the homogeneous V-solve from Q (spectral FP64 operator, no triharmonic chain)
+  double* V0 = nullptr;
   double* af64 = nullptr;
   double* src_v = nullptr;
   double* src_u = nullptr;  // null when g_D = 0
@@ -669,7 +672,8 @@ template <typename T> int face_dst2(ahoc_handle* h, Prec<T>& P, hipStream_t st) 
 // layers of the lift, their 2-D spectra, then the slowest-axis pass generates the 3-D
 // spectrum, scales it and inverts along its axis; the other axes are inverted as usual.
 template <typename T>
-int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st, bool skip_x = false, bool lifted = false) {
+int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st, bool skip_x = false, bool lifted = false,
+                const T* addv = nullptr) {
   const Geom& g = h->g;
   if (!lifted) {  // (else the face layers are in Fx, Fy, Fz already)
     hipEvent_t e = tbegin(h, st);
@@ -714,11 +718,28 @@ int vsolve_spec(ahoc_handle* h, Prec<T>& P, const T* Q, hipStream_t st, bool ski
     tend(h, kind, ev, pass_bytes, st);
     return rc;
   };
-  if (g.dim == 3) {
-    TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, P.tile[1]));
-    if (!skip_x) TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.ni[1] * g.ni[2], 1, P.tile[0]));
-  } else if (!skip_x) {
-    TRY(run(AHOC_K_DST_ROWS, P.tb[0], (long long)g.nb * g.ni[1], 1, P.tile[0]));
+  if (g.dim == 3) TRY(run(AHOC_K_DST_STRIDED, P.tb[1], g.ni[2], g.px, P.tile[1]));
+  if (!skip_x) {
+    const long long rows = g.dim == 3 ? (long long)g.ni[1] * g.ni[2] : (long long)g.nb * g.ni[1];
+    if (addv) {
+      // V = addv + this solve: the addend enters the last row pass (FFT row kernel) or,
+      // where that kernel does not run, an axpy after the chosen pass
+      int rc = ST_UNSUPPORTED;
+      if (dst_get_variant() == 0 || dst_get_variant() == 5) {
+        hipEvent_t ev = tbegin(h, st);
+        rc = dst_rows_add_pass<T>(g.n[0], P.tb[0].tw, P.tb[0].sn, buf, buf, addv, rows, g.px, st);
+        tend(h, AHOC_K_DST_ROWS, ev, pass_bytes * 1.5, st);
+      }
+      if (rc == ST_UNSUPPORTED) {
+        TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, P.tile[0]));
+        if constexpr (std::is_same<T, double>::value) TRY(axpby(TA(g), 1.0, addv, 1.0, buf, st));
+        else return ST_UNSUPPORTED;
+      } else {
+        TRY(rc);
+      }
+    } else {
+      TRY(run(AHOC_K_DST_ROWS, P.tb[0], rows, 1, P.tile[0]));
+    }
   }
   return ST_OK;
 }
@@ -1529,6 +1550,9 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
     h->p64.spectral = false;
     h->p64.mspec = false;
   }
+  // the recovery's V-solve as the right-hand side's V (Q = 0) plus the homogeneous spectral
+  // V-solve from Q: one FP64 array more
+  if ((!mixed || schur_ir) && !h->tri && !h->cvar && h->p64.spectral) TRY(alloc_int(h, &h->V0, st));
   if (mixed) {
     h->p32.ia = ia32;
     h->p32.af = af32;
@@ -1853,6 +1877,28 @@ int zero_done(ahoc_handle* h, double* x, hipStream_t st) {
 
 // u: one output per instance; v, q only for a single instance (nb = 1).  s: nb stats.
 // With options.warm_start (single instance) q holds the initial guess on entry.
+// During a solve the right-hand side's V (the V-solve with Q = 0) is kept in h->V0: the work
+// array holding it and h->V0 trade places after the right-hand side and back when the solve
+// returns, so that the Krylov steps (and any graph captured from them) always see the same
+// work array.  The recovery's V-solve is then h->V0 plus the homogeneous spectral V-solve from
+// Q (generation, inverse y and x passes, h->V0 added by the last pass) instead of a Poisson
+// solve with the source.
+struct KeepV0 {
+  double*& a;
+  double*& b;
+  const bool on;
+  KeepV0(ahoc_handle* h, Prec<double>& P)
+      : a(P.bufA), b(h->V0), on(h->V0 != nullptr && P.spectral && !h->tri && !h->cvar) {
+    if (on) std::swap(a, b);
+  }
+  ~KeepV0() {
+    if (on) std::swap(a, b);
+  }
+};
+int vsolve_rec(ahoc_handle* h, Prec<double>& P, const double* Q, const KeepV0& k, hipStream_t st) {
+  return k.on ? vsolve_spec<double>(h, P, Q, st, false, false, h->V0) : vsolve<double>(h, P, Q, h->src_v, st);
+}
+
 int solve_fp64(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stats* s, hipStream_t st) {
   Prec<double>& P = h->p64;
   const Geom& g = h->g;
@@ -1861,12 +1907,13 @@ int solve_fp64(ahoc_handle* h, double* const* u, double* v, double* q, ahoc_stat
   const bool warm = h->opt.warm_start && q && g.nb == 1;
   if (warm) AHOC_HIP_TRY(hipMemcpyAsync(h->dq, q, sizeof(double) * g.nq, hipMemcpyDeviceToDevice, st));
   TRY(schur_rhs<double>(h, P, h->src_v, h->src_u, h->src_q, h->bvec, st));
+  const KeepV0 keep(h, P);
   TRY(gmres<double>(h, P, h->bvec, h->dq, h->opt.tol, h->opt.max_iters, gr, &mv, st, warm));
   if (h->tri) {
     TRY(tri_fields<double>(h, P, h->dq, h->src_v, h->src_u, h->src_t, st));
     TRY(write_u(h, P.bufA, u, st));
   } else {
-    TRY(vsolve<double>(h, P, h->dq, h->src_v, st));
+    TRY(vsolve_rec(h, P, h->dq, keep, st));
     TRY(usolve<double>(h, P, h->dq, h->src_u, st));
     TRY(write_u(h, P.bufB, u, st));
   }
@@ -1900,6 +1947,7 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
   const int nb = g.nb;
   int rc = 0;
   TRY(schur_rhs<double>(h, D, h->src_v, h->src_u, h->src_q, h->b64, st));
+  const KeepV0 keep(h, D);
   TRY(dot_dev(h, h->b64, h->b64, st, h->nrm));
   TRY(read_vec(h, h->nrm, 2 * nb, st));
   std::vector<double> bnorm(nb), relres(nb, 0.0);
@@ -1972,7 +2020,7 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
         TRY(tri_fields<double>(h, D, h->Q64, h->src_v, h->src_u, h->src_t, st));
         TRY(tri_gather<double>(h, D, h->Q64, h->src_q, h->R, st));
       } else {
-        TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+        TRY(vsolve_rec(h, D, h->Q64, keep, st));
         TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
         TRY(gather<double>(g, h->w, D.bufB, h->Q64, D.af, h->src_q, h->R, st));
       }
@@ -2005,7 +2053,7 @@ int solve_mixed_schur(ahoc_handle* h, double* const* u, double* v, double* q, ah
     if (h->tri) {
       TRY(tri_fields<double>(h, D, h->Q64, h->src_v, h->src_u, h->src_t, st));
     } else {
-      TRY(vsolve<double>(h, D, h->Q64, h->src_v, st));
+      TRY(vsolve_rec(h, D, h->Q64, keep, st));
       TRY(usolve<double>(h, D, h->Q64, h->src_u, st));
     }
   }

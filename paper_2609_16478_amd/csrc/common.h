@@ -230,6 +230,12 @@ template <typename T>
 int dst_rows_lift_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
                        const RowLift<T>& lf, hipStream_t st);
 
+// Row pass plus an addend: out_row = S in_row + add_row (add in the layout of out; in may
+// equal out).  ST_UNSUPPORTED where no row kernel exists for N or the shape.
+template <typename T>
+int dst_rows_add_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, const T* addv, long long nrows,
+                      long long pitch, hipStream_t st);
+
 // Two transforms of each row with a pointwise product between them (dst_rows.hip):
 // out_row = S (c_row .* (S in_row)), c nodal with the row of interior row
 // r = (j - 1) + p ni1 at c + ((p + kofs) nn1 + j) nn0 (position i at offset i); in may

@@ -40,13 +40,16 @@ template <int N> constexpr int rows_nseq() {
 // loading (the lift pass is not run): row r = (j - 1) + (k - 1) n_y' (3-D) or
 // (j - 1) + b n_y' (2-D, instance b) gets Lx[side] at its first and last position, and the
 // whole row of Ly[side] (Lz[side]) when it lies next to a y (z) face.  Layouts of face_lift.
-template <typename T, int N, bool NT, bool LIFT = false>
+// ADD: out_row = S in_row + add_row (add with the layout of out), the addend fetched after the
+// transform at the store positions.
+template <typename T, int N, bool NT, bool LIFT = false, bool ADD = false>
 __global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows(const T* __restrict__ in,
                                                                                 T* __restrict__ out,
                                                                                 const cx<T>* __restrict__ tw,
                                                                                 const T* __restrict__ sn,
                                                                                 long long nrows, long long pitch,
-                                                                                RowLift<T> lf = RowLift<T>{}) {
+                                                                                RowLift<T> lf = RowLift<T>{},
+                                                                                const T* __restrict__ addv = nullptr) {
   extern __shared__ __align__(16) unsigned char smem[];
   using PL = RPlan<N>;
   constexpr int PPT = PL::PPT;
@@ -161,6 +164,20 @@ __global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows
   fft<T, N, PL>(seq, t, tw);
   post<T, N, PL, false>(seq, tot, t, A, B, nullptr, T(0));
 
+  // ---- ADD: the addend at the store positions
+  [[maybe_unused]] T aa[PPT], ab[PPT];
+  if constexpr (ADD) {
+    const SBase asrc(addv + r0 * pitch);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+      const int m = 1 + t + k * TPS;
+      const bool in_n = k < PPT - 1 || m < N;
+      const unsigned e = (unsigned)((m - 1) * (int)sizeof(T));
+      aa[k] = (oka && in_n) ? ldr<T, NT>(asrc, oa + e) : T(0);
+      ab[k] = (okb && in_n) ? ldr<T, NT>(asrc, ob + e) : T(0);
+    }
+  }
+
   // ---- store positions m = 1 + t + k TPS
   const SBase dst(out + r0 * pitch);
   const cx<T>* lo = seq + pad(1 + t);
@@ -168,7 +185,11 @@ __global__ void __launch_bounds__(rows_nseq<N>()*(N / RPlan<N>::PPT)) k_dst_rows
   for (int k = 0; k < PPT; ++k) {
     const int m = 1 + t + k * TPS;
     if (k < PPT - 1 || m < N) {
-      const cx<T> v = LIN ? lo[poff(k * TPS)] : seq[pad(m)];
+      cx<T> v = LIN ? lo[poff(k * TPS)] : seq[pad(m)];
+      if constexpr (ADD) {
+        v.x += aa[k];
+        v.y += ab[k];
+      }
       const unsigned e = (unsigned)((m - 1) * (int)sizeof(T));
       if (oka) str_<T, NT>(dst, oa + e, v.x);
       if (okb) str_<T, NT>(dst, ob + e, v.y);
@@ -364,6 +385,27 @@ template <typename T, int N> int rows_lift_launch(const T* in, T* out, const cx<
   return ST_OK;
 }
 
+template <typename T, int N> int rows_add_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
+                                                 long long pitch, const T* addv, hipStream_t st) {
+  constexpr int TPS = N / RPlan<N>::PPT;
+  constexpr int NSEQ = rows_nseq<N>();
+  constexpr int THREADS = NSEQ * TPS;
+  constexpr size_t LDS = (size_t)(NSEQ * seq_stride<N>() + NSEQ * 2 * (TPS / 64 > 0 ? TPS / 64 : 1)) * sizeof(cx<T>);
+  if (THREADS % 64 != 0 || THREADS > 1024 || LDS > 64 * 1024) return ST_UNSUPPORTED;
+  if ((double)(2 * NSEQ) * (double)pitch * (double)sizeof(T) >= 4294967295.0) return ST_UNSUPPORTED;
+  const long long blocks = (nrows + 2 * NSEQ - 1) / (2 * NSEQ);
+  if (blocks <= 0) return ST_OK;
+  if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+  if (sizeof(T) == 4 && (double)nrows * (double)pitch * sizeof(T) >= NT_STORE_MIN_BYTES)
+    hipLaunchKernelGGL((k_dst_rows<T, N, true, false, true>), dim3((unsigned)blocks), dim3(THREADS), LDS, st, in, out,
+                       tw, sn, nrows, pitch, RowLift<T>{}, addv);
+  else
+    hipLaunchKernelGGL((k_dst_rows<T, N, false, false, true>), dim3((unsigned)blocks), dim3(THREADS), LDS, st, in,
+                       out, tw, sn, nrows, pitch, RowLift<T>{}, addv);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
 template <typename T, int N> int rows_launch(const T* in, T* out, const cx<T>* tw, const T* sn, long long nrows,
                                              long long pitch, hipStream_t st) {
   constexpr int TPS = N / RPlan<N>::PPT;
@@ -470,6 +512,24 @@ template int dst_rows_lift_pass<float>(int, const cx<float>*, const float*, cons
                                        const RowLift<float>&, hipStream_t);
 template int dst_rows_lift_pass<double>(int, const cx<double>*, const double*, const double*, double*, long long,
                                         long long, const RowLift<double>&, hipStream_t);
+
+template <typename T>
+int dst_rows_add_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, const T* addv, long long nrows,
+                      long long pitch, hipStream_t st) {
+  if (pitch < N - 1 || !addv) return ST_INVALID;
+  switch (N) {
+#define AHOC_RADD(NN) \
+  case NN: return fast::rows_add_launch<T, NN>(in, out, tw, sn, nrows, pitch, addv, st);
+    AHOC_RADD(32) AHOC_RADD(64) AHOC_RADD(96) AHOC_RADD(128) AHOC_RADD(192) AHOC_RADD(256)
+    AHOC_RADD(384) AHOC_RADD(512) AHOC_RADD(768) AHOC_RADD(1024) AHOC_RADD(2048) AHOC_RADD(4096)
+#undef AHOC_RADD
+    default: return ST_UNSUPPORTED;
+  }
+}
+template int dst_rows_add_pass<float>(int, const cx<float>*, const float*, const float*, float*, const float*,
+                                      long long, long long, hipStream_t);
+template int dst_rows_add_pass<double>(int, const cx<double>*, const double*, const double*, double*, const double*,
+                                       long long, long long, hipStream_t);
 
 template <typename T>
 int dst_rows_mul_pass(int N, const cx<T>* tw, const T* sn, const T* in, T* out, long long nrows, long long pitch,
