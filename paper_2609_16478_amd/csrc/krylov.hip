@@ -30,20 +30,31 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Per-segment small arrays: H [ns][m][m+1] (column j at j*(m+1)), cs, sn [ns][m],
 // gv, y, h1, h2 [ns][m+1], nrm, resid [ns][2], beta [ns], act [ns].
 
-// part[(s * nvec + v) * gridDim.x + block] = partial sum of <V_v, w> over segment s
+// part[(s * nvec + v) * gridDim.x + block] = partial sum of <V_v, w> over segment s.  The
+// vectors are taken MDC at a time, so that w is read once per group of vectors rather than
+// once per vector; each vector's sum runs over the same elements in the same order either way.
+constexpr int MDC = 8;
 __global__ void k_mdot_partial(const double* __restrict__ V, long long ld, int nvec,
                                const double* __restrict__ w, long long n, double* __restrict__ part) {
   __shared__ double red[TPB];
   const long long s0 = blockIdx.y * n;
-  for (int v = 0; v < nvec; ++v) {
-    const double* x = V + (long long)v * ld + s0;
-    const double* ws = w + s0;
-    double acc = 0;
+  const double* ws = w + s0;
+  for (int v0 = 0; v0 < nvec; v0 += MDC) {
+    const int nv = nvec - v0 < MDC ? nvec - v0 : MDC;
+    double acc[MDC];
+#pragma unroll
+    for (int c = 0; c < MDC; ++c) acc[c] = 0;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-         e += (long long)gridDim.x * blockDim.x)
-      acc += x[e] * ws[e];
-    const double r = block_sum(acc, red);
-    if (threadIdx.x == 0) part[((long long)blockIdx.y * nvec + v) * gridDim.x + blockIdx.x] = r;
+         e += (long long)gridDim.x * blockDim.x) {
+      const double we = ws[e];
+#pragma unroll
+      for (int c = 0; c < MDC; ++c)
+        if (c < nv) acc[c] += V[(long long)(v0 + c) * ld + s0 + e] * we;
+    }
+    for (int c = 0; c < nv; ++c) {
+      const double r = block_sum(acc[c], red);
+      if (threadIdx.x == 0) part[((long long)blockIdx.y * nvec + v0 + c) * gridDim.x + blockIdx.x] = r;
+    }
   }
 }
 
