@@ -83,10 +83,16 @@ template <typename T, int N> constexpr size_t pipe_tab_bytes() {
 template <typename T> __device__ __forceinline__ T gload(const T* p) {
   return *reinterpret_cast<const __attribute__((address_space(1))) T*>(reinterpret_cast<unsigned long long>(p));
 }
-// MODE 3 data after the tile: the face row (2 (N - 1) values), then the per-position table
-// (4 (N - 1) values) where it fits; the transform tables take precedence over the latter
+// MODE 3 data after the tile: the face row (2 (N - 1) values) where it fits beside the
+// transform tables (else it is read through the caches in the face loop: the tables take
+// precedence), then the per-position table (4 (N - 1) values) where it fits
+template <typename T, int N, int NSEQ> constexpr bool pipe_xrow_lds() {
+  return align16(pipe_tile_bytes<T, N, NSEQ>() + 2 * (size_t)(N - 1) * sizeof(T)) + pipe_tab_bytes<T, N>() <=
+             160 * 1024 ||
+         align16(pipe_tile_bytes<T, N, NSEQ>()) + pipe_tab_bytes<T, N>() > 160 * 1024;
+}
 template <typename T, int N, int NSEQ, int MODE> constexpr size_t pipe_face_bytes() {
-  return MODE == 3 ? 2 * (size_t)(N - 1) * sizeof(T) : 0;
+  return MODE == 3 && pipe_xrow_lds<T, N, NSEQ>() ? 2 * (size_t)(N - 1) * sizeof(T) : 0;
 }
 template <typename T, int N, int NSEQ, int MODE> constexpr bool pipe_tab_lds() {
   return align16(pipe_tile_bytes<T, N, NSEQ>() + pipe_face_bytes<T, N, NSEQ, MODE>()) + pipe_tab_bytes<T, N>() <=
@@ -193,6 +199,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   // weights), loaded once
   cx<T>* xrow = reinterpret_cast<cx<T>*>(smem + (size_t)(NSEQ * LDQ + NSEQ * NTOT) * sizeof(cx<T>));
   constexpr bool PTL = MODE == 3 && pipe_ptab_lds<T, N, NSEQ>();
+  constexpr bool XLDS = MODE == 3 && pipe_xrow_lds<T, N, NSEQ>();
   cx<T>* ptl = xrow + L;  // [m - 1][2]
   if constexpr (PTL) {
     const cx<T>* pg = reinterpret_cast<const cx<T>*>(a.gn.ptab);
@@ -220,7 +227,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
   constexpr int XR = MODE == 3 ? (L + NSEQ * TPS - 1) / (NSEQ * TPS) : 1;
   T xf[2][XR];
   auto xload = [&](const TileAt& d) {
-    if constexpr (MODE == 3) {
+    if constexpr (XLDS) {
       const T* la = a.gn.la + d.o * a.gn.aslab + (long long)d.ib * a.gn.arow;
       // (without a branch: positions past the row read its last one, unused)
 #pragma unroll
@@ -342,7 +349,7 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
 
   // MODE 3: the face row of the tile from the prefetched registers, as (sum, difference)
   auto stage_x = [&]() {
-    if constexpr (MODE == 3) {
+    if constexpr (XLDS) {
 #pragma unroll
       for (int r = 0; r < XR; ++r) {
         const int j = tid + r * NSEQ * TPS;
@@ -532,16 +539,23 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
         static_assert(PPT % G == 0, "whole groups of positions");
         const cx<T>* ptb = PTL ? ptl : reinterpret_cast<const cx<T>*>(a.gn.ptab);
         const SBase ys(ybase);  // byte offsets below 2^32 (checked at launch)
+        // the tile's x-face row, where it is not in LDS
+        [[maybe_unused]] const T* xla = a.gn.la + o * a.gn.aslab + ib * a.gn.arow;
 #pragma unroll 1
         for (int i0 = 0; i0 < PPT; i0 += G) {
           cx<T> t0[G], t1[G];
           T y0[G], y1[G];
+          [[maybe_unused]] T x0[G], x1[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) {
             const int m = 1 + ts + (i0 + g) * TPS;
             const int mc = m < N ? m : N - 1;
             t0[g] = ptb[2 * (mc - 1)];
             t1[g] = ptb[2 * (mc - 1) + 1];
+            if constexpr (!XLDS) {
+              x0[g] = xla[(long long)(mc - 1) * a.gn.apitch];
+              x1[g] = xla[a.gn.aplane + (long long)(mc - 1) * a.gn.apitch];
+            }
             const unsigned off = yoff + (unsigned)((mc - 1 - ts) * (int)sizeof(T));
             y0[g] = ys.template ld<T>(off);
             y1[g] = ys.template ld<T>(off + ystep);
@@ -555,7 +569,13 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_dst_pipe(Args<T
               cx<T>* pv = LIN ? seq + pad(1 + ts) + poff(i * TPS) : seq + pad(m);
               cx<T> v = *pv;
               const T st = t0[g].x, wpl = t0[g].y;
-              const cx<T> xv = xrow[m - 1];
+              cx<T> xv;  // the x-face pair as (sum, difference)
+              if constexpr (XLDS) {
+                xv = xrow[m - 1];
+              } else {
+                xv.x = x0[g] + x1[g];
+                xv.y = x0[g] - x1[g];
+              }
               const T ga = ga0 * wpl + xv.x * wla + y0[g] * wbl;
               const T gb = gb0 * wpl + xv.y * wlb + y1[g] * wbl;
               v.x = (v.x * (Ca + D * st) + (va ? ga : T(0))) * (a.fs.scale * recip(A.x + B.x * st));
