@@ -1143,8 +1143,7 @@ int dot_blocks(const ahoc_handle* h, long long n) {
 int dot_dev(ahoc_handle* h, const double* a, const double* b, hipStream_t st, double* out) {
   const long long n = h->g.nq;
   const int nbk = dot_blocks(h, n);
-  TRY(mdot_partial(a, n, 1, b, n, h->g.nb, h->part, nbk, st));
-  return mdot_reduce(h->part, nbk, 1, h->g.nb, out, 2, 0, st);
+  return mdot(a, n, 1, b, n, h->g.nb, h->part, nbk, out, 2, st);
 }
 
 double absmax(ahoc_handle* h, const void* x, bool dbl, long long n, hipStream_t st, int* rc) {
@@ -1322,15 +1321,13 @@ int gmres(ahoc_handle* h, Prec<T>& P, const double* b, double* x, double tol, in
       TRY(apply_op<T>(h, P, pre, vj, w, st));
       ++*matvecs;
       hipEvent_t ek = tbegin(h, st);
-      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, st));
-      TRY(mdot_reduce(h->part, nbk, j + 1, ns, h->h1, m + 1, 0, st));
+      TRY(mdot(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, h->h1, m + 1, st));
       TRY(maxpy(w, h->Vb, nt, j + 1, h->h1, m + 1, -1.0, nq, ns, st));
-      TRY(mdot_partial(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, st));
-      TRY(mdot_reduce(h->part, nbk, j + 1, ns, h->h2, m + 1, 0, st));
+      TRY(mdot(h->Vb, nt, j + 1, w, nq, ns, h->part, nbk, h->h2, m + 1, st));
       TRY(maxpy(w, h->Vb, nt, j + 1, h->h2, m + 1, -1.0, nq, ns, st));
       TRY(dot_dev(h, w, w, st, h->nrm));
-      TRY(givens_step(ns, h->H, m, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, st));
-      TRY(step_update(ns, j, h->resid, h->bn, tol, max_iters, inexact, h->ist, h->hist, h->eres, st));
+      TRY(givens_update(ns, h->H, m, h->h1, h->h2, h->nrm, h->cs, h->sn, h->gv, j, h->resid, h->bn, tol, max_iters,
+                        inexact, h->ist, h->hist, h->eres, st));
       TRY(scale_by_inv(w, nq, ns, h->resid, act, st));
       // CGS2: 2 x (j+1) dot sweeps and 2 x (j+1) axpy sweeps over the basis, plus norm and scale
       tend(h, AHOC_K_KRYLOV, ek, 8.0 * nt * (4.0 * (j + 1) + 2.0 * 2 + 3.0), st);

@@ -95,6 +95,10 @@ int mdot_partial(const double* V, long long ld, int nvec, const double* w, long 
                  int nbk, hipStream_t st);
 int mdot_reduce(const double* part, int nbk, int nvec, int ns, double* out, int ostride, int accumulate,
                 hipStream_t st);
+// out[s * ostride + v] = <V_v, w> over segment s: partial sums over nbk blocks and their
+// reduction, or with nbk == 1 the one block's sums written directly
+int mdot(const double* V, long long ld, int nvec, const double* w, long long n, int ns, double* part, int nbk,
+         double* out, int ostride, hipStream_t st);
 int maxpy(double* w, const double* V, long long ld, int nvec, const double* coef, int cstride, double sign,
           long long n, int ns, hipStream_t st);
 int givens_step(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2, double* cs,
@@ -118,6 +122,10 @@ int back_solve(int ns, const double* H, int m, const double* gv, const int* kk, 
 // nit | flag | hcnt], ns ints each; hist: 16 doubles per instance; eres: last active estimate
 int step_update(int ns, int j, const double* resid, const double* bnorm, double tol, int max_iters, bool inexact,
                 int* ist, double* hist, double* eres, hipStream_t st);
+// givens_step and step_update in one launch
+int givens_update(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2, double* cs,
+                  double* sn, double* gv, int j, double* resid, const double* bnorm, double tol, int max_iters,
+                  bool inexact, int* ist, double* hist, double* eres, hipStream_t st);
 int fill_int(int* p, long long n, int v, hipStream_t st);
 int start_cycle(double* v0, const double* r, long long n, int ns, const double* nrm2, double* gv, int m,
                 double* beta, hipStream_t st);

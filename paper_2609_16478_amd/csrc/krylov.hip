@@ -30,12 +30,14 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Per-segment small arrays: H [ns][m][m+1] (column j at j*(m+1)), cs, sn [ns][m],
 // gv, y, h1, h2 [ns][m+1], nrm, resid [ns][2], beta [ns], act [ns].
 
-// part[(s * nvec + v) * gridDim.x + block] = partial sum of <V_v, w> over segment s.  The
+// part[(s * nvec + v) * gridDim.x + block] = partial sum of <V_v, w> over segment s, or with
+// one block per segment and `out` given, the sum itself at out[s * ostride + v].  The
 // vectors are taken MDC at a time, so that w is read once per group of vectors rather than
 // once per vector; each vector's sum runs over the same elements in the same order either way.
 constexpr int MDC = 8;
 __global__ void k_mdot_partial(const double* __restrict__ V, long long ld, int nvec,
-                               const double* __restrict__ w, long long n, double* __restrict__ part) {
+                               const double* __restrict__ w, long long n, double* __restrict__ part,
+                               double* __restrict__ out, int ostride) {
   __shared__ double red[TPB];
   const long long s0 = blockIdx.y * n;
   const double* ws = w + s0;
@@ -53,7 +55,10 @@ __global__ void k_mdot_partial(const double* __restrict__ V, long long ld, int n
     }
     for (int c = 0; c < nv; ++c) {
       const double r = block_sum(acc[c], red);
-      if (threadIdx.x == 0) part[((long long)blockIdx.y * nvec + v0 + c) * gridDim.x + blockIdx.x] = r;
+      if (threadIdx.x == 0) {
+        if (out) out[(long long)blockIdx.y * ostride + v0 + c] = r;
+        else part[((long long)blockIdx.y * nvec + v0 + c) * gridDim.x + blockIdx.x] = r;
+      }
     }
   }
 }
@@ -87,10 +92,9 @@ __global__ void k_maxpy(double* __restrict__ w, const double* __restrict__ V, lo
 }
 
 // one thread per segment
-__global__ void k_givens(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2,
-                         double* cs, double* sn, double* gv, int j, double* resid) {
-  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
-  if (sg >= ns) return;
+__device__ __forceinline__ void givens_body(int sg, double* H, int m, const double* h1, const double* h2,
+                                            const double* nrm2, double* cs, double* sn, double* gv, int j,
+                                            double* resid) {
   const int ldh = m + 1;
   double* col = H + (long long)sg * m * ldh + (long long)j * ldh;
   const double* a1 = h1 + (long long)sg * ldh;
@@ -118,6 +122,13 @@ __global__ void k_givens(int ns, double* H, int m, const double* h1, const doubl
   // keep the un-rotated subdiagonal for normalising v_{j+1}
   resid[2 * sg + 1] = nn;
   col[j + 1] = 0.0;
+}
+
+__global__ void k_givens(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2,
+                         double* cs, double* sn, double* gv, int j, double* resid) {
+  const int sg = blockIdx.x * blockDim.x + threadIdx.x;
+  if (sg >= ns) return;
+  givens_body(sg, H, m, h1, h2, nrm2, cs, sn, gv, j, resid);
 }
 
 __global__ void k_axpby(long long n, double a, const double* __restrict__ x, double b, double* __restrict__ y) {
@@ -235,11 +246,9 @@ __global__ void k_start(double* __restrict__ v0, const double* __restrict__ r, l
 // estimate is not finite or, for an FP32 operator (inexact), when eight steps gained less
 // than a factor 2 below 1e-2 (ring of its last 16 estimates in hist), and without a flag at
 // the iteration cap.  eres keeps each instance's estimate of its last active step.
-__global__ void k_step_update(int ns, int j, const double* __restrict__ resid, const double* __restrict__ bnorm,
-                              double tol, int max_iters, int inexact, int* __restrict__ ist,
-                              double* __restrict__ hist, double* __restrict__ eres) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ns) return;
+__device__ __forceinline__ void update_body(int s, int ns, int j, const double* resid, const double* bnorm,
+                                            double tol, int max_iters, int inexact, int* ist, double* hist,
+                                            double* eres) {
   int* act = ist;
   int* kk = ist + ns;
   int* nit = ist + 2 * ns;
@@ -273,6 +282,25 @@ __global__ void k_step_update(int ns, int j, const double* __restrict__ resid, c
   if (stop) act[s] = 0;
 }
 
+__global__ void k_step_update(int ns, int j, const double* __restrict__ resid, const double* __restrict__ bnorm,
+                              double tol, int max_iters, int inexact, int* __restrict__ ist,
+                              double* __restrict__ hist, double* __restrict__ eres) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  update_body(s, ns, j, resid, bnorm, tol, max_iters, inexact, ist, hist, eres);
+}
+
+// k_givens then k_step_update for each segment, in one launch (each segment's update reads
+// only the residual estimate its own rotation wrote)
+__global__ void k_givens_update(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2,
+                                double* cs, double* sn, double* gv, int j, double* resid, const double* bnorm,
+                                double tol, int max_iters, int inexact, int* ist, double* hist, double* eres) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ns) return;
+  givens_body(s, H, m, h1, h2, nrm2, cs, sn, gv, j, resid);
+  update_body(s, ns, j, resid, bnorm, tol, max_iters, inexact, ist, hist, eres);
+}
+
 __global__ void k_fill_int(int* __restrict__ p, long long n, int v) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
     p[e] = v;
@@ -288,9 +316,20 @@ inline unsigned nblk(long long n, int cap) {
 
 int mdot_partial(const double* V, long long ld, int nvec, const double* w, long long n, int ns, double* part,
                  int nbk, hipStream_t st) {
-  hipLaunchKernelGGL(k_mdot_partial, dim3(nbk, ns), dim3(TPB), 0, st, V, ld, nvec, w, n, part);
+  hipLaunchKernelGGL(k_mdot_partial, dim3(nbk, ns), dim3(TPB), 0, st, V, ld, nvec, w, n, part, nullptr, 0);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
+}
+
+int mdot(const double* V, long long ld, int nvec, const double* w, long long n, int ns, double* part, int nbk,
+         double* out, int ostride, hipStream_t st) {
+  if (nbk == 1) {  // one block per segment: its sum is the result (no reduction launch)
+    hipLaunchKernelGGL(k_mdot_partial, dim3(1, ns), dim3(TPB), 0, st, V, ld, nvec, w, n, part, out, ostride);
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
+  }
+  TRY_ST(mdot_partial(V, ld, nvec, w, n, ns, part, nbk, st));
+  return mdot_reduce(part, nbk, nvec, ns, out, ostride, 0, st);
 }
 
 int mdot_reduce(const double* part, int nbk, int nvec, int ns, double* out, int ostride, int accumulate,
@@ -368,6 +407,15 @@ int step_update(int ns, int j, const double* resid, const double* bnorm, double 
                 int* ist, double* hist, double* eres, hipStream_t st) {
   hipLaunchKernelGGL(k_step_update, dim3((ns + 63) / 64), dim3(64), 0, st, ns, j, resid, bnorm, tol, max_iters,
                      inexact ? 1 : 0, ist, hist, eres);
+  AHOC_HIP_TRY(hipGetLastError());
+  return ST_OK;
+}
+
+int givens_update(int ns, double* H, int m, const double* h1, const double* h2, const double* nrm2, double* cs,
+                  double* sn, double* gv, int j, double* resid, const double* bnorm, double tol, int max_iters,
+                  bool inexact, int* ist, double* hist, double* eres, hipStream_t st) {
+  hipLaunchKernelGGL(k_givens_update, dim3((ns + 63) / 64), dim3(64), 0, st, ns, H, m, h1, h2, nrm2, cs, sn, gv, j,
+                     resid, bnorm, tol, max_iters, inexact ? 1 : 0, ist, hist, eres);
   AHOC_HIP_TRY(hipGetLastError());
   return ST_OK;
 }
