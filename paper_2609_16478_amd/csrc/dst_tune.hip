@@ -7,10 +7,12 @@
 //                  of pencil pairs per work-group (for N = 512, 1024 also another radix plan:
 //                  32 points per thread instead of 16),
 //   DST_M_GEMM     the matrix-core products (even N <= 128).
-// Candidates that cannot launch (LDS, thread or length limits) are skipped.  The first
+// Passes over arrays of NT_STORE_MIN_BYTES or more skip the one-tile kernels.  Candidates
+// that cannot launch (LDS, thread or length limits) are skipped.  The first
 // timing of a shape is kept for the process, so every handle with that shape runs the same
 // kernels and gives bit-identical results.
 #include "common.h"
+#include "dst_device.h"
 
 #include <map>
 #include <mutex>
@@ -62,7 +64,11 @@ int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, lon
   };
   std::vector<Cand> cands{{DST_M_DEFAULT, 0}};
   if (tb.S) cands.push_back({DST_M_GEMM, 0});
-  if (dst_fast_supported(N)) {
+  // arrays beyond the caches: the persistent kernels, which overlap the next tile's loads
+  // with the current transform, beat the one-tile kernels on every measured shape, so only
+  // cache-resident passes time them
+  const bool big = (double)extent * sizeof(T) >= fast::NT_STORE_MIN_BYTES;
+  if (!big && dst_fast_supported(N)) {
     const int d = dst_fast_tile(N, (int)sizeof(T), inner == 1 ? DST_PASS_ROWS : DST_PASS_STRIDED);
     for (int t : {d / 2, d, 2 * d})
       if (t >= 1 && (t & (t - 1)) == 0) cands.push_back({DST_M_TILE, t});
@@ -75,7 +81,7 @@ int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, lon
     set_last_error(hipGetErrorString(he), "dst_autotune");
     return ST_HIP;
   }
-  constexpr int REPS = 5;
+  const int REPS = cands.size() > 1 ? 5 : 1;  // a lone candidate is timed for the report only
   Tuned r{-1, 0, -1.0, -1.0, -1.0};
   int rc = ST_OK;
   for (const Cand& c : cands) {
