@@ -1066,7 +1066,8 @@ __global__ void __launch_bounds__(NSEQ*(N / PipePlan<N>::PPT)) k_gen_pipe(GenPip
         }
       }
     }
-    __syncthreads();  // the next tile overwrites LDS
+    // the next tile's generation first stages its x-face row (a region the stores do not
+    // read), then waits at its own barrier before it overwrites the sequences
     if (nxt < ntiles) generate(nd);
     cur = nd;
   }
