@@ -331,6 +331,64 @@ __global__ void __launch_bounds__(256) k_face_reduce_w(const T* __restrict__ W, 
   }
 }
 
+// Row dots alone (no column sums): one wavefront per RPW rows of any plane (row r of the
+// planes' stack at W + r px), the RPW x CPL loads of a column chunk issued together, the
+// dots reduced with shuffles; no work-group barrier, so every row of a batch of small
+// planes is in flight at once.  Columns from nx on are not read.
+template <typename T, int CPL, int RPW>
+__global__ void __launch_bounds__(256) k_face_rows(const T* __restrict__ W, long long nrows, int ny, int nx, int px,
+                                                   const T* __restrict__ wx, T* __restrict__ fx, long long fx_side,
+                                                   long long fx_plane, long long fx_row) {
+  const int lane = threadIdx.x & 63;
+  const long long r0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
+  if (r0 >= nrows) return;  // whole wavefronts only
+  T dl[RPW], dh[RPW];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) dl[i] = dh[i] = T(0);
+  for (int c0 = 0; c0 < nx; c0 += 64 * CPL) {
+    T v[RPW][CPL];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const bool okr = r0 + i < nrows;
+      const T* __restrict__ row = W + (r0 + i) * (long long)px;
+#pragma unroll
+      for (int j = 0; j < CPL; ++j) {
+        const int c = c0 + lane + 64 * j;
+        v[i][j] = (okr && c < nx) ? row[c] : T(0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < CPL; ++j) {
+      const int c = c0 + lane + 64 * j;
+      const T wl = c < nx ? wx[c] : T(0), wh = c < nx ? wx[nx + c] : T(0);
+#pragma unroll
+      for (int i = 0; i < RPW; ++i) {
+        dl[i] += v[i][j] * wl;
+        dh[i] += v[i][j] * wh;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      dl[i] += __shfl_xor(dl[i], m, 64);
+      dh[i] += __shfl_xor(dh[i], m, 64);
+    }
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const long long r = r0 + i;
+      if (r < nrows) {
+        const long long o = r / ny, ky = r - o * ny;
+        fx[o * fx_plane + ky * fx_row] = dl[i];
+        fx[fx_side + o * fx_plane + ky * fx_row] = dh[i];
+      }
+    }
+  }
+}
+
 }  // namespace fast
 
 template <typename T>
@@ -394,14 +452,27 @@ int face_reduce(const T* W, long long planes, int ny, int nx, int px, const T* w
     }
 #undef AHOC_FRW
   }
-  const int cpt = (px + 255) / 256;
-  // whole planes when column sums are formed; otherwise split rows for enough work-groups
-  int rows_per = ny;
-  if (!fy && planes < 1024) {
-    long long chunks = (1024 + planes - 1) / planes;
-    rows_per = (int)((ny + chunks - 1) / chunks);
-    if (rows_per < 64) rows_per = 64;
+  if (!fy) {
+    // row dots alone: one wavefront per 8 / CPL rows (CPL columns per lane and chunk)
+    const long long nrows = planes * (long long)ny;
+    const int cpl = px <= 64 ? 1 : px <= 128 ? 2 : px <= 256 ? 4 : 8;
+    const long long waves = (nrows + 8 / cpl - 1) / (8 / cpl);
+    const long long blocks = (waves + 3) / 4;
+    if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
+#define AHOC_FROWS(C)                                                                                     \
+  hipLaunchKernelGGL((fast::k_face_rows<T, C, 8 / C>), dim3((unsigned)blocks), dim3(256), 0, st, W, nrows, ny, nx, \
+                     px, wx, fx, fx_side, fx_plane, fx_row)
+    if (cpl == 1) AHOC_FROWS(1);
+    else if (cpl == 2) AHOC_FROWS(2);
+    else if (cpl == 4) AHOC_FROWS(4);
+    else AHOC_FROWS(8);
+#undef AHOC_FROWS
+    AHOC_HIP_TRY(hipGetLastError());
+    return ST_OK;
   }
+  const int cpt = (px + 255) / 256;
+  // whole planes when column sums are formed
+  const int rows_per = ny;
   const long long nchunk = (ny + rows_per - 1) / rows_per;
   const long long blocks = planes * nchunk;
   if (blocks > 0x7fffffffLL) return ST_UNSUPPORTED;
