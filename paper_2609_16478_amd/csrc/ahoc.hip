@@ -119,7 +119,7 @@ struct ahoc_handle {
   float *ru = nullptr, *rv = nullptr, *rq = nullptr;
   // Krylov
   int m = 30;
-  int nb_dot = 256;
+  int nb_dot = 2048;  // most work-groups of a dot sweep (each >= 2048 entries)
   double *Vb = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *gv = nullptr;
   double *h1 = nullptr, *h2 = nullptr, *nrm = nullptr, *part = nullptr, *y = nullptr;
   double *resid = nullptr, *beta = nullptr, *bvec = nullptr, *dq = nullptr, *rvec = nullptr, *R = nullptr;
@@ -1579,7 +1579,7 @@ int setup_impl(const ahoc_problem* pbs, int count, hipStream_t st, ahoc_handle* 
   TRY(alloc_t(h, &h->resid, 2 * nb));
   TRY(alloc_t(h, &h->beta, nb));
   TRY(alloc_t(h, &h->y, nb * (m + 1)));
-  TRY(alloc_t(h, &h->part, nb * (m + 1) * h->nb_dot));
+  TRY(alloc_t(h, &h->part, nb * (m + 1) * dot_blocks(h, g.nq)));
   TRY(alloc_t(h, &h->act, nb));
   TRY(alloc_t(h, &h->ist, 5 * nb));
   TRY(alloc_t(h, &h->hist, 16 * nb));

@@ -35,10 +35,16 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // vectors are taken MDC at a time, so that w is read once per group of vectors rather than
 // once per vector; each vector's sum runs over the same elements in the same order either way.
 constexpr int MDC = 8;
+// The group's MDC sums are reduced together: across each wavefront with shuffles, then the
+// TPB/64 wavefront sums added in wavefront order by one thread per vector (one barrier per
+// group; the LDS rows alternate between groups, so a group's rows are not overwritten before
+// they are read).
 __global__ void k_mdot_partial(const double* __restrict__ V, long long ld, int nvec,
                                const double* __restrict__ w, long long n, double* __restrict__ part,
                                double* __restrict__ out, int ostride) {
-  __shared__ double red[TPB];
+  constexpr int NW = TPB / 64;
+  __shared__ double red[2][NW][MDC];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long s0 = blockIdx.y * n;
   const double* ws = w + s0;
   for (int v0 = 0; v0 < nvec; v0 += MDC) {
@@ -53,12 +59,24 @@ __global__ void k_mdot_partial(const double* __restrict__ V, long long ld, int n
       for (int c = 0; c < MDC; ++c)
         if (c < nv) acc[c] += V[(long long)(v0 + c) * ld + s0 + e] * we;
     }
-    for (int c = 0; c < nv; ++c) {
-      const double r = block_sum(acc[c], red);
-      if (threadIdx.x == 0) {
-        if (out) out[(long long)blockIdx.y * ostride + v0 + c] = r;
-        else part[((long long)blockIdx.y * nvec + v0 + c) * gridDim.x + blockIdx.x] = r;
-      }
+#pragma unroll
+    for (int c = 0; c < MDC; ++c) {
+#pragma unroll
+      for (int m = 32; m >= 1; m >>= 1) acc[c] += __shfl_xor(acc[c], m, 64);
+    }
+    const int buf = (v0 / MDC) & 1;
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < MDC; ++c) red[buf][wv][c] = acc[c];
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+      const int c = threadIdx.x;
+      double r = red[buf][0][c];
+#pragma unroll
+      for (int k = 1; k < NW; ++k) r += red[buf][k][c];
+      if (out) out[(long long)blockIdx.y * ostride + v0 + c] = r;
+      else part[((long long)blockIdx.y * nvec + v0 + c) * gridDim.x + blockIdx.x] = r;
     }
   }
 }
