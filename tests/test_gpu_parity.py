@@ -412,7 +412,9 @@ def test_precond_rejected_when_disabled(ah):
 # calibration copies (the bandwidth references of the DST passes)
 # ------------------------------------------------------------------------------------------
 
-@pytest.mark.parametrize("shape", [(17, 33, 64), (5, 1023, 1024), (70, 3, 32)])
+# (65, 1023, 1024): 272 MB, above the streaming threshold (non-temporal copies), with a
+# partial last round of the linear copy
+@pytest.mark.parametrize("shape", [(17, 33, 64), (5, 1023, 1024), (70, 3, 32), (65, 1023, 1024)])
 def test_copy_bandwidth_patterns_are_exact_copies(ah, shape):
     x = torch.randn(*shape, dtype=torch.float32, device="cuda")
     for pattern in (0, 1, 2):
