@@ -214,6 +214,10 @@ def main():
                     help="profiling target: contiguous and strided DST-I passes over 2^20 pencils of "
                          "N-1 = 31, 63, 127 points in FP32 and FP64, three each with the FFT kernels "
                          "and three with the matrix-core products")
+    ap.add_argument("--profile-solve", action="store_true",
+                    help="profiling target: one warm-up and one timed solve of the benchmark problem in "
+                         "the --profile-prec form (tolerance --tol), 0.3 s apart so that a kernel trace "
+                         "separates them, then exit (no JSON line)")
     ap.add_argument("--no-instance-loop", action="store_true",
                     help="skip the per-instance FP64 loop over the batched workload")
     ap.add_argument("--batch-profile", type=int, default=0,
@@ -311,6 +315,20 @@ def main():
         torch.cuda.synchronize()
         s.close()
         print(f"[bench] {args.profile_matvec} Schur matvecs done (n={n}, {args.profile_prec})", file=sys.stderr)
+        return
+
+    if args.profile_solve:
+        s = ah.Solver(prob, precision=ah.MIXED if args.profile_prec == "mixed" else ah.FP64, tol=args.tol)
+        out = torch.empty(s.nodal_shape, dtype=torch.float64, device=dev)
+        for i in range(2):
+            torch.cuda.synchronize()
+            time.sleep(0.3)
+            t = time.perf_counter()
+            _, _, _, st = s.solve(out=out)
+            torch.cuda.synchronize()
+            print(f"[bench] solve {i} ({args.profile_prec}): {(time.perf_counter() - t) * 1e3:.1f} ms, "
+                  f"{st.gmres_iters} GMRES iterations", file=sys.stderr, flush=True)
+        s.close()
         return
 
     # kernel classes that launch kernels themselves (the matvec and residual classes wrap them)
