@@ -236,7 +236,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the solver has no "
-              "multi-GPU path; see DESIGN.md for how it would shard.", file=sys.stderr)
+              "multi-GPU path (batches would split by instance, a single volume into z slabs with an "
+              "all-to-all around each z pass).", file=sys.stderr)
         sys.exit(2)
 
     import torch
