@@ -151,7 +151,7 @@ def _paper_timing(ah, W, torch, dev):
     choice) and solve are timed separately with the device synchronised, FP64 and mixed, each
     to a Schur tolerance of h^3.5; the error is against the exact solution.  Handle memory
     comes from PyTorch's caching allocator, whose cache is kept between the solvers as in a
-    process that solves repeatedly: device memory handed back to the driver and requested
+    process that solves repeatedly: device memory handed back to the device runtime and requested
     again moments later can take up to seconds per multi-GiB block to map.  (16-thread CPU
     times in the paper: context only.)"""
     out = {"metric": "setup + solve seconds of the paper's timing-table workloads, Schur tol h^3.5",

@@ -51,7 +51,7 @@ typedef enum {
   AHOC_E_NOMEM = -2,       /* device allocation failed                           */
   AHOC_E_NOCONV = -3,      /* tolerance not reached; outputs hold the last iterate */
   AHOC_E_HIP = -4,         /* a HIP runtime call failed                          */
-  AHOC_E_UNSUPPORTED = -5  /* an option or problem combination this build does not solve
+  AHOC_E_UNSUPPORTED = -5  /* an option or problem combination the library does not solve
                               (see ahoc_problem, ahoc_options)                     */
 } ahoc_status;
 
