@@ -350,7 +350,8 @@ def main():
         for name, axis, kind in (("x_rows", 0, 0), ("y_strided", 1, 1)):
             m, tile, td, tg, tb = s.dst_choice(prec, axis, kind)
             choices[f"{'mixed' if prec == ah.MIXED else 'fp64'}_{name}"] = {
-                "method": {0: "fft_default", 1: "matrix_core", 2: f"fft_one_tile_{tile}"}.get(m, "untimed"),
+                "method": {0: "fft_default", 1: "matrix_core", 2: f"fft_one_tile_{tile}"}.get(
+                    m, "fft_default_untimed (no other candidate on arrays of 256 MB or more)"),
                 "us_default": td, "us_chosen": tb}
         out = torch.empty(s.nodal_shape, dtype=torch.float64, device=dev)
         for i in range(warmup):

@@ -7,8 +7,9 @@
 //                  of pencil pairs per work-group (for N = 512, 1024 also another radix plan:
 //                  32 points per thread instead of 16),
 //   DST_M_GEMM     the matrix-core products (even N <= 128).
-// Passes over arrays of NT_STORE_MIN_BYTES or more skip the one-tile kernels.  Candidates
-// that cannot launch (LDS, thread or length limits) are skipped.  The first
+// Passes over arrays of NT_STORE_MIN_BYTES or more skip the one-tile kernels (and, with no other
+// candidate, keep the default kernel untimed).  Candidates that cannot launch (LDS, thread or
+// length limits) are skipped.  The first
 // timing of a shape is kept for the process, so every handle with that shape runs the same
 // kernels and gives bit-identical results.
 #include "common.h"
@@ -57,8 +58,6 @@ int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, lon
   }
   const int N = tb.N, L = N - 1;
   const long long extent = inner == 1 ? (outer - 1) * pitch + L : outer * (long long)L * inner;
-  // zeros: the timings do not depend on the values, and repeated transforms stay finite
-  AHOC_HIP_TRY(hipMemsetAsync(buf, 0, sizeof(T) * (size_t)extent, st));
   struct Cand {
     int method, tile;
   };
@@ -73,6 +72,9 @@ int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, lon
     for (int t : {d / 2, d, 2 * d})
       if (t >= 1 && (t & (t - 1)) == 0) cands.push_back({DST_M_TILE, t});
   }
+  if (cands.size() == 1) return ST_OK;  // nothing to choose: the default kernel, untimed
+  // zeros: the timings do not depend on the values, and repeated transforms stay finite
+  AHOC_HIP_TRY(hipMemsetAsync(buf, 0, sizeof(T) * (size_t)extent, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   AHOC_HIP_TRY(hipEventCreate(&e0));
   const hipError_t he = hipEventCreate(&e1);
@@ -81,7 +83,7 @@ int dst_autotune(DstTables<T>& tb, T* buf, long long outer, long long inner, lon
     set_last_error(hipGetErrorString(he), "dst_autotune");
     return ST_HIP;
   }
-  const int REPS = cands.size() > 1 ? 5 : 1;  // a lone candidate is timed for the report only
+  constexpr int REPS = 5;
   Tuned r{-1, 0, -1.0, -1.0, -1.0};
   int rc = ST_OK;
   for (const Cand& c : cands) {
